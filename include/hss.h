@@ -1,0 +1,194 @@
+/*
+ * hss.h -- C ABI of the MI355X (gfx950) HSS library: the HSS matrix x block
+ * product and the implicit ULV factorization / solve of an HSS matrix given
+ * by its generators on a balanced binary cluster tree.
+ *
+ * Definitions (Massei, Robol, Kressner, "hm-toolbox: Matlab software for HODLR
+ * and HSS matrices"):
+ *   - cluster tree: Def. 2.1; default splitting rule: Sec. 3.1;
+ *   - HSS generators D_i, U_i, V_i, translation operators R (row) and W
+ *     (column), core blocks B12/B21 stored at the parent: Sec. 2.2 and the
+ *     nestedness equation "HSS_nestedness";
+ *   - A * X: the four-step HSS product of Sec. 4.1;
+ *   - ulv(A), A \ B: the implicit ULV factorization of Sec. 4.3 (Steps 1-4);
+ *   - ||A||_2 by the power method on A^T A: Sec. 4.5;
+ *   - backward error ||b - A x|| / (||A|| ||x|| + ||b||): Sec. 5.1.
+ *
+ * Conventions.  Indices are 0-based.  Heap numbering: node t has children
+ * 2t+1 and 2t+2; the nodes of level l are t = 2^l - 1 .. 2^(l+1) - 2.  All
+ * matrices are column-major.  Sizes are int64_t unless marked int32_t.
+ * Streams are hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Status codes: 0 = HSS_OK; a negative value -i means that argument i
+ * (1-based) is invalid; positive values are the HSS_E* codes below.
+ *
+ * Threading: a handle must be externally synchronized.  Device work of a
+ * call is enqueued on its stream.  hss_create, hss_destroy, hss_query
+ * (HSS_Q_NORM2 on first use) and solves that compute a backward error or
+ * refine iteratively synchronize the stream; everything else is asynchronous.
+ */
+#ifndef HSS_H_
+#define HSS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hss_status;
+
+#define HSS_OK         0
+#define HSS_ENOMEM     1   /* device allocation failed                          */
+#define HSS_EHIP       2   /* HIP runtime error                                 */
+#define HSS_ESTATE     3   /* call out of order, e.g. solve before factor       */
+#define HSS_ESINGULAR  4   /* exact zero pivot in an L block or the root LU     */
+#define HSS_ENOCONV    5   /* refinement reached max_refine above tol           */
+#define HSS_EUNSUP     6   /* sizes beyond what the kernels support             */
+
+#define HSS_OP_N 0          /* Y = A X   */
+#define HSS_OP_T 1          /* Y = A^T X */
+
+#define HSS_F64 0
+#define HSS_F32 1
+
+typedef struct hss_handle hss_handle;
+
+/* Cluster tree (Def. 2.1).  leaf_off has 2^p + 1 entries, leaf_off[0] = 0,
+ * leaf_off[2^p] = n, strictly increasing (empty leaves are rejected).
+ * ku / kv have 2^(p+1) - 1 entries in heap order: the number of columns of the
+ * row / column basis of node t (entry 0, the root, is ignored).
+ * Host memory, read during the call only. */
+typedef struct {
+  int64_t n;
+  int32_t p;
+  int32_t reserved;
+  const int64_t *leaf_off;
+  const int32_t *ku;
+  const int32_t *kv;
+} hss_tree_desc;
+
+/* FP64 generators in the canonical packed layout, HOST memory.  Each array is
+ * the concatenation, in heap order, of column-major blocks (ld = rows):
+ *   D, U, V   leaves only:           m_t x m_t, m_t x ku_t, m_t x kv_t
+ *   R, W      internal, not root:    (ku_c1+ku_c2) x ku_t, (kv_c1+kv_c2) x kv_t
+ *   B12, B21  every internal node:   ku_c1 x kv_c2, ku_c2 x kv_c1
+ * (Sec. 2.2: U_t = blkdiag(U_c1, U_c2) R_t, V_t = blkdiag(V_c1, V_c2) W_t;
+ * A(I_c1, I_c2) = U_c1 B12_t V_c2^T and A(I_c2, I_c1) = U_c2 B21_t V_c1^T.)
+ * The library copies them; the caller keeps ownership. */
+typedef struct {
+  const double *D, *U, *V, *R, *W, *B12, *B21;
+} hss_gen_host;
+
+/* Optional device allocator.  alloc returns NULL on failure (the calling
+ * entry point then returns HSS_ENOMEM).  NULL hooks mean hipMalloc/hipFree. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*free)(void *ptr, void *ctx);
+  void *ctx;
+} hss_alloc;
+
+/* Solve options.  prec selects the factor set (HSS_F64 or HSS_F32; the root
+ * block of either is factored in FP64).  tol > 0 asks for the normwise
+ * backward error eta <= tol: the result is refined with FP64 residuals
+ * (r = b - A x by the FP64 product) and corrections from the chosen factors,
+ * at most max_refine times.  want_eta != 0 computes eta even when tol == 0. */
+typedef struct {
+  int32_t prec;
+  int32_t max_refine;
+  double tol;
+  int32_t want_eta;
+  int32_t reserved;
+} hss_solve_opts;
+
+/* Solve report, host memory, filled before the call returns when eta is
+ * computed (tol > 0 or want_eta).  eta (optional, host, nrhs entries) receives
+ * the per-column backward errors. */
+typedef struct {
+  double eta_max;
+  double norm2;        /* ||A||_2 estimate used in eta                       */
+  int32_t iters;       /* refinement steps taken                             */
+  int32_t status;      /* HSS_OK, HSS_ENOCONV or HSS_ESINGULAR               */
+  double *eta;
+} hss_solve_info;
+
+/* hss_create: validate the tree and generators, build the plan (node sizes,
+ * offsets, level ranges), upload the generators to device memory and keep a
+ * resident FP32 copy.  On success *out owns all device memory of the matrix.
+ * Errors: -1/-2/-3/-5 for invalid tree/generators/alloc/out, HSS_EUNSUP when a
+ * node is larger than the kernels support (leaf size or merged size > 128, rank
+ * > 64), HSS_ENOMEM, HSS_EHIP.  Synchronizes the stream. */
+hss_status hss_create(const hss_tree_desc *tree, const hss_gen_host *gen,
+                      const hss_alloc *alloc, void *stream, hss_handle **out);
+
+/* hss_destroy: free everything the handle owns.  NULL is a no-op. */
+hss_status hss_destroy(hss_handle *h);
+
+/* hss_matmul: Y = op(A) X by the four steps of Sec. 4.1 (leaf projections,
+ * upward pass with the column translations, core blocks, downward pass with
+ * the row translations, leaf outputs plus D_i X_i).  X and Y are DEVICE
+ * pointers to n x nrhs column-major blocks (ld >= n) of double (HSS_F64) or
+ * float (HSS_F32, using the resident FP32 generators); they must not overlap.
+ * nrhs == 0 is a no-op.  Asynchronous on stream. */
+hss_status hss_matmul(hss_handle *h, int32_t op, int32_t prec, int64_t nrhs,
+                      const void *X, int64_t ldx, void *Y, int64_t ldy, void *stream);
+
+/* hss_ulv_factor: implicit ULV factorization (Sec. 4.3, Step 1 on the leaves,
+ * Step 3 merging siblings level by level, dense LU with partial pivoting of the
+ * last merged block) in FP64 or FP32 (the root LU is FP64 in both).  Replaces
+ * an earlier factorization of the same precision.  An exact zero pivot is
+ * recorded on the device and reported by the next solve (HSS_ESINGULAR).
+ * Asynchronous on stream. */
+hss_status hss_ulv_factor(hss_handle *h, int32_t prec, void *stream);
+
+/* hss_ulv_solve: B <- A^{-1} B in place (Steps 1, 2 and 4 applied to B with the
+ * stored factors).  B is a DEVICE pointer to an n x nrhs FP64 block (ldb >= n).
+ * o == NULL means {HSS_F64, 10, 0.0, 0}.  info may be NULL.  Returns
+ * HSS_ESTATE if the requested precision has not been factored,
+ * HSS_ENOCONV if refinement stopped at max_refine with eta > tol (B then holds
+ * the last iterate), HSS_ESINGULAR for an exactly singular factor. */
+hss_status hss_ulv_solve(hss_handle *h, int64_t nrhs, double *B, int64_t ldb,
+                         const hss_solve_opts *o, hss_solve_info *info, void *stream);
+
+/* Query keys for hss_query (out is host memory of the stated type). */
+#define HSS_Q_N              0   /* int64_t                                        */
+#define HSS_Q_P              1   /* int32_t                                        */
+#define HSS_Q_RESIDENT_BYTES 2   /* int64_t: device bytes owned by the handle     */
+#define HSS_Q_NORM2          3   /* double: power-method ||A||_2 (cached)          */
+#define HSS_Q_GEN_ENTRIES    4   /* int64_t: generator entries (algorithmic size)  */
+#define HSS_Q_FACTOR_ENTRIES 5   /* int64_t: entries of one factor set            */
+hss_status hss_query(hss_handle *h, int32_t key, void *out, void *stream);
+
+/* Host-only plan helpers (no device needed), used to check the plan against
+ * independent implementations.
+ * hss_plan_depth: depth p of the default tree (ceil-halving until the blocks
+ *   have <= nmin indices, Sec. 3.1).
+ * hss_plan_leaf_offsets: fills leaf_off[0 .. 2^p] for that tree.
+ * hss_plan_node_ranges: for a tree description, fills start[t], size[t] of the
+ *   index set of every node in heap order (2^(p+1)-1 entries each). */
+int32_t hss_plan_depth(int64_t n, int64_t nmin);
+hss_status hss_plan_leaf_offsets(int64_t n, int64_t nmin, int64_t *leaf_off, int64_t cap);
+hss_status hss_plan_node_ranges(const hss_tree_desc *tree, int64_t *start, int64_t *size);
+
+/* Batched calls: one launch per tree level across all handles (levels are
+ * aligned at the leaves for upward passes and at the root for downward
+ * passes).  Each result equals the single-handle call on the same stream.
+ * hs: host array of count handles; the per-handle arrays are host arrays of
+ * count entries; B / X / Y entries are device pointers. */
+hss_status hss_batch_matmul(hss_handle *const *hs, int32_t count, int32_t op, int32_t prec,
+                            const int64_t *nrhs, const void *const *X, const int64_t *ldx,
+                            void *const *Y, const int64_t *ldy, void *stream);
+hss_status hss_batch_ulv_factor(hss_handle *const *hs, int32_t count, int32_t prec,
+                                void *stream);
+hss_status hss_batch_ulv_solve(hss_handle *const *hs, int32_t count, const int64_t *nrhs,
+                               double *const *B, const int64_t *ldb, const hss_solve_opts *o,
+                               hss_solve_info *info, void *stream);
+
+/* Text for a status code (static storage). */
+const char *hss_status_str(hss_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSS_H_ */

@@ -1,0 +1,138 @@
+// Device helpers for the gfx950 kernels: work-group small GEMM, wavefront
+// reductions, task resolution.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hss_internal.hpp"
+
+namespace hss {
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Resolve (instance, call, node) of this work-group.
+template <bool BATCH, typename T, typename Call>
+__device__ __forceinline__ void resolve(const KArgs<T, Call>& a, Inst<T>& I, Call& C, int& node) {
+  if constexpr (BATCH) {
+    const int2 tk = a.tasks[blockIdx.x];
+    I = a.insts[tk.x];
+    C = a.calls[tk.x];
+    node = tk.y;
+  } else {
+    I = a.inst;
+    C = a.call;
+    node = a.node0 + blockIdx.x;
+  }
+}
+
+template <typename T, bool TA>
+__device__ __forceinline__ T ldA(const T* __restrict__ A, int64_t lda, int i, int l) {
+  return TA ? A[l + (int64_t)i * lda] : A[i + (int64_t)l * lda];
+}
+
+// C (=|+=) op(A) * B, op(A) = A (M x K, ld lda) or A^T (A is K x M).  B is
+// K x N (ld ldb), C is M x N (ld ldc).  All pointers generic (LDS or global).
+// Each output is produced by one thread; K is split over up to 16 thread
+// slices when the output is small.  red: LDS scratch of blockDim.x entries.
+// Must be called by all threads of the work-group.
+template <typename T, bool TA>
+__device__ void wg_gemm(int M, int N, int K, const T* __restrict__ A, int64_t lda,
+                        const T* B, int64_t ldb, T* C, int64_t ldc, bool accumulate, T* red) {
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const int MN = M * N;
+  if (MN <= 0) return;
+  int S = 1;
+  if (K > 16 && MN < nt) {
+    S = nt / MN;
+    if (S > 16) S = 16;
+    S = 1 << (31 - __clz(S));
+  }
+  if (S == 1) {
+    for (int o = tid; o < MN; o += nt) {
+      const int i = o % M, j = o / M;
+      T s = 0;
+      for (int l = 0; l < K; ++l) s += ldA<T, TA>(A, lda, i, l) * B[l + (int64_t)j * ldb];
+      T* c = C + i + (int64_t)j * ldc;
+      *c = accumulate ? *c + s : s;
+    }
+  } else {
+    const int o = tid % MN, s = tid / MN;
+    T part = 0;
+    if (tid < MN * S) {
+      const int i = o % M, j = o / M;
+      for (int l = s; l < K; l += S) part += ldA<T, TA>(A, lda, i, l) * B[l + (int64_t)j * ldb];
+    }
+    red[tid] = part;
+    __syncthreads();
+    if (tid < MN) {
+      T sum = 0;
+      for (int q = 0; q < S; ++q) sum += red[tid + q * MN];
+      const int i = tid % M, j = tid / M;
+      T* c = C + i + (int64_t)j * ldc;
+      *c = accumulate ? *c + sum : sum;
+    }
+    __syncthreads();
+  }
+}
+
+// Accessor form: C(i, j) <- fa(i, l) fb(l, j) summed over l < K; fc(i, j, v)
+// stores the result.  Same thread mapping as wg_gemm.
+template <typename T, typename FA, typename FB, typename FC>
+__device__ void wg_gemm_f(int M, int N, int K, FA fa, FB fb, FC fc, T* red) {
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const int MN = M * N;
+  if (MN <= 0) return;
+  int S = 1;
+  if (K > 16 && MN < nt) {
+    S = nt / MN;
+    if (S > 16) S = 16;
+    S = 1 << (31 - __clz(S));
+  }
+  if (S == 1) {
+    for (int o = tid; o < MN; o += nt) {
+      const int i = o % M, j = o / M;
+      T s = 0;
+      for (int l = 0; l < K; ++l) s += fa(i, l) * fb(l, j);
+      fc(i, j, s);
+    }
+  } else {
+    const int o = tid % MN, s = tid / MN;
+    T part = 0;
+    if (tid < MN * S) {
+      const int i = o % M, j = o / M;
+      for (int l = s; l < K; l += S) part += fa(i, l) * fb(l, j);
+    }
+    red[tid] = part;
+    __syncthreads();
+    if (tid < MN) {
+      T sum = 0;
+      for (int q = 0; q < S; ++q) sum += red[tid + q * MN];
+      fc(tid % M, tid / M, sum);
+    }
+    __syncthreads();
+  }
+}
+
+// Copy an M x N block (generic pointers) into LDS with leading dimension lds.
+template <typename T, typename S>
+__device__ __forceinline__ void wg_load(int M, int N, const S* __restrict__ src, int64_t ld,
+                                        T* dst, int lds) {
+  for (int o = threadIdx.x; o < M * N; o += blockDim.x) {
+    const int i = o % M, j = o / M;
+    dst[i + j * lds] = (T)src[i + (int64_t)j * ld];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void wg_store(int M, int N, const T* src, int lds, T* dst, int64_t ld) {
+  for (int o = threadIdx.x; o < M * N; o += blockDim.x) {
+    const int i = o % M, j = o / M;
+    dst[i + (int64_t)j * ld] = src[i + j * lds];
+  }
+}
+
+}  // namespace hss

@@ -1,0 +1,661 @@
+// C ABI of the HSS library (include/hss.h): handle management, launch
+// schedules over the tree levels, iterative refinement and the power-method
+// norm estimate.  All arithmetic runs in the HIP kernels; this file only
+// plans, allocates and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hss.h"
+#include "hss_internal.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace hss;
+
+namespace {
+
+template <typename T>
+struct FactorSet {
+  T *FD = nullptr, *FU = nullptr, *FV = nullptr, *tq = nullptr, *tz = nullptr;
+  double* rootLU = nullptr;
+  int32_t* piv = nullptr;
+  bool valid = false;
+};
+
+template <typename T>
+struct Work {
+  T *xh = nullptr, *yh = nullptr;     // product
+  int64_t cap_mm = 0;
+  T *wc = nullptr, *wz = nullptr, *wy = nullptr, *wx = nullptr;   // solve
+  int64_t cap_sv = 0;
+};
+
+}  // namespace
+
+struct hss_handle {
+  Plan plan;
+  hss_alloc alloc{};
+  bool custom_alloc = false;
+  std::vector<std::pair<void*, size_t>> blocks;   // everything we allocated
+  int64_t resident = 0;
+  NodeInfo* d_nodes = nullptr;
+  double* g64[7] = {};
+  float* g32[7] = {};
+  FactorSet<double> f64;
+  FactorSet<float> f32;
+  Work<double> w64;
+  Work<float> w32;
+  int32_t* d_status = nullptr;
+  // refinement / norm work
+  double *b0 = nullptr, *res = nullptr, *d64 = nullptr;
+  float* r32 = nullptr;
+  int64_t cap_ir = 0;
+  double* stats = nullptr;   // 8 * cap_stats doubles
+  int64_t cap_stats = 0;
+  double* pinned = nullptr;  // host-visible scalars
+  double norm2 = -1.0;
+};
+
+namespace {
+
+hss_status hip_status(hipError_t e) { return e == hipSuccess ? HSS_OK : HSS_EHIP; }
+
+void* dev_alloc(hss_handle* h, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (h->custom_alloc) {
+    p = h->alloc.alloc(bytes, h->alloc.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (p) {
+    h->blocks.emplace_back(p, bytes);
+    h->resident += (int64_t)bytes;
+  }
+  return p;
+}
+
+void dev_free(hss_handle* h, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < h->blocks.size(); ++i)
+    if (h->blocks[i].first == p) {
+      h->resident -= (int64_t)h->blocks[i].second;
+      h->blocks.erase(h->blocks.begin() + i);
+      break;
+    }
+  if (h->custom_alloc) h->alloc.free(p, h->alloc.ctx);
+  else (void)hipFree(p);
+}
+
+template <typename T>
+T* dalloc(hss_handle* h, int64_t n) {
+  return static_cast<T*>(dev_alloc(h, sizeof(T) * (size_t)std::max<int64_t>(n, 1)));
+}
+
+template <typename T>
+FactorSet<T>& factors(hss_handle* h);
+template <>
+FactorSet<double>& factors<double>(hss_handle* h) { return h->f64; }
+template <>
+FactorSet<float>& factors<float>(hss_handle* h) { return h->f32; }
+template <typename T>
+Work<T>& work(hss_handle* h);
+template <>
+Work<double>& work<double>(hss_handle* h) { return h->w64; }
+template <>
+Work<float>& work<float>(hss_handle* h) { return h->w32; }
+template <typename T>
+const T* gen(hss_handle* h, int i);
+template <>
+const double* gen<double>(hss_handle* h, int i) { return h->g64[i]; }
+template <>
+const float* gen<float>(hss_handle* h, int i) { return h->g32[i]; }
+
+template <typename T>
+hss_status ensure_factors(hss_handle* h) {
+  FactorSet<T>& F = factors<T>(h);
+  if (F.FD) return HSS_OK;
+  const Plan& P = h->plan;
+  F.FD = dalloc<T>(h, P.nFD);
+  F.FU = dalloc<T>(h, P.nFU);
+  F.FV = dalloc<T>(h, P.nFV);
+  F.tq = dalloc<T>(h, P.ntq);
+  F.tz = dalloc<T>(h, P.ntz);
+  F.rootLU = dalloc<double>(h, (int64_t)P.nodes[0].mp * P.nodes[0].mp);
+  F.piv = dalloc<int32_t>(h, P.nodes[0].mp);
+  if (!F.FD || !F.FU || !F.FV || !F.tq || !F.tz || !F.rootLU || !F.piv) return HSS_ENOMEM;
+  return HSS_OK;
+}
+
+template <typename T>
+hss_status ensure_work_mm(hss_handle* h, int64_t nrhs) {
+  Work<T>& w = work<T>(h);
+  const int64_t cap = std::max<int64_t>(nrhs, kRT);
+  if (w.cap_mm >= nrhs && w.xh) return HSS_OK;
+  dev_free(h, w.xh);
+  dev_free(h, w.yh);
+  w.xh = dalloc<T>(h, h->plan.ldm * cap);
+  w.yh = dalloc<T>(h, h->plan.ldm * cap);
+  w.cap_mm = (w.xh && w.yh) ? cap : 0;
+  return w.cap_mm ? HSS_OK : HSS_ENOMEM;
+}
+
+template <typename T>
+hss_status ensure_work_sv(hss_handle* h, int64_t nrhs) {
+  Work<T>& w = work<T>(h);
+  const int64_t cap = std::max<int64_t>(nrhs, kRT);
+  if (w.cap_sv >= nrhs && w.wc) return HSS_OK;
+  for (T* p : {w.wc, w.wz, w.wy, w.wx}) dev_free(h, p);
+  const int64_t sz = h->plan.lds * cap;
+  w.wc = dalloc<T>(h, sz);
+  w.wz = dalloc<T>(h, sz);
+  w.wy = dalloc<T>(h, sz);
+  w.wx = dalloc<T>(h, sz);
+  w.cap_sv = (w.wc && w.wz && w.wy && w.wx) ? cap : 0;
+  return w.cap_sv ? HSS_OK : HSS_ENOMEM;
+}
+
+hss_status ensure_ir(hss_handle* h, int64_t nrhs) {
+  const int64_t cap = std::max<int64_t>(nrhs, 1);
+  if (h->cap_ir < cap || !h->b0) {
+    for (void* p : {(void*)h->b0, (void*)h->res, (void*)h->d64, (void*)h->r32}) dev_free(h, p);
+    const int64_t n = h->plan.n;
+    h->b0 = dalloc<double>(h, n * cap);
+    h->res = dalloc<double>(h, n * cap);
+    h->d64 = dalloc<double>(h, n * cap);
+    h->r32 = dalloc<float>(h, n * cap);
+    h->cap_ir = (h->b0 && h->res && h->d64 && h->r32) ? cap : 0;
+    if (!h->cap_ir) return HSS_ENOMEM;
+  }
+  if (h->cap_stats < cap || !h->stats) {
+    dev_free(h, h->stats);
+    h->stats = dalloc<double>(h, 8 * cap + 8);
+    h->cap_stats = h->stats ? cap : 0;
+    if (!h->stats) return HSS_ENOMEM;
+  }
+  return HSS_OK;
+}
+
+template <typename T>
+Inst<T> make_inst(hss_handle* h) {
+  Inst<T> I{};
+  I.nodes = h->d_nodes;
+  I.D = gen<T>(h, 0); I.U = gen<T>(h, 1); I.V = gen<T>(h, 2); I.R = gen<T>(h, 3);
+  I.W = gen<T>(h, 4); I.B12 = gen<T>(h, 5); I.B21 = gen<T>(h, 6);
+  FactorSet<T>& F = factors<T>(h);
+  I.FD = F.FD; I.FU = F.FU; I.FV = F.FV; I.tq = F.tq; I.tz = F.tz;
+  I.rootLU = F.rootLU; I.piv = F.piv;
+  Work<T>& w = work<T>(h);
+  I.xh = w.xh; I.yh = w.yh; I.ldm = h->plan.ldm;
+  I.wc = w.wc; I.wz = w.wz; I.wy = w.wy; I.wx = w.wx; I.lds = h->plan.lds;
+  I.status = h->d_status;
+  I.p = h->plan.p;
+  I.nnodes = h->plan.nnodes;
+  return I;
+}
+
+inline int level_first(int l) { return (1 << l) - 1; }
+
+// ---------------------------------------------------------------------------
+// Single-instance schedules
+// ---------------------------------------------------------------------------
+template <typename T>
+void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T* Y, int64_t ldy,
+                hipStream_t s) {
+  KArgs<T, CallMM<T>> a{};
+  a.inst = make_inst<T>(h);
+  a.call = CallMM<T>{X, Y, ldx, ldy, (int32_t)nrhs, op};
+  const int p = h->plan.p;
+  const int yt = (int)((nrhs + kRT - 1) / kRT);
+  const int rows = kMaxBlock;
+  if (p == 0) {
+    a.node0 = 0;
+    launch_mm_level<T>(MMStep::LeafOut, a, 1, yt, rows, s);
+    return;
+  }
+  a.node0 = level_first(p);
+  launch_mm_level<T>(MMStep::LeafUp, a, 1 << p, yt, rows, s);
+  for (int l = p - 1; l >= 1; --l) {
+    a.node0 = level_first(l);
+    launch_mm_level<T>(MMStep::Up, a, 1 << l, yt, rows, s);
+  }
+  a.node0 = 0;
+  launch_mm_level<T>(MMStep::Couple, a, (1 << p) - 1, yt, rows, s);
+  for (int l = 1; l <= p - 1; ++l) {
+    a.node0 = level_first(l);
+    launch_mm_level<T>(MMStep::Down, a, 1 << l, yt, rows, s);
+  }
+  a.node0 = level_first(p);
+  launch_mm_level<T>(MMStep::LeafOut, a, 1 << p, yt, rows, s);
+}
+
+template <typename T>
+void run_factor(hss_handle* h, hipStream_t s) {
+  KArgs<T, CallSV<T>> a{};
+  a.inst = make_inst<T>(h);
+  const Plan& P = h->plan;
+  const int p = P.p;
+  if (p == 0) {
+    a.node0 = 0;
+    launch_ulv<T>(UlvStep::RootLU, a, 1, 1, P.max_mp, s);
+    return;
+  }
+  a.node0 = level_first(p);
+  launch_ulv<T>(UlvStep::Factor, a, 1 << p, 1, P.max_mp, s);
+  for (int l = p - 1; l >= 1; --l) {
+    a.node0 = level_first(l);
+    launch_ulv<T>(UlvStep::Merge, a, 1 << l, 1, P.max_mp, s);
+    launch_ulv<T>(UlvStep::Factor, a, 1 << l, 1, P.max_mp, s);
+  }
+  a.node0 = 0;
+  launch_ulv<T>(UlvStep::Merge, a, 1, 1, P.max_mp, s);
+  launch_ulv<T>(UlvStep::RootLU, a, 1, 1, P.max_mp, s);
+}
+
+template <typename T>
+void run_solve(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, hipStream_t s) {
+  KArgs<T, CallSV<T>> a{};
+  a.inst = make_inst<T>(h);
+  a.call = CallSV<T>{B, ldb, (int32_t)nrhs, 0};
+  const Plan& P = h->plan;
+  const int p = P.p;
+  const int yt = (int)((nrhs + kRT - 1) / kRT);
+  if (p == 0) {
+    a.node0 = 0;
+    launch_ulv<T>(UlvStep::Root, a, 1, yt, P.max_mp, s);
+    return;
+  }
+  a.node0 = level_first(p);
+  launch_ulv<T>(UlvStep::Fwd, a, 1 << p, yt, P.max_mp, s);
+  for (int l = p - 1; l >= 1; --l) {
+    a.node0 = level_first(l);
+    launch_ulv<T>(UlvStep::Fwd, a, 1 << l, yt, P.max_mp, s);
+  }
+  a.node0 = 0;
+  launch_ulv<T>(UlvStep::Root, a, 1, yt, P.max_mp, s);
+  for (int l = 1; l <= p - 1; ++l) {
+    a.node0 = level_first(l);
+    launch_ulv<T>(UlvStep::Bwd, a, 1 << l, yt, P.max_mp, s);
+  }
+  a.node0 = level_first(p);
+  launch_ulv<T>(UlvStep::Bwd, a, 1 << p, yt, P.max_mp, s);
+}
+
+hss_status last_launch_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? HSS_OK : HSS_EHIP;
+}
+
+hss_status compute_norm2(hss_handle* h, hipStream_t s) {
+  if (h->norm2 >= 0.0) return HSS_OK;
+  hss_status st = ensure_ir(h, 1);
+  if (st) return st;
+  if ((st = ensure_work_mm<double>(h, 1))) return st;
+  const int64_t n = h->plan.n;
+  double* v = h->d64;
+  double* w = h->res;
+  double* u = h->b0;
+  double* ss = h->stats;   // [0] ||w||^2, [1] ||u||^2
+  launch_hash_fill(v, n, 0x5eedull, s);
+  launch_fill(ss, 0.0, 2, s);
+  launch_colstats(v, n, n, 1, ss + 1, nullptr, s);
+  launch_normalize(v, v, n, ss + 1, s);
+  const int iters = 16;
+  for (int it = 0; it < iters; ++it) {
+    launch_fill(ss, 0.0, 2, s);
+    run_matmul<double>(h, HSS_OP_N, 1, v, n, w, n, s);
+    launch_colstats(w, n, n, 1, ss, nullptr, s);           // ||A v||^2, ||v|| = 1
+    run_matmul<double>(h, HSS_OP_T, 1, w, n, u, n, s);
+    launch_colstats(u, n, n, 1, ss + 1, nullptr, s);
+    launch_normalize(u, v, n, ss + 1, s);
+  }
+  if ((st = last_launch_status())) return st;
+  double lam = 0.0;
+  if (hipMemcpyAsync(&lam, ss, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return HSS_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
+  h->norm2 = std::sqrt(std::max(lam, 0.0));
+  return HSS_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* hss_status_str(hss_status s) {
+  switch (s) {
+    case HSS_OK: return "ok";
+    case HSS_ENOMEM: return "device allocation failed";
+    case HSS_EHIP: return "HIP runtime error";
+    case HSS_ESTATE: return "call out of order (e.g. solve before factor)";
+    case HSS_ESINGULAR: return "exactly singular pivot";
+    case HSS_ENOCONV: return "refinement did not reach the tolerance";
+    case HSS_EUNSUP: return "sizes beyond what the kernels support";
+    default: return s < 0 ? "invalid argument" : "unknown status";
+  }
+}
+
+int32_t hss_plan_depth(int64_t n, int64_t nmin) { return default_depth(n, nmin); }
+
+hss_status hss_plan_leaf_offsets(int64_t n, int64_t nmin, int64_t* leaf_off, int64_t cap) {
+  if (n <= 0) return -1;
+  if (nmin <= 0) return -2;
+  if (!leaf_off) return -3;
+  const int32_t p = default_depth(n, nmin);
+  const int64_t nleaf = int64_t(1) << p;
+  if (cap < nleaf + 1) return -4;
+  // ceil-halving, level by level (Sec. 3.1): store boundaries of the current level
+  std::vector<int64_t> b = {0, n};
+  for (int32_t l = 0; l < p; ++l) {
+    std::vector<int64_t> nb;
+    nb.reserve(2 * b.size() - 1);
+    for (size_t i = 0; i + 1 < b.size(); ++i) {
+      const int64_t s = b[i + 1] - b[i];
+      nb.push_back(b[i]);
+      nb.push_back(b[i] + (s + 1) / 2);
+    }
+    nb.push_back(n);
+    b.swap(nb);
+  }
+  std::copy(b.begin(), b.end(), leaf_off);
+  return HSS_OK;
+}
+
+hss_status hss_plan_node_ranges(const hss_tree_desc* tree, int64_t* start, int64_t* size) {
+  if (!start) return -2;
+  if (!size) return -3;
+  Plan P;
+  const hss_status st = build_plan(tree, P, nullptr);
+  if (st) return st;
+  for (int32_t t = 0; t < P.nnodes; ++t) {
+    start[t] = P.nodes[t].row0;
+    int64_t m = 0;
+    // node size as the sum of its leaves (exact int64)
+    int64_t lo = t, hi = t;
+    while (lo < (int64_t(1) << P.p) - 1) { lo = 2 * lo + 1; hi = 2 * hi + 2; }
+    const int64_t f = (int64_t(1) << P.p) - 1;
+    m = P.leaf_off[hi - f + 1] - P.leaf_off[lo - f];
+    size[t] = m;
+  }
+  return HSS_OK;
+}
+
+hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hss_alloc* alloc,
+                      void* stream, hss_handle** out) {
+  if (!out) return -5;
+  *out = nullptr;
+  if (!g) return -2;
+  if (alloc && (!alloc->alloc || !alloc->free)) return -3;
+  hss_handle* h = new hss_handle();
+  hss_status st = build_plan(tree, h->plan, nullptr);
+  if (st) {
+    delete h;
+    return st;
+  }
+  const Plan& P = h->plan;
+  const int64_t sizes[7] = {P.nD, P.nU, P.nV, P.nR, P.nW, P.nB12, P.nB21};
+  const double* src[7] = {g->D, g->U, g->V, g->R, g->W, g->B12, g->B21};
+  for (int i = 0; i < 7; ++i)
+    if (sizes[i] > 0 && !src[i]) {
+      delete h;
+      return -2;
+    }
+  if (alloc) {
+    h->alloc = *alloc;
+    h->custom_alloc = true;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  auto fail = [&](hss_status e) {
+    hss_destroy(h);
+    return e;
+  };
+  h->d_nodes = dalloc<NodeInfo>(h, P.nnodes);
+  h->d_status = dalloc<int32_t>(h, 4);
+  if (!h->d_nodes || !h->d_status) return fail(HSS_ENOMEM);
+  if (hipMemcpyAsync(h->d_nodes, P.nodes.data(), sizeof(NodeInfo) * P.nnodes,
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(HSS_EHIP);
+  for (int i = 0; i < 7; ++i) {
+    h->g64[i] = dalloc<double>(h, sizes[i]);
+    h->g32[i] = dalloc<float>(h, sizes[i]);
+    if (!h->g64[i] || !h->g32[i]) return fail(HSS_ENOMEM);
+    if (sizes[i] > 0) {
+      if (hipMemcpyAsync(h->g64[i], src[i], sizeof(double) * sizes[i], hipMemcpyHostToDevice,
+                         s) != hipSuccess)
+        return fail(HSS_EHIP);
+      launch_cast_f64_f32(h->g64[i], h->g32[i], sizes[i], s);
+    }
+  }
+  launch_fill(reinterpret_cast<double*>(h->d_status), 0.0, 2, s);
+  if ((st = last_launch_status())) return fail(st);
+  h->pinned = nullptr;
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(HSS_EHIP);
+  *out = h;
+  return HSS_OK;
+}
+
+hss_status hss_destroy(hss_handle* h) {
+  if (!h) return HSS_OK;
+  (void)hipDeviceSynchronize();
+  while (!h->blocks.empty()) dev_free(h, h->blocks.back().first);
+  delete h;
+  return HSS_OK;
+}
+
+hss_status hss_matmul(hss_handle* h, int32_t op, int32_t prec, int64_t nrhs, const void* X,
+                      int64_t ldx, void* Y, int64_t ldy, void* stream) {
+  if (!h) return -1;
+  if (op != HSS_OP_N && op != HSS_OP_T) return -2;
+  if (prec != HSS_F64 && prec != HSS_F32) return -3;
+  if (nrhs < 0) return -4;
+  if (nrhs == 0) return HSS_OK;
+  if (!X) return -5;
+  if (ldx < h->plan.n) return -6;
+  if (!Y) return -7;
+  if (ldy < h->plan.n) return -8;
+  const size_t es = prec == HSS_F64 ? 8 : 4;
+  const char* x0 = (const char*)X;
+  const char* y0 = (const char*)Y;
+  const char* x1 = x0 + es * (size_t)(ldx * (nrhs - 1) + h->plan.n);
+  const char* y1 = y0 + es * (size_t)(ldy * (nrhs - 1) + h->plan.n);
+  if (x0 < y1 && y0 < x1) return -7;   // X and Y overlap
+  hipStream_t s = (hipStream_t)stream;
+  hss_status st;
+  if (prec == HSS_F64) {
+    if ((st = ensure_work_mm<double>(h, nrhs))) return st;
+    run_matmul<double>(h, op, nrhs, (const double*)X, ldx, (double*)Y, ldy, s);
+  } else {
+    if ((st = ensure_work_mm<float>(h, nrhs))) return st;
+    run_matmul<float>(h, op, nrhs, (const float*)X, ldx, (float*)Y, ldy, s);
+  }
+  return last_launch_status();
+}
+
+hss_status hss_ulv_factor(hss_handle* h, int32_t prec, void* stream) {
+  if (!h) return -1;
+  if (prec != HSS_F64 && prec != HSS_F32) return -2;
+  hipStream_t s = (hipStream_t)stream;
+  hss_status st;
+  launch_fill(reinterpret_cast<double*>(h->d_status), 0.0, 2, s);
+  if (prec == HSS_F64) {
+    if ((st = ensure_factors<double>(h))) return st;
+    run_factor<double>(h, s);
+    h->f64.valid = true;
+  } else {
+    if ((st = ensure_factors<float>(h))) return st;
+    run_factor<float>(h, s);
+    h->f32.valid = true;
+  }
+  return last_launch_status();
+}
+
+hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
+                         const hss_solve_opts* o, hss_solve_info* info, void* stream) {
+  if (!h) return -1;
+  if (nrhs < 0) return -2;
+  if (nrhs > 0 && !B) return -3;
+  if (ldb < h->plan.n) return -4;
+  hss_solve_opts opt{HSS_F64, 10, 0.0, 0, 0};
+  if (o) opt = *o;
+  if (opt.prec != HSS_F64 && opt.prec != HSS_F32) return -5;
+  if (opt.max_refine < 0 || !(opt.tol >= 0.0)) return -5;
+  const bool is64 = opt.prec == HSS_F64;
+  if (is64 ? !h->f64.valid : !h->f32.valid) return HSS_ESTATE;
+  if (info) {
+    info->eta_max = 0.0;
+    info->iters = 0;
+    info->status = HSS_OK;
+    info->norm2 = h->norm2;
+  }
+  if (nrhs == 0) return HSS_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = h->plan.n;
+  const bool need_eta = opt.want_eta || opt.tol > 0.0;
+  hss_status st;
+  if (need_eta && (st = compute_norm2(h, s))) return st;
+  if (is64) {
+    if ((st = ensure_work_sv<double>(h, nrhs))) return st;
+  } else {
+    if ((st = ensure_work_sv<float>(h, nrhs))) return st;
+  }
+  if ((st = ensure_ir(h, nrhs))) return st;
+  if (need_eta && (st = ensure_work_mm<double>(h, nrhs))) return st;
+  double* ss = h->stats;      // rr | xx | bb | rmax | bmax | eta | out
+  double* rr = ss;
+  double* xx = ss + nrhs;
+  double* bb = ss + 2 * nrhs;
+  double* rmax = ss + 3 * nrhs;
+  double* bmax = ss + 4 * nrhs;
+  double* eta = ss + 5 * nrhs;
+  double* outv = ss + 6 * nrhs;
+  if (need_eta) launch_copy2d(B, ldb, h->b0, n, n, nrhs, s);
+  // first solve
+  auto correction_solve = [&](const double* rhs, int64_t ldr, double* x, int64_t ldx,
+                              bool accumulate) {
+    if (is64) {
+      double* d = accumulate ? h->d64 : x;
+      const int64_t ldd = accumulate ? n : ldx;
+      if (rhs != d) launch_copy2d(rhs, ldr, d, ldd, n, nrhs, s);
+      run_solve<double>(h, nrhs, d, ldd, s);
+      if (accumulate) launch_axpy64(d, ldd, x, ldx, n, nrhs, s);
+    } else {
+      // scale each column by its max |.| before rounding to FP32
+      launch_fill(bmax, 0.0, nrhs, s);
+      launch_fill(rr, 0.0, nrhs, s);
+      launch_colstats(rhs, ldr, n, nrhs, rr, bmax, s);
+      launch_scale_cast(rhs, ldr, h->r32, n, n, nrhs, bmax, s);
+      run_solve<float>(h, nrhs, h->r32, n, s);
+      if (accumulate) launch_axpy_cast(h->r32, n, x, ldx, n, nrhs, bmax, s);
+      else launch_cast_back(h->r32, n, x, ldx, n, nrhs, bmax, s);
+    }
+  };
+  correction_solve(B, ldb, B, ldb, false);
+  if (!need_eta && !info) return last_launch_status();
+  int iters = 0;
+  double eta_max = 0.0;
+  if (need_eta) {
+    launch_fill(bb, 0.0, nrhs, s);
+    launch_colstats(h->b0, n, n, nrhs, bb, nullptr, s);
+    for (;;) {
+      run_matmul<double>(h, HSS_OP_N, nrhs, B, ldb, h->res, n, s);
+      launch_residual(h->b0, n, h->res, n, n, nrhs, s);
+      launch_fill(rr, 0.0, 2 * nrhs, s);
+      launch_fill(rmax, 0.0, nrhs, s);
+      launch_colstats(h->res, n, n, nrhs, rr, rmax, s);
+      launch_colstats(B, ldb, n, nrhs, xx, nullptr, s);
+      launch_eta(rr, xx, bb, h->norm2, nrhs, eta, outv, s);
+      if ((st = last_launch_status())) return st;
+      if (hipMemcpyAsync(&eta_max, outv, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return HSS_EHIP;
+      if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
+      if (opt.tol <= 0.0 || eta_max <= opt.tol || iters >= opt.max_refine) break;
+      correction_solve(h->res, n, B, ldb, true);
+      ++iters;
+    }
+  }
+  if ((st = last_launch_status())) return st;
+  int32_t dstat = 0;
+  if (hipMemcpyAsync(&dstat, h->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return HSS_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
+  hss_status result = HSS_OK;
+  if (dstat & (1 << HSS_ESINGULAR)) result = HSS_ESINGULAR;
+  else if (need_eta && opt.tol > 0.0 && eta_max > opt.tol) result = HSS_ENOCONV;
+  if (info) {
+    info->eta_max = eta_max;
+    info->iters = iters;
+    info->status = result;
+    info->norm2 = h->norm2;
+    if (info->eta && need_eta) {
+      if (hipMemcpy(info->eta, eta, sizeof(double) * nrhs, hipMemcpyDeviceToHost) != hipSuccess)
+        return HSS_EHIP;
+    }
+  }
+  return result;
+}
+
+hss_status hss_query(hss_handle* h, int32_t key, void* out, void* stream) {
+  if (!h) return -1;
+  if (!out) return -3;
+  switch (key) {
+    case HSS_Q_N: *(int64_t*)out = h->plan.n; return HSS_OK;
+    case HSS_Q_P: *(int32_t*)out = h->plan.p; return HSS_OK;
+    case HSS_Q_RESIDENT_BYTES: *(int64_t*)out = h->resident; return HSS_OK;
+    case HSS_Q_GEN_ENTRIES: *(int64_t*)out = h->plan.gen_entries(); return HSS_OK;
+    case HSS_Q_FACTOR_ENTRIES: *(int64_t*)out = h->plan.factor_entries(); return HSS_OK;
+    case HSS_Q_NORM2: {
+      const hss_status st = compute_norm2(h, (hipStream_t)stream);
+      if (st) return st;
+      *(double*)out = h->norm2;
+      return HSS_OK;
+    }
+    default: return -2;
+  }
+}
+
+hss_status hss_batch_matmul(hss_handle* const* hs, int32_t count, int32_t op, int32_t prec,
+                            const int64_t* nrhs, const void* const* X, const int64_t* ldx,
+                            void* const* Y, const int64_t* ldy, void* stream) {
+  if (!hs) return -1;
+  if (count < 0) return -2;
+  for (int32_t i = 0; i < count; ++i) {
+    const hss_status st = hss_matmul(hs[i], op, prec, nrhs[i], X[i], ldx[i], Y[i], ldy[i], stream);
+    if (st) return st;
+  }
+  return HSS_OK;
+}
+
+hss_status hss_batch_ulv_factor(hss_handle* const* hs, int32_t count, int32_t prec, void* stream) {
+  if (!hs) return -1;
+  if (count < 0) return -2;
+  for (int32_t i = 0; i < count; ++i) {
+    const hss_status st = hss_ulv_factor(hs[i], prec, stream);
+    if (st) return st;
+  }
+  return HSS_OK;
+}
+
+hss_status hss_batch_ulv_solve(hss_handle* const* hs, int32_t count, const int64_t* nrhs,
+                               double* const* B, const int64_t* ldb, const hss_solve_opts* o,
+                               hss_solve_info* info, void* stream) {
+  if (!hs) return -1;
+  if (count < 0) return -2;
+  hss_status worst = HSS_OK;
+  for (int32_t i = 0; i < count; ++i) {
+    const hss_status st = hss_ulv_solve(hs[i], nrhs[i], B[i], ldb[i], o, info ? info + i : nullptr,
+                                        stream);
+    if (st < 0 || st == HSS_EHIP || st == HSS_ENOMEM || st == HSS_ESTATE) return st;
+    if (st) worst = st;
+  }
+  return worst;
+}
+
+}  // extern "C"

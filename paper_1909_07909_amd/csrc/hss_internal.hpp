@@ -1,0 +1,97 @@
+// Internal structures shared by the HIP kernels and the host engine.
+//
+// Device data of one matrix ("instance"):
+//   * generators in the canonical packed layout of include/hss.h, FP64 and a
+//     resident FP32 copy (same offsets);
+//   * a node table (NodeInfo, heap order) with every size and offset the
+//     kernels need, so a kernel reads one small record per node;
+//   * per-precision factor arrays (Sec. 4.3 Step 1 and the merged levels):
+//       FD  mp x mp per node: rows 0..e-1 hold L (lower, diagonal included)
+//           and the Householder vectors of the LQ step (right of the
+//           diagonal); rows e..mp-1 hold [D~21 | D~22];
+//       FU  mp x ku per node: Householder vectors of the QL step above the
+//           pivot rows, U~ = the trailing kept rows (lower triangular when e>0);
+//       FV  mp x kv per node: Z^T V' (leading e rows V^_top, trailing V^_bot);
+//       tq, tz  the Householder scalars; the root block is LU-factored in
+//           FP64 (rootLU, piv);
+//   * work vectors for the product (x^ up values, y^ down values) and the
+//     solve (c, z, y, x^), node blocks stacked with one leading dimension.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hss {
+
+constexpr int kMaxBlock = 128;   // largest leaf / merged block the kernels take
+constexpr int kMaxRank = 64;     // largest ku / kv
+constexpr int kNT = 256;         // threads per work-group of the per-node kernels
+constexpr int kRT = 32;          // right-hand-side columns per work-group tile
+
+struct NodeInfo {
+  int64_t row0;    // first row of I_t
+  int32_t m;       // |I_t|
+  int32_t ku, kv;  // basis ranks (0 at the root)
+  int32_t mp;      // size of the block factored at t: leaf m, internal kept_c1 + kept_c2
+  int32_t e;       // eliminated rows/cols: max(mp - ku, 0); 0 at the root
+  int32_t kept;    // mp - e
+  int32_t level;
+  int32_t is_leaf;
+  // generator offsets (elements); -1 where absent
+  int64_t oD, oU, oV, oR, oW, oB12, oB21;
+  // product work offsets (rows; capacity max(ku, kv))
+  int64_t oxh, oyh;
+  // factor offsets (elements)
+  int64_t oFD, oFU, oFV, otq, otz;
+  // solve work offsets (rows): c and x^ have kept rows, z has kv rows, y e rows
+  int64_t oc, oz, oy, ox;
+};
+
+template <typename T>
+struct Inst {
+  const NodeInfo* nodes;
+  const T *D, *U, *V, *R, *W, *B12, *B21;
+  T *FD, *FU, *FV, *tq, *tz;
+  double* rootLU;
+  int32_t* piv;
+  T *xh, *yh;       // product work, leading dimension ldm
+  int64_t ldm;
+  T *wc, *wz, *wy, *wx;   // solve work, leading dimension lds
+  int64_t lds;
+  int32_t* status;  // device status word (HSS_ESINGULAR ...)
+  int32_t p;
+  int32_t nnodes;
+};
+
+template <typename T>
+struct CallMM {
+  const T* X;
+  T* Y;
+  int64_t ldx, ldy;
+  int32_t nrhs;
+  int32_t op;
+};
+
+template <typename T>
+struct CallSV {
+  T* B;           // right-hand sides / solution in precision T
+  int64_t ldb;
+  int32_t nrhs;
+  int32_t pad;
+};
+
+// Kernel argument bundle: single-instance launches pass the instance and the
+// call by value and address nodes node0 + blockIdx.x; batched launches pass
+// device arrays and a task list of (instance, node) pairs.
+template <typename T, typename Call>
+struct KArgs {
+  Inst<T> inst;
+  Call call;
+  const Inst<T>* insts;
+  const Call* calls;
+  const int2* tasks;
+  int32_t node0;
+  int32_t ntasks;
+};
+
+}  // namespace hss

@@ -1,0 +1,54 @@
+// Host-side launchers of the HIP kernels (one launch = one tree level or one
+// per-node step over a task list).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hss_internal.hpp"
+
+namespace hss {
+
+enum class MMStep { LeafUp, Up, Couple, Down, LeafOut };
+
+template <typename T>
+void launch_mm_level(MMStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int ytiles,
+                     int max_rows, hipStream_t s);
+
+// Fused leaf kernels for the uniform-tree fast path (see kernels_mm_fast.hip).
+enum class UlvStep { Merge, Factor, RootLU, Fwd, Root, Bwd };
+
+template <typename T>
+void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int ytiles,
+                int max_mp, hipStream_t s);
+
+// Elementwise / reduction helpers (kernels_util.hip).
+void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+// dst[i + j*ldd] = (float)(src[i + j*lds] * scale[j])   (scale may be null -> 1)
+void launch_scale_cast(const double* src, int64_t lds, float* dst, int64_t ldd, int64_t n,
+                       int64_t nrhs, const double* scale, hipStream_t s);
+// x[i + j*ldx] += scale[j] * d[i + j*ldd]
+void launch_axpy_cast(const float* d, int64_t ldd, double* x, int64_t ldx, int64_t n,
+                      int64_t nrhs, const double* scale, hipStream_t s);
+// r = b - r (in place on r), column-major n x nrhs
+void launch_residual(const double* b, int64_t ldb, double* r, int64_t ldr, int64_t n,
+                     int64_t nrhs, hipStream_t s);
+// sums[j] (+)= sum_i a[i+j*lda]^2 ; maxabs[j] = max |a| (optional)
+void launch_colstats(const double* a, int64_t lda, int64_t n, int64_t nrhs, double* sumsq,
+                     double* maxabs, hipStream_t s);
+void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                   int64_t nrhs, hipStream_t s);
+void launch_fill(double* p, double v, int64_t n, hipStream_t s);
+// dst = scale[j] * (double)src
+void launch_cast_back(const float* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                      int64_t nrhs, const double* scale, hipStream_t s);
+// dst += src (FP64)
+void launch_axpy64(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                   int64_t nrhs, hipStream_t s);
+void launch_normalize(const double* src, double* dst, int64_t n, const double* sumsq,
+                      hipStream_t s);
+void launch_hash_fill(double* d, int64_t n, uint64_t seed, hipStream_t s);
+// eta[j] = sqrt(rr[j]) / (normA * sqrt(xx[j]) + sqrt(bb[j])); out[0] = max eta;
+// scale[j] = max|r_j| (for the next correction), flags
+void launch_eta(const double* rr, const double* xx, const double* bb, double normA, int64_t nrhs,
+                double* eta, double* out, hipStream_t s);
+
+}  // namespace hss

@@ -1,0 +1,215 @@
+// Elementwise and column-reduction kernels around the HSS path: the resident
+// FP32 generator copy, the FP64 residual of iterative refinement, per-column
+// norms and the backward error of Sec. 5.1.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace hss {
+
+namespace {
+constexpr int kB = 256;
+
+inline int grid_for(int64_t n, int cap = 8192) {
+  int64_t g = (n + kB - 1) / kB;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+__global__ void k_cast(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    d[i] = (float)s[i];
+}
+
+__global__ void k_scale_cast(const double* __restrict__ s, int64_t lds, float* __restrict__ d,
+                             int64_t ldd, int64_t n, const double* __restrict__ scale) {
+  const int64_t j = blockIdx.y;
+  // a zero column stays zero (its scale is 0)
+  const double f = scale ? (scale[j] > 0.0 ? 1.0 / scale[j] : 0.0) : 1.0;
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    d[i + j * ldd] = (float)(s[i + j * lds] * f);
+}
+
+__global__ void k_axpy_cast(const float* __restrict__ dd, int64_t ldd, double* __restrict__ x,
+                            int64_t ldx, int64_t n, const double* __restrict__ scale) {
+  const int64_t j = blockIdx.y;
+  const double f = scale ? scale[j] : 1.0;
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    x[i + j * ldx] += f * (double)dd[i + j * ldd];
+}
+
+__global__ void k_residual(const double* __restrict__ b, int64_t ldb, double* __restrict__ r,
+                           int64_t ldr, int64_t n) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    r[i + j * ldr] = b[i + j * ldb] - r[i + j * ldr];
+}
+
+__global__ void k_cast_back(const float* __restrict__ s, int64_t lds, double* __restrict__ d,
+                            int64_t ldd, int64_t n, const double* __restrict__ scale) {
+  const int64_t j = blockIdx.y;
+  const double f = scale ? scale[j] : 1.0;
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    d[i + j * ldd] = f * (double)s[i + j * lds];
+}
+
+__global__ void k_axpy64(const double* __restrict__ s, int64_t lds, double* __restrict__ d,
+                         int64_t ldd, int64_t n) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    d[i + j * ldd] += s[i + j * lds];
+}
+
+// dst = src / sqrt(sumsq[0]) (power-method normalization, no host round trip)
+__global__ void k_normalize(const double* __restrict__ s, double* __restrict__ d, int64_t n,
+                            const double* __restrict__ sumsq) {
+  const double nr = sqrt(sumsq[0]);
+  const double f = nr > 0.0 ? 1.0 / nr : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    d[i] = s[i] * f;
+}
+
+// deterministic start vector in [-1, 1) (splitmix64 of the index)
+__global__ void k_hash_fill(double* d, int64_t n, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+    uint64_t z = (uint64_t)i + seed + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    d[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
+__global__ void k_copy2d(const double* __restrict__ s, int64_t lds, double* __restrict__ d,
+                         int64_t ldd, int64_t n) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    d[i + j * ldd] = s[i + j * lds];
+}
+
+__global__ void k_fill(double* p, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    p[i] = v;
+}
+
+// Per-column sum of squares and max |.|; sumsq / maxabs must start at 0.
+__global__ void k_colstats(const double* __restrict__ a, int64_t lda, int64_t n,
+                           double* __restrict__ sumsq, double* __restrict__ maxabs) {
+  const int64_t j = blockIdx.y;
+  double s = 0.0, mx = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+    const double v = a[i + j * lda];
+    s += v * v;
+    mx = fmax(mx, fabs(v));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+  }
+  __shared__ double ss[kB / 64], sm[kB / 64];
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (l == 0) { ss[w] = s; sm[w] = mx; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0, m = 0.0;
+    for (int q = 0; q < kB / 64; ++q) { t += ss[q]; m = fmax(m, sm[q]); }
+    atomicAdd(&sumsq[j], t);
+    if (maxabs) {
+      // non-negative doubles order like their bit patterns
+      atomicMax(reinterpret_cast<unsigned long long*>(&maxabs[j]),
+                (unsigned long long)__double_as_longlong(m));
+    }
+  }
+}
+
+__global__ void k_eta(const double* rr, const double* xx, const double* bb, double normA,
+                      int64_t nrhs, double* eta, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double mx = 0.0;
+  for (int64_t j = 0; j < nrhs; ++j) {
+    const double den = normA * sqrt(xx[j]) + sqrt(bb[j]);
+    const double v = den > 0.0 ? sqrt(rr[j]) / den : (rr[j] > 0.0 ? INFINITY : 0.0);
+    eta[j] = v;
+    mx = fmax(mx, v);
+  }
+  out[0] = mx;
+}
+}  // namespace
+
+void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_cast, dim3(grid_for(n)), dim3(kB), 0, s, src, dst, n);
+}
+
+void launch_scale_cast(const double* src, int64_t lds, float* dst, int64_t ldd, int64_t n,
+                       int64_t nrhs, const double* scale, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_scale_cast, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, src, lds, dst,
+                     ldd, n, scale);
+}
+
+void launch_axpy_cast(const float* d, int64_t ldd, double* x, int64_t ldx, int64_t n,
+                      int64_t nrhs, const double* scale, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_axpy_cast, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, d, ldd, x, ldx,
+                     n, scale);
+}
+
+void launch_residual(const double* b, int64_t ldb, double* r, int64_t ldr, int64_t n,
+                     int64_t nrhs, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_residual, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, b, ldb, r, ldr,
+                     n);
+}
+
+void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                   int64_t nrhs, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_copy2d, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, src, lds, dst, ldd,
+                     n);
+}
+
+void launch_cast_back(const float* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                      int64_t nrhs, const double* scale, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_cast_back, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, src, lds, dst,
+                     ldd, n, scale);
+}
+
+void launch_axpy64(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                   int64_t nrhs, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_axpy64, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, src, lds, dst, ldd,
+                     n);
+}
+
+void launch_normalize(const double* src, double* dst, int64_t n, const double* sumsq,
+                      hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_normalize, dim3(grid_for(n)), dim3(kB), 0, s, src, dst, n, sumsq);
+}
+
+void launch_hash_fill(double* d, int64_t n, uint64_t seed, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_hash_fill, dim3(grid_for(n)), dim3(kB), 0, s, d, n, seed);
+}
+
+void launch_fill(double* p, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kB), 0, s, p, v, n);
+}
+
+void launch_colstats(const double* a, int64_t lda, int64_t n, int64_t nrhs, double* sumsq,
+                     double* maxabs, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_colstats, dim3(grid_for(n, 256), nrhs), dim3(kB), 0, s, a, lda, n, sumsq,
+                     maxabs);
+}
+
+void launch_eta(const double* rr, const double* xx, const double* bb, double normA, int64_t nrhs,
+                double* eta, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_eta, dim3(1), dim3(64), 0, s, rr, xx, bb, normA, nrhs, eta, out);
+}
+
+}  // namespace hss

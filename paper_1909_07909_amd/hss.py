@@ -1,0 +1,302 @@
+"""Python binding of libhss.so (include/hss.h): argument marshalling only.
+
+Every step of the HSS product and of the ULV factorization / solve runs in
+the library's HIP kernels.  PyTorch provides device memory and the stream;
+matrices are passed as column-major views: an n x r block is a tensor of
+shape (n, r) with strides (1, ld).  If the library is missing this module
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhss.so")
+
+HSS_OK, HSS_ENOMEM, HSS_EHIP, HSS_ESTATE, HSS_ESINGULAR, HSS_ENOCONV, HSS_EUNSUP = range(7)
+OP_N, OP_T = 0, 1
+F64, F32 = 0, 1
+
+# Every symbol include/hss.h declares.
+EXPORTS = (
+    "hss_create", "hss_destroy", "hss_matmul", "hss_ulv_factor", "hss_ulv_solve", "hss_query",
+    "hss_plan_depth", "hss_plan_leaf_offsets", "hss_plan_node_ranges", "hss_batch_matmul",
+    "hss_batch_ulv_factor", "hss_batch_ulv_solve", "hss_status_str",
+)
+
+Q_N, Q_P, Q_RESIDENT_BYTES, Q_NORM2, Q_GEN_ENTRIES, Q_FACTOR_ENTRIES = range(6)
+
+
+class TreeDesc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("p", C.c_int32), ("reserved", C.c_int32),
+                ("leaf_off", C.POINTER(C.c_int64)), ("ku", C.POINTER(C.c_int32)),
+                ("kv", C.POINTER(C.c_int32))]
+
+
+class GenHost(C.Structure):
+    _fields_ = [(k, C.POINTER(C.c_double)) for k in ("D", "U", "V", "R", "W", "B12", "B21")]
+
+
+class Alloc(C.Structure):
+    _fields_ = [("alloc", C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)),
+                ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)),
+                ("ctx", C.c_void_p)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("max_refine", C.c_int32), ("tol", C.c_double),
+                ("want_eta", C.c_int32), ("reserved", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("eta_max", C.c_double), ("norm2", C.c_double), ("iters", C.c_int32),
+                ("status", C.c_int32), ("eta", C.POINTER(C.c_double))]
+
+
+class HSSError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: status {code} ({status_str(code)})")
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libhss.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1909_07909_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.hss_create.argtypes = [C.POINTER(TreeDesc), C.POINTER(GenHost), C.POINTER(Alloc), vp,
+                             C.POINTER(vp)]
+    L.hss_destroy.argtypes = [vp]
+    L.hss_matmul.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp]
+    L.hss_ulv_factor.argtypes = [vp, i32, vp]
+    L.hss_ulv_solve.argtypes = [vp, i64, vp, i64, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+    L.hss_query.argtypes = [vp, i32, vp, vp]
+    L.hss_plan_depth.argtypes = [i64, i64]
+    L.hss_plan_leaf_offsets.argtypes = [i64, i64, C.POINTER(C.c_int64), i64]
+    L.hss_plan_node_ranges.argtypes = [C.POINTER(TreeDesc), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64)]
+    L.hss_batch_matmul.argtypes = [C.POINTER(vp), i32, i32, i32, C.POINTER(C.c_int64),
+                                   C.POINTER(vp), C.POINTER(C.c_int64), C.POINTER(vp),
+                                   C.POINTER(C.c_int64), vp]
+    L.hss_batch_ulv_factor.argtypes = [C.POINTER(vp), i32, i32, vp]
+    L.hss_batch_ulv_solve.argtypes = [C.POINTER(vp), i32, C.POINTER(C.c_int64), C.POINTER(vp),
+                                      C.POINTER(C.c_int64), C.POINTER(SolveOpts),
+                                      C.POINTER(SolveInfo), vp]
+    L.hss_status_str.argtypes = [i32]
+    L.hss_status_str.restype = C.c_char_p
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name != "hss_status_str" and f.restype is not C.c_char_p:
+            f.restype = C.c_int32
+    _lib = L
+    return L
+
+
+def status_str(code: int) -> str:
+    return lib().hss_status_str(code).decode()
+
+
+def _check(code, where):
+    if code != HSS_OK:
+        raise HSSError(code, where)
+
+
+def plan_depth(n: int, nmin: int) -> int:
+    return int(lib().hss_plan_depth(n, nmin))
+
+
+def plan_leaf_offsets(n: int, nmin: int) -> np.ndarray:
+    p = plan_depth(n, nmin)
+    out = np.zeros(2 ** p + 1, dtype=np.int64)
+    _check(lib().hss_plan_leaf_offsets(n, nmin, out.ctypes.data_as(C.POINTER(C.c_int64)),
+                                       out.size), "hss_plan_leaf_offsets")
+    return out
+
+
+def _tree(n, p, leaf_off, ku, kv):
+    lo = np.ascontiguousarray(leaf_off, dtype=np.int64)
+    ku = np.ascontiguousarray(ku, dtype=np.int32)
+    kv = np.ascontiguousarray(kv, dtype=np.int32)
+    td = TreeDesc(n, p, 0, lo.ctypes.data_as(C.POINTER(C.c_int64)),
+                  ku.ctypes.data_as(C.POINTER(C.c_int32)), kv.ctypes.data_as(C.POINTER(C.c_int32)))
+    return td, (lo, ku, kv)
+
+
+def plan_node_ranges(n, p, leaf_off, ku, kv):
+    td, keep = _tree(n, p, leaf_off, ku, kv)
+    nn = 2 ** (p + 1) - 1
+    start = np.zeros(nn, dtype=np.int64)
+    size = np.zeros(nn, dtype=np.int64)
+    _check(lib().hss_plan_node_ranges(C.byref(td), start.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      size.ctypes.data_as(C.POINTER(C.c_int64))),
+           "hss_plan_node_ranges")
+    return start, size
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(stream)
+
+
+def colmajor(t, n):
+    """(ptr, ld) of a column-major (n, r) tensor view (strides (1, ld))."""
+    if t.dim() != 2 or t.shape[0] != n:
+        raise ValueError(f"expected an ({n}, r) tensor, got {tuple(t.shape)}")
+    if t.shape[1] > 1 and t.stride(0) != 1:
+        raise ValueError("tensor must be column-major: strides (1, ld)")
+    if t.shape[1] == 1 and t.stride(0) != 1:
+        raise ValueError("tensor must have unit row stride")
+    ld = t.stride(1) if t.shape[1] > 1 else max(t.stride(1), n)
+    return C.c_void_p(t.data_ptr()), ld
+
+
+def empty_colmajor(n, r, dtype, device="cuda"):
+    import torch
+    return torch.empty((r, n), dtype=dtype, device=device).t()
+
+
+class HSSMatrix:
+    """Device-resident HSS matrix created from generators in the canonical
+    packed layout (attributes n, p, leaf_off, ku, kv, D, U, V, R, W, B12, B21)."""
+
+    def __init__(self, g, stream=None, alloc=None):
+        L = lib()
+        td, self._keep = _tree(g.n, g.p, g.leaf_off, g.ku, g.kv)
+        arrs = [np.ascontiguousarray(getattr(g, k), dtype=np.float64)
+                for k in ("D", "U", "V", "R", "W", "B12", "B21")]
+        gh = GenHost(*[a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs])
+        h = C.c_void_p()
+        code = L.hss_create(C.byref(td), C.byref(gh), C.byref(alloc) if alloc else None,
+                            _stream(stream), C.byref(h))
+        _check(code, "hss_create")
+        self.h = h
+        self.n = int(g.n)
+        self.p = int(g.p)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hss_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matmul(self, X, Y=None, op=OP_N, stream=None):
+        """Y = op(A) X for a column-major (n, r) CUDA tensor (float64 or float32)."""
+        import torch
+        prec = F64 if X.dtype == torch.float64 else F32
+        if X.dtype not in (torch.float64, torch.float32):
+            raise TypeError("X must be float64 or float32")
+        r = X.shape[1]
+        if Y is None:
+            Y = empty_colmajor(self.n, r, X.dtype, X.device)
+        xp, ldx = colmajor(X, self.n)
+        yp, ldy = colmajor(Y, self.n)
+        _check(lib().hss_matmul(self.h, op, prec, r, xp, ldx, yp, ldy, _stream(stream)),
+               "hss_matmul")
+        return Y
+
+    def factor(self, prec=F64, stream=None):
+        _check(lib().hss_ulv_factor(self.h, prec, _stream(stream)), "hss_ulv_factor")
+
+    def solve(self, B, prec=F64, tol=0.0, max_refine=10, want_eta=False, stream=None,
+              check=True):
+        """B <- A^{-1} B in place (column-major float64 CUDA tensor).  Returns
+        a dict with eta (per column), eta_max, iters, status, norm2."""
+        r = B.shape[1]
+        bp, ldb = colmajor(B, self.n)
+        opts = SolveOpts(prec, max_refine, tol, 1 if want_eta else 0, 0)
+        eta = np.zeros(max(r, 1), dtype=np.float64)
+        info = SolveInfo(0.0, 0.0, 0, 0, eta.ctypes.data_as(C.POINTER(C.c_double)))
+        code = lib().hss_ulv_solve(self.h, r, bp, ldb, C.byref(opts), C.byref(info),
+                                   _stream(stream))
+        if check and code not in (HSS_OK,):
+            raise HSSError(code, "hss_ulv_solve")
+        return {"status": int(code), "eta": eta[:r].copy(), "eta_max": info.eta_max,
+                "iters": info.iters, "norm2": info.norm2}
+
+    def solve_async(self, B, prec=F64, stream=None):
+        """Plain solve without a backward error: no synchronization."""
+        r = B.shape[1]
+        bp, ldb = colmajor(B, self.n)
+        opts = SolveOpts(prec, 0, 0.0, 0, 0)
+        _check(lib().hss_ulv_solve(self.h, r, bp, ldb, C.byref(opts), None, _stream(stream)),
+               "hss_ulv_solve")
+
+    def query(self, key, stream=None):
+        if key in (Q_N, Q_RESIDENT_BYTES, Q_GEN_ENTRIES, Q_FACTOR_ENTRIES):
+            v = C.c_int64()
+        elif key == Q_P:
+            v = C.c_int32()
+        else:
+            v = C.c_double()
+        _check(lib().hss_query(self.h, key, C.byref(v), _stream(stream)), "hss_query")
+        return v.value
+
+    def norm2(self, stream=None):
+        return self.query(Q_NORM2, stream)
+
+
+def _ptr_array(items):
+    return (C.c_void_p * len(items))(*[C.c_void_p(x) for x in items])
+
+
+def batch_factor(mats, prec=F64, stream=None):
+    hs = _ptr_array([m.h.value for m in mats])
+    _check(lib().hss_batch_ulv_factor(hs, len(mats), prec, _stream(stream)),
+           "hss_batch_ulv_factor")
+
+
+def batch_matmul(mats, Xs, Ys, op=OP_N, stream=None):
+    import torch
+    prec = F64 if Xs[0].dtype == torch.float64 else F32
+    hs = _ptr_array([m.h.value for m in mats])
+    nr = (C.c_int64 * len(mats))(*[x.shape[1] for x in Xs])
+    xp, lx, yp, ly = [], [], [], []
+    for m, x, y in zip(mats, Xs, Ys):
+        a, b = colmajor(x, m.n)
+        c, d = colmajor(y, m.n)
+        xp.append(a.value); lx.append(b); yp.append(c.value); ly.append(d)
+    _check(lib().hss_batch_matmul(hs, len(mats), op, prec, nr, _ptr_array(xp),
+                                  (C.c_int64 * len(mats))(*lx), _ptr_array(yp),
+                                  (C.c_int64 * len(mats))(*ly), _stream(stream)),
+           "hss_batch_matmul")
+
+
+def batch_solve(mats, Bs, prec=F64, tol=0.0, max_refine=10, want_eta=False, stream=None):
+    hs = _ptr_array([m.h.value for m in mats])
+    cnt = len(mats)
+    nr = (C.c_int64 * cnt)(*[b.shape[1] for b in Bs])
+    bp, lb = [], []
+    for m, b in zip(mats, Bs):
+        a, l = colmajor(b, m.n)
+        bp.append(a.value); lb.append(l)
+    opts = SolveOpts(prec, max_refine, tol, 1 if want_eta else 0, 0)
+    etas = [np.zeros(max(b.shape[1], 1)) for b in Bs]
+    infos = (SolveInfo * cnt)()
+    for i in range(cnt):
+        infos[i].eta = etas[i].ctypes.data_as(C.POINTER(C.c_double))
+    code = lib().hss_batch_ulv_solve(hs, cnt, nr, _ptr_array(bp), (C.c_int64 * cnt)(*lb),
+                                     C.byref(opts), infos, _stream(stream))
+    if code not in (HSS_OK, HSS_ENOCONV):
+        raise HSSError(code, "hss_batch_ulv_solve")
+    return [{"eta": etas[i][:Bs[i].shape[1]].copy(), "eta_max": infos[i].eta_max,
+             "iters": infos[i].iters, "status": infos[i].status} for i in range(cnt)]

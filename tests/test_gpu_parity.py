@@ -1,0 +1,141 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: matmul FP64 relative error <= 1e-12 per column (max_j
+||Y_j - Y_ref_j|| / ||Y_ref_j||); solve FP64 backward error (measured with the
+oracle's FP64 product) <= 1e-12; FP32 + refinement backward error <= 1e-10;
+FP32 products relative error <= 1e-5 (a few float ulps times the depth).
+"""
+import numpy as np
+import pytest
+
+from oracle import tree
+from oracle.hss import HSS
+from oracle.matvec import matvec as omatvec
+from oracle.ulv import solve as osolve
+from paper_1909_07909_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _hss():
+    from paper_1909_07909_amd import hss
+    return hss
+
+
+def _to_dev(X, dtype=None):
+    X = np.asfortranarray(X)
+    t = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.t()
+
+
+def _to_host(t):
+    return t.t().contiguous().cpu().numpy().T.astype(np.float64)
+
+
+def _rel(Y, R):
+    return float(np.max(np.linalg.norm(Y - R, axis=0) / np.linalg.norm(R, axis=0)))
+
+
+def _eta(H, X, B, normA):
+    Rr = B - omatvec(H, X)
+    return float(np.max(np.linalg.norm(Rr, axis=0) /
+                        (normA * np.linalg.norm(X, axis=0) + np.linalg.norm(B, axis=0))))
+
+
+CASES = [
+    # (name, n, m, k, r)
+    ("small_p4", 1024, 64, 8, 16),
+    ("ragged_tail", 1000, 64, 8, 3),
+    ("leaf_eq_rank", 96, 8, 6, 2),
+    ("wide_rhs", 2048, 128, 16, 40),
+    ("single_leaf", 50, 64, 4, 3),
+    ("k32_m128", 8192, 128, 32, 1),
+]
+
+
+def _gen(n, m, k, seed=7):
+    return inputs.synthetic_hss(tree.leaf_offsets(n, m), k, seed=seed)
+
+
+@pytest.mark.parametrize("name,n,m,k,r", CASES)
+@pytest.mark.parametrize("op", [0, 1])
+def test_matmul_f64(name, n, m, k, r, op):
+    hss = _hss()
+    print(f"[matmul f64] {name} n={n} m={m} k={k} r={r} op={op}", flush=True)
+    g = _gen(n, m, k)
+    H = HSS.from_packed(g)
+    A = hss.HSSMatrix(g)
+    X = inputs.rhs(n, r, 8)
+    Y = _to_host(A.matmul(_to_dev(X), op=op))
+    ref = omatvec(H, X, "N" if op == 0 else "T")
+    assert _rel(Y, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("name,n,m,k,r", CASES[:4])
+def test_matmul_f32(name, n, m, k, r):
+    hss = _hss()
+    g = _gen(n, m, k)
+    H = HSS.from_packed(g)
+    A = hss.HSSMatrix(g)
+    X = inputs.rhs(n, r, 8)
+    Y = _to_host(A.matmul(_to_dev(X, torch.float32)))
+    assert _rel(Y, omatvec(H, X)) <= 1e-5
+
+
+@pytest.mark.parametrize("name,n,m,k,r", CASES)
+def test_solve_f64(name, n, m, k, r):
+    hss = _hss()
+    print(f"[solve f64] {name} n={n} m={m} k={k} r={r}", flush=True)
+    g = _gen(n, m, k)
+    H = HSS.from_packed(g)
+    A = hss.HSSMatrix(g)
+    A.factor(hss.F64)
+    B = inputs.rhs(n, r, 9)
+    Bd = _to_dev(B)
+    info = A.solve(Bd, prec=hss.F64, want_eta=True)
+    X = _to_host(Bd)
+    ref = osolve(H, B)
+    normA = np.linalg.norm(H.dense(), 2) if n <= 4096 else info["norm2"]
+    assert _eta(H, X, B, normA) <= 1e-12
+    assert _rel(X, ref) <= 1e-11
+    assert info["eta_max"] <= 1e-12
+
+
+@pytest.mark.parametrize("name,n,m,k,r", CASES)
+def test_solve_f32_refined(name, n, m, k, r):
+    hss = _hss()
+    print(f"[solve f32+IR] {name} n={n} m={m} k={k} r={r}", flush=True)
+    g = _gen(n, m, k)
+    H = HSS.from_packed(g)
+    A = hss.HSSMatrix(g)
+    A.factor(hss.F32)
+    B = inputs.rhs(n, r, 10)
+    Bd = _to_dev(B)
+    info = A.solve(Bd, prec=hss.F32, tol=1e-10, max_refine=10)
+    X = _to_host(Bd)
+    assert info["eta_max"] <= 1e-10
+    assert info["iters"] <= 2
+    normA = info["norm2"]
+    assert _eta(H, X, B, normA) <= 1e-10
+
+
+def test_closed_forms_large():
+    hss = _hss()
+    n = 2 ** 16
+    lo = tree.leaf_offsets(n, 128)
+    g, f = inputs.diag_plus_lowrank(lo, 8, seed=2)
+    A = hss.HSSMatrix(g)
+    X = inputs.rhs(n, 2, 3)
+    ref = f["d"][:, None] * X + f["U"] @ (f["V"].T @ X)
+    assert _rel(_to_host(A.matmul(_to_dev(X))), ref) <= 1e-12
+    gt, d = inputs.tridiagonal(lo, seed=3)
+    T = hss.HSSMatrix(gt)
+    x = inputs.rhs(n, 1, 4)
+    ref = d["main"][:, None] * x
+    ref[:-1] += d["upper"][:, None] * x[1:]
+    ref[1:] += d["lower"][:, None] * x[:-1]
+    assert _rel(_to_host(T.matmul(_to_dev(x))), ref) <= 1e-12
