@@ -1,0 +1,286 @@
+#!/usr/bin/env python3
+"""Benchmark of the HSS solve and product path on one MI355X.
+
+Workload: synthetic HSS matrix with n = 2^18, leaf size 128 (depth 11), HSS
+rank k = 32 (orthonormal bases, core singular values 0.5 * 10^(-j/4),
+D_i = 128 I + G / sqrt(128)), seeded; one right-hand side by default.
+
+A step is one fresh-system solve to a normwise backward error <= 1e-10:
+FP32 ULV factorization, FP32 solve, FP64 residual through the FP64 HSS
+product, FP32 correction, until eta <= 1e-10 (eta is stated for every result).
+Instances rotate (default 3) so the 256 MB last-level cache does not hold the
+working set between steps.  ``value`` is fresh-system solves per second.
+
+Also reported: the same step in plain FP64 (factor + solve + eta), resident
+factor solves/s for both precisions, the FP64 product in GB/s of algorithmic
+bytes at 1 and 32 right-hand sides, per-kernel times, the roofline of the
+dominant kernel, and the FP64 oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+N, LEAF, RANK = 2 ** 18, 128, 32
+HBM_PEAK_GBS = 8000.0
+FP32_VEC_TFLOPS = 157.3
+FP64_VEC_TFLOPS = 78.6
+METRIC = "HSS solves/s & matmul GB/s, n=2^18 k=32; FP32+IR vs FP64 at 1e-10 bkwd err"
+
+
+def gen_entries(n_leaf, m, k):
+    """Generator entries of the uniform tree: leaves m^2 + 2mk, non-root
+    internal 2 * (2k x k), internal 2 * (k x k)."""
+    return n_leaf * (m * m + 2 * m * k) + (n_leaf - 2) * 2 * (2 * k * k) + (n_leaf - 1) * 2 * k * k
+
+
+def householder_flops(m, ku, kv):
+    """Flops of Step 1 on one block as the kernels implement it (unblocked
+    Householder QL of U' applied to D' and U', LQ of the leading e rows applied
+    to the trailing rows and to V'): 4 flops per (reflector entry x column)."""
+    e = max(m - ku, 0)
+    f = 0
+    if e > 0:
+        for j in range(ku):
+            L = e + j + 1
+            f += 4 * L * (m + j)
+    for i in range(e):
+        L = m - i
+        f += 4 * L * (m - i - 1 + kv)
+    return f
+
+
+def kernel_units(name, n, m, k, r):
+    """(bound, algorithmic units per launch, unit) for the kernels at the
+    uniform tree with nleaf leaves; bytes for HBM-bound kernels, flops else."""
+    nleaf = n // m
+    ew = 4 if name.endswith("f32") else 8
+    if name.startswith("ulv_factor_leaf"):
+        return ("alu", householder_flops(m, k, k) * nleaf, "flop")
+    if name.startswith("mm_leaf_out"):
+        return ("hbm", (nleaf * (m * m + m * k) + 2 * n * r + nleaf * k * r) * ew, "byte")
+    if name.startswith("mm_leaf_up"):
+        return ("hbm", (nleaf * m * k + n * r + nleaf * k * r) * ew, "byte")
+    if name.startswith("sv_fwd_leaf") or name.startswith("sv_bwd_leaf"):
+        return ("hbm", (nleaf * (m * m + 2 * m * k) + 2 * n * r) * ew, "byte")
+    return (None, None, None)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--instances", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this "
+              "build (instances shard across GPUs without communication, see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1909_07909_amd import hss, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    r = args.nrhs
+    lo = hss.plan_leaf_offsets(N, LEAF)
+    p = hss.plan_depth(N, LEAF)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    log(f"[bench] n={N} leaf={LEAF} p={p} k={RANK} r={r} instances={args.instances}")
+    mats, B0 = [], []
+    for i in range(args.instances):
+        g = inputs.synthetic_hss(lo, RANK, seed=2 + 1000 * i)
+        mats.append(hss.HSSMatrix(g))
+        b = inputs.rhs(N, r, 3 + i)
+        B0.append(torch.from_numpy(np.ascontiguousarray(b.T)).to(dev).t())
+        del g
+    G = mats[0].query(hss.Q_GEN_ENTRIES)
+    assert G == gen_entries(2 ** p, LEAF, RANK)
+    log(f"[bench] created {args.instances} instances, {G} generator entries each")
+    work = [hss.empty_colmajor(N, r, torch.float64) for _ in mats]
+    for A in mats:
+        A.norm2()   # cached power-method estimate (not part of a step)
+
+    def step_fresh(i, prec, tol):
+        A = mats[i % len(mats)]
+        W = work[i % len(mats)]
+        W.copy_(B0[i % len(mats)])
+        A.factor(prec)
+        if prec == hss.F32:
+            return A.solve(W, prec=hss.F32, tol=tol, max_refine=10)
+        return A.solve(W, prec=hss.F64, want_eta=True)
+
+    def step_resident(i, prec, tol):
+        A = mats[i % len(mats)]
+        W = work[i % len(mats)]
+        W.copy_(B0[i % len(mats)])
+        if prec == hss.F32:
+            return A.solve(W, prec=hss.F32, tol=tol, max_refine=10)
+        return A.solve(W, prec=hss.F64, want_eta=True)
+
+    def timed(fn, steps, warmup, *a):
+        for i in range(warmup):
+            fn(i, *a)
+        torch.cuda.synchronize()
+        etas = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            info = fn(i, *a)
+            etas.append((info["eta_max"], info["iters"]))
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, etas
+
+    K, W = args.steps, args.warmup
+    # headline: FP32 + refinement, fresh systems
+    t32, e32 = timed(step_fresh, K, W, hss.F32, 1e-10)
+    log(f"[bench] fresh FP32+IR: {t32*1e3:.3f} ms/solve, eta_max {max(e for e, _ in e32):.2e}, "
+        f"iters {max(i for _, i in e32)}")
+    t64, e64 = timed(step_fresh, K, W, hss.F64, 0.0)
+    log(f"[bench] fresh FP64   : {t64*1e3:.3f} ms/solve, eta_max {max(e for e, _ in e64):.2e}")
+    # resident factors (both precisions factored)
+    for A in mats:
+        A.factor(hss.F32)
+        A.factor(hss.F64)
+    torch.cuda.synchronize()
+    rt32, re32 = timed(step_resident, K, W, hss.F32, 1e-10)
+    rt64, re64 = timed(step_resident, K, W, hss.F64, 0.0)
+    log(f"[bench] resident FP32+IR {rt32*1e3:.3f} ms, FP64 {rt64*1e3:.3f} ms")
+
+    # FP64 product at 1 and 32 right-hand sides (GB/s of algorithmic bytes)
+    mm = {}
+    for rr in (1, 32):
+        Xs = [hss.empty_colmajor(N, rr, torch.float64) for _ in mats]
+        Ys = [hss.empty_colmajor(N, rr, torch.float64) for _ in mats]
+        for x in Xs:
+            x.normal_()
+        for i in range(W):
+            mats[i % len(mats)].matmul(Xs[i % len(mats)], Ys[i % len(mats)])
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for i in range(K):
+            mats[i % len(mats)].matmul(Xs[i % len(mats)], Ys[i % len(mats)])
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) * 1e3 / K
+        byt = (G + 2 * N * rr) * 8
+        mm[f"r{rr}"] = {"us": round(us, 2), "algorithmic_bytes": byt,
+                        "gbps": round(byt / us / 1e3, 1),
+                        "frac_hbm_peak": round(byt / us / 1e3 / HBM_PEAK_GBS, 4)}
+        log(f"[bench] FP64 matmul r={rr}: {us:.1f} us, {byt / us / 1e3:.1f} GB/s")
+
+    # per-kernel times (events around every launch) of the headline step, the
+    # FP64 step and the FP64 product
+    def kernel_times(fn, reps):
+        hss.timing_enable(True)
+        hss.timing_report(reset=True)
+        for i in range(reps):
+            fn(i)
+        torch.cuda.synchronize()
+        rep = hss.timing_report(reset=True)
+        hss.timing_enable(False)
+        rep.sort(key=lambda d: -d["total_ms"])
+        return rep
+
+    rep = kernel_times(lambda i: step_fresh(i, hss.F32, 1e-10), K)
+    kernels = [{"kernel": d["kernel"], "launches_per_step": d["launches"] / K,
+                "ms_per_step": round(d["total_ms"] / K, 4)} for d in rep]
+    log("[bench] kernels per FP32+IR step: " + ", ".join(
+        f"{d['kernel']} {d['ms_per_step']:.3f}ms" for d in kernels[:10]))
+    rep64 = kernel_times(lambda i: step_fresh(i, hss.F64, 0.0), K)
+    log("[bench] kernels per FP64 step: " + ", ".join(
+        f"{d['kernel']} {d['total_ms'] / K:.3f}ms" for d in rep64[:10]))
+    for rr in (1, 32):
+        Xm = hss.empty_colmajor(N, rr, torch.float64).normal_()
+        Ym = hss.empty_colmajor(N, rr, torch.float64)
+        repm = kernel_times(lambda i: mats[i % len(mats)].matmul(Xm, Ym), K)
+        mm[f"r{rr}"]["kernels_us"] = {d["kernel"]: round(d["total_ms"] / K * 1e3, 2)
+                                      for d in repm}
+        log(f"[bench] matmul r={rr} kernels (us): " + ", ".join(
+            f"{d['kernel']} {d['total_ms'] / K * 1e3:.1f}" for d in repm))
+    roof = None
+    for d in rep:
+        bound, units, unit = kernel_units(d["kernel"], N, LEAF, RANK, r)
+        if bound is None:
+            continue
+        avg_s = d["total_ms"] / d["launches"] / 1e3
+        if bound == "hbm":
+            ach = units / avg_s / 1e9
+            roof = {"kernel": d["kernel"], "bound": "hbm", "achieved": round(ach, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2)}
+        else:
+            pk = FP32_VEC_TFLOPS if d["kernel"].endswith("f32") else FP64_VEC_TFLOPS
+            ach = units / avg_s / 1e12
+            roof = {"kernel": d["kernel"], "bound": "alu", "achieved": round(ach, 3),
+                    "peak": pk, "unit": "TFLOP/s", "frac": round(ach / pk, 4),
+                    "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2)}
+        break
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(lo, r)
+        log(f"[bench] cpu oracle: {cpu}")
+
+    out = {
+        "metric": METRIC, "value": round(1.0 / t32, 2), "unit": "solves/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": round(t32 * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64ir", "data": "synthetic",
+        "config": {"workload": f"HSS fresh-system solve to eta<=1e-10, n={N}, leaf={LEAF}, "
+                               f"depth={p}, k={RANK}, nrhs={r}, synthetic generators, "
+                               f"{args.instances} rotating instances",
+                   "n": N, "leaf": LEAF, "k": RANK, "nrhs": r},
+        "eta_max": max(e for e, _ in e32), "refine_iters_max": max(i for _, i in e32),
+        "fp64_solves_per_s": round(1.0 / t64, 2), "fp64_eta_max": max(e for e, _ in e64),
+        "ratio_fp32ir_over_fp64": round(t64 / t32, 3),
+        "resident_solves_per_s": {"fp32ir": round(1.0 / rt32, 2), "fp64": round(1.0 / rt64, 2)},
+        "matmul_fp64": mm,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kernels[:12],
+    }
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+def cpu_baseline(lo, r):
+    """The FP64 oracle (literal recursive ULV of Sec. 4.3) on the host: one
+    fresh-system solve (factorization and solve) of one instance."""
+    import numpy as np
+
+    from oracle.hss import HSS
+    from oracle.ulv import solve
+    from paper_1909_07909_amd import inputs
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    g = inputs.synthetic_hss(lo, RANK, seed=2)
+    H = HSS.from_packed(g)
+    b = inputs.rhs(N, r, 3)
+    t0 = time.perf_counter()
+    solve(H, b)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 4), "unit": "solves/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"1 fresh FP64 solve (literal recursive ULV, factor+solve), n={N}, "
+                      f"k={RANK}, nrhs={r}: {dt:.2f} s"}
+
+
+if __name__ == "__main__":
+    main()

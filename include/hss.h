@@ -185,6 +185,15 @@ hss_status hss_batch_ulv_solve(hss_handle *const *hs, int32_t count, const int64
                                double *const *B, const int64_t *ldb, const hss_solve_opts *o,
                                hss_solve_info *info, void *stream);
 
+/* Per-kernel timing (profiling aid).  hss_timing_enable(1) makes every
+ * kernel launch of the library record a pair of HIP events on its stream;
+ * hss_timing_report writes a JSON array [{"kernel", "launches", "total_ms"}]
+ * aggregated since the last reset into buf (cap bytes, NUL-terminated;
+ * HSS_EUNSUP if truncated), synchronizing on the recorded events.  Process
+ * wide; not for concurrent use from several threads while enabled. */
+hss_status hss_timing_enable(int32_t on);
+hss_status hss_timing_report(char *buf, int64_t cap, int32_t reset);
+
 /* Text for a status code (static storage). */
 const char *hss_status_str(hss_status s);
 

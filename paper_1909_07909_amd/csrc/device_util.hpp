@@ -7,11 +7,56 @@
 
 namespace hss {
 
+// Cross-lane moves through DPP (executed in the VALU, no LDS crossbar).
+// Control codes of the GFX9 DPP encoding.
+constexpr int kDppQuadXor1 = 0xB1;    // quad_perm(1,0,3,2)
+constexpr int kDppQuadXor2 = 0x4E;    // quad_perm(2,3,0,1)
+constexpr int kDppRowRor4 = 0x124;
+constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF,
+                                                    false));
+}
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float lane_read(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// value of lane ^ 1 (the partner of a lane pair)
+template <typename T>
+__device__ __forceinline__ T xor1(T v) {
+  return dpp<kDppQuadXor1>(v);
+}
+
+// Sum over the 64 lanes of a wavefront, returned in every lane: pairs and
+// quads by quad permutes, rows of 16 by two row rotations, then the four
+// rows by the row broadcasts (the total lands in row 3) and a lane read.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp<kDppQuadXor1>(v);
+  v += dpp<kDppQuadXor2>(v);
+  v += dpp<kDppRowRor4>(v);
+  v += dpp<kDppRowRor8>(v);
+  v += dpp<kDppRowBcast15, 0xA>(v);
+  v += dpp<kDppRowBcast31, 0x8>(v);
+  return lane_read(v, 63);
 }
 
 // Resolve (instance, call, node) of this work-group.
@@ -114,6 +159,22 @@ __device__ void wg_gemm_f(int M, int N, int K, FA fa, FB fb, FC fc, T* red) {
       fc(tid % M, tid / M, sum);
     }
     __syncthreads();
+  }
+}
+
+// Householder vector of [x; alpha] (pivot alpha at the end, QL) or
+// [alpha; x] (LQ): H = I - tau u u^T, u = (pivot 1, x * scale), H [.] = beta e.
+template <typename T>
+__device__ __forceinline__ void householder(T alpha, T sigma, T& beta, T& tau, T& scale) {
+  if (sigma == T(0)) {
+    beta = alpha;
+    tau = T(0);
+    scale = T(0);
+  } else {
+    const T nrm = sqrt(alpha * alpha + sigma);
+    beta = alpha >= T(0) ? -nrm : nrm;
+    tau = (beta - alpha) / beta;
+    scale = T(1) / (alpha - beta);
   }
 }
 

@@ -21,7 +21,7 @@ namespace {
 
 template <typename T>
 struct FactorSet {
-  T *FD = nullptr, *FU = nullptr, *FV = nullptr, *tq = nullptr, *tz = nullptr;
+  T *FD = nullptr, *FU = nullptr, *FV = nullptr, *tq = nullptr, *tz = nullptr, *FZ = nullptr;
   double* rootLU = nullptr;
   int32_t* piv = nullptr;
   bool valid = false;
@@ -127,9 +127,11 @@ hss_status ensure_factors(hss_handle* h) {
   F.FV = dalloc<T>(h, P.nFV);
   F.tq = dalloc<T>(h, P.ntq);
   F.tz = dalloc<T>(h, P.ntz);
+  F.FZ = dalloc<T>(h, P.nFZ);
   F.rootLU = dalloc<double>(h, (int64_t)P.nodes[0].mp * P.nodes[0].mp);
   F.piv = dalloc<int32_t>(h, P.nodes[0].mp);
-  if (!F.FD || !F.FU || !F.FV || !F.tq || !F.tz || !F.rootLU || !F.piv) return HSS_ENOMEM;
+  if (!F.FD || !F.FU || !F.FV || !F.tq || !F.tz || !F.FZ || !F.rootLU || !F.piv)
+    return HSS_ENOMEM;
   return HSS_OK;
 }
 
@@ -189,7 +191,7 @@ Inst<T> make_inst(hss_handle* h) {
   I.D = gen<T>(h, 0); I.U = gen<T>(h, 1); I.V = gen<T>(h, 2); I.R = gen<T>(h, 3);
   I.W = gen<T>(h, 4); I.B12 = gen<T>(h, 5); I.B21 = gen<T>(h, 6);
   FactorSet<T>& F = factors<T>(h);
-  I.FD = F.FD; I.FU = F.FU; I.FV = F.FV; I.tq = F.tq; I.tz = F.tz;
+  I.FD = F.FD; I.FU = F.FU; I.FV = F.FV; I.tq = F.tq; I.tz = F.tz; I.FZ = F.FZ;
   I.rootLU = F.rootLU; I.piv = F.piv;
   Work<T>& w = work<T>(h);
   I.xh = w.xh; I.yh = w.yh; I.ldm = h->plan.ldm;
@@ -247,16 +249,19 @@ void run_factor(hss_handle* h, hipStream_t s) {
     return;
   }
   a.node0 = level_first(p);
-  launch_ulv<T>(UlvStep::Factor, a, 1 << p, 1, P.max_mp, s);
+  launch_ulv<T>(UlvStep::Factor, a, 1 << p, 1, P.level_max_mp[p], s);
   for (int l = p - 1; l >= 1; --l) {
     a.node0 = level_first(l);
-    launch_ulv<T>(UlvStep::Merge, a, 1 << l, 1, P.max_mp, s);
-    launch_ulv<T>(UlvStep::Factor, a, 1 << l, 1, P.max_mp, s);
+    launch_ulv<T>(UlvStep::Merge, a, 1 << l, 1, P.level_max_mp[l], s);
+    launch_ulv<T>(UlvStep::Factor, a, 1 << l, 1, P.level_max_mp[l], s);
   }
   a.node0 = 0;
   launch_ulv<T>(UlvStep::Merge, a, 1, 1, P.max_mp, s);
   launch_ulv<T>(UlvStep::RootLU, a, 1, 1, P.max_mp, s);
 }
+
+// LDS bytes a work-group may use for staged copies of one node's factors.
+constexpr int64_t kStageBudget = 120 * 1024;
 
 template <typename T>
 void run_solve(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, hipStream_t s) {
@@ -265,26 +270,44 @@ void run_solve(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, hipStream_t s) {
   a.call = CallSV<T>{B, ldb, (int32_t)nrhs, 0};
   const Plan& P = h->plan;
   const int p = P.p;
-  const int yt = (int)((nrhs + kRT - 1) / kRT);
+  const int nc = (int)nrhs;   // one wavefront per (node, column)
+  auto fwd_stage = [&](int l) -> int64_t {
+    const int64_t e = P.level_fwd_stage[l];
+    return e > 0 && e * (int64_t)sizeof(T) <= kStageBudget ? e : 0;
+  };
+  auto bwd_stage = [&](int l) -> int64_t {
+    const int64_t e = P.level_bwd_stage[l];
+    return e > 0 && e * (int64_t)sizeof(T) <= kStageBudget ? e : 0;
+  };
+  // root: FP64 LU + pivots (+ the children's blocks when everything fits in LDS)
+  const int64_t mpr = P.nodes[0].mp;
+  int64_t root_bytes = mpr * mpr * 8 + 4 * ((mpr + 3) & ~int64_t(3));
+  const int64_t child_bytes = p > 0 ? P.level_fwd_stage[0] * (int64_t)sizeof(T) : 0;
+  a.flags = 0;
+  if (p > 0 && root_bytes + child_bytes <= 160 * 1024) {
+    root_bytes += child_bytes;
+    a.flags = 1;
+  }
+  const int64_t root_elems = (root_bytes + sizeof(T) - 1) / sizeof(T);
   if (p == 0) {
     a.node0 = 0;
-    launch_ulv<T>(UlvStep::Root, a, 1, yt, P.max_mp, s);
+    launch_solve_w<T>(UlvStep::Root, a, 1, nc, root_elems, s);
     return;
   }
   a.node0 = level_first(p);
-  launch_ulv<T>(UlvStep::Fwd, a, 1 << p, yt, P.max_mp, s);
+  launch_solve_w<T>(UlvStep::Fwd, a, 1 << p, nc, 0, s);
   for (int l = p - 1; l >= 1; --l) {
     a.node0 = level_first(l);
-    launch_ulv<T>(UlvStep::Fwd, a, 1 << l, yt, P.max_mp, s);
+    launch_solve_w<T>(UlvStep::Fwd, a, 1 << l, nc, fwd_stage(l), s);
   }
   a.node0 = 0;
-  launch_ulv<T>(UlvStep::Root, a, 1, yt, P.max_mp, s);
+  launch_solve_w<T>(UlvStep::Root, a, 1, nc, root_elems, s);
   for (int l = 1; l <= p - 1; ++l) {
     a.node0 = level_first(l);
-    launch_ulv<T>(UlvStep::Bwd, a, 1 << l, yt, P.max_mp, s);
+    launch_solve_w<T>(UlvStep::Bwd, a, 1 << l, nc, bwd_stage(l), s);
   }
   a.node0 = level_first(p);
-  launch_ulv<T>(UlvStep::Bwd, a, 1 << p, yt, P.max_mp, s);
+  launch_solve_w<T>(UlvStep::Bwd, a, 1 << p, nc, 0, s);
 }
 
 hss_status last_launch_status() {

@@ -12,6 +12,8 @@
 //       FU  mp x ku per node: Householder vectors of the QL step above the
 //           pivot rows, U~ = the trailing kept rows (lower triangular when e>0);
 //       FV  mp x kv per node: Z^T V' (leading e rows V^_top, trailing V^_bot);
+//       FZ  mp x e per node: the LQ reflectors again, reflector i as column i
+//           (zeros above row i, 1 at row i) for the backward sweep;
 //       tq, tz  the Householder scalars; the root block is LU-factored in
 //           FP64 (rootLU, piv);
 //   * work vectors for the product (x^ up values, y^ down values) and the
@@ -42,7 +44,7 @@ struct NodeInfo {
   // product work offsets (rows; capacity max(ku, kv))
   int64_t oxh, oyh;
   // factor offsets (elements)
-  int64_t oFD, oFU, oFV, otq, otz;
+  int64_t oFD, oFU, oFV, otq, otz, oFZ;
   // solve work offsets (rows): c and x^ have kept rows, z has kv rows, y e rows
   int64_t oc, oz, oy, ox;
 };
@@ -51,7 +53,7 @@ template <typename T>
 struct Inst {
   const NodeInfo* nodes;
   const T *D, *U, *V, *R, *W, *B12, *B21;
-  T *FD, *FU, *FV, *tq, *tz;
+  T *FD, *FU, *FV, *tq, *tz, *FZ;
   double* rootLU;
   int32_t* piv;
   T *xh, *yh;       // product work, leading dimension ldm
@@ -92,6 +94,8 @@ struct KArgs {
   const int2* tasks;
   int32_t node0;
   int32_t ntasks;
+  int32_t flags;   // kernel-specific options (root solve: bit 0 = children staged in LDS)
+  int32_t pad;
 };
 
 }  // namespace hss

@@ -16,6 +16,17 @@ void launch_mm_level(MMStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int
 // Fused leaf kernels for the uniform-tree fast path (see kernels_mm_fast.hip).
 enum class UlvStep { Merge, Factor, RootLU, Fwd, Root, Bwd };
 
+// Step 1 (QL / LQ) on one level of blocks, register-resident (kernels_factor.hip).
+template <typename T>
+void launch_factor_reg(const KArgs<T, CallSV<T>>& a, int nblocks, int max_mp, hipStream_t s);
+
+// Solve sweeps, one wavefront per (node, right-hand-side column) (kernels_solve.hip).
+// stage_elems > 0: one wavefront per work-group with that many elements of T
+// of dynamic LDS for the node's factor copies.
+template <typename T>
+void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int ncols,
+                    int64_t stage_elems, hipStream_t s);
+
 template <typename T>
 void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int ytiles,
                 int max_mp, hipStream_t s);

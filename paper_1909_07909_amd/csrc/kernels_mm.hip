@@ -10,6 +10,7 @@
 
 #include "device_util.hpp"
 #include "kernels.hpp"
+#include "timing.hpp"
 
 namespace hss {
 
@@ -154,6 +155,11 @@ void launch_mm_level(MMStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int
   dim3 grid(nblocks, ytiles), block(kNT);
   const size_t sm = mm_smem(max_rows, sizeof(T));
   const bool batch = a.tasks != nullptr;
+  static const char* names64[] = {"mm_leaf_up_f64", "mm_up_f64", "mm_couple_f64", "mm_down_f64",
+                                  "mm_leaf_out_f64"};
+  static const char* names32[] = {"mm_leaf_up_f32", "mm_up_f32", "mm_couple_f32", "mm_down_f32",
+                                  "mm_leaf_out_f32"};
+  TimedLaunch tl((sizeof(T) == 8 ? names64 : names32)[(int)step], s);
 #define HSS_LAUNCH(K)                                                         \
   if (batch) hipLaunchKernelGGL((K<T, true>), grid, block, sm, s, a);         \
   else hipLaunchKernelGGL((K<T, false>), grid, block, sm, s, a);

@@ -1,0 +1,463 @@
+// Telescoped ULV solve (Sec. 4.3, Steps 2 and 4 applied to a block of
+// right-hand sides with the stored factors).  One wavefront per (node,
+// right-hand-side column): lane l holds rows l and l + 64 of the node's
+// vector in registers, factor columns are read coalesced, reductions are
+// wavefront reductions and broadcasts are lane reads.
+//   forward:  rhs_t = b_i (leaf) or [c_c1 - U~_c1 B12_t z_c2; c_c2 - U~_c2 B21_t z_c1];
+//             b~ = Q^T rhs; y = L^{-1} b~_top; c = b~_bot - D~21 y;
+//             z_t = V^_top^T y (+ W_t^T [z_c1; z_c2] at internal nodes)
+//   root:     x' = (P L U)^{-1} rhs_root in FP64, split into x^_c1, x^_c2
+//   backward: x'_t = Z_t [y; x^_t], split to the children (leaves: into B).
+#include <hip/hip_runtime.h>
+
+#include "device_util.hpp"
+#include "kernels.hpp"
+#include "timing.hpp"
+
+namespace hss {
+
+constexpr int kSW = 4;   // wavefronts per work-group
+
+template <typename T>
+__device__ __forceinline__ T bcast(T v, int src) {
+  return lane_read(v, src);
+}
+template <typename T>
+__device__ __forceinline__ T row_of(T x0, T x1, int row) {
+  return bcast(row < 64 ? x0 : x1, row & 63);
+}
+
+// v[0..63] per lane; lane l returns the sum over all lanes of v[l]
+// (butterfly: at width w a lane keeps the half selected by bit w of its id and
+// receives the partner's copy of that half).
+template <typename T, int W>
+__device__ __forceinline__ void tsum_step(T (&v)[64], bool b) {
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const T send = b ? v[k] : v[W + k];
+    const T keep = b ? v[W + k] : v[k];
+    v[k] = keep + __shfl_xor(send, W, 64);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_transpose_sum64(T (&v)[64]) {
+  const int lane = threadIdx.x & 63;
+  tsum_step<T, 32>(v, (lane & 32) != 0);
+  tsum_step<T, 16>(v, (lane & 16) != 0);
+  tsum_step<T, 8>(v, (lane & 8) != 0);
+  tsum_step<T, 4>(v, (lane & 4) != 0);
+  tsum_step<T, 2>(v, (lane & 2) != 0);
+  tsum_step<T, 1>(v, (lane & 1) != 0);
+  return v[0];
+}
+
+// Where the sweeps read a node's factors: the factor arrays themselves, or
+// copies staged in LDS (one bulk load before the sequential steps).
+template <typename T>
+struct NodeSrc {
+  const T* U; int ldu;     // Q reflectors (FU), mp x ku
+  const T* L; int ldl;     // FD columns 0..e-1: L above, D~21 below
+  const T* V; int ldv;     // FV rows 0..e-1 (V^_top)
+  const T* W; int ldw;     // W_t
+  const T* U1; int ldu1; bool m1;   // U~ of the children; m: read zeros above the diagonal
+  const T* U2; int ldu2; bool m2;
+  const T* B12; int ld12;
+  const T* B21; int ld21;
+  const T* Z; int ldz;     // FZ (backward)
+};
+
+template <typename T>
+__device__ __forceinline__ T ut(const T* U, int ld, bool m, int a, int x) {
+  return (m && a < x) ? T(0) : U[a + x * ld];
+}
+
+template <typename T>
+__device__ __forceinline__ NodeSrc<T> src_global(const Inst<T>& I, const NodeInfo& nd, int node) {
+  NodeSrc<T> S{};
+  S.U = I.FU + nd.oFU; S.ldu = nd.mp;
+  S.L = I.FD + nd.oFD; S.ldl = nd.mp;
+  S.V = I.FV + nd.oFV; S.ldv = nd.mp;
+  S.Z = I.FZ + nd.oFZ; S.ldz = nd.mp;
+  if (!nd.is_leaf) {
+    const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+    S.W = I.W + nd.oW; S.ldw = n1.kv + n2.kv;
+    S.U1 = I.FU + n1.oFU + n1.e; S.ldu1 = n1.mp; S.m1 = n1.e > 0;
+    S.U2 = I.FU + n2.oFU + n2.e; S.ldu2 = n2.mp; S.m2 = n2.e > 0;
+    S.B12 = I.B12 + nd.oB12; S.ld12 = n1.ku;
+    S.B21 = I.B21 + nd.oB21; S.ld21 = n2.ku;
+  }
+  return S;
+}
+
+// Copy a rows x cols block (rows <= 128) into LDS with every thread of the
+// work-group: thread t covers rows t%64 and t%64 + 64 of the columns
+// congruent to t/64; 8 columns are loaded before any is stored so that 16
+// loads per thread are in flight.
+template <typename T, typename F>
+__device__ __forceinline__ T* stage_block(T* dst, int rows, int cols, F f) {
+  const int lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+  for (int j0 = w; j0 < cols; j0 += 8 * nw) {
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * nw;
+      v[2 * u] = (j < cols && lane < rows) ? f(lane, j) : T(0);
+      v[2 * u + 1] = (j < cols && lane + 64 < rows) ? f(lane + 64, j) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * nw;
+      if (j < cols && lane < rows) dst[lane + j * rows] = v[2 * u];
+      if (j < cols && lane + 64 < rows) dst[lane + 64 + j * rows] = v[2 * u + 1];
+    }
+  }
+  return dst + rows * cols;
+}
+
+// Copies of everything the forward sweep of an internal node reads, in LDS.
+template <typename T>
+__device__ NodeSrc<T> src_stage_fwd(const Inst<T>& I, const NodeInfo& nd, int node, T* sm) {
+  const NodeSrc<T> G = src_global(I, nd, node);
+  const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+  const int mp = nd.mp, e = nd.e, ku = nd.ku, kv = nd.kv, kw = n1.kv + n2.kv;
+  NodeSrc<T> S = G;
+  T* p = sm;
+  S.U = p; S.ldu = mp;
+  p = stage_block(p, mp, e > 0 ? ku : 0, [&](int i, int j) { return G.U[i + j * mp]; });
+  S.L = p; S.ldl = mp;
+  p = stage_block(p, mp, e, [&](int i, int j) { return G.L[i + j * mp]; });
+  S.V = p; S.ldv = e;
+  p = stage_block(p, e, kv, [&](int i, int j) { return G.V[i + j * mp]; });
+  S.W = p; S.ldw = kw;
+  p = stage_block(p, kw, kv, [&](int i, int j) { return G.W[i + j * kw]; });
+  S.U1 = p; S.ldu1 = n1.kept; S.m1 = false;
+  p = stage_block(p, n1.kept, n1.ku, [&](int i, int j) { return ut(G.U1, G.ldu1, G.m1, i, j); });
+  S.U2 = p; S.ldu2 = n2.kept; S.m2 = false;
+  p = stage_block(p, n2.kept, n2.ku, [&](int i, int j) { return ut(G.U2, G.ldu2, G.m2, i, j); });
+  S.B12 = p; S.ld12 = n1.ku;
+  p = stage_block(p, n1.ku, n2.kv, [&](int i, int j) { return G.B12[i + j * n1.ku]; });
+  S.B21 = p; S.ld21 = n2.ku;
+  p = stage_block(p, n2.ku, n1.kv, [&](int i, int j) { return G.B21[i + j * n2.ku]; });
+  return S;   // the caller synchronizes the work-group
+}
+
+// rhs of an internal node (rows lane, lane + 64) from the children's c and z.
+template <typename T>
+__device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, int node, int col, int lane,
+                                const NodeSrc<T>& S, T& x0, T& x1) {
+  const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+  const int64_t co = (int64_t)col * I.lds;
+  const T* z1 = I.wz + n1.oz + co;
+  const T* z2 = I.wz + n2.oz + co;
+  const T* c1 = I.wc + n1.oc + co;
+  const T* c2 = I.wc + n2.oc + co;
+  const int k1 = n1.kept, mp = nd.mp;
+  const int r0 = lane, r1 = lane + 64;
+  // vectors of the children first (independent loads)
+  const T z1l = lane < n1.kv ? z1[lane] : T(0);
+  const T z2l = lane < n2.kv ? z2[lane] : T(0);
+  const T cc0 = r0 < k1 ? c1[r0] : (r0 < mp ? c2[r0 - k1] : T(0));
+  const T cc1 = r1 < k1 ? c1[r1] : (r1 < mp ? c2[r1 - k1] : T(0));
+  T t1 = 0, t2 = 0;
+#pragma unroll 8
+  for (int y = 0; y < n2.kv; ++y) {
+    const T zy = bcast(z2l, y);
+    if (lane < n1.ku) t1 += S.B12[lane + y * S.ld12] * zy;
+  }
+#pragma unroll 8
+  for (int y = 0; y < n1.kv; ++y) {
+    const T zy = bcast(z1l, y);
+    if (lane < n2.ku) t2 += S.B21[lane + y * S.ld21] * zy;
+  }
+  T a0 = 0, a1 = 0;
+#pragma unroll 8
+  for (int x = 0; x < n1.ku; ++x) {
+    const T tx = bcast(t1, x);
+    if (r0 < k1) a0 += ut(S.U1, S.ldu1, S.m1, r0, x) * tx;
+    if (r1 < k1) a1 += ut(S.U1, S.ldu1, S.m1, r1, x) * tx;
+  }
+#pragma unroll 8
+  for (int x = 0; x < n2.ku; ++x) {
+    const T tx = bcast(t2, x);
+    if (r0 >= k1 && r0 < mp) a0 += ut(S.U2, S.ldu2, S.m2, r0 - k1, x) * tx;
+    if (r1 >= k1 && r1 < mp) a1 += ut(S.U2, S.ldu2, S.m2, r1 - k1, x) * tx;
+  }
+  x0 = cc0 - a0;
+  x1 = cc1 - a1;
+}
+
+// Work item of this wavefront.  Direct kernels: kSW wavefronts per
+// work-group, one (node, column) each.  Staged kernels: one node per
+// work-group, its kSW wavefronts take kSW consecutive columns.
+template <bool BATCH, bool STAGED, typename T>
+__device__ __forceinline__ bool sv_resolve(const KArgs<T, CallSV<T>>& a, Inst<T>& I,
+                                           CallSV<T>& C, int& node, int& col) {
+  const int w = threadIdx.x >> 6;
+  const int item = STAGED ? blockIdx.x : blockIdx.x * kSW + w;
+  col = STAGED ? blockIdx.y * kSW + w : blockIdx.y;
+  if (item >= a.ntasks) return false;
+  if constexpr (BATCH) {
+    const int2 tk = a.tasks[item];
+    I = a.insts[tk.x];
+    C = a.calls[tk.x];
+    node = tk.y;
+  } else {
+    I = a.inst;
+    C = a.call;
+    node = a.node0 + item;
+  }
+  return true;
+}
+
+// Forward sweep at one node.  STAGED: one wavefront per work-group, the
+// node's factors copied to LDS first (internal nodes); otherwise kSW
+// wavefronts per work-group reading the factor arrays (leaves).
+template <typename T, bool BATCH, bool STAGED>
+__global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  Inst<T> I; CallSV<T> C; int node, col;
+  if (!sv_resolve<BATCH, STAGED>(a, I, C, node, col)) return;   // uniform when STAGED
+  const int lane = threadIdx.x & 63;
+  const NodeInfo nd = I.nodes[node];
+  const int mp = nd.mp, e = nd.e, ku = nd.ku, kv = nd.kv;
+  const int r0 = lane, r1 = lane + 64;
+  NodeSrc<T> S;
+  if (STAGED) {
+    S = src_stage_fwd(I, nd, node, reinterpret_cast<T*>(smem_raw));
+    __syncthreads();
+  } else {
+    S = src_global(I, nd, node);
+  }
+  if (col >= C.nrhs) return;
+  const T taul = lane < ku ? I.tq[nd.otq + lane] : T(0);
+  T x0, x1;
+  if (nd.is_leaf) {
+    const T* b = C.B + nd.row0 + (int64_t)col * C.ldb;
+    x0 = r0 < mp ? b[r0] : T(0);
+    x1 = r1 < mp ? b[r1] : T(0);
+  } else {
+    gather_internal(I, nd, node, col, lane, S, x0, x1);
+  }
+  if (e > 0) {
+    // b~ = Q^T rhs = H_0 ... H_{ku-1} rhs, H_{ku-1} applied first (lane j holds tau_j)
+#pragma unroll 8
+    for (int j = ku - 1; j >= 0; --j) {
+      const T tau = bcast(taul, j);
+      const int pr = e + j;
+      const T* v = S.U + j * S.ldu;
+      const T v0 = r0 < pr ? v[r0] : (r0 == pr ? T(1) : T(0));
+      const T v1 = r1 < pr ? v[r1] : (r1 == pr ? T(1) : T(0));
+      const T w = wave_sum(v0 * x0 + v1 * x1) * tau;
+      x0 -= w * v0;
+      x1 -= w * v1;
+    }
+    // y = L^{-1} b~_top; the same column sweep leaves b~_bot - D~21 y below
+#pragma unroll 16
+    for (int i = 0; i < e; ++i) {
+      const T* Li = S.L + i * S.ldl;
+      const T l0 = r0 > i && r0 < mp ? Li[r0] : T(0);
+      const T l1 = r1 > i && r1 < mp ? Li[r1] : T(0);
+      const T yi = row_of(x0, x1, i) / Li[i];
+      if (r0 == i) x0 = yi;
+      if (r1 == i) x1 = yi;
+      x0 -= l0 * yi;
+      x1 -= l1 * yi;
+    }
+  }
+  const int64_t co = (int64_t)col * I.lds;
+  T* yo = I.wy + nd.oy + co;
+  T* cout = I.wc + nd.oc + co;
+  if (r0 < e) yo[r0] = x0; else if (r0 < mp) cout[r0 - e] = x0;
+  if (r1 < e) yo[r1] = x1; else if (r1 < mp) cout[r1 - e] = x1;
+  if (node == 0) return;
+  // z = V^_top^T y (+ W^T [z_c1; z_c2])
+  T zc0 = 0, zc1 = 0;
+  int kw = 0;
+  if (!nd.is_leaf) {
+    const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+    const T* z1 = I.wz + n1.oz + co;
+    const T* z2 = I.wz + n2.oz + co;
+    kw = n1.kv + n2.kv;
+    zc0 = r0 < n1.kv ? z1[r0] : (r0 < kw ? z2[r0 - n1.kv] : T(0));
+    zc1 = r1 < n1.kv ? z1[r1] : (r1 < kw ? z2[r1 - n1.kv] : T(0));
+  }
+  T* zo = I.wz + nd.oz + co;
+  T part[64];
+#pragma unroll
+  for (int aa = 0; aa < 64; ++aa) {
+    T acc = T(0);
+    if (aa < kv) {
+      const T* Va = S.V + aa * S.ldv;
+      acc = (r0 < e ? Va[r0] * x0 : T(0)) + (r1 < e ? Va[r1] * x1 : T(0));
+      if (kw) acc += (r0 < kw ? S.W[r0 + aa * S.ldw] * zc0 : T(0)) +
+                     (r1 < kw ? S.W[r1 + aa * S.ldw] * zc1 : T(0));
+    }
+    part[aa] = acc;
+  }
+  const T z = wave_transpose_sum64(part);
+  if (lane < kv) zo[lane] = z;
+}
+
+// Root: rhs from the children, then the FP64 LU of the merged root block
+// (staged in LDS with its pivots), split into the children's x^.
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kSW * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  Inst<T> I; CallSV<T> C; int node, col;
+  if (!sv_resolve<BATCH, true>(a, I, C, node, col)) return;
+  const int lane = threadIdx.x & 63;
+  const NodeInfo nd = I.nodes[node];
+  const int mp = nd.mp;
+  const int r0 = lane, r1 = lane + 64;
+  double* LU = reinterpret_cast<double*>(smem_raw);
+  int* piv = reinterpret_cast<int*>(LU + mp * mp);
+  T* rest = reinterpret_cast<T*>(piv + ((mp + 3) & ~3));
+  stage_block(LU, mp, mp, [&](int i, int j) { return I.rootLU[i + j * mp]; });
+  for (int o = threadIdx.x; o < mp; o += blockDim.x) piv[o] = I.piv[o];
+  NodeSrc<T> S = (nd.is_leaf || !(a.flags & 1)) ? src_global(I, nd, node)
+                                                 : src_stage_fwd(I, nd, node, rest);
+  __syncthreads();
+  if (col >= C.nrhs) return;
+  T t0, t1;
+  if (nd.is_leaf) {
+    const T* b = C.B + nd.row0 + (int64_t)col * C.ldb;
+    t0 = r0 < mp ? b[r0] : T(0);
+    t1 = r1 < mp ? b[r1] : T(0);
+  } else {
+    gather_internal(I, nd, node, col, lane, S, t0, t1);
+  }
+  double x0 = (double)t0, x1 = (double)t1;
+  for (int j = 0; j < mp; ++j) {
+    const int pj = piv[j];
+    const double vj = row_of(x0, x1, j), vp = row_of(x0, x1, pj);
+    if (r0 == j) x0 = vp;
+    if (r1 == j) x1 = vp;
+    if (r0 == pj) x0 = vj;
+    if (r1 == pj) x1 = vj;
+  }
+  for (int i = 0; i < mp; ++i) {
+    const double* Li = LU + i * mp;
+    const double xi = row_of(x0, x1, i);
+    if (r0 > i && r0 < mp) x0 -= Li[r0] * xi;
+    if (r1 > i && r1 < mp) x1 -= Li[r1] * xi;
+  }
+  for (int i = mp - 1; i >= 0; --i) {
+    const double* Ui = LU + i * mp;
+    const double xi = row_of(x0, x1, i) / Ui[i];
+    if (r0 == i) x0 = xi;
+    if (r1 == i) x1 = xi;
+    if (r0 < i) x0 -= Ui[r0] * xi;
+    if (r1 < i) x1 -= Ui[r1] * xi;
+  }
+  if (nd.is_leaf) {
+    T* out = C.B + nd.row0 + (int64_t)col * C.ldb;
+    if (r0 < mp) out[r0] = (T)x0;
+    if (r1 < mp) out[r1] = (T)x1;
+    return;
+  }
+  const NodeInfo n1 = I.nodes[1], n2 = I.nodes[2];
+  const int64_t co = (int64_t)col * I.lds;
+  T* xa = I.wx + n1.ox + co;
+  T* xb = I.wx + n2.ox + co;
+  const int k1 = n1.kept;
+  if (r0 < k1) xa[r0] = (T)x0; else if (r0 < mp) xb[r0 - k1] = (T)x0;
+  if (r1 < k1) xa[r1] = (T)x1; else if (r1 < mp) xb[r1 - k1] = (T)x1;
+}
+
+template <typename T, bool BATCH, bool STAGED>
+__global__ __launch_bounds__(kSW * 64) void k_sv_bwd_w(KArgs<T, CallSV<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  Inst<T> I; CallSV<T> C; int node, col;
+  if (!sv_resolve<BATCH, STAGED>(a, I, C, node, col)) return;
+  const int lane = threadIdx.x & 63;
+  const NodeInfo nd = I.nodes[node];
+  const int mp = nd.mp, e = nd.e;
+  const int r0 = lane, r1 = lane + 64;
+  const T* Z = I.FZ + nd.oFZ;
+  int ldz = mp;
+  if (STAGED) {
+    T* sz = reinterpret_cast<T*>(smem_raw);
+    stage_block(sz, mp, e, [&](int i, int j) { return Z[i + j * mp]; });
+    __syncthreads();
+    Z = sz;
+  }
+  if (col >= C.nrhs) return;
+  const int64_t co = (int64_t)col * I.lds;
+  const T* yi = I.wy + nd.oy + co;
+  const T* xi = I.wx + nd.ox + co;
+  T x0 = r0 < e ? yi[r0] : (r0 < mp ? xi[r0 - e] : T(0));
+  T x1 = r1 < e ? yi[r1] : (r1 < mp ? xi[r1 - e] : T(0));
+  // Z [y; x^] = H_0 ... H_{e-1} [y; x^], H_{e-1} applied first
+  const T taul0 = r0 < e ? I.tz[nd.otz + r0] : T(0);
+  const T taul1 = r1 < e ? I.tz[nd.otz + r1] : T(0);
+#pragma unroll 8
+  for (int i = e - 1; i >= 0; --i) {
+    const T tau = row_of(taul0, taul1, i);
+    const T* v = Z + i * ldz;
+    const T v0 = r0 < mp ? v[r0] : T(0);
+    const T v1 = r1 < mp ? v[r1] : T(0);
+    const T w = wave_sum(v0 * x0 + v1 * x1) * tau;
+    x0 -= w * v0;
+    x1 -= w * v1;
+  }
+  if (nd.is_leaf) {
+    T* out = C.B + nd.row0 + (int64_t)col * C.ldb;
+    if (r0 < mp) out[r0] = x0;
+    if (r1 < mp) out[r1] = x1;
+    return;
+  }
+  const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+  T* xa = I.wx + n1.ox + co;
+  T* xb = I.wx + n2.ox + co;
+  const int k1 = n1.kept;
+  if (r0 < k1) xa[r0] = x0; else if (r0 < mp) xb[r0 - k1] = x0;
+  if (r1 < k1) xa[r1] = x1; else if (r1 < mp) xb[r1 - k1] = x1;
+}
+
+template <typename T>
+void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int ncols,
+                    int64_t stage_elems, hipStream_t s) {
+  if (nitems <= 0 || ncols <= 0) return;
+  KArgs<T, CallSV<T>> b = a;
+  b.ntasks = nitems;
+  const bool batch = a.tasks != nullptr;
+  const bool staged = stage_elems > 0;
+  const size_t sm = staged ? (size_t)stage_elems * sizeof(T) : 0;
+  const bool leafy = !batch && a.node0 > 0 && a.node0 == a.inst.nnodes / 2;
+  static const char* nm64[] = {"sv_fwd_f64", "sv_fwd_leaf_f64", "sv_bwd_f64", "sv_bwd_leaf_f64",
+                               "sv_root_f64"};
+  static const char* nm32[] = {"sv_fwd_f32", "sv_fwd_leaf_f32", "sv_bwd_f32", "sv_bwd_leaf_f32",
+                               "sv_root_f32"};
+  const int ni = step == UlvStep::Root ? 4 : (step == UlvStep::Fwd ? 0 : 2) + (leafy ? 1 : 0);
+  TimedLaunch tl((sizeof(T) == 8 ? nm64 : nm32)[ni], s);
+  dim3 gridw((nitems + kSW - 1) / kSW, ncols), blockw(kSW * 64);
+  dim3 grid1(nitems, (ncols + kSW - 1) / kSW), block1(kSW * 64);
+#define HSS_SL(K, ST, G, B)                                                       \
+  if (batch) hipLaunchKernelGGL((K<T, true, ST>), G, B, sm, s, b);                \
+  else hipLaunchKernelGGL((K<T, false, ST>), G, B, sm, s, b);
+  switch (step) {
+    case UlvStep::Fwd:
+      if (staged) { HSS_SL(k_sv_fwd_w, true, grid1, block1) }
+      else { HSS_SL(k_sv_fwd_w, false, gridw, blockw) }
+      break;
+    case UlvStep::Bwd:
+      if (staged) { HSS_SL(k_sv_bwd_w, true, grid1, block1) }
+      else { HSS_SL(k_sv_bwd_w, false, gridw, blockw) }
+      break;
+    case UlvStep::Root:
+      if (batch) hipLaunchKernelGGL((k_sv_root_w<T, true>), grid1, block1, sm, s, b);
+      else hipLaunchKernelGGL((k_sv_root_w<T, false>), grid1, block1, sm, s, b);
+      break;
+    default: break;
+  }
+#undef HSS_SL
+}
+
+template void launch_solve_w<double>(UlvStep, const KArgs<double, CallSV<double>>&, int, int,
+                                     int64_t, hipStream_t);
+template void launch_solve_w<float>(UlvStep, const KArgs<float, CallSV<float>>&, int, int,
+                                    int64_t, hipStream_t);
+
+}  // namespace hss

@@ -86,7 +86,7 @@ hss_status build_plan(const hss_tree_desc* tree, Plan& P, std::string* why) {
   }
   // offsets
   int64_t oD = 0, oU = 0, oV = 0, oR = 0, oW = 0, o12 = 0, o21 = 0;
-  int64_t oFD = 0, oFU = 0, oFV = 0, otq = 0, otz = 0;
+  int64_t oFD = 0, oFU = 0, oFV = 0, otq = 0, otz = 0, oFZ = 0;
   int64_t oxh = 0, oc = 0, oz = 0, oy = 0;
   for (int32_t t = 0; t < nn; ++t) {
     NodeInfo& d = P.nodes[t];
@@ -116,6 +116,7 @@ hss_status build_plan(const hss_tree_desc* tree, Plan& P, std::string* why) {
     d.oFV = oFV; oFV += int64_t(d.mp) * d.kv;
     d.otq = otq; otq += d.ku;
     d.otz = otz; otz += d.e;
+    d.oFZ = oFZ; oFZ += int64_t(d.mp) * d.e;
     d.oc = oc; d.ox = oc; oc += d.kept;
     d.oz = oz; oz += d.kv;
     d.oy = oy; oy += d.e;
@@ -123,8 +124,26 @@ hss_status build_plan(const hss_tree_desc* tree, Plan& P, std::string* why) {
     P.max_mp = std::max(P.max_mp, d.mp);
     P.max_k = std::max(P.max_k, kmax);
   }
+  P.level_fwd_stage.assign(p + 1, 0);
+  P.level_bwd_stage.assign(p + 1, 0);
+  for (int32_t t = 0; t < nn; ++t) {
+    const NodeInfo& d = P.nodes[t];
+    if (d.is_leaf) continue;
+    const NodeInfo& a = P.nodes[2 * t + 1];
+    const NodeInfo& b = P.nodes[2 * t + 2];
+    const int64_t kw = a.kv + b.kv;
+    const int64_t f = int64_t(d.mp) * (d.e > 0 ? d.ku : 0) + int64_t(d.mp) * d.e +
+                      int64_t(d.e) * d.kv + kw * d.kv + int64_t(a.kept) * a.ku +
+                      int64_t(b.kept) * b.ku + int64_t(a.ku) * b.kv + int64_t(b.ku) * a.kv;
+    P.level_fwd_stage[d.level] = std::max(P.level_fwd_stage[d.level], f);
+    P.level_bwd_stage[d.level] =
+        std::max(P.level_bwd_stage[d.level], int64_t(d.mp) * d.e);
+  }
+  P.level_max_mp.assign(p + 1, 0);
+  for (int32_t t = 0; t < nn; ++t)
+    P.level_max_mp[P.nodes[t].level] = std::max(P.level_max_mp[P.nodes[t].level], P.nodes[t].mp);
   P.nD = oD; P.nU = oU; P.nV = oV; P.nR = oR; P.nW = oW; P.nB12 = o12; P.nB21 = o21;
-  P.nFD = oFD; P.nFU = oFU; P.nFV = oFV; P.ntq = otq; P.ntz = otz;
+  P.nFD = oFD; P.nFU = oFU; P.nFV = oFV; P.ntq = otq; P.ntz = otz; P.nFZ = oFZ;
   P.ldm = std::max<int64_t>(oxh, 1);
   P.lds = std::max<int64_t>(std::max(oc, std::max(oz, oy)), 1);
   return HSS_OK;

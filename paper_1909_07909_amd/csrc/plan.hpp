@@ -20,12 +20,17 @@ struct Plan {
   // packed generator sizes (entries)
   int64_t nD = 0, nU = 0, nV = 0, nR = 0, nW = 0, nB12 = 0, nB21 = 0;
   // factor sizes (entries)
-  int64_t nFD = 0, nFU = 0, nFV = 0, ntq = 0, ntz = 0;
+  int64_t nFD = 0, nFU = 0, nFV = 0, ntq = 0, ntz = 0, nFZ = 0;
   int64_t ldm = 0;   // product work rows
   int64_t lds = 0;   // solve work rows
   int32_t max_m = 0, max_mp = 0, max_k = 0;
+  std::vector<int32_t> level_max_mp;   // per level l = 0..p
+  // LDS copies (elements) the forward / backward sweeps of an internal level
+  // need when they stage a node's factors (max over the level); root: the
+  // children's blocks only (its FP64 LU is added separately)
+  std::vector<int64_t> level_fwd_stage, level_bwd_stage;
   int64_t gen_entries() const { return nD + nU + nV + nR + nW + nB12 + nB21; }
-  int64_t factor_entries() const { return nFD + nFU + nFV + ntq + ntz; }
+  int64_t factor_entries() const { return nFD + nFU + nFV + ntq + ntz + nFZ; }
 };
 
 // Returns 0 or a status (negative = invalid argument index as in hss.h).

@@ -24,7 +24,8 @@ F64, F32 = 0, 1
 EXPORTS = (
     "hss_create", "hss_destroy", "hss_matmul", "hss_ulv_factor", "hss_ulv_solve", "hss_query",
     "hss_plan_depth", "hss_plan_leaf_offsets", "hss_plan_node_ranges", "hss_batch_matmul",
-    "hss_batch_ulv_factor", "hss_batch_ulv_solve", "hss_status_str",
+    "hss_batch_ulv_factor", "hss_batch_ulv_solve", "hss_status_str", "hss_timing_enable",
+    "hss_timing_report",
 )
 
 Q_N, Q_P, Q_RESIDENT_BYTES, Q_NORM2, Q_GEN_ENTRIES, Q_FACTOR_ENTRIES = range(6)
@@ -93,6 +94,8 @@ def lib() -> C.CDLL:
     L.hss_batch_ulv_solve.argtypes = [C.POINTER(vp), i32, C.POINTER(C.c_int64), C.POINTER(vp),
                                       C.POINTER(C.c_int64), C.POINTER(SolveOpts),
                                       C.POINTER(SolveInfo), vp]
+    L.hss_timing_enable.argtypes = [i32]
+    L.hss_timing_report.argtypes = [C.c_char_p, i64, i32]
     L.hss_status_str.argtypes = [i32]
     L.hss_status_str.restype = C.c_char_p
     for name in EXPORTS:
@@ -142,6 +145,18 @@ def plan_node_ranges(n, p, leaf_off, ku, kv):
                                       size.ctypes.data_as(C.POINTER(C.c_int64))),
            "hss_plan_node_ranges")
     return start, size
+
+
+def timing_enable(on: bool):
+    lib().hss_timing_enable(1 if on else 0)
+
+
+def timing_report(reset: bool = True):
+    """Per-kernel event timings since the last reset: list of dicts."""
+    import json
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib().hss_timing_report(buf, len(buf), 1 if reset else 0), "hss_timing_report")
+    return json.loads(buf.value.decode())
 
 
 def _stream(stream):
