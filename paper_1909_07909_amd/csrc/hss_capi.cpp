@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -350,6 +351,426 @@ hss_status compute_norm2(hss_handle* h, hipStream_t s) {
 }  // namespace
 
 // ===========================================================================
+// Batched execution over many handles: one launch per tree level for all
+// instances.  Upward passes are aligned at the leaves (step s = level p_j - s),
+// downward passes at the root (step s = level s).  Task lists of (instance,
+// node) pairs and the per-instance pointer tables are uploaded to a device
+// scratch buffer owned by the library (one per process; batched calls on
+// different streams must not overlap).
+// ===========================================================================
+namespace {
+
+struct BatchScratch {
+  void* d = nullptr;
+  size_t cap = 0;
+  std::mutex mu;
+};
+BatchScratch g_bs;
+
+hss_status scratch_upload(const std::vector<char>& host, hipStream_t s, void** dptr) {
+  if (g_bs.cap < host.size()) {
+    if (g_bs.d) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(g_bs.d);
+      g_bs.d = nullptr;
+      g_bs.cap = 0;
+    }
+    size_t cap = std::max<size_t>(host.size() * 2, 1 << 20);
+    if (hipMalloc(&g_bs.d, cap) != hipSuccess) {
+      (void)hipGetLastError();
+      return HSS_ENOMEM;
+    }
+    g_bs.cap = cap;
+  }
+  // pageable source: the copy is staged before the call returns
+  if (!host.empty() &&
+      hipMemcpyAsync(g_bs.d, host.data(), host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return HSS_EHIP;
+  *dptr = g_bs.d;
+  return HSS_OK;
+}
+
+// Packs several arrays into one upload with 256-byte alignment.
+struct Packer {
+  std::vector<char> buf;
+  template <typename X>
+  size_t add(const std::vector<X>& v) {
+    size_t off = (buf.size() + 255) & ~size_t(255);
+    buf.resize(off + v.size() * sizeof(X));
+    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(X));
+    return off;
+  }
+};
+
+struct StepList {
+  std::vector<int2> tasks;
+  struct Range {
+    size_t off;
+    int cnt;
+    int max_mp;
+    int64_t stage;   // max staging elements over the tasks
+  };
+  std::vector<Range> ranges;
+  template <typename Pred, typename Stage>
+  void add_step(hss_handle* const* hs, int count, Pred pred, Stage stage) {
+    Range r{tasks.size(), 0, 0, 0};
+    for (int j = 0; j < count; ++j) {
+      const Plan& P = hs[j]->plan;
+      for (int t = 0; t < P.nnodes; ++t)
+        if (pred(j, P, t)) {
+          tasks.push_back(make_int2(j, t));
+          r.max_mp = std::max(r.max_mp, P.nodes[t].mp);
+          r.stage = std::max<int64_t>(r.stage, stage(P, t));
+          ++r.cnt;
+        }
+    }
+    ranges.push_back(r);
+  }
+};
+
+int max_depth(hss_handle* const* hs, int count) {
+  int mp = 0;
+  for (int j = 0; j < count; ++j) mp = std::max(mp, hs[j]->plan.p);
+  return mp;
+}
+
+template <typename T>
+hss_status batch_matmul_impl(hss_handle* const* hs, int count, int op, const int64_t* nrhs,
+                             const void* const* X, const int64_t* ldx, void* const* Y,
+                             const int64_t* ldy, hipStream_t s) {
+  int64_t maxr = 0;
+  std::vector<Inst<T>> insts(count);
+  std::vector<CallMM<T>> calls(count);
+  for (int j = 0; j < count; ++j) {
+    hss_status st = ensure_work_mm<T>(hs[j], std::max<int64_t>(nrhs[j], 1));
+    if (st) return st;
+    insts[j] = make_inst<T>(hs[j]);
+    calls[j] = CallMM<T>{(const T*)X[j], (T*)Y[j], ldx[j], ldy[j], (int32_t)nrhs[j], op};
+    maxr = std::max(maxr, nrhs[j]);
+  }
+  if (maxr == 0) return HSS_OK;
+  const int pmax = max_depth(hs, count);
+  StepList L;
+  auto none = [](const Plan&, int) -> int64_t { return 0; };
+  auto lvl = [](const Plan& P, int t) { return P.nodes[t].level; };
+  L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
+             none);                                                      // 0: leaf up
+  for (int st = 1; st <= pmax - 1; ++st)                                 // 1..: up
+    L.add_step(hs, count, [&](int, const Plan& P, int t) {
+      return lvl(P, t) == P.p - st && lvl(P, t) >= 1; }, none);
+  L.add_step(hs, count, [&](int, const Plan& P, int t) { return !P.nodes[t].is_leaf; }, none);
+  for (int st = 1; st <= pmax - 1; ++st)
+    L.add_step(hs, count, [&](int, const Plan& P, int t) {
+      return lvl(P, t) == st && st <= P.p - 1; }, none);
+  L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.nodes[t].is_leaf != 0; }, none);
+  Packer pk;
+  const size_t oi = pk.add(insts), oc = pk.add(calls), ot = pk.add(L.tasks);
+  void* d = nullptr;
+  hss_status st = scratch_upload(pk.buf, s, &d);
+  if (st) return st;
+  KArgs<T, CallMM<T>> a{};
+  a.insts = reinterpret_cast<const Inst<T>*>((char*)d + oi);
+  a.calls = reinterpret_cast<const CallMM<T>*>((char*)d + oc);
+  const int yt = (int)((maxr + kRT - 1) / kRT);
+  size_t k = 0;
+  auto run = [&](MMStep stp) {
+    const auto& r = L.ranges[k++];
+    a.tasks = reinterpret_cast<const int2*>((char*)d + ot) + r.off;
+    a.ntasks = r.cnt;
+    launch_mm_level<T>(stp, a, r.cnt, yt, kMaxBlock, s);
+  };
+  run(MMStep::LeafUp);
+  for (int q = 1; q <= pmax - 1; ++q) run(MMStep::Up);
+  run(MMStep::Couple);
+  for (int q = 1; q <= pmax - 1; ++q) run(MMStep::Down);
+  run(MMStep::LeafOut);
+  return last_launch_status();
+}
+
+template <typename T>
+hss_status batch_matmul(hss_handle* const* hs, int count, int op, const int64_t* nrhs,
+                        const void* const* X, const int64_t* ldx, void* const* Y,
+                        const int64_t* ldy, hipStream_t s) {
+  std::lock_guard<std::mutex> g(g_bs.mu);
+  return batch_matmul_impl<T>(hs, count, op, nrhs, X, ldx, Y, ldy, s);
+}
+
+// FP64 A X for the refinement residuals (the caller holds the scratch lock).
+hss_status batch_matmul_unlocked(hss_handle* const* hs, int count, const int64_t* nrhs,
+                                 double* const* X, const int64_t* ldx, double* const* Y,
+                                 const int64_t* ldy, hipStream_t s) {
+  std::vector<const void*> xv(X, X + count);
+  std::vector<void*> yv(Y, Y + count);
+  return batch_matmul_impl<double>(hs, count, HSS_OP_N, nrhs, xv.data(), ldx, yv.data(), ldy, s);
+}
+
+template <typename T>
+hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
+  std::lock_guard<std::mutex> g(g_bs.mu);
+  std::vector<Inst<T>> insts(count);
+  for (int j = 0; j < count; ++j) {
+    hss_status st = ensure_factors<T>(hs[j]);
+    if (st) return st;
+    insts[j] = make_inst<T>(hs[j]);
+  }
+  const int pmax = max_depth(hs, count);
+  StepList L;
+  auto none = [](const Plan&, int) -> int64_t { return 0; };
+  auto lvl = [](const Plan& P, int t) { return P.nodes[t].level; };
+  L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
+             none);
+  for (int st = 1; st <= pmax - 1; ++st)
+    L.add_step(hs, count, [&](int, const Plan& P, int t) {
+      return lvl(P, t) == P.p - st && lvl(P, t) >= 1; }, none);
+  L.add_step(hs, count, [&](int, const Plan& P, int t) { return t == 0 && P.p > 0; }, none);
+  L.add_step(hs, count, [&](int, const Plan&, int t) { return t == 0; }, none);
+  Packer pk;
+  const size_t oi = pk.add(insts), ot = pk.add(L.tasks);
+  void* d = nullptr;
+  hss_status st = scratch_upload(pk.buf, s, &d);
+  if (st) return st;
+  for (int j = 0; j < count; ++j) launch_fill(reinterpret_cast<double*>(hs[j]->d_status), 0.0, 2, s);
+  KArgs<T, CallSV<T>> a{};
+  a.insts = reinterpret_cast<const Inst<T>*>((char*)d + oi);
+  size_t k = 0;
+  auto rng = [&]() -> const StepList::Range& {
+    const auto& r = L.ranges[k++];
+    a.tasks = reinterpret_cast<const int2*>((char*)d + ot) + r.off;
+    a.ntasks = r.cnt;
+    return r;
+  };
+  {
+    const auto& r = rng();
+    launch_ulv<T>(UlvStep::Factor, a, r.cnt, 1, r.max_mp, s);
+  }
+  for (int q = 1; q <= pmax - 1; ++q) {
+    const auto& r = rng();
+    launch_ulv<T>(UlvStep::Merge, a, r.cnt, 1, r.max_mp, s);
+    launch_ulv<T>(UlvStep::Factor, a, r.cnt, 1, r.max_mp, s);
+  }
+  {
+    const auto& r = rng();
+    launch_ulv<T>(UlvStep::Merge, a, r.cnt, 1, r.max_mp, s);
+  }
+  {
+    const auto& r = rng();
+    launch_ulv<T>(UlvStep::RootLU, a, r.cnt, 1, r.max_mp, s);
+  }
+  for (int j = 0; j < count; ++j) (sizeof(T) == 8 ? hs[j]->f64.valid : hs[j]->f32.valid) = true;
+  return last_launch_status();
+}
+
+// One batched solve sweep (forward, root, backward) on per-instance
+// right-hand sides rhs[j] (precision T, leading dimension ld[j]).
+template <typename T>
+hss_status batch_sweep(hss_handle* const* hs, int count, const int64_t* nrhs, T* const* rhs,
+                       const int64_t* ld, hipStream_t s) {
+  std::vector<Inst<T>> insts(count);
+  std::vector<CallSV<T>> calls(count);
+  int64_t maxr = 0;
+  for (int j = 0; j < count; ++j) {
+    hss_status st = ensure_work_sv<T>(hs[j], std::max<int64_t>(nrhs[j], 1));
+    if (st) return st;
+    insts[j] = make_inst<T>(hs[j]);
+    calls[j] = CallSV<T>{rhs[j], ld[j], (int32_t)nrhs[j], 0};
+    maxr = std::max(maxr, nrhs[j]);
+  }
+  if (maxr == 0) return HSS_OK;
+  const int pmax = max_depth(hs, count);
+  StepList L;
+  auto lvl = [](const Plan& P, int t) { return P.nodes[t].level; };
+  auto fst = [](const Plan& P, int t) { return P.level_fwd_stage[P.nodes[t].level]; };
+  auto bst = [](const Plan& P, int t) { return P.level_bwd_stage[P.nodes[t].level]; };
+  auto none = [](const Plan&, int) -> int64_t { return 0; };
+  L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
+             none);
+  for (int st = 1; st <= pmax - 1; ++st)
+    L.add_step(hs, count, [&](int, const Plan& P, int t) {
+      return lvl(P, t) == P.p - st && lvl(P, t) >= 1; }, fst);
+  L.add_step(hs, count, [&](int, const Plan&, int t) { return t == 0; }, fst);
+  for (int st = 1; st <= pmax - 1; ++st)
+    L.add_step(hs, count, [&](int, const Plan& P, int t) {
+      return lvl(P, t) == st && st <= P.p - 1; }, bst);
+  L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
+             none);
+  // root staging: FP64 LU + pivots (+ children when everything fits)
+  int64_t root_bytes = 0, child_bytes = 0;
+  for (int j = 0; j < count; ++j) {
+    const Plan& P = hs[j]->plan;
+    const int64_t mpr = P.nodes[0].mp;
+    root_bytes = std::max(root_bytes, mpr * mpr * 8 + 4 * ((mpr + 3) & ~int64_t(3)));
+    if (P.p > 0) child_bytes = std::max(child_bytes, P.level_fwd_stage[0] * (int64_t)sizeof(T));
+  }
+  Packer pk;
+  const size_t oi = pk.add(insts), oc = pk.add(calls), ot = pk.add(L.tasks);
+  void* d = nullptr;
+  hss_status st = scratch_upload(pk.buf, s, &d);
+  if (st) return st;
+  KArgs<T, CallSV<T>> a{};
+  a.insts = reinterpret_cast<const Inst<T>*>((char*)d + oi);
+  a.calls = reinterpret_cast<const CallSV<T>*>((char*)d + oc);
+  const int nc = (int)maxr;
+  size_t k = 0;
+  auto staged = [&](int64_t e) -> int64_t {
+    return e > 0 && e * (int64_t)sizeof(T) <= kStageBudget ? e : 0;
+  };
+  auto go = [&](UlvStep stp, bool use_stage) {
+    const auto& r = L.ranges[k++];
+    a.tasks = reinterpret_cast<const int2*>((char*)d + ot) + r.off;
+    a.ntasks = r.cnt;
+    launch_solve_w<T>(stp, a, r.cnt, nc, use_stage ? staged(r.stage) : 0, s);
+  };
+  go(UlvStep::Fwd, false);
+  for (int q = 1; q <= pmax - 1; ++q) go(UlvStep::Fwd, true);
+  {
+    const auto& r = L.ranges[k++];
+    a.tasks = reinterpret_cast<const int2*>((char*)d + ot) + r.off;
+    a.ntasks = r.cnt;
+    int64_t rb = root_bytes;
+    a.flags = 0;
+    if (root_bytes + child_bytes <= 160 * 1024) {
+      rb += child_bytes;
+      a.flags = 1;
+    }
+    launch_solve_w<T>(UlvStep::Root, a, r.cnt, nc, (rb + sizeof(T) - 1) / sizeof(T), s);
+    a.flags = 0;
+  }
+  for (int q = 1; q <= pmax - 1; ++q) go(UlvStep::Bwd, true);
+  go(UlvStep::Bwd, false);
+  return last_launch_status();
+}
+
+hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, double* const* B,
+                       const int64_t* ldb, const hss_solve_opts& opt, hss_solve_info* info,
+                       hipStream_t s) {
+  std::lock_guard<std::mutex> g(g_bs.mu);
+  const bool is64 = opt.prec == HSS_F64;
+  const bool need_eta = opt.want_eta || opt.tol > 0.0;
+  hss_status st;
+  int64_t maxn = 0;
+  for (int j = 0; j < count; ++j) {
+    if (need_eta && (st = compute_norm2(hs[j], s))) return st;
+    if ((st = ensure_ir(hs[j], std::max<int64_t>(nrhs[j], 1)))) return st;
+    if (need_eta && (st = ensure_work_mm<double>(hs[j], std::max<int64_t>(nrhs[j], 1)))) return st;
+    maxn = std::max(maxn, hs[j]->plan.n);
+  }
+  // refinement descriptors + the global max eta live in the scratch as well
+  std::vector<IRSeg> segs(count);
+  std::vector<double> gm(1, 0.0);
+  std::vector<int64_t> n_ld(count);
+  std::vector<float*> r32(count);
+  std::vector<double*> d64(count), res(count), Bv(B, B + count);
+  for (int j = 0; j < count; ++j) {
+    hss_handle* h = hs[j];
+    segs[j] = IRSeg{B[j], ldb[j], h->b0, h->res, h->d64, h->r32, h->plan.n, (int32_t)nrhs[j], 0,
+                    h->stats, h->norm2};
+    n_ld[j] = h->plan.n;
+    r32[j] = h->r32;
+    d64[j] = h->d64;
+    res[j] = h->res;
+  }
+  // the sweeps below use the scratch too, so the refinement tables get their own buffer
+  static std::mutex ir_mu;
+  static void* ir_d = nullptr;
+  static size_t ir_cap = 0;
+  std::lock_guard<std::mutex> g2(ir_mu);
+  const size_t bytes = sizeof(IRSeg) * count + 256;
+  if (ir_cap < bytes) {
+    if (ir_d) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(ir_d);
+    }
+    ir_cap = std::max<size_t>(bytes * 2, 1 << 16);
+    if (hipMalloc(&ir_d, ir_cap) != hipSuccess) {
+      ir_d = nullptr;
+      ir_cap = 0;
+      return HSS_ENOMEM;
+    }
+  }
+  double* gmax = reinterpret_cast<double*>(ir_d);
+  IRSeg* dsegs = reinterpret_cast<IRSeg*>((char*)ir_d + 256);
+  if (hipMemcpyAsync(dsegs, segs.data(), sizeof(IRSeg) * count, hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return HSS_EHIP;
+  auto ir = [&](int op) { launch_ir_batch(op, dsegs, count, maxn, gmax, s); };
+  ir(IR_ZERO_ALL);
+  if (need_eta) ir(IR_SAVE_B0);
+  auto correction = [&](bool first) -> hss_status {
+    hss_status e;
+    if (is64) {
+      if (first) return batch_sweep<double>(hs, count, nrhs, Bv.data(), ldb, s);
+      ir(IR_COPY_RES);
+      if ((e = batch_sweep<double>(hs, count, nrhs, d64.data(), n_ld.data(), s))) return e;
+      ir(IR_AXPY64);
+      return HSS_OK;
+    }
+    if (first) {
+      ir(IR_STATS_BMAX);
+      ir(IR_SCALE_B);
+    } else {
+      ir(IR_SCALE_RES);
+    }
+    if ((e = batch_sweep<float>(hs, count, nrhs, r32.data(), n_ld.data(), s))) return e;
+    ir(first ? IR_CAST_BACK : IR_AXPY_CAST);
+    return HSS_OK;
+  };
+  if ((st = correction(true))) return st;
+  int iters = 0;
+  double eta_max = 0.0;
+  if (need_eta) {
+    ir(IR_STATS_B0);
+    for (;;) {
+      if ((st = batch_matmul_unlocked(hs, count, nrhs, Bv.data(), ldb, res.data(), n_ld.data(),
+                                      s)))
+        return st;
+      ir(IR_ZERO);
+      launch_fill(gmax, 0.0, 1, s);
+      ir(IR_RESID);
+      ir(IR_STATS_X);
+      ir(IR_ETA);
+      if ((st = last_launch_status())) return st;
+      if (hipMemcpyAsync(&eta_max, gmax, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return HSS_EHIP;
+      if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
+      if (opt.tol <= 0.0 || eta_max <= opt.tol || iters >= opt.max_refine) break;
+      if ((st = correction(false))) return st;
+      ++iters;
+    }
+  }
+  if ((st = last_launch_status())) return st;
+  if (!need_eta && !info) return HSS_OK;
+  if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
+  hss_status worst = HSS_OK;
+  for (int j = 0; j < count; ++j) {
+    int32_t dstat = 0;
+    double out[1] = {0.0};
+    if (hipMemcpy(&dstat, hs[j]->d_status, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      return HSS_EHIP;
+    const int64_t nr = nrhs[j];
+    if (need_eta &&
+        hipMemcpy(out, hs[j]->stats + 6 * nr, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return HSS_EHIP;
+    hss_status r = HSS_OK;
+    if (dstat & (1 << HSS_ESINGULAR)) r = HSS_ESINGULAR;
+    else if (need_eta && opt.tol > 0.0 && out[0] > opt.tol) r = HSS_ENOCONV;
+    if (r && !worst) worst = r;
+    if (info) {
+      info[j].eta_max = out[0];
+      info[j].iters = iters;
+      info[j].status = r;
+      info[j].norm2 = hs[j]->norm2;
+      if (info[j].eta && need_eta && nr > 0 &&
+          hipMemcpy(info[j].eta, hs[j]->stats + 5 * nr, sizeof(double) * nr,
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return HSS_EHIP;
+    }
+  }
+  return worst;
+}
+
+}  // namespace
+
+// ===========================================================================
 extern "C" {
 
 const char* hss_status_str(hss_status s) {
@@ -649,21 +1070,30 @@ hss_status hss_batch_matmul(hss_handle* const* hs, int32_t count, int32_t op, in
                             void* const* Y, const int64_t* ldy, void* stream) {
   if (!hs) return -1;
   if (count < 0) return -2;
+  if (op != HSS_OP_N && op != HSS_OP_T) return -3;
+  if (prec != HSS_F64 && prec != HSS_F32) return -4;
+  if (count > 0 && (!nrhs || !X || !ldx || !Y || !ldy)) return -5;
   for (int32_t i = 0; i < count; ++i) {
-    const hss_status st = hss_matmul(hs[i], op, prec, nrhs[i], X[i], ldx[i], Y[i], ldy[i], stream);
-    if (st) return st;
+    if (!hs[i] || nrhs[i] < 0 || (nrhs[i] > 0 && (!X[i] || !Y[i])) || ldx[i] < hs[i]->plan.n ||
+        ldy[i] < hs[i]->plan.n)
+      return -5;
   }
-  return HSS_OK;
+  if (count == 0) return HSS_OK;
+  hipStream_t s = (hipStream_t)stream;
+  return prec == HSS_F64
+             ? batch_matmul<double>(hs, count, op, nrhs, X, ldx, Y, ldy, s)
+             : batch_matmul<float>(hs, count, op, nrhs, X, ldx, Y, ldy, s);
 }
 
 hss_status hss_batch_ulv_factor(hss_handle* const* hs, int32_t count, int32_t prec, void* stream) {
   if (!hs) return -1;
   if (count < 0) return -2;
-  for (int32_t i = 0; i < count; ++i) {
-    const hss_status st = hss_ulv_factor(hs[i], prec, stream);
-    if (st) return st;
-  }
-  return HSS_OK;
+  if (prec != HSS_F64 && prec != HSS_F32) return -3;
+  for (int32_t i = 0; i < count; ++i)
+    if (!hs[i]) return -1;
+  if (count == 0) return HSS_OK;
+  hipStream_t s = (hipStream_t)stream;
+  return prec == HSS_F64 ? batch_factor<double>(hs, count, s) : batch_factor<float>(hs, count, s);
 }
 
 hss_status hss_batch_ulv_solve(hss_handle* const* hs, int32_t count, const int64_t* nrhs,
@@ -671,14 +1101,17 @@ hss_status hss_batch_ulv_solve(hss_handle* const* hs, int32_t count, const int64
                                hss_solve_info* info, void* stream) {
   if (!hs) return -1;
   if (count < 0) return -2;
-  hss_status worst = HSS_OK;
+  if (count > 0 && (!nrhs || !B || !ldb)) return -3;
+  hss_solve_opts opt{HSS_F64, 10, 0.0, 0, 0};
+  if (o) opt = *o;
+  if (opt.prec != HSS_F64 && opt.prec != HSS_F32) return -6;
+  if (opt.max_refine < 0 || !(opt.tol >= 0.0)) return -6;
   for (int32_t i = 0; i < count; ++i) {
-    const hss_status st = hss_ulv_solve(hs[i], nrhs[i], B[i], ldb[i], o, info ? info + i : nullptr,
-                                        stream);
-    if (st < 0 || st == HSS_EHIP || st == HSS_ENOMEM || st == HSS_ESTATE) return st;
-    if (st) worst = st;
+    if (!hs[i] || nrhs[i] < 0 || (nrhs[i] > 0 && !B[i]) || ldb[i] < hs[i]->plan.n) return -3;
+    if (opt.prec == HSS_F64 ? !hs[i]->f64.valid : !hs[i]->f32.valid) return HSS_ESTATE;
   }
-  return worst;
+  if (count == 0) return HSS_OK;
+  return batch_solve(hs, count, nrhs, B, ldb, opt, info, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -62,4 +62,35 @@ void launch_hash_fill(double* d, int64_t n, uint64_t seed, hipStream_t s);
 void launch_eta(const double* rr, const double* xx, const double* bb, double normA, int64_t nrhs,
                 double* eta, double* out, hipStream_t s);
 
+// Iterative refinement over many instances (one launch per operation).
+struct IRSeg {
+  double* B;        // solution being refined (caller's memory), leading dimension ldb
+  int64_t ldb;
+  double *b0, *res, *d64;   // n x nrhs, leading dimension n
+  float* r32;
+  int64_t n;
+  int32_t nrhs;
+  int32_t pad;
+  double* stats;    // rr | xx | bb | rmax | bmax | eta | out (nrhs each)
+  double norm2;
+};
+enum IROp {
+  IR_ZERO = 0,      // clear rr, xx, rmax
+  IR_SAVE_B0,       // b0 = B
+  IR_STATS_B0,      // bb += ||b0_j||^2
+  IR_STATS_BMAX,    // bmax = max |B_j|
+  IR_SCALE_B,       // r32 = B / bmax
+  IR_CAST_BACK,     // B = bmax * r32
+  IR_RESID,         // res = b0 - res; rr, rmax
+  IR_STATS_X,       // xx += ||B_j||^2
+  IR_ETA,           // eta_j, out = max_j eta_j, gmax = max over instances
+  IR_SCALE_RES,     // r32 = res / rmax
+  IR_AXPY_CAST,     // B += rmax * r32
+  IR_COPY_RES,      // d64 = res
+  IR_AXPY64,        // B += d64
+  IR_ZERO_ALL       // clear all stats
+};
+void launch_ir_batch(int op, const IRSeg* segs, int count, int64_t max_n, double* gmax,
+                     hipStream_t s);
+
 }  // namespace hss

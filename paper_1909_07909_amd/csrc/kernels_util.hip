@@ -135,7 +135,101 @@ __global__ void k_eta(const double* rr, const double* xx, const double* bb, doub
   }
   out[0] = mx;
 }
+// ---------------------------------------------------------------------------
+// Refinement bookkeeping over many instances in one launch: blockIdx.y picks
+// the instance, the x dimension strides over the rows of every column.
+__device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void k_ir_batch(int op, const IRSeg* __restrict__ segs, int count, double* gmax) {
+  const IRSeg S = segs[blockIdx.y];
+  const int64_t n = S.n;
+  const int nr = S.nrhs;
+  double* rr = S.stats;
+  double* xx = rr + nr;
+  double* bb = xx + nr;
+  double* rmax = bb + nr;
+  double* bmax = rmax + nr;
+  double* eta = bmax + nr;
+  double* outv = eta + nr;
+  const int64_t i0 = blockIdx.x * (int64_t)kB + threadIdx.x, st = (int64_t)gridDim.x * kB;
+  if (op == IR_ZERO_ALL || op == IR_ZERO) {
+    if (blockIdx.x == 0)
+      for (int j = threadIdx.x; j < 7 * nr; j += kB) {
+        const int blk = j / nr;   // 0 rr, 1 xx, 2 bb, 3 rmax, 4 bmax, 5 eta, 6 out
+        if (op == IR_ZERO_ALL || blk == 0 || blk == 1 || blk == 3) S.stats[j] = 0.0;
+      }
+    return;
+  }
+  if (op == IR_ETA) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      double mx = 0.0;
+      for (int j = 0; j < nr; ++j) {
+        const double den = S.norm2 * sqrt(xx[j]) + sqrt(bb[j]);
+        const double v = den > 0.0 ? sqrt(rr[j]) / den : (rr[j] > 0.0 ? INFINITY : 0.0);
+        eta[j] = v;
+        mx = fmax(mx, v);
+      }
+      outv[0] = mx;
+      atomic_max_nonneg(gmax, mx);
+    }
+    return;
+  }
+  for (int j = 0; j < nr; ++j) {
+    double* Bj = S.B + j * S.ldb;
+    double* b0 = S.b0 + j * n;
+    double* rs = S.res + j * n;
+    double* d64 = S.d64 + j * n;
+    float* r32 = S.r32 + j * n;
+    double acc = 0.0, mx = 0.0;
+    for (int64_t i = i0; i < n; i += st) {
+      switch (op) {
+        case IR_SAVE_B0: b0[i] = Bj[i]; break;
+        case IR_STATS_B0: acc += b0[i] * b0[i]; break;
+        case IR_STATS_BMAX: mx = fmax(mx, fabs(Bj[i])); break;
+        case IR_SCALE_B: r32[i] = bmax[j] > 0.0 ? (float)(Bj[i] / bmax[j]) : 0.f; break;
+        case IR_CAST_BACK: Bj[i] = bmax[j] * (double)r32[i]; break;
+        case IR_RESID: {
+          const double r = b0[i] - rs[i];
+          rs[i] = r;
+          acc += r * r;
+          mx = fmax(mx, fabs(r));
+          break;
+        }
+        case IR_STATS_X: acc += Bj[i] * Bj[i]; break;
+        case IR_SCALE_RES: r32[i] = rmax[j] > 0.0 ? (float)(rs[i] / rmax[j]) : 0.f; break;
+        case IR_AXPY_CAST: Bj[i] += rmax[j] * (double)r32[i]; break;
+        case IR_COPY_RES: d64[i] = rs[i]; break;
+        case IR_AXPY64: Bj[i] += d64[i]; break;
+        default: break;
+      }
+    }
+    if (op == IR_STATS_B0 || op == IR_RESID || op == IR_STATS_X || op == IR_STATS_BMAX) {
+      for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_xor(acc, off, 64);
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+      }
+      if ((threadIdx.x & 63) == 0) {
+        if (op == IR_STATS_B0) atomicAdd(&bb[j], acc);
+        if (op == IR_STATS_X) atomicAdd(&xx[j], acc);
+        if (op == IR_RESID) {
+          atomicAdd(&rr[j], acc);
+          atomic_max_nonneg(&rmax[j], mx);
+        }
+        if (op == IR_STATS_BMAX) atomic_max_nonneg(&bmax[j], mx);
+      }
+    }
+  }
+}
 }  // namespace
+
+void launch_ir_batch(int op, const IRSeg* segs, int count, int64_t max_n, double* gmax,
+                     hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_ir_batch, dim3(grid_for(max_n, 64), count), dim3(kB), 0, s, op, segs,
+                     count, gmax);
+}
 
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
   if (n <= 0) return;

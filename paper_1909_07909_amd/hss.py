@@ -314,4 +314,5 @@ def batch_solve(mats, Bs, prec=F64, tol=0.0, max_refine=10, want_eta=False, stre
     if code not in (HSS_OK, HSS_ENOCONV):
         raise HSSError(code, "hss_batch_ulv_solve")
     return [{"eta": etas[i][:Bs[i].shape[1]].copy(), "eta_max": infos[i].eta_max,
-             "iters": infos[i].iters, "status": infos[i].status} for i in range(cnt)]
+             "iters": infos[i].iters, "status": infos[i].status, "norm2": infos[i].norm2}
+            for i in range(cnt)]

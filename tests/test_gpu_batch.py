@@ -1,0 +1,96 @@
+"""GPU: the batched calls (one launch per tree level across instances of
+different sizes, depths and ranks) give each instance exactly what the
+single-instance call gives, and match the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import tree
+from oracle.hss import HSS
+from oracle.matvec import matvec as omatvec
+from paper_1909_07909_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev(X):
+    return torch.from_numpy(np.ascontiguousarray(np.asfortranarray(X).T)).cuda().t()
+
+
+def _host(t):
+    return t.t().contiguous().cpu().numpy().T
+
+
+def _instances(count=10, seed=3):
+    """Uneven instances of the batching workload family: n a multiple of 64,
+    leaf size 64, rank in {8, 16, 24}; plus one single-leaf instance."""
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(count)
+    out = []
+    for j, child in enumerate(kids):
+        r = np.random.default_rng(child)
+        n = 64 * int(r.integers(32, 129))
+        k = int(r.choice([8, 16, 24]))
+        out.append(inputs.synthetic_hss(tree.leaf_offsets(n, 64), k, seed=child))
+    out.append(inputs.synthetic_hss(tree.leaf_offsets(50, 64), 4, seed=99))
+    return out
+
+
+@pytest.fixture(scope="module")
+def batch():
+    from paper_1909_07909_amd import hss
+    gens = _instances()
+    mats = [hss.HSSMatrix(g) for g in gens]
+    return gens, mats
+
+
+def test_batch_matmul_equals_single(batch):
+    from paper_1909_07909_amd import hss
+    gens, mats = batch
+    r = 8
+    Xs = [_dev(inputs.rhs(g.n, r, 10 + j)) for j, g in enumerate(gens)]
+    Ys = [hss.empty_colmajor(g.n, r, torch.float64) for g in gens]
+    hss.batch_matmul(mats, Xs, Ys)
+    for j, (g, A) in enumerate(zip(gens, mats)):
+        single = _host(A.matmul(Xs[j]))
+        np.testing.assert_array_equal(_host(Ys[j]), single)
+        ref = omatvec(HSS.from_packed(g), _host(Xs[j]))
+        assert np.max(np.linalg.norm(single - ref, axis=0) / np.linalg.norm(ref, axis=0)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_solve_equals_single(batch, prec):
+    from paper_1909_07909_amd import hss
+    gens, mats = batch
+    r = 8
+    B = [inputs.rhs(g.n, r, 20 + j) for j, g in enumerate(gens)]
+    hss.batch_factor(mats, prec)
+    Bb = [_dev(b) for b in B]
+    hss.batch_solve(mats, Bb, prec=prec)               # plain sweep, no refinement
+    for j, A in enumerate(mats):
+        A.factor(prec)
+        Bs = _dev(B[j])
+        A.solve_async(Bs, prec=prec)
+        np.testing.assert_array_equal(_host(Bb[j]), _host(Bs))
+
+
+def test_batch_refined_solves(batch):
+    from paper_1909_07909_amd import hss
+    gens, mats = batch
+    r = 8
+    B = [inputs.rhs(g.n, r, 30 + j) for j, g in enumerate(gens)]
+    hss.batch_factor(mats, hss.F32)
+    Bb = [_dev(b) for b in B]
+    infos = hss.batch_solve(mats, Bb, prec=hss.F32, tol=1e-10, max_refine=10)
+    for j, (g, info) in enumerate(zip(gens, infos)):
+        assert info["eta_max"] <= 1e-10, (j, info)
+        H = HSS.from_packed(g)
+        X = _host(Bb[j])
+        res = B[j] - omatvec(H, X)
+        eta = np.linalg.norm(res, axis=0) / (info["norm2"] * np.linalg.norm(X, axis=0)
+                                             + np.linalg.norm(B[j], axis=0))
+        assert eta.max() <= 1e-10
+    hss.batch_factor(mats, hss.F64)
+    Bd = [_dev(b) for b in B]
+    infos = hss.batch_solve(mats, Bd, prec=hss.F64, want_eta=True)
+    assert max(i["eta_max"] for i in infos) <= 1e-12
