@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -360,33 +361,52 @@ hss_status compute_norm2(hss_handle* h, hipStream_t s) {
 // ===========================================================================
 namespace {
 
+// Device scratch for the task / pointer tables of batched calls, one per
+// stream: batched calls on different streams run concurrently, calls on one
+// stream are serialized by the scratch's lock (and by the stream itself).
 struct BatchScratch {
   void* d = nullptr;
   size_t cap = 0;
+  void* ir = nullptr;    // refinement descriptors
+  size_t ir_cap = 0;
   std::mutex mu;
 };
-BatchScratch g_bs;
+std::mutex g_scratch_mu;
+std::map<hipStream_t, BatchScratch*> g_scratch;
 
-hss_status scratch_upload(const std::vector<char>& host, hipStream_t s, void** dptr) {
-  if (g_bs.cap < host.size()) {
-    if (g_bs.d) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(g_bs.d);
-      g_bs.d = nullptr;
-      g_bs.cap = 0;
-    }
-    size_t cap = std::max<size_t>(host.size() * 2, 1 << 20);
-    if (hipMalloc(&g_bs.d, cap) != hipSuccess) {
-      (void)hipGetLastError();
-      return HSS_ENOMEM;
-    }
-    g_bs.cap = cap;
+BatchScratch& scratch_for(hipStream_t s) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  BatchScratch*& p = g_scratch[s];
+  if (!p) p = new BatchScratch();
+  return *p;
+}
+
+hss_status grow(void** d, size_t* cap, size_t need, hipStream_t s) {
+  if (*cap >= need) return HSS_OK;
+  if (*d) {
+    if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
+    (void)hipFree(*d);
+    *d = nullptr;
+    *cap = 0;
   }
-  // pageable source: the copy is staged before the call returns
+  const size_t c = std::max<size_t>(need * 2, 1 << 20);
+  if (hipMalloc(d, c) != hipSuccess) {
+    (void)hipGetLastError();
+    return HSS_ENOMEM;
+  }
+  *cap = c;
+  return HSS_OK;
+}
+
+hss_status scratch_upload(BatchScratch& B, const std::vector<char>& host, hipStream_t s,
+                          void** dptr) {
+  hss_status st = grow(&B.d, &B.cap, host.size(), s);
+  if (st) return st;
+  // pageable source: the runtime stages it before the call returns
   if (!host.empty() &&
-      hipMemcpyAsync(g_bs.d, host.data(), host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+      hipMemcpyAsync(B.d, host.data(), host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
     return HSS_EHIP;
-  *dptr = g_bs.d;
+  *dptr = B.d;
   return HSS_OK;
 }
 
@@ -435,7 +455,8 @@ int max_depth(hss_handle* const* hs, int count) {
 }
 
 template <typename T>
-hss_status batch_matmul_impl(hss_handle* const* hs, int count, int op, const int64_t* nrhs,
+hss_status batch_matmul_impl(BatchScratch& BS, hss_handle* const* hs, int count, int op,
+                             const int64_t* nrhs,
                              const void* const* X, const int64_t* ldx, void* const* Y,
                              const int64_t* ldy, hipStream_t s) {
   int64_t maxr = 0;
@@ -466,7 +487,7 @@ hss_status batch_matmul_impl(hss_handle* const* hs, int count, int op, const int
   Packer pk;
   const size_t oi = pk.add(insts), oc = pk.add(calls), ot = pk.add(L.tasks);
   void* d = nullptr;
-  hss_status st = scratch_upload(pk.buf, s, &d);
+  hss_status st = scratch_upload(BS, pk.buf, s, &d);
   if (st) return st;
   KArgs<T, CallMM<T>> a{};
   a.insts = reinterpret_cast<const Inst<T>*>((char*)d + oi);
@@ -491,22 +512,25 @@ template <typename T>
 hss_status batch_matmul(hss_handle* const* hs, int count, int op, const int64_t* nrhs,
                         const void* const* X, const int64_t* ldx, void* const* Y,
                         const int64_t* ldy, hipStream_t s) {
-  std::lock_guard<std::mutex> g(g_bs.mu);
-  return batch_matmul_impl<T>(hs, count, op, nrhs, X, ldx, Y, ldy, s);
+  BatchScratch& B = scratch_for(s);
+  std::lock_guard<std::mutex> g(B.mu);
+  return batch_matmul_impl<T>(B, hs, count, op, nrhs, X, ldx, Y, ldy, s);
 }
 
 // FP64 A X for the refinement residuals (the caller holds the scratch lock).
-hss_status batch_matmul_unlocked(hss_handle* const* hs, int count, const int64_t* nrhs,
-                                 double* const* X, const int64_t* ldx, double* const* Y,
-                                 const int64_t* ldy, hipStream_t s) {
+hss_status batch_matmul_unlocked(BatchScratch& BS, hss_handle* const* hs, int count,
+                                 const int64_t* nrhs, double* const* X, const int64_t* ldx,
+                                 double* const* Y, const int64_t* ldy, hipStream_t s) {
   std::vector<const void*> xv(X, X + count);
   std::vector<void*> yv(Y, Y + count);
-  return batch_matmul_impl<double>(hs, count, HSS_OP_N, nrhs, xv.data(), ldx, yv.data(), ldy, s);
+  return batch_matmul_impl<double>(BS, hs, count, HSS_OP_N, nrhs, xv.data(), ldx, yv.data(), ldy,
+                                   s);
 }
 
 template <typename T>
 hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
-  std::lock_guard<std::mutex> g(g_bs.mu);
+  BatchScratch& BS = scratch_for(s);
+  std::lock_guard<std::mutex> g(BS.mu);
   std::vector<Inst<T>> insts(count);
   for (int j = 0; j < count; ++j) {
     hss_status st = ensure_factors<T>(hs[j]);
@@ -527,7 +551,7 @@ hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
   Packer pk;
   const size_t oi = pk.add(insts), ot = pk.add(L.tasks);
   void* d = nullptr;
-  hss_status st = scratch_upload(pk.buf, s, &d);
+  hss_status st = scratch_upload(BS, pk.buf, s, &d);
   if (st) return st;
   for (int j = 0; j < count; ++j) launch_fill(reinterpret_cast<double*>(hs[j]->d_status), 0.0, 2, s);
   KArgs<T, CallSV<T>> a{};
@@ -563,8 +587,8 @@ hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
 // One batched solve sweep (forward, root, backward) on per-instance
 // right-hand sides rhs[j] (precision T, leading dimension ld[j]).
 template <typename T>
-hss_status batch_sweep(hss_handle* const* hs, int count, const int64_t* nrhs, T* const* rhs,
-                       const int64_t* ld, hipStream_t s) {
+hss_status batch_sweep(BatchScratch& BS, hss_handle* const* hs, int count, const int64_t* nrhs,
+                       T* const* rhs, const int64_t* ld, hipStream_t s) {
   std::vector<Inst<T>> insts(count);
   std::vector<CallSV<T>> calls(count);
   int64_t maxr = 0;
@@ -604,7 +628,7 @@ hss_status batch_sweep(hss_handle* const* hs, int count, const int64_t* nrhs, T*
   Packer pk;
   const size_t oi = pk.add(insts), oc = pk.add(calls), ot = pk.add(L.tasks);
   void* d = nullptr;
-  hss_status st = scratch_upload(pk.buf, s, &d);
+  hss_status st = scratch_upload(BS, pk.buf, s, &d);
   if (st) return st;
   KArgs<T, CallSV<T>> a{};
   a.insts = reinterpret_cast<const Inst<T>*>((char*)d + oi);
@@ -643,7 +667,8 @@ hss_status batch_sweep(hss_handle* const* hs, int count, const int64_t* nrhs, T*
 hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, double* const* B,
                        const int64_t* ldb, const hss_solve_opts& opt, hss_solve_info* info,
                        hipStream_t s) {
-  std::lock_guard<std::mutex> g(g_bs.mu);
+  BatchScratch& BS = scratch_for(s);
+  std::lock_guard<std::mutex> g(BS.mu);
   const bool is64 = opt.prec == HSS_F64;
   const bool need_eta = opt.want_eta || opt.tol > 0.0;
   hss_status st;
@@ -669,24 +694,9 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
     d64[j] = h->d64;
     res[j] = h->res;
   }
-  // the sweeps below use the scratch too, so the refinement tables get their own buffer
-  static std::mutex ir_mu;
-  static void* ir_d = nullptr;
-  static size_t ir_cap = 0;
-  std::lock_guard<std::mutex> g2(ir_mu);
-  const size_t bytes = sizeof(IRSeg) * count + 256;
-  if (ir_cap < bytes) {
-    if (ir_d) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(ir_d);
-    }
-    ir_cap = std::max<size_t>(bytes * 2, 1 << 16);
-    if (hipMalloc(&ir_d, ir_cap) != hipSuccess) {
-      ir_d = nullptr;
-      ir_cap = 0;
-      return HSS_ENOMEM;
-    }
-  }
+  // the sweeps below use the table scratch, so the refinement descriptors get their own
+  if ((st = grow(&BS.ir, &BS.ir_cap, sizeof(IRSeg) * count + 256, s))) return st;
+  void* ir_d = BS.ir;
   double* gmax = reinterpret_cast<double*>(ir_d);
   IRSeg* dsegs = reinterpret_cast<IRSeg*>((char*)ir_d + 256);
   if (hipMemcpyAsync(dsegs, segs.data(), sizeof(IRSeg) * count, hipMemcpyHostToDevice, s) !=
@@ -698,9 +708,9 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
   auto correction = [&](bool first) -> hss_status {
     hss_status e;
     if (is64) {
-      if (first) return batch_sweep<double>(hs, count, nrhs, Bv.data(), ldb, s);
+      if (first) return batch_sweep<double>(BS, hs, count, nrhs, Bv.data(), ldb, s);
       ir(IR_COPY_RES);
-      if ((e = batch_sweep<double>(hs, count, nrhs, d64.data(), n_ld.data(), s))) return e;
+      if ((e = batch_sweep<double>(BS, hs, count, nrhs, d64.data(), n_ld.data(), s))) return e;
       ir(IR_AXPY64);
       return HSS_OK;
     }
@@ -710,7 +720,7 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
     } else {
       ir(IR_SCALE_RES);
     }
-    if ((e = batch_sweep<float>(hs, count, nrhs, r32.data(), n_ld.data(), s))) return e;
+    if ((e = batch_sweep<float>(BS, hs, count, nrhs, r32.data(), n_ld.data(), s))) return e;
     ir(first ? IR_CAST_BACK : IR_AXPY_CAST);
     return HSS_OK;
   };
@@ -720,7 +730,7 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
   if (need_eta) {
     ir(IR_STATS_B0);
     for (;;) {
-      if ((st = batch_matmul_unlocked(hs, count, nrhs, Bv.data(), ldb, res.data(), n_ld.data(),
+      if ((st = batch_matmul_unlocked(BS, hs, count, nrhs, Bv.data(), ldb, res.data(), n_ld.data(),
                                       s)))
         return st;
       ir(IR_ZERO);

@@ -1,0 +1,302 @@
+"""Continuous-batching HSS solve server.
+
+Requests (matrix id, right-hand-side block, target backward error) arrive
+while earlier ones run on the GPU.  The factored matrices stay resident in HBM
+(a catalogue of HSSMatrix objects, FP32 ULV factors).  Worker threads, one
+HIP stream each, repeatedly form a round from the admitted requests:
+
+* admission is by device memory: a request is admitted once the bytes of its
+  right-hand sides and refinement buffers fit in the in-flight budget;
+* a round takes the admitted requests in arrival order, at most one group per
+  matrix and only matrices no other worker is using; requests on the same
+  matrix and tolerance class merge into one multi-column block;
+* a round runs one batched solve per tolerance class (one launch per tree
+  level across all its matrices, FP32 sweeps with FP64 refinement until the
+  class tolerance); requests that arrive meanwhile are admitted as memory frees
+  and picked up by the next free worker, so rounds overlap on the device.
+
+Each completed request records its latency (arrival to result on the host)
+and the backward error of every column.  The GPU work is all in libhss.so;
+this module only schedules.
+"""
+from __future__ import annotations
+
+import math
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import hss, inputs
+
+
+@dataclass
+class Request:
+    rid: int
+    mat: int
+    tol: float
+    nrhs: int
+    t_arrival: float
+    B: np.ndarray = field(repr=False, default=None)      # host, n x nrhs
+    X: np.ndarray = field(repr=False, default=None)      # host result
+    eta: np.ndarray = field(repr=False, default=None)
+    iters: int = 0
+    t_done: float = 0.0
+    status: int = 0
+
+
+def request_bytes(n: int, nrhs: int) -> int:
+    """Device bytes a request holds while in flight: its FP64 right-hand side
+    block plus the FP64 refinement copies (b0, residual, correction) and the
+    FP32 working block."""
+    return n * nrhs * (8 * 4 + 4)
+
+
+def draw_catalogue(count: int, seed: int, n_lo: int = 4096, n_hi: int = 2 ** 20,
+                   leaf: int = 128, ranks=(16, 32, 64)):
+    """(n, k) of the resident matrices: n log-uniform in [n_lo, n_hi] rounded to
+    a multiple of the leaf size, k uniform over ``ranks``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi))) / leaf)) * leaf
+        n = max(leaf, n)
+        out.append((n, int(rng.choice(ranks))))
+    return out
+
+
+def _gen_one(args):
+    n, k, seed, leaf = args
+    lo = hss.plan_leaf_offsets(n, leaf)
+    return inputs.synthetic_hss(lo, k, seed=seed)
+
+
+def build_catalogue(specs, seed: int, leaf: int = 128, workers: int = 8):
+    """Generators of the catalogue (host), drawn in parallel processes."""
+    from concurrent.futures import ProcessPoolExecutor
+    jobs = [(n, k, seed * 1000 + j, leaf) for j, (n, k) in enumerate(specs)]
+    if workers <= 1:
+        return [_gen_one(j) for j in jobs]
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_gen_one, jobs))
+
+
+def poisson_requests(rate: float, duration: float, n_mats: int, seed: int,
+                     tols=(1e-6, 1e-10), max_rhs: int = 16):
+    """Arrival times (exponential gaps at ``rate`` per second), matrix ids,
+    tolerance class (equal odds) and block widths U{1..max_rhs}."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    rid = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        out.append(Request(rid=rid, mat=int(rng.integers(n_mats)), tol=float(rng.choice(tols)),
+                           nrhs=int(rng.integers(1, max_rhs + 1)), t_arrival=t))
+        rid += 1
+    return out
+
+
+def rhs_for(req: Request, n: int) -> np.ndarray:
+    return inputs.rhs(n, req.nrhs, 10_000 + req.rid)
+
+
+def rhs_pools(mats, width: int = 32, seed: int = 77):
+    """One seeded n x width random block per matrix; a request takes a window
+    of consecutive columns (so that long runs do not draw fresh normals for
+    every request)."""
+    return [inputs.rhs(m.n, width, seed + j) for j, m in enumerate(mats)]
+
+
+def rhs_from_pool(req: Request, pools) -> np.ndarray:
+    P = pools[req.mat]
+    s = req.rid % (P.shape[1] - req.nrhs + 1)
+    return P[:, s:s + req.nrhs]
+
+
+class Server:
+    def __init__(self, mats, budget_bytes: int, workers: int = 2, max_mats_per_round: int = 64,
+                 max_cols_per_group: int = 64, max_refine: int = 10):
+        import torch
+        self.torch = torch
+        self.mats = mats
+        self.n = [m.n for m in mats]
+        self.budget = budget_bytes
+        self.max_mats = max_mats_per_round
+        self.max_cols = max_cols_per_group
+        self.max_refine = max_refine
+        self.pending = deque()        # arrived, waiting for memory
+        self.admitted = deque()       # admitted, waiting for a round
+        self.inflight_bytes = 0
+        self.peak_bytes = 0
+        self.busy = set()             # matrices used by a running round
+        self.done = []
+        self.cv = threading.Condition()
+        self.closed = False
+        self.nworkers = workers
+        self.rounds = 0
+        self.round_sizes = []
+        self.errors = []
+
+    # -- producer side ---------------------------------------------------------
+    def submit(self, req: Request):
+        with self.cv:
+            self.pending.append(req)
+            self._admit_locked()
+            self.cv.notify_all()
+
+    def close(self):
+        with self.cv:
+            self.closed = True
+            self.cv.notify_all()
+
+    def _admit_locked(self):
+        while self.pending:
+            r = self.pending[0]
+            b = request_bytes(self.n[r.mat], r.nrhs)
+            if self.inflight_bytes + b > self.budget and self.inflight_bytes > 0:
+                break
+            self.pending.popleft()
+            self.inflight_bytes += b
+            self.peak_bytes = max(self.peak_bytes, self.inflight_bytes)
+            self.admitted.append(r)
+
+    # -- rounds ----------------------------------------------------------------
+    def _take_round_locked(self):
+        groups = {}        # (mat, tol) -> [requests]
+        cols = {}
+        used = set()
+        keep = deque()
+        while self.admitted:
+            r = self.admitted.popleft()
+            key = (r.mat, r.tol)
+            if r.mat in self.busy or (r.mat in used and key not in groups):
+                keep.append(r)
+                continue
+            if key not in groups:
+                if len(used) >= self.max_mats:
+                    keep.append(r)
+                    continue
+                groups[key] = []
+                cols[key] = 0
+                used.add(r.mat)
+            if cols[key] + r.nrhs > self.max_cols and groups[key]:
+                keep.append(r)
+                continue
+            groups[key].append(r)
+            cols[key] += r.nrhs
+        # requests of one matrix in two tolerance classes: the matrix serves one
+        # class this round
+        by_mat = {}
+        for (m, t) in list(groups):
+            if m in by_mat:
+                keep.extendleft(reversed(groups.pop((m, t))))
+            else:
+                by_mat[m] = t
+        self.admitted = keep + self.admitted
+        for m in by_mat:
+            self.busy.add(m)
+        return groups
+
+    def _worker(self):
+        torch = self.torch
+        stream = torch.cuda.Stream()
+        while True:
+            with self.cv:
+                while True:
+                    groups = self._take_round_locked() if self.admitted else {}
+                    if groups:
+                        break
+                    if self.closed and not self.admitted and not self.pending:
+                        return
+                    self.cv.wait(timeout=0.01)
+            try:
+                self._run_round(groups, stream)
+            except Exception as ex:            # recorded; the loop keeps serving
+                self.errors.append(repr(ex))
+                for reqs in groups.values():
+                    for r in reqs:
+                        r.status = -1
+                        r.t_done = time.perf_counter()
+            with self.cv:
+                for (m, _t), reqs in groups.items():
+                    self.busy.discard(m)
+                    for r in reqs:
+                        self.inflight_bytes -= request_bytes(self.n[r.mat], r.nrhs)
+                        self.done.append(r)
+                self.rounds += 1
+                self.round_sizes.append(sum(len(v) for v in groups.values()))
+                self._admit_locked()
+                self.cv.notify_all()
+
+    def _run_round(self, groups, stream):
+        torch = self.torch
+        by_tol = {}
+        for (m, t), reqs in groups.items():
+            by_tol.setdefault(t, []).append((m, reqs))
+        with torch.cuda.stream(stream):
+            for tol, items in by_tol.items():
+                mats, blocks, splits = [], [], []
+                for m, reqs in items:
+                    n = self.n[m]
+                    host = np.concatenate([r.B for r in reqs], axis=1)
+                    dev = torch.from_numpy(np.ascontiguousarray(host.T)).to(
+                        "cuda", non_blocking=False).t()
+                    mats.append(self.mats[m])
+                    blocks.append(dev)
+                    splits.append(reqs)
+                infos = hss.batch_solve(mats, blocks, prec=hss.F32, tol=tol,
+                                        max_refine=self.max_refine, stream=stream)
+                for dev, reqs, info in zip(blocks, splits, infos):
+                    X = dev.t().contiguous().cpu().numpy().T
+                    now = time.perf_counter()
+                    c = 0
+                    for r in reqs:
+                        r.X = X[:, c:c + r.nrhs]
+                        r.eta = info["eta"][c:c + r.nrhs]
+                        r.iters = info["iters"]
+                        r.status = info["status"]
+                        r.t_done = now
+                        c += r.nrhs
+
+    def start(self):
+        self.threads = [threading.Thread(target=self._worker, daemon=True)
+                        for _ in range(self.nworkers)]
+        for t in self.threads:
+            t.start()
+
+    def join(self):
+        for t in self.threads:
+            t.join()
+
+
+def run_stream(mats, requests, budget_bytes: int, workers: int = 2, pools=None):
+    """Release ``requests`` at their arrival times (relative to now) into a
+    server and wait for all of them.  Returns (server, wall seconds)."""
+    for r in requests:
+        if r.B is None:
+            r.B = rhs_from_pool(r, pools) if pools is not None else rhs_for(r, mats[r.mat].n)
+    srv = Server(mats, budget_bytes, workers=workers)
+    srv.start()
+    start = time.perf_counter()
+    for r in requests:
+        delay = start + r.t_arrival - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        r.t_arrival = time.perf_counter()
+        srv.submit(r)
+    srv.close()
+    srv.join()
+    return srv, time.perf_counter() - start
+
+
+def latency_stats(reqs):
+    lat = np.array([r.t_done - r.t_arrival for r in reqs if r.status in (0,)])
+    if lat.size == 0:
+        return {}
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3)}
