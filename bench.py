@@ -78,6 +78,14 @@ def main():
     ap.add_argument("--instances", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--workload", default="headline", choices=["headline", "batch", "serve"],
+                    help="headline: one n=2^18 system (default); batch: 512 uneven instances "
+                         "in level-batched launches; serve: Poisson request stream")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run one plain device copy of this many bytes (a reference "
+                         "kernel of known traffic for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this "
@@ -90,6 +98,16 @@ def main():
 
     from paper_1909_07909_amd import hss, inputs
 
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
@@ -255,6 +273,147 @@ def main():
     if args.out:
         with open(args.out, "w") as f:
             f.write(line + "\n")
+
+
+def _emit(out, args):
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+def _gen_batch_instance(child):
+    import numpy as np
+
+    from paper_1909_07909_amd import hss, inputs
+    r = np.random.default_rng(child)
+    n = 64 * int(r.integers(32, 513))
+    k = int(r.choice([8, 16, 24]))
+    return inputs.synthetic_hss(hss.plan_leaf_offsets(n, 64), k, seed=child)
+
+
+def bench_batch(args):
+    """512 independent instances, n = 64 * U{32..512}, leaf 64, k in {8,16,24},
+    8 right-hand sides each; all factored and solved with one launch per tree
+    level across the instances, FP32+IR (eta <= 1e-10) and FP64."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    import numpy as np
+    import torch
+
+    from paper_1909_07909_amd import hss, inputs
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    count, r = 512, 8
+    kids = np.random.SeedSequence(3).spawn(count)
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=16) as ex:
+        gens = list(ex.map(_gen_batch_instance, kids, chunksize=8))
+    log(f"[bench-batch] generated {count} instances in {time.perf_counter() - t0:.1f} s, "
+        f"sum n = {sum(g.n for g in gens)}")
+    mats = [hss.HSSMatrix(g) for g in gens]
+    G = sum(m.query(hss.Q_GEN_ENTRIES) for m in mats)
+    B0 = [torch.from_numpy(np.ascontiguousarray(inputs.rhs(g.n, r, 7 + j).T)).cuda().t()
+          for j, g in enumerate(gens)]
+    del gens
+    work = [b.clone().t().contiguous().t() for b in B0]
+    for m in mats:
+        m.norm2()
+
+    def step(prec):
+        for w, b in zip(work, B0):
+            w.copy_(b)
+        hss.batch_factor(mats, prec)
+        if prec == hss.F32:
+            return hss.batch_solve(mats, work, prec=hss.F32, tol=1e-10, max_refine=10)
+        return hss.batch_solve(mats, work, prec=hss.F64, want_eta=True)
+
+    res = {}
+    for name, prec in (("fp32ir", hss.F32), ("fp64", hss.F64)):
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            infos = step(prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        res[name] = {"ms_per_step": round(dt * 1e3, 3), "systems_per_s": round(count / dt, 1),
+                     "eta_max": max(i["eta_max"] for i in infos),
+                     "iters_max": max(i["iters"] for i in infos)}
+        log(f"[bench-batch] {name}: {dt * 1e3:.2f} ms per {count} systems, "
+            f"eta_max {res[name]['eta_max']:.2e}")
+    # level-batched FP64 product, 8 columns each
+    Ys = [hss.empty_colmajor(m.n, r, torch.float64) for m in mats]
+    for _ in range(args.warmup):
+        hss.batch_matmul(mats, B0, Ys)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        hss.batch_matmul(mats, B0, Ys)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    nsum = sum(m.n for m in mats)
+    byt = (G + 2 * nsum * r) * 8
+    res["matmul_fp64"] = {"ms": round(dt * 1e3, 3), "gbps": round(byt / dt / 1e9, 1)}
+    out = {"metric": METRIC + " [batching workload]", "value": res["fp32ir"]["systems_per_s"],
+           "unit": "systems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["fp32ir"]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64ir", "data": "synthetic",
+           "config": {"workload": f"{count} HSS instances, n=64*U{{32..512}} (sum {nsum}), leaf 64, "
+                                  f"k in {{8,16,24}}, nrhs={r}, factor + solve to eta<=1e-10, "
+                                  "one launch per tree level across instances"},
+           "fp64": res["fp64"], "fp32ir": res["fp32ir"], "matmul_fp64": res["matmul_fp64"],
+           "ratio_fp32ir_over_fp64": round(res["fp64"]["ms_per_step"] / res["fp32ir"]["ms_per_step"], 3),
+           "roofline": None, "cpu_baseline": None}
+    _emit(out, args)
+
+
+def bench_serve(args):
+    """Poisson stream of solve requests against a catalogue of resident,
+    FP32-factored matrices (n log-uniform in [4096, 2^20], k in {16,32,64},
+    leaf 128), tolerance 1e-6 or 1e-10 at equal odds, 1-16 columns."""
+    import numpy as np
+    import torch
+
+    from paper_1909_07909_amd import hss, serve
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    specs = serve.draw_catalogue(16, seed=4)
+    t0 = time.perf_counter()
+    gens = serve.build_catalogue(specs, seed=4, workers=16)
+    log(f"[bench-serve] catalogue {specs} generated in {time.perf_counter() - t0:.1f} s")
+    mats = [hss.HSSMatrix(g) for g in gens]
+    del gens
+    t0 = time.perf_counter()
+    for m in mats:
+        m.factor(hss.F32)
+        m.norm2()
+    torch.cuda.synchronize()
+    log(f"[bench-serve] factored in {time.perf_counter() - t0:.2f} s")
+    pools = serve.rhs_pools(mats)
+    warm = serve.poisson_requests(args.serve_rate, 0.2, len(mats), seed=40)
+    serve.run_stream(mats, warm, budget_bytes=24 << 30, workers=2, pools=pools)
+    reqs = serve.poisson_requests(args.serve_rate, args.serve_seconds, len(mats), seed=41)
+    srv, wall = serve.run_stream(mats, reqs, budget_bytes=24 << 30, workers=2, pools=pools)
+    ok = [r for r in srv.done if r.status == 0]
+    lat = serve.latency_stats(srv.done)
+    good = all(r.eta.max() <= r.tol for r in ok)
+    cols = sum(r.nrhs for r in ok)
+    log(f"[bench-serve] {len(ok)}/{len(reqs)} requests in {wall:.2f} s, {lat}, all within tol: {good}")
+    out = {"metric": METRIC + " [serving workload]", "value": round(len(ok) / wall, 1),
+           "unit": "solves/s", "n_gpus": 1, "steps": len(reqs), "warmup": len(warm),
+           "ms_per_step": round(wall / max(len(ok), 1) * 1e3, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64ir", "data": "synthetic",
+           "config": {"workload": f"Poisson {args.serve_rate:.0f} req/s for {args.serve_seconds} s, "
+                                  "16 resident matrices n log-uniform [4096, 2^20], k in {16,32,64}, "
+                                  "leaf 128, tol 1e-6 / 1e-10, 1-16 rhs"},
+           "latency": lat, "rhs_columns_per_s": round(cols / wall, 1),
+           "all_within_tol": good, "rounds": srv.rounds,
+           "mean_requests_per_round": round(float(np.mean(srv.round_sizes)), 2),
+           "peak_inflight_bytes": srv.peak_bytes,
+           "resident_bytes": int(sum(m.query(hss.Q_RESIDENT_BYTES) for m in mats)),
+           "errors": srv.errors[:3], "roofline": None, "cpu_baseline": None}
+    _emit(out, args)
 
 
 def cpu_baseline(lo, r):
