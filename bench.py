@@ -343,6 +343,17 @@ def bench_batch(args):
                      "iters_max": max(i["iters"] for i in infos)}
         log(f"[bench-batch] {name}: {dt * 1e3:.2f} ms per {count} systems, "
             f"eta_max {res[name]['eta_max']:.2e}")
+    # per-kernel event timings of one step of each precision
+    for name, prec in (("fp32ir", hss.F32), ("fp64", hss.F64)):
+        hss.timing_enable(True)
+        hss.timing_report(reset=True)
+        step(prec)
+        torch.cuda.synchronize()
+        rep = sorted(hss.timing_report(reset=True), key=lambda d: -d["total_ms"])
+        hss.timing_enable(False)
+        res[name]["kernels_ms"] = {d["kernel"]: round(d["total_ms"], 3) for d in rep[:12]}
+        log(f"[bench-batch] {name} kernels: " + ", ".join(
+            f"{d['kernel']} {d['total_ms']:.2f}ms/{d['launches']}" for d in rep[:12]))
     # level-batched FP64 product, 8 columns each
     Ys = [hss.empty_colmajor(m.n, r, torch.float64) for m in mats]
     for _ in range(args.warmup):
@@ -411,6 +422,7 @@ def bench_serve(args):
            "all_within_tol": good, "rounds": srv.rounds,
            "mean_requests_per_round": round(float(np.mean(srv.round_sizes)), 2),
            "peak_inflight_bytes": srv.peak_bytes,
+           "worker_phase_s": {k: round(v, 3) for k, v in srv.phase_s.items()},
            "resident_bytes": int(sum(m.query(hss.Q_RESIDENT_BYTES) for m in mats)),
            "errors": srv.errors[:3], "roofline": None, "cpu_baseline": None}
     _emit(out, args)

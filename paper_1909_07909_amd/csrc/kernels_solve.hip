@@ -143,60 +143,76 @@ __device__ NodeSrc<T> src_stage_fwd(const Inst<T>& I, const NodeInfo& nd, int no
   return S;   // the caller synchronizes the work-group
 }
 
-// rhs of an internal node (rows lane, lane + 64) from the children's c and z.
-template <typename T>
-__device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, int node, int col, int lane,
-                                const NodeSrc<T>& S, T& x0, T& x1) {
+// rhs of an internal node (rows lane, lane + 64) from the children's c and z,
+// for CPW columns col0 .. col0+CPW-1 (columns >= nrhs read as zero).
+template <typename T, int CPW>
+__device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, int node, int col0,
+                                int nrhs, int lane, const NodeSrc<T>& S, T (&x0)[CPW],
+                                T (&x1)[CPW]) {
   const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
-  const int64_t co = (int64_t)col * I.lds;
-  const T* z1 = I.wz + n1.oz + co;
-  const T* z2 = I.wz + n2.oz + co;
-  const T* c1 = I.wc + n1.oc + co;
-  const T* c2 = I.wc + n2.oc + co;
   const int k1 = n1.kept, mp = nd.mp;
   const int r0 = lane, r1 = lane + 64;
-  // vectors of the children first (independent loads)
-  const T z1l = lane < n1.kv ? z1[lane] : T(0);
-  const T z2l = lane < n2.kv ? z2[lane] : T(0);
-  const T cc0 = r0 < k1 ? c1[r0] : (r0 < mp ? c2[r0 - k1] : T(0));
-  const T cc1 = r1 < k1 ? c1[r1] : (r1 < mp ? c2[r1 - k1] : T(0));
-  T t1 = 0, t2 = 0;
-#pragma unroll 8
+  T t1[CPW], t2[CPW], z1l[CPW], z2l[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const bool cv = col0 + c < nrhs;
+    const int64_t co = (int64_t)(cv ? col0 + c : 0) * I.lds;
+    const T* z1 = I.wz + n1.oz + co;
+    const T* z2 = I.wz + n2.oz + co;
+    const T* c1 = I.wc + n1.oc + co;
+    const T* c2 = I.wc + n2.oc + co;
+    z1l[c] = cv && lane < n1.kv ? z1[lane] : T(0);
+    z2l[c] = cv && lane < n2.kv ? z2[lane] : T(0);
+    x0[c] = !cv ? T(0) : (r0 < k1 ? c1[r0] : (r0 < mp ? c2[r0 - k1] : T(0)));
+    x1[c] = !cv ? T(0) : (r1 < k1 ? c1[r1] : (r1 < mp ? c2[r1 - k1] : T(0)));
+    t1[c] = T(0);
+    t2[c] = T(0);
+  }
+#pragma unroll 4
   for (int y = 0; y < n2.kv; ++y) {
-    const T zy = bcast(z2l, y);
-    if (lane < n1.ku) t1 += S.B12[lane + y * S.ld12] * zy;
+    const T b = lane < n1.ku ? S.B12[lane + y * S.ld12] : T(0);
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) t1[c] += b * bcast(z2l[c], y);
   }
-#pragma unroll 8
+#pragma unroll 4
   for (int y = 0; y < n1.kv; ++y) {
-    const T zy = bcast(z1l, y);
-    if (lane < n2.ku) t2 += S.B21[lane + y * S.ld21] * zy;
+    const T b = lane < n2.ku ? S.B21[lane + y * S.ld21] : T(0);
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) t2[c] += b * bcast(z1l[c], y);
   }
-  T a0 = 0, a1 = 0;
-#pragma unroll 8
+#pragma unroll 4
   for (int x = 0; x < n1.ku; ++x) {
-    const T tx = bcast(t1, x);
-    if (r0 < k1) a0 += ut(S.U1, S.ldu1, S.m1, r0, x) * tx;
-    if (r1 < k1) a1 += ut(S.U1, S.ldu1, S.m1, r1, x) * tx;
+    const T u0 = r0 < k1 ? ut(S.U1, S.ldu1, S.m1, r0, x) : T(0);
+    const T u1 = r1 < k1 ? ut(S.U1, S.ldu1, S.m1, r1, x) : T(0);
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const T tx = bcast(t1[c], x);
+      x0[c] -= u0 * tx;
+      x1[c] -= u1 * tx;
+    }
   }
-#pragma unroll 8
+#pragma unroll 4
   for (int x = 0; x < n2.ku; ++x) {
-    const T tx = bcast(t2, x);
-    if (r0 >= k1 && r0 < mp) a0 += ut(S.U2, S.ldu2, S.m2, r0 - k1, x) * tx;
-    if (r1 >= k1 && r1 < mp) a1 += ut(S.U2, S.ldu2, S.m2, r1 - k1, x) * tx;
+    const T u0 = r0 >= k1 && r0 < mp ? ut(S.U2, S.ldu2, S.m2, r0 - k1, x) : T(0);
+    const T u1 = r1 >= k1 && r1 < mp ? ut(S.U2, S.ldu2, S.m2, r1 - k1, x) : T(0);
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const T tx = bcast(t2[c], x);
+      x0[c] -= u0 * tx;
+      x1[c] -= u1 * tx;
+    }
   }
-  x0 = cc0 - a0;
-  x1 = cc1 - a1;
 }
 
 // Work item of this wavefront.  Direct kernels: kSW wavefronts per
-// work-group, one (node, column) each.  Staged kernels: one node per
-// work-group, its kSW wavefronts take kSW consecutive columns.
-template <bool BATCH, bool STAGED, typename T>
+// work-group, one node each, CPW columns per wavefront.  Staged kernels: one
+// node per work-group, its kSW wavefronts take kSW * CPW consecutive columns.
+template <bool BATCH, bool STAGED, int CPW, typename T>
 __device__ __forceinline__ bool sv_resolve(const KArgs<T, CallSV<T>>& a, Inst<T>& I,
-                                           CallSV<T>& C, int& node, int& col) {
+                                           CallSV<T>& C, int& node, int& col0) {
   const int w = threadIdx.x >> 6;
   const int item = STAGED ? blockIdx.x : blockIdx.x * kSW + w;
-  col = STAGED ? blockIdx.y * kSW + w : blockIdx.y;
+  col0 = (STAGED ? blockIdx.y * kSW + w : blockIdx.y) * CPW;
   if (item >= a.ntasks) return false;
   if constexpr (BATCH) {
     const int2 tk = a.tasks[item];
@@ -211,14 +227,15 @@ __device__ __forceinline__ bool sv_resolve(const KArgs<T, CallSV<T>>& a, Inst<T>
   return true;
 }
 
-// Forward sweep at one node.  STAGED: one wavefront per work-group, the
-// node's factors copied to LDS first (internal nodes); otherwise kSW
-// wavefronts per work-group reading the factor arrays (leaves).
-template <typename T, bool BATCH, bool STAGED>
+// Forward sweep at one node.  STAGED: the node's factors are copied to LDS by
+// the whole work-group first (internal nodes); otherwise kSW wavefronts per
+// work-group read the factor arrays (leaves).  Each wavefront carries CPW
+// right-hand-side columns through the same factor reads.
+template <typename T, bool BATCH, bool STAGED, int CPW>
 __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
-  Inst<T> I; CallSV<T> C; int node, col;
-  if (!sv_resolve<BATCH, STAGED>(a, I, C, node, col)) return;   // uniform when STAGED
+  Inst<T> I; CallSV<T> C; int node, col0;
+  if (!sv_resolve<BATCH, STAGED, CPW>(a, I, C, node, col0)) return;   // uniform when STAGED
   const int lane = threadIdx.x & 63;
   const NodeInfo nd = I.nodes[node];
   const int mp = nd.mp, e = nd.e, ku = nd.ku, kv = nd.kv;
@@ -230,83 +247,129 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
   } else {
     S = src_global(I, nd, node);
   }
-  if (col >= C.nrhs) return;
+  if (col0 >= C.nrhs) return;
   const T taul = lane < ku ? I.tq[nd.otq + lane] : T(0);
-  T x0, x1;
+  T x0[CPW], x1[CPW];
   if (nd.is_leaf) {
-    const T* b = C.B + nd.row0 + (int64_t)col * C.ldb;
-    x0 = r0 < mp ? b[r0] : T(0);
-    x1 = r1 < mp ? b[r1] : T(0);
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const bool cv = col0 + c < C.nrhs;
+      const T* b = C.B + nd.row0 + (int64_t)(cv ? col0 + c : 0) * C.ldb;
+      x0[c] = cv && r0 < mp ? b[r0] : T(0);
+      x1[c] = cv && r1 < mp ? b[r1] : T(0);
+    }
   } else {
-    gather_internal(I, nd, node, col, lane, S, x0, x1);
+    gather_internal<T, CPW>(I, nd, node, col0, C.nrhs, lane, S, x0, x1);
   }
   if (e > 0) {
     // b~ = Q^T rhs = H_0 ... H_{ku-1} rhs, H_{ku-1} applied first (lane j holds tau_j)
-#pragma unroll 8
+#pragma unroll 4
     for (int j = ku - 1; j >= 0; --j) {
       const T tau = bcast(taul, j);
       const int pr = e + j;
       const T* v = S.U + j * S.ldu;
       const T v0 = r0 < pr ? v[r0] : (r0 == pr ? T(1) : T(0));
       const T v1 = r1 < pr ? v[r1] : (r1 == pr ? T(1) : T(0));
-      const T w = wave_sum(v0 * x0 + v1 * x1) * tau;
-      x0 -= w * v0;
-      x1 -= w * v1;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const T w = wave_sum(v0 * x0[c] + v1 * x1[c]) * tau;
+        x0[c] -= w * v0;
+        x1[c] -= w * v1;
+      }
     }
     // y = L^{-1} b~_top; the same column sweep leaves b~_bot - D~21 y below
-#pragma unroll 16
+#pragma unroll 8
     for (int i = 0; i < e; ++i) {
       const T* Li = S.L + i * S.ldl;
       const T l0 = r0 > i && r0 < mp ? Li[r0] : T(0);
       const T l1 = r1 > i && r1 < mp ? Li[r1] : T(0);
-      const T yi = row_of(x0, x1, i) / Li[i];
-      if (r0 == i) x0 = yi;
-      if (r1 == i) x1 = yi;
-      x0 -= l0 * yi;
-      x1 -= l1 * yi;
+      const T dinv = T(1) / Li[i];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const T yi = row_of(x0[c], x1[c], i) * dinv;
+        if (r0 == i) x0[c] = yi;
+        if (r1 == i) x1[c] = yi;
+        x0[c] -= l0 * yi;
+        x1[c] -= l1 * yi;
+      }
     }
   }
-  const int64_t co = (int64_t)col * I.lds;
-  T* yo = I.wy + nd.oy + co;
-  T* cout = I.wc + nd.oc + co;
-  if (r0 < e) yo[r0] = x0; else if (r0 < mp) cout[r0 - e] = x0;
-  if (r1 < e) yo[r1] = x1; else if (r1 < mp) cout[r1 - e] = x1;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    if (col0 + c >= C.nrhs) break;
+    const int64_t co = (int64_t)(col0 + c) * I.lds;
+    T* yo = I.wy + nd.oy + co;
+    T* cout = I.wc + nd.oc + co;
+    if (r0 < e) yo[r0] = x0[c]; else if (r0 < mp) cout[r0 - e] = x0[c];
+    if (r1 < e) yo[r1] = x1[c]; else if (r1 < mp) cout[r1 - e] = x1[c];
+  }
   if (node == 0) return;
   // z = V^_top^T y (+ W^T [z_c1; z_c2])
-  T zc0 = 0, zc1 = 0;
+  T zc0[CPW], zc1[CPW];
   int kw = 0;
+  int kv1 = 0;
   if (!nd.is_leaf) {
     const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
-    const T* z1 = I.wz + n1.oz + co;
-    const T* z2 = I.wz + n2.oz + co;
+    kv1 = n1.kv;
     kw = n1.kv + n2.kv;
-    zc0 = r0 < n1.kv ? z1[r0] : (r0 < kw ? z2[r0 - n1.kv] : T(0));
-    zc1 = r1 < n1.kv ? z1[r1] : (r1 < kw ? z2[r1 - n1.kv] : T(0));
   }
-  T* zo = I.wz + nd.oz + co;
-  T part[64];
 #pragma unroll
-  for (int aa = 0; aa < 64; ++aa) {
-    T acc = T(0);
-    if (aa < kv) {
-      const T* Va = S.V + aa * S.ldv;
-      acc = (r0 < e ? Va[r0] * x0 : T(0)) + (r1 < e ? Va[r1] * x1 : T(0));
-      if (kw) acc += (r0 < kw ? S.W[r0 + aa * S.ldw] * zc0 : T(0)) +
-                     (r1 < kw ? S.W[r1 + aa * S.ldw] * zc1 : T(0));
+  for (int c = 0; c < CPW; ++c) {
+    zc0[c] = zc1[c] = T(0);
+    if (kw && col0 + c < C.nrhs) {
+      const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+      const int64_t co = (int64_t)(col0 + c) * I.lds;
+      const T* z1 = I.wz + n1.oz + co;
+      const T* z2 = I.wz + n2.oz + co;
+      zc0[c] = r0 < kv1 ? z1[r0] : (r0 < kw ? z2[r0 - kv1] : T(0));
+      zc1[c] = r1 < kv1 ? z1[r1] : (r1 < kw ? z2[r1 - kv1] : T(0));
     }
-    part[aa] = acc;
   }
-  const T z = wave_transpose_sum64(part);
-  if (lane < kv) zo[lane] = z;
+  if constexpr (CPW == 1) {
+    T* zo = I.wz + nd.oz + (int64_t)col0 * I.lds;
+    T part[64];
+#pragma unroll
+    for (int aa = 0; aa < 64; ++aa) {
+      T acc = T(0);
+      if (aa < kv) {
+        const T* Va = S.V + aa * S.ldv;
+        acc = (r0 < e ? Va[r0] * x0[0] : T(0)) + (r1 < e ? Va[r1] * x1[0] : T(0));
+        if (kw) acc += (r0 < kw ? S.W[r0 + aa * S.ldw] * zc0[0] : T(0)) +
+                       (r1 < kw ? S.W[r1 + aa * S.ldw] * zc1[0] : T(0));
+      }
+      part[aa] = acc;
+    }
+    const T z = wave_transpose_sum64(part);
+    if (lane < kv) zo[lane] = z;
+  } else {
+    // one wavefront reduction per (entry, column); results kept by lane aa
+    T zr[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) zr[c] = T(0);
+    for (int aa = 0; aa < kv; ++aa) {
+      const T* Va = S.V + aa * S.ldv;
+      const T va0 = r0 < e ? Va[r0] : T(0), va1 = r1 < e ? Va[r1] : T(0);
+      const T wa0 = kw && r0 < kw ? S.W[r0 + aa * S.ldw] : T(0);
+      const T wa1 = kw && r1 < kw ? S.W[r1 + aa * S.ldw] : T(0);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const T sz = wave_sum(va0 * x0[c] + va1 * x1[c] + wa0 * zc0[c] + wa1 * zc1[c]);
+        if (lane == aa) zr[c] = sz;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+      if (col0 + c < C.nrhs && lane < kv) I.wz[nd.oz + (int64_t)(col0 + c) * I.lds + lane] = zr[c];
+  }
 }
 
 // Root: rhs from the children, then the FP64 LU of the merged root block
 // (staged in LDS with its pivots), split into the children's x^.
-template <typename T, bool BATCH>
+template <typename T, bool BATCH, int CPW>
 __global__ __launch_bounds__(kSW * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
-  Inst<T> I; CallSV<T> C; int node, col;
-  if (!sv_resolve<BATCH, true>(a, I, C, node, col)) return;
+  Inst<T> I; CallSV<T> C; int node, col0;
+  if (!sv_resolve<BATCH, true, CPW>(a, I, C, node, col0)) return;
   const int lane = threadIdx.x & 63;
   const NodeInfo nd = I.nodes[node];
   const int mp = nd.mp;
@@ -319,101 +382,140 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
   NodeSrc<T> S = (nd.is_leaf || !(a.flags & 1)) ? src_global(I, nd, node)
                                                  : src_stage_fwd(I, nd, node, rest);
   __syncthreads();
-  if (col >= C.nrhs) return;
-  T t0, t1;
+  if (col0 >= C.nrhs) return;
+  T t0[CPW], t1[CPW];
   if (nd.is_leaf) {
-    const T* b = C.B + nd.row0 + (int64_t)col * C.ldb;
-    t0 = r0 < mp ? b[r0] : T(0);
-    t1 = r1 < mp ? b[r1] : T(0);
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const bool cv = col0 + c < C.nrhs;
+      const T* b = C.B + nd.row0 + (int64_t)(cv ? col0 + c : 0) * C.ldb;
+      t0[c] = cv && r0 < mp ? b[r0] : T(0);
+      t1[c] = cv && r1 < mp ? b[r1] : T(0);
+    }
   } else {
-    gather_internal(I, nd, node, col, lane, S, t0, t1);
+    gather_internal<T, CPW>(I, nd, node, col0, C.nrhs, lane, S, t0, t1);
   }
-  double x0 = (double)t0, x1 = (double)t1;
+  double x0[CPW], x1[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    x0[c] = (double)t0[c];
+    x1[c] = (double)t1[c];
+  }
   for (int j = 0; j < mp; ++j) {
     const int pj = piv[j];
-    const double vj = row_of(x0, x1, j), vp = row_of(x0, x1, pj);
-    if (r0 == j) x0 = vp;
-    if (r1 == j) x1 = vp;
-    if (r0 == pj) x0 = vj;
-    if (r1 == pj) x1 = vj;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const double vj = row_of(x0[c], x1[c], j), vp = row_of(x0[c], x1[c], pj);
+      if (r0 == j) x0[c] = vp;
+      if (r1 == j) x1[c] = vp;
+      if (r0 == pj) x0[c] = vj;
+      if (r1 == pj) x1[c] = vj;
+    }
   }
   for (int i = 0; i < mp; ++i) {
     const double* Li = LU + i * mp;
-    const double xi = row_of(x0, x1, i);
-    if (r0 > i && r0 < mp) x0 -= Li[r0] * xi;
-    if (r1 > i && r1 < mp) x1 -= Li[r1] * xi;
+    const double l0 = r0 > i && r0 < mp ? Li[r0] : 0.0;
+    const double l1 = r1 > i && r1 < mp ? Li[r1] : 0.0;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const double xi = row_of(x0[c], x1[c], i);
+      x0[c] -= l0 * xi;
+      x1[c] -= l1 * xi;
+    }
   }
   for (int i = mp - 1; i >= 0; --i) {
     const double* Ui = LU + i * mp;
-    const double xi = row_of(x0, x1, i) / Ui[i];
-    if (r0 == i) x0 = xi;
-    if (r1 == i) x1 = xi;
-    if (r0 < i) x0 -= Ui[r0] * xi;
-    if (r1 < i) x1 -= Ui[r1] * xi;
+    const double u0 = r0 < i ? Ui[r0] : 0.0, u1 = r1 < i ? Ui[r1] : 0.0;
+    const double dinv = 1.0 / Ui[i];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const double xi = row_of(x0[c], x1[c], i) * dinv;
+      if (r0 == i) x0[c] = xi;
+      if (r1 == i) x1[c] = xi;
+      x0[c] -= u0 * xi;
+      x1[c] -= u1 * xi;
+    }
   }
-  if (nd.is_leaf) {
-    T* out = C.B + nd.row0 + (int64_t)col * C.ldb;
-    if (r0 < mp) out[r0] = (T)x0;
-    if (r1 < mp) out[r1] = (T)x1;
-    return;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    if (col0 + c >= C.nrhs) break;
+    if (nd.is_leaf) {
+      T* out = C.B + nd.row0 + (int64_t)(col0 + c) * C.ldb;
+      if (r0 < mp) out[r0] = (T)x0[c];
+      if (r1 < mp) out[r1] = (T)x1[c];
+      continue;
+    }
+    const NodeInfo n1 = I.nodes[1], n2 = I.nodes[2];
+    const int64_t co = (int64_t)(col0 + c) * I.lds;
+    T* xa = I.wx + n1.ox + co;
+    T* xb = I.wx + n2.ox + co;
+    const int k1 = n1.kept;
+    if (r0 < k1) xa[r0] = (T)x0[c]; else if (r0 < mp) xb[r0 - k1] = (T)x0[c];
+    if (r1 < k1) xa[r1] = (T)x1[c]; else if (r1 < mp) xb[r1 - k1] = (T)x1[c];
   }
-  const NodeInfo n1 = I.nodes[1], n2 = I.nodes[2];
-  const int64_t co = (int64_t)col * I.lds;
-  T* xa = I.wx + n1.ox + co;
-  T* xb = I.wx + n2.ox + co;
-  const int k1 = n1.kept;
-  if (r0 < k1) xa[r0] = (T)x0; else if (r0 < mp) xb[r0 - k1] = (T)x0;
-  if (r1 < k1) xa[r1] = (T)x1; else if (r1 < mp) xb[r1 - k1] = (T)x1;
 }
 
-template <typename T, bool BATCH, bool STAGED>
+template <typename T, bool BATCH, bool STAGED, int CPW>
 __global__ __launch_bounds__(kSW * 64) void k_sv_bwd_w(KArgs<T, CallSV<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
-  Inst<T> I; CallSV<T> C; int node, col;
-  if (!sv_resolve<BATCH, STAGED>(a, I, C, node, col)) return;
+  Inst<T> I; CallSV<T> C; int node, col0;
+  if (!sv_resolve<BATCH, STAGED, CPW>(a, I, C, node, col0)) return;
   const int lane = threadIdx.x & 63;
   const NodeInfo nd = I.nodes[node];
   const int mp = nd.mp, e = nd.e;
   const int r0 = lane, r1 = lane + 64;
   const T* Z = I.FZ + nd.oFZ;
-  int ldz = mp;
+  const int ldz = mp;
   if (STAGED) {
     T* sz = reinterpret_cast<T*>(smem_raw);
     stage_block(sz, mp, e, [&](int i, int j) { return Z[i + j * mp]; });
     __syncthreads();
     Z = sz;
   }
-  if (col >= C.nrhs) return;
-  const int64_t co = (int64_t)col * I.lds;
-  const T* yi = I.wy + nd.oy + co;
-  const T* xi = I.wx + nd.ox + co;
-  T x0 = r0 < e ? yi[r0] : (r0 < mp ? xi[r0 - e] : T(0));
-  T x1 = r1 < e ? yi[r1] : (r1 < mp ? xi[r1 - e] : T(0));
+  if (col0 >= C.nrhs) return;
+  T x0[CPW], x1[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const bool cv = col0 + c < C.nrhs;
+    const int64_t co = (int64_t)(cv ? col0 + c : 0) * I.lds;
+    const T* yi = I.wy + nd.oy + co;
+    const T* xi = I.wx + nd.ox + co;
+    x0[c] = !cv ? T(0) : (r0 < e ? yi[r0] : (r0 < mp ? xi[r0 - e] : T(0)));
+    x1[c] = !cv ? T(0) : (r1 < e ? yi[r1] : (r1 < mp ? xi[r1 - e] : T(0)));
+  }
   // Z [y; x^] = H_0 ... H_{e-1} [y; x^], H_{e-1} applied first
   const T taul0 = r0 < e ? I.tz[nd.otz + r0] : T(0);
   const T taul1 = r1 < e ? I.tz[nd.otz + r1] : T(0);
-#pragma unroll 8
+#pragma unroll 4
   for (int i = e - 1; i >= 0; --i) {
     const T tau = row_of(taul0, taul1, i);
     const T* v = Z + i * ldz;
     const T v0 = r0 < mp ? v[r0] : T(0);
     const T v1 = r1 < mp ? v[r1] : T(0);
-    const T w = wave_sum(v0 * x0 + v1 * x1) * tau;
-    x0 -= w * v0;
-    x1 -= w * v1;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const T w = wave_sum(v0 * x0[c] + v1 * x1[c]) * tau;
+      x0[c] -= w * v0;
+      x1[c] -= w * v1;
+    }
   }
-  if (nd.is_leaf) {
-    T* out = C.B + nd.row0 + (int64_t)col * C.ldb;
-    if (r0 < mp) out[r0] = x0;
-    if (r1 < mp) out[r1] = x1;
-    return;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    if (col0 + c >= C.nrhs) break;
+    if (nd.is_leaf) {
+      T* out = C.B + nd.row0 + (int64_t)(col0 + c) * C.ldb;
+      if (r0 < mp) out[r0] = x0[c];
+      if (r1 < mp) out[r1] = x1[c];
+      continue;
+    }
+    const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+    const int64_t co = (int64_t)(col0 + c) * I.lds;
+    T* xa = I.wx + n1.ox + co;
+    T* xb = I.wx + n2.ox + co;
+    const int k1 = n1.kept;
+    if (r0 < k1) xa[r0] = x0[c]; else if (r0 < mp) xb[r0 - k1] = x0[c];
+    if (r1 < k1) xa[r1] = x1[c]; else if (r1 < mp) xb[r1 - k1] = x1[c];
   }
-  const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
-  T* xa = I.wx + n1.ox + co;
-  T* xb = I.wx + n2.ox + co;
-  const int k1 = n1.kept;
-  if (r0 < k1) xa[r0] = x0; else if (r0 < mp) xb[r0 - k1] = x0;
-  if (r1 < k1) xa[r1] = x1; else if (r1 < mp) xb[r1 - k1] = x1;
 }
 
 template <typename T>
@@ -432,26 +534,38 @@ void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int 
                                "sv_root_f32"};
   const int ni = step == UlvStep::Root ? 4 : (step == UlvStep::Fwd ? 0 : 2) + (leafy ? 1 : 0);
   TimedLaunch tl((sizeof(T) == 8 ? nm64 : nm32)[ni], s);
-  dim3 gridw((nitems + kSW - 1) / kSW, ncols), blockw(kSW * 64);
-  dim3 grid1(nitems, (ncols + kSW - 1) / kSW), block1(kSW * 64);
-#define HSS_SL(K, ST, G, B)                                                       \
-  if (batch) hipLaunchKernelGGL((K<T, true, ST>), G, B, sm, s, b);                \
-  else hipLaunchKernelGGL((K<T, false, ST>), G, B, sm, s, b);
+  // columns per wavefront: 4 when there are enough columns to share the factor reads
+  const int cpw = ncols >= 4 ? 4 : 1;
+  const int cgroups = (ncols + cpw - 1) / cpw;
+  dim3 gridw((nitems + kSW - 1) / kSW, cgroups), blockw(kSW * 64);
+  dim3 grid1(nitems, (cgroups + kSW - 1) / kSW), block1(kSW * 64);
+#define HSS_SL(K, ST, CP, G, B)                                                   \
+  if (batch) hipLaunchKernelGGL((K<T, true, ST, CP>), G, B, sm, s, b);            \
+  else hipLaunchKernelGGL((K<T, false, ST, CP>), G, B, sm, s, b);
+#define HSS_SL2(K, ST, G, B)                 \
+  if (cpw == 4) { HSS_SL(K, ST, 4, G, B) }   \
+  else { HSS_SL(K, ST, 1, G, B) }
   switch (step) {
     case UlvStep::Fwd:
-      if (staged) { HSS_SL(k_sv_fwd_w, true, grid1, block1) }
-      else { HSS_SL(k_sv_fwd_w, false, gridw, blockw) }
+      if (staged) { HSS_SL2(k_sv_fwd_w, true, grid1, block1) }
+      else { HSS_SL2(k_sv_fwd_w, false, gridw, blockw) }
       break;
     case UlvStep::Bwd:
-      if (staged) { HSS_SL(k_sv_bwd_w, true, grid1, block1) }
-      else { HSS_SL(k_sv_bwd_w, false, gridw, blockw) }
+      if (staged) { HSS_SL2(k_sv_bwd_w, true, grid1, block1) }
+      else { HSS_SL2(k_sv_bwd_w, false, gridw, blockw) }
       break;
     case UlvStep::Root:
-      if (batch) hipLaunchKernelGGL((k_sv_root_w<T, true>), grid1, block1, sm, s, b);
-      else hipLaunchKernelGGL((k_sv_root_w<T, false>), grid1, block1, sm, s, b);
+      if (cpw == 4) {
+        if (batch) hipLaunchKernelGGL((k_sv_root_w<T, true, 4>), grid1, block1, sm, s, b);
+        else hipLaunchKernelGGL((k_sv_root_w<T, false, 4>), grid1, block1, sm, s, b);
+      } else {
+        if (batch) hipLaunchKernelGGL((k_sv_root_w<T, true, 1>), grid1, block1, sm, s, b);
+        else hipLaunchKernelGGL((k_sv_root_w<T, false, 1>), grid1, block1, sm, s, b);
+      }
       break;
     default: break;
   }
+#undef HSS_SL2
 #undef HSS_SL
 }
 

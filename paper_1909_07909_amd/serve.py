@@ -141,6 +141,7 @@ class Server:
         self.rounds = 0
         self.round_sizes = []
         self.errors = []
+        self.phase_s = {"stage_in": 0.0, "solve": 0.0, "stage_out": 0.0}
 
     # -- producer side ---------------------------------------------------------
     def submit(self, req: Request):
@@ -240,6 +241,7 @@ class Server:
             by_tol.setdefault(t, []).append((m, reqs))
         with torch.cuda.stream(stream):
             for tol, items in by_tol.items():
+                t0 = time.perf_counter()
                 mats, blocks, splits = [], [], []
                 for m, reqs in items:
                     n = self.n[m]
@@ -249,8 +251,10 @@ class Server:
                     mats.append(self.mats[m])
                     blocks.append(dev)
                     splits.append(reqs)
+                t1 = time.perf_counter()
                 infos = hss.batch_solve(mats, blocks, prec=hss.F32, tol=tol,
                                         max_refine=self.max_refine, stream=stream)
+                t2 = time.perf_counter()
                 for dev, reqs, info in zip(blocks, splits, infos):
                     X = dev.t().contiguous().cpu().numpy().T
                     now = time.perf_counter()
@@ -262,6 +266,11 @@ class Server:
                         r.status = info["status"]
                         r.t_done = now
                         c += r.nrhs
+                t3 = time.perf_counter()
+                with self.cv:
+                    self.phase_s["stage_in"] += t1 - t0
+                    self.phase_s["solve"] += t2 - t1
+                    self.phase_s["stage_out"] += t3 - t2
 
     def start(self):
         self.threads = [threading.Thread(target=self._worker, daemon=True)
