@@ -59,6 +59,38 @@ __device__ __forceinline__ T wave_sum(T v) {
   return lane_read(v, 63);
 }
 
+// *p if ok, else 0.  p must be a valid address either way (callers clamp the
+// index): the load is issued unconditionally and the mask applied to its
+// result, so that a sequence of such loads is in flight together instead of
+// being turned into one branch and one memory round trip per element.
+template <typename T>
+__device__ __forceinline__ T ld_or0(const T* p, bool ok) {
+  const T v = *p;
+  return ok ? v : T(0);
+}
+
+// store(i, j, f(i, j)) for i < M, j < N by all threads of the work-group.  f
+// must be a plain read that is valid for every (i, j) in range: each thread
+// issues the reads of U elements before it stores any, so that they are in
+// flight together.
+template <int U, typename T, typename F, typename S>
+__device__ __forceinline__ void wg_stage(int M, int N, F f, S store) {
+  const int total = M * N, nt = blockDim.x;
+  for (int base = 0; base < total; base += U * nt) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int o = min(base + (int)threadIdx.x + u * nt, total - 1);
+      v[u] = f(o % M, o / M);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int o = base + (int)threadIdx.x + u * nt;
+      if (o < total) store(o % M, o / M, v[u]);
+    }
+  }
+}
+
 // Resolve (instance, call, node) of this work-group.
 template <bool BATCH, typename T, typename Call>
 __device__ __forceinline__ void resolve(const KArgs<T, Call>& a, Inst<T>& I, Call& C, int& node) {

@@ -53,6 +53,7 @@ struct hss_handle {
   Work<double> w64;
   Work<float> w32;
   int32_t* d_status = nullptr;
+  uint32_t* d_cnt = nullptr;   // arrival counters of the fused product, one per node
   // refinement / norm work
   double *b0 = nullptr, *res = nullptr, *d64 = nullptr;
   float* r32 = nullptr;
@@ -199,6 +200,7 @@ Inst<T> make_inst(hss_handle* h) {
   I.xh = w.xh; I.yh = w.yh; I.ldm = h->plan.ldm;
   I.wc = w.wc; I.wz = w.wz; I.wy = w.wy; I.wx = w.wx; I.lds = h->plan.lds;
   I.status = h->d_status;
+  I.cnt = h->d_cnt;
   I.p = h->plan.p;
   I.nnodes = h->plan.nnodes;
   return I;
@@ -216,6 +218,20 @@ void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T*
   a.inst = make_inst<T>(h);
   a.call = CallMM<T>{X, Y, ldx, ldy, (int32_t)nrhs, op};
   const int p = h->plan.p;
+  if (op == HSS_OP_N) {
+    // fused: leaves (with the climb), subtree walks, leaf outputs
+    const int mku = h->plan.leaf_max_ku, mk = h->plan.max_k;
+    if (p > 0) {
+      a.node0 = level_first(p);
+      launch_mmf<T>(MMFStep::Up, a, 1 << p, (int)nrhs, mku, mk, s);
+      const int ls = std::max(p - mmf_down_height(), 0);
+      a.node0 = level_first(ls);
+      launch_mmf<T>(MMFStep::Down, a, 1 << ls, (int)nrhs, mku, mk, s);
+    }
+    a.node0 = level_first(p);
+    launch_mmf<T>(MMFStep::Leaf, a, 1 << p, (int)nrhs, mku, mk, s);
+    return;
+  }
   const int yt = (int)((nrhs + kRT - 1) / kRT);
   const int rows = kMaxBlock;
   if (p == 0) {
@@ -474,6 +490,36 @@ hss_status batch_matmul_impl(BatchScratch& BS, hss_handle* const* hs, int count,
   StepList L;
   auto none = [](const Plan&, int) -> int64_t { return 0; };
   auto lvl = [](const Plan& P, int t) { return P.nodes[t].level; };
+  if (op == HSS_OP_N) {
+    const int dh = mmf_down_height();
+    L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
+               none);                                                    // up: leaves, p > 0
+    L.add_step(hs, count, [&](int, const Plan& P, int t) {
+      return P.p > 0 && lvl(P, t) == std::max(P.p - dh, 0); }, none);   // down: subtree roots
+    L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.nodes[t].is_leaf != 0; },
+               none);                                                    // leaf outputs
+    Packer pk;
+    const size_t oi = pk.add(insts), oc = pk.add(calls), ot = pk.add(L.tasks);
+    void* d = nullptr;
+    hss_status st = scratch_upload(BS, pk.buf, s, &d);
+    if (st) return st;
+    KArgs<T, CallMM<T>> a{};
+    a.insts = reinterpret_cast<const Inst<T>*>((char*)d + oi);
+    a.calls = reinterpret_cast<const CallMM<T>*>((char*)d + oc);
+    const MMFStep steps[3] = {MMFStep::Up, MMFStep::Down, MMFStep::Leaf};
+    int mku = 0, mk = 0;
+    for (int j = 0; j < count; ++j) {
+      mku = std::max(mku, hs[j]->plan.leaf_max_ku);
+      mk = std::max(mk, hs[j]->plan.max_k);
+    }
+    for (int q = 0; q < 3; ++q) {
+      const auto& r = L.ranges[q];
+      a.tasks = reinterpret_cast<const int2*>((char*)d + ot) + r.off;
+      a.ntasks = r.cnt;
+      launch_mmf<T>(steps[q], a, r.cnt, (int)maxr, mku, mk, s);
+    }
+    return last_launch_status();
+  }
   L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
              none);                                                      // 0: leaf up
   for (int st = 1; st <= pmax - 1; ++st)                                 // 1..: up
@@ -872,7 +918,8 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
   };
   h->d_nodes = dalloc<NodeInfo>(h, P.nnodes);
   h->d_status = dalloc<int32_t>(h, 4);
-  if (!h->d_nodes || !h->d_status) return fail(HSS_ENOMEM);
+  h->d_cnt = dalloc<uint32_t>(h, (P.nnodes + 2) & ~1);
+  if (!h->d_nodes || !h->d_status || !h->d_cnt) return fail(HSS_ENOMEM);
   if (hipMemcpyAsync(h->d_nodes, P.nodes.data(), sizeof(NodeInfo) * P.nnodes,
                      hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(HSS_EHIP);
@@ -888,6 +935,7 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
     }
   }
   launch_fill(reinterpret_cast<double*>(h->d_status), 0.0, 2, s);
+  launch_fill(reinterpret_cast<double*>(h->d_cnt), 0.0, (P.nnodes + 2) / 2, s);
   if ((st = last_launch_status())) return fail(st);
   h->pinned = nullptr;
   if (hipStreamSynchronize(s) != hipSuccess) return fail(HSS_EHIP);

@@ -61,6 +61,7 @@ struct Inst {
   T *wc, *wz, *wy, *wx;   // solve work, leading dimension lds
   int64_t lds;
   int32_t* status;  // device status word (HSS_ESINGULAR ...)
+  uint32_t* cnt;    // per-node arrival counters of the fused product (even between calls)
   int32_t p;
   int32_t nnodes;
 };

@@ -57,12 +57,13 @@ __global__ __launch_bounds__(kFNT) void k_ulv_factor_reg(KArgs<T, CallSV<T>> a) 
   const bool isD = c < mp;
   const bool isU = c >= mp && c < mp + ku;
   {
+    // clamped addresses, unconditional loads (all in flight together), masks after
     const T* src = isD ? Dsrc + (int64_t)c * mp : (isU ? Usrc + (int64_t)(c - mp) * mp : Dsrc);
-    const bool any = isD || isU;
+    const bool any = isD | isU;
 #pragma unroll
     for (int j = 0; j < COLS; ++j) {
       const int r = base + j;
-      reg[j] = (any && r < mp) ? src[r] : T(0);
+      reg[j] = ld_or0(src + min(r, mp - 1), any & (r < mp));
     }
   }
   if (e > 0) {
@@ -130,14 +131,15 @@ __global__ __launch_bounds__(kFNT) void k_ulv_factor_reg(KArgs<T, CallSV<T>> a) 
 #pragma unroll
     for (int j = 0; j < COLS; ++j) {
       const int cc = base + j;
-      reg[j] = cc < mp ? Ms[r + cc * ldm] : T(0);
+      const T v = Ms[r + min(cc, mp - 1) * ldm];
+      reg[j] = cc < mp ? v : T(0);
     }
   } else {
     const T* src = Vsrc + (int64_t)(isV ? r - mp : 0) * mp;
 #pragma unroll
     for (int j = 0; j < COLS; ++j) {
       const int cc = base + j;
-      reg[j] = (isV && cc < mp) ? src[cc] : T(0);
+      reg[j] = ld_or0(src + min(cc, mp - 1), isV & (cc < mp));
     }
   }
   __syncthreads();   // Ms now parks the finished rows 0..e-1

@@ -1,0 +1,606 @@
+// HSS matrix x block product Y = A X (Sec. 4.1) in three launches:
+//
+//   up    one work-group per leaf: x^_i = V_i^T X_i; the work-group that
+//         completes the second child of a node goes on to that node
+//         (arrival counted by an atomic per node): core blocks
+//         y^_c1 = B12_t x^_c2, y^_c2 = B21_t x^_c1, and, below the root,
+//         x^_t = W_t^T [x^_c1; x^_c2]; so the whole upward pass and all
+//         core blocks are one launch;
+//   down  one work-group per node s at level max(p-3, 0): walks the path
+//         from the root to s and then the levels of its subtree,
+//         y^_c = y^_c(core) + R_t[c rows] y^_t, and stores y^ of its leaves;
+//   leaf  one work-group per (leaf, chunk of right-hand sides):
+//         Y_i = D_i X_i + U_i y^_i, D_i and U_i streamed once into registers.
+//
+// The per-level launches of kernels_mm.hip remain for A^T X.
+#include <hip/hip_runtime.h>
+
+#include "device_util.hpp"
+#include "kernels.hpp"
+#include "timing.hpp"
+
+namespace hss {
+
+constexpr int kDC = 8;       // right-hand-side columns per down work-group
+constexpr int kUT = 256;     // threads of the up kernel
+constexpr int kDT = 512;     // threads of the down kernel
+constexpr int kLT = 512;     // threads of the leaf kernel
+constexpr int kDnH = 3;      // subtree height of a down work-group
+constexpr int kXP = kMaxBlock + 8;   // padded LDS column of an X chunk
+
+// LDS row of element i of an X chunk: a gap of two after every 32 rows so that
+// the four quarter-wavefronts of the leaf kernel read different banks.
+__device__ __forceinline__ int xrow(int i) { return i + ((i >> 5) << 1); }
+
+// Raw buffer access: base and size in a resource descriptor (SGPRs), a
+// per-lane byte offset and a uniform byte offset; reads at or beyond the size
+// return zero.
+// Every caller passes wavefront-uniform bases, sizes and uniform offsets; they
+// are moved to scalar registers explicitly so that the compiler does not fall
+// back to a per-lane loop over descriptors.
+__device__ __forceinline__ uint32_t uni(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  const uint64_t b = reinterpret_cast<uint64_t>(base);
+  const uint64_t ub = ((uint64_t)uni((uint32_t)(b >> 32)) << 32) | uni((uint32_t)b);
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(ub), 0, (int)uni(bytes),
+                                           0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                   uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, uni(soff), 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                 uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, uni(soff), 0));
+}
+
+// x^ values cross work-groups inside the up kernel: agent-scope atomic
+// accesses, which are coherent across the XCDs' L2 caches without cache-wide
+// write-back or invalidation.
+template <typename T>
+__device__ __forceinline__ void xh_put(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T xh_get(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// dst[i + c*ldd] = src[i + c*lds] for i < rows (zero for rows <= i < ldd),
+// c < nc <= MC, by all threads of the work-group: every load is issued (from
+// a clamped, valid address) before the first LDS store.
+template <int MC, typename T>
+__device__ __forceinline__ void stage_cols(T* dst, int ldd, int rows, int nc, const T* src,
+                                           int64_t lds) {
+  const int total = ldd * nc;
+  constexpr int U = (kMaxBlock * MC + 255) / 256;
+  const int nt = blockDim.x;
+  T v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int o = threadIdx.x + u * nt;
+    const int i = o % ldd, c = min(o / ldd, nc - 1);
+    const T x = src[min(i, rows - 1) + (int64_t)c * lds];
+    v[u] = (i < rows) ? x : T(0);
+    if (u * nt >= total) break;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int o = threadIdx.x + u * nt;
+    if (o < total) dst[o] = v[u];
+  }
+}
+
+// out(i, c, sum_l A(i, l) * in[l + c*ldi]) for i < M, c < nc, by all threads of
+// the work-group; A(i, l) = A[i + l*lda] (or A[l + i*lda] when TA).  One thread
+// per output; its coefficient loads are issued 64 at a time from clamped
+// (always valid) addresses and masked afterwards, so they are all in flight
+// together instead of one round trip each.
+template <typename T, bool TA, typename Out>
+__device__ __forceinline__ void wg_small_gemm(int M, int K, int nc, const T* __restrict__ A,
+                                              int lda, const T* in, int ldi, Out out) {
+  constexpr int KB = 32;
+  const uint32_t span = TA ? (uint32_t)((M - 1) * lda + K) : (uint32_t)((K - 1) * lda + M);
+  const auto Ar = buf_rsrc(A, span * (uint32_t)sizeof(T));
+  const uint32_t ls = (uint32_t)(TA ? 1 : lda) * (uint32_t)sizeof(T);   // stride of l
+  for (int o = threadIdx.x; o < M * nc; o += blockDim.x) {
+    const int i = o % M, c = o / M;
+    const uint32_t vo = (uint32_t)(TA ? i * lda : i) * (uint32_t)sizeof(T);
+    T s = T(0);
+    for (int l0 = 0; l0 < K; l0 += KB) {
+      T av[KB];
+#pragma unroll
+      for (int l = 0; l < KB; ++l) av[l] = buf_load<T>(Ar, vo, (uint32_t)(l0 + l) * ls);
+#pragma unroll
+      for (int l = 0; l < KB; ++l) {
+        const int lc = min(l0 + l, K - 1);
+        const T t = av[l] * in[lc + c * ldi];
+        s += (l0 + l < K) ? t : T(0);
+      }
+    }
+    out(i, c, s);
+  }
+}
+
+// NV: V columns per wavefront of a leaf (>= kv / 4); KQ: coefficients per
+// lane of a climb product (>= every rank; a W^T wavefront takes at most KQ/2
+// outputs, the children's ranks kk <= 128 in two halves of 64 lanes).
+template <typename T, bool BATCH, int MC, int NV, int KQ>
+__global__ __launch_bounds__(kUT) void k_mmf_up(KArgs<T, CallMM<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  __shared__ unsigned s_arrive;
+  Inst<T> I; CallMM<T> C; int node;
+  resolve<BATCH>(a, I, C, node);
+  const int ncw = min(MC, C.nrhs);
+  T* xs = reinterpret_cast<T*>(smem_raw);   // kMaxBlock x ncw: X chunk, then children's x^
+  T* os = xs + kMaxBlock * ncw;             // kMaxRank x ncw: x^ being formed
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nrhs = C.nrhs;
+  const int64_t ldm = I.ldm;
+  {
+    const NodeInfo nd = I.nodes[node];
+    const int m = nd.m, kv = nd.kv;
+    const T* V = I.V + nd.oV;
+    const int r0 = lane, r1 = lane + 64;
+    // V columns w, w+4, ... of this wavefront (rows lane, lane+64), all loads
+    // issued before any is used
+    T v0[NV], v1[NV];   // NV >= kv / 4; columns >= kv read as zero
+    const auto Vr = buf_rsrc(V, (uint32_t)(m * kv * (int)sizeof(T)));
+    const uint32_t cs = (uint32_t)(m * (int)sizeof(T));
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const uint32_t so = (uint32_t)(w + 4 * u) * cs;
+      const T a0 = buf_load<T>(Vr, (uint32_t)(min(r0, m - 1) * (int)sizeof(T)), so);
+      const T a1 = buf_load<T>(Vr, (uint32_t)(min(r1, m - 1) * (int)sizeof(T)), so);
+      v0[u] = (r0 < m) ? a0 : T(0);
+      v1[u] = (r1 < m) ? a1 : T(0);
+    }
+    for (int c0 = 0; c0 < nrhs; c0 += MC) {
+      const int nc = min(MC, nrhs - c0);
+      stage_cols<MC>(xs, kMaxBlock, m, nc, C.X + nd.row0 + (int64_t)c0 * C.ldx, C.ldx);
+      __syncthreads();
+      // x^ = V^T X: wavefront w forms columns w, w+4, ... of V^T X
+#pragma unroll
+      for (int u = 0; u < NV; ++u) {
+        const int col = w + 4 * u;
+        if (col < kv)
+          for (int c = 0; c < nc; ++c) {
+            const T s = wave_sum(v0[u] * xs[r0 + c * kMaxBlock] + v1[u] * xs[r1 + c * kMaxBlock]);
+            if (lane == 0) os[col + c * kMaxRank] = s;
+          }
+      }
+      __syncthreads();
+      if (w == 0)
+        for (int o = lane; o < kv * nc; o += 64)
+          xh_put(I.xh + nd.oxh + o % kv + (int64_t)(c0 + o / kv) * ldm,
+                 os[o % kv + (o / kv) * kMaxRank]);
+      __syncthreads();
+    }
+  }
+  // Climb: the second arrival at a node carries on with it.  Every x^ is
+  // written with agent-coherent stores and read with agent-coherent loads;
+  // the writers wait for their stores to complete before the barrier that
+  // precedes the arrival count, and the reads of the children's x^ are
+  // issued only after the count has been seen (through the barrier).
+  int t = node;
+  while (t > 0) {
+    const int par = (t - 1) >> 1;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) s_arrive = atomicAdd(I.cnt + par, 1u);
+    __syncthreads();
+    const bool second = (s_arrive & 1u) != 0;
+    __syncthreads();
+    if (!second) return;
+    t = par;
+    const NodeInfo nt = I.nodes[t];
+    const NodeInfo n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
+    const int kv1 = n1.kv, kv2 = n2.kv, kk = kv1 + kv2;
+    // one product per wavefront, coefficients loaded straight into registers
+    // (all loads of a wavefront issued together with the children's x^):
+    //   wavefront 0: y^_c1 = B12 x^_c2   (lane = row, loop over the columns)
+    //   wavefront 1: y^_c2 = B21 x^_c1
+    //   wavefronts 2, 3: x^_t = W^T [x^_c1; x^_c2] below the root, half of
+    //   the outputs each (lanes over the inner index, wavefront sums)
+    const bool bw = w < 2;
+    const T* Bm = w == 0 ? I.B12 + nt.oB12 : I.B21 + nt.oB21;
+    const int bM = w == 0 ? n1.ku : n2.ku, bK = w == 0 ? kv2 : kv1, bx = w == 0 ? kv1 : 0;
+    T* bout = I.yh + (w == 0 ? n1.oyh : n2.oyh);
+    const int kvt = (t > 0 && kk > 0) ? nt.kv : 0;
+    const int half = (kvt + 1) >> 1;
+    const int i0 = (w - 2) * half, ni = bw ? 0 : min(half, kvt - i0);
+    const T* Wt = I.W + (t > 0 ? nt.oW : 0);
+    T cf[KQ];
+    // (clamped addresses, loads unconditional, masks applied afterwards)
+    if (bw && bM > 0 && bK > 0) {
+      const int rr = min(lane, bM - 1);
+      const bool lr = lane < bM;
+#pragma unroll
+      for (int k = 0; k < KQ; ++k) cf[k] = ld_or0(Bm + rr + (int64_t)min(k, bK - 1) * bM, lr & (k < bK));
+    } else if (!bw && ni > 0) {
+      // lane l: W[l + i*kk] (in cf[q]) and W[l + 64 + i*kk] (in cf[KQ/2 + q])
+      // for the ni <= KQ/2 outputs i0 .. i0+ni-1.  Only below the root: the
+      // root has no W block.
+      const int la = min(lane, kk - 1), lb = min(lane + 64, kk - 1);
+      const bool ka = lane < kk, kb = lane + 64 < kk;
+#pragma unroll
+      for (int q = 0; q < KQ / 2; ++q) {
+        const T* wi = Wt + (int64_t)(i0 + min(q, ni - 1)) * kk;
+        cf[q] = ld_or0(wi + la, ka & (q < ni));
+        cf[KQ / 2 + q] = ld_or0(wi + lb, kb & (q < ni));
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) cf[q] = T(0);
+    }
+    for (int c0 = 0; c0 < nrhs; c0 += MC) {
+      const int nc = min(MC, nrhs - c0);
+      if (kk > 0) {
+        constexpr int UX = (2 * kMaxRank * MC + kUT - 1) / kUT;
+        T xv[UX];
+#pragma unroll
+        for (int u = 0; u < UX; ++u) {
+          const int o = min(tid + u * kUT, kk * nc - 1);
+          const int i = o % kk, c = o / kk;
+          const int64_t co = (int64_t)(c0 + c) * ldm;
+          xv[u] = xh_get(I.xh + (i < kv1 ? n1.oxh + i : n2.oxh + i - kv1) + co);
+        }
+#pragma unroll
+        for (int u = 0; u < UX; ++u) {
+          const int o = tid + u * kUT;
+          if (o < kk * nc) xs[o % kk + (o / kk) * kMaxBlock] = xv[u];
+        }
+      }
+      __syncthreads();
+      if (bw) {
+        for (int c = 0; c < nc; ++c) {
+          const T* x = xs + bx + c * kMaxBlock;
+          T acc = T(0);
+#pragma unroll
+          for (int k = 0; k < KQ; ++k) acc += cf[k] * x[min(k, max(bK - 1, 0))];
+          if (lane < bM) bout[lane + (int64_t)(c0 + c) * ldm] = acc;
+        }
+      } else if (ni > 0) {
+        for (int c = 0; c < nc; ++c) {
+          const T xa = xs[min(lane, kk - 1) + c * kMaxBlock];
+          const T xb = xs[min(lane + 64, kk - 1) + c * kMaxBlock];
+#pragma unroll
+          for (int q = 0; q < KQ / 2; ++q) {
+            if (q < ni) {
+              const T sum = wave_sum(cf[q] * xa + cf[KQ / 2 + q] * xb);
+              if (lane == 0) os[i0 + q + c * kMaxRank] = sum;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (t > 0 && w == 0)
+        for (int o = lane; o < nt.kv * nc; o += 64)
+          xh_put(I.xh + nt.oxh + o % nt.kv + (int64_t)(c0 + o / nt.kv) * ldm,
+                 os[o % nt.kv + (o / nt.kv) * kMaxRank]);
+      __syncthreads();
+    }
+  }
+}
+
+// Down work-group for subtree root s at level ls: levels 1 .. p of the path
+// from the root to s and then of the subtree of s.  Level 1 starts from the
+// core values alone; at a deeper level every (node c, row i) slot computes
+//   y^_c[i, :] = y^_c(core)[i, :] + R_t[row of c's block + i, :] y^_t
+// with t the parent.  Slots are numbered level by level (KR slots per node)
+// and dealt to the threads round-robin; the R rows and core values of the
+// first NR rounds are loaded before any level is computed, so that the walk
+// costs one memory round trip plus one barrier per level.
+struct DownMap {
+  int ls, p, s;
+  // node of slot-level d (d >= 1) and position j (0 .. cnt(d)-1)
+  __device__ int cnt(int d) const { return d <= ls ? 1 : 1 << (d - ls); }
+  __device__ int node(int d, int j) const {
+    return d <= ls ? ((s + 1) >> (ls - d)) - 1 : ((s + 1) << (d - ls)) - 1 + j;
+  }
+};
+
+template <typename T, int KR>
+struct DownSlot {
+  int d = 0, j = 0, i = 0, ku = 0;   // level (0: none), position, row, rank of the node
+  T r[KR];
+  T yc[kDC];
+};
+
+// level of slot g (0: past the last slot)
+template <int KR>
+__device__ __forceinline__ int down_slot_level(const DownMap& mp, int g) {
+  int base = 0;
+  for (int d = 2; d <= mp.p; ++d) {
+    base += mp.cnt(d) * KR;
+    if (g < base) return d;
+  }
+  return 0;
+}
+
+template <typename T, int KR>
+__device__ __forceinline__ void down_slot_load(const Inst<T>& I, const DownMap& mp, int g,
+                                               int c0, int nc, DownSlot<T, KR>& sl) {
+  sl.d = 0;
+  int d = 2, base = 0;
+  for (; d <= mp.p; ++d) {
+    const int n = mp.cnt(d) * KR;
+    if (g < base + n) break;
+    base += n;
+  }
+  const bool have = d <= mp.p;
+  const int dd = have ? d : mp.p;
+  const int j = have ? (g - base) / KR : 0, i = have ? (g - base) % KR : 0;
+  const int cn = mp.node(dd, j), t = (cn - 1) >> 1;
+  const NodeInfo nt = I.nodes[t], nn = I.nodes[cn];
+  const NodeInfo n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
+  const int kk = n1.ku + n2.ku;
+  const int ro = cn == 2 * t + 1 ? 0 : n1.ku;
+  const bool live = have & (i < nn.ku) & (nt.ku > 0);   // rows ku .. KR-1 are written as zero
+  const int ic = max(min(i, nn.ku - 1), 0);
+  const T* Rr = I.R + nt.oR + ro + ic;
+  if (nn.ku > 0 && nt.ku > 0) {
+#pragma unroll
+    for (int l = 0; l < KR; ++l) {
+      const T v = Rr[(int64_t)min(l, nt.ku - 1) * kk];
+      sl.r[l] = (l < nt.ku) ? v : T(0);
+    }
+    const T* yc = I.yh + nn.oyh + ic + (int64_t)c0 * I.ldm;
+#pragma unroll
+    for (int c = 0; c < kDC; ++c) sl.yc[c] = yc[(int64_t)min(c, nc - 1) * I.ldm];
+  } else {
+#pragma unroll
+    for (int l = 0; l < KR; ++l) sl.r[l] = T(0);
+#pragma unroll
+    for (int c = 0; c < kDC; ++c) sl.yc[c] = T(0);
+  }
+  if (!live) {
+#pragma unroll
+    for (int l = 0; l < KR; ++l) sl.r[l] = T(0);
+#pragma unroll
+    for (int c = 0; c < kDC; ++c) sl.yc[c] = T(0);
+  }
+  sl.d = have ? dd : 0;
+  sl.j = j;
+  sl.i = i;
+  sl.ku = nn.ku;
+}
+
+template <typename T, int KR>
+__device__ __forceinline__ void down_slot_apply(const DownSlot<T, KR>& sl, int nc,
+                                                const T* src, T* dst, int64_t blk) {
+  const T* ps = src + (int64_t)(sl.j >> 1) * blk;
+  T* o = dst + (int64_t)sl.j * blk + sl.i;
+#pragma unroll
+  for (int c = 0; c < kDC; ++c) {
+    if (c >= nc) break;
+    T acc = sl.yc[c];
+#pragma unroll
+    for (int l = 0; l < KR; ++l) acc += sl.r[l] * ps[l + c * kMaxRank];
+    o[c * kMaxRank] = sl.i < sl.ku ? acc : T(0);
+  }
+}
+
+template <typename T, bool BATCH, int KR, int NR>
+__global__ __launch_bounds__(kDT) void k_mmf_down(KArgs<T, CallMM<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  Inst<T> I; CallMM<T> C; int s;
+  resolve<BATCH>(a, I, C, s);
+  const int c0 = blockIdx.y * kDC;
+  if (c0 >= C.nrhs) return;
+  const int nc = min(kDC, C.nrhs - c0);
+  const int ncw = min(kDC, C.nrhs);
+  const int64_t blk = (int64_t)kMaxRank * ncw;
+  T* cur = reinterpret_cast<T*>(smem_raw);   // two levels x 2^kDnH nodes x blk
+  T* nxt = cur + (int64_t)(1 << kDnH) * blk;
+  DownMap mp;
+  mp.s = s;
+  mp.p = I.p;
+  mp.ls = I.nodes[s].level;
+  // every slot's level: total count and the prefetched rounds
+  int total = 0;
+  for (int d = 2; d <= mp.p; ++d) total += mp.cnt(d) * KR;
+  DownSlot<T, KR> sl[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) down_slot_load(I, mp, threadIdx.x + r * kDT, c0, nc, sl[r]);
+  // level 1: core values of its node(s)
+  {
+    const int n1c = mp.cnt(1);
+    for (int o = threadIdx.x; o < n1c * kMaxRank * nc; o += kDT) {
+      const int j = o / (kMaxRank * nc), rem = o % (kMaxRank * nc);
+      const int i = rem % kMaxRank, c = rem / kMaxRank;
+      const NodeInfo nn = I.nodes[mp.node(1, j)];
+      cur[j * blk + i + c * kMaxRank] =
+          i < nn.ku ? I.yh[nn.oyh + i + (int64_t)(c0 + c) * I.ldm] : T(0);
+    }
+  }
+  __syncthreads();
+  const int rounds = (total + kDT - 1) / kDT;
+  for (int d = 2; d <= mp.p; ++d) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (sl[r].d == d) down_slot_apply(sl[r], nc, cur, nxt, blk);
+    for (int r = NR; r < rounds; ++r) {   // slots beyond the prefetched rounds
+      const int g = threadIdx.x + r * kDT;
+      if (down_slot_level<KR>(mp, g) != d) continue;
+      DownSlot<T, KR> x;
+      down_slot_load(I, mp, g, c0, nc, x);
+      down_slot_apply(x, nc, cur, nxt, blk);
+    }
+    __syncthreads();
+    T* q = cur; cur = nxt; nxt = q;
+  }
+  // y^ of the leaves of the subtree
+  const int dl = mp.p > mp.ls ? mp.p : mp.ls;
+  const int nl = mp.cnt(dl);
+  for (int o = threadIdx.x; o < nl * kMaxRank * nc; o += kDT) {
+    const int j = o / (kMaxRank * nc), rem = o % (kMaxRank * nc);
+    const int i = rem % kMaxRank, c = rem / kMaxRank;
+    const NodeInfo nn = I.nodes[mp.node(dl, j)];
+    if (i < nn.ku) I.yh[nn.oyh + i + (int64_t)(c0 + c) * I.ldm] = cur[j * blk + i + c * kMaxRank];
+  }
+}
+
+// Y_i = D_i X_i + U_i y^_i.  Wavefront w owns rows 16w .. 16w+15; lane l holds
+// row 16w + (l & 15) of the columns 32q .. 32q+31 of D_i (q = l >> 4) and of
+// the columns q, q+4, ... of U_i; the four quarters are combined by two lane
+// exchanges.
+template <typename T, bool BATCH, int NU, int MC>
+__global__ __launch_bounds__(kLT) void k_mmf_leaf(KArgs<T, CallMM<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  Inst<T> I; CallMM<T> C; int node;
+  resolve<BATCH>(a, I, C, node);
+  const int c0 = blockIdx.y * MC;
+  if (c0 >= C.nrhs) return;
+  const int nc = min(MC, C.nrhs - c0);
+  const int ncw = min(MC, C.nrhs);
+  T* xs = reinterpret_cast<T*>(smem_raw);   // kXP x ncw
+  T* ys = xs + kXP * ncw;                   // kMaxRank x ncw
+  const NodeInfo nd = I.nodes[node];
+  const int m = nd.m, ku = I.p > 0 ? nd.ku : 0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int row = 16 * w + (lane & 15), q = lane >> 4;
+  const bool rv = row < m;
+  // every global load of the work-group is issued before the first use: D and
+  // U into registers, X and y^ into registers and then LDS.  Out-of-range
+  // rows and columns read a valid element and are zeroed afterwards.
+  // buffer loads: the block base in a resource descriptor, one lane offset
+  // register for all columns (the column offset is uniform), and reads past
+  // the block (columns >= m, or >= ku) return zero
+  const uint32_t rb = (uint32_t)(min(row, m - 1) * (int)sizeof(T));
+  const auto Dr = buf_rsrc(I.D + nd.oD, (uint32_t)(m * m * (int)sizeof(T)));
+  const auto Ur = buf_rsrc(ku > 0 ? I.U + nd.oU : I.D + nd.oD,
+                           (uint32_t)(m * ku * (int)sizeof(T)));
+  const uint32_t cs = (uint32_t)(m * (int)sizeof(T));   // column stride in bytes
+  T dv[32];
+#pragma unroll
+  for (int jj = 0; jj < 32; ++jj) {
+    const T v = buf_load<T>(Dr, rb + (uint32_t)(32 * q) * cs, (uint32_t)jj * cs);
+    dv[jj] = rv ? v : T(0);
+  }
+  T uv[NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    const T v = buf_load<T>(Ur, rb + (uint32_t)q * cs, (uint32_t)(4 * i) * cs);
+    uv[i] = rv ? v : T(0);
+  }
+  constexpr int UX = (kMaxBlock * MC + kLT - 1) / kLT, UY = (kMaxRank * MC + kLT - 1) / kLT;
+  T xv[UX], yv[UY];
+  const T* Xb = C.X + nd.row0 + (int64_t)c0 * C.ldx;
+#pragma unroll
+  for (int u = 0; u < UX; ++u) {
+    const int o = tid + u * kLT, i = o % kMaxBlock, c = min(o / kMaxBlock, nc - 1);
+    const T v = Xb[min(i, m - 1) + (int64_t)c * C.ldx];
+    xv[u] = (i < m) ? v : T(0);
+  }
+  const T* Yh = I.yh + nd.oyh + (int64_t)c0 * I.ldm;
+#pragma unroll
+  for (int u = 0; u < UY; ++u) {
+    const int o = tid + u * kLT, i = o % kMaxRank, c = min(o / kMaxRank, nc - 1);
+    const T v = ku > 0 ? Yh[min(i, ku - 1) + (int64_t)c * I.ldm] : T(0);
+    yv[u] = (i < ku) ? v : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < UX; ++u) {
+    const int o = tid + u * kLT;
+    if (o < kMaxBlock * nc) xs[xrow(o % kMaxBlock) + (o / kMaxBlock) * kXP] = xv[u];
+  }
+#pragma unroll
+  for (int u = 0; u < UY; ++u) {
+    const int o = tid + u * kLT;
+    if (o < kMaxRank * nc) ys[o % kMaxRank + (o / kMaxRank) * kMaxRank] = yv[u];
+  }
+  __syncthreads();
+  for (int c = 0; c < nc; ++c) {
+    const T* xc = xs + c * kXP + xrow(32 * q);
+    const T* yc = ys + c * kMaxRank + q;
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int jj = 0; jj < 32; jj += 2) {
+      s0 += dv[jj] * xc[jj];
+      s1 += dv[jj + 1] * xc[jj + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < NU; i += 2) {
+      s0 += uv[i] * yc[4 * i];
+      s1 += uv[i + 1] * yc[4 * i + 4];
+    }
+    T sum = s0 + s1;
+    sum += __shfl_xor(sum, 16, 64);
+    sum += __shfl_xor(sum, 32, 64);
+    if (q == 0 && rv) C.Y[nd.row0 + row + (int64_t)(c0 + c) * C.ldy] = sum;
+  }
+}
+
+template <typename T>
+void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrhs, int max_ku,
+                int max_k, hipStream_t s) {
+  if (nblocks <= 0 || nrhs <= 0) return;
+  const bool batch = a.tasks != nullptr;
+  // right-hand-side chunk of the up and leaf kernels: 1, 8 or 32 columns
+  const int mc = nrhs == 1 ? 1 : (nrhs <= 8 ? 8 : 32);
+  const int ytiles = (nrhs + mc - 1) / mc;
+  const int ncw = nrhs < mc ? nrhs : mc;
+  const bool wide = max_k > 32;
+  static const char* n64[] = {"mmf_up_f64", "mmf_down_f64", "mmf_leaf_f64"};
+  static const char* n32[] = {"mmf_up_f32", "mmf_down_f32", "mmf_leaf_f32"};
+  TimedLaunch tl((sizeof(T) == 8 ? n64 : n32)[(int)step], s);
+#define HSS_MMF(K, G, B, SM)                                              \
+  if (batch) hipLaunchKernelGGL((K<T, true>), G, B, SM, s, a);            \
+  else hipLaunchKernelGGL((K<T, false>), G, B, SM, s, a);
+#define HSS_MMF_UP(MC, NV)                                                                     \
+  if (batch) hipLaunchKernelGGL((k_mmf_up<T, true, MC, NV, 4 * NV>), dim3(nblocks), dim3(kUT), sm, \
+                                s, a);                                                         \
+  else hipLaunchKernelGGL((k_mmf_up<T, false, MC, NV, 4 * NV>), dim3(nblocks), dim3(kUT), sm, s, a);
+#define HSS_MMF_LEAF(NU, MC)                                                              \
+  if (batch) hipLaunchKernelGGL((k_mmf_leaf<T, true, NU, MC>), g, b, sm, s, a);          \
+  else hipLaunchKernelGGL((k_mmf_leaf<T, false, NU, MC>), g, b, sm, s, a);
+  switch (step) {
+    case MMFStep::Up: {
+      const size_t sm = (size_t)(kMaxBlock + kMaxRank) * ncw * sizeof(T);
+      if (mc == 1) { if (wide) { HSS_MMF_UP(1, 16) } else { HSS_MMF_UP(1, 8) } }
+      else if (mc == 8) { if (wide) { HSS_MMF_UP(8, 16) } else { HSS_MMF_UP(8, 8) } }
+      else { if (wide) { HSS_MMF_UP(32, 16) } else { HSS_MMF_UP(32, 8) } }
+      break;
+    }
+    case MMFStep::Down: {
+      const size_t sm = (size_t)2 * (1 << kDnH) * kMaxRank * (nrhs < kDC ? nrhs : kDC) * sizeof(T);
+      const dim3 g(nblocks, (nrhs + kDC - 1) / kDC), b(kDT);
+      if (!wide) {
+        if (batch) hipLaunchKernelGGL((k_mmf_down<T, true, 32, 1>), g, b, sm, s, a);
+        else hipLaunchKernelGGL((k_mmf_down<T, false, 32, 1>), g, b, sm, s, a);
+      } else {
+        if (batch) hipLaunchKernelGGL((k_mmf_down<T, true, 64, 1>), g, b, sm, s, a);
+        else hipLaunchKernelGGL((k_mmf_down<T, false, 64, 1>), g, b, sm, s, a);
+      }
+      break;
+    }
+    case MMFStep::Leaf: {
+      const size_t sm = (size_t)(kXP + kMaxRank) * ncw * sizeof(T);
+      const dim3 g(nblocks, ytiles), b(kLT);
+      const bool wu = max_ku > 32;
+      if (mc == 1) { if (wu) { HSS_MMF_LEAF(16, 1) } else { HSS_MMF_LEAF(8, 1) } }
+      else if (mc == 8) { if (wu) { HSS_MMF_LEAF(16, 8) } else { HSS_MMF_LEAF(8, 8) } }
+      else { if (wu) { HSS_MMF_LEAF(16, 32) } else { HSS_MMF_LEAF(8, 32) } }
+      break;
+    }
+  }
+#undef HSS_MMF_UP
+#undef HSS_MMF_LEAF
+#undef HSS_MMF
+}
+
+int mmf_down_height() { return kDnH; }
+
+template void launch_mmf<double>(MMFStep, const KArgs<double, CallMM<double>>&, int, int, int,
+                                 int, hipStream_t);
+template void launch_mmf<float>(MMFStep, const KArgs<float, CallMM<float>>&, int, int, int, int,
+                                hipStream_t);
+
+}  // namespace hss

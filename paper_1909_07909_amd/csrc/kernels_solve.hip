@@ -69,7 +69,18 @@ struct NodeSrc {
 
 template <typename T>
 __device__ __forceinline__ T ut(const T* U, int ld, bool m, int a, int x) {
-  return (m && a < x) ? T(0) : U[a + x * ld];
+  const T v = U[a + x * ld];
+  return (m & (a < x)) ? T(0) : v;
+}
+
+// Row r of [a; b] (ka + kb rows), zero past the end; both reads are issued
+// from clamped (valid) addresses whatever r is.
+template <typename T>
+__device__ __forceinline__ T stacked(const T* a, int ka, const T* b, int kb, int r) {
+  // (ka and kb are uniform: an empty part is not read at all)
+  const T va = ka > 0 ? a[min(r, ka - 1)] : T(0);
+  const T vb = kb > 0 ? b[min(max(r - ka, 0), kb - 1)] : T(0);
+  return r < ka ? va : (r < ka + kb ? vb : T(0));
 }
 
 template <typename T>
@@ -98,13 +109,15 @@ template <typename T, typename F>
 __device__ __forceinline__ T* stage_block(T* dst, int rows, int cols, F f) {
   const int lane = threadIdx.x & 63;
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+  if (rows <= 0 || cols <= 0) return dst;
+  const int ra = min(lane, rows - 1), rb = min(lane + 64, rows - 1);
   for (int j0 = w; j0 < cols; j0 += 8 * nw) {
     T v[16];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int j = j0 + u * nw;
-      v[2 * u] = (j < cols && lane < rows) ? f(lane, j) : T(0);
-      v[2 * u + 1] = (j < cols && lane + 64 < rows) ? f(lane + 64, j) : T(0);
+      const int jc = min(j0 + u * nw, cols - 1);
+      v[2 * u] = f(ra, jc);        // unconditional reads from clamped indices
+      v[2 * u + 1] = f(rb, jc);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -161,29 +174,34 @@ __device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, int node, 
     const T* z2 = I.wz + n2.oz + co;
     const T* c1 = I.wc + n1.oc + co;
     const T* c2 = I.wc + n2.oc + co;
-    z1l[c] = cv && lane < n1.kv ? z1[lane] : T(0);
-    z2l[c] = cv && lane < n2.kv ? z2[lane] : T(0);
-    x0[c] = !cv ? T(0) : (r0 < k1 ? c1[r0] : (r0 < mp ? c2[r0 - k1] : T(0)));
-    x1[c] = !cv ? T(0) : (r1 < k1 ? c1[r1] : (r1 < mp ? c2[r1 - k1] : T(0)));
+    z1l[c] = n1.kv > 0 ? ld_or0(z1 + min(lane, n1.kv - 1), cv & (lane < n1.kv)) : T(0);
+    z2l[c] = n2.kv > 0 ? ld_or0(z2 + min(lane, n2.kv - 1), cv & (lane < n2.kv)) : T(0);
+    const T a0 = stacked(c1, k1, c2, mp - k1, r0), a1 = stacked(c1, k1, c2, mp - k1, r1);
+    x0[c] = cv ? a0 : T(0);
+    x1[c] = cv ? a1 : T(0);
     t1[c] = T(0);
     t2[c] = T(0);
   }
 #pragma unroll 4
-  for (int y = 0; y < n2.kv; ++y) {
-    const T b = lane < n1.ku ? S.B12[lane + y * S.ld12] : T(0);
+  for (int y = 0; y < (n1.ku > 0 ? n2.kv : 0); ++y) {
+    const T bv = S.B12[max(min(lane, n1.ku - 1), 0) + y * S.ld12];
+    const T b = lane < n1.ku ? bv : T(0);
 #pragma unroll
     for (int c = 0; c < CPW; ++c) t1[c] += b * bcast(z2l[c], y);
   }
 #pragma unroll 4
-  for (int y = 0; y < n1.kv; ++y) {
-    const T b = lane < n2.ku ? S.B21[lane + y * S.ld21] : T(0);
+  for (int y = 0; y < (n2.ku > 0 ? n1.kv : 0); ++y) {
+    const T bv = S.B21[max(min(lane, n2.ku - 1), 0) + y * S.ld21];
+    const T b = lane < n2.ku ? bv : T(0);
 #pragma unroll
     for (int c = 0; c < CPW; ++c) t2[c] += b * bcast(z1l[c], y);
   }
 #pragma unroll 4
   for (int x = 0; x < n1.ku; ++x) {
-    const T u0 = r0 < k1 ? ut(S.U1, S.ldu1, S.m1, r0, x) : T(0);
-    const T u1 = r1 < k1 ? ut(S.U1, S.ldu1, S.m1, r1, x) : T(0);
+    const T a0 = ut(S.U1, S.ldu1, S.m1, min(r0, k1 - 1), x);
+    const T a1 = ut(S.U1, S.ldu1, S.m1, min(r1, k1 - 1), x);
+    const T u0 = r0 < k1 ? a0 : T(0);
+    const T u1 = r1 < k1 ? a1 : T(0);
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
       const T tx = bcast(t1[c], x);
@@ -193,8 +211,11 @@ __device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, int node, 
   }
 #pragma unroll 4
   for (int x = 0; x < n2.ku; ++x) {
-    const T u0 = r0 >= k1 && r0 < mp ? ut(S.U2, S.ldu2, S.m2, r0 - k1, x) : T(0);
-    const T u1 = r1 >= k1 && r1 < mp ? ut(S.U2, S.ldu2, S.m2, r1 - k1, x) : T(0);
+    const int k2 = mp - k1;
+    const T a0 = ut(S.U2, S.ldu2, S.m2, min(max(r0 - k1, 0), k2 - 1), x);
+    const T a1 = ut(S.U2, S.ldu2, S.m2, min(max(r1 - k1, 0), k2 - 1), x);
+    const T u0 = ((r0 >= k1) & (r0 < mp)) ? a0 : T(0);
+    const T u1 = ((r1 >= k1) & (r1 < mp)) ? a1 : T(0);
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
       const T tx = bcast(t2[c], x);
@@ -248,28 +269,29 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
     S = src_global(I, nd, node);
   }
   if (col0 >= C.nrhs) return;
-  const T taul = lane < ku ? I.tq[nd.otq + lane] : T(0);
+  const T taul = ku > 0 ? ld_or0(I.tq + nd.otq + min(lane, ku - 1), lane < ku) : T(0);
   T x0[CPW], x1[CPW];
   if (nd.is_leaf) {
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
       const bool cv = col0 + c < C.nrhs;
       const T* b = C.B + nd.row0 + (int64_t)(cv ? col0 + c : 0) * C.ldb;
-      x0[c] = cv && r0 < mp ? b[r0] : T(0);
-      x1[c] = cv && r1 < mp ? b[r1] : T(0);
+      x0[c] = ld_or0(b + min(r0, mp - 1), cv & (r0 < mp));
+      x1[c] = ld_or0(b + min(r1, mp - 1), cv & (r1 < mp));
     }
   } else {
     gather_internal<T, CPW>(I, nd, node, col0, C.nrhs, lane, S, x0, x1);
   }
   if (e > 0) {
     // b~ = Q^T rhs = H_0 ... H_{ku-1} rhs, H_{ku-1} applied first (lane j holds tau_j)
-#pragma unroll 4
+#pragma unroll 8
     for (int j = ku - 1; j >= 0; --j) {
       const T tau = bcast(taul, j);
       const int pr = e + j;
       const T* v = S.U + j * S.ldu;
-      const T v0 = r0 < pr ? v[r0] : (r0 == pr ? T(1) : T(0));
-      const T v1 = r1 < pr ? v[r1] : (r1 == pr ? T(1) : T(0));
+      const T a0 = v[min(r0, mp - 1)], a1 = v[min(r1, mp - 1)];
+      const T v0 = r0 < pr ? a0 : (r0 == pr ? T(1) : T(0));
+      const T v1 = r1 < pr ? a1 : (r1 == pr ? T(1) : T(0));
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const T w = wave_sum(v0 * x0[c] + v1 * x1[c]) * tau;
@@ -278,11 +300,12 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
       }
     }
     // y = L^{-1} b~_top; the same column sweep leaves b~_bot - D~21 y below
-#pragma unroll 8
+#pragma unroll 16
     for (int i = 0; i < e; ++i) {
       const T* Li = S.L + i * S.ldl;
-      const T l0 = r0 > i && r0 < mp ? Li[r0] : T(0);
-      const T l1 = r1 > i && r1 < mp ? Li[r1] : T(0);
+      const T a0 = Li[min(r0, mp - 1)], a1 = Li[min(r1, mp - 1)];
+      const T l0 = ((r0 > i) & (r0 < mp)) ? a0 : T(0);
+      const T l1 = ((r1 > i) & (r1 < mp)) ? a1 : T(0);
       const T dinv = T(1) / Li[i];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
@@ -321,36 +344,27 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
       const int64_t co = (int64_t)(col0 + c) * I.lds;
       const T* z1 = I.wz + n1.oz + co;
       const T* z2 = I.wz + n2.oz + co;
-      zc0[c] = r0 < kv1 ? z1[r0] : (r0 < kw ? z2[r0 - kv1] : T(0));
-      zc1[c] = r1 < kv1 ? z1[r1] : (r1 < kw ? z2[r1 - kv1] : T(0));
+      zc0[c] = stacked(z1, kv1, z2, kw - kv1, r0);
+      zc1[c] = stacked(z1, kv1, z2, kw - kv1, r1);
     }
   }
-  if constexpr (CPW == 1) {
-    T* zo = I.wz + nd.oz + (int64_t)col0 * I.lds;
-    T part[64];
-#pragma unroll
-    for (int aa = 0; aa < 64; ++aa) {
-      T acc = T(0);
-      if (aa < kv) {
-        const T* Va = S.V + aa * S.ldv;
-        acc = (r0 < e ? Va[r0] * x0[0] : T(0)) + (r1 < e ? Va[r1] * x1[0] : T(0));
-        if (kw) acc += (r0 < kw ? S.W[r0 + aa * S.ldw] * zc0[0] : T(0)) +
-                       (r1 < kw ? S.W[r1 + aa * S.ldw] * zc1[0] : T(0));
-      }
-      part[aa] = acc;
-    }
-    const T z = wave_transpose_sum64(part);
-    if (lane < kv) zo[lane] = z;
-  } else {
+  {
     // one wavefront reduction per (entry, column); results kept by lane aa
     T zr[CPW];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) zr[c] = T(0);
+#pragma unroll 8
     for (int aa = 0; aa < kv; ++aa) {
       const T* Va = S.V + aa * S.ldv;
-      const T va0 = r0 < e ? Va[r0] : T(0), va1 = r1 < e ? Va[r1] : T(0);
-      const T wa0 = kw && r0 < kw ? S.W[r0 + aa * S.ldw] : T(0);
-      const T wa1 = kw && r1 < kw ? S.W[r1 + aa * S.ldw] : T(0);
+      const int ec = max(e - 1, 0);
+      const T a0 = Va[min(r0, ec)], a1 = Va[min(r1, ec)];
+      const T va0 = r0 < e ? a0 : T(0), va1 = r1 < e ? a1 : T(0);
+      T wa0 = T(0), wa1 = T(0);
+      if (kw) {
+        const T w0 = S.W[min(r0, kw - 1) + aa * S.ldw], w1 = S.W[min(r1, kw - 1) + aa * S.ldw];
+        wa0 = r0 < kw ? w0 : T(0);
+        wa1 = r1 < kw ? w1 : T(0);
+      }
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const T sz = wave_sum(va0 * x0[c] + va1 * x1[c] + wa0 * zc0[c] + wa1 * zc1[c]);
@@ -378,7 +392,7 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
   int* piv = reinterpret_cast<int*>(LU + mp * mp);
   T* rest = reinterpret_cast<T*>(piv + ((mp + 3) & ~3));
   stage_block(LU, mp, mp, [&](int i, int j) { return I.rootLU[i + j * mp]; });
-  for (int o = threadIdx.x; o < mp; o += blockDim.x) piv[o] = I.piv[o];
+  for (int o = threadIdx.x; o < mp; o += blockDim.x) piv[o] = I.piv[o];   // (mp <= 128 < blockDim)
   NodeSrc<T> S = (nd.is_leaf || !(a.flags & 1)) ? src_global(I, nd, node)
                                                  : src_stage_fwd(I, nd, node, rest);
   __syncthreads();
@@ -389,8 +403,8 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
     for (int c = 0; c < CPW; ++c) {
       const bool cv = col0 + c < C.nrhs;
       const T* b = C.B + nd.row0 + (int64_t)(cv ? col0 + c : 0) * C.ldb;
-      t0[c] = cv && r0 < mp ? b[r0] : T(0);
-      t1[c] = cv && r1 < mp ? b[r1] : T(0);
+      t0[c] = ld_or0(b + min(r0, mp - 1), cv & (r0 < mp));
+      t1[c] = ld_or0(b + min(r1, mp - 1), cv & (r1 < mp));
     }
   } else {
     gather_internal<T, CPW>(I, nd, node, col0, C.nrhs, lane, S, t0, t1);
@@ -480,18 +494,21 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_bwd_w(KArgs<T, CallSV<T>> a) {
     const int64_t co = (int64_t)(cv ? col0 + c : 0) * I.lds;
     const T* yi = I.wy + nd.oy + co;
     const T* xi = I.wx + nd.ox + co;
-    x0[c] = !cv ? T(0) : (r0 < e ? yi[r0] : (r0 < mp ? xi[r0 - e] : T(0)));
-    x1[c] = !cv ? T(0) : (r1 < e ? yi[r1] : (r1 < mp ? xi[r1 - e] : T(0)));
+    const T a0 = stacked(yi, e, xi, mp - e, r0), a1 = stacked(yi, e, xi, mp - e, r1);
+    x0[c] = cv ? a0 : T(0);
+    x1[c] = cv ? a1 : T(0);
   }
   // Z [y; x^] = H_0 ... H_{e-1} [y; x^], H_{e-1} applied first
-  const T taul0 = r0 < e ? I.tz[nd.otz + r0] : T(0);
-  const T taul1 = r1 < e ? I.tz[nd.otz + r1] : T(0);
+  const int ec = max(e - 1, 0);
+  const T taul0 = e > 0 ? ld_or0(I.tz + nd.otz + min(r0, ec), r0 < e) : T(0);
+  const T taul1 = e > 0 ? ld_or0(I.tz + nd.otz + min(r1, ec), r1 < e) : T(0);
 #pragma unroll 4
   for (int i = e - 1; i >= 0; --i) {
     const T tau = row_of(taul0, taul1, i);
     const T* v = Z + i * ldz;
-    const T v0 = r0 < mp ? v[r0] : T(0);
-    const T v1 = r1 < mp ? v[r1] : T(0);
+    const T a0 = v[min(r0, mp - 1)], a1 = v[min(r1, mp - 1)];
+    const T v0 = r0 < mp ? a0 : T(0);
+    const T v1 = r1 < mp ? a1 : T(0);
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
       const T w = wave_sum(v0 * x0[c] + v1 * x1[c]) * tau;

@@ -44,10 +44,8 @@ __device__ __forceinline__ T utilde(const T* FU, const NodeInfo& n, int a, int x
 template <typename T, typename F>
 __device__ __forceinline__ void stage(int M, int N, F f, T* dst) {
   constexpr int ld = kMaxRank + 1;
-  for (int o = threadIdx.x; o < M * N; o += blockDim.x) {
-    const int i = o % M, j = o / M;
-    dst[i + j * ld] = f(i, j);
-  }
+  if (M <= 0 || N <= 0) return;
+  wg_stage<8, T>(M, N, f, [&](int i, int j, T v) { dst[i + j * ld] = v; });
 }
 
 // out(i, j) = sum_l A(i, l) B(l, j) (TB: B(l, j) = Bs[j + l*ld]), A, B in LDS
@@ -80,18 +78,22 @@ __global__ __launch_bounds__(kNT) void k_ulv_merge(KArgs<T, CallSV<T>> a) {
   T* Bs = As + kMaxRank * ld;
   T* Cs = Bs + kMaxRank * ld;
   // diagonal blocks D~22 of the children
-  for (int o = threadIdx.x; o < k1 * k1; o += blockDim.x) {
-    const int i = o % k1, j = o / k1;
-    FD[i + (int64_t)j * mp] = FD1[n1.e + i + (int64_t)(n1.e + j) * n1.mp];
-  }
-  for (int o = threadIdx.x; o < k2 * k2; o += blockDim.x) {
-    const int i = o % k2, j = o / k2;
-    FD[k1 + i + (int64_t)(k1 + j) * mp] = FD2[n2.e + i + (int64_t)(n2.e + j) * n2.mp];
-  }
+  if (k1 > 0)
+    wg_stage<8, T>(k1, k1, [&](int i, int j) { return FD1[n1.e + i + (int64_t)(n1.e + j) * n1.mp]; },
+                   [&](int i, int j, T v) { FD[i + (int64_t)j * mp] = v; });
+  if (k2 > 0)
+    wg_stage<8, T>(k2, k2, [&](int i, int j) { return FD2[n2.e + i + (int64_t)(n2.e + j) * n2.mp]; },
+                   [&](int i, int j, T v) { FD[k1 + i + (int64_t)(k1 + j) * mp] = v; });
   const T* B12 = I.B12 + nd.oB12;
   const T* B21 = I.B21 + nd.oB21;
-  auto ut1 = [&](int i, int x) { return (n1.e > 0 && i < x) ? T(0) : FU1[n1.e + i + (int64_t)x * n1.mp]; };
-  auto ut2 = [&](int i, int x) { return (n2.e > 0 && i < x) ? T(0) : FU2[n2.e + i + (int64_t)x * n2.mp]; };
+  auto ut1 = [&](int i, int x) {
+    const T v = FU1[n1.e + i + (int64_t)x * n1.mp];
+    return ((n1.e > 0) & (i < x)) ? T(0) : v;
+  };
+  auto ut2 = [&](int i, int x) {
+    const T v = FU2[n2.e + i + (int64_t)x * n2.mp];
+    return ((n2.e > 0) & (i < x)) ? T(0) : v;
+  };
   auto vb1 = [&](int i, int x) { return FV1[n1.e + i + (int64_t)x * n1.mp]; };
   auto vb2 = [&](int i, int x) { return FV2[n2.e + i + (int64_t)x * n2.mp]; };
   // D'(c1, c2) = U~_c1 (B12 V^b_c2^T)
@@ -162,7 +164,8 @@ __global__ __launch_bounds__(kNT) void k_ulv_root_lu(KArgs<T, CallSV<T>> a) {
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ int pivs;
   const T* src = I.p == 0 ? I.D + nd.oD : I.FD + nd.oFD;
-  for (int o = tid; o < mp * mp; o += nt) Ls[o % mp + (o / mp) * ld] = (double)src[o];
+  wg_stage<16, T>(mp, mp, [&](int i, int j) { return src[i + (int64_t)j * mp]; },
+                  [&](int i, int j, T v) { Ls[i + j * ld] = (double)v; });
   __syncthreads();
   for (int j = 0; j < mp; ++j) {
     if (tid < 64) {

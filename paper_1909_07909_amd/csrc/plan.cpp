@@ -123,6 +123,7 @@ hss_status build_plan(const hss_tree_desc* tree, Plan& P, std::string* why) {
     P.max_m = std::max(P.max_m, d.is_leaf ? d.m : 0);
     P.max_mp = std::max(P.max_mp, d.mp);
     P.max_k = std::max(P.max_k, kmax);
+    if (d.is_leaf) P.leaf_max_ku = std::max(P.leaf_max_ku, d.ku);
   }
   P.level_fwd_stage.assign(p + 1, 0);
   P.level_bwd_stage.assign(p + 1, 0);

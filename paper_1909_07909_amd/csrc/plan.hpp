@@ -24,6 +24,7 @@ struct Plan {
   int64_t ldm = 0;   // product work rows
   int64_t lds = 0;   // solve work rows
   int32_t max_m = 0, max_mp = 0, max_k = 0;
+  int32_t leaf_max_ku = 0;
   std::vector<int32_t> level_max_mp;   // per level l = 0..p
   // LDS copies (elements) the forward / backward sweeps of an internal level
   // need when they stage a node's factors (max over the level); root: the

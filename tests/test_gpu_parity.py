@@ -54,6 +54,7 @@ CASES = [
     ("wide_rhs", 2048, 128, 16, 40),
     ("single_leaf", 50, 64, 4, 3),
     ("k32_m128", 8192, 128, 32, 1),
+    ("k64_m128", 4096, 128, 64, 3),
 ]
 
 
