@@ -222,8 +222,9 @@ void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T*
     // fused: leaves (with the climb), subtree walks, leaf outputs
     const int mku = h->plan.leaf_max_ku, mk = h->plan.max_k;
     if (p > 0) {
-      a.node0 = level_first(p);
-      launch_mmf<T>(MMFStep::Up, a, 1 << p, (int)nrhs, mku, mk, s);
+      const int lu = std::max(p - mmf_up_height(), 0);
+      a.node0 = level_first(lu);
+      launch_mmf<T>(MMFStep::Up, a, 1 << lu, (int)nrhs, mku, mk, s);
       const int ls = std::max(p - mmf_down_height(), 0);
       a.node0 = level_first(ls);
       launch_mmf<T>(MMFStep::Down, a, 1 << ls, (int)nrhs, mku, mk, s);
@@ -491,9 +492,9 @@ hss_status batch_matmul_impl(BatchScratch& BS, hss_handle* const* hs, int count,
   auto none = [](const Plan&, int) -> int64_t { return 0; };
   auto lvl = [](const Plan& P, int t) { return P.nodes[t].level; };
   if (op == HSS_OP_N) {
-    const int dh = mmf_down_height();
-    L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
-               none);                                                    // up: leaves, p > 0
+    const int dh = mmf_down_height(), uh = mmf_up_height();
+    L.add_step(hs, count, [&](int, const Plan& P, int t) {
+      return P.p > 0 && lvl(P, t) == std::max(P.p - uh, 0); }, none);   // up: subtree roots
     L.add_step(hs, count, [&](int, const Plan& P, int t) {
       return P.p > 0 && lvl(P, t) == std::max(P.p - dh, 0); }, none);   // down: subtree roots
     L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.nodes[t].is_leaf != 0; },

@@ -13,16 +13,17 @@ template <typename T>
 void launch_mm_level(MMStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int ytiles,
                      int max_rows, hipStream_t s);
 
-// Y = A X in three launches (kernels_mmf.hip): Up over the leaves (with the
-// upward pass and core blocks carried on by the last arrival at each node),
-// Down over the nodes at level max(p - mmf_down_height(), 0), Leaf over the
-// leaves.  nrhs: the largest right-hand-side count of the launch; max_ku: the
+// Y = A X in three launches (kernels_mmf.hip): Up over the nodes at level
+// max(p - mmf_up_height(), 0) (their subtrees, then the upward pass and core
+// blocks carried on by the last arrival at each node), Down over the nodes at
+// level max(p - mmf_down_height(), 0), Leaf over the leaves.  nrhs: the largest right-hand-side count of the launch; max_ku: the
 // largest leaf rank ku; max_k: the largest rank of any node.
 enum class MMFStep { Up, Down, Leaf };
 template <typename T>
 void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrhs, int max_ku,
                 int max_k, hipStream_t s);
 int mmf_down_height();
+int mmf_up_height();
 
 enum class UlvStep { Merge, Factor, RootLU, Fwd, Root, Bwd };
 

@@ -26,6 +26,7 @@ constexpr int kUT = 256;     // threads of the up kernel
 constexpr int kDT = 512;     // threads of the down kernel
 constexpr int kLT = 512;     // threads of the leaf kernel
 constexpr int kDnH = 3;      // subtree height of a down work-group
+constexpr int kUpH = 2;      // subtree height of an up work-group
 constexpr int kXP = kMaxBlock + 8;   // padded LDS column of an X chunk
 
 // LDS row of element i of an X chunk: a gap of two after every 32 rows so that
@@ -128,105 +129,44 @@ __device__ __forceinline__ void wg_small_gemm(int M, int K, int nc, const T* __r
   }
 }
 
-// NV: V columns per wavefront of a leaf (>= kv / 4); KQ: coefficients per
-// lane of a climb product (>= every rank; a W^T wavefront takes at most KQ/2
-// outputs, the children's ranks kk <= 128 in two halves of 64 lanes).
-template <typename T, bool BATCH, int MC, int NV, int KQ>
-__global__ __launch_bounds__(kUT) void k_mmf_up(KArgs<T, CallMM<T>> a) {
-  HIP_DYNAMIC_SHARED(char, smem_raw)
-  __shared__ unsigned s_arrive;
-  Inst<T> I; CallMM<T> C; int node;
-  resolve<BATCH>(a, I, C, node);
-  const int ncw = min(MC, C.nrhs);
-  T* xs = reinterpret_cast<T*>(smem_raw);   // kMaxBlock x ncw: X chunk, then children's x^
-  T* os = xs + kMaxBlock * ncw;             // kMaxRank x ncw: x^ being formed
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int nrhs = C.nrhs;
-  const int64_t ldm = I.ldm;
-  {
-    const NodeInfo nd = I.nodes[node];
-    const int m = nd.m, kv = nd.kv;
-    const T* V = I.V + nd.oV;
-    const int r0 = lane, r1 = lane + 64;
-    // V columns w, w+4, ... of this wavefront (rows lane, lane+64), all loads
-    // issued before any is used
-    T v0[NV], v1[NV];   // NV >= kv / 4; columns >= kv read as zero
-    const auto Vr = buf_rsrc(V, (uint32_t)(m * kv * (int)sizeof(T)));
-    const uint32_t cs = (uint32_t)(m * (int)sizeof(T));
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-      const uint32_t so = (uint32_t)(w + 4 * u) * cs;
-      const T a0 = buf_load<T>(Vr, (uint32_t)(min(r0, m - 1) * (int)sizeof(T)), so);
-      const T a1 = buf_load<T>(Vr, (uint32_t)(min(r1, m - 1) * (int)sizeof(T)), so);
-      v0[u] = (r0 < m) ? a0 : T(0);
-      v1[u] = (r1 < m) ? a1 : T(0);
-    }
-    for (int c0 = 0; c0 < nrhs; c0 += MC) {
-      const int nc = min(MC, nrhs - c0);
-      stage_cols<MC>(xs, kMaxBlock, m, nc, C.X + nd.row0 + (int64_t)c0 * C.ldx, C.ldx);
-      __syncthreads();
-      // x^ = V^T X: wavefront w forms columns w, w+4, ... of V^T X
-#pragma unroll
-      for (int u = 0; u < NV; ++u) {
-        const int col = w + 4 * u;
-        if (col < kv)
-          for (int c = 0; c < nc; ++c) {
-            const T s = wave_sum(v0[u] * xs[r0 + c * kMaxBlock] + v1[u] * xs[r1 + c * kMaxBlock]);
-            if (lane == 0) os[col + c * kMaxRank] = s;
-          }
-      }
-      __syncthreads();
-      if (w == 0)
-        for (int o = lane; o < kv * nc; o += 64)
-          xh_put(I.xh + nd.oxh + o % kv + (int64_t)(c0 + o / kv) * ldm,
-                 os[o % kv + (o / kv) * kMaxRank]);
-      __syncthreads();
-    }
-  }
-  // Climb: the second arrival at a node carries on with it.  Every x^ is
-  // written with agent-coherent stores and read with agent-coherent loads;
-  // the writers wait for their stores to complete before the barrier that
-  // precedes the arrival count, and the reads of the children's x^ are
-  // issued only after the count has been seen (through the barrier).
-  int t = node;
-  while (t > 0) {
-    const int par = (t - 1) >> 1;
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (tid == 0) s_arrive = atomicAdd(I.cnt + par, 1u);
-    __syncthreads();
-    const bool second = (s_arrive & 1u) != 0;
-    __syncthreads();
-    if (!second) return;
-    t = par;
+// Products of one node t with its children's x^ staged in xs (rows
+// [x^_c1; x^_c2], column c at xs + c*kMaxBlock), one per wavefront:
+//   wavefront 0: y^_c1 = B12 x^_c2 (global, read by the down kernel)
+//   wavefront 1: y^_c2 = B21 x^_c1
+//   wavefronts 2, 3 (below the root): x^_t = W^T [x^_c1; x^_c2], half of the
+//   outputs each, into xo (kMaxRank x nc in LDS)
+// The coefficients are loaded into registers first (cf_load) so that their
+// loads overlap with the staging of xs; cf_apply runs after a barrier.
+template <typename T, int KQ>
+struct NodeStep {
+  int t, kv1, kk, ni, i0;
+  bool bw;
+  T cf[KQ];
+
+  __device__ __forceinline__ void load(const Inst<T>& I, int node, int w, int lane) {
+    t = node;
     const NodeInfo nt = I.nodes[t];
     const NodeInfo n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
-    const int kv1 = n1.kv, kv2 = n2.kv, kk = kv1 + kv2;
-    // one product per wavefront, coefficients loaded straight into registers
-    // (all loads of a wavefront issued together with the children's x^):
-    //   wavefront 0: y^_c1 = B12 x^_c2   (lane = row, loop over the columns)
-    //   wavefront 1: y^_c2 = B21 x^_c1
-    //   wavefronts 2, 3: x^_t = W^T [x^_c1; x^_c2] below the root, half of
-    //   the outputs each (lanes over the inner index, wavefront sums)
-    const bool bw = w < 2;
-    const T* Bm = w == 0 ? I.B12 + nt.oB12 : I.B21 + nt.oB21;
-    const int bM = w == 0 ? n1.ku : n2.ku, bK = w == 0 ? kv2 : kv1, bx = w == 0 ? kv1 : 0;
-    T* bout = I.yh + (w == 0 ? n1.oyh : n2.oyh);
+    kv1 = n1.kv;
+    kk = n1.kv + n2.kv;
+    bw = w < 2;
     const int kvt = (t > 0 && kk > 0) ? nt.kv : 0;
     const int half = (kvt + 1) >> 1;
-    const int i0 = (w - 2) * half, ni = bw ? 0 : min(half, kvt - i0);
-    const T* Wt = I.W + (t > 0 ? nt.oW : 0);
-    T cf[KQ];
-    // (clamped addresses, loads unconditional, masks applied afterwards)
+    i0 = (w - 2) * half;
+    ni = bw ? 0 : min(half, kvt - i0);
+    const int bM = w == 0 ? n1.ku : n2.ku, bK = w == 0 ? n2.kv : n1.kv;
+    // (clamped addresses, loads unconditional, masks applied to the values)
     if (bw && bM > 0 && bK > 0) {
+      const T* Bm = w == 0 ? I.B12 + nt.oB12 : I.B21 + nt.oB21;
       const int rr = min(lane, bM - 1);
       const bool lr = lane < bM;
 #pragma unroll
-      for (int k = 0; k < KQ; ++k) cf[k] = ld_or0(Bm + rr + (int64_t)min(k, bK - 1) * bM, lr & (k < bK));
+      for (int k = 0; k < KQ; ++k)
+        cf[k] = ld_or0(Bm + rr + (int64_t)min(k, bK - 1) * bM, lr & (k < bK));
     } else if (!bw && ni > 0) {
-      // lane l: W[l + i*kk] (in cf[q]) and W[l + 64 + i*kk] (in cf[KQ/2 + q])
-      // for the ni <= KQ/2 outputs i0 .. i0+ni-1.  Only below the root: the
-      // root has no W block.
+      // lane l: W[l + i*kk] (cf[q]) and W[l + 64 + i*kk] (cf[KQ/2 + q]) for
+      // the ni <= KQ/2 outputs i0 .. i0+ni-1; the root has no W block
+      const T* Wt = I.W + nt.oW;
       const int la = min(lane, kk - 1), lb = min(lane + 64, kk - 1);
       const bool ka = lane < kk, kb = lane + 64 < kk;
 #pragma unroll
@@ -239,6 +179,155 @@ __global__ __launch_bounds__(kUT) void k_mmf_up(KArgs<T, CallMM<T>> a) {
 #pragma unroll
       for (int q = 0; q < KQ; ++q) cf[q] = T(0);
     }
+  }
+
+  __device__ __forceinline__ void apply(const Inst<T>& I, int w, int lane, int c0, int nc,
+                                        const T* xs, T* xo) const {
+    if (bw) {
+      const NodeInfo nc1 = I.nodes[2 * t + 1 + w];
+      const int bM = nc1.ku, bK = w == 0 ? kk - kv1 : kv1, bx = w == 0 ? kv1 : 0;
+      T* bout = I.yh + nc1.oyh;
+      for (int c = 0; c < nc; ++c) {
+        const T* x = xs + bx + c * kMaxBlock;
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) acc += cf[k] * x[min(k, max(bK - 1, 0))];
+        if (lane < bM) bout[lane + (int64_t)(c0 + c) * I.ldm] = acc;
+      }
+    } else if (ni > 0) {
+      for (int c = 0; c < nc; ++c) {
+        const T xa = xs[min(lane, kk - 1) + c * kMaxBlock];
+        const T xb = xs[min(lane + 64, kk - 1) + c * kMaxBlock];
+#pragma unroll
+        for (int q = 0; q < KQ / 2; ++q) {
+          if (q < ni) {
+            const T sum = wave_sum(cf[q] * xa + cf[KQ / 2 + q] * xb);
+            if (lane == 0) xo[i0 + q + c * kMaxRank] = sum;
+          }
+        }
+      }
+    }
+  }
+};
+
+// One work-group per subtree of 2^h leaves (h = min(kUpH, p)), rooted at node
+// g of level p - h.  Each wavefront projects its leaves (x^_i = V_i^T X_i),
+// the subtree's internal nodes are then taken bottom-up inside the
+// work-group (x^ kept in LDS), and from g the work-group climbs while it is
+// the second arrival at the next node (arrival counted by an atomic per node).
+// MC: right-hand-side chunk; KQ: coefficients per lane of a product (>= every
+// rank; a W^T wavefront takes at most KQ/2 outputs, children's ranks <= 128).
+template <typename T, bool BATCH, int MC, int KQ>
+__global__ __launch_bounds__(kUT) void k_mmf_up(KArgs<T, CallMM<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  __shared__ unsigned s_arrive;
+  Inst<T> I; CallMM<T> C; int g;
+  resolve<BATCH>(a, I, C, g);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nrhs = C.nrhs;
+  const int ncw = min(MC, nrhs);
+  const int64_t ldm = I.ldm;
+  const int h = I.p - I.nodes[g].level;          // subtree height (<= kUpH)
+  const int nl = 1 << h;                          // leaves of the subtree
+  T* xs = reinterpret_cast<T*>(smem_raw);         // kMaxBlock x ncw: children's x^
+  T* xl = xs + kMaxBlock * ncw;                   // 2 x nl x kMaxRank x ncw: x^ of a level
+  const int64_t slot = (int64_t)kMaxRank * ncw;
+  for (int c0 = 0; c0 < nrhs; c0 += MC) {
+    const int nc = min(MC, nrhs - c0);
+    // ---- leaves: wavefront w takes leaves w, w+4, ...; lane rows l, l+64
+    for (int j = w; j < nl; j += kUT / 64) {
+      const int leaf = ((g + 1) << h) - 1 + j;
+      const NodeInfo nd = I.nodes[leaf];
+      const int m = nd.m, kv = nd.kv;
+      const int r0 = min(lane, m - 1), r1 = min(lane + 64, m - 1);
+      T x0[MC], x1[MC];
+      const T* Xb = C.X + nd.row0 + (int64_t)c0 * C.ldx;
+#pragma unroll
+      for (int c = 0; c < MC; ++c) {
+        const int cc = min(c, nc - 1);
+        x0[c] = ld_or0(Xb + r0 + (int64_t)cc * C.ldx, (lane < m) & (c < nc));
+        x1[c] = ld_or0(Xb + r1 + (int64_t)cc * C.ldx, (lane + 64 < m) & (c < nc));
+      }
+      const auto Vr = buf_rsrc(I.V + nd.oV, (uint32_t)(m * kv * (int)sizeof(T)));
+      const uint32_t cs = (uint32_t)(m * (int)sizeof(T));
+      const uint32_t o0 = (uint32_t)(r0 * (int)sizeof(T)), o1 = (uint32_t)(r1 * (int)sizeof(T));
+      T* out = xl + (int64_t)j * slot;
+      for (int b = 0; b < kv; b += 16) {       // 16 columns of V in flight
+        T va[16], vb[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          va[u] = buf_load<T>(Vr, o0, (uint32_t)(b + u) * cs);   // columns >= kv read zero
+          vb[u] = buf_load<T>(Vr, o1, (uint32_t)(b + u) * cs);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          if (b + u < kv) {
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+              if (c < nc) {
+                const T sv = wave_sum(va[u] * x0[c] + vb[u] * x1[c]);
+                if (lane == 0) out[b + u + c * kMaxRank] = sv;
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- internal nodes of the subtree, level by level (x^ of level d in
+    // half (d & 1) of xl, node j of the level in slot j)
+    for (int d = h - 1; d >= 0; --d) {
+      T* src = xl + (int64_t)((h - 1 - d) & 1) * nl * slot;   // children level
+      T* dst = xl + (int64_t)((h - d) & 1) * nl * slot;
+      if (d == h - 1) src = xl;                                // the leaves' x^
+      for (int j = 0; j < (1 << d); ++j) {
+        const int t = ((g + 1) << d) - 1 + j;
+        NodeStep<T, KQ> st;
+        st.load(I, t, w, lane);
+        // children's x^ -> xs
+        const int kv1 = st.kv1, kk = st.kk;
+        for (int o = tid; o < kk * nc; o += kUT) {
+          const int i = o % kk, c = o / kk;
+          xs[i + c * kMaxBlock] = i < kv1 ? src[(int64_t)(2 * j) * slot + i + c * kMaxRank]
+                                          : src[(int64_t)(2 * j + 1) * slot + i - kv1 + c * kMaxRank];
+        }
+        __syncthreads();
+        st.apply(I, w, lane, c0, nc, xs, dst + (int64_t)j * slot);
+        __syncthreads();
+      }
+    }
+    // x^ of g (below the root) for the climb
+    if (g > 0) {
+      const T* xg = h == 0 ? xl : xl + (int64_t)(h & 1) * nl * slot;
+      const int kvg = I.nodes[g].kv;
+      if (w == 0)
+        for (int o = lane; o < kvg * nc; o += 64)
+          xh_put(I.xh + I.nodes[g].oxh + o % kvg + (int64_t)(c0 + o / kvg) * ldm,
+                 xg[o % kvg + (o / kvg) * kMaxRank]);
+    }
+    __syncthreads();
+  }
+  // Climb: the second arrival at a node carries on with it.  Every x^ that
+  // crosses work-groups is written with agent-coherent stores and read with
+  // agent-coherent loads; the writers wait for their stores to complete
+  // before the barrier that precedes the arrival count, and the reads of the
+  // children's x^ are issued only after the count has been seen.
+  T* os = xl;   // x^ being formed
+  int t = g;
+  while (t > 0) {
+    const int par = (t - 1) >> 1;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) s_arrive = atomicAdd(I.cnt + par, 1u);
+    __syncthreads();
+    const bool second = (s_arrive & 1u) != 0;
+    __syncthreads();
+    if (!second) return;
+    t = par;
+    NodeStep<T, KQ> st;
+    st.load(I, t, w, lane);
+    const NodeInfo n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
+    const int kv1 = st.kv1, kk = st.kk;
     for (int c0 = 0; c0 < nrhs; c0 += MC) {
       const int nc = min(MC, nrhs - c0);
       if (kk > 0) {
@@ -258,32 +347,14 @@ __global__ __launch_bounds__(kUT) void k_mmf_up(KArgs<T, CallMM<T>> a) {
         }
       }
       __syncthreads();
-      if (bw) {
-        for (int c = 0; c < nc; ++c) {
-          const T* x = xs + bx + c * kMaxBlock;
-          T acc = T(0);
-#pragma unroll
-          for (int k = 0; k < KQ; ++k) acc += cf[k] * x[min(k, max(bK - 1, 0))];
-          if (lane < bM) bout[lane + (int64_t)(c0 + c) * ldm] = acc;
-        }
-      } else if (ni > 0) {
-        for (int c = 0; c < nc; ++c) {
-          const T xa = xs[min(lane, kk - 1) + c * kMaxBlock];
-          const T xb = xs[min(lane + 64, kk - 1) + c * kMaxBlock];
-#pragma unroll
-          for (int q = 0; q < KQ / 2; ++q) {
-            if (q < ni) {
-              const T sum = wave_sum(cf[q] * xa + cf[KQ / 2 + q] * xb);
-              if (lane == 0) os[i0 + q + c * kMaxRank] = sum;
-            }
-          }
-        }
-      }
+      st.apply(I, w, lane, c0, nc, xs, os);
       __syncthreads();
-      if (t > 0 && w == 0)
+      if (t > 0 && w == 0) {
+        const NodeInfo nt = I.nodes[t];
         for (int o = lane; o < nt.kv * nc; o += 64)
           xh_put(I.xh + nt.oxh + o % nt.kv + (int64_t)(c0 + o / nt.kv) * ldm,
                  os[o % nt.kv + (o / nt.kv) * kMaxRank]);
+      }
       __syncthreads();
     }
   }
@@ -543,30 +614,28 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
                 int max_k, hipStream_t s) {
   if (nblocks <= 0 || nrhs <= 0) return;
   const bool batch = a.tasks != nullptr;
-  // right-hand-side chunk of the up and leaf kernels: 1, 8 or 32 columns
+  // right-hand-side chunk of the leaf kernel: 1, 8 or 32 columns; of the up
+  // kernel: 1 or 8
   const int mc = nrhs == 1 ? 1 : (nrhs <= 8 ? 8 : 32);
   const int ytiles = (nrhs + mc - 1) / mc;
   const int ncw = nrhs < mc ? nrhs : mc;
+  const int mcu = nrhs == 1 ? 1 : 8;
+  const int ncu = nrhs < mcu ? nrhs : mcu;
   const bool wide = max_k > 32;
   static const char* n64[] = {"mmf_up_f64", "mmf_down_f64", "mmf_leaf_f64"};
   static const char* n32[] = {"mmf_up_f32", "mmf_down_f32", "mmf_leaf_f32"};
   TimedLaunch tl((sizeof(T) == 8 ? n64 : n32)[(int)step], s);
-#define HSS_MMF(K, G, B, SM)                                              \
-  if (batch) hipLaunchKernelGGL((K<T, true>), G, B, SM, s, a);            \
-  else hipLaunchKernelGGL((K<T, false>), G, B, SM, s, a);
-#define HSS_MMF_UP(MC, NV)                                                                     \
-  if (batch) hipLaunchKernelGGL((k_mmf_up<T, true, MC, NV, 4 * NV>), dim3(nblocks), dim3(kUT), sm, \
-                                s, a);                                                         \
-  else hipLaunchKernelGGL((k_mmf_up<T, false, MC, NV, 4 * NV>), dim3(nblocks), dim3(kUT), sm, s, a);
+#define HSS_MMF_UP(MC, KQ)                                                                   \
+  if (batch) hipLaunchKernelGGL((k_mmf_up<T, true, MC, KQ>), dim3(nblocks), dim3(kUT), sm, s, a); \
+  else hipLaunchKernelGGL((k_mmf_up<T, false, MC, KQ>), dim3(nblocks), dim3(kUT), sm, s, a);
 #define HSS_MMF_LEAF(NU, MC)                                                              \
   if (batch) hipLaunchKernelGGL((k_mmf_leaf<T, true, NU, MC>), g, b, sm, s, a);          \
   else hipLaunchKernelGGL((k_mmf_leaf<T, false, NU, MC>), g, b, sm, s, a);
   switch (step) {
     case MMFStep::Up: {
-      const size_t sm = (size_t)(kMaxBlock + kMaxRank) * ncw * sizeof(T);
-      if (mc == 1) { if (wide) { HSS_MMF_UP(1, 16) } else { HSS_MMF_UP(1, 8) } }
-      else if (mc == 8) { if (wide) { HSS_MMF_UP(8, 16) } else { HSS_MMF_UP(8, 8) } }
-      else { if (wide) { HSS_MMF_UP(32, 16) } else { HSS_MMF_UP(32, 8) } }
+      const size_t sm = (size_t)(kMaxBlock + 2 * (1 << kUpH) * kMaxRank) * ncu * sizeof(T);
+      if (mcu == 1) { if (wide) { HSS_MMF_UP(1, 64) } else { HSS_MMF_UP(1, 32) } }
+      else { if (wide) { HSS_MMF_UP(8, 64) } else { HSS_MMF_UP(8, 32) } }
       break;
     }
     case MMFStep::Down: {
@@ -594,9 +663,11 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
 #undef HSS_MMF_UP
 #undef HSS_MMF_LEAF
 #undef HSS_MMF
+#undef HSS_MMF
 }
 
 int mmf_down_height() { return kDnH; }
+int mmf_up_height() { return kUpH; }
 
 template void launch_mmf<double>(MMFStep, const KArgs<double, CallMM<double>>&, int, int, int,
                                  int, hipStream_t);
