@@ -401,7 +401,7 @@ def bench_serve(args):
         m.norm2()
     torch.cuda.synchronize()
     log(f"[bench-serve] factored in {time.perf_counter() - t0:.2f} s")
-    pools = serve.rhs_pools(mats)
+    pools = serve.rhs_pools(mats, device=True)   # request blocks resident in HBM
     warm = serve.poisson_requests(args.serve_rate, 0.2, len(mats), seed=40)
     serve.run_stream(mats, warm, budget_bytes=24 << 30, workers=2, pools=pools)
     reqs = serve.poisson_requests(args.serve_rate, args.serve_seconds, len(mats), seed=41)
@@ -417,7 +417,7 @@ def bench_serve(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64ir", "data": "synthetic",
            "config": {"workload": f"Poisson {args.serve_rate:.0f} req/s for {args.serve_seconds} s, "
                                   "16 resident matrices n log-uniform [4096, 2^20], k in {16,32,64}, "
-                                  "leaf 128, tol 1e-6 / 1e-10, 1-16 rhs"},
+                                  "leaf 128, tol 1e-6 / 1e-10, 1-16 rhs, request blocks in HBM"},
            "latency": lat, "rhs_columns_per_s": round(cols / wall, 1),
            "all_within_tol": good, "rounds": srv.rounds,
            "mean_requests_per_round": round(float(np.mean(srv.round_sizes)), 2),

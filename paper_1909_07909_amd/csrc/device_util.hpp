@@ -91,6 +91,22 @@ __device__ __forceinline__ void wg_stage(int M, int N, F f, S store) {
   }
 }
 
+// Maximum / minimum over the 64 lanes (same DPP pattern as wave_sum).
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+  v = max(v, dpp<kDppQuadXor1>(v));
+  v = max(v, dpp<kDppQuadXor2>(v));
+  v = max(v, dpp<kDppRowRor4>(v));
+  v = max(v, dpp<kDppRowRor8>(v));
+  v = max(v, dpp<kDppRowBcast15, 0xA>(v));
+  v = max(v, dpp<kDppRowBcast31, 0x8>(v));
+  return lane_read(v, 63);
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+  return -wave_max(-v);
+}
+
 // Resolve (instance, call, node) of this work-group.
 template <bool BATCH, typename T, typename Call>
 __device__ __forceinline__ void resolve(const KArgs<T, Call>& a, Inst<T>& I, Call& C, int& node) {

@@ -264,19 +264,19 @@ void run_factor(hss_handle* h, hipStream_t s) {
   const int p = P.p;
   if (p == 0) {
     a.node0 = 0;
-    launch_ulv<T>(UlvStep::RootLU, a, 1, 1, P.max_mp, s);
+    launch_ulv<T>(UlvStep::RootLU, a, 1, P.max_k, P.max_mp, s);
     return;
   }
   a.node0 = level_first(p);
-  launch_ulv<T>(UlvStep::Factor, a, 1 << p, 1, P.level_max_mp[p], s);
+  launch_ulv<T>(UlvStep::Factor, a, 1 << p, P.max_k, P.level_max_mp[p], s);
   for (int l = p - 1; l >= 1; --l) {
     a.node0 = level_first(l);
-    launch_ulv<T>(UlvStep::Merge, a, 1 << l, 1, P.level_max_mp[l], s);
-    launch_ulv<T>(UlvStep::Factor, a, 1 << l, 1, P.level_max_mp[l], s);
+    launch_ulv<T>(UlvStep::Merge, a, 1 << l, P.max_k, P.level_max_mp[l], s);
+    launch_ulv<T>(UlvStep::Factor, a, 1 << l, P.max_k, P.level_max_mp[l], s);
   }
   a.node0 = 0;
-  launch_ulv<T>(UlvStep::Merge, a, 1, 1, P.max_mp, s);
-  launch_ulv<T>(UlvStep::RootLU, a, 1, 1, P.max_mp, s);
+  launch_ulv<T>(UlvStep::Merge, a, 1, P.max_k, P.nodes[0].mp, s);
+  launch_ulv<T>(UlvStep::RootLU, a, 1, P.max_k, P.nodes[0].mp, s);
 }
 
 // LDS bytes a work-group may use for staged copies of one node's factors.
@@ -601,6 +601,8 @@ hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
   hss_status st = scratch_upload(BS, pk.buf, s, &d);
   if (st) return st;
   for (int j = 0; j < count; ++j) launch_fill(reinterpret_cast<double*>(hs[j]->d_status), 0.0, 2, s);
+  int mk = 0;
+  for (int j = 0; j < count; ++j) mk = std::max(mk, hs[j]->plan.max_k);
   KArgs<T, CallSV<T>> a{};
   a.insts = reinterpret_cast<const Inst<T>*>((char*)d + oi);
   size_t k = 0;
@@ -612,20 +614,20 @@ hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
   };
   {
     const auto& r = rng();
-    launch_ulv<T>(UlvStep::Factor, a, r.cnt, 1, r.max_mp, s);
+    launch_ulv<T>(UlvStep::Factor, a, r.cnt, mk, r.max_mp, s);
   }
   for (int q = 1; q <= pmax - 1; ++q) {
     const auto& r = rng();
-    launch_ulv<T>(UlvStep::Merge, a, r.cnt, 1, r.max_mp, s);
-    launch_ulv<T>(UlvStep::Factor, a, r.cnt, 1, r.max_mp, s);
+    launch_ulv<T>(UlvStep::Merge, a, r.cnt, mk, r.max_mp, s);
+    launch_ulv<T>(UlvStep::Factor, a, r.cnt, mk, r.max_mp, s);
   }
   {
     const auto& r = rng();
-    launch_ulv<T>(UlvStep::Merge, a, r.cnt, 1, r.max_mp, s);
+    launch_ulv<T>(UlvStep::Merge, a, r.cnt, mk, r.max_mp, s);
   }
   {
     const auto& r = rng();
-    launch_ulv<T>(UlvStep::RootLU, a, r.cnt, 1, r.max_mp, s);
+    launch_ulv<T>(UlvStep::RootLU, a, r.cnt, mk, r.max_mp, s);
   }
   for (int j = 0; j < count; ++j) (sizeof(T) == 8 ? hs[j]->f64.valid : hs[j]->f32.valid) = true;
   return last_launch_status();

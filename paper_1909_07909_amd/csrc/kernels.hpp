@@ -38,8 +38,9 @@ template <typename T>
 void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int ncols,
                     int64_t stage_elems, hipStream_t s);
 
+// max_k: the largest rank of the nodes involved; max_mp: the largest block.
 template <typename T>
-void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int ytiles,
+void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max_k,
                 int max_mp, hipStream_t s);
 
 // Elementwise / reduction helpers (kernels_util.hip).

@@ -21,11 +21,27 @@ namespace hss {
 
 constexpr int kFNT = 512;   // 256 owner slots x 2 halves
 
+// reg <- reg - tau (v . reg_pair) v on the half vector this lane holds; the
+// dot product of the lane pair is combined with one lane exchange and runs on
+// four independent partial sums (a single chain of dependent FMAs would leave
+// the VALU waiting on its own latency).
+template <typename T, int COLS>
+__device__ __forceinline__ void apply_reflector(const T* v, T (&reg)[COLS], T tau) {
+  T p[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int j = 0; j < COLS; ++j) p[j & 3] += v[j] * reg[j];
+  T w = (p[0] + p[1]) + (p[2] + p[3]);
+  w += xor1(w);
+  w *= tau;
+#pragma unroll
+  for (int j = 0; j < COLS; ++j) reg[j] -= w * v[j];
+}
+
 template <typename T, int MAXC, bool BATCH>
 __global__ __launch_bounds__(kFNT) void k_ulv_factor_reg(KArgs<T, CallSV<T>> a) {
   constexpr int COLS = MAXC / 2;
   constexpr int VB = MAXC + 8;
-  HIP_DYNAMIC_SHARED(char, smem_raw)
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];   // 16-byte aligned: vector LDS reads
   T* smem = reinterpret_cast<T*>(smem_raw);
   Inst<T> I; CallSV<T> C; int node;
   resolve<BATCH>(a, I, C, node);
@@ -60,10 +76,15 @@ __global__ __launch_bounds__(kFNT) void k_ulv_factor_reg(KArgs<T, CallSV<T>> a) 
     // clamped addresses, unconditional loads (all in flight together), masks after
     const T* src = isD ? Dsrc + (int64_t)c * mp : (isU ? Usrc + (int64_t)(c - mp) * mp : Dsrc);
     const bool any = isD | isU;
+    if (base + COLS <= mp) {   // whole half in range: constant offsets from one address
 #pragma unroll
-    for (int j = 0; j < COLS; ++j) {
-      const int r = base + j;
-      reg[j] = ld_or0(src + min(r, mp - 1), any & (r < mp));
+      for (int j = 0; j < COLS; ++j) reg[j] = ld_or0(src + base + j, any);
+    } else {
+#pragma unroll
+      for (int j = 0; j < COLS; ++j) {
+        const int r = base + j;
+        reg[j] = ld_or0(src + min(r, mp - 1), any & (r < mp));
+      }
     }
   }
   if (e > 0) {
@@ -96,15 +117,7 @@ __global__ __launch_bounds__(kFNT) void k_ulv_factor_reg(KArgs<T, CallSV<T>> a) 
       }
       __syncthreads();
       const T tau = vb[MAXC];
-      if (tau != T(0) && (isD || (c >= mp && c < owner))) {
-        T w = 0;
-#pragma unroll
-        for (int j = 0; j < COLS; ++j) w += vb[base + j] * reg[j];
-        w += xor1(w);
-        w *= tau;
-#pragma unroll
-        for (int j = 0; j < COLS; ++j) reg[j] -= w * vb[base + j];
-      }
+      if (tau != T(0) && (isD || (c >= mp && c < owner))) apply_reflector<T, COLS>(vb + base, reg, tau);
     }
     __syncthreads();
     for (int o = tid; o < mp * ku; o += kFNT) FU[o] = Ms[o];
@@ -136,10 +149,15 @@ __global__ __launch_bounds__(kFNT) void k_ulv_factor_reg(KArgs<T, CallSV<T>> a) 
     }
   } else {
     const T* src = Vsrc + (int64_t)(isV ? r - mp : 0) * mp;
+    if (base + COLS <= mp) {
 #pragma unroll
-    for (int j = 0; j < COLS; ++j) {
-      const int cc = base + j;
-      reg[j] = ld_or0(src + min(cc, mp - 1), isV & (cc < mp));
+      for (int j = 0; j < COLS; ++j) reg[j] = ld_or0(src + base + j, isV);
+    } else {
+#pragma unroll
+      for (int j = 0; j < COLS; ++j) {
+        const int cc = base + j;
+        reg[j] = ld_or0(src + min(cc, mp - 1), isV & (cc < mp));
+      }
     }
   }
   __syncthreads();   // Ms now parks the finished rows 0..e-1
@@ -172,15 +190,7 @@ __global__ __launch_bounds__(kFNT) void k_ulv_factor_reg(KArgs<T, CallSV<T>> a) 
     }
     __syncthreads();
     const T tau = vb[MAXC];
-    if (tau != T(0) && r > i && (isM || isV)) {
-      T w = 0;
-#pragma unroll
-      for (int j = 0; j < COLS; ++j) w += vb[base + j] * reg[j];
-      w += xor1(w);
-      w *= tau;
-#pragma unroll
-      for (int j = 0; j < COLS; ++j) reg[j] -= w * vb[base + j];
-    }
+    if (tau != T(0) && r > i && (isM || isV)) apply_reflector<T, COLS>(vb + base, reg, tau);
   }
   __syncthreads();
   if (tid < e) I.tz[nd.otz + tid] = taus[kMaxRank + tid];

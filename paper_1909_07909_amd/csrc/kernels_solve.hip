@@ -129,7 +129,53 @@ __device__ __forceinline__ T* stage_block(T* dst, int rows, int cols, F f) {
   return dst + rows * cols;
 }
 
-// Copies of everything the forward sweep of an internal node reads, in LDS.
+// A block copied to LDS: element (i, j) of a rows x cols block is src[i + j*ld]
+// (zero above the diagonal when upper_zero) and lands at dst[i + j*rows].
+template <typename T>
+struct SBlk {
+  const T* src;
+  int ld, rows, cols;
+  bool upper_zero;
+  T* dst;
+};
+
+// Copy NB blocks to LDS: the block table goes through LDS, wavefront w copies
+// blocks w, w + nw, ... with 16 reads in flight per lane (compact code: the
+// sweeps of the upper levels are short, and their instructions are fetched
+// afresh by every launch).
+template <typename T, int NB>
+__device__ __forceinline__ void stage_blocks(const SBlk<T> (&b)[NB], SBlk<T>* tab) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) tab[q] = b[q];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll 1
+  for (int q = w; q < NB; q += nw) {
+    const SBlk<T> B = tab[q];
+    const int total = B.rows * B.cols;
+#pragma unroll 1
+    for (int o0 = 0; o0 < total; o0 += 16 * 64) {
+      T v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int o = min(o0 + lane + 64 * u, total - 1);
+        const int i = o % B.rows, c = o / B.rows;
+        const T x = B.src[i + (int64_t)c * B.ld];
+        v[u] = (B.upper_zero & (i < c)) ? T(0) : x;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int o = o0 + lane + 64 * u;
+        if (o < total) B.dst[o] = v[u];
+      }
+    }
+  }
+}
+
+// Copies of everything the forward sweep of an internal node reads, in LDS,
+// staged in one pass (all reads in flight together).
 template <typename T>
 __device__ NodeSrc<T> src_stage_fwd(const Inst<T>& I, const NodeInfo& nd, int node, T* sm) {
   const NodeSrc<T> G = src_global(I, nd, node);
@@ -137,22 +183,20 @@ __device__ NodeSrc<T> src_stage_fwd(const Inst<T>& I, const NodeInfo& nd, int no
   const int mp = nd.mp, e = nd.e, ku = nd.ku, kv = nd.kv, kw = n1.kv + n2.kv;
   NodeSrc<T> S = G;
   T* p = sm;
-  S.U = p; S.ldu = mp;
-  p = stage_block(p, mp, e > 0 ? ku : 0, [&](int i, int j) { return G.U[i + j * mp]; });
-  S.L = p; S.ldl = mp;
-  p = stage_block(p, mp, e, [&](int i, int j) { return G.L[i + j * mp]; });
-  S.V = p; S.ldv = e;
-  p = stage_block(p, e, kv, [&](int i, int j) { return G.V[i + j * mp]; });
-  S.W = p; S.ldw = kw;
-  p = stage_block(p, kw, kv, [&](int i, int j) { return G.W[i + j * kw]; });
+  SBlk<T> b[8];
+  const int kq = e > 0 ? ku : 0;
+  S.U = p; S.ldu = mp;         b[0] = {G.U, mp, mp, kq, false, p}; p += mp * kq;
+  S.L = p; S.ldl = mp;         b[1] = {G.L, mp, mp, e, false, p}; p += mp * e;
+  S.V = p; S.ldv = e;          b[2] = {G.V, mp, e, kv, false, p}; p += e * kv;
+  S.W = p; S.ldw = kw;         b[3] = {G.W, kw, kw, kv, false, p}; p += kw * kv;
   S.U1 = p; S.ldu1 = n1.kept; S.m1 = false;
-  p = stage_block(p, n1.kept, n1.ku, [&](int i, int j) { return ut(G.U1, G.ldu1, G.m1, i, j); });
+  b[4] = {G.U1, G.ldu1, n1.kept, n1.ku, G.m1, p}; p += n1.kept * n1.ku;
   S.U2 = p; S.ldu2 = n2.kept; S.m2 = false;
-  p = stage_block(p, n2.kept, n2.ku, [&](int i, int j) { return ut(G.U2, G.ldu2, G.m2, i, j); });
-  S.B12 = p; S.ld12 = n1.ku;
-  p = stage_block(p, n1.ku, n2.kv, [&](int i, int j) { return G.B12[i + j * n1.ku]; });
-  S.B21 = p; S.ld21 = n2.ku;
-  p = stage_block(p, n2.ku, n1.kv, [&](int i, int j) { return G.B21[i + j * n2.ku]; });
+  b[5] = {G.U2, G.ldu2, n2.kept, n2.ku, G.m2, p}; p += n2.kept * n2.ku;
+  S.B12 = p; S.ld12 = n1.ku;   b[6] = {G.B12, n1.ku, n1.ku, n2.kv, false, p}; p += n1.ku * n2.kv;
+  S.B21 = p; S.ld21 = n2.ku;   b[7] = {G.B21, n2.ku, n2.ku, n1.kv, false, p};
+  __shared__ SBlk<T> tab[8];
+  stage_blocks<T, 8>(b, tab);
   return S;   // the caller synchronizes the work-group
 }
 
@@ -182,21 +226,21 @@ __device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, int node, 
     t1[c] = T(0);
     t2[c] = T(0);
   }
-#pragma unroll 4
+#pragma unroll 1
   for (int y = 0; y < (n1.ku > 0 ? n2.kv : 0); ++y) {
     const T bv = S.B12[max(min(lane, n1.ku - 1), 0) + y * S.ld12];
     const T b = lane < n1.ku ? bv : T(0);
 #pragma unroll
     for (int c = 0; c < CPW; ++c) t1[c] += b * bcast(z2l[c], y);
   }
-#pragma unroll 4
+#pragma unroll 1
   for (int y = 0; y < (n2.ku > 0 ? n1.kv : 0); ++y) {
     const T bv = S.B21[max(min(lane, n2.ku - 1), 0) + y * S.ld21];
     const T b = lane < n2.ku ? bv : T(0);
 #pragma unroll
     for (int c = 0; c < CPW; ++c) t2[c] += b * bcast(z1l[c], y);
   }
-#pragma unroll 4
+#pragma unroll 1
   for (int x = 0; x < n1.ku; ++x) {
     const T a0 = ut(S.U1, S.ldu1, S.m1, min(r0, k1 - 1), x);
     const T a1 = ut(S.U1, S.ldu1, S.m1, min(r1, k1 - 1), x);
@@ -209,7 +253,7 @@ __device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, int node, 
       x1[c] -= u1 * tx;
     }
   }
-#pragma unroll 4
+#pragma unroll 1
   for (int x = 0; x < n2.ku; ++x) {
     const int k2 = mp - k1;
     const T a0 = ut(S.U2, S.ldu2, S.m2, min(max(r0 - k1, 0), k2 - 1), x);
@@ -284,7 +328,9 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
   }
   if (e > 0) {
     // b~ = Q^T rhs = H_0 ... H_{ku-1} rhs, H_{ku-1} applied first (lane j holds tau_j)
-#pragma unroll 8
+    // (deep unrolling for the leaf level, which reads its factors from memory;
+    // compact loops for the staged upper levels)
+#pragma unroll(STAGED ? 1 : 8)
     for (int j = ku - 1; j >= 0; --j) {
       const T tau = bcast(taul, j);
       const int pr = e + j;
@@ -300,7 +346,7 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
       }
     }
     // y = L^{-1} b~_top; the same column sweep leaves b~_bot - D~21 y below
-#pragma unroll 16
+#pragma unroll(STAGED ? 1 : 16)
     for (int i = 0; i < e; ++i) {
       const T* Li = S.L + i * S.ldl;
       const T a0 = Li[min(r0, mp - 1)], a1 = Li[min(r1, mp - 1)];
@@ -353,7 +399,7 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
     T zr[CPW];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) zr[c] = T(0);
-#pragma unroll 8
+#pragma unroll(STAGED ? 1 : 8)
     for (int aa = 0; aa < kv; ++aa) {
       const T* Va = S.V + aa * S.ldv;
       const int ec = max(e - 1, 0);

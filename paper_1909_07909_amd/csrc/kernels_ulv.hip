@@ -150,6 +150,174 @@ __global__ __launch_bounds__(kNT) void k_ulv_merge(KArgs<T, CallSV<T>> a) {
                      [&](int i, int j, T v) { FV[k1 + i + (int64_t)j * mp] = v; });
 }
 
+// The merge with every input staged in LDS in one pass (all loads in flight
+// together), then two product phases.  For blocks of at most kMB elements.
+constexpr int kMB = 2048;
+constexpr int kMU = kMB / kNT;   // elements per thread and block
+
+template <typename T, typename F>
+__device__ __forceinline__ void blk_load(T (&v)[kMU], int M, int N, F f) {
+#pragma unroll
+  for (int u = 0; u < kMU; ++u) {
+    const int o = min((int)threadIdx.x + u * kNT, max(M * N - 1, 0));
+    v[u] = M * N > 0 ? f(o % M, o / M) : T(0);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void blk_store(const T (&v)[kMU], int M, int N, T* dst) {
+#pragma unroll
+  for (int u = 0; u < kMU; ++u) {
+    const int o = threadIdx.x + u * kNT;
+    if (o < M * N) dst[o % M + (o / M) * (M + 1)] = v[u];
+  }
+}
+// C(i, j) = sum_l A(i, l) B(l, j) (TB: B(l, j) = B[j + l*ldb]) over LDS blocks.
+template <typename T, bool TB>
+__device__ __forceinline__ T lds_dot(const T* A, int lda, const T* B, int ldb, int i, int j,
+                                     int K) {
+  T s = T(0);
+  for (int l = 0; l < K; ++l) s += A[i + l * lda] * (TB ? B[j + l * ldb] : B[l + j * ldb]);
+  return s;
+}
+
+// 2 x 2 tile of C = A B at (i0, j0), A(i, l) = A[i + l*lda], B(l, j) = B[l + j*ldb]
+// (TB: B[j + l*ldb]); out(i, j, value) for the in-range entries.
+template <typename T, bool TB, typename Out>
+__device__ __forceinline__ void tile22(const T* A, int lda, const T* B, int ldb, int M, int N,
+                                       int K, int i0, int j0, Out out) {
+  const int i1 = min(i0 + 1, M - 1), j1 = min(j0 + 1, N - 1);
+  T c00 = T(0), c01 = T(0), c10 = T(0), c11 = T(0);
+#pragma unroll 4
+  for (int l = 0; l < K; ++l) {
+    const T a0 = A[i0 + l * lda], a1 = A[i1 + l * lda];
+    const T b0 = TB ? B[j0 + l * ldb] : B[l + j0 * ldb];
+    const T b1 = TB ? B[j1 + l * ldb] : B[l + j1 * ldb];
+    c00 += a0 * b0; c01 += a0 * b1; c10 += a1 * b0; c11 += a1 * b1;
+  }
+  out(i0, j0, c00);
+  if (j0 + 1 < N) out(i0, j0 + 1, c01);
+  if (i0 + 1 < M) out(i0 + 1, j0, c10);
+  if (i0 + 1 < M && j0 + 1 < N) out(i0 + 1, j0 + 1, c11);
+}
+// number of 2 x 2 tiles of an M x N product
+__device__ __forceinline__ int ntiles(int M, int N) { return ((M + 1) >> 1) * ((N + 1) >> 1); }
+
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_ulv_merge1(KArgs<T, CallSV<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  Inst<T> I; CallSV<T> C; int node;
+  resolve<BATCH>(a, I, C, node);
+  const NodeInfo nd = I.nodes[node];
+  const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+  const int k1 = n1.kept, k2 = n2.kept, mp = nd.mp;
+  const int ku1 = n1.ku, ku2 = n2.ku, kv1 = n1.kv, kv2 = n2.kv;
+  const int kr = ku1 + ku2, kw = kv1 + kv2;
+  const bool top = node != 0;   // U', V' below the root
+  const int ku = top ? nd.ku : 0, kv = top ? nd.kv : 0;
+  const T* FD1 = I.FD + n1.oFD; const T* FD2 = I.FD + n2.oFD;
+  const T* FU1 = I.FU + n1.oFU; const T* FU2 = I.FU + n2.oFU;
+  const T* FV1 = I.FV + n1.oFV; const T* FV2 = I.FV + n2.oFV;
+  const T* B12 = I.B12 + nd.oB12;
+  const T* B21 = I.B21 + nd.oB21;
+  const T* R = I.R + (top ? nd.oR : 0);
+  const T* W = I.W + (top ? nd.oW : 0);
+  T* FD = I.FD + nd.oFD;
+  // LDS blocks (leading dimension rows + 1)
+  T* sB12 = sm;                         T* sB21 = sB12 + (ku1 + 1) * kv2;
+  T* sV1 = sB21 + (ku2 + 1) * kv1;      T* sV2 = sV1 + (k1 + 1) * kv1;
+  T* sU1 = sV2 + (k2 + 1) * kv2;        T* sU2 = sU1 + (k1 + 1) * ku1;
+  T* sR = sU2 + (k2 + 1) * ku2;         T* sW = sR + (kr + 1) * ku;
+  T* sC12 = sW + (kw + 1) * kv;         T* sC21 = sC12 + (ku1 + 1) * k2;
+  {
+    T v0[kMU], v1[kMU], v2[kMU], v3[kMU], v4[kMU], v5[kMU], v6[kMU], v7[kMU], v8[kMU], v9[kMU];
+    blk_load(v0, ku1, kv2, [&](int i, int j) { return B12[i + (int64_t)j * ku1]; });
+    blk_load(v1, ku2, kv1, [&](int i, int j) { return B21[i + (int64_t)j * ku2]; });
+    blk_load(v2, k1, kv1, [&](int i, int j) { return FV1[n1.e + i + (int64_t)j * n1.mp]; });
+    blk_load(v3, k2, kv2, [&](int i, int j) { return FV2[n2.e + i + (int64_t)j * n2.mp]; });
+    blk_load(v4, k1, ku1, [&](int i, int j) {
+      const T x = FU1[n1.e + i + (int64_t)j * n1.mp];
+      return ((n1.e > 0) & (i < j)) ? T(0) : x;
+    });
+    blk_load(v5, k2, ku2, [&](int i, int j) {
+      const T x = FU2[n2.e + i + (int64_t)j * n2.mp];
+      return ((n2.e > 0) & (i < j)) ? T(0) : x;
+    });
+    blk_load(v6, kr, ku, [&](int i, int j) { return R[i + (int64_t)j * kr]; });
+    blk_load(v7, kw, kv, [&](int i, int j) { return W[i + (int64_t)j * kw]; });
+    // diagonal blocks D~22 of the children, copied through registers
+    blk_load(v8, k1, k1, [&](int i, int j) { return FD1[n1.e + i + (int64_t)(n1.e + j) * n1.mp]; });
+    blk_load(v9, k2, k2, [&](int i, int j) { return FD2[n2.e + i + (int64_t)(n2.e + j) * n2.mp]; });
+    blk_store(v0, ku1, kv2, sB12);
+    blk_store(v1, ku2, kv1, sB21);
+    blk_store(v2, k1, kv1, sV1);
+    blk_store(v3, k2, kv2, sV2);
+    blk_store(v4, k1, ku1, sU1);
+    blk_store(v5, k2, ku2, sU2);
+    blk_store(v6, kr, ku, sR);
+    blk_store(v7, kw, kv, sW);
+#pragma unroll
+    for (int u = 0; u < kMU; ++u) {
+      const int o = threadIdx.x + u * kNT;
+      if (o < k1 * k1) FD[o % k1 + (int64_t)(o / k1) * mp] = v8[u];
+      if (o < k2 * k2) FD[k1 + o % k2 + (int64_t)(k1 + o / k2) * mp] = v9[u];
+    }
+  }
+  __syncthreads();
+  // phase 1 (2 x 2 tiles): C12 = B12 V^b_c2^T, C21 = B21 V^b_c1^T,
+  //   U' = blkdiag(U~_c1, U~_c2) R_t, V' = blkdiag(V^b_c1, V^b_c2) W_t
+  {
+    T* FU = I.FU + nd.oFU;
+    T* FV = I.FV + nd.oFV;
+    const int t0 = ntiles(ku1, k2), t1 = t0 + ntiles(ku2, k1);
+    const int t2 = t1 + ntiles(k1, ku), t3 = t2 + ntiles(k2, ku);
+    const int t4 = t3 + ntiles(k1, kv), t5 = t4 + ntiles(k2, kv);
+    for (int o = threadIdx.x; o < t5; o += kNT) {
+      if (o < t0) {
+        const int nr = (ku1 + 1) >> 1;
+        tile22<T, true>(sB12, ku1 + 1, sV2, k2 + 1, ku1, k2, kv2, 2 * (o % nr), 2 * (o / nr),
+                        [&](int i, int j, T v) { sC12[i + j * (ku1 + 1)] = v; });
+      } else if (o < t1) {
+        const int q = o - t0, nr = (ku2 + 1) >> 1;
+        tile22<T, true>(sB21, ku2 + 1, sV1, k1 + 1, ku2, k1, kv1, 2 * (q % nr), 2 * (q / nr),
+                        [&](int i, int j, T v) { sC21[i + j * (ku2 + 1)] = v; });
+      } else if (o < t2) {
+        const int q = o - t1, nr = (k1 + 1) >> 1;
+        tile22<T, false>(sU1, k1 + 1, sR, kr + 1, k1, ku, ku1, 2 * (q % nr), 2 * (q / nr),
+                         [&](int i, int j, T v) { FU[i + (int64_t)j * mp] = v; });
+      } else if (o < t3) {
+        const int q = o - t2, nr = (k2 + 1) >> 1;
+        tile22<T, false>(sU2, k2 + 1, sR + ku1, kr + 1, k2, ku, ku2, 2 * (q % nr), 2 * (q / nr),
+                         [&](int i, int j, T v) { FU[k1 + i + (int64_t)j * mp] = v; });
+      } else if (o < t4) {
+        const int q = o - t3, nr = (k1 + 1) >> 1;
+        tile22<T, false>(sV1, k1 + 1, sW, kw + 1, k1, kv, kv1, 2 * (q % nr), 2 * (q / nr),
+                         [&](int i, int j, T v) { FV[i + (int64_t)j * mp] = v; });
+      } else {
+        const int q = o - t4, nr = (k2 + 1) >> 1;
+        tile22<T, false>(sV2, k2 + 1, sW + kv1, kw + 1, k2, kv, kv2, 2 * (q % nr), 2 * (q / nr),
+                         [&](int i, int j, T v) { FV[k1 + i + (int64_t)j * mp] = v; });
+      }
+    }
+  }
+  __syncthreads();
+  // phase 2: D'(c1, c2) = U~_c1 C12, D'(c2, c1) = U~_c2 C21
+  {
+    const int t0 = ntiles(k1, k2), t1 = t0 + ntiles(k2, k1);
+    for (int o = threadIdx.x; o < t1; o += kNT) {
+      if (o < t0) {
+        const int nr = (k1 + 1) >> 1;
+        tile22<T, false>(sU1, k1 + 1, sC12, ku1 + 1, k1, k2, ku1, 2 * (o % nr), 2 * (o / nr),
+                         [&](int i, int j, T v) { FD[i + (int64_t)(k1 + j) * mp] = v; });
+      } else {
+        const int q = o - t0, nr = (k2 + 1) >> 1;
+        tile22<T, false>(sU2, k2 + 1, sC21, ku2 + 1, k2, k1, ku2, 2 * (q % nr), 2 * (q / nr),
+                         [&](int i, int j, T v) { FD[k1 + i + (int64_t)j * mp] = v; });
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Root: LU with partial pivoting (FP64) of D'_root (or of D when p = 0).
 // ---------------------------------------------------------------------------
@@ -209,9 +377,78 @@ __global__ __launch_bounds__(kNT) void k_ulv_root_lu(KArgs<T, CallSV<T>> a) {
   for (int o = tid; o < mp * mp; o += nt) I.rootLU[o] = Ls[o % mp + (o / mp) * ld];
 }
 
+// The same factorization for mp <= 128, organised for short steps: the pivot
+// search by wavefront 0 (wavefront max, then the smallest row index among
+// equals), one reciprocal per column, and a rank-1 update in which thread t
+// owns column j+1 + t % 64 and every fourth row below the pivot; three
+// barriers per column.
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_ulv_root_lu2(KArgs<T, CallSV<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  double* Ls = reinterpret_cast<double*>(smem_raw);
+  __shared__ int s_piv;
+  __shared__ int s_sing;
+  Inst<T> I; CallSV<T> C; int node;
+  resolve<BATCH>(a, I, C, node);
+  const NodeInfo nd = I.nodes[node];
+  const int mp = nd.mp, ld = mp + 1;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const T* src = I.p == 0 ? I.D + nd.oD : I.FD + nd.oFD;
+  wg_stage<16, T>(mp, mp, [&](int i, int j) { return src[i + (int64_t)j * mp]; },
+                  [&](int i, int j, T v) { Ls[i + j * ld] = (double)v; });
+  if (tid == 0) s_sing = 0;
+  __syncthreads();
+  for (int j = 0; j < mp; ++j) {
+    if (w == 0) {
+      const int r0 = j + lane, r1 = j + 64 + lane;
+      const double v0 = r0 < mp ? fabs(Ls[r0 + j * ld]) : -1.0;
+      const double v1 = r1 < mp ? fabs(Ls[r1 + j * ld]) : -1.0;
+      const double mx = wave_max(max(v0, v1));
+      const double cand = v0 == mx ? (double)r0 : (v1 == mx ? (double)r1 : 1e9);
+      int p = (int)wave_min(cand);
+      if (!(mx > 0.0)) p = j;
+      if (lane == 0) {
+        s_piv = p;
+        I.piv[j] = p;
+        if (!(mx > 0.0)) s_sing = 1;
+      }
+    }
+    __syncthreads();
+    const int p = s_piv;
+    // swap rows j and p (columns tid), then scale the column below the pivot
+    if (p != j)
+      for (int c = tid; c < mp; c += kNT) {
+        const double t = Ls[j + c * ld];
+        Ls[j + c * ld] = Ls[p + c * ld];
+        Ls[p + c * ld] = t;
+      }
+    __syncthreads();
+    const double d = Ls[j + j * ld];
+    const double dinv = d != 0.0 ? 1.0 / d : 0.0;
+    for (int r = j + 1 + tid; r < mp; r += kNT) Ls[r + j * ld] *= dinv;
+    __syncthreads();
+    // rank-1 update of the trailing block
+    const int c = j + 1 + lane;
+    if (c < mp) {
+      const double u = Ls[j + c * ld];
+      for (int r = j + 1 + w; r < mp; r += kNT / 64) Ls[r + c * ld] -= Ls[r + j * ld] * u;
+    }
+    if (mp - j - 1 > 64) {   // columns beyond the first 64 of the trailing block
+      const int c2 = j + 65 + lane;
+      if (c2 < mp) {
+        const double u = Ls[j + c2 * ld];
+        for (int r = j + 1 + w; r < mp; r += kNT / 64) Ls[r + c2 * ld] -= Ls[r + j * ld] * u;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && s_sing) atomicOr(I.status, 1 << kStatusSingular);
+  for (int o = tid; o < mp * mp; o += kNT) I.rootLU[o] = Ls[o % mp + (o / mp) * ld];
+}
+
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int ytiles, int max_mp,
+void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max_k, int max_mp,
                 hipStream_t s) {
   if (nblocks <= 0) return;
   const bool batch = a.tasks != nullptr;
@@ -220,7 +457,11 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int yti
   dim3 grid(nblocks, 1);
   const size_t TB = sizeof(T);
   switch (step) {
-    case UlvStep::Merge: sm = (size_t)3 * kMaxRank * (kMaxRank + 1) * TB; break;
+    case UlvStep::Merge:
+      // one-pass merge while every block has at most kMB elements (ranks <= 32)
+      sm = (max_mp <= 64 && max_k <= 32) ? (size_t)(8 * 33 * 32 + 2 * 65 * 32) * TB
+                                         : (size_t)3 * kMaxRank * (kMaxRank + 1) * TB;
+      break;
     case UlvStep::Factor: break;
     case UlvStep::RootLU: sm = (size_t)max_mp * (max_mp + 1) * sizeof(double); break;
     default: break;
@@ -242,9 +483,15 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int yti
   if (batch) hipLaunchKernelGGL((K<T, true>), grid, block, sm, s, a);         \
   else hipLaunchKernelGGL((K<T, false>), grid, block, sm, s, a);
   switch (step) {
-    case UlvStep::Merge: HSS_LAUNCH(k_ulv_merge); break;
+    case UlvStep::Merge:
+      if (max_mp <= 64 && max_k <= 32) { HSS_LAUNCH(k_ulv_merge1); }
+      else { HSS_LAUNCH(k_ulv_merge); }
+      break;
     case UlvStep::Factor: launch_factor_reg<T>(a, nblocks, max_mp, s); break;
-    case UlvStep::RootLU: HSS_LAUNCH(k_ulv_root_lu); break;
+    case UlvStep::RootLU:
+      if (max_mp <= 128) { HSS_LAUNCH(k_ulv_root_lu2); }
+      else { HSS_LAUNCH(k_ulv_root_lu); }
+      break;
     default: break;
   }
 #undef HSS_LAUNCH

@@ -15,8 +15,9 @@ HIP stream each, repeatedly form a round from the admitted requests:
   class tolerance); requests that arrive meanwhile are admitted as memory frees
   and picked up by the next free worker, so rounds overlap on the device.
 
-Each completed request records its latency (arrival to result on the host)
-and the backward error of every column.  The GPU work is all in libhss.so;
+Each completed request records its latency (arrival to result: on the
+host for host requests, in device memory for device-resident requests) and
+the backward error of every column.  The GPU work is all in libhss.so;
 this module only schedules.
 """
 from __future__ import annotations
@@ -39,8 +40,8 @@ class Request:
     tol: float
     nrhs: int
     t_arrival: float
-    B: np.ndarray = field(repr=False, default=None)      # host, n x nrhs
-    X: np.ndarray = field(repr=False, default=None)      # host result
+    B: object = field(repr=False, default=None)   # n x nrhs: numpy (host) or device tensor
+    X: object = field(repr=False, default=None)   # result, same kind as B
     eta: np.ndarray = field(repr=False, default=None)
     iters: int = 0
     t_done: float = 0.0
@@ -105,11 +106,16 @@ def rhs_for(req: Request, n: int) -> np.ndarray:
     return inputs.rhs(n, req.nrhs, 10_000 + req.rid)
 
 
-def rhs_pools(mats, width: int = 32, seed: int = 77):
+def rhs_pools(mats, width: int = 32, seed: int = 77, device: bool = False):
     """One seeded n x width random block per matrix; a request takes a window
     of consecutive columns (so that long runs do not draw fresh normals for
-    every request)."""
-    return [inputs.rhs(m.n, width, seed + j) for j, m in enumerate(mats)]
+    every request).  device=True: the pools are column-major device tensors
+    (requests then carry device views, as from a client on the GPU)."""
+    pools = [inputs.rhs(m.n, width, seed + j) for j, m in enumerate(mats)]
+    if device:
+        import torch
+        pools = [torch.from_numpy(np.ascontiguousarray(P.T)).cuda().t() for P in pools]
+    return pools
 
 
 def rhs_from_pool(req: Request, pools) -> np.ndarray:
@@ -235,6 +241,11 @@ class Server:
                 self.cv.notify_all()
 
     def _run_round(self, groups, stream):
+        """One round: per tolerance class, pack each matrix's requests into one
+        column-major device block, run one batched solve over all of them, and
+        hand every request its columns.  Device-resident requests (torch
+        tensors) are packed with device copies and get views of the block as
+        results; host requests go through a pinned staging block."""
         torch = self.torch
         by_tol = {}
         for (m, t), reqs in groups.items():
@@ -245,9 +256,21 @@ class Server:
                 mats, blocks, splits = [], [], []
                 for m, reqs in items:
                     n = self.n[m]
-                    host = np.concatenate([r.B for r in reqs], axis=1)
-                    dev = torch.from_numpy(np.ascontiguousarray(host.T)).to(
-                        "cuda", non_blocking=False).t()
+                    cols = sum(r.nrhs for r in reqs)
+                    if all(isinstance(r.B, torch.Tensor) for r in reqs):
+                        dev = hss.empty_colmajor(n, cols, torch.float64)
+                        c = 0
+                        for r in reqs:
+                            dev[:, c:c + r.nrhs].copy_(r.B, non_blocking=True)
+                            c += r.nrhs
+                    else:
+                        host = torch.empty((cols, n), dtype=torch.float64, pin_memory=True)
+                        c = 0
+                        for r in reqs:
+                            Bh = r.B.cpu().numpy() if isinstance(r.B, torch.Tensor) else r.B
+                            host[c:c + r.nrhs].copy_(torch.from_numpy(np.ascontiguousarray(Bh.T)))
+                            c += r.nrhs
+                        dev = host.to("cuda", non_blocking=True).t()
                     mats.append(self.mats[m])
                     blocks.append(dev)
                     splits.append(reqs)
@@ -256,11 +279,17 @@ class Server:
                                         max_refine=self.max_refine, stream=stream)
                 t2 = time.perf_counter()
                 for dev, reqs, info in zip(blocks, splits, infos):
-                    X = dev.t().contiguous().cpu().numpy().T
+                    host_out = None
                     now = time.perf_counter()
                     c = 0
                     for r in reqs:
-                        r.X = X[:, c:c + r.nrhs]
+                        if isinstance(r.B, torch.Tensor):
+                            r.X = dev[:, c:c + r.nrhs]
+                        else:
+                            if host_out is None:
+                                host_out = dev.t().contiguous().cpu().numpy().T
+                                now = time.perf_counter()
+                            r.X = host_out[:, c:c + r.nrhs]
                         r.eta = info["eta"][c:c + r.nrhs]
                         r.iters = info["iters"]
                         r.status = info["status"]

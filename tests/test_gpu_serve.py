@@ -42,3 +42,29 @@ def test_server_alone_vs_mix():
     H = HSS.from_packed(gens[r.mat])
     res = r.B - omatvec(H, r.X)
     assert np.linalg.norm(res) / np.linalg.norm(r.B) < 10 * r.tol
+
+
+def test_server_device_requests():
+    """Device-resident request blocks: packed by device copies, results are
+    views of the round's block; each equals the request solved alone."""
+    from paper_1909_07909_amd import hss, serve
+    specs = serve.draw_catalogue(3, seed=6, n_lo=4096, n_hi=16384)
+    gens = serve.build_catalogue(specs, seed=6, workers=1)
+    mats = [hss.HSSMatrix(g) for g in gens]
+    for m in mats:
+        m.factor(hss.F32)
+    pools = serve.rhs_pools(mats, width=16, seed=9, device=True)
+    reqs = serve.poisson_requests(rate=4000.0, duration=0.02, n_mats=len(mats), seed=7)
+    srv, wall = serve.run_stream(mats, reqs, budget_bytes=1 << 30, workers=2, pools=pools)
+    assert not srv.errors, srv.errors
+    assert len(srv.done) == len(reqs)
+    for r in srv.done:
+        assert r.status == 0 and r.eta.max() <= r.tol, (r.rid, r.eta.max(), r.tol)
+        assert isinstance(r.X, torch.Tensor) and r.X.is_cuda
+    for r in srv.done[:10]:
+        A = mats[r.mat]
+        B = hss.empty_colmajor(A.n, r.nrhs, torch.float64).copy_(r.B)
+        info = A.solve(B, prec=hss.F32, tol=r.tol)
+        assert info["eta_max"] <= r.tol
+        diff = torch.linalg.norm(B - r.X, dim=0) / torch.linalg.norm(B, dim=0)
+        assert float(diff.max()) <= 10 * r.tol, (r.rid, float(diff.max()), r.tol)
