@@ -19,7 +19,10 @@
 
 namespace hss {
 
-constexpr int kFNT = 512;   // 256 owner slots x 2 halves
+// threads of a work-group: 2 MAXC owner slots (columns of [D' U'], rows of
+// [M; V'^T]) x 2 halves
+template <int MAXC>
+constexpr int fnt() { return 4 * MAXC; }
 
 // reg <- reg - tau (v . reg_pair) v on the half vector this lane holds; the
 // dot product of the lane pair is combined with one lane exchange and runs on
@@ -38,7 +41,8 @@ __device__ __forceinline__ void apply_reflector(const T* v, T (&reg)[COLS], T ta
 }
 
 template <typename T, int MAXC, bool BATCH>
-__global__ __launch_bounds__(kFNT) void k_ulv_factor_reg(KArgs<T, CallSV<T>> a) {
+__global__ __launch_bounds__(fnt<MAXC>()) void k_ulv_factor_reg(KArgs<T, CallSV<T>> a) {
+  constexpr int kFNT = fnt<MAXC>();
   constexpr int COLS = MAXC / 2;
   constexpr int VB = MAXC + 8;
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];   // 16-byte aligned: vector LDS reads
@@ -222,10 +226,11 @@ template <typename T>
 void launch_factor_reg(const KArgs<T, CallSV<T>>& a, int nblocks, int max_mp, hipStream_t s) {
   if (nblocks <= 0) return;
   const bool batch = a.tasks != nullptr;
-  dim3 grid(nblocks), block(kFNT);
+  dim3 grid(nblocks);
 #define HSS_FLAUNCH(MC)                                                                      \
   {                                                                                          \
     const size_t sm = ((size_t)MC * (MC + 1) + 2 * (MC + 8) + MC + kMaxRank + MC) * sizeof(T); \
+    const dim3 block(fnt<MC>());                                                             \
     if (batch) hipLaunchKernelGGL((k_ulv_factor_reg<T, MC, true>), grid, block, sm, s, a);    \
     else hipLaunchKernelGGL((k_ulv_factor_reg<T, MC, false>), grid, block, sm, s, a);        \
   }
