@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "hss_internal.hpp"
 
 namespace hss {
@@ -243,5 +245,51 @@ __device__ __forceinline__ void wg_store(int M, int N, const T* src, int lds, T*
     dst[i + (int64_t)j * ld] = src[i + j * lds];
   }
 }
+
+// Raw buffer access: base and size in a resource descriptor (SGPRs), a
+// per-lane byte offset and a uniform byte offset; reads at or beyond the size
+// return zero.
+// Every caller passes wavefront-uniform bases, sizes and uniform offsets; they
+// are moved to scalar registers explicitly so that the compiler does not fall
+// back to a per-lane loop over descriptors.
+__device__ __forceinline__ uint32_t uni(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  const uint64_t b = reinterpret_cast<uint64_t>(base);
+  const uint64_t ub = ((uint64_t)uni((uint32_t)(b >> 32)) << 32) | uni((uint32_t)b);
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(ub), 0, (int)uni(bytes),
+                                           0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                   uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, uni(soff), 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                 uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, uni(soff), 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                          uint32_t soff);
+template <>
+__device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r,
+                                                  uint32_t voff, uint32_t soff) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, uni(soff), 0);
+}
+template <>
+__device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                 uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, uni(soff), 0);
+}
+// A byte offset that every buffer access treats as out of range (stores are
+// dropped, loads return zero).
+constexpr uint32_t kBufOOB = 0x80000000u;
 
 }  // namespace hss

@@ -31,6 +31,14 @@ enum class UlvStep { Merge, Factor, RootLU, Fwd, Root, Bwd };
 template <typename T>
 void launch_factor_reg(const KArgs<T, CallSV<T>>& a, int nblocks, int max_mp, hipStream_t s);
 
+// Step 1 blocked (kernels_factor_blk.hip): panels of 32 Householder vectors
+// applied in compact WY form on the matrix cores, for blocks of 65..128 rows
+// with every rank <= 32.
+template <typename T>
+bool factor_blk_fits(int max_mp, int max_k);
+template <typename T>
+void launch_factor_blk(const KArgs<T, CallSV<T>>& a, int nblocks, hipStream_t s);
+
 // Solve sweeps, one wavefront per (node, right-hand-side column) (kernels_solve.hip).
 // stage_elems > 0: one wavefront per work-group with that many elements of T
 // of dynamic LDS for the node's factor copies.

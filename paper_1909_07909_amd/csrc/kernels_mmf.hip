@@ -33,34 +33,6 @@ constexpr int kXP = kMaxBlock + 8;   // padded LDS column of an X chunk
 // the four quarter-wavefronts of the leaf kernel read different banks.
 __device__ __forceinline__ int xrow(int i) { return i + ((i >> 5) << 1); }
 
-// Raw buffer access: base and size in a resource descriptor (SGPRs), a
-// per-lane byte offset and a uniform byte offset; reads at or beyond the size
-// return zero.
-// Every caller passes wavefront-uniform bases, sizes and uniform offsets; they
-// are moved to scalar registers explicitly so that the compiler does not fall
-// back to a per-lane loop over descriptors.
-__device__ __forceinline__ uint32_t uni(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
-  const uint64_t b = reinterpret_cast<uint64_t>(base);
-  const uint64_t ub = ((uint64_t)uni((uint32_t)(b >> 32)) << 32) | uni((uint32_t)b);
-  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(ub), 0, (int)uni(bytes),
-                                           0x00020000);
-}
-template <typename T>
-__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
-template <>
-__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                                   uint32_t soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, uni(soff), 0));
-}
-template <>
-__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                                 uint32_t soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, uni(soff), 0));
-}
-
 // x^ values cross work-groups inside the up kernel: agent-scope atomic
 // accesses, which are coherent across the XCDs' L2 caches without cache-wide
 // write-back or invalidation.

@@ -487,7 +487,10 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max
       if (max_mp <= 64 && max_k <= 32) { HSS_LAUNCH(k_ulv_merge1); }
       else { HSS_LAUNCH(k_ulv_merge); }
       break;
-    case UlvStep::Factor: launch_factor_reg<T>(a, nblocks, max_mp, s); break;
+    case UlvStep::Factor:
+      if (factor_blk_fits<T>(max_mp, max_k)) launch_factor_blk<T>(a, nblocks, s);
+      else launch_factor_reg<T>(a, nblocks, max_mp, s);
+      break;
     case UlvStep::RootLU:
       if (max_mp <= 128) { HSS_LAUNCH(k_ulv_root_lu2); }
       else { HSS_LAUNCH(k_ulv_root_lu); }
