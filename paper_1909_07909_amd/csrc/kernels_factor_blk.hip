@@ -102,10 +102,16 @@ __device__ __forceinline__ double xsum_rows(double v) {
          __longlong_as_double(((uint64_t)bh[1] << 32) | bl[1]);
 }
 
+// Offsets of buffer accesses stay non-negative in the offset register: the
+// hardware checks that register (with the immediate) against the size, so an
+// offset that is negative there and positive only after the immediate is
+// added would read zero.  Shifted accesses (s > 0) therefore clamp the row
+// per element instead of folding the shift into the register.
+
 // Slab element (R, C) = A[(R - s) + (c0 + C) * ld] for 0 <= R - s < rows and
 // c0 + C < cols, else 0 (A holds ld * cols elements, ld >= rows).  Buffer
-// reads: one offset register per tile column plus immediate offsets; reads
-// past the array return zero, the rows above the shift are masked.
+// reads: with no shift, one offset register per tile column plus immediate
+// offsets; reads past the array return zero.
 template <typename T>
 __device__ __forceinline__ void slab_load_cols(v4<T> (&X)[8][2], const T* A, int ld, int rows,
                                                int cols, int s, int c0, int g, int c) {
@@ -114,21 +120,23 @@ __device__ __forceinline__ void slab_load_cols(v4<T> (&X)[8][2], const T* A, int
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     const int col = c0 + 16 * ct + c;
-    const uint32_t vo = col < cols ? (uint32_t)(4 * g - s + col * ld) * sz : kBufOOB;
+    const bool cok = col < cols;
+    if (s == 0) {
+      const uint32_t vo = cok ? (uint32_t)(4 * g + col * ld) * sz : kBufOOB;
 #pragma unroll
-    for (int rt = 0; rt < 8; ++rt)
+      for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) X[rt][ct][r] = buf_load<T>(R, vo + (16 * rt + r) * sz, 0);
-  }
-  if (s > 0) {
+        for (int r = 0; r < 4; ++r) X[rt][ct][r] = buf_load<T>(R, vo + (16 * rt + r) * sz, 0);
+    } else {
 #pragma unroll
-    for (int rt = 0; rt < 8; ++rt)
+      for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const bool above = 4 * g < su(s - 16 * rt - r);
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) X[rt][ct][r] = above ? T(0) : X[rt][ct][r];
-      }
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * rt + 4 * g + r - s;
+          const uint32_t o = cok & (row >= 0) ? (uint32_t)(row + col * ld) * sz : kBufOOB;
+          X[rt][ct][r] = buf_load<T>(R, o, 0);
+        }
+    }
   }
 }
 
@@ -165,8 +173,9 @@ __device__ __forceinline__ void slab_store_cols(const v4<T> (&X)[8][2], T* A, in
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     const int col = c0 + 16 * ct + c;
-    const uint32_t vo = col < cols ? (uint32_t)(4 * g - s + col * ld) * sz : kBufOOB;
+    const bool cok = col < cols;
     if (full) {
+      const uint32_t vo = cok ? (uint32_t)(4 * g + col * ld) * sz : kBufOOB;
 #pragma unroll
       for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
@@ -176,8 +185,9 @@ __device__ __forceinline__ void slab_store_cols(const v4<T> (&X)[8][2], T* A, in
       for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const bool in = (4 * g >= su(s - 16 * rt - r)) & (4 * g < su(rows + s - 16 * rt - r));
-          buf_store<T>(X[rt][ct][r], R, in ? vo + (16 * rt + r) * sz : kBufOOB, 0);
+          const int row = 16 * rt + 4 * g + r - s;
+          const bool in = cok & (row >= 0) & (row < rows);
+          buf_store<T>(X[rt][ct][r], R, in ? (uint32_t)(row + col * ld) * sz : kBufOOB, 0);
         }
     }
   }
@@ -213,13 +223,14 @@ __device__ __forceinline__ void panel_load_cols(Panel<T>& Pn, const T* A, int ld
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     const int vec = 16 * ct + c;
-    const uint32_t vo = vec < cols ? (uint32_t)(base + 4 * g - s + vec * ld) * sz : kBufOOB;
+    const bool vok = vec < cols;
 #pragma unroll
     for (int rl = 0; rl < 2; ++rl)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const T v = buf_load<T>(R, vo + (16 * rl + r) * sz, 0);
-        Pn.t[rl][ct][r] = 4 * g < su(s - base - 16 * rl - r) ? T(0) : v;
+        const int row = base + 16 * rl + 4 * g + r - s;
+        const uint32_t o = vok & (row >= 0) ? (uint32_t)(row + vec * ld) * sz : kBufOOB;
+        Pn.t[rl][ct][r] = buf_load<T>(R, o, 0);
       }
   }
 }
@@ -248,6 +259,27 @@ __device__ __forceinline__ void panel_clear(const PanelLds<T>& L, int w, int lan
     L.taus[lane] = T(0);
   }
   wave_lds_sync();
+}
+
+// The Householder scalars of a panel step (as householder() in device_util),
+// FP32 with the hardware square root and reciprocal (about one ulp): the FP32
+// factors only precondition the refinement, which restores the accuracy.
+__device__ __forceinline__ void householder_step(float alpha, float sigma, float& beta, float& tau,
+                                                 float& scale) {
+  if (sigma == 0.f) {
+    beta = alpha;
+    tau = 0.f;
+    scale = 0.f;
+  } else {
+    const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
+    beta = alpha >= 0.f ? -nrm : nrm;
+    tau = (beta - alpha) * __builtin_amdgcn_rcpf(beta);
+    scale = __builtin_amdgcn_rcpf(alpha - beta);
+  }
+}
+__device__ __forceinline__ void householder_step(double alpha, double sigma, double& beta,
+                                                 double& tau, double& scale) {
+  householder(alpha, sigma, beta, tau, scale);
 }
 
 __device__ __forceinline__ float lane_fetch(int addr, float v) {
@@ -343,7 +375,7 @@ __device__ __forceinline__ void panel_step(Panel<T>& Pn, int jv, int pp, const P
   const T* pj = dred + 8 * jv;
   const T alpha = (pj[1] + pj[3]) + (pj[5] + pj[7]);
   T beta, tau, scale;
-  householder(alpha, sigma, beta, tau, scale);
+  householder_step(alpha, sigma, beta, tau, scale);
   const v4<T> e0a = *reinterpret_cast<const v4<T>*>(dred + 8 * c);
   const v4<T> e0b = *reinterpret_cast<const v4<T>*>(dred + 8 * c + 4);
   const v4<T> e1a = *reinterpret_cast<const v4<T>*>(dred + 8 * (16 + c));
@@ -610,7 +642,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int jv = 16 * ct + c;
         const T b = bet[jv];
         const T* y = Yt + jv * kLY + base + 4 * g;
-        const uint32_t vo = jv < ku ? (uint32_t)(base + 4 * g - s + jv * mp) * sz : kBufOOB;
 #pragma unroll
         for (int rl = 0; rl < 2; ++rl)
 #pragma unroll
@@ -618,8 +649,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             const int th = su(kBP - ku + 16 * ct - base - 16 * rl - r);
             const T yv = y[16 * rl + r];
             const T v = dgc < th ? yv : (dgc == th ? b : Pn.t[rl][ct][r]);
-            const bool in = (s == 0) | (4 * g >= su(s - base - 16 * rl - r));
-            buf_store<T>(v, RU, in ? vo + (16 * rl + r) * sz : kBufOOB, 0);
+            const int row = base + 16 * rl + 4 * g + r - s;
+            const bool in = (jv < ku) & (row >= 0);
+            buf_store<T>(v, RU, in ? (uint32_t)(row + jv * mp) * sz : kBufOOB, 0);
           }
       }
       if (tid < ku) I.tq[nd.otq + tid] = taus[tid];

@@ -55,6 +55,10 @@ CASES = [
     ("single_leaf", 50, 64, 4, 3),
     ("k32_m128", 8192, 128, 32, 1),
     ("k64_m128", 4096, 128, 64, 3),
+    # leaves of 93 / 94 rows: blocks of 65..127 rows are shifted in the blocked
+    # leaf factor, by amounts that are not multiples of four
+    ("ragged_m128", 3001, 128, 16, 2),
+    ("ragged_k32", 1500, 128, 32, 1),
 ]
 
 
