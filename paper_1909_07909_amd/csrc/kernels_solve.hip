@@ -40,6 +40,17 @@ __device__ __forceinline__ void tsum_step(T (&v)[64], bool b) {
   }
 }
 
+// tsum_step on a 32-entry array (widths 16 .. 1).
+template <typename T, int W>
+__device__ __forceinline__ void tsum_half(T (&v)[32], bool b) {
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const T send = b ? v[k] : v[W + k];
+    const T keep = b ? v[W + k] : v[k];
+    v[k] = keep + __shfl_xor(send, W, 64);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_transpose_sum64(T (&v)[64]) {
   const int lane = threadIdx.x & 63;
@@ -50,6 +61,24 @@ __device__ __forceinline__ T wave_transpose_sum64(T (&v)[64]) {
   tsum_step<T, 2>(v, (lane & 2) != 0);
   tsum_step<T, 1>(v, (lane & 1) != 0);
   return v[0];
+}
+
+// v[0..31] per lane; lanes l and l + 32 return the sum over all lanes of
+// v[l & 31].
+template <typename T>
+__device__ __forceinline__ T wave_transpose_sum32(T (&v)[32]) {
+  const int lane = threadIdx.x & 63;
+  // the 16-wide and narrower butterflies of the 64-value version, then the
+  // two 32-lane halves added
+  T x[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) x[k] = v[k];
+  tsum_half<T, 16>(x, (lane & 16) != 0);
+  tsum_half<T, 8>(x, (lane & 8) != 0);
+  tsum_half<T, 4>(x, (lane & 4) != 0);
+  tsum_half<T, 2>(x, (lane & 2) != 0);
+  tsum_half<T, 1>(x, (lane & 1) != 0);
+  return x[0] + __shfl_xor(x[0], 32, 64);
 }
 
 // Where the sweeps read a node's factors: the factor arrays themselves, or
@@ -84,14 +113,14 @@ __device__ __forceinline__ T stacked(const T* a, int ka, const T* b, int kb, int
 }
 
 template <typename T>
-__device__ __forceinline__ NodeSrc<T> src_global(const Inst<T>& I, const NodeInfo& nd, int node) {
+__device__ __forceinline__ NodeSrc<T> src_global(const Inst<T>& I, const NodeInfo& nd,
+                                                 const NodeInfo& n1, const NodeInfo& n2) {
   NodeSrc<T> S{};
   S.U = I.FU + nd.oFU; S.ldu = nd.mp;
   S.L = I.FD + nd.oFD; S.ldl = nd.mp;
   S.V = I.FV + nd.oFV; S.ldv = nd.mp;
   S.Z = I.FZ + nd.oFZ; S.ldz = nd.mp;
   if (!nd.is_leaf) {
-    const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
     S.W = I.W + nd.oW; S.ldw = n1.kv + n2.kv;
     S.U1 = I.FU + n1.oFU + n1.e; S.ldu1 = n1.mp; S.m1 = n1.e > 0;
     S.U2 = I.FU + n2.oFU + n2.e; S.ldu2 = n2.mp; S.m2 = n2.e > 0;
@@ -140,11 +169,14 @@ struct SBlk {
 };
 
 // Copy NB blocks to LDS: the block table goes through LDS, wavefront w copies
-// blocks w, w + nw, ... with 16 reads in flight per lane (compact code: the
+// blocks w, w + nw, ... with 32 reads in flight per lane (compact code: the
 // sweeps of the upper levels are short, and their instructions are fetched
-// afresh by every launch).
+// afresh by every launch).  Element o = lane + 64 u of a block is (i, c) with
+// o = i + c rows; (i, c) advance by the constant (64 mod rows, 64 / rows) per
+// u, so no division is done per element.
 template <typename T, int NB>
 __device__ __forceinline__ void stage_blocks(const SBlk<T> (&b)[NB], SBlk<T>* tab) {
+  constexpr int U = 32;
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < NB; ++q) tab[q] = b[q];
@@ -155,18 +187,29 @@ __device__ __forceinline__ void stage_blocks(const SBlk<T> (&b)[NB], SBlk<T>* ta
   for (int q = w; q < NB; q += nw) {
     const SBlk<T> B = tab[q];
     const int total = B.rows * B.cols;
+    if (total <= 0) continue;
+    const int qr = 64 / B.rows, rr = 64 - qr * B.rows;   // 64 = qr rows + rr
 #pragma unroll 1
-    for (int o0 = 0; o0 < total; o0 += 16 * 64) {
-      T v[16];
+    for (int o0 = 0; o0 < total; o0 += U * 64) {
+      const int oa = min(o0 + lane, total - 1);
+      int i = oa % B.rows, c = oa / B.rows;
+      T v[U];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int o = min(o0 + lane + 64 * u, total - 1);
-        const int i = o % B.rows, c = o / B.rows;
+      for (int u = 0; u < U; ++u) {
         const T x = B.src[i + (int64_t)c * B.ld];
         v[u] = (B.upper_zero & (i < c)) ? T(0) : x;
+        // next element (clamped to the last one past the end)
+        i += rr;
+        c += qr;
+        const bool wrap = i >= B.rows;
+        i = wrap ? i - B.rows : i;
+        c = wrap ? c + 1 : c;
+        const bool past = c >= B.cols;
+        i = past ? B.rows - 1 : i;
+        c = past ? B.cols - 1 : c;
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int o = o0 + lane + 64 * u;
         if (o < total) B.dst[o] = v[u];
       }
@@ -177,9 +220,9 @@ __device__ __forceinline__ void stage_blocks(const SBlk<T> (&b)[NB], SBlk<T>* ta
 // Copies of everything the forward sweep of an internal node reads, in LDS,
 // staged in one pass (all reads in flight together).
 template <typename T>
-__device__ NodeSrc<T> src_stage_fwd(const Inst<T>& I, const NodeInfo& nd, int node, T* sm) {
-  const NodeSrc<T> G = src_global(I, nd, node);
-  const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+__device__ NodeSrc<T> src_stage_fwd(const Inst<T>& I, const NodeInfo& nd, const NodeInfo& n1,
+                                    const NodeInfo& n2, T* sm) {
+  const NodeSrc<T> G = src_global(I, nd, n1, n2);
   const int mp = nd.mp, e = nd.e, ku = nd.ku, kv = nd.kv, kw = n1.kv + n2.kv;
   NodeSrc<T> S = G;
   T* p = sm;
@@ -200,16 +243,29 @@ __device__ NodeSrc<T> src_stage_fwd(const Inst<T>& I, const NodeInfo& nd, int no
   return S;   // the caller synchronizes the work-group
 }
 
-// rhs of an internal node (rows lane, lane + 64) from the children's c and z,
-// for CPW columns col0 .. col0+CPW-1 (columns >= nrhs read as zero).
+// The children's c and z an internal node's rhs is built from (rows lane,
+// lane + 64 of [c_c1; c_c2]; entries lane of z_c1, z_c2), for CPW columns
+// col0 .. (columns >= nrhs read as zero).  Independent of the node's own
+// factors, so they can be read before those are staged.
 template <typename T, int CPW>
-__device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, int node, int col0,
-                                int nrhs, int lane, const NodeSrc<T>& S, T (&x0)[CPW],
-                                T (&x1)[CPW]) {
-  const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+struct Gathered {
+  T x0[CPW], x1[CPW], z1[CPW], z2[CPW];
+};
+
+// A read issued where it is written: a relaxed atomic load may not be moved
+// past the work-group barrier that follows, so it is in flight while the
+// factors are staged (a plain load would be sunk to its first use).
+template <typename T>
+__device__ __forceinline__ T ld_early_or0(const T* p, bool ok) {
+  const T v = __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return ok ? v : T(0);
+}
+
+template <typename T, int CPW>
+__device__ __forceinline__ void gather_load(const Inst<T>& I, const NodeInfo& nd, const NodeInfo& n1,
+                                            const NodeInfo& n2, int col0, int nrhs, int lane,
+                                            Gathered<T, CPW>& G) {
   const int k1 = n1.kept, mp = nd.mp;
-  const int r0 = lane, r1 = lane + 64;
-  T t1[CPW], t2[CPW], z1l[CPW], z2l[CPW];
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
     const bool cv = col0 + c < nrhs;
@@ -218,55 +274,118 @@ __device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, int node, 
     const T* z2 = I.wz + n2.oz + co;
     const T* c1 = I.wc + n1.oc + co;
     const T* c2 = I.wc + n2.oc + co;
-    z1l[c] = n1.kv > 0 ? ld_or0(z1 + min(lane, n1.kv - 1), cv & (lane < n1.kv)) : T(0);
-    z2l[c] = n2.kv > 0 ? ld_or0(z2 + min(lane, n2.kv - 1), cv & (lane < n2.kv)) : T(0);
-    const T a0 = stacked(c1, k1, c2, mp - k1, r0), a1 = stacked(c1, k1, c2, mp - k1, r1);
-    x0[c] = cv ? a0 : T(0);
-    x1[c] = cv ? a1 : T(0);
+    G.z1[c] = n1.kv > 0 ? ld_early_or0(z1 + min(lane, n1.kv - 1), cv & (lane < n1.kv)) : T(0);
+    G.z2[c] = n2.kv > 0 ? ld_early_or0(z2 + min(lane, n2.kv - 1), cv & (lane < n2.kv)) : T(0);
+    // rows r of [c_c1; c_c2] (both parts read from clamped, valid addresses)
+    const int k2 = mp - k1;
+    const T c1a = k1 > 0 ? ld_early_or0(c1 + min(lane, k1 - 1), true) : T(0);
+    const T c1b = k1 > 0 ? ld_early_or0(c1 + min(lane + 64, k1 - 1), true) : T(0);
+    const T c2a = k2 > 0 ? ld_early_or0(c2 + min(max(lane - k1, 0), k2 - 1), true) : T(0);
+    const T c2b = k2 > 0 ? ld_early_or0(c2 + min(max(lane + 64 - k1, 0), k2 - 1), true) : T(0);
+    const T a0 = lane < k1 ? c1a : (lane < mp ? c2a : T(0));
+    const T a1 = lane + 64 < k1 ? c1b : (lane + 64 < mp ? c2b : T(0));
+    G.x0[c] = cv ? a0 : T(0);
+    G.x1[c] = cv ? a1 : T(0);
+  }
+}
+
+// rhs of an internal node (rows lane, lane + 64) from the children's c and z
+// (already read into G): [c_c1 - U~_c1 B12 z_c2; c_c2 - U~_c2 B21 z_c1].
+template <typename T, int CPW>
+__device__ void gather_apply(const NodeInfo& nd, const NodeInfo& n1, const NodeInfo& n2, int lane,
+                             const NodeSrc<T>& S, const Gathered<T, CPW>& G, T (&x0)[CPW],
+                             T (&x1)[CPW]) {
+  const int k1 = n1.kept, mp = nd.mp;
+  const int r0 = lane, r1 = lane + 64;
+  T t1[CPW], t2[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    x0[c] = G.x0[c];
+    x1[c] = G.x1[c];
     t1[c] = T(0);
     t2[c] = T(0);
   }
-#pragma unroll 1
-  for (int y = 0; y < (n1.ku > 0 ? n2.kv : 0); ++y) {
-    const T bv = S.B12[max(min(lane, n1.ku - 1), 0) + y * S.ld12];
-    const T b = lane < n1.ku ? bv : T(0);
+  // t1 = B12 z_c2, t2 = B21 z_c1 (lane = row), then x -= [U~_c1 t1; U~_c2 t2]:
+  // chunks of 8 terms, the reads of a chunk issued together, masked terms
+  // instead of branches
+  const int ny1 = n1.ku > 0 ? n2.kv : 0, ny2 = n2.ku > 0 ? n1.kv : 0;
+  const int lb1 = max(min(lane, n1.ku - 1), 0), lb2 = max(min(lane, n2.ku - 1), 0);
+  for (int y0 = 0; y0 < ny1; y0 += 8) {
+    T bv[8];
 #pragma unroll
-    for (int c = 0; c < CPW; ++c) t1[c] += b * bcast(z2l[c], y);
-  }
-#pragma unroll 1
-  for (int y = 0; y < (n2.ku > 0 ? n1.kv : 0); ++y) {
-    const T bv = S.B21[max(min(lane, n2.ku - 1), 0) + y * S.ld21];
-    const T b = lane < n2.ku ? bv : T(0);
+    for (int u = 0; u < 8; ++u) bv[u] = S.B12[lb1 + min(y0 + u, ny1 - 1) * S.ld12];
 #pragma unroll
-    for (int c = 0; c < CPW; ++c) t2[c] += b * bcast(z1l[c], y);
-  }
-#pragma unroll 1
-  for (int x = 0; x < n1.ku; ++x) {
-    const T a0 = ut(S.U1, S.ldu1, S.m1, min(r0, k1 - 1), x);
-    const T a1 = ut(S.U1, S.ldu1, S.m1, min(r1, k1 - 1), x);
-    const T u0 = r0 < k1 ? a0 : T(0);
-    const T u1 = r1 < k1 ? a1 : T(0);
+    for (int u = 0; u < 8; ++u) {
+      const T b = ((lane < n1.ku) & (y0 + u < ny1)) ? bv[u] : T(0);
 #pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-      const T tx = bcast(t1[c], x);
-      x0[c] -= u0 * tx;
-      x1[c] -= u1 * tx;
+      for (int c = 0; c < CPW; ++c) t1[c] += b * bcast(G.z2[c], min(y0 + u, 63));
     }
   }
-#pragma unroll 1
-  for (int x = 0; x < n2.ku; ++x) {
-    const int k2 = mp - k1;
-    const T a0 = ut(S.U2, S.ldu2, S.m2, min(max(r0 - k1, 0), k2 - 1), x);
-    const T a1 = ut(S.U2, S.ldu2, S.m2, min(max(r1 - k1, 0), k2 - 1), x);
-    const T u0 = ((r0 >= k1) & (r0 < mp)) ? a0 : T(0);
-    const T u1 = ((r1 >= k1) & (r1 < mp)) ? a1 : T(0);
+  for (int y0 = 0; y0 < ny2; y0 += 8) {
+    T bv[8];
 #pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-      const T tx = bcast(t2[c], x);
-      x0[c] -= u0 * tx;
-      x1[c] -= u1 * tx;
+    for (int u = 0; u < 8; ++u) bv[u] = S.B21[lb2 + min(y0 + u, ny2 - 1) * S.ld21];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const T b = ((lane < n2.ku) & (y0 + u < ny2)) ? bv[u] : T(0);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) t2[c] += b * bcast(G.z1[c], min(y0 + u, 63));
     }
   }
+  const int k2 = mp - k1;
+  const int a10 = min(r0, k1 - 1), a11 = min(r1, k1 - 1);
+  const int a20 = min(max(r0 - k1, 0), k2 - 1), a21 = min(max(r1 - k1, 0), k2 - 1);
+  const bool in10 = r0 < k1, in11 = r1 < k1;
+  const bool in20 = (r0 >= k1) & (r0 < mp), in21 = (r1 >= k1) & (r1 < mp);
+  for (int x0c = 0; x0c < n1.ku; x0c += 8) {
+    T ua[8], ub[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int x = min(x0c + u, n1.ku - 1);
+      ua[u] = ut(S.U1, S.ldu1, S.m1, a10, x);
+      ub[u] = ut(S.U1, S.ldu1, S.m1, a11, x);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool ok = x0c + u < n1.ku;
+      const T u0 = (in10 & ok) ? ua[u] : T(0), u1 = (in11 & ok) ? ub[u] : T(0);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const T tx = bcast(t1[c], min(x0c + u, 63));
+        x0[c] -= u0 * tx;
+        x1[c] -= u1 * tx;
+      }
+    }
+  }
+  for (int x0c = 0; x0c < n2.ku; x0c += 8) {
+    T ua[8], ub[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int x = min(x0c + u, n2.ku - 1);
+      ua[u] = ut(S.U2, S.ldu2, S.m2, a20, x);
+      ub[u] = ut(S.U2, S.ldu2, S.m2, a21, x);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool ok = x0c + u < n2.ku;
+      const T u0 = (in20 & ok) ? ua[u] : T(0), u1 = (in21 & ok) ? ub[u] : T(0);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const T tx = bcast(t2[c], min(x0c + u, 63));
+        x0[c] -= u0 * tx;
+        x1[c] -= u1 * tx;
+      }
+    }
+  }
+}
+
+template <typename T, int CPW>
+__device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, const NodeInfo& n1,
+                                const NodeInfo& n2, int col0, int nrhs, int lane,
+                                const NodeSrc<T>& S, T (&x0)[CPW], T (&x1)[CPW]) {
+  Gathered<T, CPW> G;
+  gather_load<T, CPW>(I, nd, n1, n2, col0, nrhs, lane, G);
+  gather_apply<T, CPW>(nd, n1, n2, lane, S, G, x0, x1);
 }
 
 // Work item of this wavefront.  Direct kernels: kSW wavefronts per
@@ -305,15 +424,24 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
   const NodeInfo nd = I.nodes[node];
   const int mp = nd.mp, e = nd.e, ku = nd.ku, kv = nd.kv;
   const int r0 = lane, r1 = lane + 64;
+  // the children's records, read once (reads after a barrier are not merged
+  // with those before it)
+  NodeInfo n1{}, n2{};
+  if (!nd.is_leaf) {
+    n1 = I.nodes[2 * node + 1];
+    n2 = I.nodes[2 * node + 2];
+  }
   NodeSrc<T> S;
+  Gathered<T, CPW> G;
+  if (!nd.is_leaf) gather_load<T, CPW>(I, nd, n1, n2, col0, C.nrhs, lane, G);   // before the staging
+  const T taul = ku > 0 ? ld_early_or0(I.tq + nd.otq + min(lane, ku - 1), lane < ku) : T(0);
   if (STAGED) {
-    S = src_stage_fwd(I, nd, node, reinterpret_cast<T*>(smem_raw));
+    S = src_stage_fwd(I, nd, n1, n2, reinterpret_cast<T*>(smem_raw));
     __syncthreads();
   } else {
-    S = src_global(I, nd, node);
+    S = src_global(I, nd, n1, n2);
   }
   if (col0 >= C.nrhs) return;
-  const T taul = ku > 0 ? ld_or0(I.tq + nd.otq + min(lane, ku - 1), lane < ku) : T(0);
   T x0[CPW], x1[CPW];
   if (nd.is_leaf) {
 #pragma unroll
@@ -324,18 +452,24 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
       x1[c] = ld_or0(b + min(r1, mp - 1), cv & (r1 < mp));
     }
   } else {
-    gather_internal<T, CPW>(I, nd, node, col0, C.nrhs, lane, S, x0, x1);
+    gather_apply<T, CPW>(nd, n1, n2, lane, S, G, x0, x1);
   }
   if (e > 0) {
-    // b~ = Q^T rhs = H_0 ... H_{ku-1} rhs, H_{ku-1} applied first (lane j holds tau_j)
-    // (deep unrolling for the leaf level, which reads its factors from memory;
-    // compact loops for the staged upper levels)
+    // b~ = Q^T rhs = H_0 ... H_{ku-1} rhs, H_{ku-1} applied first (lane j holds tau_j);
+    // the next reflector is read while this one is applied
+    T n0 = T(0), n1 = T(0);
+    if (ku > 0) {
+      n0 = S.U[(ku - 1) * S.ldu + min(r0, mp - 1)];
+      n1 = S.U[(ku - 1) * S.ldu + min(r1, mp - 1)];
+    }
 #pragma unroll(STAGED ? 1 : 8)
     for (int j = ku - 1; j >= 0; --j) {
       const T tau = bcast(taul, j);
       const int pr = e + j;
-      const T* v = S.U + j * S.ldu;
-      const T a0 = v[min(r0, mp - 1)], a1 = v[min(r1, mp - 1)];
+      const T a0 = n0, a1 = n1;
+      const T* vn = S.U + max(j - 1, 0) * S.ldu;
+      n0 = vn[min(r0, mp - 1)];
+      n1 = vn[min(r1, mp - 1)];
       const T v0 = r0 < pr ? a0 : (r0 == pr ? T(1) : T(0));
       const T v1 = r1 < pr ? a1 : (r1 == pr ? T(1) : T(0));
 #pragma unroll
@@ -346,13 +480,20 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
       }
     }
     // y = L^{-1} b~_top; the same column sweep leaves b~_bot - D~21 y below
+    // (the reciprocals of L's diagonal are formed up front, one per lane)
+    const int ec = max(e - 1, 0);
+    const T dg0 = S.L[min(r0, ec) * (S.ldl + 1)], dg1 = S.L[min(r1, ec) * (S.ldl + 1)];
+    const T dinv0 = T(1) / dg0, dinv1 = T(1) / dg1;
+    T m0 = S.L[min(r0, mp - 1)], m1 = S.L[min(r1, mp - 1)];
 #pragma unroll(STAGED ? 1 : 16)
     for (int i = 0; i < e; ++i) {
-      const T* Li = S.L + i * S.ldl;
-      const T a0 = Li[min(r0, mp - 1)], a1 = Li[min(r1, mp - 1)];
+      const T a0 = m0, a1 = m1;
+      const T* Ln = S.L + min(i + 1, ec) * S.ldl;
+      m0 = Ln[min(r0, mp - 1)];
+      m1 = Ln[min(r1, mp - 1)];
       const T l0 = ((r0 > i) & (r0 < mp)) ? a0 : T(0);
       const T l1 = ((r1 > i) & (r1 < mp)) ? a1 : T(0);
-      const T dinv = T(1) / Li[i];
+      const T dinv = row_of(dinv0, dinv1, i);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const T yi = row_of(x0[c], x1[c], i) * dinv;
@@ -378,28 +519,54 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
   int kw = 0;
   int kv1 = 0;
   if (!nd.is_leaf) {
-    const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
     kv1 = n1.kv;
     kw = n1.kv + n2.kv;
   }
+  // rows r0, r1 of [z_c1; z_c2], from the children's z read at the start
+  // (lane l holds entry l of each): a lane shift for the z_c2 part
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
     zc0[c] = zc1[c] = T(0);
-    if (kw && col0 + c < C.nrhs) {
-      const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
-      const int64_t co = (int64_t)(col0 + c) * I.lds;
-      const T* z1 = I.wz + n1.oz + co;
-      const T* z2 = I.wz + n2.oz + co;
-      zc0[c] = stacked(z1, kv1, z2, kw - kv1, r0);
-      zc1[c] = stacked(z1, kv1, z2, kw - kv1, r1);
+    if (kw) {
+      const T s0 = __shfl(G.z2[c], min(max(r0 - kv1, 0), 63), 64);
+      const T s1 = __shfl(G.z2[c], min(max(r1 - kv1, 0), 63), 64);
+      zc0[c] = r0 < kv1 ? G.z1[c] : (r0 < kw ? s0 : T(0));
+      zc1[c] = r1 < kv1 ? G.z1[c] : (r1 < kw ? s1 : T(0));
     }
   }
-  {
+  if (CPW == 1 && kv <= 32) {
+    // every lane forms its terms of all kv entries, one transposed sum over
+    // the wavefront leaves entry aa in lanes aa and aa + 32
+    T v[32];
+    const int ec = max(e - 1, 0);
+    const T* V0 = S.V + min(r0, ec);
+    const T* V1 = S.V + min(r1, ec);
+    const T x0e = r0 < e ? x0[0] : T(0), x1e = r1 < e ? x1[0] : T(0);
+#pragma unroll
+    for (int aa = 0; aa < 32; ++aa) {
+      const int ac = min(aa, max(kv - 1, 0));
+      v[aa] = V0[ac * S.ldv] * x0e + V1[ac * S.ldv] * x1e;
+    }
+    if (kw) {
+      const T* W0 = S.W + min(r0, kw - 1);
+      const T* W1 = S.W + min(r1, kw - 1);
+      const T z0e = r0 < kw ? zc0[0] : T(0), z1e = r1 < kw ? zc1[0] : T(0);
+#pragma unroll
+      for (int aa = 0; aa < 32; ++aa) {
+        const int ac = min(aa, max(kv - 1, 0));
+        v[aa] += W0[ac * S.ldw] * z0e + W1[ac * S.ldw] * z1e;
+      }
+    }
+#pragma unroll
+    for (int aa = 0; aa < 32; ++aa) v[aa] = aa < kv ? v[aa] : T(0);
+    const T zs = wave_transpose_sum32(v);
+    if (col0 < C.nrhs && lane < kv) I.wz[nd.oz + (int64_t)col0 * I.lds + lane] = zs;
+  } else {
     // one wavefront reduction per (entry, column); results kept by lane aa
     T zr[CPW];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) zr[c] = T(0);
-#pragma unroll(STAGED ? 1 : 8)
+#pragma unroll(STAGED ? 4 : 8)
     for (int aa = 0; aa < kv; ++aa) {
       const T* Va = S.V + aa * S.ldv;
       const int ec = max(e - 1, 0);
@@ -439,8 +606,13 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
   T* rest = reinterpret_cast<T*>(piv + ((mp + 3) & ~3));
   stage_block(LU, mp, mp, [&](int i, int j) { return I.rootLU[i + j * mp]; });
   for (int o = threadIdx.x; o < mp; o += blockDim.x) piv[o] = I.piv[o];   // (mp <= 128 < blockDim)
-  NodeSrc<T> S = (nd.is_leaf || !(a.flags & 1)) ? src_global(I, nd, node)
-                                                 : src_stage_fwd(I, nd, node, rest);
+  NodeInfo n1{}, n2{};
+  if (!nd.is_leaf) {
+    n1 = I.nodes[2 * node + 1];
+    n2 = I.nodes[2 * node + 2];
+  }
+  NodeSrc<T> S = (nd.is_leaf || !(a.flags & 1)) ? src_global(I, nd, n1, n2)
+                                                 : src_stage_fwd(I, nd, n1, n2, rest);
   __syncthreads();
   if (col0 >= C.nrhs) return;
   T t0[CPW], t1[CPW];
@@ -453,7 +625,7 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
       t1[c] = ld_or0(b + min(r1, mp - 1), cv & (r1 < mp));
     }
   } else {
-    gather_internal<T, CPW>(I, nd, node, col0, C.nrhs, lane, S, t0, t1);
+    gather_internal<T, CPW>(I, nd, n1, n2, col0, C.nrhs, lane, S, t0, t1);
   }
   double x0[CPW], x1[CPW];
 #pragma unroll
