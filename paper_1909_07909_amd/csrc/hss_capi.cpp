@@ -60,7 +60,8 @@ struct hss_handle {
   int64_t cap_ir = 0;
   double* stats = nullptr;   // 8 * cap_stats doubles
   int64_t cap_stats = 0;
-  double* pinned = nullptr;  // host-visible scalars
+  double* pinned = nullptr;  // host-visible refinement results (pinned), cap_pin + 2 doubles
+  int64_t cap_pin = 0;
   double norm2 = -1.0;
 };
 
@@ -183,6 +184,15 @@ hss_status ensure_ir(hss_handle* h, int64_t nrhs) {
     h->stats = dalloc<double>(h, 8 * cap + 8);
     h->cap_stats = h->stats ? cap : 0;
     if (!h->stats) return HSS_ENOMEM;
+  }
+  if (h->cap_pin < cap || !h->pinned) {
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    h->pinned = nullptr;
+    h->cap_pin = 0;
+    if (hipHostMalloc((void**)&h->pinned, sizeof(double) * (cap + 2), hipHostMallocDefault) !=
+        hipSuccess)
+      return HSS_ENOMEM;
+    h->cap_pin = cap;
   }
   return HSS_OK;
 }
@@ -941,6 +951,7 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
   launch_fill(reinterpret_cast<double*>(h->d_cnt), 0.0, (P.nnodes + 2) / 2, s);
   if ((st = last_launch_status())) return fail(st);
   h->pinned = nullptr;
+  h->cap_pin = 0;
   if (hipStreamSynchronize(s) != hipSuccess) return fail(HSS_EHIP);
   *out = h;
   return HSS_OK;
@@ -950,6 +961,7 @@ hss_status hss_destroy(hss_handle* h) {
   if (!h) return HSS_OK;
   (void)hipDeviceSynchronize();
   while (!h->blocks.empty()) dev_free(h, h->blocks.back().first);
+  if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return HSS_OK;
 }
@@ -1042,8 +1054,10 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
   double* outv = ss + 6 * nrhs;
   if (need_eta) launch_copy2d(B, ldb, h->b0, n, n, nrhs, s);
   // first solve
+  // gate: the FP32 correction is added only while gate[0] > tol (a correction
+  // queued before the host has read the backward error it depends on)
   auto correction_solve = [&](const double* rhs, int64_t ldr, double* x, int64_t ldx,
-                              bool accumulate) {
+                              bool accumulate, const double* gate = nullptr) {
     if (is64) {
       double* d = accumulate ? h->d64 : x;
       const int64_t ldd = accumulate ? n : ldx;
@@ -1057,7 +1071,7 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
       launch_colstats(rhs, ldr, n, nrhs, rr, bmax, s);
       launch_scale_cast(rhs, ldr, h->r32, n, n, nrhs, bmax, s);
       run_solve<float>(h, nrhs, h->r32, n, s);
-      if (accumulate) launch_axpy_cast(h->r32, n, x, ldx, n, nrhs, bmax, s);
+      if (accumulate) launch_axpy_cast(h->r32, n, x, ldx, n, nrhs, bmax, s, gate, opt.tol);
       else launch_cast_back(h->r32, n, x, ldx, n, nrhs, bmax, s);
     }
   };
@@ -1065,6 +1079,16 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
   if (!need_eta && !info) return last_launch_status();
   int iters = 0;
   double eta_max = 0.0;
+  int32_t dstat = 0;
+  bool have_stat = false;
+  // The backward error, the status word and (wanted) the per-column errors
+  // come back together in one copy to pinned memory per check.  The first
+  // FP32 correction is queued before the host reads the first check (gated on
+  // the device by that check): an FP32 solve alone rarely meets an FP64-level
+  // tolerance, so the GPU keeps working instead of idling through the round
+  // trip.
+  double* hp = h->pinned;
+  const bool copy_eta = info && info->eta && need_eta;
   if (need_eta) {
     launch_fill(bb, 0.0, nrhs, s);
     launch_colstats(h->b0, n, n, nrhs, bb, nullptr, s);
@@ -1077,20 +1101,34 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
       launch_colstats(B, ldb, n, nrhs, xx, nullptr, s);
       launch_eta(rr, xx, bb, h->norm2, nrhs, eta, outv, s);
       if ((st = last_launch_status())) return st;
-      if (hipMemcpyAsync(&eta_max, outv, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+      if (hipMemcpyAsync(hp, outv, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipMemcpyAsync(hp + 1, h->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+              hipSuccess)
         return HSS_EHIP;
+      if (copy_eta &&
+          hipMemcpyAsync(hp + 2, eta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s) !=
+              hipSuccess)
+        return HSS_EHIP;
+      const bool spec = !is64 && iters == 0 && opt.tol > 0.0 && opt.max_refine > 0;
+      if (spec) correction_solve(h->res, n, B, ldb, true, outv);
       if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
+      eta_max = hp[0];
+      std::memcpy(&dstat, hp + 1, sizeof(int32_t));
+      have_stat = true;
+      if (copy_eta) std::memcpy(info->eta, hp + 2, sizeof(double) * nrhs);
       if (opt.tol <= 0.0 || eta_max <= opt.tol || iters >= opt.max_refine) break;
-      correction_solve(h->res, n, B, ldb, true);
+      if (!spec) correction_solve(h->res, n, B, ldb, true);
       ++iters;
+      have_stat = false;
     }
   }
   if ((st = last_launch_status())) return st;
-  int32_t dstat = 0;
-  if (hipMemcpyAsync(&dstat, h->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
-      hipSuccess)
-    return HSS_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
+  if (!have_stat) {
+    if (hipMemcpyAsync(&dstat, h->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+      return HSS_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
+  }
   hss_status result = HSS_OK;
   if (dstat & (1 << HSS_ESINGULAR)) result = HSS_ESINGULAR;
   else if (need_eta && opt.tol > 0.0 && eta_max > opt.tol) result = HSS_ENOCONV;
@@ -1099,10 +1137,6 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
     info->iters = iters;
     info->status = result;
     info->norm2 = h->norm2;
-    if (info->eta && need_eta) {
-      if (hipMemcpy(info->eta, eta, sizeof(double) * nrhs, hipMemcpyDeviceToHost) != hipSuccess)
-        return HSS_EHIP;
-    }
   }
   return result;
 }

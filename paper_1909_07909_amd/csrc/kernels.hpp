@@ -56,9 +56,11 @@ void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s
 // dst[i + j*ldd] = (float)(src[i + j*lds] * scale[j])   (scale may be null -> 1)
 void launch_scale_cast(const double* src, int64_t lds, float* dst, int64_t ldd, int64_t n,
                        int64_t nrhs, const double* scale, hipStream_t s);
-// x[i + j*ldx] += scale[j] * d[i + j*ldd]
+// x[i + j*ldx] += scale[j] * d[i + j*ldd]; with gate, only when gate[0] > tol
+// (not when gate[0] <= tol)
 void launch_axpy_cast(const float* d, int64_t ldd, double* x, int64_t ldx, int64_t n,
-                      int64_t nrhs, const double* scale, hipStream_t s);
+                      int64_t nrhs, const double* scale, hipStream_t s,
+                      const double* gate = nullptr, double tol = 0.0);
 // r = b - r (in place on r), column-major n x nrhs
 void launch_residual(const double* b, int64_t ldb, double* r, int64_t ldr, int64_t n,
                      int64_t nrhs, hipStream_t s);

@@ -32,7 +32,9 @@ __global__ void k_scale_cast(const double* __restrict__ s, int64_t lds, float* _
 }
 
 __global__ void k_axpy_cast(const float* __restrict__ dd, int64_t ldd, double* __restrict__ x,
-                            int64_t ldx, int64_t n, const double* __restrict__ scale) {
+                            int64_t ldx, int64_t n, const double* __restrict__ scale,
+                            const double* __restrict__ gate, double tol) {
+  if (gate && gate[0] <= tol) return;   // converged: the correction is not applied
   const int64_t j = blockIdx.y;
   const double f = scale ? scale[j] : 1.0;
   for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
@@ -244,10 +246,11 @@ void launch_scale_cast(const double* src, int64_t lds, float* dst, int64_t ldd, 
 }
 
 void launch_axpy_cast(const float* d, int64_t ldd, double* x, int64_t ldx, int64_t n,
-                      int64_t nrhs, const double* scale, hipStream_t s) {
+                      int64_t nrhs, const double* scale, hipStream_t s, const double* gate,
+                      double tol) {
   if (n <= 0 || nrhs <= 0) return;
   hipLaunchKernelGGL(k_axpy_cast, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, d, ldd, x, ldx,
-                     n, scale);
+                     n, scale, gate, tol);
 }
 
 void launch_residual(const double* b, int64_t ldb, double* r, int64_t ldr, int64_t n,

@@ -128,6 +128,38 @@ def test_solve_f32_refined(name, n, m, k, r):
     assert _eta(H, X, B, normA) <= 1e-10
 
 
+@pytest.mark.parametrize("tol", [1e-2, 1e-10])
+def test_solve_f32_first_check(tol):
+    """The first FP32 correction is queued before the first backward-error check
+    is read back, gated on the device by that check: when the FP32 solve already
+    meets the tolerance the queued correction must leave x untouched, and the
+    reported error, iteration count and per-column errors must be those of the
+    checks actually made."""
+    hss = _hss()
+    n, m, k, r = 2048, 128, 16, 3
+    g = _gen(n, m, k)
+    H = HSS.from_packed(g)
+    A = hss.HSSMatrix(g)
+    A.factor(hss.F32)
+    B = inputs.rhs(n, r, 12)
+    B0d = _to_dev(B)
+    A.solve(B0d, prec=hss.F32, tol=0.0)          # the plain FP32 solve
+    X0 = _to_host(B0d)
+    Bd = _to_dev(B)
+    info = A.solve(Bd, prec=hss.F32, tol=tol, max_refine=10, want_eta=True)
+    X = _to_host(Bd)
+    normA = info["norm2"]
+    e0 = _eta(H, X0, B, normA)
+    if e0 <= tol:
+        assert info["iters"] == 0
+        assert np.array_equal(X, X0)
+    else:
+        assert info["iters"] >= 1
+    assert info["eta_max"] <= tol
+    assert abs(_eta(H, X, B, normA) - info["eta_max"]) <= 0.05 * info["eta_max"] + 1e-15
+    assert np.max(info["eta"]) == info["eta_max"]
+
+
 def test_closed_forms_large():
     hss = _hss()
     n = 2 ** 16
