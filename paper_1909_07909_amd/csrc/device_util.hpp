@@ -228,6 +228,37 @@ __device__ __forceinline__ void householder(T alpha, T sigma, T& beta, T& tau, T
   }
 }
 
+// LDS written by some lanes and then read by other lanes of the same
+// wavefront: the hardware executes a wavefront's LDS operations in order, so
+// only the compiler has to be kept from reordering or forwarding across this
+// point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// householder() for the FP32 factors with the hardware square root and
+// reciprocal (about one ulp each): FP32 factors only precondition the FP64
+// refinement, which restores the accuracy.  FP64 keeps the exact operations.
+__device__ __forceinline__ void householder_fast(float alpha, float sigma, float& beta, float& tau,
+                                                 float& scale) {
+  if (sigma == 0.f) {
+    beta = alpha;
+    tau = 0.f;
+    scale = 0.f;
+  } else {
+    const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
+    beta = alpha >= 0.f ? -nrm : nrm;
+    tau = (beta - alpha) * __builtin_amdgcn_rcpf(beta);
+    scale = __builtin_amdgcn_rcpf(alpha - beta);
+  }
+}
+__device__ __forceinline__ void householder_fast(double alpha, double sigma, double& beta,
+                                                 double& tau, double& scale) {
+  householder(alpha, sigma, beta, tau, scale);
+}
+
 // Copy an M x N block (generic pointers) into LDS with leading dimension lds.
 template <typename T, typename S>
 __device__ __forceinline__ void wg_load(int M, int N, const S* __restrict__ src, int64_t ld,

@@ -100,13 +100,14 @@ __global__ __launch_bounds__(fnt<MAXC>()) void k_ulv_factor_reg(KArgs<T, CallSV<
 #pragma unroll
         for (int j = 0; j < COLS; ++j) pub[base + j] = reg[j];
       }
+      wave_lds_sync();
       if (wave == (2 * owner) >> 6) {
         const T x0 = pub[r0];
         const T x1 = MAXC > 64 ? pub[r1] : T(0);
         const T sig = wave_sum((r0 < pr ? x0 * x0 : T(0)) + (r1 < pr ? x1 * x1 : T(0)));
         const T al = pub[pr];
         T beta, tau, scale;
-        householder(al, sig, beta, tau, scale);
+        householder_fast(al, sig, beta, tau, scale);
         const T v0 = r0 < pr ? x0 * scale : (r0 == pr ? T(1) : T(0));
         const T v1 = r1 < pr ? x1 * scale : (r1 == pr ? T(1) : T(0));
         vb[r0] = v0;
@@ -171,6 +172,7 @@ __global__ __launch_bounds__(fnt<MAXC>()) void k_ulv_factor_reg(KArgs<T, CallSV<
 #pragma unroll
       for (int j = 0; j < COLS; ++j) pub[base + j] = reg[j];
     }
+    wave_lds_sync();
     if (wave == (2 * i) >> 6) {
       const T x0 = pub[r0];
       const T x1 = MAXC > 64 ? pub[r1] : T(0);
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(fnt<MAXC>()) void k_ulv_factor_reg(KArgs<T, CallSV<
                              (r1 > i && r1 < mp ? x1 * x1 : T(0)));
       const T al = pub[i];
       T beta, tau, scale;
-      householder(al, sig, beta, tau, scale);
+      householder_fast(al, sig, beta, tau, scale);
       const T v0 = r0 > i ? x0 * scale : (r0 == i ? T(1) : T(0));
       const T v1 = r1 > i ? x1 * scale : (r1 == i ? T(1) : T(0));
       vb[r0] = v0;

@@ -67,16 +67,6 @@ __device__ __forceinline__ v4<T> v4zero() {
 // position register is needed.
 __device__ __forceinline__ int su(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// LDS written by some lanes and then read by other lanes of the same
-// wavefront: the hardware executes a wavefront's LDS operations in order, so
-// only the compiler has to be kept from reordering or forwarding across this
-// point.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Sum over the four lanes l, l ^ 16, l ^ 32, l ^ 48 (the four g of one c),
 // returned in all of them.  The row swaps exchange 16- and 32-lane halves in
 // the VALU: swapping v with itself leaves the two halves' values in the two
@@ -261,27 +251,6 @@ __device__ __forceinline__ void panel_clear(const PanelLds<T>& L, int w, int lan
   wave_lds_sync();
 }
 
-// The Householder scalars of a panel step (as householder() in device_util),
-// FP32 with the hardware square root and reciprocal (about one ulp): the FP32
-// factors only precondition the refinement, which restores the accuracy.
-__device__ __forceinline__ void householder_step(float alpha, float sigma, float& beta, float& tau,
-                                                 float& scale) {
-  if (sigma == 0.f) {
-    beta = alpha;
-    tau = 0.f;
-    scale = 0.f;
-  } else {
-    const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
-    beta = alpha >= 0.f ? -nrm : nrm;
-    tau = (beta - alpha) * __builtin_amdgcn_rcpf(beta);
-    scale = __builtin_amdgcn_rcpf(alpha - beta);
-  }
-}
-__device__ __forceinline__ void householder_step(double alpha, double sigma, double& beta,
-                                                 double& tau, double& scale) {
-  householder(alpha, sigma, beta, tau, scale);
-}
-
 __device__ __forceinline__ float lane_fetch(int addr, float v) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
 }
@@ -375,7 +344,7 @@ __device__ __forceinline__ void panel_step(Panel<T>& Pn, int jv, int pp, const P
   const T* pj = dred + 8 * jv;
   const T alpha = (pj[1] + pj[3]) + (pj[5] + pj[7]);
   T beta, tau, scale;
-  householder_step(alpha, sigma, beta, tau, scale);
+  householder_fast(alpha, sigma, beta, tau, scale);
   const v4<T> e0a = *reinterpret_cast<const v4<T>*>(dred + 8 * c);
   const v4<T> e0b = *reinterpret_cast<const v4<T>*>(dred + 8 * c + 4);
   const v4<T> e1a = *reinterpret_cast<const v4<T>*>(dred + 8 * (16 + c));
