@@ -155,20 +155,45 @@ __global__ __launch_bounds__(kNT) void k_ulv_merge(KArgs<T, CallSV<T>> a) {
 constexpr int kMB = 2048;
 constexpr int kMU = kMB / kNT;   // elements per thread and block
 
+// Element o = threadIdx.x + u kNT of an M-row column-major block is (i, c)
+// with o = i + c M; (i, c) advance by the constant (kNT mod M, kNT / M) per u,
+// so only the first index of a block costs a division.
+struct BlkIdx {
+  int i, c, qi, ri, M;
+  __device__ __forceinline__ explicit BlkIdx(int m) : M(max(m, 1)) {
+    i = (int)threadIdx.x % M;
+    c = (int)threadIdx.x / M;
+    qi = kNT / M;
+    ri = kNT - qi * M;
+  }
+  __device__ __forceinline__ void next() {
+    i += ri;
+    c += qi;
+    const bool wrap = i >= M;
+    i = wrap ? i - M : i;
+    c = wrap ? c + 1 : c;
+  }
+};
+
 template <typename T, typename F>
 __device__ __forceinline__ void blk_load(T (&v)[kMU], int M, int N, F f) {
+  BlkIdx x(M);
+  const int ni = max(M - 1, 0), nc = max(N - 1, 0);
 #pragma unroll
   for (int u = 0; u < kMU; ++u) {
-    const int o = min((int)threadIdx.x + u * kNT, max(M * N - 1, 0));
-    v[u] = M * N > 0 ? f(o % M, o / M) : T(0);
+    // past the end: the last element (a valid address), never stored
+    const bool past = x.c >= N;
+    v[u] = M * N > 0 ? f(past ? ni : x.i, past ? nc : x.c) : T(0);
+    x.next();
   }
 }
 template <typename T>
 __device__ __forceinline__ void blk_store(const T (&v)[kMU], int M, int N, T* dst) {
+  BlkIdx x(M);
 #pragma unroll
   for (int u = 0; u < kMU; ++u) {
-    const int o = threadIdx.x + u * kNT;
-    if (o < M * N) dst[o % M + (o / M) * (M + 1)] = v[u];
+    if (x.c < N) dst[x.i + x.c * (M + 1)] = v[u];
+    x.next();
   }
 }
 // C(i, j) = sum_l A(i, l) B(l, j) (TB: B(l, j) = B[j + l*ldb]) over LDS blocks.
@@ -256,11 +281,15 @@ __global__ __launch_bounds__(kNT) void k_ulv_merge1(KArgs<T, CallSV<T>> a) {
     blk_store(v5, k2, ku2, sU2);
     blk_store(v6, kr, ku, sR);
     blk_store(v7, kw, kv, sW);
+    {
+      BlkIdx x1(k1), x2(k2);
 #pragma unroll
-    for (int u = 0; u < kMU; ++u) {
-      const int o = threadIdx.x + u * kNT;
-      if (o < k1 * k1) FD[o % k1 + (int64_t)(o / k1) * mp] = v8[u];
-      if (o < k2 * k2) FD[k1 + o % k2 + (int64_t)(k1 + o / k2) * mp] = v9[u];
+      for (int u = 0; u < kMU; ++u) {
+        if (x1.c < k1) FD[x1.i + (int64_t)x1.c * mp] = v8[u];
+        if (x2.c < k2) FD[k1 + x2.i + (int64_t)(k1 + x2.c) * mp] = v9[u];
+        x1.next();
+        x2.next();
+      }
     }
   }
   __syncthreads();
