@@ -23,7 +23,10 @@
  * (1-based) is invalid; positive values are the HSS_E* codes below.
  *
  * Threading: a handle must be externally synchronized.  Device work of a
- * call is enqueued on its stream.  hss_create, hss_destroy, hss_query
+ * call is enqueued on its stream; the product (op N) forks part of its work
+ * to a stream the handle owns and joins it back with events, so it is
+ * ordered after earlier work on the caller's stream and before later work
+ * there, as if it ran on that stream alone.  hss_create, hss_destroy, hss_query
  * (HSS_Q_NORM2 on first use) and solves that compute a backward error or
  * refine iteratively synchronize the stream; everything else is asynchronous.
  */

@@ -71,6 +71,15 @@ __device__ __forceinline__ T ld_or0(const T* p, bool ok) {
   return ok ? v : T(0);
 }
 
+// ld_or0 for a read issued where it is written: a relaxed atomic load may not
+// be moved past a work-group barrier that follows, so it stays in flight
+// across it (a plain load would be sunk to its first use).
+template <typename T>
+__device__ __forceinline__ T ld_early_or0(const T* p, bool ok) {
+  const T v = __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return ok ? v : T(0);
+}
+
 // store(i, j, f(i, j)) for i < M, j < N by all threads of the work-group.  f
 // must be a plain read that is valid for every (i, j) in range: each thread
 // issues the reads of U elements before it stores any, so that they are in

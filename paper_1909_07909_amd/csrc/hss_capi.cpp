@@ -63,6 +63,10 @@ struct hss_handle {
   double* pinned = nullptr;  // host-visible refinement results (pinned), cap_pin + 2 doubles
   int64_t cap_pin = 0;
   double norm2 = -1.0;
+  // second stream of the product: the leaves' D X runs on it beside the
+  // up and down kernels (forked from and joined back to the caller's stream)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -232,12 +236,27 @@ void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T*
     // fused: leaves (with the climb), subtree walks, leaf outputs
     const int mku = h->plan.leaf_max_ku, mk = h->plan.max_k;
     if (p > 0) {
+      // D X on the side stream, beside the up and down passes; U y^ after both
+      const bool fork = h->side != nullptr &&
+                        hipEventRecord(h->ev_fork, s) == hipSuccess &&
+                        hipStreamWaitEvent(h->side, h->ev_fork, 0) == hipSuccess;
       const int lu = std::max(p - mmf_up_height(), 0);
       a.node0 = level_first(lu);
       launch_mmf<T>(MMFStep::Up, a, 1 << lu, (int)nrhs, mku, mk, s);
+      if (fork) {
+        a.node0 = level_first(p);
+        launch_mmf<T>(MMFStep::LeafDX, a, 1 << p, (int)nrhs, mku, mk, h->side);
+        (void)hipEventRecord(h->ev_join, h->side);
+      }
       const int ls = std::max(p - mmf_down_height(), 0);
       a.node0 = level_first(ls);
       launch_mmf<T>(MMFStep::Down, a, 1 << ls, (int)nrhs, mku, mk, s);
+      if (fork) {
+        (void)hipStreamWaitEvent(s, h->ev_join, 0);
+        a.node0 = level_first(p);
+        launch_mmf<T>(MMFStep::LeafUY, a, 1 << p, (int)nrhs, mku, mk, s);
+        return;
+      }
     }
     a.node0 = level_first(p);
     launch_mmf<T>(MMFStep::Leaf, a, 1 << p, (int)nrhs, mku, mk, s);
@@ -929,6 +948,10 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
     hss_destroy(h);
     return e;
   };
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
+    return fail(HSS_EHIP);
   h->d_nodes = dalloc<NodeInfo>(h, P.nnodes);
   h->d_status = dalloc<int32_t>(h, 4);
   h->d_cnt = dalloc<uint32_t>(h, (P.nnodes + 2) & ~1);
@@ -962,6 +985,9 @@ hss_status hss_destroy(hss_handle* h) {
   (void)hipDeviceSynchronize();
   while (!h->blocks.empty()) dev_free(h, h->blocks.back().first);
   if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->side) (void)hipStreamDestroy(h->side);
   delete h;
   return HSS_OK;
 }

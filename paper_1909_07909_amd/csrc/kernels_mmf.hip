@@ -332,6 +332,296 @@ __global__ __launch_bounds__(kUT) void k_mmf_up(KArgs<T, CallMM<T>> a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Up kernel for one right-hand side with every rank <= 32: the work split of
+// k_mmf_up (a subtree of 2^h leaves per work-group, then the climb), with
+// each internal node taken by ONE wavefront whose coefficients it loaded
+// ahead of need, every load coalesced:
+//   lane i < 32      row i of B12_t        -> (B12_t x^_c2)[i]
+//   lane 32 + i      row i of B21_t        -> (B21_t x^_c1)[i]
+//   lane l           row l of W_t          -> W_t[l, :] [x^_c1; x^_c2][l],
+//                    summed over the lanes by one transposed reduction
+// The wavefronts take the subtree's nodes first and then climb steps s in
+// rotation (step s by wavefront (c + s) mod 4, c = number of subtree nodes);
+// each loads its next node's coefficients as soon as it is free, so every
+// node's loads are in flight while the levels below it are formed.  The
+// loads go straight into the coefficient registers (clamped, valid
+// addresses; the masks act on the results), so nothing waits for them before
+// their use.  x^ vectors live in LDS slots of 32 entries, zero past the rank.
+template <typename T>
+struct UpCoef {
+  T b[32], w[32];
+  int kv1, kk, kvt;     // children's ranks (kv1, kv1 + kv2) and the node's
+  int bM, bK;           // core block of this lane's half: rows, columns
+  int64_t oy;           // y^ of the child this lane's half writes
+  int64_t ox1, ox2, oxt;   // x^ of the children and of the node
+};
+
+template <typename T>
+__device__ __forceinline__ T ld_early(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <typename T>
+__device__ __forceinline__ void up_coef_load(const Inst<T>& I, int t, int lane, UpCoef<T>& c) {
+  const NodeInfo nt = I.nodes[t];
+  const NodeInfo n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
+  const int i = lane & 31;
+  const bool h = lane >= 32;
+  c.kv1 = n1.kv;
+  c.kk = n1.kv + n2.kv;
+  c.kvt = t > 0 ? nt.kv : 0;
+  c.bM = h ? n2.ku : n1.ku;
+  c.bK = h ? n1.kv : n2.kv;
+  c.oy = h ? n2.oyh : n1.oyh;
+  c.ox1 = n1.oxh;
+  c.ox2 = n2.oxh;
+  c.oxt = nt.oxh;
+  // an empty block reads the node table instead (a valid address; its
+  // result is masked)
+  const T* dummy = reinterpret_cast<const T*>(I.nodes);
+  const bool bv = c.bM > 0 && c.bK > 0;
+  const T* br = bv ? (h ? I.B21 + nt.oB21 : I.B12 + nt.oB12) + min(i, c.bM - 1) : dummy;
+  const int bs = bv ? c.bM : 0, bk = bv ? c.bK - 1 : 0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) c.b[k] = ld_early(br + (int64_t)min(k, bk) * bs);
+  const bool wv = c.kvt > 0 && c.kk > 0;
+  const T* wr = wv ? I.W + nt.oW + min(lane, c.kk - 1) : dummy;
+  const int ws = wv ? c.kk : 0, wk = wv ? c.kvt - 1 : 0;
+#pragma unroll
+  for (int q = 0; q < 32; ++q) c.w[q] = ld_early(wr + (int64_t)min(q, wk) * ws);
+}
+
+// update_dpp with an old value and a bank mask (banks: lanes 4b..4b+3 of a row)
+template <int CTRL, int BANKS>
+__device__ __forceinline__ double dpp_old(double old, double v) {
+  const long long o = __double_as_longlong(old), b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), CTRL,
+                                             0xF, BANKS, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, 0xF, BANKS, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, int BANKS>
+__device__ __forceinline__ float dpp_old(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
+                                                    0xF, BANKS, false));
+}
+// (x, y) -> the permlane swap pair; .first + .second is the butterfly sum
+template <bool P32>
+__device__ __forceinline__ void plswap(float& x, float& y) {
+  const auto r = P32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false)
+                     : __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+template <bool P32>
+__device__ __forceinline__ void plswap(double& x, double& y) {
+  const uint64_t a = __double_as_longlong(x), b = __double_as_longlong(y);
+  const auto l = P32 ? __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false)
+                     : __builtin_amdgcn_permlane16_swap((uint32_t)a, (uint32_t)b, false, false);
+  const auto u = P32 ? __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false)
+                     : __builtin_amdgcn_permlane16_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+  x = __longlong_as_double(((uint64_t)u[0] << 32) | l[0]);
+  y = __longlong_as_double(((uint64_t)u[1] << 32) | l[1]);
+}
+
+// Transposed wavefront sum: v[0..31] per lane; lanes i and i + 32 return the
+// sum over all 64 lanes of v[i].  Five halving butterflies over lane bits
+// 4..0 (value k stays with the lanes whose bit is clear, k + W with the
+// others), then the two 32-lane halves are added; every exchange is a
+// permlane swap or a DPP move, no LDS.
+template <typename T>
+__device__ __forceinline__ T tsum32_dpp(T (&v)[32]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {          // bit 4: permlane16 swap
+    T x = v[k], y = v[16 + k];
+    plswap<false>(x, y);
+    v[k] = x + y;
+  }
+  {
+    const bool b = (lane & 8) != 0;       // bit 3: rotate rows by 8
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const T send = b ? v[k] : v[8 + k], keep = b ? v[8 + k] : v[k];
+      v[k] = keep + dpp<kDppRowRor8>(send);
+    }
+  }
+  {
+    const bool b = (lane & 4) != 0;       // bit 2: shift left 4 into banks 0, 2, right 4 into 1, 3
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const T send = b ? v[k] : v[4 + k], keep = b ? v[4 + k] : v[k];
+      const T r = dpp_old<0x114, 0xA>(dpp_old<0x104, 0x5>(T(0), send), send);
+      v[k] = keep + r;
+    }
+  }
+  {
+    const bool b = (lane & 2) != 0;       // bit 1
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const T send = b ? v[k] : v[2 + k], keep = b ? v[2 + k] : v[k];
+      v[k] = keep + dpp<kDppQuadXor2>(send);
+    }
+  }
+  {
+    const bool b = (lane & 1) != 0;       // bit 0
+    const T send = b ? v[0] : v[1], keep = b ? v[1] : v[0];
+    v[0] = keep + dpp<kDppQuadXor1>(send);
+  }
+  T x = v[0], y = v[0];
+  plswap<true>(x, y);
+  return x + y;
+}
+
+// Node t from its children's x^ in LDS (xa: c1, xb: c2, 32 entries each):
+// stores the core products y^_c1, y^_c2 and returns x^_t[lane & 31] (zero
+// below the root when W_t is empty; unused at the root).
+template <typename T>
+__device__ __forceinline__ T up_node(const Inst<T>& I, int lane, UpCoef<T>& c, const T* xa,
+                                     const T* xb) {
+  const int i = lane & 31;
+  const bool h = lane >= 32;
+  const T* xo = h ? xa : xb;   // B12 takes x^_c2, B21 takes x^_c1
+  T b0 = T(0), b1 = T(0);
+#pragma unroll
+  for (int k = 0; k < 32; k += 2) {
+    b0 += c.b[k] * xo[k];
+    b1 += c.b[k + 1] * xo[k + 1];
+  }
+  if (i < c.bM) I.yh[c.oy + i] = c.bK > 0 ? b0 + b1 : T(0);
+  // row `lane` of [x^_c1; x^_c2]
+  const T x1 = xa[min(lane, 31)], x2 = xb[min(max(lane - c.kv1, 0), 31)];
+  const T xl = lane < c.kv1 ? x1 : (lane < c.kk ? x2 : T(0));
+#pragma unroll
+  for (int q = 0; q < 32; ++q) c.w[q] *= xl;
+  const T x = tsum32_dpp(c.w);
+  return c.kk > 0 ? x : T(0);
+}
+
+static_assert(kUpH <= 2, "k_mmf_up1 keeps at most three subtree nodes in LDS slots 4-6");
+
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kUT) void k_mmf_up1(KArgs<T, CallMM<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  __shared__ unsigned s_arrive;
+  Inst<T> I; CallMM<T> C; int g;
+  resolve<BATCH>(a, I, C, g);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  T* xs = reinterpret_cast<T*>(smem_raw);   // slots of 32: leaves 0-3, subtree nodes 4-6, climb 7-8
+  const int h = I.p - I.nodes[g].level;     // subtree height (<= kUpH)
+  const int nl = 1 << h, cnt = nl - 1;       // leaves and internal nodes of the subtree
+  // internal node q of the subtree, bottom-up: level d = h-1 first
+  auto sub_node = [&](int q) {
+    const int d = q < nl - 2 ? h - 1 : 0;    // (h <= 2: at most two levels)
+    const int j = d == h - 1 ? q : q - (nl - 2);
+    return ((g + 1) << d) - 1 + j;
+  };
+  // ancestor of g at climb step s (-1: past the root)
+  auto step_node = [&](int s) { return s < 31 ? ((g + 1) >> (s + 1)) - 1 : -1; };
+  UpCoef<T> cf;
+  {
+    const int s0 = w - cnt;
+    const int t0 = w < cnt ? sub_node(w) : step_node(s0);
+    if (t0 >= 0) up_coef_load(I, t0, lane, cf);
+  }
+  // ---- leaves: wavefront w takes leaf w; lane rows l, l + 64
+  if (w < nl) {
+    const int leaf = ((g + 1) << h) - 1 + w;
+    const NodeInfo nd = I.nodes[leaf];
+    const int m = nd.m, kv = nd.kv;
+    const int r0 = min(lane, m - 1), r1 = min(lane + 64, m - 1);
+    const T* Xb = C.X + nd.row0;
+    const T x0 = ld_or0(Xb + r0, lane < m), x1 = ld_or0(Xb + r1, lane + 64 < m);
+    const auto Vr = buf_rsrc(I.V + nd.oV, (uint32_t)(m * kv * (int)sizeof(T)));
+    const uint32_t cs = (uint32_t)(m * (int)sizeof(T));
+    const uint32_t o0 = (uint32_t)(r0 * (int)sizeof(T)), o1 = (uint32_t)(r1 * (int)sizeof(T));
+    T* out = xs + 32 * w;
+    for (int b = 0; b < kv; b += 16) {       // 16 columns of V in flight
+      T va[16], vb[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        va[u] = buf_load<T>(Vr, o0, (uint32_t)(b + u) * cs);   // columns >= kv read zero
+        vb[u] = buf_load<T>(Vr, o1, (uint32_t)(b + u) * cs);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        if (b + u < kv) {
+          const T sv = wave_sum(va[u] * x0 + vb[u] * x1);
+          if (lane == 0) out[b + u] = sv;
+        }
+      }
+    }
+    if (lane >= kv && lane < 32) out[lane] = T(0);
+  }
+  __syncthreads();
+  // ---- internal nodes of the subtree, one wavefront each
+  int prod = 0;          // wavefront that formed x^_g
+  int own = 0;           // slot of x^_g
+  for (int d = h - 1; d >= 0; --d) {
+    const int qb = (1 << h) - (1 << (d + 1));         // nodes below level d
+    const int q = w - qb;
+    if (q >= 0 && q < (1 << d)) {
+      const int t = ((g + 1) << d) - 1 + q;
+      const int cs0 = d == h - 1 ? 2 * q : 4 + (qb - (1 << (d + 1))) + 2 * q;
+      const T x = up_node(I, lane, cf, xs + 32 * cs0, xs + 32 * (cs0 + 1));
+      if (lane < 32) xs[32 * (4 + w) + lane] = lane < cf.kvt ? x : T(0);
+      if (t == g && lane < cf.kvt) xh_put(I.xh + cf.oxt + lane, x);
+      // next coefficients (the wavefront of g waits for its x^ stores first
+      // and loads after the arrival, below)
+      const int sn = step_node(w - cnt + 4);
+      if (t != g && sn >= 0) up_coef_load(I, sn, lane, cf);
+    }
+    __syncthreads();
+  }
+  if (h > 0) {
+    prod = cnt - 1;
+    own = 4 + cnt - 1;
+  } else if (g > 0 && w == 0) {   // g is a leaf
+    const int kv = I.nodes[g].kv;
+    if (lane < kv) xh_put(I.xh + I.nodes[g].oxh + lane, xs[lane]);
+  }
+  // ---- climb: the second arrival at a node carries on with it.  x^ crossing
+  // work-groups is written with agent-coherent stores, which the writer waits
+  // for before the barrier that precedes the arrival count, and the sibling's
+  // x^ is read with agent-coherent loads only after the count has been seen.
+  int t = g;
+  for (int s = 0; t > 0; ++s) {
+    const int par = (t - 1) >> 1;
+    if (w == prod) __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) s_arrive = atomicAdd(I.cnt + par, 1u);
+    __syncthreads();
+    if ((s_arrive & 1u) == 0) return;
+    // the previous step's wavefront loads the coefficients of step s + 3
+    if (w == prod && (s > 0 || h > 0)) {
+      const int sn = step_node(s + 3);
+      if (sn >= 0) up_coef_load(I, sn, lane, cf);
+    }
+    const int hw = (cnt + s) & 3;
+    const int slot = 7 + (s & 1);
+    if (w == hw) {
+      const bool first = (t & 1) != 0;   // t is c1 of par; the sibling is the other child
+      const int ksib = first ? cf.kk - cf.kv1 : cf.kv1;
+      const int64_t osib = first ? cf.ox2 : cf.ox1;
+      if (lane < 32) {
+        const T v = ksib > 0 ? xh_get(I.xh + osib + min(lane, ksib - 1)) : T(0);
+        xs[32 * slot + lane] = lane < ksib ? v : T(0);
+      }
+      wave_lds_sync();
+      const T* xo = xs + 32 * own;
+      const T* xn = xs + 32 * slot;
+      const T x = up_node(I, lane, cf, first ? xo : xn, first ? xn : xo);
+      wave_lds_sync();
+      if (lane < 32) xs[32 * slot + lane] = lane < cf.kvt ? x : T(0);
+      if (lane < cf.kvt) xh_put(I.xh + cf.oxt + lane, x);
+    }
+    prod = hw;
+    own = slot;
+    t = par;
+  }
+}
+
 // Down work-group for subtree root s at level ls: levels 1 .. p of the path
 // from the root to s and then of the subtree of s.  Level 1 starts from the
 // core values alone; at a deeper level every (node c, row i) slot computes
@@ -493,9 +783,12 @@ __global__ __launch_bounds__(kDT) void k_mmf_down(KArgs<T, CallMM<T>> a) {
 // Y_i = D_i X_i + U_i y^_i.  Wavefront w owns rows 16w .. 16w+15; lane l holds
 // row 16w + (l & 15) of the columns 32q .. 32q+31 of D_i (q = l >> 4) and of
 // the columns q, q+4, ... of U_i; the four quarters are combined by two lane
-// exchanges.
-template <typename T, bool BATCH, int NU, int MC>
+// exchanges.  MODE 1 computes only Y_i = D_i X_i (it needs nothing from the
+// up and down kernels, so it can run beside them); MODE 2 then adds U_i y^_i
+// to Y_i.
+template <typename T, bool BATCH, int NU, int MC, int MODE>
 __global__ __launch_bounds__(kLT) void k_mmf_leaf(KArgs<T, CallMM<T>> a) {
+  constexpr bool WD = MODE != 2, WU = MODE != 1;
   HIP_DYNAMIC_SHARED(char, smem_raw)
   Inst<T> I; CallMM<T> C; int node;
   resolve<BATCH>(a, I, C, node);
@@ -524,14 +817,20 @@ __global__ __launch_bounds__(kLT) void k_mmf_leaf(KArgs<T, CallMM<T>> a) {
   T dv[32];
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) {
-    const T v = buf_load<T>(Dr, rb + (uint32_t)(32 * q) * cs, (uint32_t)jj * cs);
+    const T v = WD ? buf_load<T>(Dr, rb + (uint32_t)(32 * q) * cs, (uint32_t)jj * cs) : T(0);
     dv[jj] = rv ? v : T(0);
   }
   T uv[NU];
 #pragma unroll
   for (int i = 0; i < NU; ++i) {
-    const T v = buf_load<T>(Ur, rb + (uint32_t)q * cs, (uint32_t)(4 * i) * cs);
+    const T v = WU ? buf_load<T>(Ur, rb + (uint32_t)q * cs, (uint32_t)(4 * i) * cs) : T(0);
     uv[i] = rv ? v : T(0);
+  }
+  T yo[MC];   // MODE 2: the D X part already in Y
+#pragma unroll
+  for (int c = 0; c < MC; ++c) {
+    const int cc = min(c, nc - 1);
+    yo[c] = MODE == 2 ? C.Y[nd.row0 + min(row, m - 1) + (int64_t)(c0 + cc) * C.ldy] : T(0);
   }
   constexpr int UX = (kMaxBlock * MC + kLT - 1) / kLT, UY = (kMaxRank * MC + kLT - 1) / kLT;
   T xv[UX], yv[UY];
@@ -539,45 +838,62 @@ __global__ __launch_bounds__(kLT) void k_mmf_leaf(KArgs<T, CallMM<T>> a) {
 #pragma unroll
   for (int u = 0; u < UX; ++u) {
     const int o = tid + u * kLT, i = o % kMaxBlock, c = min(o / kMaxBlock, nc - 1);
-    const T v = Xb[min(i, m - 1) + (int64_t)c * C.ldx];
+    const T v = WD ? Xb[min(i, m - 1) + (int64_t)c * C.ldx] : T(0);
     xv[u] = (i < m) ? v : T(0);
   }
   const T* Yh = I.yh + nd.oyh + (int64_t)c0 * I.ldm;
 #pragma unroll
   for (int u = 0; u < UY; ++u) {
     const int o = tid + u * kLT, i = o % kMaxRank, c = min(o / kMaxRank, nc - 1);
-    const T v = ku > 0 ? Yh[min(i, ku - 1) + (int64_t)c * I.ldm] : T(0);
+    const T v = (WU && ku > 0) ? Yh[min(i, ku - 1) + (int64_t)c * I.ldm] : T(0);
     yv[u] = (i < ku) ? v : T(0);
   }
 #pragma unroll
   for (int u = 0; u < UX; ++u) {
     const int o = tid + u * kLT;
-    if (o < kMaxBlock * nc) xs[xrow(o % kMaxBlock) + (o / kMaxBlock) * kXP] = xv[u];
+    if (WD && o < kMaxBlock * nc) xs[xrow(o % kMaxBlock) + (o / kMaxBlock) * kXP] = xv[u];
   }
 #pragma unroll
   for (int u = 0; u < UY; ++u) {
     const int o = tid + u * kLT;
-    if (o < kMaxRank * nc) ys[o % kMaxRank + (o / kMaxRank) * kMaxRank] = yv[u];
+    if (WU && o < kMaxRank * nc) ys[o % kMaxRank + (o / kMaxRank) * kMaxRank] = yv[u];
   }
   __syncthreads();
   for (int c = 0; c < nc; ++c) {
     const T* xc = xs + c * kXP + xrow(32 * q);
     const T* yc = ys + c * kMaxRank + q;
-    T s0 = T(0), s1 = T(0);
+    // the D X and U y^ parts are reduced separately and added last, in every
+    // mode, so that the split and the one-pass forms round identically
+    T sd = T(0), su = T(0);
+    if (WD) {
+      T s0 = T(0), s1 = T(0);
 #pragma unroll
-    for (int jj = 0; jj < 32; jj += 2) {
-      s0 += dv[jj] * xc[jj];
-      s1 += dv[jj + 1] * xc[jj + 1];
+      for (int jj = 0; jj < 32; jj += 2) {
+        s0 += dv[jj] * xc[jj];
+        s1 += dv[jj + 1] * xc[jj + 1];
+      }
+      sd = s0 + s1;
+      sd += __shfl_xor(sd, 16, 64);
+      sd += __shfl_xor(sd, 32, 64);
     }
+    if (WU) {
+      T s0 = T(0), s1 = T(0);
 #pragma unroll
-    for (int i = 0; i < NU; i += 2) {
-      s0 += uv[i] * yc[4 * i];
-      s1 += uv[i + 1] * yc[4 * i + 4];
+      for (int i = 0; i < NU; i += 2) {
+        s0 += uv[i] * yc[4 * i];
+        s1 += uv[i + 1] * yc[4 * i + 4];
+      }
+      su = s0 + s1;
+      su += __shfl_xor(su, 16, 64);
+      su += __shfl_xor(su, 32, 64);
     }
-    T sum = s0 + s1;
-    sum += __shfl_xor(sum, 16, 64);
-    sum += __shfl_xor(sum, 32, 64);
-    if (q == 0 && rv) C.Y[nd.row0 + row + (int64_t)(c0 + c) * C.ldy] = sum;
+    if (MODE == 2) {
+      T yc0 = yo[0];
+#pragma unroll
+      for (int cc = 1; cc < MC; ++cc) yc0 = cc == c ? yo[cc] : yc0;
+      sd = yc0;
+    }
+    if (q == 0 && rv) C.Y[nd.row0 + row + (int64_t)(c0 + c) * C.ldy] = MODE == 1 ? sd : sd + su;
   }
 }
 
@@ -594,19 +910,27 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
   const int mcu = nrhs == 1 ? 1 : 8;
   const int ncu = nrhs < mcu ? nrhs : mcu;
   const bool wide = max_k > 32;
-  static const char* n64[] = {"mmf_up_f64", "mmf_down_f64", "mmf_leaf_f64"};
-  static const char* n32[] = {"mmf_up_f32", "mmf_down_f32", "mmf_leaf_f32"};
+  static const char* n64[] = {"mmf_up_f64", "mmf_down_f64", "mmf_leaf_f64", "mmf_leaf_dx_f64",
+                              "mmf_leaf_uy_f64"};
+  static const char* n32[] = {"mmf_up_f32", "mmf_down_f32", "mmf_leaf_f32", "mmf_leaf_dx_f32",
+                              "mmf_leaf_uy_f32"};
   TimedLaunch tl((sizeof(T) == 8 ? n64 : n32)[(int)step], s);
 #define HSS_MMF_UP(MC, KQ)                                                                   \
   if (batch) hipLaunchKernelGGL((k_mmf_up<T, true, MC, KQ>), dim3(nblocks), dim3(kUT), sm, s, a); \
   else hipLaunchKernelGGL((k_mmf_up<T, false, MC, KQ>), dim3(nblocks), dim3(kUT), sm, s, a);
-#define HSS_MMF_LEAF(NU, MC)                                                              \
-  if (batch) hipLaunchKernelGGL((k_mmf_leaf<T, true, NU, MC>), g, b, sm, s, a);          \
-  else hipLaunchKernelGGL((k_mmf_leaf<T, false, NU, MC>), g, b, sm, s, a);
+#define HSS_MMF_LEAF(NU, MC)                                                                   \
+  if (batch) hipLaunchKernelGGL((k_mmf_leaf<T, true, NU, MC, 0>), g, b, sm, s, a);               \
+  else if (step == MMFStep::LeafDX) hipLaunchKernelGGL((k_mmf_leaf<T, false, NU, MC, 1>), g, b, sm, s, a); \
+  else if (step == MMFStep::LeafUY) hipLaunchKernelGGL((k_mmf_leaf<T, false, NU, MC, 2>), g, b, sm, s, a); \
+  else hipLaunchKernelGGL((k_mmf_leaf<T, false, NU, MC, 0>), g, b, sm, s, a);
   switch (step) {
     case MMFStep::Up: {
       const size_t sm = (size_t)(kMaxBlock + 2 * (1 << kUpH) * kMaxRank) * ncu * sizeof(T);
-      if (mcu == 1) { if (wide) { HSS_MMF_UP(1, 64) } else { HSS_MMF_UP(1, 32) } }
+      if (mcu == 1 && !wide) {
+        const size_t sm1 = (size_t)9 * 32 * sizeof(T);
+        if (batch) hipLaunchKernelGGL((k_mmf_up1<T, true>), dim3(nblocks), dim3(kUT), sm1, s, a);
+        else hipLaunchKernelGGL((k_mmf_up1<T, false>), dim3(nblocks), dim3(kUT), sm1, s, a);
+      } else if (mcu == 1) { HSS_MMF_UP(1, 64) }
       else { if (wide) { HSS_MMF_UP(8, 64) } else { HSS_MMF_UP(8, 32) } }
       break;
     }
@@ -622,7 +946,9 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
       }
       break;
     }
-    case MMFStep::Leaf: {
+    case MMFStep::Leaf:
+    case MMFStep::LeafDX:
+    case MMFStep::LeafUY: {
       const size_t sm = (size_t)(kXP + kMaxRank) * ncw * sizeof(T);
       const dim3 g(nblocks, ytiles), b(kLT);
       const bool wu = max_ku > 32;

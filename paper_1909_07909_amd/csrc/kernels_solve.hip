@@ -252,15 +252,6 @@ struct Gathered {
   T x0[CPW], x1[CPW], z1[CPW], z2[CPW];
 };
 
-// A read issued where it is written: a relaxed atomic load may not be moved
-// past the work-group barrier that follows, so it is in flight while the
-// factors are staged (a plain load would be sunk to its first use).
-template <typename T>
-__device__ __forceinline__ T ld_early_or0(const T* p, bool ok) {
-  const T v = __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  return ok ? v : T(0);
-}
-
 template <typename T, int CPW>
 __device__ __forceinline__ void gather_load(const Inst<T>& I, const NodeInfo& nd, const NodeInfo& n1,
                                             const NodeInfo& n2, int col0, int nrhs, int lane,
