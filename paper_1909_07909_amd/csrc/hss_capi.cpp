@@ -32,12 +32,15 @@ struct FactorSet {
 template <typename T>
 struct Work {
   T *xh = nullptr, *yh = nullptr;     // product
+  T* mb = nullptr;                    // one-rhs product mailboxes (kMbSlot per node)
   int64_t cap_mm = 0;
   T *wc = nullptr, *wz = nullptr, *wy = nullptr, *wx = nullptr;   // solve
   int64_t cap_sv = 0;
 };
 
 }  // namespace
+
+static_assert(kStatusWaitCode == HSS_EHIP, "status bit of a run-out wait");
 
 struct hss_handle {
   Plan plan;
@@ -212,6 +215,7 @@ Inst<T> make_inst(hss_handle* h) {
   I.rootLU = F.rootLU; I.piv = F.piv;
   Work<T>& w = work<T>(h);
   I.xh = w.xh; I.yh = w.yh; I.ldm = h->plan.ldm;
+  I.mb = w.mb;
   I.wc = w.wc; I.wz = w.wz; I.wy = w.wy; I.wx = w.wx; I.lds = h->plan.lds;
   I.status = h->d_status;
   I.cnt = h->d_cnt;
@@ -840,6 +844,7 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
       return HSS_EHIP;
     hss_status r = HSS_OK;
     if (dstat & (1 << HSS_ESINGULAR)) r = HSS_ESINGULAR;
+    if (dstat & (1 << kStatusWaitCode)) r = HSS_EHIP;
     else if (need_eta && opt.tol > 0.0 && out[0] > opt.tol) r = HSS_ENOCONV;
     if (r && !worst) worst = r;
     if (info) {
@@ -972,6 +977,19 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
   }
   launch_fill(reinterpret_cast<double*>(h->d_status), 0.0, 2, s);
   launch_fill(reinterpret_cast<double*>(h->d_cnt), 0.0, (P.nnodes + 2) / 2, s);
+  {
+    // product mailboxes, all empty
+    const int64_t nmb = (int64_t)P.nnodes * kMbSlot;
+    h->w64.mb = dalloc<double>(h, nmb);
+    h->w32.mb = dalloc<float>(h, nmb + 1);
+    if (!h->w64.mb || !h->w32.mb) return fail(HSS_ENOMEM);
+    const uint64_t e32 = ((uint64_t)kMbEmpty32 << 32) | kMbEmpty32;
+    double v64, v32;
+    std::memcpy(&v64, &kMbEmpty64, sizeof v64);
+    std::memcpy(&v32, &e32, sizeof v32);
+    launch_fill(h->w64.mb, v64, nmb, s);
+    launch_fill(reinterpret_cast<double*>(h->w32.mb), v32, (nmb + 1) / 2, s);
+  }
   if ((st = last_launch_status())) return fail(st);
   h->pinned = nullptr;
   h->cap_pin = 0;
@@ -1157,6 +1175,7 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
   }
   hss_status result = HSS_OK;
   if (dstat & (1 << HSS_ESINGULAR)) result = HSS_ESINGULAR;
+  if (dstat & (1 << kStatusWaitCode)) result = HSS_EHIP;
   else if (need_eta && opt.tol > 0.0 && eta_max > opt.tol) result = HSS_ENOCONV;
   if (info) {
     info->eta_max = eta_max;

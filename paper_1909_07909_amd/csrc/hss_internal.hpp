@@ -49,6 +49,15 @@ struct NodeInfo {
   int64_t oc, oz, oy, ox;
 };
 
+// Empty-mailbox marker of the one-rhs product: signalling NaNs, which no
+// arithmetic produces, so a mailbox entry is either this or a written value.
+constexpr uint64_t kMbEmpty64 = 0x7FF4A5A5A5A5A5A5ull;
+constexpr uint32_t kMbEmpty32 = 0x7FA5A5A5u;
+constexpr int kMbSlot = 32;   // mailbox entries per node
+// Status bit (1 << code) set by a kernel whose bounded wait for another
+// work-group ran out; the code is HSS_EHIP.
+constexpr int kStatusWaitCode = 2;
+
 template <typename T>
 struct Inst {
   const NodeInfo* nodes;
@@ -62,6 +71,7 @@ struct Inst {
   int64_t lds;
   int32_t* status;  // device status word (HSS_ESINGULAR ...)
   uint32_t* cnt;    // per-node arrival counters of the fused product (even between calls)
+  T* mb;            // per-node x^ mailboxes of the one-rhs product (32 entries, empty = kMbEmpty)
   int32_t p;
   int32_t nnodes;
 };

@@ -354,7 +354,14 @@ struct UpCoef {
   int kv1, kk, kvt;     // children's ranks (kv1, kv1 + kv2) and the node's
   int bM, bK;           // core block of this lane's half: rows, columns
   int64_t oy;           // y^ of the child this lane's half writes
-  int64_t ox1, ox2, oxt;   // x^ of the children and of the node
+};
+
+// What a node's coefficient loads need from the node table: read a climb
+// step ahead of the loads themselves, so that no wavefront waits for the
+// table in front of a barrier.
+struct UpMeta {
+  int64_t oB12, oB21, oW, oy1, oy2;
+  int ku1, ku2, kv1, kv2, kvt;
 };
 
 template <typename T>
@@ -363,33 +370,53 @@ __device__ __forceinline__ T ld_early(const T* p) {
 }
 
 template <typename T>
-__device__ __forceinline__ void up_coef_load(const Inst<T>& I, int t, int lane, UpCoef<T>& c) {
-  const NodeInfo nt = I.nodes[t];
-  const NodeInfo n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
+__device__ __forceinline__ void up_meta_load(const Inst<T>& I, int t, UpMeta& m) {
+  const NodeInfo* nt = I.nodes + t;
+  const NodeInfo* n1 = I.nodes + 2 * t + 1;
+  const NodeInfo* n2 = I.nodes + 2 * t + 2;
+  m.oB12 = ld_early(&nt->oB12);
+  m.oB21 = ld_early(&nt->oB21);
+  m.oW = ld_early(&nt->oW);
+  m.kvt = t > 0 ? ld_early(&nt->kv) : 0;
+  m.oy1 = ld_early(&n1->oyh);
+  m.oy2 = ld_early(&n2->oyh);
+  m.ku1 = ld_early(&n1->ku);
+  m.ku2 = ld_early(&n2->ku);
+  m.kv1 = ld_early(&n1->kv);
+  m.kv2 = ld_early(&n2->kv);
+}
+
+template <typename T>
+__device__ __forceinline__ void up_coef_issue(const Inst<T>& I, const UpMeta& m, int lane,
+                                              UpCoef<T>& c) {
   const int i = lane & 31;
   const bool h = lane >= 32;
-  c.kv1 = n1.kv;
-  c.kk = n1.kv + n2.kv;
-  c.kvt = t > 0 ? nt.kv : 0;
-  c.bM = h ? n2.ku : n1.ku;
-  c.bK = h ? n1.kv : n2.kv;
-  c.oy = h ? n2.oyh : n1.oyh;
-  c.ox1 = n1.oxh;
-  c.ox2 = n2.oxh;
-  c.oxt = nt.oxh;
+  c.kv1 = m.kv1;
+  c.kk = m.kv1 + m.kv2;
+  c.kvt = m.kvt;
+  c.bM = h ? m.ku2 : m.ku1;
+  c.bK = h ? m.kv1 : m.kv2;
+  c.oy = h ? m.oy2 : m.oy1;
   // an empty block reads the node table instead (a valid address; its
   // result is masked)
   const T* dummy = reinterpret_cast<const T*>(I.nodes);
   const bool bv = c.bM > 0 && c.bK > 0;
-  const T* br = bv ? (h ? I.B21 + nt.oB21 : I.B12 + nt.oB12) + min(i, c.bM - 1) : dummy;
+  const T* br = bv ? (h ? I.B21 + m.oB21 : I.B12 + m.oB12) + min(i, c.bM - 1) : dummy;
   const int bs = bv ? c.bM : 0, bk = bv ? c.bK - 1 : 0;
 #pragma unroll
   for (int k = 0; k < 32; ++k) c.b[k] = ld_early(br + (int64_t)min(k, bk) * bs);
   const bool wv = c.kvt > 0 && c.kk > 0;
-  const T* wr = wv ? I.W + nt.oW + min(lane, c.kk - 1) : dummy;
+  const T* wr = wv ? I.W + m.oW + min(lane, c.kk - 1) : dummy;
   const int ws = wv ? c.kk : 0, wk = wv ? c.kvt - 1 : 0;
 #pragma unroll
   for (int q = 0; q < 32; ++q) c.w[q] = ld_early(wr + (int64_t)min(q, wk) * ws);
+}
+
+template <typename T>
+__device__ __forceinline__ void up_coef_load(const Inst<T>& I, int t, int lane, UpCoef<T>& c) {
+  UpMeta m;
+  up_meta_load(I, t, m);
+  up_coef_issue(I, m, lane, c);
 }
 
 // update_dpp with an old value and a bank mask (banks: lanes 4b..4b+3 of a row)
@@ -474,15 +501,13 @@ __device__ __forceinline__ T tsum32_dpp(T (&v)[32]) {
   return x + y;
 }
 
-// Node t from its children's x^ in LDS (xa: c1, xb: c2, 32 entries each):
-// stores the core products y^_c1, y^_c2 and returns x^_t[lane & 31] (zero
-// below the root when W_t is empty; unused at the root).
+// Core products of node t from its children's x^ in LDS (xa: c1, xb: c2,
+// 32 entries each): y^_c1 = B12_t x^_c2 (lanes < 32), y^_c2 = B21_t x^_c1.
 template <typename T>
-__device__ __forceinline__ T up_node(const Inst<T>& I, int lane, UpCoef<T>& c, const T* xa,
-                                     const T* xb) {
+__device__ __forceinline__ void up_core(const Inst<T>& I, int lane, const UpCoef<T>& c,
+                                        const T* xa, const T* xb) {
   const int i = lane & 31;
-  const bool h = lane >= 32;
-  const T* xo = h ? xa : xb;   // B12 takes x^_c2, B21 takes x^_c1
+  const T* xo = lane >= 32 ? xa : xb;
   T b0 = T(0), b1 = T(0);
 #pragma unroll
   for (int k = 0; k < 32; k += 2) {
@@ -490,7 +515,11 @@ __device__ __forceinline__ T up_node(const Inst<T>& I, int lane, UpCoef<T>& c, c
     b1 += c.b[k + 1] * xo[k + 1];
   }
   if (i < c.bM) I.yh[c.oy + i] = c.bK > 0 ? b0 + b1 : T(0);
-  // row `lane` of [x^_c1; x^_c2]
+}
+// x^_t[lane & 31] = (W_t^T [x^_c1; x^_c2]) (zero when W_t is empty; unused at
+// the root).  Consumes the W coefficients.
+template <typename T>
+__device__ __forceinline__ T up_w(int lane, UpCoef<T>& c, const T* xa, const T* xb) {
   const T x1 = xa[min(lane, 31)], x2 = xb[min(max(lane - c.kv1, 0), 31)];
   const T xl = lane < c.kv1 ? x1 : (lane < c.kk ? x2 : T(0));
 #pragma unroll
@@ -501,14 +530,35 @@ __device__ __forceinline__ T up_node(const Inst<T>& I, int lane, UpCoef<T>& c, c
 
 static_assert(kUpH <= 2, "k_mmf_up1 keeps at most three subtree nodes in LDS slots 4-6");
 
+// Mailbox entries: written once per product by the first arrival at a node,
+// read and emptied again by the second.
+__device__ __forceinline__ bool mb_empty(double v) {
+  return (uint64_t)__double_as_longlong(v) == kMbEmpty64;
+}
+__device__ __forceinline__ bool mb_empty(float v) { return __float_as_uint(v) == kMbEmpty32; }
+template <typename T>
+__device__ __forceinline__ T mb_empty_value();
+template <>
+__device__ __forceinline__ double mb_empty_value<double>() {
+  return __longlong_as_double((long long)kMbEmpty64);
+}
+template <>
+__device__ __forceinline__ float mb_empty_value<float>() {
+  return __uint_as_float(kMbEmpty32);
+}
+constexpr int kMbPolls = 1 << 20;   // bound of a mailbox wait (~0.1 s); never reached in practice
+
 template <typename T, bool BATCH>
-__global__ __launch_bounds__(kUT) void k_mmf_up1(KArgs<T, CallMM<T>> a) {
+__global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k_mmf_up1(
+    KArgs<T, CallMM<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
   __shared__ unsigned s_arrive;
   Inst<T> I; CallMM<T> C; int g;
   resolve<BATCH>(a, I, C, g);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  T* xs = reinterpret_cast<T*>(smem_raw);   // slots of 32: leaves 0-3, subtree nodes 4-6, climb 7-8
+  // LDS slots of 32 entries: leaves 0-3, subtree nodes 4-6, then per climb
+  // step s: the node's x^ in 7 + (s & 3), its sibling child's x^ in 11 + (s & 3)
+  T* xs = reinterpret_cast<T*>(smem_raw);
   const int h = I.p - I.nodes[g].level;     // subtree height (<= kUpH)
   const int nl = 1 << h, cnt = nl - 1;       // leaves and internal nodes of the subtree
   // internal node q of the subtree, bottom-up: level d = h-1 first
@@ -517,13 +567,17 @@ __global__ __launch_bounds__(kUT) void k_mmf_up1(KArgs<T, CallMM<T>> a) {
     const int j = d == h - 1 ? q : q - (nl - 2);
     return ((g + 1) << d) - 1 + j;
   };
-  // ancestor of g at climb step s (-1: past the root)
+  // node of climb step s (the ancestor of g s + 1 levels up; -1 past the root)
+  // and its wavefront
   auto step_node = [&](int s) { return s < 31 ? ((g + 1) >> (s + 1)) - 1 : -1; };
+  auto holder = [&](int s) { return (cnt + s) & 3; };
   UpCoef<T> cf;
+  UpMeta mt;   // node table entries of this wavefront's next climb node
   {
-    const int s0 = w - cnt;
-    const int t0 = w < cnt ? sub_node(w) : step_node(s0);
+    const int t0 = w < cnt ? sub_node(w) : (w == holder(0) ? step_node(0) : -1);
     if (t0 >= 0) up_coef_load(I, t0, lane, cf);
+    const int tm = w == holder(1) ? step_node(1) : (w == holder(2) ? step_node(2) : -1);
+    if (tm >= 0) up_meta_load(I, tm, mt);
   }
   // ---- leaves: wavefront w takes leaf w; lane rows l, l + 64
   if (w < nl) {
@@ -555,71 +609,92 @@ __global__ __launch_bounds__(kUT) void k_mmf_up1(KArgs<T, CallMM<T>> a) {
     if (lane >= kv && lane < 32) out[lane] = T(0);
   }
   __syncthreads();
-  // ---- internal nodes of the subtree, one wavefront each
-  int prod = 0;          // wavefront that formed x^_g
-  int own = 0;           // slot of x^_g
+  // ---- internal nodes of the subtree, one wavefront each (core products and W)
+  T xmine = T(0);   // lanes < 32 of the wavefront that formed the latest x^: its entries
   for (int d = h - 1; d >= 0; --d) {
     const int qb = (1 << h) - (1 << (d + 1));         // nodes below level d
     const int q = w - qb;
     if (q >= 0 && q < (1 << d)) {
       const int t = ((g + 1) << d) - 1 + q;
       const int cs0 = d == h - 1 ? 2 * q : 4 + (qb - (1 << (d + 1))) + 2 * q;
-      const T x = up_node(I, lane, cf, xs + 32 * cs0, xs + 32 * (cs0 + 1));
-      if (lane < 32) xs[32 * (4 + w) + lane] = lane < cf.kvt ? x : T(0);
-      if (t == g && lane < cf.kvt) xh_put(I.xh + cf.oxt + lane, x);
-      // next coefficients (the wavefront of g waits for its x^ stores first
-      // and loads after the arrival, below)
-      const int sn = step_node(w - cnt + 4);
-      if (t != g && sn >= 0) up_coef_load(I, sn, lane, cf);
+      const T* xa = xs + 32 * cs0;
+      const T* xb = xs + 32 * (cs0 + 1);
+      const T x = up_w(lane, cf, xa, xb);
+      xmine = lane < cf.kvt ? x : T(0);
+      if (lane < 32) xs[32 * (4 + w) + lane] = xmine;
+      up_core(I, lane, cf, xa, xb);
     }
     __syncthreads();
   }
-  if (h > 0) {
-    prod = cnt - 1;
-    own = 4 + cnt - 1;
-  } else if (g > 0 && w == 0) {   // g is a leaf
-    const int kv = I.nodes[g].kv;
-    if (lane < kv) xh_put(I.xh + I.nodes[g].oxh + lane, xs[lane]);
-  }
-  // ---- climb: the second arrival at a node carries on with it.  x^ crossing
-  // work-groups is written with agent-coherent stores, which the writer waits
-  // for before the barrier that precedes the arrival count, and the sibling's
-  // x^ is read with agent-coherent loads only after the count has been seen.
-  int t = g;
-  for (int s = 0; t > 0; ++s) {
+  const int gslot = h > 0 ? 4 + cnt - 1 : 0;   // x^_g
+  int prod = h > 0 ? cnt - 1 : 0;              // wavefront holding x^ of the climb's node in xmine
+  // ---- climb: the second arrival at a node carries on with it.  The first
+  // arrival hands its x^ over through the node's mailbox after counting (so
+  // it waits for nothing); the second polls the sibling's mailbox until every
+  // entry is written (the writer is running: it has already counted), takes
+  // the values and empties the mailbox for the next product.  Mailbox
+  // accesses are agent-coherent (across the XCDs' L2 caches).
+  // Step s: wavefront holder(s) forms x^ of node s (W part), wavefront
+  // holder(s-1) forms the core products of node s-1 (off the critical path)
+  // and reads the node table for node s+3, wavefront holder(s+2) loads the
+  // coefficients of node s+2.
+  auto own_slot = [&](int s) { return s == 0 ? gslot : 7 + ((s - 1) & 3); };
+  auto core_of = [&](int s) {   // core products of climb step s, by holder(s)
+    const int ch = s == 0 ? g : step_node(s - 1);
+    const bool first = (ch & 1) != 0;
+    const T* xo = xs + 32 * own_slot(s);
+    const T* xn = xs + 32 * (11 + (s & 3));
+    up_core(I, lane, cf, first ? xo : xn, first ? xn : xo);
+  };
+  int t = g, s = 0;
+  while (t > 0) {
     const int par = (t - 1) >> 1;
-    if (w == prod) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) s_arrive = atomicAdd(I.cnt + par, 1u);
     __syncthreads();
-    if ((s_arrive & 1u) == 0) return;
-    // the previous step's wavefront loads the coefficients of step s + 3
-    if (w == prod && (s > 0 || h > 0)) {
-      const int sn = step_node(s + 3);
-      if (sn >= 0) up_coef_load(I, sn, lane, cf);
+    const bool go = (s_arrive & 1u) != 0;
+    // first arrival: x^_t (zero past its rank) into t's mailbox
+    if (!go && w == prod && lane < kMbSlot) xh_put(I.mb + (int64_t)t * kMbSlot + lane, xmine);
+    if (s > 0 && w == holder(s - 1)) core_of(s - 1);
+    if (!go) return;
+    if (s == 0 && w == holder(1)) {
+      if (step_node(1) >= 0) up_coef_issue(I, mt, lane, cf);
+    } else if (w == holder(s + 2)) {
+      if (step_node(s + 2) >= 0) up_coef_issue(I, mt, lane, cf);
+    } else if (w == holder(s + 3)) {
+      if (step_node(s + 3) >= 0) up_meta_load(I, step_node(s + 3), mt);
     }
-    const int hw = (cnt + s) & 3;
-    const int slot = 7 + (s & 1);
-    if (w == hw) {
+    if (w == holder(s)) {
       const bool first = (t & 1) != 0;   // t is c1 of par; the sibling is the other child
-      const int ksib = first ? cf.kk - cf.kv1 : cf.kv1;
-      const int64_t osib = first ? cf.ox2 : cf.ox1;
-      if (lane < 32) {
-        const T v = ksib > 0 ? xh_get(I.xh + osib + min(lane, ksib - 1)) : T(0);
-        xs[32 * slot + lane] = lane < ksib ? v : T(0);
+      const int sib = first ? t + 1 : t - 1;
+      T* xn = xs + 32 * (11 + (s & 3));
+      T* box = I.mb + (int64_t)sib * kMbSlot + min(lane, kMbSlot - 1);
+      T v = xh_get(box);
+      for (int it = 0; __any(mb_empty(v)); ++it) {
+        if (it == kMbPolls) {   // the writer never came: report, go on
+          if (lane == 0) atomicOr(I.status, 1 << kStatusWaitCode);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        v = xh_get(box);
+      }
+      if (lane < kMbSlot) {
+        xn[lane] = v;
+        xh_put(box, mb_empty_value<T>());
       }
       wave_lds_sync();
-      const T* xo = xs + 32 * own;
-      const T* xn = xs + 32 * slot;
-      const T x = up_node(I, lane, cf, first ? xo : xn, first ? xn : xo);
-      wave_lds_sync();
-      if (lane < 32) xs[32 * slot + lane] = lane < cf.kvt ? x : T(0);
-      if (lane < cf.kvt) xh_put(I.xh + cf.oxt + lane, x);
+      const T* xo = xs + 32 * own_slot(s);
+      const T x = up_w(lane, cf, first ? xo : xn, first ? xn : xo);
+      xmine = lane < cf.kvt ? x : T(0);
+      if (lane < 32) xs[32 * (7 + (s & 3)) + lane] = xmine;
     }
-    prod = hw;
-    own = slot;
+    prod = holder(s);
     t = par;
+    ++s;
   }
+  // the root's core products (by the wavefront that formed nothing else
+  // since: its own LDS writes precede these reads in program order)
+  if (s > 0 && w == holder(s - 1)) core_of(s - 1);
 }
 
 // Down work-group for subtree root s at level ls: levels 1 .. p of the path
@@ -639,11 +714,11 @@ struct DownMap {
   }
 };
 
-template <typename T, int KR>
+template <typename T, int KR, int DC>
 struct DownSlot {
   int d = 0, j = 0, i = 0, ku = 0;   // level (0: none), position, row, rank of the node
   T r[KR];
-  T yc[kDC];
+  T yc[DC];
 };
 
 // level of slot g (0: past the last slot)
@@ -657,9 +732,9 @@ __device__ __forceinline__ int down_slot_level(const DownMap& mp, int g) {
   return 0;
 }
 
-template <typename T, int KR>
+template <typename T, int KR, int DC>
 __device__ __forceinline__ void down_slot_load(const Inst<T>& I, const DownMap& mp, int g,
-                                               int c0, int nc, DownSlot<T, KR>& sl) {
+                                               int c0, int nc, DownSlot<T, KR, DC>& sl) {
   sl.d = 0;
   int d = 2, base = 0;
   for (; d <= mp.p; ++d) {
@@ -686,18 +761,18 @@ __device__ __forceinline__ void down_slot_load(const Inst<T>& I, const DownMap& 
     }
     const T* yc = I.yh + nn.oyh + ic + (int64_t)c0 * I.ldm;
 #pragma unroll
-    for (int c = 0; c < kDC; ++c) sl.yc[c] = yc[(int64_t)min(c, nc - 1) * I.ldm];
+    for (int c = 0; c < DC; ++c) sl.yc[c] = yc[(int64_t)min(c, nc - 1) * I.ldm];
   } else {
 #pragma unroll
     for (int l = 0; l < KR; ++l) sl.r[l] = T(0);
 #pragma unroll
-    for (int c = 0; c < kDC; ++c) sl.yc[c] = T(0);
+    for (int c = 0; c < DC; ++c) sl.yc[c] = T(0);
   }
   if (!live) {
 #pragma unroll
     for (int l = 0; l < KR; ++l) sl.r[l] = T(0);
 #pragma unroll
-    for (int c = 0; c < kDC; ++c) sl.yc[c] = T(0);
+    for (int c = 0; c < DC; ++c) sl.yc[c] = T(0);
   }
   sl.d = have ? dd : 0;
   sl.j = j;
@@ -705,13 +780,13 @@ __device__ __forceinline__ void down_slot_load(const Inst<T>& I, const DownMap& 
   sl.ku = nn.ku;
 }
 
-template <typename T, int KR>
-__device__ __forceinline__ void down_slot_apply(const DownSlot<T, KR>& sl, int nc,
+template <typename T, int KR, int DC>
+__device__ __forceinline__ void down_slot_apply(const DownSlot<T, KR, DC>& sl, int nc,
                                                 const T* src, T* dst, int64_t blk) {
   const T* ps = src + (int64_t)(sl.j >> 1) * blk;
   T* o = dst + (int64_t)sl.j * blk + sl.i;
 #pragma unroll
-  for (int c = 0; c < kDC; ++c) {
+  for (int c = 0; c < DC; ++c) {
     if (c >= nc) break;
     T acc = sl.yc[c];
 #pragma unroll
@@ -720,15 +795,15 @@ __device__ __forceinline__ void down_slot_apply(const DownSlot<T, KR>& sl, int n
   }
 }
 
-template <typename T, bool BATCH, int KR, int NR>
+template <typename T, bool BATCH, int KR, int NR, int DC>
 __global__ __launch_bounds__(kDT) void k_mmf_down(KArgs<T, CallMM<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
   Inst<T> I; CallMM<T> C; int s;
   resolve<BATCH>(a, I, C, s);
-  const int c0 = blockIdx.y * kDC;
+  const int c0 = blockIdx.y * DC;
   if (c0 >= C.nrhs) return;
-  const int nc = min(kDC, C.nrhs - c0);
-  const int ncw = min(kDC, C.nrhs);
+  const int nc = min(DC, C.nrhs - c0);
+  const int ncw = min(DC, C.nrhs);
   const int64_t blk = (int64_t)kMaxRank * ncw;
   T* cur = reinterpret_cast<T*>(smem_raw);   // two levels x 2^kDnH nodes x blk
   T* nxt = cur + (int64_t)(1 << kDnH) * blk;
@@ -739,7 +814,7 @@ __global__ __launch_bounds__(kDT) void k_mmf_down(KArgs<T, CallMM<T>> a) {
   // every slot's level: total count and the prefetched rounds
   int total = 0;
   for (int d = 2; d <= mp.p; ++d) total += mp.cnt(d) * KR;
-  DownSlot<T, KR> sl[NR];
+  DownSlot<T, KR, DC> sl[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) down_slot_load(I, mp, threadIdx.x + r * kDT, c0, nc, sl[r]);
   // level 1: core values of its node(s)
@@ -762,7 +837,7 @@ __global__ __launch_bounds__(kDT) void k_mmf_down(KArgs<T, CallMM<T>> a) {
     for (int r = NR; r < rounds; ++r) {   // slots beyond the prefetched rounds
       const int g = threadIdx.x + r * kDT;
       if (down_slot_level<KR>(mp, g) != d) continue;
-      DownSlot<T, KR> x;
+      DownSlot<T, KR, DC> x;
       down_slot_load(I, mp, g, c0, nc, x);
       down_slot_apply(x, nc, cur, nxt, blk);
     }
@@ -927,7 +1002,7 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
     case MMFStep::Up: {
       const size_t sm = (size_t)(kMaxBlock + 2 * (1 << kUpH) * kMaxRank) * ncu * sizeof(T);
       if (mcu == 1 && !wide) {
-        const size_t sm1 = (size_t)9 * 32 * sizeof(T);
+        const size_t sm1 = (size_t)15 * 32 * sizeof(T);
         if (batch) hipLaunchKernelGGL((k_mmf_up1<T, true>), dim3(nblocks), dim3(kUT), sm1, s, a);
         else hipLaunchKernelGGL((k_mmf_up1<T, false>), dim3(nblocks), dim3(kUT), sm1, s, a);
       } else if (mcu == 1) { HSS_MMF_UP(1, 64) }
@@ -935,14 +1010,19 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
       break;
     }
     case MMFStep::Down: {
-      const size_t sm = (size_t)2 * (1 << kDnH) * kMaxRank * (nrhs < kDC ? nrhs : kDC) * sizeof(T);
-      const dim3 g(nblocks, (nrhs + kDC - 1) / kDC), b(kDT);
-      if (!wide) {
-        if (batch) hipLaunchKernelGGL((k_mmf_down<T, true, 32, 1>), g, b, sm, s, a);
-        else hipLaunchKernelGGL((k_mmf_down<T, false, 32, 1>), g, b, sm, s, a);
+      // one right-hand side: every slot of a work-group prefetched (two rounds)
+      const int dc = nrhs == 1 ? 1 : kDC;
+      const size_t sm = (size_t)2 * (1 << kDnH) * kMaxRank * (nrhs < dc ? nrhs : dc) * sizeof(T);
+      const dim3 g(nblocks, (nrhs + dc - 1) / dc), b(kDT);
+      if (nrhs == 1 && !wide) {
+        if (batch) hipLaunchKernelGGL((k_mmf_down<T, true, 32, 2, 1>), g, b, sm, s, a);
+        else hipLaunchKernelGGL((k_mmf_down<T, false, 32, 2, 1>), g, b, sm, s, a);
+      } else if (!wide) {
+        if (batch) hipLaunchKernelGGL((k_mmf_down<T, true, 32, 1, kDC>), g, b, sm, s, a);
+        else hipLaunchKernelGGL((k_mmf_down<T, false, 32, 1, kDC>), g, b, sm, s, a);
       } else {
-        if (batch) hipLaunchKernelGGL((k_mmf_down<T, true, 64, 1>), g, b, sm, s, a);
-        else hipLaunchKernelGGL((k_mmf_down<T, false, 64, 1>), g, b, sm, s, a);
+        if (batch) hipLaunchKernelGGL((k_mmf_down<T, true, 64, 1, kDC>), g, b, sm, s, a);
+        else hipLaunchKernelGGL((k_mmf_down<T, false, 64, 1, kDC>), g, b, sm, s, a);
       }
       break;
     }
