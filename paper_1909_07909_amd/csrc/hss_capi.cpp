@@ -63,6 +63,8 @@ struct hss_handle {
   int64_t cap_ir = 0;
   double* stats = nullptr;   // 8 * cap_stats doubles
   int64_t cap_stats = 0;
+  double* part = nullptr;    // partials of the fused check kernels (check_partials(cap_stats))
+  uint32_t* chk_cnt = nullptr;   // their arrival counter (0 between launches)
   double* pinned = nullptr;  // host-visible refinement results (pinned), cap_pin + 2 doubles
   int64_t cap_pin = 0;
   double norm2 = -1.0;
@@ -188,10 +190,13 @@ hss_status ensure_ir(hss_handle* h, int64_t nrhs) {
   }
   if (h->cap_stats < cap || !h->stats) {
     dev_free(h, h->stats);
+    dev_free(h, h->part);
     h->stats = dalloc<double>(h, 8 * cap + 8);
-    h->cap_stats = h->stats ? cap : 0;
-    if (!h->stats) return HSS_ENOMEM;
+    h->part = dalloc<double>(h, check_partials(cap));
+    h->cap_stats = (h->stats && h->part) ? cap : 0;
+    if (!h->cap_stats) return HSS_ENOMEM;
   }
+
   if (h->cap_pin < cap || !h->pinned) {
     if (h->pinned) (void)hipHostFree(h->pinned);
     h->pinned = nullptr;
@@ -843,8 +848,8 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
         hipMemcpy(out, hs[j]->stats + 6 * nr, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
       return HSS_EHIP;
     hss_status r = HSS_OK;
-    if (dstat & (1 << HSS_ESINGULAR)) r = HSS_ESINGULAR;
     if (dstat & (1 << kStatusWaitCode)) r = HSS_EHIP;
+    else if (dstat & (1 << HSS_ESINGULAR)) r = HSS_ESINGULAR;
     else if (need_eta && opt.tol > 0.0 && out[0] > opt.tol) r = HSS_ENOCONV;
     if (r && !worst) worst = r;
     if (info) {
@@ -960,7 +965,8 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
   h->d_nodes = dalloc<NodeInfo>(h, P.nnodes);
   h->d_status = dalloc<int32_t>(h, 4);
   h->d_cnt = dalloc<uint32_t>(h, (P.nnodes + 2) & ~1);
-  if (!h->d_nodes || !h->d_status || !h->d_cnt) return fail(HSS_ENOMEM);
+  h->chk_cnt = dalloc<uint32_t>(h, 2);
+  if (!h->d_nodes || !h->d_status || !h->d_cnt || !h->chk_cnt) return fail(HSS_ENOMEM);
   if (hipMemcpyAsync(h->d_nodes, P.nodes.data(), sizeof(NodeInfo) * P.nnodes,
                      hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(HSS_EHIP);
@@ -977,6 +983,7 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
   }
   launch_fill(reinterpret_cast<double*>(h->d_status), 0.0, 2, s);
   launch_fill(reinterpret_cast<double*>(h->d_cnt), 0.0, (P.nnodes + 2) / 2, s);
+  launch_fill(reinterpret_cast<double*>(h->chk_cnt), 0.0, 1, s);
   {
     // product mailboxes, all empty
     const int64_t nmb = (int64_t)P.nnodes * kMbSlot;
@@ -1088,20 +1095,17 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
   }
   if ((st = ensure_ir(h, nrhs))) return st;
   if (need_eta && (st = ensure_work_mm<double>(h, nrhs))) return st;
-  double* ss = h->stats;      // rr | xx | bb | rmax | bmax | eta | out
-  double* rr = ss;
-  double* xx = ss + nrhs;
-  double* bb = ss + 2 * nrhs;
-  double* rmax = ss + 3 * nrhs;
+  double* ss = h->stats;      // bmax at 4 nrhs; [eta_max, status, eta_0 ..] at 6 nrhs
   double* bmax = ss + 4 * nrhs;
-  double* eta = ss + 5 * nrhs;
   double* outv = ss + 6 * nrhs;
   if (need_eta) launch_copy2d(B, ldb, h->b0, n, n, nrhs, s);
   // first solve
   // gate: the FP32 correction is added only while gate[0] > tol (a correction
   // queued before the host has read the backward error it depends on)
+  // scaled: bmax already holds max |rhs| per column (the check computed it)
   auto correction_solve = [&](const double* rhs, int64_t ldr, double* x, int64_t ldx,
-                              bool accumulate, const double* gate = nullptr) {
+                              bool accumulate, const double* gate = nullptr,
+                              bool scaled = false) {
     if (is64) {
       double* d = accumulate ? h->d64 : x;
       const int64_t ldd = accumulate ? n : ldx;
@@ -1110,9 +1114,7 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
       if (accumulate) launch_axpy64(d, ldd, x, ldx, n, nrhs, s);
     } else {
       // scale each column by its max |.| before rounding to FP32
-      launch_fill(bmax, 0.0, nrhs, s);
-      launch_fill(rr, 0.0, nrhs, s);
-      launch_colstats(rhs, ldr, n, nrhs, rr, bmax, s);
+      if (!scaled) launch_colmax(rhs, ldr, n, nrhs, h->part, h->chk_cnt, bmax, s);
       launch_scale_cast(rhs, ldr, h->r32, n, n, nrhs, bmax, s);
       run_solve<float>(h, nrhs, h->r32, n, s);
       if (accumulate) launch_axpy_cast(h->r32, n, x, ldx, n, nrhs, bmax, s, gate, opt.tol);
@@ -1134,34 +1136,25 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
   double* hp = h->pinned;
   const bool copy_eta = info && info->eta && need_eta;
   if (need_eta) {
-    launch_fill(bb, 0.0, nrhs, s);
-    launch_colstats(h->b0, n, n, nrhs, bb, nullptr, s);
     for (;;) {
+      // residual, norms, eta, status and max |r| in one launch; outv =
+      // [eta_max, status, eta_0 ..], copied to the host in one piece
       run_matmul<double>(h, HSS_OP_N, nrhs, B, ldb, h->res, n, s);
-      launch_residual(h->b0, n, h->res, n, n, nrhs, s);
-      launch_fill(rr, 0.0, 2 * nrhs, s);
-      launch_fill(rmax, 0.0, nrhs, s);
-      launch_colstats(h->res, n, n, nrhs, rr, rmax, s);
-      launch_colstats(B, ldb, n, nrhs, xx, nullptr, s);
-      launch_eta(rr, xx, bb, h->norm2, nrhs, eta, outv, s);
+      launch_check(h->b0, n, h->res, n, B, ldb, n, nrhs, h->norm2, h->part, h->chk_cnt,
+                   h->d_status, bmax, outv, s);
       if ((st = last_launch_status())) return st;
-      if (hipMemcpyAsync(hp, outv, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-          hipMemcpyAsync(hp + 1, h->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
-              hipSuccess)
-        return HSS_EHIP;
-      if (copy_eta &&
-          hipMemcpyAsync(hp + 2, eta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s) !=
-              hipSuccess)
+      if (hipMemcpyAsync(hp, outv, sizeof(double) * (copy_eta ? 2 + nrhs : 2),
+                         hipMemcpyDeviceToHost, s) != hipSuccess)
         return HSS_EHIP;
       const bool spec = !is64 && iters == 0 && opt.tol > 0.0 && opt.max_refine > 0;
-      if (spec) correction_solve(h->res, n, B, ldb, true, outv);
+      if (spec) correction_solve(h->res, n, B, ldb, true, outv, true);
       if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
       eta_max = hp[0];
-      std::memcpy(&dstat, hp + 1, sizeof(int32_t));
+      dstat = (int32_t)hp[1];
       have_stat = true;
       if (copy_eta) std::memcpy(info->eta, hp + 2, sizeof(double) * nrhs);
       if (opt.tol <= 0.0 || eta_max <= opt.tol || iters >= opt.max_refine) break;
-      if (!spec) correction_solve(h->res, n, B, ldb, true);
+      if (!spec) correction_solve(h->res, n, B, ldb, true, nullptr, true);
       ++iters;
       have_stat = false;
     }
@@ -1174,8 +1167,8 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
     if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
   }
   hss_status result = HSS_OK;
-  if (dstat & (1 << HSS_ESINGULAR)) result = HSS_ESINGULAR;
   if (dstat & (1 << kStatusWaitCode)) result = HSS_EHIP;
+  else if (dstat & (1 << HSS_ESINGULAR)) result = HSS_ESINGULAR;
   else if (need_eta && opt.tol > 0.0 && eta_max > opt.tol) result = HSS_ENOCONV;
   if (info) {
     info->eta_max = eta_max;

@@ -71,6 +71,16 @@ void launch_colstats(const double* a, int64_t lda, int64_t n, int64_t nrhs, doub
 void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
                    int64_t nrhs, hipStream_t s);
 void launch_fill(double* p, double v, int64_t n, hipStream_t s);
+// Fused refinement check (residual, norms, eta, status, max |r|) and per-column
+// max |a|; part holds check_partials(nrhs) doubles, cnt one counter that
+// starts at 0 (each launch leaves it at 0).
+int check_partials(int64_t nrhs);
+void launch_check(const double* b, int64_t ldb, double* r, int64_t ldr, const double* x,
+                  int64_t ldx, int64_t n, int64_t nrhs, double normA, double* part,
+                  unsigned* cnt, const int32_t* status, double* rmax, double* out,
+                  hipStream_t s);
+void launch_colmax(const double* a, int64_t lda, int64_t n, int64_t nrhs, double* part,
+                   unsigned* cnt, double* amax, hipStream_t s);
 // dst = scale[j] * (double)src
 void launch_cast_back(const float* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
                       int64_t nrhs, const double* scale, hipStream_t s);

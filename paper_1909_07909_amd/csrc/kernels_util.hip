@@ -3,6 +3,8 @@
 // norms and the backward error of Sec. 5.1.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace hss {
@@ -137,6 +139,121 @@ __global__ void k_eta(const double* rr, const double* xx, const double* bb, doub
   }
   out[0] = mx;
 }
+// ---------------------------------------------------------------------------
+// Fused single-instance refinement bookkeeping.  Each block reduces its rows
+// into per-block partials; the last block to finish (arrival counter, which it
+// resets) reduces the partials, so neither kernel needs zeroed accumulators.
+constexpr int kChkBlocks = 128;   // blocks per column of the fused kernels
+
+__device__ __forceinline__ void block_reduce2(double& s, double& m) {
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    m = fmax(m, __shfl_xor(m, off, 64));
+  }
+  __shared__ double bs[kB / 64], bm[kB / 64];
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (l == 0) { bs[w] = s; bm[w] = m; }
+  __syncthreads();
+  s = 0.0; m = 0.0;
+  for (int q = 0; q < kB / 64; ++q) { s += bs[q]; m = fmax(m, bm[q]); }
+  __syncthreads();
+}
+
+// true in the last block to arrive (after a device-scope release of the
+// block's partials; the last block acquires everyone's)
+__device__ __forceinline__ bool last_block(unsigned* cnt, unsigned total) {
+  __shared__ unsigned s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(cnt, 1u) == total - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (s_last) __threadfence();
+  return s_last != 0;
+}
+
+// One backward-error check: r = b - r (r holds A x on entry); per column
+// ||r||^2, max |r|, ||x||^2, ||b||^2; then, in the last block,
+// eta_j = ||r_j|| / (||A|| ||x_j|| + ||b_j||) and out = [max_j eta_j,
+// status word, eta_0 .. eta_{nrhs-1}] (one contiguous block for the host),
+// and rmax_j = max |r_j| (the scale of the next correction).
+__global__ void k_check(const double* __restrict__ b, int64_t ldb, double* __restrict__ r,
+                        int64_t ldr, const double* __restrict__ x, int64_t ldx, int64_t n,
+                        int nrhs, double normA, double* part, unsigned* cnt,
+                        const int32_t* status, double* rmax, double* out) {
+  const int64_t j = blockIdx.y;
+  double sr = 0.0, mr = 0.0, sx = 0.0, sb = 0.0, dummy = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+    const double bv = b[i + j * ldb];
+    const double rv = bv - r[i + j * ldr];
+    const double xv = x[i + j * ldx];
+    r[i + j * ldr] = rv;
+    sr += rv * rv;
+    mr = fmax(mr, fabs(rv));
+    sx += xv * xv;
+    sb += bv * bv;
+  }
+  block_reduce2(sr, mr);
+  block_reduce2(sx, dummy);
+  block_reduce2(sb, dummy);
+  const int nb = gridDim.x;
+  double* pj = part + (int64_t)4 * nb * j;
+  if (threadIdx.x == 0) {
+    pj[blockIdx.x] = sr;
+    pj[nb + blockIdx.x] = mr;
+    pj[2 * nb + blockIdx.x] = sx;
+    pj[3 * nb + blockIdx.x] = sb;
+  }
+  if (!last_block(cnt, (unsigned)(nb * nrhs))) return;
+  double emax = 0.0;
+  for (int c = 0; c < nrhs; ++c) {
+    const double* pc = part + (int64_t)4 * nb * c;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int q = threadIdx.x; q < nb; q += kB) {
+      a0 += pc[q];
+      a1 = fmax(a1, pc[nb + q]);
+      a2 += pc[2 * nb + q];
+      a3 += pc[3 * nb + q];
+    }
+    block_reduce2(a0, a1);
+    block_reduce2(a2, dummy);
+    block_reduce2(a3, dummy);
+    const double den = normA * sqrt(a2) + sqrt(a3);
+    const double e = den > 0.0 ? sqrt(a0) / den : (a0 > 0.0 ? INFINITY : 0.0);
+    if (threadIdx.x == 0) {
+      out[2 + c] = e;
+      rmax[c] = a1;
+    }
+    emax = fmax(emax, e);
+  }
+  if (threadIdx.x == 0) {
+    out[0] = emax;
+    out[1] = (double)status[0];
+    *cnt = 0u;
+  }
+}
+
+// Per-column max |a| (the scale of an FP32 correction), by the same scheme.
+__global__ void k_colmax(const double* __restrict__ a, int64_t lda, int64_t n, int nrhs,
+                         double* part, unsigned* cnt, double* amax) {
+  const int64_t j = blockIdx.y;
+  double m = 0.0, dummy = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+    m = fmax(m, fabs(a[i + j * lda]));
+  block_reduce2(dummy, m);
+  const int nb = gridDim.x;
+  if (threadIdx.x == 0) part[(int64_t)nb * j + blockIdx.x] = m;
+  if (!last_block(cnt, (unsigned)(nb * nrhs))) return;
+  for (int c = 0; c < nrhs; ++c) {
+    double mm = 0.0, d2 = 0.0;
+    for (int q = threadIdx.x; q < nb; q += kB) mm = fmax(mm, part[(int64_t)nb * c + q]);
+    block_reduce2(d2, mm);
+    if (threadIdx.x == 0) amax[c] = mm;
+  }
+  if (threadIdx.x == 0) *cnt = 0u;
+}
+
 // ---------------------------------------------------------------------------
 // Refinement bookkeeping over many instances in one launch: blockIdx.y picks
 // the instance, the x dimension strides over the rows of every column.
@@ -307,6 +424,26 @@ void launch_colstats(const double* a, int64_t lda, int64_t n, int64_t nrhs, doub
 void launch_eta(const double* rr, const double* xx, const double* bb, double normA, int64_t nrhs,
                 double* eta, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_eta, dim3(1), dim3(64), 0, s, rr, xx, bb, normA, nrhs, eta, out);
+}
+
+int check_partials(int64_t nrhs) { return 4 * kChkBlocks * (int)std::max<int64_t>(nrhs, 1); }
+
+void launch_check(const double* b, int64_t ldb, double* r, int64_t ldr, const double* x,
+                  int64_t ldx, int64_t n, int64_t nrhs, double normA, double* part,
+                  unsigned* cnt, const int32_t* status, double* rmax, double* out,
+                  hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  const int nb = (int)std::min<int64_t>(kChkBlocks, (n + kB - 1) / kB);
+  hipLaunchKernelGGL(k_check, dim3(nb, nrhs), dim3(kB), 0, s, b, ldb, r, ldr, x, ldx, n,
+                     (int)nrhs, normA, part, cnt, status, rmax, out);
+}
+
+void launch_colmax(const double* a, int64_t lda, int64_t n, int64_t nrhs, double* part,
+                   unsigned* cnt, double* amax, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  const int nb = (int)std::min<int64_t>(kChkBlocks, (n + kB - 1) / kB);
+  hipLaunchKernelGGL(k_colmax, dim3(nb, nrhs), dim3(kB), 0, s, a, lda, n, (int)nrhs, part, cnt,
+                     amax);
 }
 
 }  // namespace hss
