@@ -244,6 +244,19 @@ void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T*
   if (op == HSS_OP_N) {
     // fused: leaves (with the climb), subtree walks, leaf outputs
     const int mku = h->plan.leaf_max_ku, mk = h->plan.max_k;
+    if (p > 0 && nrhs == 1 && mk <= 32) {
+      // one launch for the up pass and the leaves' D X (their blocks start as
+      // the subtree blocks finish their leaves), then the down pass, then U y^
+      const int lu = std::max(p - mmf_up_height(), 0);
+      a.node0 = level_first(lu);
+      launch_mmf<T>(MMFStep::UpDX, a, 1 << lu, (int)nrhs, mku, mk, s);
+      const int ls = std::max(p - mmf_down_height(), 0);
+      a.node0 = level_first(ls);
+      launch_mmf<T>(MMFStep::Down, a, 1 << ls, (int)nrhs, mku, mk, s);
+      a.node0 = level_first(p);
+      launch_mmf<T>(MMFStep::LeafUY, a, 1 << p, (int)nrhs, mku, mk, s);
+      return;
+    }
     if (p > 0) {
       // D X on the side stream, beside the up and down passes; U y^ after both
       const bool fork = h->side != nullptr &&

@@ -18,8 +18,10 @@ void launch_mm_level(MMStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int
 // blocks carried on by the last arrival at each node), Down over the nodes at
 // level max(p - mmf_down_height(), 0), Leaf over the leaves.  nrhs: the largest right-hand-side count of the launch; max_ku: the
 // largest leaf rank ku; max_k: the largest rank of any node.
-// Leaf: Y = D X + U y^ in one pass; LeafDX: Y = D X; LeafUY: Y += U y^
-enum class MMFStep { Up, Down, Leaf, LeafDX, LeafUY };
+// Leaf: Y = D X + U y^ in one pass; LeafDX: Y = D X; LeafUY: Y += U y^;
+// UpDX: the up pass with the leaves' Y = D X in the same launch (one rhs,
+// ranks <= 32, single instance)
+enum class MMFStep { Up, Down, Leaf, LeafDX, LeafUY, UpDX };
 template <typename T>
 void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrhs, int max_ku,
                 int max_k, hipStream_t s);

@@ -15,6 +15,8 @@
 // The per-level launches of kernels_mm.hip remain for A^T X.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_util.hpp"
 #include "kernels.hpp"
 #include "timing.hpp"
@@ -548,11 +550,66 @@ __device__ __forceinline__ float mb_empty_value<float>() {
 }
 constexpr int kMbPolls = 1 << 20;   // bound of a mailbox wait (~0.1 s); never reached in practice
 
-template <typename T, bool BATCH>
+// Y_i = D_i X_i for one leaf (one right-hand side) by a work-group of kUT
+// threads: wavefront w takes the row blocks of waves w and w + 4 of the leaf
+// kernel's layout (rows 16v .. 16v+15, lane quarter q: columns 32q .. 32q+31)
+// with the same sums in the same order, so Y matches k_mmf_leaf bit for bit.
+template <typename T>
+__device__ __forceinline__ void up_leaf_dx(const Inst<T>& I, const CallMM<T>& C, int leaf,
+                                           T* xs) {
+  const NodeInfo nd = I.nodes[leaf];
+  const int m = nd.m;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4;
+  const auto Dr = buf_rsrc(I.D + nd.oD, (uint32_t)(m * m * (int)sizeof(T)));
+  const uint32_t cs = (uint32_t)(m * (int)sizeof(T));
+  T dv[2][32];
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    const int row = 16 * (w + 4 * v) + (lane & 15);
+    const uint32_t rb = (uint32_t)(min(row, m - 1) * (int)sizeof(T));
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) {
+      const T x = buf_load<T>(Dr, rb + (uint32_t)(32 * q) * cs, (uint32_t)jj * cs);
+      dv[v][jj] = row < m ? x : T(0);
+    }
+  }
+  if (threadIdx.x < kMaxBlock) {
+    const int i = threadIdx.x;
+    const T x = C.X[nd.row0 + min(i, m - 1)];
+    xs[xrow(i)] = i < m ? x : T(0);
+  }
+  __syncthreads();
+  const T* xc = xs + xrow(32 * q);
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    const int row = 16 * (w + 4 * v) + (lane & 15);
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int jj = 0; jj < 32; jj += 2) {
+      s0 += dv[v][jj] * xc[jj];
+      s1 += dv[v][jj + 1] * xc[jj + 1];
+    }
+    T sd = s0 + s1;
+    sd += __shfl_xor(sd, 16, 64);
+    sd += __shfl_xor(sd, 32, 64);
+    if (q == 0 && row < m) C.Y[nd.row0 + row] = sd;
+  }
+}
+
+// DX: blocks a.ntasks .. a.ntasks + 2^p - 1 (dispatched after the subtree
+// blocks, so they start as those finish their leaves) form Y_i = D_i X_i.
+template <typename T, bool BATCH, bool DX>
 __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k_mmf_up1(
     KArgs<T, CallMM<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
   __shared__ unsigned s_arrive;
+  if constexpr (DX) {
+    if ((int)blockIdx.x >= a.ntasks) {
+      up_leaf_dx(a.inst, a.call, (1 << a.inst.p) - 1 + (int)blockIdx.x - a.ntasks,
+                 reinterpret_cast<T*>(smem_raw));
+      return;
+    }
+  }
   Inst<T> I; CallMM<T> C; int g;
   resolve<BATCH>(a, I, C, g);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -986,9 +1043,9 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
   const int ncu = nrhs < mcu ? nrhs : mcu;
   const bool wide = max_k > 32;
   static const char* n64[] = {"mmf_up_f64", "mmf_down_f64", "mmf_leaf_f64", "mmf_leaf_dx_f64",
-                              "mmf_leaf_uy_f64"};
+                              "mmf_leaf_uy_f64", "mmf_up_dx_f64"};
   static const char* n32[] = {"mmf_up_f32", "mmf_down_f32", "mmf_leaf_f32", "mmf_leaf_dx_f32",
-                              "mmf_leaf_uy_f32"};
+                              "mmf_leaf_uy_f32", "mmf_up_dx_f32"};
   TimedLaunch tl((sizeof(T) == 8 ? n64 : n32)[(int)step], s);
 #define HSS_MMF_UP(MC, KQ)                                                                   \
   if (batch) hipLaunchKernelGGL((k_mmf_up<T, true, MC, KQ>), dim3(nblocks), dim3(kUT), sm, s, a); \
@@ -1003,8 +1060,8 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
       const size_t sm = (size_t)(kMaxBlock + 2 * (1 << kUpH) * kMaxRank) * ncu * sizeof(T);
       if (mcu == 1 && !wide) {
         const size_t sm1 = (size_t)15 * 32 * sizeof(T);
-        if (batch) hipLaunchKernelGGL((k_mmf_up1<T, true>), dim3(nblocks), dim3(kUT), sm1, s, a);
-        else hipLaunchKernelGGL((k_mmf_up1<T, false>), dim3(nblocks), dim3(kUT), sm1, s, a);
+        if (batch) hipLaunchKernelGGL((k_mmf_up1<T, true, false>), dim3(nblocks), dim3(kUT), sm1, s, a);
+        else hipLaunchKernelGGL((k_mmf_up1<T, false, false>), dim3(nblocks), dim3(kUT), sm1, s, a);
       } else if (mcu == 1) { HSS_MMF_UP(1, 64) }
       else { if (wide) { HSS_MMF_UP(8, 64) } else { HSS_MMF_UP(8, 32) } }
       break;
@@ -1024,6 +1081,17 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
         if (batch) hipLaunchKernelGGL((k_mmf_down<T, true, 64, 1, kDC>), g, b, sm, s, a);
         else hipLaunchKernelGGL((k_mmf_down<T, false, 64, 1, kDC>), g, b, sm, s, a);
       }
+      break;
+    }
+    case MMFStep::UpDX: {
+      // (single instance, one right-hand side, ranks <= 32 only): nblocks
+      // subtree blocks, then one block per leaf
+      if (batch || nrhs != 1 || wide) break;
+      KArgs<T, CallMM<T>> b = a;
+      b.ntasks = nblocks;
+      const int nleaf = 1 << a.inst.p;
+      const size_t sm1 = (size_t)std::max(15 * 32, kXP) * sizeof(T);
+      hipLaunchKernelGGL((k_mmf_up1<T, false, true>), dim3(nblocks + nleaf), dim3(kUT), sm1, s, b);
       break;
     }
     case MMFStep::Leaf:
