@@ -999,7 +999,7 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
   launch_fill(reinterpret_cast<double*>(h->chk_cnt), 0.0, 1, s);
   {
     // product mailboxes, all empty
-    const int64_t nmb = (int64_t)P.nnodes * kMbSlot;
+    const int64_t nmb = (int64_t)P.nnodes * kMbSlot * kMbCols;
     h->w64.mb = dalloc<double>(h, nmb);
     h->w32.mb = dalloc<float>(h, nmb + 1);
     if (!h->w64.mb || !h->w32.mb) return fail(HSS_ENOMEM);

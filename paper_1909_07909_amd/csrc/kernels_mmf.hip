@@ -356,6 +356,8 @@ struct UpCoef {
   int kv1, kk, kvt;     // children's ranks (kv1, kv1 + kv2) and the node's
   int bM, bK;           // core block of this lane's half: rows, columns
   int64_t oy;           // y^ of the child this lane's half writes
+  const T* bp;          // this lane's row of the core block (b[k] = bp[min(k, bk) * bs])
+  int bs, bk;
 };
 
 // What a node's coefficient loads need from the node table: read a climb
@@ -388,7 +390,8 @@ __device__ __forceinline__ void up_meta_load(const Inst<T>& I, int t, UpMeta& m)
   m.kv2 = ld_early(&n2->kv);
 }
 
-template <typename T>
+// LOADB: load the core-block row now (else up_core_load brings it in later)
+template <typename T, bool LOADB = true>
 __device__ __forceinline__ void up_coef_issue(const Inst<T>& I, const UpMeta& m, int lane,
                                               UpCoef<T>& c) {
   const int i = lane & 31;
@@ -405,8 +408,13 @@ __device__ __forceinline__ void up_coef_issue(const Inst<T>& I, const UpMeta& m,
   const bool bv = c.bM > 0 && c.bK > 0;
   const T* br = bv ? (h ? I.B21 + m.oB21 : I.B12 + m.oB12) + min(i, c.bM - 1) : dummy;
   const int bs = bv ? c.bM : 0, bk = bv ? c.bK - 1 : 0;
+  c.bp = br;
+  c.bs = bs;
+  c.bk = bk;
+  if (LOADB) {
 #pragma unroll
-  for (int k = 0; k < 32; ++k) c.b[k] = ld_early(br + (int64_t)min(k, bk) * bs);
+    for (int k = 0; k < 32; ++k) c.b[k] = ld_early(br + (int64_t)min(k, bk) * bs);
+  }
   const bool wv = c.kvt > 0 && c.kk > 0;
   const T* wr = wv ? I.W + m.oW + min(lane, c.kk - 1) : dummy;
   const int ws = wv ? c.kk : 0, wk = wv ? c.kvt - 1 : 0;
@@ -414,11 +422,16 @@ __device__ __forceinline__ void up_coef_issue(const Inst<T>& I, const UpMeta& m,
   for (int q = 0; q < 32; ++q) c.w[q] = ld_early(wr + (int64_t)min(q, wk) * ws);
 }
 
-template <typename T>
+template <typename T, bool LOADB = true>
 __device__ __forceinline__ void up_coef_load(const Inst<T>& I, int t, int lane, UpCoef<T>& c) {
   UpMeta m;
   up_meta_load(I, t, m);
-  up_coef_issue(I, m, lane, c);
+  up_coef_issue<T, LOADB>(I, m, lane, c);
+}
+template <typename T>
+__device__ __forceinline__ void up_core_load(UpCoef<T>& c) {
+#pragma unroll
+  for (int k = 0; k < 32; ++k) c.b[k] = c.bp[(int64_t)min(k, c.bk) * c.bs];
 }
 
 // update_dpp with an old value and a bank mask (banks: lanes 4b..4b+3 of a row)
@@ -503,23 +516,118 @@ __device__ __forceinline__ T tsum32_dpp(T (&v)[32]) {
   return x + y;
 }
 
+// tsum32_dpp for v[0..15]: lanes i, i + 16, i + 32, i + 48 return the sum over
+// all 64 lanes of v[i].
+template <typename T>
+__device__ __forceinline__ T tsum16_dpp(T (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+  {
+    const bool b = (lane & 8) != 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const T send = b ? v[k] : v[8 + k], keep = b ? v[8 + k] : v[k];
+      v[k] = keep + dpp<kDppRowRor8>(send);
+    }
+  }
+  {
+    const bool b = (lane & 4) != 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const T send = b ? v[k] : v[4 + k], keep = b ? v[4 + k] : v[k];
+      const T r = dpp_old<0x114, 0xA>(dpp_old<0x104, 0x5>(T(0), send), send);
+      v[k] = keep + r;
+    }
+  }
+  {
+    const bool b = (lane & 2) != 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const T send = b ? v[k] : v[2 + k], keep = b ? v[2 + k] : v[k];
+      v[k] = keep + dpp<kDppQuadXor2>(send);
+    }
+  }
+  {
+    const bool b = (lane & 1) != 0;
+    const T send = b ? v[0] : v[1], keep = b ? v[1] : v[0];
+    v[0] = keep + dpp<kDppQuadXor1>(send);
+  }
+  T x = v[0], y = v[0];
+  plswap<false>(x, y);
+  T x2 = x + y, y2 = x + y;
+  plswap<true>(x2, y2);
+  return x2 + y2;
+}
+
+// tsum32_dpp for v[0..7]: lane l returns the sum over all 64 lanes of v[l & 7].
+template <typename T>
+__device__ __forceinline__ T tsum8_dpp(T (&v)[8]) {
+  const int lane = threadIdx.x & 63;
+  {
+    const bool b = (lane & 4) != 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const T send = b ? v[k] : v[4 + k], keep = b ? v[4 + k] : v[k];
+      const T r = dpp_old<0x114, 0xA>(dpp_old<0x104, 0x5>(T(0), send), send);
+      v[k] = keep + r;
+    }
+  }
+  {
+    const bool b = (lane & 2) != 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const T send = b ? v[k] : v[2 + k], keep = b ? v[2 + k] : v[k];
+      v[k] = keep + dpp<kDppQuadXor2>(send);
+    }
+  }
+  {
+    const bool b = (lane & 1) != 0;
+    const T send = b ? v[0] : v[1], keep = b ? v[1] : v[0];
+    v[0] = keep + dpp<kDppQuadXor1>(send);
+  }
+  T x = v[0] + dpp<kDppRowRor8>(v[0]);
+  T y = x;
+  plswap<false>(x, y);
+  T x2 = x + y, y2 = x + y;
+  plswap<true>(x2, y2);
+  return x2 + y2;
+}
+
 // Core products of node t from its children's x^ in LDS (xa: c1, xb: c2,
 // 32 entries each): y^_c1 = B12_t x^_c2 (lanes < 32), y^_c2 = B21_t x^_c1.
 template <typename T>
 __device__ __forceinline__ void up_core(const Inst<T>& I, int lane, const UpCoef<T>& c,
-                                        const T* xa, const T* xb) {
+                                        const T* xa, const T* xb, int nc = 1) {
   const int i = lane & 31;
-  const T* xo = lane >= 32 ? xa : xb;
-  T b0 = T(0), b1 = T(0);
+  for (int col = 0; col < nc; ++col) {
+    const T* xo = (lane >= 32 ? xa : xb) + 32 * col;
+    T b0 = T(0), b1 = T(0);
 #pragma unroll
-  for (int k = 0; k < 32; k += 2) {
-    b0 += c.b[k] * xo[k];
-    b1 += c.b[k + 1] * xo[k + 1];
+    for (int k = 0; k < 32; k += 2) {
+      b0 += c.b[k] * xo[k];
+      b1 += c.b[k + 1] * xo[k + 1];
+    }
+    if (i < c.bM) I.yh[c.oy + i + (int64_t)col * I.ldm] = c.bK > 0 ? b0 + b1 : T(0);
   }
-  if (i < c.bM) I.yh[c.oy + i] = c.bK > 0 ? b0 + b1 : T(0);
 }
 // x^_t[lane & 31] = (W_t^T [x^_c1; x^_c2]) (zero when W_t is empty; unused at
 // the root).  Consumes the W coefficients.
+// Column col of x^_t for several right-hand sides (keeps the coefficients).
+template <typename T>
+__device__ __forceinline__ T up_w_col(int lane, const UpCoef<T>& c, const T* xa, const T* xb,
+                                      int col) {
+  const T x1 = xa[32 * col + min(lane, 31)], x2 = xb[32 * col + min(max(lane - c.kv1, 0), 31)];
+  const T xl = lane < c.kv1 ? x1 : (lane < c.kk ? x2 : T(0));
+  // outputs 0..15, then 16..31 (lane i < 32 keeps output i)
+  T p[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) p[q] = c.w[q] * xl;
+  const T lo = tsum16_dpp(p);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) p[q] = c.w[16 + q] * xl;
+  const T hi = tsum16_dpp(p);
+  const T x = (lane & 16) ? hi : lo;
+  return c.kk > 0 ? x : T(0);
+}
 template <typename T>
 __device__ __forceinline__ T up_w(int lane, UpCoef<T>& c, const T* xa, const T* xb) {
   const T x1 = xa[min(lane, 31)], x2 = xb[min(max(lane - c.kv1, 0), 31)];
@@ -598,7 +706,10 @@ __device__ __forceinline__ void up_leaf_dx(const Inst<T>& I, const CallMM<T>& C,
 
 // DX: blocks a.ntasks .. a.ntasks + 2^p - 1 (dispatched after the subtree
 // blocks, so they start as those finish their leaves) form Y_i = D_i X_i.
-template <typename T, bool BATCH, bool DX>
+// NC > 1: up to NC right-hand sides (columns c of a slot at 32 c), the
+// products column by column with the coefficients kept, the leaves' x^ by
+// 16-column transposed sums.
+template <typename T, bool BATCH, bool DX, int NC>
 __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k_mmf_up1(
     KArgs<T, CallMM<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
@@ -613,7 +724,10 @@ __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k
   Inst<T> I; CallMM<T> C; int g;
   resolve<BATCH>(a, I, C, g);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // LDS slots of 32 entries: leaves 0-3, subtree nodes 4-6, then per climb
+  constexpr int SL = 32 * NC;                // LDS slot
+  constexpr int MB = kMbSlot * NC;           // mailbox entries per node
+  const int nc = min(NC, C.nrhs);
+  // LDS slots of SL entries: leaves 0-3, subtree nodes 4-6, then per climb
   // step s: the node's x^ in 7 + (s & 3), its sibling child's x^ in 11 + (s & 3)
   T* xs = reinterpret_cast<T*>(smem_raw);
   const int h = I.p - I.nodes[g].level;     // subtree height (<= kUpH)
@@ -632,12 +746,50 @@ __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k
   UpMeta mt;   // node table entries of this wavefront's next climb node
   {
     const int t0 = w < cnt ? sub_node(w) : (w == holder(0) ? step_node(0) : -1);
-    if (t0 >= 0) up_coef_load(I, t0, lane, cf);
+    if (t0 >= 0) up_coef_load<T, NC == 1>(I, t0, lane, cf);
     const int tm = w == holder(1) ? step_node(1) : (w == holder(2) ? step_node(2) : -1);
     if (tm >= 0) up_meta_load(I, tm, mt);
   }
   // ---- leaves: wavefront w takes leaf w; lane rows l, l + 64
-  if (w < nl) {
+  if (NC > 1 && w < nl) {
+    const int leaf = ((g + 1) << h) - 1 + w;
+    const NodeInfo nd = I.nodes[leaf];
+    const int m = nd.m, kv = nd.kv;
+    const int r0 = min(lane, m - 1), r1 = min(lane + 64, m - 1);
+    T x0[NC], x1[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const T* Xc = C.X + nd.row0 + (int64_t)min(c, nc - 1) * C.ldx;
+      x0[c] = ld_or0(Xc + r0, (lane < m) & (c < nc));
+      x1[c] = ld_or0(Xc + r1, (lane + 64 < m) & (c < nc));
+    }
+    const auto Vr = buf_rsrc(I.V + nd.oV, (uint32_t)(m * kv * (int)sizeof(T)));
+    const uint32_t cs = (uint32_t)(m * (int)sizeof(T));
+    const uint32_t o0 = (uint32_t)(r0 * (int)sizeof(T)), o1 = (uint32_t)(r1 * (int)sizeof(T));
+    T* out = xs + SL * w;
+    for (int b = 0; b < kv; b += 8) {        // 8 columns of V at a time
+      T va[8], vb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        va[u] = buf_load<T>(Vr, o0, (uint32_t)(b + u) * cs);   // columns >= kv read zero
+        vb[u] = buf_load<T>(Vr, o1, (uint32_t)(b + u) * cs);
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (c < nc) {
+          T pv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) pv[u] = va[u] * x0[c] + vb[u] * x1[c];
+          const T sv = tsum8_dpp(pv);
+          if (lane < 8) out[32 * c + b + lane] = b + lane < kv ? sv : T(0);
+        }
+      }
+    }
+    if (lane < 32)
+      for (int c = 0; c < nc; ++c)
+        if (lane >= kv) out[32 * c + lane] = T(0);
+  }
+  if (NC == 1 && w < nl) {
     const int leaf = ((g + 1) << h) - 1 + w;
     const NodeInfo nd = I.nodes[leaf];
     const int m = nd.m, kv = nd.kv;
@@ -647,7 +799,7 @@ __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k
     const auto Vr = buf_rsrc(I.V + nd.oV, (uint32_t)(m * kv * (int)sizeof(T)));
     const uint32_t cs = (uint32_t)(m * (int)sizeof(T));
     const uint32_t o0 = (uint32_t)(r0 * (int)sizeof(T)), o1 = (uint32_t)(r1 * (int)sizeof(T));
-    T* out = xs + 32 * w;
+    T* out = xs + SL * w;
     for (int b = 0; b < kv; b += 16) {       // 16 columns of V in flight
       T va[16], vb[16];
 #pragma unroll
@@ -667,19 +819,33 @@ __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   __syncthreads();
   // ---- internal nodes of the subtree, one wavefront each (core products and W)
-  T xmine = T(0);   // lanes < 32 of the wavefront that formed the latest x^: its entries
+  T xmine[NC];   // lanes < 32 of the wavefront that formed the latest x^: its entries
+#pragma unroll
+  for (int c = 0; c < NC; ++c) xmine[c] = T(0);
   for (int d = h - 1; d >= 0; --d) {
     const int qb = (1 << h) - (1 << (d + 1));         // nodes below level d
     const int q = w - qb;
     if (q >= 0 && q < (1 << d)) {
       const int t = ((g + 1) << d) - 1 + q;
       const int cs0 = d == h - 1 ? 2 * q : 4 + (qb - (1 << (d + 1))) + 2 * q;
-      const T* xa = xs + 32 * cs0;
-      const T* xb = xs + 32 * (cs0 + 1);
-      const T x = up_w(lane, cf, xa, xb);
-      xmine = lane < cf.kvt ? x : T(0);
-      if (lane < 32) xs[32 * (4 + w) + lane] = xmine;
-      up_core(I, lane, cf, xa, xb);
+      const T* xa = xs + SL * cs0;
+      const T* xb = xs + SL * (cs0 + 1);
+      if constexpr (NC == 1) {
+        const T x = up_w(lane, cf, xa, xb);
+        xmine[0] = lane < cf.kvt ? x : T(0);
+        if (lane < 32) xs[SL * (4 + w) + lane] = xmine[0];
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          if (c < nc) {
+            const T x = up_w_col(lane, cf, xa, xb, c);
+            xmine[c] = lane < cf.kvt ? x : T(0);
+            if (lane < 32) xs[SL * (4 + w) + 32 * c + lane] = xmine[c];
+          }
+        }
+      }
+      if (NC > 1) up_core_load(cf);
+      up_core(I, lane, cf, xa, xb, nc);
     }
     __syncthreads();
   }
@@ -699,9 +865,10 @@ __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k
   auto core_of = [&](int s) {   // core products of climb step s, by holder(s)
     const int ch = s == 0 ? g : step_node(s - 1);
     const bool first = (ch & 1) != 0;
-    const T* xo = xs + 32 * own_slot(s);
-    const T* xn = xs + 32 * (11 + (s & 3));
-    up_core(I, lane, cf, first ? xo : xn, first ? xn : xo);
+    const T* xo = xs + SL * own_slot(s);
+    const T* xn = xs + SL * (11 + (s & 3));
+    if (NC > 1) up_core_load(cf);
+    up_core(I, lane, cf, first ? xo : xn, first ? xn : xo, nc);
   };
   int t = g, s = 0;
   while (t > 0) {
@@ -711,39 +878,67 @@ __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k
     __syncthreads();
     const bool go = (s_arrive & 1u) != 0;
     // first arrival: x^_t (zero past its rank) into t's mailbox
-    if (!go && w == prod && lane < kMbSlot) xh_put(I.mb + (int64_t)t * kMbSlot + lane, xmine);
+    if (!go && w == prod && lane < kMbSlot) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c < nc) xh_put(I.mb + (int64_t)t * MB + 32 * c + lane, xmine[c]);
+    }
     if (s > 0 && w == holder(s - 1)) core_of(s - 1);
     if (!go) return;
     if (s == 0 && w == holder(1)) {
-      if (step_node(1) >= 0) up_coef_issue(I, mt, lane, cf);
+      if (step_node(1) >= 0) up_coef_issue<T, NC == 1>(I, mt, lane, cf);
     } else if (w == holder(s + 2)) {
-      if (step_node(s + 2) >= 0) up_coef_issue(I, mt, lane, cf);
+      if (step_node(s + 2) >= 0) up_coef_issue<T, NC == 1>(I, mt, lane, cf);
     } else if (w == holder(s + 3)) {
       if (step_node(s + 3) >= 0) up_meta_load(I, step_node(s + 3), mt);
     }
     if (w == holder(s)) {
       const bool first = (t & 1) != 0;   // t is c1 of par; the sibling is the other child
       const int sib = first ? t + 1 : t - 1;
-      T* xn = xs + 32 * (11 + (s & 3));
-      T* box = I.mb + (int64_t)sib * kMbSlot + min(lane, kMbSlot - 1);
-      T v = xh_get(box);
-      for (int it = 0; __any(mb_empty(v)); ++it) {
+      T* xn = xs + SL * (11 + (s & 3));
+      T* box = I.mb + (int64_t)sib * MB + min(lane, kMbSlot - 1);
+      T v[NC];
+      auto poll = [&]() {
+        bool empty = false;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          v[c] = c < nc ? xh_get(box + 32 * c) : T(0);
+          empty |= c < nc && mb_empty(v[c]);
+        }
+        return empty;
+      };
+      for (int it = 0; __any(poll()); ++it) {
         if (it == kMbPolls) {   // the writer never came: report, go on
           if (lane == 0) atomicOr(I.status, 1 << kStatusWaitCode);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        v = xh_get(box);
       }
       if (lane < kMbSlot) {
-        xn[lane] = v;
-        xh_put(box, mb_empty_value<T>());
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          if (c < nc) {
+            xn[32 * c + lane] = v[c];
+            xh_put(box + 32 * c, mb_empty_value<T>());
+          }
+        }
       }
       wave_lds_sync();
-      const T* xo = xs + 32 * own_slot(s);
-      const T x = up_w(lane, cf, first ? xo : xn, first ? xn : xo);
-      xmine = lane < cf.kvt ? x : T(0);
-      if (lane < 32) xs[32 * (7 + (s & 3)) + lane] = xmine;
+      const T* xo = xs + SL * own_slot(s);
+      if constexpr (NC == 1) {
+        const T x = up_w(lane, cf, first ? xo : xn, first ? xn : xo);
+        xmine[0] = lane < cf.kvt ? x : T(0);
+        if (lane < 32) xs[SL * (7 + (s & 3)) + lane] = xmine[0];
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          if (c < nc) {
+            const T x = up_w_col(lane, cf, first ? xo : xn, first ? xn : xo, c);
+            xmine[c] = lane < cf.kvt ? x : T(0);
+            if (lane < 32) xs[SL * (7 + (s & 3)) + 32 * c + lane] = xmine[c];
+          }
+        }
+      }
     }
     prod = holder(s);
     t = par;
@@ -1060,9 +1255,24 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
       const size_t sm = (size_t)(kMaxBlock + 2 * (1 << kUpH) * kMaxRank) * ncu * sizeof(T);
       if (mcu == 1 && !wide) {
         const size_t sm1 = (size_t)15 * 32 * sizeof(T);
-        if (batch) hipLaunchKernelGGL((k_mmf_up1<T, true, false>), dim3(nblocks), dim3(kUT), sm1, s, a);
-        else hipLaunchKernelGGL((k_mmf_up1<T, false, false>), dim3(nblocks), dim3(kUT), sm1, s, a);
-      } else if (mcu == 1) { HSS_MMF_UP(1, 64) }
+        if (batch) hipLaunchKernelGGL((k_mmf_up1<T, true, false, 1>), dim3(nblocks), dim3(kUT), sm1, s, a);
+        else hipLaunchKernelGGL((k_mmf_up1<T, false, false, 1>), dim3(nblocks), dim3(kUT), sm1, s, a);
+      } else if (mcu == 1) {
+        HSS_MMF_UP(1, 64)
+      } else if (!wide && (!batch || nrhs <= kMbCols)) {
+        // up to kMbCols columns per launch; a wider block in successive launches
+        const size_t sm8 = (size_t)15 * 32 * kMbCols * sizeof(T);
+        for (int c0 = 0; c0 < nrhs; c0 += kMbCols) {
+          KArgs<T, CallMM<T>> b = a;
+          if (!batch) {
+            b.call.X += (int64_t)c0 * a.call.ldx;
+            b.call.nrhs = std::min(kMbCols, nrhs - c0);
+            b.inst.yh += (int64_t)c0 * a.inst.ldm;
+          }
+          if (batch) hipLaunchKernelGGL((k_mmf_up1<T, true, false, kMbCols>), dim3(nblocks), dim3(kUT), sm8, s, b);
+          else hipLaunchKernelGGL((k_mmf_up1<T, false, false, kMbCols>), dim3(nblocks), dim3(kUT), sm8, s, b);
+        }
+      }
       else { if (wide) { HSS_MMF_UP(8, 64) } else { HSS_MMF_UP(8, 32) } }
       break;
     }
@@ -1091,7 +1301,7 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
       b.ntasks = nblocks;
       const int nleaf = 1 << a.inst.p;
       const size_t sm1 = (size_t)std::max(15 * 32, kXP) * sizeof(T);
-      hipLaunchKernelGGL((k_mmf_up1<T, false, true>), dim3(nblocks + nleaf), dim3(kUT), sm1, s, b);
+      hipLaunchKernelGGL((k_mmf_up1<T, false, true, 1>), dim3(nblocks + nleaf), dim3(kUT), sm1, s, b);
       break;
     }
     case MMFStep::Leaf:
