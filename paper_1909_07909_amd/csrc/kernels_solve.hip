@@ -447,14 +447,44 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
   }
   if (e > 0) {
     // b~ = Q^T rhs = H_0 ... H_{ku-1} rhs, H_{ku-1} applied first (lane j holds tau_j);
-    // the next reflector is read while this one is applied
+    // the next reflector is read while this one is applied; a leaf (factors
+    // in global memory, one wavefront per node) has all of them in flight at
+    // once instead
+    bool u_done = false;
+    if constexpr (!STAGED) {
+      if (ku > 0 && ku <= 32) {
+        T ua[32], ub[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+          const T* vj = S.U + min(j, ku - 1) * S.ldu;
+          ua[j] = vj[min(r0, mp - 1)];
+          ub[j] = vj[min(r1, mp - 1)];
+        }
+#pragma unroll
+        for (int j = 31; j >= 0; --j) {
+          if (j < ku) {
+            const T tau = bcast(taul, j);
+            const int pr = e + j;
+            const T v0 = r0 < pr ? ua[j] : (r0 == pr ? T(1) : T(0));
+            const T v1 = r1 < pr ? ub[j] : (r1 == pr ? T(1) : T(0));
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+              const T w = wave_sum(v0 * x0[c] + v1 * x1[c]) * tau;
+              x0[c] -= w * v0;
+              x1[c] -= w * v1;
+            }
+          }
+        }
+        u_done = true;
+      }
+    }
     T n0 = T(0), n1 = T(0);
-    if (ku > 0) {
+    if (ku > 0 && !u_done) {
       n0 = S.U[(ku - 1) * S.ldu + min(r0, mp - 1)];
       n1 = S.U[(ku - 1) * S.ldu + min(r1, mp - 1)];
     }
 #pragma unroll(STAGED ? 1 : 8)
-    for (int j = ku - 1; j >= 0; --j) {
+    for (int j = u_done ? -1 : ku - 1; j >= 0; --j) {
       const T tau = bcast(taul, j);
       const int pr = e + j;
       const T a0 = n0, a1 = n1;
@@ -475,9 +505,52 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
     const int ec = max(e - 1, 0);
     const T dg0 = S.L[min(r0, ec) * (S.ldl + 1)], dg1 = S.L[min(r1, ec) * (S.ldl + 1)];
     const T dinv0 = T(1) / dg0, dinv1 = T(1) / dg1;
+    bool l_done = false;
+    if constexpr (!STAGED) {
+      // 32 columns of L in registers, the next 32 requested before these are used
+      T la0[32], la1[32];
+#pragma unroll
+      for (int ii = 0; ii < 32; ++ii) {
+        const T* Ln = S.L + min(ii, ec) * S.ldl;
+        la0[ii] = Ln[min(r0, mp - 1)];
+        la1[ii] = Ln[min(r1, mp - 1)];
+      }
+      for (int i0 = 0; i0 < e; i0 += 32) {
+        T lb0[32], lb1[32];
+#pragma unroll
+        for (int ii = 0; ii < 32; ++ii) {
+          const T* Ln = S.L + min(i0 + 32 + ii, ec) * S.ldl;
+          lb0[ii] = Ln[min(r0, mp - 1)];
+          lb1[ii] = Ln[min(r1, mp - 1)];
+        }
+#pragma unroll
+        for (int ii = 0; ii < 32; ++ii) {
+          const int i = i0 + ii;
+          if (i < e) {
+            const T l0 = ((r0 > i) & (r0 < mp)) ? la0[ii] : T(0);
+            const T l1 = ((r1 > i) & (r1 < mp)) ? la1[ii] : T(0);
+            const T dinv = row_of(dinv0, dinv1, i);
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+              const T yi = row_of(x0[c], x1[c], i) * dinv;
+              if (r0 == i) x0[c] = yi;
+              if (r1 == i) x1[c] = yi;
+              x0[c] -= l0 * yi;
+              x1[c] -= l1 * yi;
+            }
+          }
+        }
+#pragma unroll
+        for (int ii = 0; ii < 32; ++ii) {
+          la0[ii] = lb0[ii];
+          la1[ii] = lb1[ii];
+        }
+      }
+      l_done = true;
+    }
     T m0 = S.L[min(r0, mp - 1)], m1 = S.L[min(r1, mp - 1)];
 #pragma unroll(STAGED ? 1 : 16)
-    for (int i = 0; i < e; ++i) {
+    for (int i = l_done ? e : 0; i < e; ++i) {
       const T a0 = m0, a1 = m1;
       const T* Ln = S.L + min(i + 1, ec) * S.ldl;
       m0 = Ln[min(r0, mp - 1)];
@@ -711,8 +784,52 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_bwd_w(KArgs<T, CallSV<T>> a) {
   const int ec = max(e - 1, 0);
   const T taul0 = e > 0 ? ld_or0(I.tz + nd.otz + min(r0, ec), r0 < e) : T(0);
   const T taul1 = e > 0 ? ld_or0(I.tz + nd.otz + min(r1, ec), r1 < e) : T(0);
+  bool z_done = false;
+  if constexpr (!STAGED) {
+    // factors in global memory, one wavefront per node: 32 reflectors in
+    // registers, the next 32 requested before these are applied
+    if (e > 0) {
+      T za0[32], za1[32];
+#pragma unroll
+      for (int qq = 0; qq < 32; ++qq) {
+        const T* v = Z + max(e - 1 - qq, 0) * ldz;
+        za0[qq] = v[min(r0, mp - 1)];
+        za1[qq] = v[min(r1, mp - 1)];
+      }
+      for (int q0 = 0; q0 < e; q0 += 32) {
+        T zb0[32], zb1[32];
+#pragma unroll
+        for (int qq = 0; qq < 32; ++qq) {
+          const T* v = Z + max(e - 1 - q0 - 32 - qq, 0) * ldz;
+          zb0[qq] = v[min(r0, mp - 1)];
+          zb1[qq] = v[min(r1, mp - 1)];
+        }
+#pragma unroll
+        for (int qq = 0; qq < 32; ++qq) {
+          const int i = e - 1 - q0 - qq;
+          if (i >= 0) {
+            const T tau = row_of(taul0, taul1, i);
+            const T v0 = r0 < mp ? za0[qq] : T(0);
+            const T v1 = r1 < mp ? za1[qq] : T(0);
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+              const T w = wave_sum(v0 * x0[c] + v1 * x1[c]) * tau;
+              x0[c] -= w * v0;
+              x1[c] -= w * v1;
+            }
+          }
+        }
+#pragma unroll
+        for (int qq = 0; qq < 32; ++qq) {
+          za0[qq] = zb0[qq];
+          za1[qq] = zb1[qq];
+        }
+      }
+    }
+    z_done = true;
+  }
 #pragma unroll 4
-  for (int i = e - 1; i >= 0; --i) {
+  for (int i = z_done ? -1 : e - 1; i >= 0; --i) {
     const T tau = row_of(taul0, taul1, i);
     const T* v = Z + i * ldz;
     const T a0 = v[min(r0, mp - 1)], a1 = v[min(r1, mp - 1)];
