@@ -278,17 +278,26 @@ class Server:
                 infos = hss.batch_solve(mats, blocks, prec=hss.F32, tol=tol,
                                         max_refine=self.max_refine, stream=stream)
                 t2 = time.perf_counter()
-                for dev, reqs, info in zip(blocks, splits, infos):
-                    host_out = None
+                # host requests: one copy per block into pinned memory (the
+                # caching host allocator reuses it), all issued before one wait
+                staged = []
+                for dev, reqs in zip(blocks, splits):
+                    if all(isinstance(r.B, torch.Tensor) for r in reqs):
+                        staged.append(None)
+                        continue
+                    ht = torch.empty(tuple(dev.t().shape), dtype=torch.float64, pin_memory=True)
+                    ht.copy_(dev.t(), non_blocking=True)
+                    staged.append(ht)
+                if any(ht is not None for ht in staged):
+                    stream.synchronize()
+                for dev, reqs, info, ht in zip(blocks, splits, infos, staged):
+                    host_out = ht.numpy().T if ht is not None else None
                     now = time.perf_counter()
                     c = 0
                     for r in reqs:
                         if isinstance(r.B, torch.Tensor):
                             r.X = dev[:, c:c + r.nrhs]
                         else:
-                            if host_out is None:
-                                host_out = dev.t().contiguous().cpu().numpy().T
-                                now = time.perf_counter()
                             r.X = host_out[:, c:c + r.nrhs]
                         r.eta = info["eta"][c:c + r.nrhs]
                         r.iters = info["iters"]
