@@ -16,7 +16,9 @@
 
 namespace hss {
 
-constexpr int kSW = 4;   // wavefronts per work-group
+constexpr int kSW = 4;   // wavefronts per work-group (direct sweeps)
+constexpr int kSWS = 8;  // wavefronts per work-group of the staged sweeps: one
+                         // factor block each, so the staging is one round trip
 
 template <typename T>
 __device__ __forceinline__ T bcast(T v, int src) {
@@ -381,13 +383,13 @@ __device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, const Node
 
 // Work item of this wavefront.  Direct kernels: kSW wavefronts per
 // work-group, one node each, CPW columns per wavefront.  Staged kernels: one
-// node per work-group, its kSW wavefronts take kSW * CPW consecutive columns.
+// node per work-group, its kSWS wavefronts take kSWS * CPW consecutive columns.
 template <bool BATCH, bool STAGED, int CPW, typename T>
 __device__ __forceinline__ bool sv_resolve(const KArgs<T, CallSV<T>>& a, Inst<T>& I,
                                            CallSV<T>& C, int& node, int& col0) {
   const int w = threadIdx.x >> 6;
   const int item = STAGED ? blockIdx.x : blockIdx.x * kSW + w;
-  col0 = (STAGED ? blockIdx.y * kSW + w : blockIdx.y) * CPW;
+  col0 = (STAGED ? blockIdx.y * kSWS + w : blockIdx.y) * CPW;
   if (item >= a.ntasks) return false;
   if constexpr (BATCH) {
     const int2 tk = a.tasks[item];
@@ -402,26 +404,34 @@ __device__ __forceinline__ bool sv_resolve(const KArgs<T, CallSV<T>>& a, Inst<T>
   return true;
 }
 
+// A node's record and its children's, all three reads issued together (the
+// children's from clamped indices, so that they do not wait for is_leaf);
+// a leaf's children come back empty.
+__device__ __forceinline__ void node_and_children(const NodeInfo* nodes, int nnodes, int node,
+                                                  NodeInfo& nd, NodeInfo& n1, NodeInfo& n2) {
+  const int c1 = min(2 * node + 1, nnodes - 1), c2 = min(2 * node + 2, nnodes - 1);
+  nd = nodes[node];
+  const NodeInfo a1 = nodes[c1], a2 = nodes[c2];
+  n1 = nd.is_leaf ? NodeInfo{} : a1;
+  n2 = nd.is_leaf ? NodeInfo{} : a2;
+}
+
 // Forward sweep at one node.  STAGED: the node's factors are copied to LDS by
 // the whole work-group first (internal nodes); otherwise kSW wavefronts per
 // work-group read the factor arrays (leaves).  Each wavefront carries CPW
 // right-hand-side columns through the same factor reads.
 template <typename T, bool BATCH, bool STAGED, int CPW>
-__global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
+__global__ __launch_bounds__((STAGED ? kSWS : kSW) * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
   Inst<T> I; CallSV<T> C; int node, col0;
   if (!sv_resolve<BATCH, STAGED, CPW>(a, I, C, node, col0)) return;   // uniform when STAGED
   const int lane = threadIdx.x & 63;
-  const NodeInfo nd = I.nodes[node];
+  // the node's and children's records, read once (reads after a barrier are
+  // not merged with those before it)
+  NodeInfo nd, n1, n2;
+  node_and_children(I.nodes, I.nnodes, node, nd, n1, n2);
   const int mp = nd.mp, e = nd.e, ku = nd.ku, kv = nd.kv;
   const int r0 = lane, r1 = lane + 64;
-  // the children's records, read once (reads after a barrier are not merged
-  // with those before it)
-  NodeInfo n1{}, n2{};
-  if (!nd.is_leaf) {
-    n1 = I.nodes[2 * node + 1];
-    n2 = I.nodes[2 * node + 2];
-  }
   NodeSrc<T> S;
   Gathered<T, CPW> G;
   if (!nd.is_leaf) gather_load<T, CPW>(I, nd, n1, n2, col0, C.nrhs, lane, G);   // before the staging
@@ -657,12 +667,13 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
 // Root: rhs from the children, then the FP64 LU of the merged root block
 // (staged in LDS with its pivots), split into the children's x^.
 template <typename T, bool BATCH, int CPW>
-__global__ __launch_bounds__(kSW * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
+__global__ __launch_bounds__(kSWS * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
   Inst<T> I; CallSV<T> C; int node, col0;
   if (!sv_resolve<BATCH, true, CPW>(a, I, C, node, col0)) return;
   const int lane = threadIdx.x & 63;
-  const NodeInfo nd = I.nodes[node];
+  NodeInfo nd, n1, n2;
+  node_and_children(I.nodes, I.nnodes, node, nd, n1, n2);
   const int mp = nd.mp;
   const int r0 = lane, r1 = lane + 64;
   double* LU = reinterpret_cast<double*>(smem_raw);
@@ -670,11 +681,6 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
   T* rest = reinterpret_cast<T*>(piv + ((mp + 3) & ~3));
   stage_block(LU, mp, mp, [&](int i, int j) { return I.rootLU[i + j * mp]; });
   for (int o = threadIdx.x; o < mp; o += blockDim.x) piv[o] = I.piv[o];   // (mp <= 128 < blockDim)
-  NodeInfo n1{}, n2{};
-  if (!nd.is_leaf) {
-    n1 = I.nodes[2 * node + 1];
-    n2 = I.nodes[2 * node + 2];
-  }
   NodeSrc<T> S = (nd.is_leaf || !(a.flags & 1)) ? src_global(I, nd, n1, n2)
                                                  : src_stage_fwd(I, nd, n1, n2, rest);
   __syncthreads();
@@ -752,7 +758,7 @@ __global__ __launch_bounds__(kSW * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) {
 }
 
 template <typename T, bool BATCH, bool STAGED, int CPW>
-__global__ __launch_bounds__(kSW * 64) void k_sv_bwd_w(KArgs<T, CallSV<T>> a) {
+__global__ __launch_bounds__((STAGED ? kSWS : kSW) * 64) void k_sv_bwd_w(KArgs<T, CallSV<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
   Inst<T> I; CallSV<T> C; int node, col0;
   if (!sv_resolve<BATCH, STAGED, CPW>(a, I, C, node, col0)) return;
@@ -881,7 +887,7 @@ void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int 
   const int cpw = ncols >= 4 ? 4 : 1;
   const int cgroups = (ncols + cpw - 1) / cpw;
   dim3 gridw((nitems + kSW - 1) / kSW, cgroups), blockw(kSW * 64);
-  dim3 grid1(nitems, (cgroups + kSW - 1) / kSW), block1(kSW * 64);
+  dim3 grid1(nitems, (cgroups + kSWS - 1) / kSWS), block1(kSWS * 64);
 #define HSS_SL(K, ST, CP, G, B)                                                   \
   if (batch) hipLaunchKernelGGL((K<T, true, ST, CP>), G, B, sm, s, b);            \
   else hipLaunchKernelGGL((K<T, false, ST, CP>), G, B, sm, s, b);
