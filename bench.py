@@ -180,6 +180,38 @@ def main():
     rt64, re64 = timed(step_resident, K, W, hss.F64, 0.0)
     log(f"[bench] resident FP32+IR {rt32*1e3:.3f} ms, FP64 {rt64*1e3:.3f} ms")
 
+    # the same fresh-system solves with a block of 32 right-hand sides
+    wide = None
+    if r == 1:
+        rw = 32
+        Bw = [torch.from_numpy(np.ascontiguousarray(inputs.rhs(N, rw, 50 + i).T)).to(dev).t()
+              for i in range(len(mats))]
+        Ww = [hss.empty_colmajor(N, rw, torch.float64) for _ in mats]
+
+        def step_wide(i, prec, tol):
+            A = mats[i % len(mats)]
+            X = Ww[i % len(mats)]
+            X.copy_(Bw[i % len(mats)])
+            A.factor(prec)
+            if prec == hss.F32:
+                return A.solve(X, prec=hss.F32, tol=tol, max_refine=10)
+            return A.solve(X, prec=hss.F64, want_eta=True)
+
+        kw = max(K // 2, 3)
+        w32, ew32 = timed(step_wide, kw, W, hss.F32, 1e-10)
+        w64, ew64 = timed(step_wide, kw, W, hss.F64, 0.0)
+        wide = {"nrhs": rw, "steps": kw,
+                "fp32ir": {"solves_per_s": round(1.0 / w32, 2), "ms": round(w32 * 1e3, 3),
+                           "eta_max": max(e for e, _ in ew32),
+                           "refine_iters_max": max(i for _, i in ew32)},
+                "fp64": {"solves_per_s": round(1.0 / w64, 2), "ms": round(w64 * 1e3, 3),
+                         "eta_max": max(e for e, _ in ew64)},
+                "ratio_fp32ir_over_fp64": round(w64 / w32, 3)}
+        log(f"[bench] fresh r={rw}: FP32+IR {w32*1e3:.3f} ms (eta_max "
+            f"{wide['fp32ir']['eta_max']:.2e}), FP64 {w64*1e3:.3f} ms (eta_max "
+            f"{wide['fp64']['eta_max']:.2e})")
+        del Bw, Ww
+
     # FP64 product at 1 and 32 right-hand sides (GB/s of algorithmic bytes)
     mm = {}
     for rr in (1, 32):
@@ -269,6 +301,7 @@ def main():
         "fp64_solves_per_s": round(1.0 / t64, 2), "fp64_eta_max": max(e for e, _ in e64),
         "ratio_fp32ir_over_fp64": round(t64 / t32, 3),
         "resident_solves_per_s": {"fp32ir": round(1.0 / rt32, 2), "fp64": round(1.0 / rt64, 2)},
+        "fresh_nrhs32": wide,
         "matmul_fp64": mm,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -56,7 +56,7 @@ struct hss_handle {
   Work<double> w64;
   Work<float> w32;
   int32_t* d_status = nullptr;
-  uint32_t* d_cnt = nullptr;   // arrival counters of the fused product, one per node
+  uint32_t* d_cnt = nullptr;   // arrival counters of the fused product, one per node and column chunk
   // refinement / norm work
   double *b0 = nullptr, *res = nullptr, *d64 = nullptr;
   float* r32 = nullptr;
@@ -977,7 +977,7 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
     return fail(HSS_EHIP);
   h->d_nodes = dalloc<NodeInfo>(h, P.nnodes);
   h->d_status = dalloc<int32_t>(h, 4);
-  h->d_cnt = dalloc<uint32_t>(h, (P.nnodes + 2) & ~1);
+  h->d_cnt = dalloc<uint32_t>(h, (int64_t)((P.nnodes + 2) & ~1) * kMbChunks);
   h->chk_cnt = dalloc<uint32_t>(h, 2);
   if (!h->d_nodes || !h->d_status || !h->d_cnt || !h->chk_cnt) return fail(HSS_ENOMEM);
   if (hipMemcpyAsync(h->d_nodes, P.nodes.data(), sizeof(NodeInfo) * P.nnodes,
@@ -995,11 +995,11 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
     }
   }
   launch_fill(reinterpret_cast<double*>(h->d_status), 0.0, 2, s);
-  launch_fill(reinterpret_cast<double*>(h->d_cnt), 0.0, (P.nnodes + 2) / 2, s);
+  launch_fill(reinterpret_cast<double*>(h->d_cnt), 0.0, (int64_t)((P.nnodes + 2) / 2) * kMbChunks, s);
   launch_fill(reinterpret_cast<double*>(h->chk_cnt), 0.0, 1, s);
   {
-    // product mailboxes, all empty
-    const int64_t nmb = (int64_t)P.nnodes * kMbSlot * kMbCols;
+    // product mailboxes (one set per column chunk), all empty
+    const int64_t nmb = (int64_t)P.nnodes * kMbSlot * kMbCols * kMbChunks;
     h->w64.mb = dalloc<double>(h, nmb);
     h->w32.mb = dalloc<float>(h, nmb + 1);
     if (!h->w64.mb || !h->w32.mb) return fail(HSS_ENOMEM);

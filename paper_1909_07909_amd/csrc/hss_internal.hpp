@@ -54,7 +54,9 @@ struct NodeInfo {
 constexpr uint64_t kMbEmpty64 = 0x7FF4A5A5A5A5A5A5ull;
 constexpr uint32_t kMbEmpty32 = 0x7FA5A5A5u;
 constexpr int kMbSlot = 32;   // mailbox entries per node and right-hand side
-constexpr int kMbCols = 8;    // right-hand sides per product launch through the mailboxes
+constexpr int kMbCols = 8;    // right-hand sides per work-group of the mailbox product
+constexpr int kMbChunks = 4;  // column chunks of kMbCols one product launch takes side by
+                              // side, each with its own arrival counters and mailboxes
 // Status bit (1 << code) set by a kernel whose bounded wait for another
 // work-group ran out; the code is HSS_EHIP.
 constexpr int kStatusWaitCode = 2;

@@ -723,6 +723,17 @@ __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   Inst<T> I; CallMM<T> C; int g;
   resolve<BATCH>(a, I, C, g);
+  if constexpr (!BATCH && NC > 1) {
+    // column chunk blockIdx.y (the grid has no empty chunk): its columns, and
+    // arrival counters and mailboxes of its own, so that the chunks climb
+    // side by side
+    const int y = blockIdx.y;
+    C.X += (int64_t)y * NC * C.ldx;
+    C.nrhs -= y * NC;
+    I.yh += (int64_t)y * NC * I.ldm;
+    I.cnt += (int64_t)y * ((I.nnodes + 2) & ~1);
+    I.mb += (int64_t)y * I.nnodes * kMbSlot * kMbCols;
+  }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int SL = 32 * NC;                // LDS slot
   constexpr int MB = kMbSlot * NC;           // mailbox entries per node
@@ -1260,17 +1271,21 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
       } else if (mcu == 1) {
         HSS_MMF_UP(1, 64)
       } else if (!wide && (!batch || nrhs <= kMbCols)) {
-        // up to kMbCols columns per launch; a wider block in successive launches
+        // up to kMbChunks chunks of kMbCols columns per launch (grid.y), a
+        // wider block in successive launches; batched: one chunk
         const size_t sm8 = (size_t)15 * 32 * kMbCols * sizeof(T);
-        for (int c0 = 0; c0 < nrhs; c0 += kMbCols) {
+        const int span = kMbCols * kMbChunks;
+        for (int c0 = 0; c0 < nrhs; c0 += batch ? nrhs : span) {
           KArgs<T, CallMM<T>> b = a;
+          int ny = 1;
           if (!batch) {
             b.call.X += (int64_t)c0 * a.call.ldx;
-            b.call.nrhs = std::min(kMbCols, nrhs - c0);
+            b.call.nrhs = std::min(span, nrhs - c0);
             b.inst.yh += (int64_t)c0 * a.inst.ldm;
+            ny = (b.call.nrhs + kMbCols - 1) / kMbCols;
           }
           if (batch) hipLaunchKernelGGL((k_mmf_up1<T, true, false, kMbCols>), dim3(nblocks), dim3(kUT), sm8, s, b);
-          else hipLaunchKernelGGL((k_mmf_up1<T, false, false, kMbCols>), dim3(nblocks), dim3(kUT), sm8, s, b);
+          else hipLaunchKernelGGL((k_mmf_up1<T, false, false, kMbCols>), dim3(nblocks, ny), dim3(kUT), sm8, s, b);
         }
       }
       else { if (wide) { HSS_MMF_UP(8, 64) } else { HSS_MMF_UP(8, 32) } }
