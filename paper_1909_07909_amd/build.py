@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhss.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["plan.cpp", "timing.cpp", "hss_capi.cpp", "kernels_util.hip", "kernels_mm.hip", "kernels_mmf.hip", "kernels_ulv.hip",
+SOURCES = ["plan.cpp", "timing.cpp", "hss_capi.cpp", "kernels_util.hip", "kernels_mm.hip", "kernels_mmf.hip", "kernels_mmw.hip", "kernels_ulv.hip",
            "kernels_factor.hip", "kernels_factor_blk.hip", "kernels_solve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

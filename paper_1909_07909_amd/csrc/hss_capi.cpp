@@ -257,6 +257,24 @@ void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T*
       launch_mmf<T>(MMFStep::LeafUY, a, 1 << p, (int)nrhs, mku, mk, s);
       return;
     }
+    if (p > 0 && nrhs > kMbCols && mmw_fits(h->plan.level_max_mp[p], mk)) {
+      // blocks wider than the batched product's (whose sums at up to kMbCols
+      // columns the single-instance call repeats bit for bit): one launch
+      // per level
+      a.node0 = level_first(p);
+      launch_mmw<T>(MMWStep::LeafUp, a, 1 << p, (int)nrhs, s);
+      for (int l = p - 1; l >= 0; --l) {
+        a.node0 = level_first(l);
+        launch_mmw<T>(MMWStep::Up, a, 1 << l, (int)nrhs, s);
+      }
+      for (int l = 1; l <= p - 1; ++l) {
+        a.node0 = level_first(l);
+        launch_mmw<T>(MMWStep::Down, a, 1 << l, (int)nrhs, s);
+      }
+      a.node0 = level_first(p);
+      launch_mmw<T>(MMWStep::LeafOut, a, 1 << p, (int)nrhs, s);
+      return;
+    }
     if (p > 0) {
       // D X on the side stream, beside the up and down passes; U y^ after both
       const bool fork = h->side != nullptr &&

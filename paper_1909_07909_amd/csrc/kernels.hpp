@@ -28,6 +28,15 @@ void launch_mmf(MMFStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
 int mmf_down_height();
 int mmf_up_height();
 
+// Y = A X for blocks of right-hand sides, one launch per level
+// (kernels_mmw.hip): LeafUp over the leaves, Up over levels p-1 .. 0, Down
+// over levels 1 .. p-1, LeafOut over the leaves.  Single instance, op N,
+// leaves <= 128 rows and ranks <= 32 (mmw_fits).
+enum class MMWStep { LeafUp, Up, Down, LeafOut };
+bool mmw_fits(int max_leaf, int max_k);
+template <typename T>
+void launch_mmw(MMWStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrhs,
+                hipStream_t s);
 enum class UlvStep { Merge, Factor, RootLU, Fwd, Root, Bwd };
 
 // Step 1 (QL / LQ) on one level of blocks, register-resident (kernels_factor.hip).

@@ -1,0 +1,280 @@
+// HSS matrix x block product Y = A X (Sec. 4.1) for blocks of several
+// right-hand sides, one launch per tree level:
+//   leaf up   x^_i = V_i^T X_i                                  (leaves)
+//   up        x^_t = W_t^T [x^_c1; x^_c2] (below the root) and the core
+//             blocks y^_c1 = B12_t x^_c2, y^_c2 = B21_t x^_c1    (levels p-1 .. 0)
+//   down      [y^_c1; y^_c2] += R_t y^_t                         (levels 1 .. p-1)
+//   leaf out  Y_i = D_i X_i + U_i y^_i                           (leaves)
+// Every work-group stages the operands of its node (and column tile) in LDS
+// with all global reads in flight together, then forms its outputs as dot
+// products out of LDS.  The leaf-out kernel streams D_i and U_i once per
+// 32-column tile: thread (row r, half h) keeps row r of 16 output columns in
+// registers, reads D_i and U_i coalesced down their columns and takes the
+// X / y^ entries as LDS broadcasts.  Ranks <= 32 and leaves <= 128 rows.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_util.hpp"
+#include "kernels.hpp"
+#include "timing.hpp"
+
+namespace hss {
+
+namespace {
+
+constexpr int kWT = 256;   // threads of every kernel here
+constexpr int kWR = 32;    // largest rank
+constexpr int kWC = 16;    // right-hand-side columns per tile of the level kernels
+constexpr int kWL = 32;    // right-hand-side columns per tile of the leaf-out kernel
+
+// Node t of the launch: a level is a contiguous heap range from node0.
+template <typename T>
+__device__ __forceinline__ int wnode(const KArgs<T, CallMM<T>>& a) {
+  return a.node0 + (int)blockIdx.x;
+}
+
+// Stage a rows x cols block (element (i, j) at src[i + j*ld]) into LDS at
+// dst[i*lr + j] (TR) or dst[i + j*lr]: NPT elements per thread, every load
+// issued (from a clamped, valid address) before the first store.
+template <typename T, int NPT, bool TR>
+struct Stage {
+  T v[NPT];
+  __device__ __forceinline__ void load(const T* src, int64_t ld, int rows, int cols) {
+    const int total = rows * cols;
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const int o = min((int)threadIdx.x + u * kWT, max(total - 1, 0));
+      const int i = o % max(rows, 1), j = o / max(rows, 1);
+      v[u] = total > 0 ? src[i + j * ld] : T(0);
+    }
+  }
+  __device__ __forceinline__ void store(T* dst, int lr, int rows, int cols) const {
+    const int total = rows * cols;
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const int o = (int)threadIdx.x + u * kWT;
+      if (o < total) {
+        const int i = o % rows, j = o / rows;
+        dst[TR ? i * lr + j : i + j * lr] = v[u];
+      }
+    }
+  }
+};
+
+// x^_i = V_i^T X_i for leaf i and columns c0 .. c0 + kWC - 1.
+template <typename T>
+__global__ __launch_bounds__(kWT) void k_mmw_leaf_up(KArgs<T, CallMM<T>> a) {
+  __shared__ T Vs[kMaxBlock * (kWR + 1)];   // Vs[k][a] (row k of V)
+  __shared__ T Xs[kMaxBlock * (kWC + 1)];   // Xs[k][c]
+  const Inst<T>& I = a.inst;
+  const CallMM<T>& C = a.call;
+  const int t = wnode(a), c0 = blockIdx.y * kWC;
+  const NodeInfo nd = I.nodes[t];
+  const int m = nd.m, kv = nd.kv, nc = min(kWC, C.nrhs - c0);
+  {
+    Stage<T, kMaxBlock * kWR / kWT, true> sv;
+    Stage<T, kMaxBlock * kWC / kWT, true> sx;
+    sv.load(I.V + nd.oV, m, m, kv);
+    sx.load(C.X + nd.row0 + (int64_t)c0 * C.ldx, C.ldx, m, nc);
+    sv.store(Vs, kWR + 1, m, kv);
+    sx.store(Xs, kWC + 1, m, nc);
+  }
+  __syncthreads();
+  // thread (r = tid % 32, column pair tid / 32): x^[r, 2q], x^[r, 2q + 1]
+  const int r = threadIdx.x & 31, q = threadIdx.x >> 5;
+  T s0 = T(0), s1 = T(0);
+  for (int k = 0; k < m; ++k) {
+    const T v = Vs[k * (kWR + 1) + r];
+    s0 += v * Xs[k * (kWC + 1) + 2 * q];
+    s1 += v * Xs[k * (kWC + 1) + 2 * q + 1];
+  }
+  T* xo = I.xh + nd.oxh + (int64_t)c0 * I.ldm;
+  if (r < kv) {
+    if (2 * q < nc) xo[r + (int64_t)(2 * q) * I.ldm] = s0;
+    if (2 * q + 1 < nc) xo[r + (int64_t)(2 * q + 1) * I.ldm] = s1;
+  }
+}
+
+// Node t at one level: x^_t = W_t^T [x^_c1; x^_c2] below the root, and the
+// core blocks y^_c1 = B12_t x^_c2, y^_c2 = B21_t x^_c1.
+template <typename T>
+__global__ __launch_bounds__(kWT) void k_mmw_up(KArgs<T, CallMM<T>> a) {
+  __shared__ T Xs[2 * kWR * (kWC + 1)];      // [x^_c1; x^_c2], row j at j*(kWC+1)
+  __shared__ T Ws[2 * kWR * (kWR + 1)];      // Ws[j][b] = W_t(j, b)
+  __shared__ T Bs[2 * kWR * (kWR + 1)];      // B12 rows 0..ku1-1, then B21
+  const Inst<T>& I = a.inst;
+  const CallMM<T>& C = a.call;
+  const int t = wnode(a), c0 = blockIdx.y * kWC;
+  const NodeInfo nd = I.nodes[t], n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
+  const int kv1 = n1.kv, kv2 = n2.kv, ku1 = n1.ku, ku2 = n2.ku, kw = kv1 + kv2;
+  const int kv = t > 0 ? nd.kv : 0;
+  const int nc = min(kWC, C.nrhs - c0);
+  {
+    constexpr int NX = kWR * kWC / kWT, NW = 2 * kWR * kWR / kWT, NB = kWR * kWR / kWT;
+    Stage<T, NX, true> x1, x2;
+    Stage<T, NW, true> sw;
+    Stage<T, NB, true> b12, b21;
+    x1.load(I.xh + n1.oxh + (int64_t)c0 * I.ldm, I.ldm, kv1, nc);
+    x2.load(I.xh + n2.oxh + (int64_t)c0 * I.ldm, I.ldm, kv2, nc);
+    sw.load(I.W + (kv > 0 ? nd.oW : 0), kw, kw, kv);
+    b12.load(I.B12 + nd.oB12, ku1, ku1, kv2);
+    b21.load(I.B21 + nd.oB21, ku2, ku2, kv1);
+    x1.store(Xs, kWC + 1, kv1, nc);
+    x2.store(Xs + kv1 * (kWC + 1), kWC + 1, kv2, nc);
+    sw.store(Ws, kWR + 1, kw, kv);
+    b12.store(Bs, kWR + 1, ku1, kv2);
+    b21.store(Bs + ku1 * (kWR + 1), kWR + 1, ku2, kv1);
+  }
+  __syncthreads();
+  // outputs: rows 0..kv-1 of x^_t, then ku1 rows of y^_c1, then ku2 of y^_c2
+  const int rows = kv + ku1 + ku2;
+  for (int o = threadIdx.x; o < rows * kWC; o += kWT) {
+    const int i = o % rows, c = o / rows;
+    if (c >= nc) continue;
+    T s = T(0);
+    if (i < kv) {
+      for (int j = 0; j < kw; ++j) s += Ws[j * (kWR + 1) + i] * Xs[j * (kWC + 1) + c];
+      I.xh[nd.oxh + i + (int64_t)(c0 + c) * I.ldm] = s;
+    } else if (i < kv + ku1) {
+      const int b = i - kv;
+      const T* xb = Xs + kv1 * (kWC + 1) + c;
+      for (int j = 0; j < kv2; ++j) s += Bs[b * (kWR + 1) + j] * xb[j * (kWC + 1)];
+      I.yh[n1.oyh + b + (int64_t)(c0 + c) * I.ldm] = s;
+    } else {
+      const int b = i - kv - ku1;
+      const T* xa = Xs + c;
+      for (int j = 0; j < kv1; ++j) s += Bs[(ku1 + b) * (kWR + 1) + j] * xa[j * (kWC + 1)];
+      I.yh[n2.oyh + b + (int64_t)(c0 + c) * I.ldm] = s;
+    }
+  }
+}
+
+// Node t below the root: [y^_c1; y^_c2] += R_t y^_t.
+template <typename T>
+__global__ __launch_bounds__(kWT) void k_mmw_down(KArgs<T, CallMM<T>> a) {
+  __shared__ T Ys[kWR * (kWC + 1)];          // y^_t, row j at j*(kWC+1)
+  __shared__ T Rs[2 * kWR * (kWR + 1)];      // Rs[i][j] = R_t(i, j)
+  const Inst<T>& I = a.inst;
+  const CallMM<T>& C = a.call;
+  const int t = wnode(a), c0 = blockIdx.y * kWC;
+  const NodeInfo nd = I.nodes[t], n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
+  const int ku = nd.ku, ku1 = n1.ku, ku2 = n2.ku, kr = ku1 + ku2;
+  const int nc = min(kWC, C.nrhs - c0);
+  {
+    Stage<T, kWR * kWC / kWT, true> sy;
+    Stage<T, 2 * kWR * kWR / kWT, true> sr;
+    sy.load(I.yh + nd.oyh + (int64_t)c0 * I.ldm, I.ldm, ku, nc);
+    sr.load(I.R + nd.oR, kr, kr, ku);
+    sy.store(Ys, kWC + 1, ku, nc);
+    sr.store(Rs, kWR + 1, kr, ku);
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < kr * kWC; o += kWT) {
+    const int i = o % kr, c = o / kr;
+    if (c >= nc) continue;
+    T s = T(0);
+    for (int j = 0; j < ku; ++j) s += Rs[i * (kWR + 1) + j] * Ys[j * (kWC + 1) + c];
+    T* yc = i < ku1 ? I.yh + n1.oyh + i : I.yh + n2.oyh + (i - ku1);
+    yc[(int64_t)(c0 + c) * I.ldm] += s;
+  }
+}
+
+// Y_i = D_i X_i + U_i y^_i for leaf i and columns c0 .. c0 + kWL - 1: thread
+// (r = tid % 128, h = tid / 128) forms row r of columns 16h .. 16h + 15.
+template <typename T>
+__global__ __launch_bounds__(kWT) void k_mmw_leaf_out(KArgs<T, CallMM<T>> a) {
+  constexpr int XL = kWL + 2;                // LDS row: 16-byte aligned halves
+  __shared__ __align__(16) T Xs[kMaxBlock * XL];
+  __shared__ __align__(16) T Ys[kWR * XL];
+  const Inst<T>& I = a.inst;
+  const CallMM<T>& C = a.call;
+  const int t = wnode(a), c0 = blockIdx.y * kWL;
+  const NodeInfo nd = I.nodes[t];
+  const int m = nd.m, ku = I.p > 0 ? nd.ku : 0, nc = min(kWL, C.nrhs - c0);
+  {
+    Stage<T, kMaxBlock * kWL / kWT, true> sx;
+    Stage<T, kWR * kWL / kWT, true> sy;
+    sx.load(C.X + nd.row0 + (int64_t)c0 * C.ldx, C.ldx, m, nc);
+    sy.load(I.yh + nd.oyh + (int64_t)c0 * I.ldm, I.ldm, ku, nc);
+    // columns past nc read as zero
+    for (int o = threadIdx.x; o < kMaxBlock * XL; o += kWT) Xs[o] = T(0);
+    for (int o = threadIdx.x; o < kWR * XL; o += kWT) Ys[o] = T(0);
+    __syncthreads();
+    sx.store(Xs, XL, m, nc);
+    sy.store(Ys, XL, ku, nc);
+  }
+  __syncthreads();
+  const int r = threadIdx.x & (kMaxBlock - 1), h = threadIdx.x / kMaxBlock;
+  const int rc = min(r, m - 1);
+  T acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = T(0);
+  const T* Dr = I.D + nd.oD + rc;
+  constexpr int KB = 16;   // columns of D in flight
+  T dv[KB];
+#pragma unroll
+  for (int u = 0; u < KB; ++u) dv[u] = Dr[(int64_t)min(u, m - 1) * m];
+  for (int k0 = 0; k0 < m; k0 += KB) {
+    T dn[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) dn[u] = Dr[(int64_t)min(k0 + KB + u, m - 1) * m];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int k = k0 + u;
+      const T d = k < m ? dv[u] : T(0);
+      const T* xk = Xs + min(k, kMaxBlock - 1) * XL + 16 * h;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc[c] += d * xk[c];
+    }
+#pragma unroll
+    for (int u = 0; u < KB; ++u) dv[u] = dn[u];
+  }
+  if (ku > 0) {
+    const T* Ur = I.U + nd.oU + rc;
+    T uv[kWR];
+#pragma unroll
+    for (int j = 0; j < kWR; ++j) uv[j] = Ur[(int64_t)min(j, ku - 1) * m];
+#pragma unroll
+    for (int j = 0; j < kWR; ++j) {
+      const T u = j < ku ? uv[j] : T(0);
+      const T* yk = Ys + j * XL + 16 * h;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc[c] += u * yk[c];
+    }
+  }
+  if (r < m) {
+    T* Yr = C.Y + nd.row0 + r;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (16 * h + c < nc) Yr[(int64_t)(c0 + 16 * h + c) * C.ldy] = acc[c];
+  }
+}
+
+}  // namespace
+
+bool mmw_fits(int max_leaf, int max_k) { return max_leaf <= kMaxBlock && max_k <= kWR; }
+
+template <typename T>
+void launch_mmw(MMWStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrhs,
+                hipStream_t s) {
+  if (nblocks <= 0 || nrhs <= 0) return;
+  static const char* n64[] = {"mmw_leaf_up_f64", "mmw_up_f64", "mmw_down_f64", "mmw_leaf_out_f64"};
+  static const char* n32[] = {"mmw_leaf_up_f32", "mmw_up_f32", "mmw_down_f32", "mmw_leaf_out_f32"};
+  TimedLaunch tl((sizeof(T) == 8 ? n64 : n32)[(int)step], s);
+  const dim3 b(kWT);
+  const dim3 g(nblocks, (nrhs + kWC - 1) / kWC), gl(nblocks, (nrhs + kWL - 1) / kWL);
+  switch (step) {
+    case MMWStep::LeafUp: hipLaunchKernelGGL((k_mmw_leaf_up<T>), g, b, 0, s, a); break;
+    case MMWStep::Up: hipLaunchKernelGGL((k_mmw_up<T>), g, b, 0, s, a); break;
+    case MMWStep::Down: hipLaunchKernelGGL((k_mmw_down<T>), g, b, 0, s, a); break;
+    case MMWStep::LeafOut: hipLaunchKernelGGL((k_mmw_leaf_out<T>), gl, b, 0, s, a); break;
+  }
+}
+
+template void launch_mmw<double>(MMWStep, const KArgs<double, CallMM<double>>&, int, int,
+                                 hipStream_t);
+template void launch_mmw<float>(MMWStep, const KArgs<float, CallMM<float>>&, int, int,
+                                hipStream_t);
+
+}  // namespace hss
