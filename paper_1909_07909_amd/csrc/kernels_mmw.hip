@@ -62,11 +62,26 @@ struct Stage {
   }
 };
 
-// x^_i = V_i^T X_i for leaf i and columns c0 .. c0 + kWC - 1.
+// LDS row of a kWC-column tile: 16-byte aligned halves of eight columns.
+constexpr int kXR = kWC + 2;
+
+// s[c] += coef * x[c] for the eight columns of one half-tile row (two 16-byte
+// LDS reads, the same address for every lane of the wavefront).
+template <typename T>
+__device__ __forceinline__ void axpy8(T (&s)[8], T coef, const T* x) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s[c] += coef * x[c];
+}
+
+// x^_i = V_i^T X_i for leaf i and columns c0 .. c0 + kWC - 1: wavefront w sums
+// rows 32w .. 32w + 31 of V and X; lane (a = lane % 32, half h = lane / 32)
+// keeps x^[a, 8h .. 8h + 7]; the four partial sums meet in LDS.
 template <typename T>
 __global__ __launch_bounds__(kWT) void k_mmw_leaf_up(KArgs<T, CallMM<T>> a) {
-  __shared__ T Vs[kMaxBlock * (kWR + 1)];   // Vs[k][a] (row k of V)
-  __shared__ T Xs[kMaxBlock * (kWC + 1)];   // Xs[k][c]
+  __shared__ T Vs[kMaxBlock * (kWR + 1)];              // Vs[k][a] (row k of V)
+  __shared__ __align__(16) T Xs[kMaxBlock * kXR];       // Xs[k][c]
+  T* Ps = Vs;   // the four partial sums, once V has been read
+  static_assert(4 * kWR * kWC <= kMaxBlock * (kWR + 1), "partial sums fit in Vs");
   const Inst<T>& I = a.inst;
   const CallMM<T>& C = a.call;
   const int t = wnode(a), c0 = blockIdx.y * kWC;
@@ -78,31 +93,39 @@ __global__ __launch_bounds__(kWT) void k_mmw_leaf_up(KArgs<T, CallMM<T>> a) {
     sv.load(I.V + nd.oV, m, m, kv);
     sx.load(C.X + nd.row0 + (int64_t)c0 * C.ldx, C.ldx, m, nc);
     sv.store(Vs, kWR + 1, m, kv);
-    sx.store(Xs, kWC + 1, m, nc);
+    sx.store(Xs, kXR, m, nc);
   }
   __syncthreads();
-  // thread (r = tid % 32, column pair tid / 32): x^[r, 2q], x^[r, 2q + 1]
-  const int r = threadIdx.x & 31, q = threadIdx.x >> 5;
-  T s0 = T(0), s1 = T(0);
-  for (int k = 0; k < m; ++k) {
-    const T v = Vs[k * (kWR + 1) + r];
-    s0 += v * Xs[k * (kWC + 1) + 2 * q];
-    s1 += v * Xs[k * (kWC + 1) + 2 * q + 1];
-  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  T s[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s[c] = T(0);
+  const int k1 = min(32 * w + 32, m);
+  for (int k = 32 * w; k < k1; ++k) axpy8(s, Vs[k * (kWR + 1) + r], Xs + k * kXR + 8 * h);
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 8; ++c) Ps[(w * kWR + r) * kWC + 8 * h + c] = s[c];
+  __syncthreads();
   T* xo = I.xh + nd.oxh + (int64_t)c0 * I.ldm;
-  if (r < kv) {
-    if (2 * q < nc) xo[r + (int64_t)(2 * q) * I.ldm] = s0;
-    if (2 * q + 1 < nc) xo[r + (int64_t)(2 * q + 1) * I.ldm] = s1;
+  for (int o = threadIdx.x; o < kWR * kWC; o += kWT) {
+    const int ra = o % kWR, c = o / kWR;
+    const T v = (Ps[ra * kWC + c] + Ps[(kWR + ra) * kWC + c]) +
+                (Ps[(2 * kWR + ra) * kWC + c] + Ps[(3 * kWR + ra) * kWC + c]);
+    if (ra < kv && c < nc) xo[ra + (int64_t)c * I.ldm] = v;
   }
 }
 
 // Node t at one level: x^_t = W_t^T [x^_c1; x^_c2] below the root, and the
-// core blocks y^_c1 = B12_t x^_c2, y^_c2 = B21_t x^_c1.
+// core blocks y^_c1 = B12_t x^_c2, y^_c2 = B21_t x^_c1.  Thread (row i, half
+// h) forms one output row for eight columns as a dot product of a
+// coefficient row (column i of W_t, or a row of B12 / B21) with rows of the
+// stacked children's x^.
 template <typename T>
 __global__ __launch_bounds__(kWT) void k_mmw_up(KArgs<T, CallMM<T>> a) {
-  __shared__ T Xs[2 * kWR * (kWC + 1)];      // [x^_c1; x^_c2], row j at j*(kWC+1)
-  __shared__ T Ws[2 * kWR * (kWR + 1)];      // Ws[j][b] = W_t(j, b)
-  __shared__ T Bs[2 * kWR * (kWR + 1)];      // B12 rows 0..ku1-1, then B21
+  __shared__ __align__(16) T Xs[2 * kWR * kXR];      // [x^_c1; x^_c2]
+  __shared__ T Ws[2 * kWR * (kWR + 1)];              // Ws[j][b] = W_t(j, b)
+  __shared__ T Bs[2 * kWR * (kWR + 1)];              // B12 rows 0..ku1-1, then B21
   const Inst<T>& I = a.inst;
   const CallMM<T>& C = a.call;
   const int t = wnode(a), c0 = blockIdx.y * kWC;
@@ -120,41 +143,45 @@ __global__ __launch_bounds__(kWT) void k_mmw_up(KArgs<T, CallMM<T>> a) {
     sw.load(I.W + (kv > 0 ? nd.oW : 0), kw, kw, kv);
     b12.load(I.B12 + nd.oB12, ku1, ku1, kv2);
     b21.load(I.B21 + nd.oB21, ku2, ku2, kv1);
-    x1.store(Xs, kWC + 1, kv1, nc);
-    x2.store(Xs + kv1 * (kWC + 1), kWC + 1, kv2, nc);
+    x1.store(Xs, kXR, kv1, nc);
+    x2.store(Xs + kv1 * kXR, kXR, kv2, nc);
     sw.store(Ws, kWR + 1, kw, kv);
     b12.store(Bs, kWR + 1, ku1, kv2);
     b21.store(Bs + ku1 * (kWR + 1), kWR + 1, ku2, kv1);
   }
   __syncthreads();
-  // outputs: rows 0..kv-1 of x^_t, then ku1 rows of y^_c1, then ku2 of y^_c2
+  // rows 0..kv-1: x^_t; then ku1 rows of y^_c1; then ku2 rows of y^_c2 (<= 96)
+  const int i = threadIdx.x & 127, h = threadIdx.x >> 7;
   const int rows = kv + ku1 + ku2;
-  for (int o = threadIdx.x; o < rows * kWC; o += kWT) {
-    const int i = o % rows, c = o / rows;
-    if (c >= nc) continue;
-    T s = T(0);
-    if (i < kv) {
-      for (int j = 0; j < kw; ++j) s += Ws[j * (kWR + 1) + i] * Xs[j * (kWC + 1) + c];
-      I.xh[nd.oxh + i + (int64_t)(c0 + c) * I.ldm] = s;
-    } else if (i < kv + ku1) {
-      const int b = i - kv;
-      const T* xb = Xs + kv1 * (kWC + 1) + c;
-      for (int j = 0; j < kv2; ++j) s += Bs[b * (kWR + 1) + j] * xb[j * (kWC + 1)];
-      I.yh[n1.oyh + b + (int64_t)(c0 + c) * I.ldm] = s;
-    } else {
-      const int b = i - kv - ku1;
-      const T* xa = Xs + c;
-      for (int j = 0; j < kv1; ++j) s += Bs[(ku1 + b) * (kWR + 1) + j] * xa[j * (kWC + 1)];
-      I.yh[n2.oyh + b + (int64_t)(c0 + c) * I.ldm] = s;
-    }
+  if (i >= rows) return;
+  const T* cf;     // coefficient j at cf[j * cs]
+  int cs, len;
+  const T* xr;     // row j of the x^ operand at xr + j * kXR
+  T* out;
+  if (i < kv) {
+    cf = Ws + i; cs = kWR + 1; len = kw; xr = Xs; out = I.xh + nd.oxh + i;
+  } else if (i < kv + ku1) {
+    const int b = i - kv;
+    cf = Bs + b * (kWR + 1); cs = 1; len = kv2; xr = Xs + kv1 * kXR; out = I.yh + n1.oyh + b;
+  } else {
+    const int b = i - kv - ku1;
+    cf = Bs + (ku1 + b) * (kWR + 1); cs = 1; len = kv1; xr = Xs; out = I.yh + n2.oyh + b;
   }
+  T s[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s[c] = T(0);
+  for (int j = 0; j < len; ++j) axpy8(s, cf[j * cs], xr + j * kXR + 8 * h);
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if (8 * h + c < nc) out[(int64_t)(c0 + 8 * h + c) * I.ldm] = s[c];
 }
 
-// Node t below the root: [y^_c1; y^_c2] += R_t y^_t.
+// Node t below the root: [y^_c1; y^_c2] += R_t y^_t.  Thread (row i, quarter
+// q) updates row i of four columns.
 template <typename T>
 __global__ __launch_bounds__(kWT) void k_mmw_down(KArgs<T, CallMM<T>> a) {
-  __shared__ T Ys[kWR * (kWC + 1)];          // y^_t, row j at j*(kWC+1)
-  __shared__ T Rs[2 * kWR * (kWR + 1)];      // Rs[i][j] = R_t(i, j)
+  __shared__ __align__(16) T Ys[kWR * kXR];          // y^_t
+  __shared__ T Rs[2 * kWR * (kWR + 1)];              // Rs[i][j] = R_t(i, j)
   const Inst<T>& I = a.inst;
   const CallMM<T>& C = a.call;
   const int t = wnode(a), c0 = blockIdx.y * kWC;
@@ -166,18 +193,25 @@ __global__ __launch_bounds__(kWT) void k_mmw_down(KArgs<T, CallMM<T>> a) {
     Stage<T, 2 * kWR * kWR / kWT, true> sr;
     sy.load(I.yh + nd.oyh + (int64_t)c0 * I.ldm, I.ldm, ku, nc);
     sr.load(I.R + nd.oR, kr, kr, ku);
-    sy.store(Ys, kWC + 1, ku, nc);
+    sy.store(Ys, kXR, ku, nc);
     sr.store(Rs, kWR + 1, kr, ku);
   }
   __syncthreads();
-  for (int o = threadIdx.x; o < kr * kWC; o += kWT) {
-    const int i = o % kr, c = o / kr;
-    if (c >= nc) continue;
-    T s = T(0);
-    for (int j = 0; j < ku; ++j) s += Rs[i * (kWR + 1) + j] * Ys[j * (kWC + 1) + c];
-    T* yc = i < ku1 ? I.yh + n1.oyh + i : I.yh + n2.oyh + (i - ku1);
-    yc[(int64_t)(c0 + c) * I.ldm] += s;
+  const int i = threadIdx.x & 63, q = threadIdx.x >> 6;
+  if (i >= kr) return;
+  T s[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s[c] = T(0);
+  for (int j = 0; j < ku; ++j) {
+    const T rij = Rs[i * (kWR + 1) + j];
+    const T* yj = Ys + j * kXR + 4 * q;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] += rij * yj[c];
   }
+  T* yc = i < ku1 ? I.yh + n1.oyh + i : I.yh + n2.oyh + (i - ku1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (4 * q + c < nc) yc[(int64_t)(c0 + 4 * q + c) * I.ldm] += s[c];
 }
 
 // Y_i = D_i X_i + U_i y^_i for leaf i and columns c0 .. c0 + kWL - 1: thread
