@@ -172,9 +172,10 @@ def colmajor(t, n):
     """(ptr, ld) of a column-major (n, r) tensor view (strides (1, ld))."""
     if t.dim() != 2 or t.shape[0] != n:
         raise ValueError(f"expected an ({n}, r) tensor, got {tuple(t.shape)}")
-    if t.shape[1] > 1 and t.stride(0) != 1:
+    # (the row stride of a one-row tensor is immaterial)
+    if n > 1 and t.shape[1] > 1 and t.stride(0) != 1:
         raise ValueError("tensor must be column-major: strides (1, ld)")
-    if t.shape[1] == 1 and t.stride(0) != 1:
+    if n > 1 and t.shape[1] == 1 and t.stride(0) != 1:
         raise ValueError("tensor must have unit row stride")
     ld = t.stride(1) if t.shape[1] > 1 else max(t.stride(1), n)
     return C.c_void_p(t.data_ptr()), ld
