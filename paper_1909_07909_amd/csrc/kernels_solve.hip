@@ -17,8 +17,10 @@
 namespace hss {
 
 constexpr int kSW = 4;   // wavefronts per work-group (direct sweeps)
-constexpr int kSWS = 8;  // wavefronts per work-group of the staged sweeps: one
-                         // factor block each, so the staging is one round trip
+constexpr int kSWS = 8;  // wavefronts per work-group of the staged forward sweep on
+                         // short levels and of the root: one factor block each, so
+                         // the staging is one round trip
+constexpr int kSWSMaxItems = 1024;   // longest level given kSWS wavefronts
 
 template <typename T>
 __device__ __forceinline__ T bcast(T v, int src) {
@@ -383,13 +385,14 @@ __device__ void gather_internal(const Inst<T>& I, const NodeInfo& nd, const Node
 
 // Work item of this wavefront.  Direct kernels: kSW wavefronts per
 // work-group, one node each, CPW columns per wavefront.  Staged kernels: one
-// node per work-group, its kSWS wavefronts take kSWS * CPW consecutive columns.
+// node per work-group, its wavefronts (kSWS or kSW) take consecutive groups of
+// CPW columns.
 template <bool BATCH, bool STAGED, int CPW, typename T>
 __device__ __forceinline__ bool sv_resolve(const KArgs<T, CallSV<T>>& a, Inst<T>& I,
                                            CallSV<T>& C, int& node, int& col0) {
   const int w = threadIdx.x >> 6;
   const int item = STAGED ? blockIdx.x : blockIdx.x * kSW + w;
-  col0 = (STAGED ? blockIdx.y * kSWS + w : blockIdx.y) * CPW;
+  col0 = (STAGED ? blockIdx.y * (blockDim.x >> 6) + w : blockIdx.y) * CPW;
   if (item >= a.ntasks) return false;
   if constexpr (BATCH) {
     const int2 tk = a.tasks[item];
@@ -416,12 +419,15 @@ __device__ __forceinline__ void node_and_children(const NodeInfo* nodes, int nno
   n2 = nd.is_leaf ? NodeInfo{} : a2;
 }
 
-// Forward sweep at one node.  STAGED: the node's factors are copied to LDS by
+// Forward sweep at one node.  (Single-matrix leaf launches keep a node's
+// reflectors and L columns in registers, 32 at a time, all requested ahead of
+// use; batched launches, whose long levels need more wavefronts per CU than
+// those registers allow, read them one step ahead.)  STAGED: the node's factors are copied to LDS by
 // the whole work-group first (internal nodes); otherwise kSW wavefronts per
 // work-group read the factor arrays (leaves).  Each wavefront carries CPW
 // right-hand-side columns through the same factor reads.
 template <typename T, bool BATCH, bool STAGED, int CPW>
-__global__ __launch_bounds__((STAGED ? kSWS : kSW) * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
+__global__ __launch_bounds__((STAGED && !BATCH ? kSWS : kSW) * 64) void k_sv_fwd_w(KArgs<T, CallSV<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
   Inst<T> I; CallSV<T> C; int node, col0;
   if (!sv_resolve<BATCH, STAGED, CPW>(a, I, C, node, col0)) return;   // uniform when STAGED
@@ -461,7 +467,7 @@ __global__ __launch_bounds__((STAGED ? kSWS : kSW) * 64) void k_sv_fwd_w(KArgs<T
     // in global memory, one wavefront per node) has all of them in flight at
     // once instead
     bool u_done = false;
-    if constexpr (!STAGED) {
+    if constexpr (!STAGED && !BATCH) {
       if (ku > 0 && ku <= 32) {
         T ua[32], ub[32];
 #pragma unroll
@@ -516,7 +522,7 @@ __global__ __launch_bounds__((STAGED ? kSWS : kSW) * 64) void k_sv_fwd_w(KArgs<T
     const T dg0 = S.L[min(r0, ec) * (S.ldl + 1)], dg1 = S.L[min(r1, ec) * (S.ldl + 1)];
     const T dinv0 = T(1) / dg0, dinv1 = T(1) / dg1;
     bool l_done = false;
-    if constexpr (!STAGED) {
+    if constexpr (!STAGED && !BATCH) {
       // 32 columns of L in registers, the next 32 requested before these are used
       T la0[32], la1[32];
 #pragma unroll
@@ -758,7 +764,7 @@ __global__ __launch_bounds__(kSWS * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) 
 }
 
 template <typename T, bool BATCH, bool STAGED, int CPW>
-__global__ __launch_bounds__((STAGED ? kSWS : kSW) * 64) void k_sv_bwd_w(KArgs<T, CallSV<T>> a) {
+__global__ __launch_bounds__(kSW * 64) void k_sv_bwd_w(KArgs<T, CallSV<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
   Inst<T> I; CallSV<T> C; int node, col0;
   if (!sv_resolve<BATCH, STAGED, CPW>(a, I, C, node, col0)) return;
@@ -791,7 +797,7 @@ __global__ __launch_bounds__((STAGED ? kSWS : kSW) * 64) void k_sv_bwd_w(KArgs<T
   const T taul0 = e > 0 ? ld_or0(I.tz + nd.otz + min(r0, ec), r0 < e) : T(0);
   const T taul1 = e > 0 ? ld_or0(I.tz + nd.otz + min(r1, ec), r1 < e) : T(0);
   bool z_done = false;
-  if constexpr (!STAGED) {
+  if constexpr (!STAGED && !BATCH) {
     // factors in global memory, one wavefront per node: 32 reflectors in
     // registers, the next 32 requested before these are applied
     if (e > 0) {
@@ -887,7 +893,12 @@ void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int 
   const int cpw = ncols >= 4 ? 4 : 1;
   const int cgroups = (ncols + cpw - 1) / cpw;
   dim3 gridw((nitems + kSW - 1) / kSW, cgroups), blockw(kSW * 64);
-  dim3 grid1(nitems, (cgroups + kSWS - 1) / kSWS), block1(kSWS * 64);
+  // eight wavefronts (one staging round trip) for the root and for the
+  // forward sweep of a short single-matrix level; four (more nodes per CU)
+  // for long or batched levels and for the backward sweep (one block)
+  const int sw = step == UlvStep::Root ? kSWS
+               : (step == UlvStep::Fwd && !batch && nitems <= kSWSMaxItems ? kSWS : kSW);
+  dim3 grid1(nitems, (cgroups + sw - 1) / sw), block1(sw * 64);
 #define HSS_SL(K, ST, CP, G, B)                                                   \
   if (batch) hipLaunchKernelGGL((K<T, true, ST, CP>), G, B, sm, s, b);            \
   else hipLaunchKernelGGL((K<T, false, ST, CP>), G, B, sm, s, b);
