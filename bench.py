@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--max-refine", type=int, default=2,
+                    help="refinement steps enqueued per solve, each gated on the device by "
+                         "the backward error before it (one is needed on this family)")
     ap.add_argument("--instances", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
@@ -132,43 +135,57 @@ def main():
     assert G == gen_entries(2 ** p, LEAF, RANK)
     log(f"[bench] created {args.instances} instances, {G} generator entries each")
     work = [hss.empty_colmajor(N, r, torch.float64) for _ in mats]
-    for A in mats:
-        A.norm2()   # cached power-method estimate (not part of a step)
+    # ||A||_2 is estimated once per matrix by hss_create (16 power steps, 32
+    # products); it is part of creating the matrix, not of a step
+    mr = args.max_refine
 
-    def step_fresh(i, prec, tol):
+    def step_fresh(i, prec, tol, rep, max_refine=None):
         A = mats[i % len(mats)]
         W = work[i % len(mats)]
         W.copy_(B0[i % len(mats)])
         A.factor(prec)
         if prec == hss.F32:
-            return A.solve(W, prec=hss.F32, tol=tol, max_refine=10)
-        return A.solve(W, prec=hss.F64, want_eta=True)
+            return A.solve(W, prec=hss.F32, tol=tol, max_refine=mr if max_refine is None else
+                           max_refine, sync=False, report=rep)
+        return A.solve(W, prec=hss.F64, want_eta=True, sync=False, report=rep)
 
-    def step_resident(i, prec, tol):
+    def step_resident(i, prec, tol, rep):
         A = mats[i % len(mats)]
         W = work[i % len(mats)]
         W.copy_(B0[i % len(mats)])
         if prec == hss.F32:
-            return A.solve(W, prec=hss.F32, tol=tol, max_refine=10)
-        return A.solve(W, prec=hss.F64, want_eta=True)
+            return A.solve(W, prec=hss.F32, tol=tol, max_refine=mr, sync=False, report=rep)
+        return A.solve(W, prec=hss.F64, want_eta=True, sync=False, report=rep)
 
-    def timed(fn, steps, warmup, *a):
+    def timed(fn, steps, warmup, *a, ncols=r):
+        """Steps are enqueued back to back (the solves are stream-ordered and
+        write their reports on the device); one synchronisation at the end."""
+        reps = [hss.SolveReport(ncols) for _ in range(max(steps, warmup))]
         for i in range(warmup):
-            fn(i, *a)
+            fn(i, *a, reps[i])
         torch.cuda.synchronize()
-        etas = []
         t0 = time.perf_counter()
         for i in range(steps):
-            info = fn(i, *a)
-            etas.append((info["eta_max"], info["iters"]))
+            fn(i, *a, reps[i])
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps, etas
+        dt = (time.perf_counter() - t0) / steps
+        etas = []
+        for i in range(steps):
+            info = reps[i].result()
+            if info["status"] != hss.HSS_OK:
+                raise hss.HSSError(info["status"], "bench step")
+            etas.append((info["eta_max"], info["iters"]))
+        return dt, etas
 
     K, W = args.steps, args.warmup
     # headline: FP32 + refinement, fresh systems
     t32, e32 = timed(step_fresh, K, W, hss.F32, 1e-10)
     log(f"[bench] fresh FP32+IR: {t32*1e3:.3f} ms/solve, eta_max {max(e for e, _ in e32):.2e}, "
         f"iters {max(i for _, i in e32)}")
+    # the same with ten refinement steps enqueued (the library's default): the
+    # steps after convergence are gated off on the device but still launched
+    t32_10, e32_10 = timed(lambda i, p, t, rp: step_fresh(i, p, t, rp, 10), K, W, hss.F32, 1e-10)
+    log(f"[bench] fresh FP32+IR, max_refine 10: {t32_10*1e3:.3f} ms/solve")
     t64, e64 = timed(step_fresh, K, W, hss.F64, 0.0)
     log(f"[bench] fresh FP64   : {t64*1e3:.3f} ms/solve, eta_max {max(e for e, _ in e64):.2e}")
     # resident factors (both precisions factored)
@@ -188,18 +205,18 @@ def main():
               for i in range(len(mats))]
         Ww = [hss.empty_colmajor(N, rw, torch.float64) for _ in mats]
 
-        def step_wide(i, prec, tol):
+        def step_wide(i, prec, tol, rep):
             A = mats[i % len(mats)]
             X = Ww[i % len(mats)]
             X.copy_(Bw[i % len(mats)])
             A.factor(prec)
             if prec == hss.F32:
-                return A.solve(X, prec=hss.F32, tol=tol, max_refine=10)
-            return A.solve(X, prec=hss.F64, want_eta=True)
+                return A.solve(X, prec=hss.F32, tol=tol, max_refine=mr, sync=False, report=rep)
+            return A.solve(X, prec=hss.F64, want_eta=True, sync=False, report=rep)
 
         kw = max(K // 2, 3)
-        w32, ew32 = timed(step_wide, kw, W, hss.F32, 1e-10)
-        w64, ew64 = timed(step_wide, kw, W, hss.F64, 0.0)
+        w32, ew32 = timed(step_wide, kw, W, hss.F32, 1e-10, ncols=rw)
+        w64, ew64 = timed(step_wide, kw, W, hss.F64, 0.0, ncols=rw)
         wide = {"nrhs": rw, "steps": kw,
                 "fp32ir": {"solves_per_s": round(1.0 / w32, 2), "ms": round(w32 * 1e3, 3),
                            "eta_max": max(e for e, _ in ew32),
@@ -268,12 +285,13 @@ def main():
         rep.sort(key=lambda d: -d["total_ms"])
         return rep
 
-    rep = kernel_times(lambda i: step_fresh(i, hss.F32, 1e-10), K)
+    krep = hss.SolveReport(r)
+    rep = kernel_times(lambda i: step_fresh(i, hss.F32, 1e-10, krep), K)
     kernels = [{"kernel": d["kernel"], "launches_per_step": d["launches"] / K,
                 "ms_per_step": round(d["total_ms"] / K, 4)} for d in rep]
     log("[bench] kernels per FP32+IR step: " + ", ".join(
         f"{d['kernel']} {d['ms_per_step']:.3f}ms" for d in kernels[:10]))
-    rep64 = kernel_times(lambda i: step_fresh(i, hss.F64, 0.0), K)
+    rep64 = kernel_times(lambda i: step_fresh(i, hss.F64, 0.0, krep), K)
     log("[bench] kernels per FP64 step: " + ", ".join(
         f"{d['kernel']} {d['total_ms'] / K:.3f}ms" for d in rep64[:10]))
     for rr in (1, 32):
@@ -315,9 +333,15 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64ir", "data": "synthetic",
         "config": {"workload": f"HSS fresh-system solve to eta<=1e-10, n={N}, leaf={LEAF}, "
                                f"depth={p}, k={RANK}, nrhs={r}, synthetic generators, "
-                               f"{args.instances} rotating instances",
-                   "n": N, "leaf": LEAF, "k": RANK, "nrhs": r},
+                               f"{args.instances} rotating instances, max_refine={mr} "
+                               f"(device-gated steps, no host synchronisation in a step)",
+                   "n": N, "leaf": LEAF, "k": RANK, "nrhs": r, "max_refine": mr},
         "eta_max": max(e for e, _ in e32), "refine_iters_max": max(i for _, i in e32),
+        "fp32ir_max_refine10": {"solves_per_s": round(1.0 / t32_10, 2),
+                                "ms": round(t32_10 * 1e3, 4),
+                                "eta_max": max(e for e, _ in e32_10)},
+        "norm2_note": "||A||_2 for eta is estimated once per matrix by hss_create (16 power "
+                      "steps = 32 FP64 products) and is not part of a step",
         "fp64_solves_per_s": round(1.0 / t64, 2), "fp64_eta_max": max(e for e, _ in e64),
         "ratio_fp32ir_over_fp64": round(t64 / t32, 3),
         "resident_solves_per_s": {"fp32ir": round(1.0 / rt32, 2), "fp64": round(1.0 / rt64, 2)},

@@ -26,9 +26,18 @@
  * call is enqueued on its stream; the product (op N) forks part of its work
  * to a stream the handle owns and joins it back with events, so it is
  * ordered after earlier work on the caller's stream and before later work
- * there, as if it ran on that stream alone.  hss_create, hss_destroy, hss_query
- * (HSS_Q_NORM2 on first use) and solves that compute a backward error or
- * refine iteratively synchronize the stream; everything else is asynchronous.
+ * there, as if it ran on that stream alone.  Only hss_create and hss_destroy
+ * synchronize; products, factorizations and solves (refined or not) are
+ * stream-ordered, and their device-side outcome (backward errors, refinement
+ * steps, singular pivots) is written to device-accessible memory that is
+ * valid once the stream has reached the end of the call.
+ *
+ * Work buffers and graph capture: a handle's work buffers grow when a call
+ * needs more right-hand-side columns than any earlier call; the buffers they
+ * replace stay allocated until hss_destroy, so a HIP graph that captured an
+ * earlier call stays valid when later calls are wider.  A graph must be
+ * replayed while its handle exists, and replays of graphs that use the same
+ * handle must not overlap each other or other calls on that handle.
  */
 #ifndef HSS_H_
 #define HSS_H_
@@ -105,20 +114,39 @@ typedef struct {
   int32_t reserved;
 } hss_solve_opts;
 
-/* Solve report, host memory, filled before the call returns when eta is
- * computed (tol > 0 or want_eta).  eta (optional, host, nrhs entries) receives
- * the per-column backward errors. */
+/* Solve report, written by the device into memory that the caller provides
+ * (device memory or pinned host memory from hipHostMalloc) and valid once
+ * the stream has reached the end of the solve.  The block starts with this
+ * header and continues with ncols doubles: the per-column backward errors
+ * eta_j (0 when no backward error was computed).  Its size for nrhs
+ * right-hand sides is HSS_SOLVE_INFO_BYTES(nrhs).
+ *   eta_max        max_j eta_j (0 if not computed)
+ *   norm2          the ||A||_2 estimate used in eta (power method, Sec. 4.5)
+ *   iters          refinement steps applied
+ *   status         HSS_OK, HSS_ENOCONV (tol not met after max_refine steps;
+ *                  B holds the last iterate), HSS_ESINGULAR (an exact zero
+ *                  pivot in the factors used) or HSS_EHIP (a bounded
+ *                  device-side wait ran out)
+ *   singular_node  heap id of a node whose factor has an exact zero pivot,
+ *                  -1 if none
+ *   ncols          nrhs of the solve (the number of eta_j that follow) */
 typedef struct {
   double eta_max;
-  double norm2;        /* ||A||_2 estimate used in eta                       */
-  int32_t iters;       /* refinement steps taken                             */
-  int32_t status;      /* HSS_OK, HSS_ENOCONV or HSS_ESINGULAR               */
-  double *eta;
+  double norm2;
+  int32_t iters;
+  int32_t status;
+  int32_t singular_node;
+  int32_t ncols;
 } hss_solve_info;
+#define HSS_SOLVE_INFO_BYTES(nrhs) (sizeof(hss_solve_info) + sizeof(double) * (size_t)(nrhs))
 
 /* hss_create: validate the tree and generators, build the plan (node sizes,
- * offsets, level ranges), upload the generators to device memory and keep a
- * resident FP32 copy.  On success *out owns all device memory of the matrix.
+ * offsets, level ranges), upload the generators to device memory, keep a
+ * resident FP32 copy and estimate ||A||_2 by 16 steps of the power method on
+ * A^T A (Sec. 4.5; a lower bound, so backward errors divided by it are
+ * conservative) from a fixed start vector: v_i = the splitmix64 hash of
+ * i + 0x5eed mapped to [-1, 1), normalized.  On success *out owns all device
+ * memory of the matrix.
  * Errors: -1/-2/-3/-5 for invalid tree/generators/alloc/out, HSS_EUNSUP when a
  * node is larger than the kernels support (leaf size or merged size > 128, rank
  * > 64), HSS_ENOMEM, HSS_EHIP.  Synchronizes the stream. */
@@ -147,10 +175,16 @@ hss_status hss_ulv_factor(hss_handle *h, int32_t prec, void *stream);
 
 /* hss_ulv_solve: B <- A^{-1} B in place (Steps 1, 2 and 4 applied to B with the
  * stored factors).  B is a DEVICE pointer to an n x nrhs FP64 block (ldb >= n).
- * o == NULL means {HSS_F64, 10, 0.0, 0}.  info may be NULL.  Returns
- * HSS_ESTATE if the requested precision has not been factored,
- * HSS_ENOCONV if refinement stopped at max_refine with eta > tol (B then holds
- * the last iterate), HSS_ESINGULAR for an exactly singular factor. */
+ * o == NULL means {HSS_F64, 10, 0.0, 0}.  With o->tol > 0 the solve refines
+ * B with FP64 residuals (the FP64 product) and corrections from the chosen
+ * factors: up to o->max_refine steps are enqueued, each gated on the device
+ * by the backward error of the step before it, so steps after convergence
+ * do no work and the host never waits.  info (may be NULL) is device memory
+ * or pinned host memory of HSS_SOLVE_INFO_BYTES(nrhs) bytes; the solve writes
+ * it at its end on the stream.  Returns HSS_OK once the work is enqueued,
+ * a negative code for an invalid argument, HSS_ESTATE if the requested
+ * precision has not been factored, HSS_ENOMEM or HSS_EHIP; the outcome on the
+ * device (HSS_ENOCONV, HSS_ESINGULAR) is info->status. */
 hss_status hss_ulv_solve(hss_handle *h, int64_t nrhs, double *B, int64_t ldb,
                          const hss_solve_opts *o, hss_solve_info *info, void *stream);
 
@@ -158,7 +192,7 @@ hss_status hss_ulv_solve(hss_handle *h, int64_t nrhs, double *B, int64_t ldb,
 #define HSS_Q_N              0   /* int64_t                                        */
 #define HSS_Q_P              1   /* int32_t                                        */
 #define HSS_Q_RESIDENT_BYTES 2   /* int64_t: device bytes owned by the handle     */
-#define HSS_Q_NORM2          3   /* double: power-method ||A||_2 (cached)          */
+#define HSS_Q_NORM2          3   /* double: power-method ||A||_2 (taken at create) */
 #define HSS_Q_GEN_ENTRIES    4   /* int64_t: generator entries (algorithmic size)  */
 #define HSS_Q_FACTOR_ENTRIES 5   /* int64_t: entries of one factor set            */
 hss_status hss_query(hss_handle *h, int32_t key, void *out, void *stream);
@@ -184,9 +218,13 @@ hss_status hss_batch_matmul(hss_handle *const *hs, int32_t count, int32_t op, in
                             void *const *Y, const int64_t *ldy, void *stream);
 hss_status hss_batch_ulv_factor(hss_handle *const *hs, int32_t count, int32_t prec,
                                 void *stream);
+/* hss_batch_ulv_solve: info is NULL or a host array of count pointers,
+ * each NULL or a device / pinned block of HSS_SOLVE_INFO_BYTES(nrhs[i])
+ * bytes.  Refinement is gated per instance: an instance whose backward error
+ * meets tol takes no further corrections, and its iters counts its own. */
 hss_status hss_batch_ulv_solve(hss_handle *const *hs, int32_t count, const int64_t *nrhs,
                                double *const *B, const int64_t *ldb, const hss_solve_opts *o,
-                               hss_solve_info *info, void *stream);
+                               hss_solve_info *const *info, void *stream);
 
 /* Per-kernel timing (profiling aid).  hss_timing_enable(1) makes every
  * kernel launch of the library record a pair of HIP events on its stream;

@@ -23,9 +23,13 @@ from .hss import HSS
 from .matvec import matvec
 
 
-def norm2_power(H: HSS, iters: int = 50, seed: int = 12345) -> float:
-    rng = np.random.default_rng(seed)
-    x = rng.standard_normal(H.n)
+def norm2_power(H: HSS, iters: int = 50, seed: int = 12345, x0=None) -> float:
+    """sqrt of x^T A^T A x after ``iters`` power steps; x0 (optional) is the
+    start vector, else a seeded Gaussian one."""
+    if x0 is None:
+        x = np.random.default_rng(seed).standard_normal(H.n)
+    else:
+        x = np.array(x0, dtype=np.float64)
     x /= np.linalg.norm(x)
     lam = 0.0
     for _ in range(iters):

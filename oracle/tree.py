@@ -13,7 +13,7 @@ smallest p with ceil-halving leaves of size <= n_min, i.e. p = ceil(log2(n/n_min
 
 Pins: the n = 8, n_min = 1 example of Fig. 1 (golden fixture), a brute-force
 check of the partition properties, and the cluster-vector example
-c = [2, 4, 8, 8] of Sec. 3.6.
+c = [2, 4, 8, 8] of Sec. 3.7.
 
 Index sets are returned 0-based and half-open: node t covers rows
 [start, stop).  Heap numbering: level l, position i (1-based) -> t = 2^l - 1 + i - 1.
@@ -60,7 +60,7 @@ def leaf_offsets(n: int, nmin: int) -> list[int]:
 
 def tree_from_cluster_vector(c: list[int]) -> list[list[tuple[int, int]]]:
     """Tree given by its cluster vector c = [n_1^(p), ..., n_{2^p}^(p)]
-    (Sec. 3.6): leaves are the consecutive runs, upper levels are unions of
+    (Sec. 3.7): leaves are the consecutive runs, upper levels are unions of
     siblings.  Empty leaves are allowed here."""
     nleaf = len(c)
     p = int(round(math.log2(nleaf)))

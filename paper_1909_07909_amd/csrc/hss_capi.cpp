@@ -65,8 +65,6 @@ struct hss_handle {
   int64_t cap_stats = 0;
   double* part = nullptr;    // partials of the fused check kernels (check_partials(cap_stats))
   uint32_t* chk_cnt = nullptr;   // their arrival counter (0 between launches)
-  double* pinned = nullptr;  // host-visible refinement results (pinned), cap_pin + 2 doubles
-  int64_t cap_pin = 0;
   double norm2 = -1.0;
   // second stream of the product: the leaves' D X runs on it beside the
   // up and down kernels (forked from and joined back to the caller's stream)
@@ -148,13 +146,14 @@ hss_status ensure_factors(hss_handle* h) {
   return HSS_OK;
 }
 
+// Work buffers grow to the widest call so far.  The buffers they replace are
+// not freed before hss_destroy: a HIP graph captured from an earlier call
+// still holds their addresses.
 template <typename T>
 hss_status ensure_work_mm(hss_handle* h, int64_t nrhs) {
   Work<T>& w = work<T>(h);
   const int64_t cap = std::max<int64_t>(nrhs, kRT);
   if (w.cap_mm >= nrhs && w.xh) return HSS_OK;
-  dev_free(h, w.xh);
-  dev_free(h, w.yh);
   w.xh = dalloc<T>(h, h->plan.ldm * cap);
   w.yh = dalloc<T>(h, h->plan.ldm * cap);
   w.cap_mm = (w.xh && w.yh) ? cap : 0;
@@ -166,7 +165,6 @@ hss_status ensure_work_sv(hss_handle* h, int64_t nrhs) {
   Work<T>& w = work<T>(h);
   const int64_t cap = std::max<int64_t>(nrhs, kRT);
   if (w.cap_sv >= nrhs && w.wc) return HSS_OK;
-  for (T* p : {w.wc, w.wz, w.wy, w.wx}) dev_free(h, p);
   const int64_t sz = h->plan.lds * cap;
   w.wc = dalloc<T>(h, sz);
   w.wz = dalloc<T>(h, sz);
@@ -179,7 +177,6 @@ hss_status ensure_work_sv(hss_handle* h, int64_t nrhs) {
 hss_status ensure_ir(hss_handle* h, int64_t nrhs) {
   const int64_t cap = std::max<int64_t>(nrhs, 1);
   if (h->cap_ir < cap || !h->b0) {
-    for (void* p : {(void*)h->b0, (void*)h->res, (void*)h->d64, (void*)h->r32}) dev_free(h, p);
     const int64_t n = h->plan.n;
     h->b0 = dalloc<double>(h, n * cap);
     h->res = dalloc<double>(h, n * cap);
@@ -189,22 +186,10 @@ hss_status ensure_ir(hss_handle* h, int64_t nrhs) {
     if (!h->cap_ir) return HSS_ENOMEM;
   }
   if (h->cap_stats < cap || !h->stats) {
-    dev_free(h, h->stats);
-    dev_free(h, h->part);
     h->stats = dalloc<double>(h, 8 * cap + 8);
     h->part = dalloc<double>(h, check_partials(cap));
     h->cap_stats = (h->stats && h->part) ? cap : 0;
     if (!h->cap_stats) return HSS_ENOMEM;
-  }
-
-  if (h->cap_pin < cap || !h->pinned) {
-    if (h->pinned) (void)hipHostFree(h->pinned);
-    h->pinned = nullptr;
-    h->cap_pin = 0;
-    if (hipHostMalloc((void**)&h->pinned, sizeof(double) * (cap + 2), hipHostMallocDefault) !=
-        hipSuccess)
-      return HSS_ENOMEM;
-    h->cap_pin = cap;
   }
   return HSS_OK;
 }
@@ -236,10 +221,15 @@ inline int level_first(int l) { return (1 << l) - 1; }
 // ---------------------------------------------------------------------------
 template <typename T>
 void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T* Y, int64_t ldy,
-                hipStream_t s) {
+                hipStream_t s, const int32_t* gate = nullptr, T* xh = nullptr, T* yh = nullptr) {
   KArgs<T, CallMM<T>> a{};
   a.inst = make_inst<T>(h);
-  a.call = CallMM<T>{X, Y, ldx, ldy, (int32_t)nrhs, op};
+  if (xh) {
+    // caller-provided x^ / y^ work vectors (leading dimension ldm)
+    a.inst.xh = xh;
+    a.inst.yh = yh;
+  }
+  a.call = CallMM<T>{X, Y, ldx, ldy, (int32_t)nrhs, op, gate};
   const int p = h->plan.p;
   if (op == HSS_OP_N) {
     // fused: leaves (with the climb), subtree walks, leaf outputs
@@ -352,10 +342,11 @@ void run_factor(hss_handle* h, hipStream_t s) {
 constexpr int64_t kStageBudget = 120 * 1024;
 
 template <typename T>
-void run_solve(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, hipStream_t s) {
+void run_solve(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, hipStream_t s,
+               const int32_t* gate = nullptr) {
   KArgs<T, CallSV<T>> a{};
   a.inst = make_inst<T>(h);
-  a.call = CallSV<T>{B, ldb, (int32_t)nrhs, 0};
+  a.call = CallSV<T>{B, ldb, (int32_t)nrhs, 0, gate};
   const Plan& P = h->plan;
   const int p = P.p;
   const int nc = (int)nrhs;   // one wavefront per (node, column)
@@ -403,8 +394,9 @@ hss_status last_launch_status() {
   return e == hipSuccess ? HSS_OK : HSS_EHIP;
 }
 
+// ||A||_2 by the power method on A^T A (Sec. 4.5), 16 steps from a fixed
+// hash-filled start vector; run once, by hss_create.
 hss_status compute_norm2(hss_handle* h, hipStream_t s) {
-  if (h->norm2 >= 0.0) return HSS_OK;
   hss_status st = ensure_ir(h, 1);
   if (st) return st;
   if ((st = ensure_work_mm<double>(h, 1))) return st;
@@ -467,14 +459,13 @@ BatchScratch& scratch_for(hipStream_t s) {
   return *p;
 }
 
-hss_status grow(void** d, size_t* cap, size_t need, hipStream_t s) {
+// Grows a scratch buffer.  The buffer it replaces may still be read by work
+// in flight or by captured graphs; it is kept (never freed), and growth is
+// geometric, so what is kept is bounded by the final size.
+hss_status grow(void** d, size_t* cap, size_t need, hipStream_t) {
   if (*cap >= need) return HSS_OK;
-  if (*d) {
-    if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
-    (void)hipFree(*d);
-    *d = nullptr;
-    *cap = 0;
-  }
+  *d = nullptr;
+  *cap = 0;
   const size_t c = std::max<size_t>(need * 2, 1 << 20);
   if (hipMalloc(d, c) != hipSuccess) {
     (void)hipGetLastError();
@@ -544,7 +535,7 @@ template <typename T>
 hss_status batch_matmul_impl(BatchScratch& BS, hss_handle* const* hs, int count, int op,
                              const int64_t* nrhs,
                              const void* const* X, const int64_t* ldx, void* const* Y,
-                             const int64_t* ldy, hipStream_t s) {
+                             const int64_t* ldy, hipStream_t s, bool gated = false) {
   int64_t maxr = 0;
   std::vector<Inst<T>> insts(count);
   std::vector<CallMM<T>> calls(count);
@@ -552,7 +543,8 @@ hss_status batch_matmul_impl(BatchScratch& BS, hss_handle* const* hs, int count,
     hss_status st = ensure_work_mm<T>(hs[j], std::max<int64_t>(nrhs[j], 1));
     if (st) return st;
     insts[j] = make_inst<T>(hs[j]);
-    calls[j] = CallMM<T>{(const T*)X[j], (T*)Y[j], ldx[j], ldy[j], (int32_t)nrhs[j], op};
+    calls[j] = CallMM<T>{(const T*)X[j], (T*)Y[j], ldx[j], ldy[j], (int32_t)nrhs[j], op,
+                         gated ? hs[j]->d_status + kStGate : nullptr};
     maxr = std::max(maxr, nrhs[j]);
   }
   if (maxr == 0) return HSS_OK;
@@ -633,14 +625,16 @@ hss_status batch_matmul(hss_handle* const* hs, int count, int op, const int64_t*
   return batch_matmul_impl<T>(B, hs, count, op, nrhs, X, ldx, Y, ldy, s);
 }
 
-// FP64 A X for the refinement residuals (the caller holds the scratch lock).
+// FP64 A X for the refinement residuals (the caller holds the scratch lock);
+// gated: instances whose refinement gate is 0 are skipped.
 hss_status batch_matmul_unlocked(BatchScratch& BS, hss_handle* const* hs, int count,
                                  const int64_t* nrhs, double* const* X, const int64_t* ldx,
-                                 double* const* Y, const int64_t* ldy, hipStream_t s) {
+                                 double* const* Y, const int64_t* ldy, hipStream_t s,
+                                 bool gated) {
   std::vector<const void*> xv(X, X + count);
   std::vector<void*> yv(Y, Y + count);
   return batch_matmul_impl<double>(BS, hs, count, HSS_OP_N, nrhs, xv.data(), ldx, yv.data(), ldy,
-                                   s);
+                                   s, gated);
 }
 
 template <typename T>
@@ -706,7 +700,7 @@ hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
 // right-hand sides rhs[j] (precision T, leading dimension ld[j]).
 template <typename T>
 hss_status batch_sweep(BatchScratch& BS, hss_handle* const* hs, int count, const int64_t* nrhs,
-                       T* const* rhs, const int64_t* ld, hipStream_t s) {
+                       T* const* rhs, const int64_t* ld, hipStream_t s, bool gated = false) {
   std::vector<Inst<T>> insts(count);
   std::vector<CallSV<T>> calls(count);
   int64_t maxr = 0;
@@ -714,7 +708,8 @@ hss_status batch_sweep(BatchScratch& BS, hss_handle* const* hs, int count, const
     hss_status st = ensure_work_sv<T>(hs[j], std::max<int64_t>(nrhs[j], 1));
     if (st) return st;
     insts[j] = make_inst<T>(hs[j]);
-    calls[j] = CallSV<T>{rhs[j], ld[j], (int32_t)nrhs[j], 0};
+    calls[j] = CallSV<T>{rhs[j], ld[j], (int32_t)nrhs[j], 0,
+                         gated ? hs[j]->d_status + kStGate : nullptr};
     maxr = std::max(maxr, nrhs[j]);
   }
   if (maxr == 0) return HSS_OK;
@@ -783,7 +778,7 @@ hss_status batch_sweep(BatchScratch& BS, hss_handle* const* hs, int count, const
 }
 
 hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, double* const* B,
-                       const int64_t* ldb, const hss_solve_opts& opt, hss_solve_info* info,
+                       const int64_t* ldb, const hss_solve_opts& opt, hss_solve_info* const* info,
                        hipStream_t s) {
   BatchScratch& BS = scratch_for(s);
   std::lock_guard<std::mutex> g(BS.mu);
@@ -792,21 +787,18 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
   hss_status st;
   int64_t maxn = 0;
   for (int j = 0; j < count; ++j) {
-    if (need_eta && (st = compute_norm2(hs[j], s))) return st;
     if ((st = ensure_ir(hs[j], std::max<int64_t>(nrhs[j], 1)))) return st;
     if (need_eta && (st = ensure_work_mm<double>(hs[j], std::max<int64_t>(nrhs[j], 1)))) return st;
     maxn = std::max(maxn, hs[j]->plan.n);
   }
-  // refinement descriptors + the global max eta live in the scratch as well
   std::vector<IRSeg> segs(count);
-  std::vector<double> gm(1, 0.0);
   std::vector<int64_t> n_ld(count);
   std::vector<float*> r32(count);
   std::vector<double*> d64(count), res(count), Bv(B, B + count);
   for (int j = 0; j < count; ++j) {
     hss_handle* h = hs[j];
     segs[j] = IRSeg{B[j], ldb[j], h->b0, h->res, h->d64, h->r32, h->plan.n, (int32_t)nrhs[j], 0,
-                    h->stats, h->norm2};
+                    h->stats, h->norm2, opt.tol, h->d_status, info ? (void*)info[j] : nullptr};
     n_ld[j] = h->plan.n;
     r32[j] = h->r32;
     d64[j] = h->d64;
@@ -814,87 +806,61 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
   }
   // the sweeps below use the table scratch, so the refinement descriptors get their own
   if ((st = grow(&BS.ir, &BS.ir_cap, sizeof(IRSeg) * count + 256, s))) return st;
-  void* ir_d = BS.ir;
-  double* gmax = reinterpret_cast<double*>(ir_d);
-  IRSeg* dsegs = reinterpret_cast<IRSeg*>((char*)ir_d + 256);
+  IRSeg* dsegs = reinterpret_cast<IRSeg*>((char*)BS.ir + 256);
   if (hipMemcpyAsync(dsegs, segs.data(), sizeof(IRSeg) * count, hipMemcpyHostToDevice, s) !=
       hipSuccess)
     return HSS_EHIP;
-  auto ir = [&](int op) { launch_ir_batch(op, dsegs, count, maxn, gmax, s); };
+  auto ir = [&](int op, bool gated = false, int step = 0) {
+    launch_ir_batch(op, dsegs, count, maxn, gated, step, opt.max_refine, s);
+  };
   ir(IR_ZERO_ALL);
   if (need_eta) ir(IR_SAVE_B0);
+  // first: B <- A^-1 B; later (gated per instance): B += A^-1 r
   auto correction = [&](bool first) -> hss_status {
     hss_status e;
     if (is64) {
       if (first) return batch_sweep<double>(BS, hs, count, nrhs, Bv.data(), ldb, s);
-      ir(IR_COPY_RES);
-      if ((e = batch_sweep<double>(BS, hs, count, nrhs, d64.data(), n_ld.data(), s))) return e;
-      ir(IR_AXPY64);
+      ir(IR_COPY_RES, true);
+      if ((e = batch_sweep<double>(BS, hs, count, nrhs, d64.data(), n_ld.data(), s, true)))
+        return e;
+      ir(IR_AXPY64, true);
       return HSS_OK;
     }
     if (first) {
       ir(IR_STATS_BMAX);
       ir(IR_SCALE_B);
     } else {
-      ir(IR_SCALE_RES);
+      ir(IR_SCALE_RES, true);
     }
-    if ((e = batch_sweep<float>(BS, hs, count, nrhs, r32.data(), n_ld.data(), s))) return e;
-    ir(first ? IR_CAST_BACK : IR_AXPY_CAST);
+    if ((e = batch_sweep<float>(BS, hs, count, nrhs, r32.data(), n_ld.data(), s, !first)))
+      return e;
+    ir(first ? IR_CAST_BACK : IR_AXPY_CAST, !first);
+    return HSS_OK;
+  };
+  auto check = [&](int k) -> hss_status {
+    const bool gated = k > 0;
+    hss_status e;
+    if ((e = batch_matmul_unlocked(BS, hs, count, nrhs, Bv.data(), ldb, res.data(), n_ld.data(),
+                                   s, gated)))
+      return e;
+    ir(IR_ZERO, gated);
+    ir(IR_RESID, gated);
+    ir(IR_STATS_X, gated);
+    ir(IR_ETA, gated, k);
     return HSS_OK;
   };
   if ((st = correction(true))) return st;
-  int iters = 0;
-  double eta_max = 0.0;
   if (need_eta) {
     ir(IR_STATS_B0);
-    for (;;) {
-      if ((st = batch_matmul_unlocked(BS, hs, count, nrhs, Bv.data(), ldb, res.data(), n_ld.data(),
-                                      s)))
-        return st;
-      ir(IR_ZERO);
-      launch_fill(gmax, 0.0, 1, s);
-      ir(IR_RESID);
-      ir(IR_STATS_X);
-      ir(IR_ETA);
-      if ((st = last_launch_status())) return st;
-      if (hipMemcpyAsync(&eta_max, gmax, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
-        return HSS_EHIP;
-      if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
-      if (opt.tol <= 0.0 || eta_max <= opt.tol || iters >= opt.max_refine) break;
+    if ((st = check(0))) return st;
+    const int steps = opt.tol > 0.0 ? opt.max_refine : 0;
+    for (int k = 1; k <= steps; ++k) {
       if ((st = correction(false))) return st;
-      ++iters;
+      if ((st = check(k))) return st;
     }
   }
-  if ((st = last_launch_status())) return st;
-  if (!need_eta && !info) return HSS_OK;
-  if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
-  hss_status worst = HSS_OK;
-  for (int j = 0; j < count; ++j) {
-    int32_t dstat = 0;
-    double out[1] = {0.0};
-    if (hipMemcpy(&dstat, hs[j]->d_status, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
-      return HSS_EHIP;
-    const int64_t nr = nrhs[j];
-    if (need_eta &&
-        hipMemcpy(out, hs[j]->stats + 6 * nr, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-      return HSS_EHIP;
-    hss_status r = HSS_OK;
-    if (dstat & (1 << kStatusWaitCode)) r = HSS_EHIP;
-    else if (dstat & (1 << HSS_ESINGULAR)) r = HSS_ESINGULAR;
-    else if (need_eta && opt.tol > 0.0 && out[0] > opt.tol) r = HSS_ENOCONV;
-    if (r && !worst) worst = r;
-    if (info) {
-      info[j].eta_max = out[0];
-      info[j].iters = iters;
-      info[j].status = r;
-      info[j].norm2 = hs[j]->norm2;
-      if (info[j].eta && need_eta && nr > 0 &&
-          hipMemcpy(info[j].eta, hs[j]->stats + 5 * nr, sizeof(double) * nr,
-                    hipMemcpyDeviceToHost) != hipSuccess)
-        return HSS_EHIP;
-    }
-  }
-  return worst;
+  if (info) ir(IR_INFO, false, need_eta ? 1 : 0);
+  return last_launch_status();
 }
 
 }  // namespace
@@ -1029,8 +995,7 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
     launch_fill(reinterpret_cast<double*>(h->w32.mb), v32, (nmb + 1) / 2, s);
   }
   if ((st = last_launch_status())) return fail(st);
-  h->pinned = nullptr;
-  h->cap_pin = 0;
+  if ((st = compute_norm2(h, s))) return fail(st);
   if (hipStreamSynchronize(s) != hipSuccess) return fail(HSS_EHIP);
   *out = h;
   return HSS_OK;
@@ -1040,7 +1005,6 @@ hss_status hss_destroy(hss_handle* h) {
   if (!h) return HSS_OK;
   (void)hipDeviceSynchronize();
   while (!h->blocks.empty()) dev_free(h, h->blocks.back().first);
-  if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->side) (void)hipStreamDestroy(h->side);
@@ -1107,18 +1071,10 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
   if (opt.max_refine < 0 || !(opt.tol >= 0.0)) return -5;
   const bool is64 = opt.prec == HSS_F64;
   if (is64 ? !h->f64.valid : !h->f32.valid) return HSS_ESTATE;
-  if (info) {
-    info->eta_max = 0.0;
-    info->iters = 0;
-    info->status = HSS_OK;
-    info->norm2 = h->norm2;
-  }
-  if (nrhs == 0) return HSS_OK;
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = h->plan.n;
-  const bool need_eta = opt.want_eta || opt.tol > 0.0;
+  const bool need_eta = nrhs > 0 && (opt.want_eta || opt.tol > 0.0);
   hss_status st;
-  if (need_eta && (st = compute_norm2(h, s))) return st;
   if (is64) {
     if ((st = ensure_work_sv<double>(h, nrhs))) return st;
   } else {
@@ -1126,88 +1082,52 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
   }
   if ((st = ensure_ir(h, nrhs))) return st;
   if (need_eta && (st = ensure_work_mm<double>(h, nrhs))) return st;
-  double* ss = h->stats;      // bmax at 4 nrhs; [eta_max, status, eta_0 ..] at 6 nrhs
+  double* ss = h->stats;      // bmax at 4 nrhs; [eta_max, 0, eta_0 ..] at 6 nrhs
   double* bmax = ss + 4 * nrhs;
   double* outv = ss + 6 * nrhs;
-  if (need_eta) launch_copy2d(B, ldb, h->b0, n, n, nrhs, s);
-  // first solve
-  // gate: the FP32 correction is added only while gate[0] > tol (a correction
-  // queued before the host has read the backward error it depends on)
-  // scaled: bmax already holds max |rhs| per column (the check computed it)
-  auto correction_solve = [&](const double* rhs, int64_t ldr, double* x, int64_t ldx,
-                              bool accumulate, const double* gate = nullptr,
-                              bool scaled = false) {
-    if (is64) {
-      double* d = accumulate ? h->d64 : x;
-      const int64_t ldd = accumulate ? n : ldx;
-      if (rhs != d) launch_copy2d(rhs, ldr, d, ldd, n, nrhs, s);
-      run_solve<double>(h, nrhs, d, ldd, s);
-      if (accumulate) launch_axpy64(d, ldd, x, ldx, n, nrhs, s);
-    } else {
-      // scale each column by its max |.| before rounding to FP32
-      if (!scaled) launch_colmax(rhs, ldr, n, nrhs, h->part, h->chk_cnt, bmax, s);
-      launch_scale_cast(rhs, ldr, h->r32, n, n, nrhs, bmax, s);
-      run_solve<float>(h, nrhs, h->r32, n, s);
-      if (accumulate) launch_axpy_cast(h->r32, n, x, ldx, n, nrhs, bmax, s, gate, opt.tol);
-      else launch_cast_back(h->r32, n, x, ldx, n, nrhs, bmax, s);
-    }
-  };
-  correction_solve(B, ldb, B, ldb, false);
-  if (!need_eta && !info) return last_launch_status();
-  int iters = 0;
-  double eta_max = 0.0;
-  int32_t dstat = 0;
-  bool have_stat = false;
-  // The backward error, the status word and (wanted) the per-column errors
-  // come back together in one copy to pinned memory per check.  The first
-  // FP32 correction is queued before the host reads the first check (gated on
-  // the device by that check): an FP32 solve alone rarely meets an FP64-level
-  // tolerance, so the GPU keeps working instead of idling through the round
-  // trip.
-  double* hp = h->pinned;
-  const bool copy_eta = info && info->eta && need_eta;
-  if (need_eta) {
-    for (;;) {
-      // residual, norms, eta, status and max |r| in one launch; outv =
-      // [eta_max, status, eta_0 ..], copied to the host in one piece
-      run_matmul<double>(h, HSS_OP_N, nrhs, B, ldb, h->res, n, s);
-      launch_check(h->b0, n, h->res, n, B, ldb, n, nrhs, h->norm2, h->part, h->chk_cnt,
-                   h->d_status, bmax, outv, s);
-      if ((st = last_launch_status())) return st;
-      if (hipMemcpyAsync(hp, outv, sizeof(double) * (copy_eta ? 2 + nrhs : 2),
-                         hipMemcpyDeviceToHost, s) != hipSuccess)
-        return HSS_EHIP;
-      const bool spec = !is64 && iters == 0 && opt.tol > 0.0 && opt.max_refine > 0;
-      if (spec) correction_solve(h->res, n, B, ldb, true, outv, true);
-      if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
-      eta_max = hp[0];
-      dstat = (int32_t)hp[1];
-      have_stat = true;
-      if (copy_eta) std::memcpy(info->eta, hp + 2, sizeof(double) * nrhs);
-      if (opt.tol <= 0.0 || eta_max <= opt.tol || iters >= opt.max_refine) break;
-      if (!spec) correction_solve(h->res, n, B, ldb, true, nullptr, true);
-      ++iters;
-      have_stat = false;
+  int32_t* stb = h->d_status;
+  const int32_t* gate = stb + kStGate;
+  if (nrhs > 0) {
+    if (need_eta) launch_copy2d(B, ldb, h->b0, n, n, nrhs, s);
+    // One correction: x (+)= A^-1 rhs with the chosen factors.  FP32: each
+    // column scaled by its max |.| before rounding (scaled: rmax of the last
+    // check already holds it).  g: the refinement gate (NULL for the first
+    // solve, which always runs).
+    auto correction = [&](const double* rhs, int64_t ldr, double* x, int64_t ldx, bool accumulate,
+                          const int32_t* g, bool scaled) {
+      if (is64) {
+        double* d = accumulate ? h->d64 : x;
+        const int64_t ldd = accumulate ? n : ldx;
+        if (rhs != d) launch_copy2d(rhs, ldr, d, ldd, n, nrhs, s, g);
+        run_solve<double>(h, nrhs, d, ldd, s, g);
+        if (accumulate) launch_axpy64(d, ldd, x, ldx, n, nrhs, s, g);
+      } else {
+        if (!scaled) launch_colmax(rhs, ldr, n, nrhs, h->part, h->chk_cnt, bmax, s);
+        launch_scale_cast(rhs, ldr, h->r32, n, n, nrhs, bmax, s, g);
+        run_solve<float>(h, nrhs, h->r32, n, s, g);
+        if (accumulate) launch_axpy_cast(h->r32, n, x, ldx, n, nrhs, bmax, s, g);
+        else launch_cast_back(h->r32, n, x, ldx, n, nrhs, bmax, s);
+      }
+    };
+    // check of step k: r = b - A x, eta, and the gate of the next correction
+    auto check = [&](int k, const int32_t* g) {
+      run_matmul<double>(h, HSS_OP_N, nrhs, B, ldb, h->res, n, s, g);
+      launch_check(h->b0, n, h->res, n, B, ldb, n, nrhs, h->norm2, h->part, h->chk_cnt, stb,
+                   bmax, outv, g, opt.tol, k, opt.max_refine, s);
+    };
+    correction(B, ldb, B, ldb, false, nullptr, false);
+    if (need_eta) {
+      check(0, nullptr);
+      // refinement steps, each gated on the device by the check before it
+      const int steps = opt.tol > 0.0 ? opt.max_refine : 0;
+      for (int k = 1; k <= steps; ++k) {
+        correction(h->res, n, B, ldb, true, gate, true);
+        check(k, gate);
+      }
     }
   }
-  if ((st = last_launch_status())) return st;
-  if (!have_stat) {
-    if (hipMemcpyAsync(&dstat, h->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
-      return HSS_EHIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return HSS_EHIP;
-  }
-  hss_status result = HSS_OK;
-  if (dstat & (1 << kStatusWaitCode)) result = HSS_EHIP;
-  else if (dstat & (1 << HSS_ESINGULAR)) result = HSS_ESINGULAR;
-  else if (need_eta && opt.tol > 0.0 && eta_max > opt.tol) result = HSS_ENOCONV;
-  if (info) {
-    info->eta_max = eta_max;
-    info->iters = iters;
-    info->status = result;
-    info->norm2 = h->norm2;
-  }
-  return result;
+  if (info) launch_solve_info(info, nrhs, outv, stb, h->norm2, opt.tol, need_eta, s);
+  return last_launch_status();
 }
 
 hss_status hss_query(hss_handle* h, int32_t key, void* out, void* stream) {
@@ -1219,12 +1139,7 @@ hss_status hss_query(hss_handle* h, int32_t key, void* out, void* stream) {
     case HSS_Q_RESIDENT_BYTES: *(int64_t*)out = h->resident; return HSS_OK;
     case HSS_Q_GEN_ENTRIES: *(int64_t*)out = h->plan.gen_entries(); return HSS_OK;
     case HSS_Q_FACTOR_ENTRIES: *(int64_t*)out = h->plan.factor_entries(); return HSS_OK;
-    case HSS_Q_NORM2: {
-      const hss_status st = compute_norm2(h, (hipStream_t)stream);
-      if (st) return st;
-      *(double*)out = h->norm2;
-      return HSS_OK;
-    }
+    case HSS_Q_NORM2: *(double*)out = h->norm2; return HSS_OK;
     default: return -2;
   }
 }
@@ -1262,7 +1177,7 @@ hss_status hss_batch_ulv_factor(hss_handle* const* hs, int32_t count, int32_t pr
 
 hss_status hss_batch_ulv_solve(hss_handle* const* hs, int32_t count, const int64_t* nrhs,
                                double* const* B, const int64_t* ldb, const hss_solve_opts* o,
-                               hss_solve_info* info, void* stream) {
+                               hss_solve_info* const* info, void* stream) {
   if (!hs) return -1;
   if (count < 0) return -2;
   if (count > 0 && (!nrhs || !B || !ldb)) return -3;

@@ -60,6 +60,16 @@ constexpr int kMbChunks = 4;  // column chunks of kMbCols one product launch tak
 // Status bit (1 << code) set by a kernel whose bounded wait for another
 // work-group ran out; the code is HSS_EHIP.
 constexpr int kStatusWaitCode = 2;
+// Device status block of an instance (int32 entries): [0] status bits
+// (1 << HSS_ESINGULAR, 1 << kStatusWaitCode), [1] 1 + the largest heap id of a
+// node with an exact zero pivot (0 if none), [2] refinement gate (1 while
+// the next correction is to run), [3] refinement steps taken.
+constexpr int kStatusWords = 4;
+constexpr int kCodeSingular = 4;   // HSS_ESINGULAR
+constexpr int kCodeNoConv = 5;     // HSS_ENOCONV
+constexpr int kStSingularNode = 1;
+constexpr int kStGate = 2;
+constexpr int kStIters = 3;
 
 template <typename T>
 struct Inst {
@@ -79,6 +89,9 @@ struct Inst {
   int32_t nnodes;
 };
 
+// gate: NULL, or a device flag read when a work-group starts; 0 makes the
+// call's work-groups return at once (refinement steps enqueued after the
+// backward error has met its tolerance).
 template <typename T>
 struct CallMM {
   const T* X;
@@ -86,6 +99,7 @@ struct CallMM {
   int64_t ldx, ldy;
   int32_t nrhs;
   int32_t op;
+  const int32_t* gate;
 };
 
 template <typename T>
@@ -94,7 +108,12 @@ struct CallSV {
   int64_t ldb;
   int32_t nrhs;
   int32_t pad;
+  const int32_t* gate;
 };
+
+__device__ __forceinline__ bool gated_off(const int32_t* gate) {
+  return gate != nullptr && *gate == 0;
+}
 
 // Kernel argument bundle: single-instance launches pass the instance and the
 // call by value and address nodes node0 + blockIdx.x; batched launches pass

@@ -66,30 +66,33 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max
 // Elementwise / reduction helpers (kernels_util.hip).
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 // dst[i + j*ldd] = (float)(src[i + j*lds] * scale[j])   (scale may be null -> 1)
+// gate (all launchers that take one): NULL, or a device flag; the launch does
+// nothing when it reads 0.
 void launch_scale_cast(const double* src, int64_t lds, float* dst, int64_t ldd, int64_t n,
-                       int64_t nrhs, const double* scale, hipStream_t s);
-// x[i + j*ldx] += scale[j] * d[i + j*ldd]; with gate, only when gate[0] > tol
-// (not when gate[0] <= tol)
+                       int64_t nrhs, const double* scale, hipStream_t s,
+                       const int32_t* gate = nullptr);
+// x[i + j*ldx] += scale[j] * d[i + j*ldd]
 void launch_axpy_cast(const float* d, int64_t ldd, double* x, int64_t ldx, int64_t n,
                       int64_t nrhs, const double* scale, hipStream_t s,
-                      const double* gate = nullptr, double tol = 0.0);
-// r = b - r (in place on r), column-major n x nrhs
-void launch_residual(const double* b, int64_t ldb, double* r, int64_t ldr, int64_t n,
-                     int64_t nrhs, hipStream_t s);
+                      const int32_t* gate = nullptr);
 // sums[j] (+)= sum_i a[i+j*lda]^2 ; maxabs[j] = max |a| (optional)
 void launch_colstats(const double* a, int64_t lda, int64_t n, int64_t nrhs, double* sumsq,
                      double* maxabs, hipStream_t s);
 void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
-                   int64_t nrhs, hipStream_t s);
+                   int64_t nrhs, hipStream_t s, const int32_t* gate = nullptr);
 void launch_fill(double* p, double v, int64_t n, hipStream_t s);
-// Fused refinement check (residual, norms, eta, status, max |r|) and per-column
-// max |a|; part holds check_partials(nrhs) doubles, cnt one counter that
-// starts at 0 (each launch leaves it at 0).
+// Fused refinement check (residual, norms, eta, max |r|, the refinement gate
+// and step count in the status block st) and per-column max |a|; part holds
+// check_partials(nrhs) doubles, cnt one counter that starts at 0 (each
+// launch leaves it at 0).  out = [eta_max, 0, eta_0 .. eta_{nrhs-1}].
 int check_partials(int64_t nrhs);
 void launch_check(const double* b, int64_t ldb, double* r, int64_t ldr, const double* x,
                   int64_t ldx, int64_t n, int64_t nrhs, double normA, double* part,
-                  unsigned* cnt, const int32_t* status, double* rmax, double* out,
-                  hipStream_t s);
+                  unsigned* cnt, int32_t* st, double* rmax, double* out, const int32_t* gate,
+                  double tol, int step, int max_refine, hipStream_t s);
+// Writes the solve report (include/hss.h, hss_solve_info + nrhs etas) at info.
+void launch_solve_info(void* info, int64_t nrhs, const double* out, const int32_t* st,
+                       double normA, double tol, bool have_eta, hipStream_t s);
 void launch_colmax(const double* a, int64_t lda, int64_t n, int64_t nrhs, double* part,
                    unsigned* cnt, double* amax, hipStream_t s);
 // dst = scale[j] * (double)src
@@ -97,15 +100,10 @@ void launch_cast_back(const float* src, int64_t lds, double* dst, int64_t ldd, i
                       int64_t nrhs, const double* scale, hipStream_t s);
 // dst += src (FP64)
 void launch_axpy64(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
-                   int64_t nrhs, hipStream_t s);
+                   int64_t nrhs, hipStream_t s, const int32_t* gate = nullptr);
 void launch_normalize(const double* src, double* dst, int64_t n, const double* sumsq,
                       hipStream_t s);
 void launch_hash_fill(double* d, int64_t n, uint64_t seed, hipStream_t s);
-// eta[j] = sqrt(rr[j]) / (normA * sqrt(xx[j]) + sqrt(bb[j])); out[0] = max eta;
-// scale[j] = max|r_j| (for the next correction), flags
-void launch_eta(const double* rr, const double* xx, const double* bb, double normA, int64_t nrhs,
-                double* eta, double* out, hipStream_t s);
-
 // Iterative refinement over many instances (one launch per operation).
 struct IRSeg {
   double* B;        // solution being refined (caller's memory), leading dimension ldb
@@ -117,6 +115,9 @@ struct IRSeg {
   int32_t pad;
   double* stats;    // rr | xx | bb | rmax | bmax | eta | out (nrhs each)
   double norm2;
+  double tol;
+  int32_t* st;      // the instance's status block (gate, steps, status bits)
+  void* info;       // solve report (include/hss.h) or NULL
 };
 enum IROp {
   IR_ZERO = 0,      // clear rr, xx, rmax
@@ -127,14 +128,17 @@ enum IROp {
   IR_CAST_BACK,     // B = bmax * r32
   IR_RESID,         // res = b0 - res; rr, rmax
   IR_STATS_X,       // xx += ||B_j||^2
-  IR_ETA,           // eta_j, out = max_j eta_j, gmax = max over instances
+  IR_ETA,           // eta_j, out = max_j eta_j; the gate and step count in st
   IR_SCALE_RES,     // r32 = res / rmax
   IR_AXPY_CAST,     // B += rmax * r32
   IR_COPY_RES,      // d64 = res
   IR_AXPY64,        // B += d64
-  IR_ZERO_ALL       // clear all stats
+  IR_ZERO_ALL,      // clear all stats
+  IR_INFO           // write the solve report (have_eta = step != 0)
 };
-void launch_ir_batch(int op, const IRSeg* segs, int count, int64_t max_n, double* gmax,
-                     hipStream_t s);
+// gated: instances whose gate (st[kStGate]) is 0 are skipped.  step and
+// max_refine: the refinement step a check (IR_ETA) belongs to.
+void launch_ir_batch(int op, const IRSeg* segs, int count, int64_t max_n, bool gated, int step,
+                     int max_refine, hipStream_t s);
 
 }  // namespace hss

@@ -200,7 +200,10 @@ __global__ __launch_bounds__(fnt<MAXC>()) void k_ulv_factor_reg(KArgs<T, CallSV<
   }
   __syncthreads();
   if (tid < e) I.tz[nd.otz + tid] = taus[kMaxRank + tid];
-  if (tid == 0 && sing) atomicOr(I.status, 1 << 4);
+  if (tid == 0 && sing) {
+    atomicOr(I.status, 1 << kCodeSingular);
+    atomicMax(I.status + kStSingularNode, node + 1);
+  }
   // rows 0..e-1 (parked) -> FD and, as columns, FZ
   for (int o = tid; o < e * mp; o += kFNT) {
     const int i = o % e, cc = o / e;

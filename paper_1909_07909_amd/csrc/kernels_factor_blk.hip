@@ -670,7 +670,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #undef HSS_LQ_PANEL
   if (w > plast) store_rows(X, FD, mp, w, e, mp, g, c);
   if (w == 0 && kv > 0) slab_store_cols(X, FV, mp, mp, kv, 0, 0, g, c);
-  if (tid == 0 && sing) atomicOr(I.status, 1 << 4);
+  if (tid == 0 && sing) {
+    atomicOr(I.status, 1 << kCodeSingular);
+    atomicMax(I.status + kStSingularNode, node + 1);
+  }
 }
 
 }  // namespace

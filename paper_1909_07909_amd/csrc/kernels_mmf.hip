@@ -197,6 +197,7 @@ __global__ __launch_bounds__(kUT) void k_mmf_up(KArgs<T, CallMM<T>> a) {
   __shared__ unsigned s_arrive;
   Inst<T> I; CallMM<T> C; int g;
   resolve<BATCH>(a, I, C, g);
+  if (gated_off(C.gate)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nrhs = C.nrhs;
   const int ncw = min(MC, nrhs);
@@ -716,6 +717,7 @@ __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k
   __shared__ unsigned s_arrive;
   if constexpr (DX) {
     if ((int)blockIdx.x >= a.ntasks) {
+      if (gated_off(a.call.gate)) return;
       up_leaf_dx(a.inst, a.call, (1 << a.inst.p) - 1 + (int)blockIdx.x - a.ntasks,
                  reinterpret_cast<T*>(smem_raw));
       return;
@@ -723,6 +725,7 @@ __global__ __launch_bounds__(kUT) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   Inst<T> I; CallMM<T> C; int g;
   resolve<BATCH>(a, I, C, g);
+  if (gated_off(C.gate)) return;
   if constexpr (!BATCH && NC > 1) {
     // column chunk blockIdx.y (the grid has no empty chunk): its columns, and
     // arrival counters and mailboxes of its own, so that the chunks climb
@@ -1063,6 +1066,7 @@ __global__ __launch_bounds__(kDT) void k_mmf_down(KArgs<T, CallMM<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
   Inst<T> I; CallMM<T> C; int s;
   resolve<BATCH>(a, I, C, s);
+  if (gated_off(C.gate)) return;
   const int c0 = blockIdx.y * DC;
   if (c0 >= C.nrhs) return;
   const int nc = min(DC, C.nrhs - c0);
@@ -1130,6 +1134,7 @@ __global__ __launch_bounds__(kLT) void k_mmf_leaf(KArgs<T, CallMM<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
   Inst<T> I; CallMM<T> C; int node;
   resolve<BATCH>(a, I, C, node);
+  if (gated_off(C.gate)) return;
   const int c0 = blockIdx.y * MC;
   if (c0 >= C.nrhs) return;
   const int nc = min(MC, C.nrhs - c0);

@@ -84,6 +84,7 @@ __global__ __launch_bounds__(kWT) void k_mmw_leaf_up(KArgs<T, CallMM<T>> a) {
   static_assert(4 * kWR * kWC <= kMaxBlock * (kWR + 1), "partial sums fit in Vs");
   const Inst<T>& I = a.inst;
   const CallMM<T>& C = a.call;
+  if (gated_off(C.gate)) return;
   const int t = wnode(a), c0 = blockIdx.y * kWC;
   const NodeInfo nd = I.nodes[t];
   const int m = nd.m, kv = nd.kv, nc = min(kWC, C.nrhs - c0);
@@ -128,6 +129,7 @@ __global__ __launch_bounds__(kWT) void k_mmw_up(KArgs<T, CallMM<T>> a) {
   __shared__ T Bs[2 * kWR * (kWR + 1)];              // B12 rows 0..ku1-1, then B21
   const Inst<T>& I = a.inst;
   const CallMM<T>& C = a.call;
+  if (gated_off(C.gate)) return;
   const int t = wnode(a), c0 = blockIdx.y * kWC;
   const NodeInfo nd = I.nodes[t], n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
   const int kv1 = n1.kv, kv2 = n2.kv, ku1 = n1.ku, ku2 = n2.ku, kw = kv1 + kv2;
@@ -184,6 +186,7 @@ __global__ __launch_bounds__(kWT) void k_mmw_down(KArgs<T, CallMM<T>> a) {
   __shared__ T Rs[2 * kWR * (kWR + 1)];              // Rs[i][j] = R_t(i, j)
   const Inst<T>& I = a.inst;
   const CallMM<T>& C = a.call;
+  if (gated_off(C.gate)) return;
   const int t = wnode(a), c0 = blockIdx.y * kWC;
   const NodeInfo nd = I.nodes[t], n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
   const int ku = nd.ku, ku1 = n1.ku, ku2 = n2.ku, kr = ku1 + ku2;
@@ -223,6 +226,7 @@ __global__ __launch_bounds__(kWT) void k_mmw_leaf_out(KArgs<T, CallMM<T>> a) {
   __shared__ __align__(16) T Ys[kWR * XL];
   const Inst<T>& I = a.inst;
   const CallMM<T>& C = a.call;
+  if (gated_off(C.gate)) return;
   const int t = wnode(a), c0 = blockIdx.y * kWL;
   const NodeInfo nd = I.nodes[t];
   const int m = nd.m, ku = I.p > 0 ? nd.ku : 0, nc = min(kWL, C.nrhs - c0);

@@ -404,7 +404,7 @@ __device__ __forceinline__ bool sv_resolve(const KArgs<T, CallSV<T>>& a, Inst<T>
     C = a.call;
     node = a.node0 + item;
   }
-  return true;
+  return !gated_off(C.gate);
 }
 
 // A node's record and its children's, all three reads issued together (the

@@ -26,7 +26,6 @@
 
 namespace hss {
 
-constexpr int32_t kStatusSingular = 4;
 
 // U~ of node n as a kept x ku matrix: trailing kept rows of FU; when rows were
 // eliminated the entries above the diagonal of U~ hold reflector data and
@@ -380,7 +379,10 @@ __global__ __launch_bounds__(kNT) void k_ulv_root_lu(KArgs<T, CallSV<T>> a) {
       if (tid == 0) {
         pivs = bi;
         I.piv[j] = bi;
-        if (best == 0.0) atomicOr(I.status, 1 << kStatusSingular);
+        if (best == 0.0) {
+          atomicOr(I.status, 1 << kCodeSingular);
+          atomicMax(I.status + kStSingularNode, node + 1);
+        }
       }
     }
     __syncthreads();
@@ -471,7 +473,10 @@ __global__ __launch_bounds__(kNT) void k_ulv_root_lu2(KArgs<T, CallSV<T>> a) {
     }
     __syncthreads();
   }
-  if (tid == 0 && s_sing) atomicOr(I.status, 1 << kStatusSingular);
+  if (tid == 0 && s_sing) {
+    atomicOr(I.status, 1 << kCodeSingular);
+    atomicMax(I.status + kStSingularNode, node + 1);
+  }
   for (int o = tid; o < mp * mp; o += kNT) I.rootLU[o] = Ls[o % mp + (o / mp) * ld];
 }
 

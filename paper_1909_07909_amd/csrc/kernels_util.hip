@@ -25,7 +25,9 @@ __global__ void k_cast(const double* __restrict__ s, float* __restrict__ d, int6
 }
 
 __global__ void k_scale_cast(const double* __restrict__ s, int64_t lds, float* __restrict__ d,
-                             int64_t ldd, int64_t n, const double* __restrict__ scale) {
+                             int64_t ldd, int64_t n, const double* __restrict__ scale,
+                             const int32_t* gate) {
+  if (gated_off(gate)) return;
   const int64_t j = blockIdx.y;
   // a zero column stays zero (its scale is 0)
   const double f = scale ? (scale[j] > 0.0 ? 1.0 / scale[j] : 0.0) : 1.0;
@@ -35,19 +37,12 @@ __global__ void k_scale_cast(const double* __restrict__ s, int64_t lds, float* _
 
 __global__ void k_axpy_cast(const float* __restrict__ dd, int64_t ldd, double* __restrict__ x,
                             int64_t ldx, int64_t n, const double* __restrict__ scale,
-                            const double* __restrict__ gate, double tol) {
-  if (gate && gate[0] <= tol) return;   // converged: the correction is not applied
+                            const int32_t* gate) {
+  if (gated_off(gate)) return;   // converged: the correction is not applied
   const int64_t j = blockIdx.y;
   const double f = scale ? scale[j] : 1.0;
   for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
     x[i + j * ldx] += f * (double)dd[i + j * ldd];
-}
-
-__global__ void k_residual(const double* __restrict__ b, int64_t ldb, double* __restrict__ r,
-                           int64_t ldr, int64_t n) {
-  const int64_t j = blockIdx.y;
-  for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
-    r[i + j * ldr] = b[i + j * ldb] - r[i + j * ldr];
 }
 
 __global__ void k_cast_back(const float* __restrict__ s, int64_t lds, double* __restrict__ d,
@@ -59,7 +54,8 @@ __global__ void k_cast_back(const float* __restrict__ s, int64_t lds, double* __
 }
 
 __global__ void k_axpy64(const double* __restrict__ s, int64_t lds, double* __restrict__ d,
-                         int64_t ldd, int64_t n) {
+                         int64_t ldd, int64_t n, const int32_t* gate) {
+  if (gated_off(gate)) return;
   const int64_t j = blockIdx.y;
   for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
     d[i + j * ldd] += s[i + j * lds];
@@ -86,7 +82,8 @@ __global__ void k_hash_fill(double* d, int64_t n, uint64_t seed) {
 }
 
 __global__ void k_copy2d(const double* __restrict__ s, int64_t lds, double* __restrict__ d,
-                         int64_t ldd, int64_t n) {
+                         int64_t ldd, int64_t n, const int32_t* gate) {
+  if (gated_off(gate)) return;
   const int64_t j = blockIdx.y;
   for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
     d[i + j * ldd] = s[i + j * lds];
@@ -127,18 +124,6 @@ __global__ void k_colstats(const double* __restrict__ a, int64_t lda, int64_t n,
   }
 }
 
-__global__ void k_eta(const double* rr, const double* xx, const double* bb, double normA,
-                      int64_t nrhs, double* eta, double* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double mx = 0.0;
-  for (int64_t j = 0; j < nrhs; ++j) {
-    const double den = normA * sqrt(xx[j]) + sqrt(bb[j]);
-    const double v = den > 0.0 ? sqrt(rr[j]) / den : (rr[j] > 0.0 ? INFINITY : 0.0);
-    eta[j] = v;
-    mx = fmax(mx, v);
-  }
-  out[0] = mx;
-}
 // ---------------------------------------------------------------------------
 // Fused single-instance refinement bookkeeping.  Each block reduces its rows
 // into per-block partials; the last block to finish (arrival counter, which it
@@ -175,13 +160,17 @@ __device__ __forceinline__ bool last_block(unsigned* cnt, unsigned total) {
 
 // One backward-error check: r = b - r (r holds A x on entry); per column
 // ||r||^2, max |r|, ||x||^2, ||b||^2; then, in the last block,
-// eta_j = ||r_j|| / (||A|| ||x_j|| + ||b_j||) and out = [max_j eta_j,
-// status word, eta_0 .. eta_{nrhs-1}] (one contiguous block for the host),
-// and rmax_j = max |r_j| (the scale of the next correction).
+// eta_j = ||r_j|| / (||A|| ||x_j|| + ||b_j||), out = [max_j eta_j, 0,
+// eta_0 .. eta_{nrhs-1}], rmax_j = max |r_j| (the scale of the next
+// correction), and the refinement state st (an instance's status block):
+// st[kStIters] = step, st[kStGate] = 1 if another correction is to run
+// (eta above tol and step < max_refine).  gate: skip the check when 0.
 __global__ void k_check(const double* __restrict__ b, int64_t ldb, double* __restrict__ r,
                         int64_t ldr, const double* __restrict__ x, int64_t ldx, int64_t n,
                         int nrhs, double normA, double* part, unsigned* cnt,
-                        const int32_t* status, double* rmax, double* out) {
+                        int32_t* st, double* rmax, double* out, const int32_t* gate,
+                        double tol, int step, int max_refine) {
+  if (gated_off(gate)) return;
   const int64_t j = blockIdx.y;
   double sr = 0.0, mr = 0.0, sx = 0.0, sb = 0.0, dummy = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
@@ -229,8 +218,35 @@ __global__ void k_check(const double* __restrict__ b, int64_t ldb, double* __res
   }
   if (threadIdx.x == 0) {
     out[0] = emax;
-    out[1] = (double)status[0];
+    out[1] = 0.0;
+    st[kStIters] = step;
+    st[kStGate] = (tol > 0.0 && emax > tol && step < max_refine) ? 1 : 0;
     *cnt = 0u;
+  }
+}
+
+// The solve report (hss_solve_info followed by nrhs doubles): backward
+// errors from out (when computed), refinement steps and the status from the
+// instance's status block st.
+__global__ void k_solve_info(char* info, int nrhs, const double* out, const int32_t* st,
+                             double normA, double tol, int have_eta) {
+  double* hd = reinterpret_cast<double*>(info);
+  int32_t* hi = reinterpret_cast<int32_t*>(info + 16);
+  double* eta = reinterpret_cast<double*>(info + 32);
+  for (int c = threadIdx.x; c < nrhs; c += blockDim.x) eta[c] = have_eta ? out[2 + c] : 0.0;
+  if (threadIdx.x == 0) {
+    const double em = have_eta ? out[0] : 0.0;
+    const int32_t bits = st[0];
+    int32_t status = 0;
+    if (bits & (1 << kStatusWaitCode)) status = kStatusWaitCode;
+    else if (bits & (1 << kCodeSingular)) status = kCodeSingular;
+    else if (have_eta && tol > 0.0 && !(em <= tol)) status = kCodeNoConv;
+    hd[0] = em;
+    hd[1] = normA;
+    hi[0] = have_eta ? st[kStIters] : 0;
+    hi[1] = status;
+    hi[2] = st[kStSingularNode] - 1;
+    hi[3] = nrhs;
   }
 }
 
@@ -261,8 +277,10 @@ __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
   atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
 }
 
-__global__ void k_ir_batch(int op, const IRSeg* __restrict__ segs, int count, double* gmax) {
+__global__ void k_ir_batch(int op, const IRSeg* __restrict__ segs, int count, int gated,
+                           int step, int max_refine) {
   const IRSeg S = segs[blockIdx.y];
+  if (gated && S.st[kStGate] == 0) return;
   const int64_t n = S.n;
   const int nr = S.nrhs;
   double* rr = S.stats;
@@ -291,7 +309,32 @@ __global__ void k_ir_batch(int op, const IRSeg* __restrict__ segs, int count, do
         mx = fmax(mx, v);
       }
       outv[0] = mx;
-      atomic_max_nonneg(gmax, mx);
+      S.st[kStIters] = step;
+      S.st[kStGate] = (S.tol > 0.0 && mx > S.tol && step < max_refine) ? 1 : 0;
+    }
+    return;
+  }
+  if (op == IR_INFO) {
+    if (blockIdx.x != 0 || !S.info) return;
+    char* info = static_cast<char*>(S.info);
+    double* hd = reinterpret_cast<double*>(info);
+    int32_t* hi = reinterpret_cast<int32_t*>(info + 16);
+    double* eo = reinterpret_cast<double*>(info + 32);
+    const bool have_eta = step != 0;
+    for (int c = threadIdx.x; c < nr; c += kB) eo[c] = have_eta ? eta[c] : 0.0;
+    if (threadIdx.x == 0) {
+      const double em = have_eta ? outv[0] : 0.0;
+      const int32_t bits = S.st[0];
+      int32_t status = 0;
+      if (bits & (1 << kStatusWaitCode)) status = kStatusWaitCode;
+      else if (bits & (1 << kCodeSingular)) status = kCodeSingular;
+      else if (have_eta && S.tol > 0.0 && !(em <= S.tol)) status = kCodeNoConv;
+      hd[0] = em;
+      hd[1] = S.norm2;
+      hi[0] = have_eta ? S.st[kStIters] : 0;
+      hi[1] = status;
+      hi[2] = S.st[kStSingularNode] - 1;
+      hi[3] = nr;
     }
     return;
   }
@@ -343,11 +386,11 @@ __global__ void k_ir_batch(int op, const IRSeg* __restrict__ segs, int count, do
 }
 }  // namespace
 
-void launch_ir_batch(int op, const IRSeg* segs, int count, int64_t max_n, double* gmax,
-                     hipStream_t s) {
+void launch_ir_batch(int op, const IRSeg* segs, int count, int64_t max_n, bool gated, int step,
+                     int max_refine, hipStream_t s) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_ir_batch, dim3(grid_for(max_n, 64), count), dim3(kB), 0, s, op, segs,
-                     count, gmax);
+                     count, gated ? 1 : 0, step, max_refine);
 }
 
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
@@ -356,32 +399,24 @@ void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s
 }
 
 void launch_scale_cast(const double* src, int64_t lds, float* dst, int64_t ldd, int64_t n,
-                       int64_t nrhs, const double* scale, hipStream_t s) {
+                       int64_t nrhs, const double* scale, hipStream_t s, const int32_t* gate) {
   if (n <= 0 || nrhs <= 0) return;
   hipLaunchKernelGGL(k_scale_cast, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, src, lds, dst,
-                     ldd, n, scale);
+                     ldd, n, scale, gate);
 }
 
 void launch_axpy_cast(const float* d, int64_t ldd, double* x, int64_t ldx, int64_t n,
-                      int64_t nrhs, const double* scale, hipStream_t s, const double* gate,
-                      double tol) {
+                      int64_t nrhs, const double* scale, hipStream_t s, const int32_t* gate) {
   if (n <= 0 || nrhs <= 0) return;
   hipLaunchKernelGGL(k_axpy_cast, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, d, ldd, x, ldx,
-                     n, scale, gate, tol);
-}
-
-void launch_residual(const double* b, int64_t ldb, double* r, int64_t ldr, int64_t n,
-                     int64_t nrhs, hipStream_t s) {
-  if (n <= 0 || nrhs <= 0) return;
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, b, ldb, r, ldr,
-                     n);
+                     n, scale, gate);
 }
 
 void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
-                   int64_t nrhs, hipStream_t s) {
+                   int64_t nrhs, hipStream_t s, const int32_t* gate) {
   if (n <= 0 || nrhs <= 0) return;
   hipLaunchKernelGGL(k_copy2d, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, src, lds, dst, ldd,
-                     n);
+                     n, gate);
 }
 
 void launch_cast_back(const float* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
@@ -392,10 +427,10 @@ void launch_cast_back(const float* src, int64_t lds, double* dst, int64_t ldd, i
 }
 
 void launch_axpy64(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
-                   int64_t nrhs, hipStream_t s) {
+                   int64_t nrhs, hipStream_t s, const int32_t* gate) {
   if (n <= 0 || nrhs <= 0) return;
   hipLaunchKernelGGL(k_axpy64, dim3(grid_for(n, 1024), nrhs), dim3(kB), 0, s, src, lds, dst, ldd,
-                     n);
+                     n, gate);
 }
 
 void launch_normalize(const double* src, double* dst, int64_t n, const double* sumsq,
@@ -421,21 +456,22 @@ void launch_colstats(const double* a, int64_t lda, int64_t n, int64_t nrhs, doub
                      maxabs);
 }
 
-void launch_eta(const double* rr, const double* xx, const double* bb, double normA, int64_t nrhs,
-                double* eta, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_eta, dim3(1), dim3(64), 0, s, rr, xx, bb, normA, nrhs, eta, out);
-}
-
 int check_partials(int64_t nrhs) { return 4 * kChkBlocks * (int)std::max<int64_t>(nrhs, 1); }
 
 void launch_check(const double* b, int64_t ldb, double* r, int64_t ldr, const double* x,
                   int64_t ldx, int64_t n, int64_t nrhs, double normA, double* part,
-                  unsigned* cnt, const int32_t* status, double* rmax, double* out,
-                  hipStream_t s) {
+                  unsigned* cnt, int32_t* st, double* rmax, double* out, const int32_t* gate,
+                  double tol, int step, int max_refine, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
   const int nb = (int)std::min<int64_t>(kChkBlocks, (n + kB - 1) / kB);
   hipLaunchKernelGGL(k_check, dim3(nb, nrhs), dim3(kB), 0, s, b, ldb, r, ldr, x, ldx, n,
-                     (int)nrhs, normA, part, cnt, status, rmax, out);
+                     (int)nrhs, normA, part, cnt, st, rmax, out, gate, tol, step, max_refine);
+}
+
+void launch_solve_info(void* info, int64_t nrhs, const double* out, const int32_t* st,
+                       double normA, double tol, bool have_eta, hipStream_t s) {
+  hipLaunchKernelGGL(k_solve_info, dim3(1), dim3(kB), 0, s, static_cast<char*>(info), (int)nrhs,
+                     out, st, normA, tol, have_eta ? 1 : 0);
 }
 
 void launch_colmax(const double* a, int64_t lda, int64_t n, int64_t nrhs, double* part,

@@ -8,8 +8,10 @@ raises instead of falling back to anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -53,8 +55,14 @@ class SolveOpts(C.Structure):
 
 
 class SolveInfo(C.Structure):
+    """Header of the solve report (followed by ncols doubles of eta_j)."""
     _fields_ = [("eta_max", C.c_double), ("norm2", C.c_double), ("iters", C.c_int32),
-                ("status", C.c_int32), ("eta", C.POINTER(C.c_double))]
+                ("status", C.c_int32), ("singular_node", C.c_int32), ("ncols", C.c_int32)]
+
+
+def info_bytes(nrhs: int) -> int:
+    """HSS_SOLVE_INFO_BYTES(nrhs)."""
+    return C.sizeof(SolveInfo) + 8 * int(nrhs)
 
 
 class HSSError(RuntimeError):
@@ -81,7 +89,7 @@ def lib() -> C.CDLL:
     L.hss_destroy.argtypes = [vp]
     L.hss_matmul.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp]
     L.hss_ulv_factor.argtypes = [vp, i32, vp]
-    L.hss_ulv_solve.argtypes = [vp, i64, vp, i64, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+    L.hss_ulv_solve.argtypes = [vp, i64, vp, i64, C.POINTER(SolveOpts), vp, vp]
     L.hss_query.argtypes = [vp, i32, vp, vp]
     L.hss_plan_depth.argtypes = [i64, i64]
     L.hss_plan_leaf_offsets.argtypes = [i64, i64, C.POINTER(C.c_int64), i64]
@@ -93,7 +101,7 @@ def lib() -> C.CDLL:
     L.hss_batch_ulv_factor.argtypes = [C.POINTER(vp), i32, i32, vp]
     L.hss_batch_ulv_solve.argtypes = [C.POINTER(vp), i32, C.POINTER(C.c_int64), C.POINTER(vp),
                                       C.POINTER(C.c_int64), C.POINTER(SolveOpts),
-                                      C.POINTER(SolveInfo), vp]
+                                      C.POINTER(vp), vp]
     L.hss_timing_enable.argtypes = [i32]
     L.hss_timing_report.argtypes = [C.c_char_p, i64, i32]
     L.hss_status_str.argtypes = [i32]
@@ -168,8 +176,21 @@ def _stream(stream):
     return C.c_void_p(stream)
 
 
-def colmajor(t, n):
-    """(ptr, ld) of a column-major (n, r) tensor view (strides (1, ld))."""
+def colmajor(t, n, dtypes=None):
+    """(ptr, ld) of a column-major (n, r) CUDA tensor view (strides (1, ld)).
+
+    dtypes: the accepted torch dtypes (None: float64 and float32).  Raises
+    TypeError for a host tensor or another dtype and ValueError for a shape
+    or layout the kernels cannot take, before anything reaches the library."""
+    import torch
+    if dtypes is None:
+        dtypes = (torch.float64, torch.float32)
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise TypeError("tensor must be in GPU memory (device='cuda')")
+    if t.dtype not in dtypes:
+        raise TypeError(f"tensor dtype {t.dtype} not accepted here (expected one of {dtypes})")
     if t.dim() != 2 or t.shape[0] != n:
         raise ValueError(f"expected an ({n}, r) tensor, got {tuple(t.shape)}")
     # (the row stride of a one-row tensor is immaterial)
@@ -186,16 +207,89 @@ def empty_colmajor(n, r, dtype, device="cuda"):
     return torch.empty((r, n), dtype=dtype, device=device).t()
 
 
+# Device allocator hooks backed by PyTorch's caching allocator (the memory of
+# a handle then counts in torch.cuda.memory_allocated).  Module-level, so the
+# callbacks outlive every handle that uses them.
+def _torch_alloc(nbytes, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes))
+    except RuntimeError:
+        return None
+
+
+def _torch_free(ptr, ctx):
+    import torch
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+TORCH_ALLOC = Alloc(Alloc._fields_[0][1](_torch_alloc), Alloc._fields_[1][1](_torch_free), None)
+
+
+class SolveReport:
+    """The solve report the device writes (pinned host memory).  Read it with
+    result() once the stream has reached the end of the solve."""
+
+    def __init__(self, nrhs):
+        import torch
+        self.nrhs = int(nrhs)
+        self.buf = torch.zeros(info_bytes(nrhs), dtype=torch.uint8, pin_memory=True)
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.buf.data_ptr())
+
+    def result(self):
+        raw = self.buf.numpy()
+        hdr = SolveInfo.from_buffer_copy(raw[:C.sizeof(SolveInfo)].tobytes())
+        eta = np.frombuffer(raw[C.sizeof(SolveInfo):].tobytes(), dtype=np.float64)
+        return {"status": int(hdr.status), "eta": eta[:self.nrhs].copy(),
+                "eta_max": float(hdr.eta_max), "iters": int(hdr.iters), "norm2": float(hdr.norm2),
+                "singular_node": int(hdr.singular_node), "ncols": int(hdr.ncols)}
+
+
+def _sync(stream):
+    import torch
+    if stream is None:
+        torch.cuda.current_stream().synchronize()
+    elif hasattr(stream, "synchronize"):
+        stream.synchronize()
+    else:
+        torch.cuda.synchronize()
+
+
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # handles whose memory came from PyTorch's allocator are released before
+    # the interpreter (and the allocator's Python entry points) shut down
+    for m in list(_LIVE):
+        try:
+            m.close()
+        except Exception:
+            pass
+
+
 class HSSMatrix:
     """Device-resident HSS matrix created from generators in the canonical
-    packed layout (attributes n, p, leaf_off, ku, kv, D, U, V, R, W, B12, B21)."""
+    packed layout (attributes n, p, leaf_off, ku, kv, D, U, V, R, W, B12, B21).
 
-    def __init__(self, g, stream=None, alloc=None):
+    alloc: "torch" (default) allocates the handle's device memory from
+    PyTorch's caching allocator, None uses hipMalloc, or an Alloc structure."""
+
+    def __init__(self, g, stream=None, alloc="torch"):
         L = lib()
         td, self._keep = _tree(g.n, g.p, g.leaf_off, g.ku, g.kv)
         arrs = [np.ascontiguousarray(getattr(g, k), dtype=np.float64)
                 for k in ("D", "U", "V", "R", "W", "B12", "B21")]
         gh = GenHost(*[a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs])
+        if isinstance(alloc, str):
+            if alloc != "torch":
+                raise ValueError(f"unknown allocator {alloc!r}")
+            alloc = TORCH_ALLOC
+        self._alloc = alloc
         h = C.c_void_p()
         code = L.hss_create(C.byref(td), C.byref(gh), C.byref(alloc) if alloc else None,
                             _stream(stream), C.byref(h))
@@ -203,6 +297,7 @@ class HSSMatrix:
         self.h = h
         self.n = int(g.n)
         self.p = int(g.p)
+        _LIVE.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -216,16 +311,17 @@ class HSSMatrix:
             pass
 
     def matmul(self, X, Y=None, op=OP_N, stream=None):
-        """Y = op(A) X for a column-major (n, r) CUDA tensor (float64 or float32)."""
+        """Y = op(A) X for a column-major (n, r) CUDA tensor (float64 or float32);
+        Y, if given, must have X's dtype."""
         import torch
+        xp, ldx = colmajor(X, self.n)
         prec = F64 if X.dtype == torch.float64 else F32
-        if X.dtype not in (torch.float64, torch.float32):
-            raise TypeError("X must be float64 or float32")
         r = X.shape[1]
         if Y is None:
             Y = empty_colmajor(self.n, r, X.dtype, X.device)
-        xp, ldx = colmajor(X, self.n)
-        yp, ldy = colmajor(Y, self.n)
+        yp, ldy = colmajor(Y, self.n, (X.dtype,))
+        if Y.shape[1] != r:
+            raise ValueError(f"Y has {Y.shape[1]} columns, X has {r}")
         _check(lib().hss_matmul(self.h, op, prec, r, xp, ldx, yp, ldy, _stream(stream)),
                "hss_matmul")
         return Y
@@ -234,25 +330,37 @@ class HSSMatrix:
         _check(lib().hss_ulv_factor(self.h, prec, _stream(stream)), "hss_ulv_factor")
 
     def solve(self, B, prec=F64, tol=0.0, max_refine=10, want_eta=False, stream=None,
-              check=True):
-        """B <- A^{-1} B in place (column-major float64 CUDA tensor).  Returns
-        a dict with eta (per column), eta_max, iters, status, norm2."""
+              check=True, sync=True, report=None):
+        """B <- A^{-1} B in place (column-major float64 CUDA tensor).
+
+        sync=True: waits for the stream and returns a dict with eta (per
+        column), eta_max, iters, status, norm2 and singular_node, raising
+        HSSError for a status other than HSS_OK when check is set.
+        sync=False: returns the SolveReport (read it after the stream has
+        reached the end of the solve); nothing waits.  report: a SolveReport
+        to write (e.g. one allocated before a graph capture)."""
+        import torch
+        bp, ldb = colmajor(B, self.n, (torch.float64,))
         r = B.shape[1]
-        bp, ldb = colmajor(B, self.n)
         opts = SolveOpts(prec, max_refine, tol, 1 if want_eta else 0, 0)
-        eta = np.zeros(max(r, 1), dtype=np.float64)
-        info = SolveInfo(0.0, 0.0, 0, 0, eta.ctypes.data_as(C.POINTER(C.c_double)))
-        code = lib().hss_ulv_solve(self.h, r, bp, ldb, C.byref(opts), C.byref(info),
-                                   _stream(stream))
-        if check and code not in (HSS_OK,):
-            raise HSSError(code, "hss_ulv_solve")
-        return {"status": int(code), "eta": eta[:r].copy(), "eta_max": info.eta_max,
-                "iters": info.iters, "norm2": info.norm2}
+        rep = SolveReport(r) if report is None else report
+        if rep.nrhs < r:
+            raise ValueError(f"report holds {rep.nrhs} columns, the solve has {r}")
+        code = lib().hss_ulv_solve(self.h, r, bp, ldb, C.byref(opts), rep.ptr, _stream(stream))
+        _check(code, "hss_ulv_solve")
+        if not sync:
+            return rep
+        _sync(stream)
+        out = rep.result()
+        if check and out["status"] != HSS_OK:
+            raise HSSError(out["status"], "hss_ulv_solve")
+        return out
 
     def solve_async(self, B, prec=F64, stream=None):
-        """Plain solve without a backward error: no synchronization."""
+        """Plain solve without a backward error or report: no synchronization."""
+        import torch
         r = B.shape[1]
-        bp, ldb = colmajor(B, self.n)
+        bp, ldb = colmajor(B, self.n, (torch.float64,))
         opts = SolveOpts(prec, 0, 0.0, 0, 0)
         _check(lib().hss_ulv_solve(self.h, r, bp, ldb, C.byref(opts), None, _stream(stream)),
                "hss_ulv_solve")
@@ -283,37 +391,51 @@ def batch_factor(mats, prec=F64, stream=None):
 
 def batch_matmul(mats, Xs, Ys, op=OP_N, stream=None):
     import torch
-    prec = F64 if Xs[0].dtype == torch.float64 else F32
-    hs = _ptr_array([m.h.value for m in mats])
-    nr = (C.c_int64 * len(mats))(*[x.shape[1] for x in Xs])
+    if not (len(mats) == len(Xs) == len(Ys)):
+        raise ValueError("mats, Xs and Ys must have the same length")
+    if not mats:
+        return
+    dt = Xs[0].dtype
+    if dt not in (torch.float64, torch.float32):
+        raise TypeError("X must be float64 or float32")
+    prec = F64 if dt == torch.float64 else F32
     xp, lx, yp, ly = [], [], [], []
     for m, x, y in zip(mats, Xs, Ys):
-        a, b = colmajor(x, m.n)
-        c, d = colmajor(y, m.n)
+        a, b = colmajor(x, m.n, (dt,))
+        c, d = colmajor(y, m.n, (dt,))
+        if y.shape[1] != x.shape[1]:
+            raise ValueError("each Y must have its X's column count")
         xp.append(a.value); lx.append(b); yp.append(c.value); ly.append(d)
+    hs = _ptr_array([m.h.value for m in mats])
+    nr = (C.c_int64 * len(mats))(*[x.shape[1] for x in Xs])
     _check(lib().hss_batch_matmul(hs, len(mats), op, prec, nr, _ptr_array(xp),
                                   (C.c_int64 * len(mats))(*lx), _ptr_array(yp),
                                   (C.c_int64 * len(mats))(*ly), _stream(stream)),
            "hss_batch_matmul")
 
 
-def batch_solve(mats, Bs, prec=F64, tol=0.0, max_refine=10, want_eta=False, stream=None):
-    hs = _ptr_array([m.h.value for m in mats])
+def batch_solve(mats, Bs, prec=F64, tol=0.0, max_refine=10, want_eta=False, stream=None,
+                sync=True):
+    """B_i <- A_i^{-1} B_i for every instance (one launch per tree level).
+    sync=True: waits and returns one report dict per instance; sync=False
+    returns the SolveReports."""
+    import torch
+    if len(mats) != len(Bs):
+        raise ValueError("mats and Bs must have the same length")
     cnt = len(mats)
-    nr = (C.c_int64 * cnt)(*[b.shape[1] for b in Bs])
     bp, lb = [], []
     for m, b in zip(mats, Bs):
-        a, l = colmajor(b, m.n)
+        a, l = colmajor(b, m.n, (torch.float64,))
         bp.append(a.value); lb.append(l)
+    hs = _ptr_array([m.h.value for m in mats])
+    nr = (C.c_int64 * cnt)(*[b.shape[1] for b in Bs])
     opts = SolveOpts(prec, max_refine, tol, 1 if want_eta else 0, 0)
-    etas = [np.zeros(max(b.shape[1], 1)) for b in Bs]
-    infos = (SolveInfo * cnt)()
-    for i in range(cnt):
-        infos[i].eta = etas[i].ctypes.data_as(C.POINTER(C.c_double))
+    reps = [SolveReport(b.shape[1]) for b in Bs]
     code = lib().hss_batch_ulv_solve(hs, cnt, nr, _ptr_array(bp), (C.c_int64 * cnt)(*lb),
-                                     C.byref(opts), infos, _stream(stream))
-    if code not in (HSS_OK, HSS_ENOCONV):
-        raise HSSError(code, "hss_batch_ulv_solve")
-    return [{"eta": etas[i][:Bs[i].shape[1]].copy(), "eta_max": infos[i].eta_max,
-             "iters": infos[i].iters, "status": infos[i].status, "norm2": infos[i].norm2}
-            for i in range(cnt)]
+                                     C.byref(opts), _ptr_array([r.ptr.value for r in reps]),
+                                     _stream(stream))
+    _check(code, "hss_batch_ulv_solve")
+    if not sync:
+        return reps
+    _sync(stream)
+    return [r.result() for r in reps]

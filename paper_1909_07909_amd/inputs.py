@@ -136,6 +136,71 @@ def synthetic_hss(leaf_off, k: int, seed, diag_shift: float | None = None) -> Ge
     return Generators(n=n, p=p, leaf_off=leaf_off, ku=ku, kv=kv, **a)
 
 
+def ragged_ranks(p: int, seed, lo: int = 4, hi: int = 16, max_leaf_rank: int | None = None):
+    """Per-node ranks (ku, kv) drawn independently, uniform in [lo, hi] at the
+    leaves and capped at internal nodes by what the children provide
+    (ku_t <= ku_c1 + ku_c2, likewise kv), so that every translation operator
+    has at least as many rows as columns.  Root entries are 0."""
+    nn = 2 ** (p + 1) - 1
+    rng = np.random.default_rng(seed)
+    ku = np.zeros(nn, dtype=np.int32)
+    kv = np.zeros(nn, dtype=np.int32)
+    if p == 0:
+        return ku, kv
+    cap = hi if max_leaf_rank is None else min(hi, max_leaf_rank)
+    for t in range(nn - 1, 0, -1):
+        a = int(rng.integers(lo, hi + 1))
+        b = int(rng.integers(lo, hi + 1))
+        if _is_leaf(t, p):
+            ku[t], kv[t] = min(a, cap), min(b, cap)
+        else:
+            ku[t] = min(a, ku[2 * t + 1] + ku[2 * t + 2])
+            kv[t] = min(b, kv[2 * t + 1] + kv[2 * t + 2])
+    return ku, kv
+
+
+def synthetic_hss_ranked(leaf_off, ku, kv, seed) -> Generators:
+    """The synthetic family with per-node ranks: U_i (m_i x ku_i), V_i
+    (m_i x kv_i), R_t ((ku_c1 + ku_c2) x ku_t), W_t ((kv_c1 + kv_c2) x kv_t)
+    Haar-orthonormal; B12_t = P diag(sigma) Q^T of shape ku_c1 x kv_c2 (B21
+    ku_c2 x kv_c1) with sigma_j = 0.5 * 10^(-j/4) over min(rows, cols);
+    D_i = m_i I + G/sqrt(m_i).  Same draw order as ``synthetic_hss``."""
+    leaf_off = np.asarray(leaf_off, dtype=np.int64)
+    nleaf = leaf_off.size - 1
+    p = int(round(np.log2(nleaf)))
+    assert 2 ** p == nleaf
+    n = int(leaf_off[-1])
+    ku = np.asarray(ku, dtype=np.int32).copy()
+    kv = np.asarray(kv, dtype=np.int32).copy()
+    ku[0] = kv[0] = 0
+    rng = np.random.default_rng(seed)
+
+    def core(rows, cols):
+        q = min(rows, cols)
+        sig = 0.5 * 10.0 ** (-np.arange(q) / 4.0)
+        P = haar_orthonormal(rng, rows, q)
+        Q = haar_orthonormal(rng, cols, q)
+        return (P * sig) @ Q.T
+
+    pk = _Packer()
+    for t in range(2 ** (p + 1) - 1):
+        if _is_leaf(t, p):
+            m = _leaf_size(leaf_off, t, p)
+            if p > 0:
+                pk.add("U", haar_orthonormal(rng, m, int(ku[t])))
+                pk.add("V", haar_orthonormal(rng, m, int(kv[t])))
+            pk.add("D", m * np.eye(m) + rng.standard_normal((m, m)) / np.sqrt(m))
+        else:
+            c1, c2 = 2 * t + 1, 2 * t + 2
+            if t != 0:
+                pk.add("R", haar_orthonormal(rng, int(ku[c1] + ku[c2]), int(ku[t])))
+                pk.add("W", haar_orthonormal(rng, int(kv[c1] + kv[c2]), int(kv[t])))
+            pk.add("B12", core(int(ku[c1]), int(kv[c2])))
+            pk.add("B21", core(int(ku[c2]), int(kv[c1])))
+    a = pk.arrays()
+    return Generators(n=n, p=p, leaf_off=leaf_off, ku=ku, kv=kv, **a)
+
+
 def rhs(n: int, r: int, seed) -> np.ndarray:
     """n x r standard normal block, Fortran order."""
     rng = np.random.default_rng(seed)

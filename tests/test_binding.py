@@ -1,0 +1,82 @@
+"""Host-side checks of the Python binding and of the test-side start vector
+(no GPU needed): arguments the kernels cannot take are rejected before they
+reach the library; the splitmix64 start vector matches the generator's
+published outputs; the oracle's power method honours a given start vector."""
+import numpy as np
+import pytest
+
+from oracle import tree
+from oracle.hss import HSS
+from oracle.norms import norm2_power
+from paper_1909_07909_amd import hss, inputs
+from startvec import splitmix_raw, splitmix_start
+
+torch = pytest.importorskip("torch")
+
+
+def test_splitmix_published_outputs():
+    # splitmix64 seeded with 0: its first three outputs (states g, 2g, 3g)
+    g = 0x9E3779B97F4A7C15
+    idx = np.array([0, g, (2 * g) % 2 ** 64], dtype=np.uint64)
+    got = [int(x) for x in splitmix_raw(idx, seed=0)]
+    assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    v = splitmix_start(1000)
+    assert v.min() >= -1.0 and v.max() < 1.0 and abs(v.mean()) < 0.1
+
+
+def test_power_method_start_vector():
+    """Started from the top right singular vector, one power step returns
+    sigma_1 exactly (to rounding)."""
+    g = inputs.synthetic_hss(tree.leaf_offsets(256, 32), 4, seed=1)
+    H = HSS.from_packed(g)
+    _, s, vt = np.linalg.svd(H.dense())
+    assert abs(norm2_power(H, iters=1, x0=vt[0]) - s[0]) <= 1e-12 * s[0]
+    # a start vector orthogonal to the top one: the estimate is below sigma_1
+    assert norm2_power(H, iters=1, x0=vt[-1]) < s[0] * (1 - 1e-6)
+
+
+class _Fake(hss.HSSMatrix):
+    """An HSSMatrix shell with no device handle: the argument checks run
+    before any library call, so they can be exercised without a GPU."""
+
+    def __init__(self, n):
+        self.n, self.p, self.h = n, 0, None
+
+    def close(self):
+        pass
+
+
+def test_colmajor_rejects_host_and_dtype():
+    n = 8
+    with pytest.raises(TypeError):
+        hss.colmajor(torch.zeros((n, 2), dtype=torch.float64), n)       # host tensor
+    with pytest.raises(TypeError):
+        hss.colmajor(np.zeros((n, 2)), n)                                # not a tensor
+    A = _Fake(n)
+    with pytest.raises(TypeError):
+        A.matmul(torch.zeros((2, n), dtype=torch.float64).t())
+    with pytest.raises(TypeError):
+        A.solve(torch.zeros((2, n), dtype=torch.float32).t())
+    with pytest.raises(ValueError):
+        hss.batch_solve([A], [])
+
+
+@pytest.mark.gpu
+def test_colmajor_rejects_mixed_dtypes():
+    n = 8
+    A = _Fake(n)
+    X = torch.zeros((2, n), dtype=torch.float64, device="cuda").t()
+    Y = torch.zeros((2, n), dtype=torch.float32, device="cuda").t()
+    with pytest.raises(TypeError):
+        A.matmul(X, Y)
+    with pytest.raises(TypeError):
+        A.solve(X.float())
+    with pytest.raises(ValueError):
+        A.matmul(X, torch.zeros((3, n), dtype=torch.float64, device="cuda").t())
+    with pytest.raises(TypeError):
+        hss.batch_matmul([A, A], [X, X], [X.clone(), Y])
+
+
+def test_info_layout():
+    # HSS_SOLVE_INFO_BYTES(nrhs) = 32 + 8 nrhs: two doubles, four int32
+    assert hss.info_bytes(0) == 32 and hss.info_bytes(5) == 72

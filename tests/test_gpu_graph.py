@@ -57,3 +57,86 @@ def test_product_graph_replays(r):
         assert torch.equal(Y2, ref2)
     del g
     A.close()
+
+
+def test_product_graph_survives_wider_calls():
+    """A graph captured from a 4-column product keeps working after later
+    calls on the same handle needed wider work buffers (a 64-column product
+    and a 64-column refined solve): the buffers they replaced are kept."""
+    from paper_1909_07909_amd import hss
+    n, m, k, r = 4096, 128, 16, 4
+    A = hss.HSSMatrix(inputs.synthetic_hss(tree.leaf_offsets(n, m), k, seed=44))
+    X = _to_dev(inputs.rhs(n, r, 45))
+    Y = hss.empty_colmajor(n, r, torch.float64)
+    A.matmul(X, Y)
+    torch.cuda.synchronize()
+    ref = Y.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        A.matmul(X, Y)
+    torch.cuda.synchronize()
+    Xw = _to_dev(inputs.rhs(n, 64, 46))
+    A.matmul(Xw)
+    A.factor(hss.F32)
+    A.solve(_to_dev(inputs.rhs(n, 64, 47)), prec=hss.F32, tol=1e-10)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        Y.fill_(0.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Y, ref)
+    del g
+    A.close()
+
+
+@pytest.mark.parametrize("r,max_refine", [(1, 2), (8, 3)])
+def test_fresh_refined_solve_graph(r, max_refine):
+    """A whole fresh-system step (FP32 factorization, FP32 solve, FP64
+    residuals and gated FP32 corrections up to max_refine, the device-written
+    report) captured once and replayed: the refinement steps are gated on the
+    device, so the step has no host synchronisation.  Every replay must give
+    the eager solution and report bit for bit."""
+    from paper_1909_07909_amd import hss
+    n, m, k = 8192, 128, 32
+    print(f"[graph fresh step] n={n} k={k} r={r} max_refine={max_refine}", flush=True)
+    A = hss.HSSMatrix(inputs.synthetic_hss(tree.leaf_offsets(n, m), k, seed=48))
+    B0 = _to_dev(inputs.rhs(n, r, 49))
+    B = B0.clone()
+    rep = hss.SolveReport(r)
+
+    def step():
+        B.copy_(B0)
+        A.factor(hss.F32)
+        A.solve(B, prec=hss.F32, tol=1e-10, max_refine=max_refine, sync=False, report=rep)
+
+    step()                                  # eager: sizes every work buffer
+    torch.cuda.synchronize()
+    ref_x, ref_rep = B.clone(), rep.result()
+    assert ref_rep["status"] == 0 and ref_rep["iters"] == 1 and ref_rep["eta_max"] <= 1e-10
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    Bo = _to_dev(inputs.rhs(n, r, 50))
+    for _ in range(4):
+        B.fill_(0.0)
+        rep.buf.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(B, ref_x)
+        got = rep.result()
+        assert np.array_equal(got["eta"], ref_rep["eta"])
+        assert {k: got[k] for k in ("eta_max", "iters", "status", "norm2")} == \
+               {k: ref_rep[k] for k in ("eta_max", "iters", "status", "norm2")}
+        # eager work on the handle between replays
+        A.solve(Bo.clone(), prec=hss.F32, tol=1e-10)
+        torch.cuda.synchronize()
+    del g
+    A.close()

@@ -1,5 +1,5 @@
 """Pins of the oracle's cluster tree (Def. 2.1, default split of Sec. 3.1,
-cluster vectors of Sec. 3.6)."""
+cluster vectors of Sec. 3.7)."""
 import os
 
 import pytest
