@@ -58,6 +58,7 @@ typedef int32_t hss_status;
 #define HSS_ESINGULAR  4   /* exact zero pivot in an L block or the root LU     */
 #define HSS_ENOCONV    5   /* refinement reached max_refine above tol           */
 #define HSS_EUNSUP     6   /* sizes beyond what the kernels support             */
+#define HSS_ESCRATCH   7   /* beyond the fixed scratch of hss_matmul_noalloc    */
 
 #define HSS_OP_N 0          /* Y = A X   */
 #define HSS_OP_T 1          /* Y = A^T X */
@@ -164,6 +165,23 @@ hss_status hss_destroy(hss_handle *h);
  * nrhs == 0 is a no-op.  Asynchronous on stream. */
 hss_status hss_matmul(hss_handle *h, int32_t op, int32_t prec, int64_t nrhs,
                       const void *X, int64_t ldx, void *Y, int64_t ldy, void *stream);
+
+/* hss_matmul_noalloc: hss_matmul for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as hss_matmul, but
+ * the product's work vectors (x^ and y^, 2 * ldm * max(nrhs, 8) elements,
+ * ldm = sum over nodes of max(ku_t, kv_t)) live in a fixed 32 MiB device
+ * array of the library instead of the handle's growable buffers, so the call
+ * never allocates.  Each GPU holds its own copy of that array from library
+ * load until the process ends.  Returns HSS_ESCRATCH (nothing enqueued) when
+ * the product does not fit; hss_matmul_noalloc_max_rhs gives the largest nrhs
+ * that fits (0 if none, -1 for invalid arguments).  The current device must
+ * be the handle's.  Every call on a GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (on different streams or handles) race, so the
+ * caller serializes them, e.g. on one stream. */
+hss_status hss_matmul_noalloc(hss_handle *h, int32_t op, int32_t prec, int64_t nrhs,
+                              const void *X, int64_t ldx, void *Y, int64_t ldy, void *stream);
+int64_t hss_matmul_noalloc_max_rhs(hss_handle *h, int32_t prec);
 
 /* hss_ulv_factor: implicit ULV factorization (Sec. 4.3, Step 1 on the leaves,
  * Step 3 merging siblings level by level, dense LU with partial pivoting of the

@@ -863,6 +863,42 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
   return last_launch_status();
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of hss_matmul_noalloc: the product's x^ and y^ work
+// vectors for callers that cannot allocate.  Each GPU the library runs on
+// holds its own copy from load until the process ends.  Its device address is
+// looked up once per device (hipGetSymbolAddress with that device current);
+// host code uses only that address, never the array's name.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+constexpr int kNoAllocMinCols = 8;   // columns reserved per work vector (a product chunk)
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kMaxDevices] = {};
+
+hss_status noalloc_scratch(char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return HSS_EHIP;
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return HSS_EHIP;
+    }
+    g_noalloc_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return HSS_OK;
+}
+
+// Bytes of scratch the product of nrhs columns takes: x^ and y^, each ldm
+// rows by max(nrhs, kNoAllocMinCols) columns.
+int64_t noalloc_bytes(const Plan& P, int64_t nrhs, size_t es) {
+  return 2 * P.ldm * std::max<int64_t>(nrhs, kNoAllocMinCols) * (int64_t)es;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -877,6 +913,8 @@ const char* hss_status_str(hss_status s) {
     case HSS_ESINGULAR: return "exactly singular pivot";
     case HSS_ENOCONV: return "refinement did not reach the tolerance";
     case HSS_EUNSUP: return "sizes beyond what the kernels support";
+    case HSS_ESCRATCH:
+      return "the product needs more than the fixed scratch of the allocation-free entry point";
     default: return s < 0 ? "invalid argument" : "unknown status";
   }
 }
@@ -1039,6 +1077,45 @@ hss_status hss_matmul(hss_handle* h, int32_t op, int32_t prec, int64_t nrhs, con
     run_matmul<float>(h, op, nrhs, (const float*)X, ldx, (float*)Y, ldy, s);
   }
   return last_launch_status();
+}
+
+hss_status hss_matmul_noalloc(hss_handle* h, int32_t op, int32_t prec, int64_t nrhs,
+                              const void* X, int64_t ldx, void* Y, int64_t ldy, void* stream) {
+  if (!h) return -1;
+  if (op != HSS_OP_N && op != HSS_OP_T) return -2;
+  if (prec != HSS_F64 && prec != HSS_F32) return -3;
+  if (nrhs < 0) return -4;
+  if (nrhs == 0) return HSS_OK;
+  if (!X) return -5;
+  if (ldx < h->plan.n) return -6;
+  if (!Y) return -7;
+  if (ldy < h->plan.n) return -8;
+  const size_t es = prec == HSS_F64 ? 8 : 4;
+  const char* x0 = (const char*)X;
+  const char* y0 = (const char*)Y;
+  const char* x1 = x0 + es * (size_t)(ldx * (nrhs - 1) + h->plan.n);
+  const char* y1 = y0 + es * (size_t)(ldy * (nrhs - 1) + h->plan.n);
+  if (x0 < y1 && y0 < x1) return -7;   // X and Y overlap
+  if (noalloc_bytes(h->plan, nrhs, es) > (int64_t)kNoAllocScratchBytes) return HSS_ESCRATCH;
+  char* sp = nullptr;
+  hss_status st = noalloc_scratch(&sp);
+  if (st) return st;
+  const int64_t half = h->plan.ldm * std::max<int64_t>(nrhs, kNoAllocMinCols) * (int64_t)es;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == HSS_F64)
+    run_matmul<double>(h, op, nrhs, (const double*)X, ldx, (double*)Y, ldy, s, nullptr,
+                       reinterpret_cast<double*>(sp), reinterpret_cast<double*>(sp + half));
+  else
+    run_matmul<float>(h, op, nrhs, (const float*)X, ldx, (float*)Y, ldy, s, nullptr,
+                      reinterpret_cast<float*>(sp), reinterpret_cast<float*>(sp + half));
+  return last_launch_status();
+}
+
+int64_t hss_matmul_noalloc_max_rhs(hss_handle* h, int32_t prec) {
+  if (!h || (prec != HSS_F64 && prec != HSS_F32)) return -1;
+  const int64_t es = prec == HSS_F64 ? 8 : 4;
+  const int64_t cols = (int64_t)kNoAllocScratchBytes / (2 * h->plan.ldm * es);
+  return cols >= kNoAllocMinCols ? cols : 0;
 }
 
 hss_status hss_ulv_factor(hss_handle* h, int32_t prec, void* stream) {

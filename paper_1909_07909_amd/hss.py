@@ -18,7 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhss.so")
 
-HSS_OK, HSS_ENOMEM, HSS_EHIP, HSS_ESTATE, HSS_ESINGULAR, HSS_ENOCONV, HSS_EUNSUP = range(7)
+(HSS_OK, HSS_ENOMEM, HSS_EHIP, HSS_ESTATE, HSS_ESINGULAR, HSS_ENOCONV, HSS_EUNSUP,
+ HSS_ESCRATCH) = range(8)
 OP_N, OP_T = 0, 1
 F64, F32 = 0, 1
 
@@ -27,7 +28,7 @@ EXPORTS = (
     "hss_create", "hss_destroy", "hss_matmul", "hss_ulv_factor", "hss_ulv_solve", "hss_query",
     "hss_plan_depth", "hss_plan_leaf_offsets", "hss_plan_node_ranges", "hss_batch_matmul",
     "hss_batch_ulv_factor", "hss_batch_ulv_solve", "hss_status_str", "hss_timing_enable",
-    "hss_timing_report",
+    "hss_timing_report", "hss_matmul_noalloc", "hss_matmul_noalloc_max_rhs",
 )
 
 Q_N, Q_P, Q_RESIDENT_BYTES, Q_NORM2, Q_GEN_ENTRIES, Q_FACTOR_ENTRIES = range(6)
@@ -88,6 +89,8 @@ def lib() -> C.CDLL:
                              C.POINTER(vp)]
     L.hss_destroy.argtypes = [vp]
     L.hss_matmul.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp]
+    L.hss_matmul_noalloc.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp]
+    L.hss_matmul_noalloc_max_rhs.argtypes = [vp, i32]
     L.hss_ulv_factor.argtypes = [vp, i32, vp]
     L.hss_ulv_solve.argtypes = [vp, i64, vp, i64, C.POINTER(SolveOpts), vp, vp]
     L.hss_query.argtypes = [vp, i32, vp, vp]
@@ -110,6 +113,7 @@ def lib() -> C.CDLL:
         f = getattr(L, name)
         if name != "hss_status_str" and f.restype is not C.c_char_p:
             f.restype = C.c_int32
+    L.hss_matmul_noalloc_max_rhs.restype = C.c_int64
     _lib = L
     return L
 
@@ -325,6 +329,23 @@ class HSSMatrix:
         _check(lib().hss_matmul(self.h, op, prec, r, xp, ldx, yp, ldy, _stream(stream)),
                "hss_matmul")
         return Y
+
+    def matmul_noalloc(self, X, Y, op=OP_N, stream=None):
+        """Y = op(A) X through hss_matmul_noalloc (work vectors in the library's
+        fixed device scratch; Y must be given).  Raises HSSError with
+        HSS_ESCRATCH when the product does not fit that scratch."""
+        import torch
+        xp, ldx = colmajor(X, self.n)
+        yp, ldy = colmajor(Y, self.n, (X.dtype,))
+        if Y.shape[1] != X.shape[1]:
+            raise ValueError(f"Y has {Y.shape[1]} columns, X has {X.shape[1]}")
+        prec = F64 if X.dtype == torch.float64 else F32
+        _check(lib().hss_matmul_noalloc(self.h, op, prec, X.shape[1], xp, ldx, yp, ldy,
+                                        _stream(stream)), "hss_matmul_noalloc")
+        return Y
+
+    def noalloc_max_rhs(self, prec=F64):
+        return int(lib().hss_matmul_noalloc_max_rhs(self.h, prec))
 
     def factor(self, prec=F64, stream=None):
         _check(lib().hss_ulv_factor(self.h, prec, _stream(stream)), "hss_ulv_factor")
