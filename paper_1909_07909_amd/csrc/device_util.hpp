@@ -332,4 +332,31 @@ __device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t
 // dropped, loads return zero).
 constexpr uint32_t kBufOOB = 0x80000000u;
 
+// ---------------------------------------------------------------------------
+// 16 x 16 x 4 matrix-core products (one wavefront): lane 16 g + c supplies
+// A(c, g) and B(g, c) and holds four entries of the 16 x 16 accumulator D:
+// component r is D(mma_row<T>(g, r), c), where the FP32 instruction keeps rows
+// 4 g .. 4 g + 3 in a lane and the FP64 one rows g, g + 4, g + 8, g + 12.
+template <typename T> struct MmaV4;
+template <> struct MmaV4<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct MmaV4<double> { typedef double type __attribute__((ext_vector_type(4))); };
+template <typename T> using mma4_t = typename MmaV4<T>::type;
+
+__device__ __forceinline__ mma4_t<float> mma16(float a, float b, mma4_t<float> c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mma4_t<double> mma16(double a, double b, mma4_t<double> c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ constexpr int mma_row(int g, int r) {
+  return sizeof(T) == 8 ? g + 4 * r : 4 * g + r;
+}
+template <typename T>
+__device__ __forceinline__ mma4_t<T> mma_zero() {
+  mma4_t<T> z;
+  z[0] = z[1] = z[2] = z[3] = T(0);
+  return z;
+}
+
 }  // namespace hss

@@ -347,6 +347,211 @@ __global__ __launch_bounds__(kNT) void k_ulv_merge1(KArgs<T, CallSV<T>> a) {
 }
 
 // ---------------------------------------------------------------------------
+// The merge on the matrix cores, for nodes whose children's kept sizes and
+// all ranks involved are at most 32: every operand is staged in LDS as a
+// zero-padded 32 x 32 block (buffer loads past a block's end read zero), and
+// each product is one 32 x 32 x 32 product of 16 x 16 x 4 MFMAs (2 x 2 output
+// tiles, 8 k-steps) by one wavefront.
+//   phase 1: C12 = B12 V^b_c2^T, C21 = B21 V^b_c1^T (to LDS),
+//            U' = [U~_c1 R_top; U~_c2 R_bot], V' = [V^b_c1 W_top; V^b_c2 W_bot];
+//   phase 2: D'(c1, c2) = U~_c1 C12, D'(c2, c1) = U~_c2 C21;
+// the diagonal blocks D~22 of the children are copied through registers.
+// ---------------------------------------------------------------------------
+constexpr int kMP = 33;          // LDS pitch of a staged 32 x 32 operand
+constexpr int kMBlk = 32 * kMP;  // elements of one staged operand
+
+// acc = A B for staged 32 x 32 operands; TA: A(i, k) = A[k + i kMP] (A stored
+// transposed), TB: B(k, j) = B[j + k kMP].
+template <typename T, bool TA, bool TB>
+__device__ __forceinline__ void mma_gemm32(const T* A, const T* B, mma4_t<T> (&acc)[2][2], int g,
+                                           int c) {
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) acc[it][jt] = mma_zero<T>();
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    const int k = 4 * kk + g;
+    T a[2], b[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int i = 16 * it + c;
+      a[it] = TA ? A[k + i * kMP] : A[i + k * kMP];
+    }
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) {
+      const int j = 16 * jt + c;
+      b[jt] = TB ? B[j + k * kMP] : B[k + j * kMP];
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) acc[it][jt] = mma16(a[it], b[jt], acc[it][jt]);
+  }
+}
+
+// Entries (i, j), i < M, j < N, of a 32 x 32 product to dst[i + j ld] (global,
+// through a buffer descriptor of `bytes` bytes) or, LDS, to dst[i + j kMP].
+template <typename T>
+__device__ __forceinline__ void mma_store_global(const mma4_t<T> (&acc)[2][2], T* dst, int ld,
+                                                 int M, int N, uint32_t bytes, int g, int c) {
+  const auto R = buf_rsrc(dst, bytes);
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + mma_row<T>(g, r), j = 16 * jt + c;
+        const bool in = (i < M) & (j < N);
+        buf_store<T>(acc[it][jt][r], R, in ? (uint32_t)(i + j * ld) * (uint32_t)sizeof(T) : kBufOOB,
+                     0);
+      }
+}
+template <typename T>
+__device__ __forceinline__ void mma_store_lds(const mma4_t<T> (&acc)[2][2], T* dst, int g, int c) {
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        dst[16 * it + mma_row<T>(g, r) + (16 * jt + c) * kMP] = acc[it][jt][r];
+}
+
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_ulv_merge_mma(KArgs<T, CallSV<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  Inst<T> I; CallSV<T> C; int node;
+  resolve<BATCH>(a, I, C, node);
+  const NodeInfo nd = I.nodes[node];
+  const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+  const int k1 = n1.kept, k2 = n2.kept, mp = nd.mp;
+  const int ku1 = n1.ku, ku2 = n2.ku, kv1 = n1.kv, kv2 = n2.kv;
+  const int kr = ku1 + ku2, kw = kv1 + kv2;
+  const bool top = node != 0;   // U', V' below the root
+  const int ku = top ? nd.ku : 0, kv = top ? nd.kv : 0;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, c = lane & 15;
+  constexpr uint32_t sz = sizeof(T);
+  // staged operands: 0 B12, 1 B21, 2 V^b_c1, 3 V^b_c2, 4 U~_c1, 5 U~_c2,
+  // 6 R_top, 7 R_bot, 8 W_top, 9 W_bot; then C12 (10), C21 (11)
+  {
+    struct Src {
+      const T* p;
+      uint32_t bytes;
+      int off, ld, M, N;
+      bool tri;   // U~ with rows eliminated: zeros above the diagonal
+    };
+    const T* R = I.R + (top ? nd.oR : 0);
+    const T* W = I.W + (top ? nd.oW : 0);
+    const Src src[10] = {
+        {I.B12 + nd.oB12, (uint32_t)(ku1 * kv2) * sz, 0, ku1, ku1, kv2, false},
+        {I.B21 + nd.oB21, (uint32_t)(ku2 * kv1) * sz, 0, ku2, ku2, kv1, false},
+        {I.FV + n1.oFV, (uint32_t)(n1.mp * kv1) * sz, n1.e, n1.mp, k1, kv1, false},
+        {I.FV + n2.oFV, (uint32_t)(n2.mp * kv2) * sz, n2.e, n2.mp, k2, kv2, false},
+        {I.FU + n1.oFU, (uint32_t)(n1.mp * ku1) * sz, n1.e, n1.mp, k1, ku1, n1.e > 0},
+        {I.FU + n2.oFU, (uint32_t)(n2.mp * ku2) * sz, n2.e, n2.mp, k2, ku2, n2.e > 0},
+        {R, (uint32_t)(kr * ku) * sz, 0, kr, ku1, ku, false},
+        {R, (uint32_t)(kr * ku) * sz, ku1, kr, ku2, ku, false},
+        {W, (uint32_t)(kw * kv) * sz, 0, kw, kv1, kv, false},
+        {W, (uint32_t)(kw * kv) * sz, kv1, kw, kv2, kv, false}};
+    // D~22 of the children (copied to the parent's diagonal blocks)
+    const T* FD1 = I.FD + n1.oFD;
+    const T* FD2 = I.FD + n2.oFD;
+    const auto RD1 = buf_rsrc(FD1, (uint32_t)(n1.mp * n1.mp) * sz);
+    const auto RD2 = buf_rsrc(FD2, (uint32_t)(n2.mp * n2.mp) * sz);
+    T v[10][4], d1[4], d2[4];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const auto Rq = buf_rsrc(src[q].p, src[q].bytes);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int o = tid + u * kNT, i = o & 31, j = o >> 5;
+        const bool in = (i < src[q].M) & (j < src[q].N) & !(src[q].tri & (i < j));
+        v[q][u] = buf_load<T>(Rq, in ? (uint32_t)(src[q].off + i + j * src[q].ld) * sz : kBufOOB, 0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int o = tid + u * kNT, i = o & 31, j = o >> 5;
+      d1[u] = buf_load<T>(RD1, (i < k1) & (j < k1) ? (uint32_t)(n1.e + i + (n1.e + j) * n1.mp) * sz
+                                                   : kBufOOB, 0);
+      d2[u] = buf_load<T>(RD2, (i < k2) & (j < k2) ? (uint32_t)(n2.e + i + (n2.e + j) * n2.mp) * sz
+                                                   : kBufOOB, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int o = tid + u * kNT, i = o & 31, j = o >> 5;
+        sm[q * kMBlk + i + j * kMP] = v[q][u];
+      }
+    const auto RD = buf_rsrc(I.FD + nd.oFD, (uint32_t)(mp * mp) * sz);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int o = tid + u * kNT, i = o & 31, j = o >> 5;
+      buf_store<T>(d1[u], RD, (i < k1) & (j < k1) ? (uint32_t)(i + j * mp) * sz : kBufOOB, 0);
+      buf_store<T>(d2[u], RD, (i < k2) & (j < k2) ? (uint32_t)(k1 + i + (k1 + j) * mp) * sz
+                                                 : kBufOOB, 0);
+    }
+  }
+  __syncthreads();
+  const T* sB12 = sm;
+  const T* sB21 = sm + kMBlk;
+  const T* sV1 = sm + 2 * kMBlk;
+  const T* sV2 = sm + 3 * kMBlk;
+  const T* sU1 = sm + 4 * kMBlk;
+  const T* sU2 = sm + 5 * kMBlk;
+  const T* sRt = sm + 6 * kMBlk;
+  const T* sRb = sm + 7 * kMBlk;
+  const T* sWt = sm + 8 * kMBlk;
+  const T* sWb = sm + 9 * kMBlk;
+  T* sC12 = sm + 10 * kMBlk;
+  T* sC21 = sm + 11 * kMBlk;
+  T* FU = I.FU + nd.oFU;
+  T* FV = I.FV + nd.oFV;
+  T* FD = I.FD + nd.oFD;
+  mma4_t<T> acc[2][2];
+  if (w == 0) {
+    mma_gemm32<T, false, true>(sB12, sV2, acc, g, c);   // C12 = B12 V^b_c2^T
+    mma_store_lds<T>(acc, sC12, g, c);
+    if (kv > 0) {
+      mma_gemm32<T, false, false>(sV1, sWt, acc, g, c);   // V'_top
+      mma_store_global<T>(acc, FV, mp, k1, kv, (uint32_t)(mp * kv) * sz, g, c);
+    }
+  } else if (w == 1) {
+    mma_gemm32<T, false, true>(sB21, sV1, acc, g, c);   // C21 = B21 V^b_c1^T
+    mma_store_lds<T>(acc, sC21, g, c);
+    if (kv > 0) {
+      mma_gemm32<T, false, false>(sV2, sWb, acc, g, c);   // V'_bot
+      mma_store_global<T>(acc, FV + k1, mp, k2, kv, (uint32_t)(mp * kv - k1) * sz, g, c);
+    }
+  } else if (w == 2) {
+    if (ku > 0) {
+      mma_gemm32<T, false, false>(sU1, sRt, acc, g, c);   // U'_top
+      mma_store_global<T>(acc, FU, mp, k1, ku, (uint32_t)(mp * ku) * sz, g, c);
+    }
+  } else {
+    if (ku > 0) {
+      mma_gemm32<T, false, false>(sU2, sRb, acc, g, c);   // U'_bot
+      mma_store_global<T>(acc, FU + k1, mp, k2, ku, (uint32_t)(mp * ku - k1) * sz, g, c);
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    mma_gemm32<T, false, false>(sU1, sC12, acc, g, c);   // D'(c1, c2) = U~_c1 C12
+    mma_store_global<T>(acc, FD + (int64_t)k1 * mp, mp, k1, k2, (uint32_t)(mp * (mp - k1)) * sz,
+                        g, c);
+  } else if (w == 1) {
+    mma_gemm32<T, false, false>(sU2, sC21, acc, g, c);   // D'(c2, c1) = U~_c2 C21
+    mma_store_global<T>(acc, FD + k1, mp, k2, k1, (uint32_t)(mp * mp - k1) * sz, g, c);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Root: LU with partial pivoting (FP64) of D'_root (or of D when p = 0).
 // ---------------------------------------------------------------------------
 template <typename T, bool BATCH>
@@ -518,7 +723,10 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max
   else hipLaunchKernelGGL((K<T, false>), grid, block, sm, s, a);
   switch (step) {
     case UlvStep::Merge:
-      if (max_mp <= 64 && max_k <= 32) { HSS_LAUNCH(k_ulv_merge1); }
+      if (max_mp <= 64 && max_k <= 32) {
+        sm = (size_t)12 * kMBlk * TB;
+        HSS_LAUNCH(k_ulv_merge_mma);
+      }
       else { HSS_LAUNCH(k_ulv_merge); }
       break;
     case UlvStep::Factor:
