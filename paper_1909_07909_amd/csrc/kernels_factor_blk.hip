@@ -16,7 +16,8 @@
 //
 // Work-group: four wavefronts, each holding a 128 x 32 slab of the working
 // matrix as 16 accumulator tiles of the 16x16x4 MFMA: tile (rt, ct), lane
-// l = 16 g + c, component r holds element (16 rt + 4 g + r, 16 ct + c).
+// l = 16 g + c, component r holds element (16 rt + rho(g, r), 16 ct + c) with
+// rho = 4 g + r for the FP32 instruction and g + 4 r for the FP64 one.
 //   QL phase: wavefront w holds columns 32 w .. 32 w + 31 of D', its rows
 //   shifted down by 128 - mp, so that the pivot rows of U' are always the
 //   last ku <= 32 rows (tiles 6 and 7).
@@ -53,6 +54,29 @@ __device__ __forceinline__ v4<float> mfma4(float a, float b, v4<float> c) {
 }
 __device__ __forceinline__ v4<double> mfma4(double a, double b, v4<double> c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// The four rows 16 t + rho(g, 0 .. 3) of a position-indexed LDS vector (base
+// at position 16 t): contiguous for FP32, a stride of four for FP64.
+template <typename T>
+__device__ __forceinline__ v4<T> lds_rows4(const T* base, int g) {
+  if constexpr (sizeof(T) == 4) {
+    return *reinterpret_cast<const v4<T>*>(base + 4 * g);
+  } else {
+    v4<T> v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = base[g + 4 * r];
+    return v;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void lds_put_rows4(T* base, int g, v4<T> v) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<v4<T>*>(base + 4 * g) = v;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) base[g + 4 * r] = v[r];
+  }
 }
 
 template <typename T>
@@ -112,17 +136,18 @@ __device__ __forceinline__ void slab_load_cols(v4<T> (&X)[8][2], const T* A, int
     const int col = c0 + 16 * ct + c;
     const bool cok = col < cols;
     if (s == 0) {
-      const uint32_t vo = cok ? (uint32_t)(4 * g + col * ld) * sz : kBufOOB;
+      const uint32_t vo = cok ? (uint32_t)(mma_row<T>(g, 0) + col * ld) * sz : kBufOOB;
 #pragma unroll
       for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) X[rt][ct][r] = buf_load<T>(R, vo + (16 * rt + r) * sz, 0);
+        for (int r = 0; r < 4; ++r)
+          X[rt][ct][r] = buf_load<T>(R, vo + (16 * rt + mma_row<T>(0, r)) * sz, 0);
     } else {
 #pragma unroll
       for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = 16 * rt + 4 * g + r - s;
+          const int row = 16 * rt + mma_row<T>(g, r) - s;
           const uint32_t o = cok & (row >= 0) ? (uint32_t)(row + col * ld) * sz : kBufOOB;
           X[rt][ct][r] = buf_load<T>(R, o, 0);
         }
@@ -140,10 +165,10 @@ __device__ __forceinline__ void slab_load_rows(v4<T> (&X)[8][2], const T* A, int
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     const int row = r0 + 16 * ct + c;
-    const uint32_t vo = row < rows ? (uint32_t)(row + 4 * g * ld) * sz : kBufOOB;
+    const uint32_t vo = row < rows ? (uint32_t)(row + mma_row<T>(g, 0) * ld) * sz : kBufOOB;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const uint32_t vr = vo + (uint32_t)(r * ld) * sz;
+      const uint32_t vr = vo + (uint32_t)(mma_row<T>(0, r) * ld) * sz;
 #pragma unroll
       for (int rt = 0; rt < 8; ++rt)
         X[rt][ct][r] = buf_load<T>(R, vr, (uint32_t)(16 * rt * ld) * sz);
@@ -165,17 +190,18 @@ __device__ __forceinline__ void slab_store_cols(const v4<T> (&X)[8][2], T* A, in
     const int col = c0 + 16 * ct + c;
     const bool cok = col < cols;
     if (full) {
-      const uint32_t vo = cok ? (uint32_t)(4 * g + col * ld) * sz : kBufOOB;
+      const uint32_t vo = cok ? (uint32_t)(mma_row<T>(g, 0) + col * ld) * sz : kBufOOB;
 #pragma unroll
       for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) buf_store<T>(X[rt][ct][r], R, vo + (16 * rt + r) * sz, 0);
+        for (int r = 0; r < 4; ++r)
+          buf_store<T>(X[rt][ct][r], R, vo + (16 * rt + mma_row<T>(0, r)) * sz, 0);
     } else {
 #pragma unroll
       for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = 16 * rt + 4 * g + r - s;
+          const int row = 16 * rt + mma_row<T>(g, r) - s;
           const bool in = cok & (row >= 0) & (row < rows);
           buf_store<T>(X[rt][ct][r], R, in ? (uint32_t)(row + col * ld) * sz : kBufOOB, 0);
         }
@@ -414,7 +440,7 @@ __device__ __forceinline__ void make_t(const T* Yt, T* Ts, const T* taus, int w,
       for (int r = 0; r < 4; ++r) acc = mfma4(va[r], vb[r], acc);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Ts[(16 * it + 4 * g + r) * kLT + 16 * jt + c] = acc[r];
+    for (int r = 0; r < 4; ++r) Ts[(16 * it + mma_row<T>(g, r)) * kLT + 16 * jt + c] = acc[r];
   }
   __syncthreads();
   if (gw == 1) {
@@ -452,8 +478,8 @@ __device__ __forceinline__ void block_update(v4<T> (&X)[8][2], const T* Yt, cons
     for (int b = 0; b < 2; ++b) P[a][b] = v4zero<T>();
 #pragma unroll
   for (int rt = RLO; rt < 8; ++rt) {
-    const v4<T> y0 = *reinterpret_cast<const v4<T>*>(Yt + c * kLY + 16 * rt + 4 * g);
-    const v4<T> y1 = *reinterpret_cast<const v4<T>*>(Yt + (16 + c) * kLY + 16 * rt + 4 * g);
+    const v4<T> y0 = lds_rows4(Yt + c * kLY + 16 * rt, g);
+    const v4<T> y1 = lds_rows4(Yt + (16 + c) * kLY + 16 * rt, g);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
 #pragma unroll
@@ -470,8 +496,8 @@ __device__ __forceinline__ void block_update(v4<T> (&X)[8][2], const T* Yt, cons
     for (int b = 0; b < 2; ++b) Q[a][b] = v4zero<T>();
 #pragma unroll
   for (int pt = 0; pt < 2; ++pt) {
-    const v4<T> t0 = *reinterpret_cast<const v4<T>*>(Ts + c * kLT + 16 * pt + 4 * g);
-    const v4<T> t1 = *reinterpret_cast<const v4<T>*>(Ts + (16 + c) * kLT + 16 * pt + 4 * g);
+    const v4<T> t0 = lds_rows4(Ts + c * kLT + 16 * pt, g);
+    const v4<T> t1 = lds_rows4(Ts + (16 + c) * kLT + 16 * pt, g);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
 #pragma unroll
@@ -485,7 +511,7 @@ __device__ __forceinline__ void block_update(v4<T> (&X)[8][2], const T* Yt, cons
   for (int qt = 0; qt < 2; ++qt) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const T* yk = Yt + (16 * qt + 4 * g + r) * kLY + c;
+      const T* yk = Yt + (16 * qt + mma_row<T>(g, r)) * kLY + c;
 #pragma unroll
       for (int rt = RLO; rt < 8; ++rt) {
         const T a = -yk[16 * rt];
@@ -506,10 +532,11 @@ __device__ __forceinline__ void store_rows(const v4<T> (&X)[8][2], T* FD, int mp
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     const int row = 32 * q + 16 * ct + c;
-    const uint32_t vo = (row >= lo) & (row < hi) ? (uint32_t)(row + 4 * g * mp) * sz : kBufOOB;
+    const uint32_t vo =
+        (row >= lo) & (row < hi) ? (uint32_t)(row + mma_row<T>(g, 0) * mp) * sz : kBufOOB;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const uint32_t vr = vo + (uint32_t)(r * mp) * sz;
+      const uint32_t vr = vo + (uint32_t)(mma_row<T>(0, r) * mp) * sz;
 #pragma unroll
       for (int rt = 0; rt < 8; ++rt)
         buf_store<T>(X[rt][ct][r], R, vr, (uint32_t)(16 * rt * mp) * sz);
@@ -558,8 +585,10 @@ __device__ __forceinline__ void store_lq_panel(const Panel<T>& Pn, const PanelLd
   }
 }
 
+// FP32: four waves per SIMD (128 registers); FP64: two (its accumulator
+// tiles and panel registers take twice the space).
 template <typename T, bool BATCH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ulv_factor_blk(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_ulv_factor_blk(
     KArgs<T, CallSV<T>> a) {
   __shared__ __attribute__((aligned(16))) T Yt[kBW * kLY];
   __shared__ __attribute__((aligned(16))) T Ts[kBW * kLT];
@@ -645,7 +674,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (w == P) {                                                                           \
       _Pragma("unroll") for (int ct = 0; ct < 2; ++ct)                                      \
         _Pragma("unroll") for (int rt = 0; rt < 8; ++rt)                                    \
-          *reinterpret_cast<v4<T>*>(Yt + (16 * ct + c) * kLY + 16 * rt + 4 * g) = X[rt][ct]; \
+          lds_put_rows4(Yt + (16 * ct + c) * kLY + 16 * rt, g, X[rt][ct]);                 \
     }                                                                                       \
     __syncthreads();                                                                        \
     panel_load_lds(Pn, Yt, w, g, c);                                                        \
@@ -680,7 +709,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 
 template <typename T>
 bool factor_blk_fits(int max_mp, int max_k) {
-  return sizeof(T) == 4 && max_mp > 64 && max_mp <= kBP && max_k <= kBW;
+  return max_mp > 64 && max_mp <= kBP && max_k <= kBW;
 }
 
 template <typename T>
