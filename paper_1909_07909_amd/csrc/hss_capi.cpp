@@ -24,6 +24,7 @@ namespace {
 template <typename T>
 struct FactorSet {
   T *FD = nullptr, *FU = nullptr, *FV = nullptr, *tq = nullptr, *tz = nullptr, *FZ = nullptr;
+  T* FOP = nullptr;
   double* rootLU = nullptr;
   int32_t* piv = nullptr;
   bool valid = false;
@@ -139,9 +140,10 @@ hss_status ensure_factors(hss_handle* h) {
   F.tq = dalloc<T>(h, P.ntq);
   F.tz = dalloc<T>(h, P.ntz);
   F.FZ = dalloc<T>(h, P.nFZ);
+  F.FOP = dalloc<T>(h, sizeof(T) == 4 ? P.nOP : 0);
   F.rootLU = dalloc<double>(h, (int64_t)P.nodes[0].mp * P.nodes[0].mp);
   F.piv = dalloc<int32_t>(h, P.nodes[0].mp);
-  if (!F.FD || !F.FU || !F.FV || !F.tq || !F.tz || !F.FZ || !F.rootLU || !F.piv)
+  if (!F.FD || !F.FU || !F.FV || !F.tq || !F.tz || !F.FZ || !F.FOP || !F.rootLU || !F.piv)
     return HSS_ENOMEM;
   return HSS_OK;
 }
@@ -202,6 +204,7 @@ Inst<T> make_inst(hss_handle* h) {
   I.W = gen<T>(h, 4); I.B12 = gen<T>(h, 5); I.B21 = gen<T>(h, 6);
   FactorSet<T>& F = factors<T>(h);
   I.FD = F.FD; I.FU = F.FU; I.FV = F.FV; I.tq = F.tq; I.tz = F.tz; I.FZ = F.FZ;
+  I.FOP = F.FOP;
   I.rootLU = F.rootLU; I.piv = F.piv;
   Work<T>& w = work<T>(h);
   I.xh = w.xh; I.yh = w.yh; I.ldm = h->plan.ldm;
@@ -215,6 +218,14 @@ Inst<T> make_inst(hss_handle* h) {
 }
 
 inline int level_first(int l) { return (1 << l) - 1; }
+
+// Forward-operator records (FOP) are built by the FP32 factorization, whose
+// solves run at least twice per refined solve; an FP64 factorization is
+// usually solved once, and its solves keep the sequential forward steps.
+template <typename T>
+bool use_fwd_op(const Plan& P) {
+  return sizeof(T) == 4 && P.nOP > 0;
+}
 
 // ---------------------------------------------------------------------------
 // Single-instance schedules
@@ -332,6 +343,7 @@ void run_factor(hss_handle* h, hipStream_t s) {
     a.node0 = level_first(l);
     launch_ulv<T>(UlvStep::Merge, a, 1 << l, P.max_k, P.level_max_mp[l], s);
     launch_ulv<T>(UlvStep::Factor, a, 1 << l, P.max_k, P.level_max_mp[l], s);
+    if (use_fwd_op<T>(P)) launch_ulv<T>(UlvStep::FwdOp, a, 1 << l, P.max_k, P.level_max_mp[l], s);
   }
   a.node0 = 0;
   launch_ulv<T>(UlvStep::Merge, a, 1, P.max_k, P.nodes[0].mp, s);
@@ -377,7 +389,9 @@ void run_solve(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, hipStream_t s,
   launch_solve_w<T>(UlvStep::Fwd, a, 1 << p, nc, 0, s);
   for (int l = p - 1; l >= 1; --l) {
     a.node0 = level_first(l);
-    launch_solve_w<T>(UlvStep::Fwd, a, 1 << l, nc, fwd_stage(l), s);
+    if (use_fwd_op<T>(P) && P.level_fwd_op[l])
+      launch_solve_w<T>(UlvStep::FwdOp, a, 1 << l, nc, 0, s);
+    else launch_solve_w<T>(UlvStep::Fwd, a, 1 << l, nc, fwd_stage(l), s);
   }
   a.node0 = 0;
   launch_solve_w<T>(UlvStep::Root, a, 1, nc, root_elems, s);
@@ -506,11 +520,12 @@ struct StepList {
     int cnt;
     int max_mp;
     int64_t stage;   // max staging elements over the tasks
+    bool all_op;     // every task's node has a forward operator
   };
   std::vector<Range> ranges;
   template <typename Pred, typename Stage>
   void add_step(hss_handle* const* hs, int count, Pred pred, Stage stage) {
-    Range r{tasks.size(), 0, 0, 0};
+    Range r{tasks.size(), 0, 0, 0, true};
     for (int j = 0; j < count; ++j) {
       const Plan& P = hs[j]->plan;
       for (int t = 0; t < P.nnodes; ++t)
@@ -518,6 +533,7 @@ struct StepList {
           tasks.push_back(make_int2(j, t));
           r.max_mp = std::max(r.max_mp, P.nodes[t].mp);
           r.stage = std::max<int64_t>(r.stage, stage(P, t));
+          r.all_op = r.all_op && P.nodes[t].oOP >= 0;
           ++r.cnt;
         }
     }
@@ -679,10 +695,13 @@ hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
     const auto& r = rng();
     launch_ulv<T>(UlvStep::Factor, a, r.cnt, mk, r.max_mp, s);
   }
+  bool any_op = false;
+  for (int j = 0; j < count; ++j) any_op |= use_fwd_op<T>(hs[j]->plan);
   for (int q = 1; q <= pmax - 1; ++q) {
     const auto& r = rng();
     launch_ulv<T>(UlvStep::Merge, a, r.cnt, mk, r.max_mp, s);
     launch_ulv<T>(UlvStep::Factor, a, r.cnt, mk, r.max_mp, s);
+    if (any_op) launch_ulv<T>(UlvStep::FwdOp, a, r.cnt, mk, r.max_mp, s);
   }
   {
     const auto& r = rng();
@@ -758,7 +777,10 @@ hss_status batch_sweep(BatchScratch& BS, hss_handle* const* hs, int count, const
     launch_solve_w<T>(stp, a, r.cnt, nc, use_stage ? staged(r.stage) : 0, s);
   };
   go(UlvStep::Fwd, false);
-  for (int q = 1; q <= pmax - 1; ++q) go(UlvStep::Fwd, true);
+  for (int q = 1; q <= pmax - 1; ++q) {
+    const bool op = L.ranges[k].all_op && sizeof(T) == 4;
+    go(op ? UlvStep::FwdOp : UlvStep::Fwd, !op);
+  }
   {
     const auto& r = L.ranges[k++];
     a.tasks = reinterpret_cast<const int2*>((char*)d + ot) + r.off;

@@ -16,6 +16,9 @@
 //           (zeros above row i, 1 at row i) for the backward sweep;
 //       tq, tz  the Householder scalars; the root block is LU-factored in
 //           FP64 (rootLU, piv);
+//       FOP (internal nodes with a forward operator, fwd_op_ok) the forward
+//           step of the solve as products, one record of kRecSize elements
+//           per node laid out as the solve stages it in LDS (see kRec*);
 //   * work vectors for the product (x^ up values, y^ down values) and the
 //     solve (c, z, y, x^), node blocks stacked with one leading dimension.
 #pragma once
@@ -45,6 +48,8 @@ struct NodeInfo {
   int64_t oxh, oyh;
   // factor offsets (elements)
   int64_t oFD, oFU, oFV, otq, otz, oFZ;
+  // forward-operator record offset (elements), -1 where the node has none
+  int64_t oOP;
   // solve work offsets (rows): c and x^ have kept rows, z has kv rows, y e rows
   int64_t oc, oz, oy, ox;
 };
@@ -76,6 +81,7 @@ struct Inst {
   const NodeInfo* nodes;
   const T *D, *U, *V, *R, *W, *B12, *B21;
   T *FD, *FU, *FV, *tq, *tz, *FZ;
+  T* FOP;           // forward-operator records (internal nodes that have them)
   double* rootLU;
   int32_t* piv;
   T *xh, *yh;       // product work, leading dimension ldm
@@ -88,6 +94,35 @@ struct Inst {
   int32_t p;
   int32_t nnodes;
 };
+
+// Whether an internal node's forward step is precomputed as products (FY,
+// FF): every operand fits a 32 x 32 block of the matrix-core kernels (the
+// node's ranks and eliminated count, and its children's ranks, at most 32;
+// child_k is the largest of ku_c1, kv_c1, ku_c2, kv_c2).
+__host__ __device__ inline bool fwd_op_ok(int is_leaf, int node, int mp, int e, int ku, int kv,
+                                          int child_k) {
+  return !is_leaf && node != 0 && e > 0 && e <= 32 && mp <= 64 && ku <= 32 && kv <= 32 &&
+         child_k <= 32;
+}
+
+// Forward-operator record of an internal node (elements; every block at a
+// 16-byte boundary, unused rows and columns zero):
+//   G  = [[0, U~_c1 B12], [U~_c2 B21, 0]]  mp x (kv_c1 + kv_c2), pitch 64:
+//        rhs = [c_c1; c_c2] - G [z_c1; z_c2];
+//   W  = W_t                               (kv_c1 + kv_c2) x kv, pitch 65;
+//   Y  = the QL reflectors with their unit pivots, mp x ku, pitch 65, and
+//   YT = Y T (compact WY: Q^T = I - Y T Y^T), mp x ku, pitch 64:
+//        b~ = rhs - YT (Y^T rhs);
+//   F  = [L^-1; D~21 L^-1; V^_top^T L^-1]  (e + kept + kv) x e, pitch 96:
+//        [y; d; v] = F b~(0:e), c = b~(e:) - d, z = v + W^T [z_c1; z_c2].
+constexpr int kRecG = 0;
+constexpr int kRecW = kRecG + 64 * 64;
+constexpr int kRecY = kRecW + 65 * 32;
+constexpr int kRecYT = kRecY + 65 * 32;
+constexpr int kRecF = kRecYT + 64 * 32;
+constexpr int kRecSize = kRecF + 96 * 32;
+static_assert(kRecW % 4 == 0 && kRecY % 4 == 0 && kRecYT % 4 == 0 && kRecF % 4 == 0 &&
+                  kRecSize % 4 == 0, "record blocks at 16-byte boundaries");
 
 // gate: NULL, or a device flag read when a work-group starts; 0 makes the
 // call's work-groups return at once (refinement steps enqueued after the

@@ -37,7 +37,7 @@ bool mmw_fits(int max_leaf, int max_k);
 template <typename T>
 void launch_mmw(MMWStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrhs,
                 hipStream_t s);
-enum class UlvStep { Merge, Factor, RootLU, Fwd, Root, Bwd };
+enum class UlvStep { Merge, Factor, RootLU, Fwd, Root, Bwd, FwdOp };
 
 // Step 1 (QL / LQ) on one level of blocks, register-resident (kernels_factor.hip).
 template <typename T>

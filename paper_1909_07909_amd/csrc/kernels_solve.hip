@@ -670,6 +670,163 @@ __global__ __launch_bounds__((STAGED && !BATCH ? kSWS : kSW) * 64) void k_sv_fwd
   }
 }
 
+// Forward step of an internal node from its forward-operator record (layout
+// kRec* in hss_internal.hpp):
+//   rhs = [c_c1; c_c2] - G [z_c1; z_c2];  zw = W^T [z_c1; z_c2];
+//   w = Y^T rhs;  b~ = rhs - YT w;
+//   [y; d; v] = F b~(0:e);  c = b~(e:) - d;  z = v + zw.
+// One node per work-group: the record is copied to LDS with 16-byte loads
+// (all issued before any is stored); then wavefront w carries columns
+// col0 = CPW (4 blockIdx.y + w) ...; lane r holds entry r of every length-64
+// vector and each product is a dot product over LDS with fixed trip counts
+// (unused rows and columns of the record are zero).
+constexpr int kOpW = 4;                        // wavefronts per work-group
+constexpr int kOpScrW = 4 * 64;                // per wavefront and column: x, z, w, b
+
+int fwd_op_lds_elems(int cpw) { return kRecSize + kOpW * kOpScrW * cpw; }
+
+template <typename T, bool BATCH, int CPW>
+__global__ __launch_bounds__(kOpW * 64) void k_sv_fwd_op(KArgs<T, CallSV<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  Inst<T> I; CallSV<T> C; int node, col0;
+  if (!sv_resolve<BATCH, true, CPW>(a, I, C, node, col0)) return;   // uniform
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  NodeInfo nd, n1, n2;
+  node_and_children(I.nodes, I.nnodes, node, nd, n1, n2);
+  const int mp = nd.mp, e = nd.e, kv = nd.kv, kept = nd.kept;
+  const int kw = n1.kv + n2.kv, kv1 = n1.kv;
+  const int ldf = e + kept + kv;
+  Gathered<T, CPW> G;
+  gather_load<T, CPW>(I, nd, n1, n2, col0, C.nrhs, lane, G);   // before the copy
+  {
+    // the record: kRecSize elements = kRecSize * sizeof(T) / 16 chunks
+    constexpr int nch = kRecSize * (int)sizeof(T) / 16;
+    constexpr int per = (nch + kOpW * 64 - 1) / (kOpW * 64);
+    const int4* src = reinterpret_cast<const int4*>(I.FOP + nd.oOP);
+    int4* dst = reinterpret_cast<int4*>(sm);
+    int4 v[per];
+#pragma unroll
+    for (int u = 0; u < per; ++u) v[u] = src[min((int)threadIdx.x + u * kOpW * 64, nch - 1)];
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+      const int q = (int)threadIdx.x + u * kOpW * 64;
+      if (q < nch) dst[q] = v[u];
+    }
+  }
+  __syncthreads();
+  if (col0 >= C.nrhs) return;
+  const T* sG = sm + kRecG;
+  const T* sW = sm + kRecW;
+  const T* sY = sm + kRecY;
+  const T* sYT = sm + kRecYT;
+  const T* sF = sm + kRecF;
+  T* scr = sm + kRecSize + w * kOpScrW * CPW;
+  T* zs = scr;                 // 64 per column: [z_c1; z_c2]
+  T* xs = scr + 64 * CPW;      // 64 per column: rhs
+  T* ws = xs + 64 * CPW;       // 32 per column: Y^T rhs
+  T* bs = ws + 32 * CPW;       // 64 per column: b~
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    // entry lane of [z_c1; z_c2]: z_c1 in lanes < kv1, then z_c2
+    const T z2s = __shfl(G.z2[c], min(max(lane - kv1, 0), 63), 64);
+    zs[lane + 64 * c] = lane < kv1 ? G.z1[c] : (lane < kw ? z2s : T(0));
+  }
+  wave_lds_sync();
+  // rhs = c - G zc (lane r); zw = W^T zc (lane a)
+  T x[CPW], zw[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    x[c] = G.x0[c];
+    zw[c] = T(0);
+  }
+  {
+    const int aw = min(lane, 31);
+#pragma unroll 16
+    for (int q = 0; q < 64; ++q) {
+      const T gq = sG[lane + q * 64];
+      const T wq = sW[q + aw * 65];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const T zq = zs[q + 64 * c];
+        x[c] -= gq * zq;
+        zw[c] += wq * zq;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) xs[lane + 64 * c] = lane < mp ? x[c] : T(0);
+  wave_lds_sync();
+  // w = Y^T rhs (lane i < 32)
+  {
+    const int i = min(lane, 31);
+    T wv[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) wv[c] = T(0);
+#pragma unroll 16
+    for (int r = 0; r < 64; ++r) {
+      const T y = sY[r + i * 65];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) wv[c] += y * xs[r + 64 * c];
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+      if (lane < 32) ws[lane + 32 * c] = wv[c];
+  }
+  wave_lds_sync();
+  // b~ = rhs - (Y T) w (lane r)
+#pragma unroll 16
+  for (int i = 0; i < 32; ++i) {
+    const T yt = sYT[lane + i * 64];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) x[c] -= yt * ws[i + 32 * c];
+  }
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) bs[lane + 64 * c] = lane < mp ? x[c] : T(0);
+  wave_lds_sync();
+  // [y; d; v] = F b~(0:e): outputs o = lane and o = lane + 64 (ldf <= 96)
+  T o0[CPW], o1[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) { o0[c] = T(0); o1[c] = T(0); }
+  {
+    const int ob = min(lane + 64, 95);
+#pragma unroll 16
+    for (int i = 0; i < 32; ++i) {
+      const T fa = sF[lane + i * 96], fb = sF[ob + i * 96];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const T bi = bs[i + 64 * c];
+        o0[c] += fa * bi;
+        o1[c] += fb * bi;
+      }
+    }
+  }
+  // outputs: o < e -> y; e <= o < e + kept -> c = b~[o] - d; else z = v + zw
+  // (z entry a is output row e + kept + a; its W^T zc part is zw of lane a,
+  // fetched by every lane before the stores)
+  const int64_t lds = I.lds;
+  const int ea = e + kept;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const T zwa0 = __shfl(zw[c], min(max(lane - ea, 0), 63), 64);
+    const T zwa1 = __shfl(zw[c], min(max(lane + 64 - ea, 0), 63), 64);
+    if (col0 + c >= C.nrhs) continue;
+    const int64_t co = (int64_t)(col0 + c) * lds;
+    T* yo = I.wy + nd.oy + co;
+    T* cout = I.wc + nd.oc + co;
+    T* zo = I.wz + nd.oz + co;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int o = lane + 64 * h;
+      const T val = h ? o1[c] : o0[c];
+      if (o < e) yo[o] = val;
+      else if (o < ea) cout[o - e] = bs[min(o, 63) + 64 * c] - val;
+      else if (o < ldf) zo[o - ea] = val + (h ? zwa1 : zwa0);
+    }
+  }
+}
+
 // Root: rhs from the children, then the FP64 LU of the merged root block
 // (staged in LDS with its pivots), split into the children's x^.
 template <typename T, bool BATCH, int CPW>
@@ -887,7 +1044,9 @@ void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int 
                                "sv_root_f64"};
   static const char* nm32[] = {"sv_fwd_f32", "sv_fwd_leaf_f32", "sv_bwd_f32", "sv_bwd_leaf_f32",
                                "sv_root_f32"};
-  const int ni = step == UlvStep::Root ? 4 : (step == UlvStep::Fwd ? 0 : 2) + (leafy ? 1 : 0);
+  const int ni = step == UlvStep::Root
+                     ? 4
+                     : (step == UlvStep::Fwd || step == UlvStep::FwdOp ? 0 : 2) + (leafy ? 1 : 0);
   TimedLaunch tl((sizeof(T) == 8 ? nm64 : nm32)[ni], s);
   // columns per wavefront: 4 when there are enough columns to share the factor reads
   const int cpw = ncols >= 4 ? 4 : 1;
@@ -906,6 +1065,19 @@ void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int 
   if (cpw == 4) { HSS_SL(K, ST, 4, G, B) }   \
   else { HSS_SL(K, ST, 1, G, B) }
   switch (step) {
+    case UlvStep::FwdOp: {
+      const int g4 = (cgroups + kOpW - 1) / kOpW;
+      const dim3 go(nitems, g4), bo(kOpW * 64);
+      const size_t smo = (size_t)fwd_op_lds_elems(cpw) * sizeof(T);
+      if (cpw == 4) {
+        if (batch) hipLaunchKernelGGL((k_sv_fwd_op<T, true, 4>), go, bo, smo, s, b);
+        else hipLaunchKernelGGL((k_sv_fwd_op<T, false, 4>), go, bo, smo, s, b);
+      } else {
+        if (batch) hipLaunchKernelGGL((k_sv_fwd_op<T, true, 1>), go, bo, smo, s, b);
+        else hipLaunchKernelGGL((k_sv_fwd_op<T, false, 1>), go, bo, smo, s, b);
+      }
+      break;
+    }
     case UlvStep::Fwd:
       if (staged) { HSS_SL2(k_sv_fwd_w, true, grid1, block1) }
       else { HSS_SL2(k_sv_fwd_w, false, gridw, blockw) }

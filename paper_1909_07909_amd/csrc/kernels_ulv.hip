@@ -552,6 +552,219 @@ __global__ __launch_bounds__(kNT) void k_ulv_merge_mma(KArgs<T, CallSV<T>> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Forward-operator records of a factored level (nodes with fwd_op_ok; record
+// layout kRec* in hss_internal.hpp).  The forward step of the solve,
+// rhs = [c_c1 - U~_c1 B12 z_c2; c_c2 - U~_c2 B21 z_c1], b~ = Q^T rhs,
+// y = L^-1 b~_top, c = b~_bot - D~21 y, z = V^_top^T y + W^T [z_c1; z_c2],
+// becomes four products instead of ku + e sequential steps:
+//   Q^T = H_0 ... H_{ku-1} = I - Y T Y^T (compact WY: Y the QL reflectors
+//   with their unit pivots, T upper triangular with
+//   T(i, j) = tau_i (delta_ij - sum_{m > i} (Y^T Y)(i, m) T(m, j)), rows from
+//   the bottom up), so b~ = rhs - (Y T) (Y^T rhs);
+//   [y; D~21 y; V^_top^T y] = [L^-1; D~21 L^-1; V^_top^T L^-1] b~_top.
+// Y^T Y, U~ B and the products of the last phase on the matrix cores
+// (zero-padded 32 x 32 blocks in LDS), T and L^-1 by one wavefront each
+// (lane j: column j).  The record is cleared first, then written.
+// ---------------------------------------------------------------------------
+// acc (+)= A B for staged 32 x 32 operands (see mma_gemm32), without zeroing.
+template <typename T, bool TA, bool TB>
+__device__ __forceinline__ void mma_gemm32_acc(const T* A, const T* B, mma4_t<T> (&acc)[2][2],
+                                               int g, int c) {
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    const int k = 4 * kk + g;
+    T a[2], b[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int i = 16 * it + c;
+      a[it] = TA ? A[k + i * kMP] : A[i + k * kMP];
+    }
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) {
+      const int j = 16 * jt + c;
+      b[jt] = TB ? B[j + k * kMP] : B[k + j * kMP];
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) acc[it][jt] = mma16(a[it], b[jt], acc[it][jt]);
+  }
+}
+
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_ulv_fwdop(KArgs<T, CallSV<T>> a) {
+  HIP_DYNAMIC_SHARED(char, smem_raw)
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  Inst<T> I; CallSV<T> C; int node;
+  resolve<BATCH>(a, I, C, node);
+  const NodeInfo nd = I.nodes[node];
+  if (nd.oOP < 0) return;
+  const NodeInfo n1 = I.nodes[2 * node + 1], n2 = I.nodes[2 * node + 2];
+  const int mp = nd.mp, ku = nd.ku, kv = nd.kv, e = nd.e, kept = nd.kept;
+  const int k1 = n1.kept, k2 = n2.kept, ku1 = n1.ku, ku2 = n2.ku, kv1 = n1.kv, kv2 = n2.kv;
+  const int kw = kv1 + kv2;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, c = lane & 15;
+  constexpr uint32_t sz = sizeof(T);
+  // staged: 0 Y rows 0-31, 1 Y rows 32-63, 2 L^T (L(i, k) at k + i kMP, k <= i),
+  // 3 D~21, 4 V^_top, 5 U~_c1, 6 U~_c2, 7 B12, 8 B21, then G = Y^T Y (9),
+  // T (10), L^-1 (11); taus after them
+  T* sY0 = sm;
+  T* sY1 = sm + kMBlk;
+  T* sLt = sm + 2 * kMBlk;
+  T* sD = sm + 3 * kMBlk;
+  T* sV = sm + 4 * kMBlk;
+  T* sU1 = sm + 5 * kMBlk;
+  T* sU2 = sm + 6 * kMBlk;
+  T* sB12 = sm + 7 * kMBlk;
+  T* sB21 = sm + 8 * kMBlk;
+  T* sG = sm + 9 * kMBlk;
+  T* sT = sm + 10 * kMBlk;
+  T* sLi = sm + 11 * kMBlk;
+  T* staus = sm + 12 * kMBlk;
+  T* rec = I.FOP + nd.oOP;
+  {
+    const auto RU = buf_rsrc(I.FU + nd.oFU, (uint32_t)(mp * ku) * sz);
+    const auto RD = buf_rsrc(I.FD + nd.oFD, (uint32_t)(mp * mp) * sz);
+    const auto RV = buf_rsrc(I.FV + nd.oFV, (uint32_t)(mp * kv) * sz);
+    const auto RU1 = buf_rsrc(I.FU + n1.oFU, (uint32_t)(n1.mp * ku1) * sz);
+    const auto RU2 = buf_rsrc(I.FU + n2.oFU, (uint32_t)(n2.mp * ku2) * sz);
+    const auto R12 = buf_rsrc(I.B12 + nd.oB12, (uint32_t)(ku1 * kv2) * sz);
+    const auto R21 = buf_rsrc(I.B21 + nd.oB21, (uint32_t)(ku2 * kv1) * sz);
+    T v[9][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int o = tid + u * kNT, i = o & 31, j = o >> 5;
+      // Y: reflector j above its pivot row e + j (the pivot itself is a unit)
+      const int r0 = i, r1 = 32 + i;
+      v[0][u] = buf_load<T>(RU, (j < ku) & (r0 < e + j) ? (uint32_t)(r0 + j * mp) * sz : kBufOOB, 0);
+      v[1][u] = buf_load<T>(RU, (j < ku) & (r1 < e + j) & (r1 < mp) ? (uint32_t)(r1 + j * mp) * sz
+                                                                     : kBufOOB, 0);
+      // L(i, j) for j <= i < e (rows of FD above e hold L left of the diagonal)
+      v[2][u] = buf_load<T>(RD, (i < e) & (j <= i) ? (uint32_t)(i + j * mp) * sz : kBufOOB, 0);
+      v[3][u] = buf_load<T>(RD, (i < kept) & (j < e) ? (uint32_t)(e + i + j * mp) * sz : kBufOOB, 0);
+      v[4][u] = buf_load<T>(RV, (i < e) & (j < kv) ? (uint32_t)(i + j * mp) * sz : kBufOOB, 0);
+      // U~ of the children: trailing kept rows of FU, zero above the diagonal
+      // when rows were eliminated
+      v[5][u] = buf_load<T>(RU1, (i < k1) & (j < ku1) & !((n1.e > 0) & (i < j))
+                                     ? (uint32_t)(n1.e + i + j * n1.mp) * sz : kBufOOB, 0);
+      v[6][u] = buf_load<T>(RU2, (i < k2) & (j < ku2) & !((n2.e > 0) & (i < j))
+                                     ? (uint32_t)(n2.e + i + j * n2.mp) * sz : kBufOOB, 0);
+      v[7][u] = buf_load<T>(R12, (i < ku1) & (j < kv2) ? (uint32_t)(i + j * ku1) * sz : kBufOOB, 0);
+      v[8][u] = buf_load<T>(R21, (i < ku2) & (j < kv1) ? (uint32_t)(i + j * ku2) * sz : kBufOOB, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int o = tid + u * kNT, i = o & 31, j = o >> 5;
+      const bool p0 = (j < ku) & (i == e + j), p1 = (j < ku) & (32 + i == e + j);
+      sY0[i + j * kMP] = p0 ? T(1) : v[0][u];
+      sY1[i + j * kMP] = p1 ? T(1) : v[1][u];
+      sLt[j + i * kMP] = v[2][u];
+      sD[i + j * kMP] = v[3][u];
+      sV[i + j * kMP] = v[4][u];
+      sU1[i + j * kMP] = v[5][u];
+      sU2[i + j * kMP] = v[6][u];
+      sB12[i + j * kMP] = v[7][u];
+      sB21[i + j * kMP] = v[8][u];
+    }
+    if (tid < 32) staus[tid] = tid < ku ? I.tq[nd.otq + tid] : T(0);
+    // the record starts cleared (its unused rows and columns stay zero)
+    for (int o = tid; o < kRecSize; o += kNT) rec[o] = T(0);
+  }
+  __syncthreads();
+  mma4_t<T> acc[2][2];
+  constexpr uint32_t rb = (uint32_t)kRecSize * sz;
+  if (w == 0) {
+    // G = Y^T Y over both row halves
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) acc[it][jt] = mma_zero<T>();
+    mma_gemm32_acc<T, true, false>(sY0, sY0, acc, g, c);
+    mma_gemm32_acc<T, true, false>(sY1, sY1, acc, g, c);
+    mma_store_lds<T>(acc, sG, g, c);
+  } else if (w == 1) {
+    if (lane < 32) {
+      // column j = lane of L^-1 by forward substitution (rows i < j stay zero)
+      const int j = lane;
+      T x[32];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        T s = (i == j) ? T(1) : T(0);
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= sLt[k + i * kMP] * x[k];
+        const T d = sLt[i + i * kMP];
+        x[i] = (i < e) & (j < e) ? s / d : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < 32; ++i) sLi[i + j * kMP] = x[i];
+    }
+  } else if (w == 2) {
+    // rows 0 .. k1-1, columns kv1 .. of G: U~_c1 B12
+    mma_gemm32<T, false, false>(sU1, sB12, acc, g, c);
+    mma_store_global<T>(acc, rec + kRecG + (int64_t)kv1 * 64, 64, k1, kv2,
+                        rb - (uint32_t)(kRecG + kv1 * 64) * sz, g, c);
+  } else {
+    // rows k1 .. mp-1, columns 0 .. kv1-1 of G: U~_c2 B21
+    mma_gemm32<T, false, false>(sU2, sB21, acc, g, c);
+    mma_store_global<T>(acc, rec + kRecG + k1, 64, k2, kv1, rb - (uint32_t)(kRecG + k1) * sz, g,
+                        c);
+  }
+  __syncthreads();
+  if (w == 0 && lane < 32) {
+    // column j = lane of T, rows from the bottom up
+    const int j = lane;
+    T t[32];
+#pragma unroll
+    for (int i = 31; i >= 0; --i) {
+      T s = (i == j) ? T(1) : T(0);
+#pragma unroll
+      for (int m = i + 1; m < 32; ++m) s -= sG[i + m * kMP] * t[m];
+      t[i] = (i < ku) & (j < ku) ? staus[i] * s : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) sT[i + j * kMP] = t[i];
+  } else if (w == 1) {
+    // W (kw x kv) into the record, pitch 65
+    const T* W = I.W + nd.oW;
+    for (int o = lane; o < kw * kv; o += 64) {
+      const int i = o % kw, j = o / kw;
+      rec[kRecW + i + j * 65] = W[o];
+    }
+  } else if (w == 2) {
+    // Y (with its unit pivots), pitch 65
+    for (int o = lane; o < mp * ku; o += 64) {
+      const int i = o % mp, j = o / mp;
+      rec[kRecY + i + j * 65] = i < 32 ? sY0[i + j * kMP] : sY1[i - 32 + j * kMP];
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    mma_gemm32<T, false, false>(sY0, sT, acc, g, c);   // (Y T), rows 0..31
+    mma_store_global<T>(acc, rec + kRecYT, 64, min(mp, 32), ku, rb - (uint32_t)kRecYT * sz, g, c);
+  } else if (w == 1) {
+    if (mp > 32) {
+      mma_gemm32<T, false, false>(sY1, sT, acc, g, c);   // (Y T), rows 32..
+      mma_store_global<T>(acc, rec + kRecYT + 32, 64, mp - 32, ku,
+                          rb - (uint32_t)(kRecYT + 32) * sz, g, c);
+    }
+    // L^-1 into F, rows 0 .. e-1
+    for (int o = lane; o < e * e; o += 64) {
+      const int i = o % e, j = o / e;
+      rec[kRecF + i + j * 96] = sLi[i + j * kMP];
+    }
+  } else if (w == 2) {
+    mma_gemm32<T, false, false>(sD, sLi, acc, g, c);   // D~21 L^-1
+    mma_store_global<T>(acc, rec + kRecF + e, 96, kept, e, rb - (uint32_t)(kRecF + e) * sz, g, c);
+  } else {
+    mma_gemm32<T, true, false>(sV, sLi, acc, g, c);    // V^_top^T L^-1
+    mma_store_global<T>(acc, rec + kRecF + e + kept, 96, kv, e,
+                        rb - (uint32_t)(kRecF + e + kept) * sz, g, c);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Root: LU with partial pivoting (FP64) of D'_root (or of D when p = 0).
 // ---------------------------------------------------------------------------
 template <typename T, bool BATCH>
@@ -707,13 +920,13 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max
   }
   // leaf launches (nblocks == number of leaves at the bottom level) get their own names
   static const char* names64[] = {"ulv_merge_f64", "ulv_factor_f64", "ulv_root_lu_f64",
-                                  "sv_fwd_f64", "sv_root_f64", "sv_bwd_f64"};
+                                  "sv_fwd_f64", "sv_root_f64", "sv_bwd_f64", "ulv_fwdop_f64"};
   static const char* names32[] = {"ulv_merge_f32", "ulv_factor_f32", "ulv_root_lu_f32",
-                                  "sv_fwd_f32", "sv_root_f32", "sv_bwd_f32"};
+                                  "sv_fwd_f32", "sv_root_f32", "sv_bwd_f32", "ulv_fwdop_f32"};
   static const char* leaf64[] = {"", "ulv_factor_leaf_f64", "", "sv_fwd_leaf_f64", "",
-                                 "sv_bwd_leaf_f64"};
+                                 "sv_bwd_leaf_f64", ""};
   static const char* leaf32[] = {"", "ulv_factor_leaf_f32", "", "sv_fwd_leaf_f32", "",
-                                 "sv_bwd_leaf_f32"};
+                                 "sv_bwd_leaf_f32", ""};
   const bool leafy = a.node0 > 0 && a.node0 == a.inst.nnodes / 2 && !batch;
   const char* nm = leafy ? (sizeof(T) == 8 ? leaf64 : leaf32)[(int)step]
                          : (sizeof(T) == 8 ? names64 : names32)[(int)step];
@@ -721,6 +934,9 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max
 #define HSS_LAUNCH(K)                                                         \
   if (batch) hipLaunchKernelGGL((K<T, true>), grid, block, sm, s, a);         \
   else hipLaunchKernelGGL((K<T, false>), grid, block, sm, s, a);
+#define HSS_LAUNCH_SM(K, SM)                                                  \
+  if (batch) hipLaunchKernelGGL((K<T, true>), grid, block, SM, s, a);         \
+  else hipLaunchKernelGGL((K<T, false>), grid, block, SM, s, a);
   switch (step) {
     case UlvStep::Merge:
       if (max_mp <= 64 && max_k <= 32) {
@@ -728,6 +944,9 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max
         HSS_LAUNCH(k_ulv_merge_mma);
       }
       else { HSS_LAUNCH(k_ulv_merge); }
+      break;
+    case UlvStep::FwdOp:
+      HSS_LAUNCH_SM(k_ulv_fwdop, (size_t)(12 * kMBlk + 32) * TB);
       break;
     case UlvStep::Factor:
       if (factor_blk_fits<T>(max_mp, max_k)) launch_factor_blk<T>(a, nblocks, s);
@@ -740,6 +959,7 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max
     default: break;
   }
 #undef HSS_LAUNCH
+#undef HSS_LAUNCH_SM
 }
 
 template void launch_ulv<double>(UlvStep, const KArgs<double, CallSV<double>>&, int, int, int,

@@ -86,7 +86,7 @@ hss_status build_plan(const hss_tree_desc* tree, Plan& P, std::string* why) {
   }
   // offsets
   int64_t oD = 0, oU = 0, oV = 0, oR = 0, oW = 0, o12 = 0, o21 = 0;
-  int64_t oFD = 0, oFU = 0, oFV = 0, otq = 0, otz = 0, oFZ = 0;
+  int64_t oFD = 0, oFU = 0, oFV = 0, otq = 0, otz = 0, oFZ = 0, oOP = 0;
   int64_t oxh = 0, oc = 0, oz = 0, oy = 0;
   for (int32_t t = 0; t < nn; ++t) {
     NodeInfo& d = P.nodes[t];
@@ -117,6 +117,17 @@ hss_status build_plan(const hss_tree_desc* tree, Plan& P, std::string* why) {
     d.otq = otq; otq += d.ku;
     d.otz = otz; otz += d.e;
     d.oFZ = oFZ; oFZ += int64_t(d.mp) * d.e;
+    int child_k = 0;
+    if (!d.is_leaf) {
+      const NodeInfo& a = P.nodes[2 * t + 1];
+      const NodeInfo& b = P.nodes[2 * t + 2];
+      child_k = std::max(std::max(a.ku, a.kv), std::max(b.ku, b.kv));
+    }
+    if (fwd_op_ok(d.is_leaf, t, d.mp, d.e, d.ku, d.kv, child_k)) {
+      d.oOP = oOP; oOP += kRecSize;
+    } else {
+      d.oOP = -1;
+    }
     d.oc = oc; d.ox = oc; oc += d.kept;
     d.oz = oz; oz += d.kv;
     d.oy = oy; oy += d.e;
@@ -140,11 +151,15 @@ hss_status build_plan(const hss_tree_desc* tree, Plan& P, std::string* why) {
     P.level_bwd_stage[d.level] =
         std::max(P.level_bwd_stage[d.level], int64_t(d.mp) * d.e);
   }
+  P.level_fwd_op.assign(p + 1, 1);
+  for (int32_t t = 0; t < nn; ++t)
+    if (P.nodes[t].oOP < 0) P.level_fwd_op[P.nodes[t].level] = 0;
   P.level_max_mp.assign(p + 1, 0);
   for (int32_t t = 0; t < nn; ++t)
     P.level_max_mp[P.nodes[t].level] = std::max(P.level_max_mp[P.nodes[t].level], P.nodes[t].mp);
   P.nD = oD; P.nU = oU; P.nV = oV; P.nR = oR; P.nW = oW; P.nB12 = o12; P.nB21 = o21;
   P.nFD = oFD; P.nFU = oFU; P.nFV = oFV; P.ntq = otq; P.ntz = otz; P.nFZ = oFZ;
+  P.nOP = oOP;
   P.ldm = std::max<int64_t>(oxh, 1);
   P.lds = std::max<int64_t>(std::max(oc, std::max(oz, oy)), 1);
   return HSS_OK;

@@ -21,6 +21,7 @@ struct Plan {
   int64_t nD = 0, nU = 0, nV = 0, nR = 0, nW = 0, nB12 = 0, nB21 = 0;
   // factor sizes (entries)
   int64_t nFD = 0, nFU = 0, nFV = 0, ntq = 0, ntz = 0, nFZ = 0;
+  int64_t nOP = 0;   // forward-operator records of the internal nodes
   int64_t ldm = 0;   // product work rows
   int64_t lds = 0;   // solve work rows
   int32_t max_m = 0, max_mp = 0, max_k = 0;
@@ -30,8 +31,10 @@ struct Plan {
   // need when they stage a node's factors (max over the level); root: the
   // children's blocks only (its FP64 LU is added separately)
   std::vector<int64_t> level_fwd_stage, level_bwd_stage;
+  // per level: every node has a forward-operator record
+  std::vector<int8_t> level_fwd_op;
   int64_t gen_entries() const { return nD + nU + nV + nR + nW + nB12 + nB21; }
-  int64_t factor_entries() const { return nFD + nFU + nFV + ntq + ntz + nFZ; }
+  int64_t factor_entries() const { return nFD + nFU + nFV + ntq + ntz + nFZ + nOP; }
 };
 
 // Returns 0 or a status (negative = invalid argument index as in hss.h).
