@@ -32,7 +32,7 @@ FP64_VEC_TFLOPS = 78.6
 # rocprofv3 runs (FETCH_SIZE, then WRITE_SIZE) at the headline size, each
 # scaled by what the counter reads for a plain device copy of known size
 # (x2.0 and x1.0); reported as the roofline line's "traffic".
-MEASURED_TRAFFIC = {"ulv_factor_leaf_f32": 834_430_213}
+MEASURED_TRAFFIC = {"ulv_factor_leaf_f32": 835_566_341, "ulv_factor_leaf_f64": 1_592_086_440}
 METRIC = "HSS solves/s & matmul GB/s, n=2^18 k=32; FP32+IR vs FP64 at 1e-10 bkwd err"
 
 
@@ -86,9 +86,11 @@ def main():
     ap.add_argument("--instances", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
-    ap.add_argument("--workload", default="headline", choices=["headline", "batch", "serve"],
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "batch", "serve", "cpu"],
                     help="headline: one n=2^18 system (default); batch: 512 uneven instances "
-                         "in level-batched launches; serve: Poisson request stream")
+                         "in level-batched launches; serve: Poisson request stream; cpu: the "
+                         "FP64 oracle timed on the host for every workload (no GPU)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -100,6 +102,9 @@ def main():
               "build (instances shard across GPUs without communication, see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "cpu":
+        return bench_cpu(args)
 
     import numpy as np
     import torch
@@ -272,6 +277,19 @@ def main():
         log(f"[bench] FP64 matmul r={rr}: {us:.1f} us, {byt / us / 1e3:.1f} GB/s; "
             f"graph replay {gus:.1f} us, {byt / gus / 1e3:.1f} GB/s")
 
+    # what the ||A||_2 estimate of hss_create costs (16 power steps: 16
+    # products with A and 16 with A^T at one column)
+    xv = hss.empty_colmajor(N, 1, torch.float64).normal_()
+    yv = hss.empty_colmajor(N, 1, torch.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(16):
+        mats[0].matmul(xv, yv)
+        mats[0].matmul(yv, xv, op=hss.OP_T)
+    torch.cuda.synchronize()
+    norm_ms = (time.perf_counter() - t0) * 1e3
+    log(f"[bench] ||A||_2 estimate (16 power steps at create): {norm_ms:.2f} ms")
+
     # per-kernel times (events around every launch) of the headline step, the
     # FP64 step and the FP64 product
     def kernel_times(fn, reps):
@@ -342,6 +360,7 @@ def main():
                                 "eta_max": max(e for e, _ in e32_10)},
         "norm2_note": "||A||_2 for eta is estimated once per matrix by hss_create (16 power "
                       "steps = 32 FP64 products) and is not part of a step",
+        "norm2_estimate_ms": round(norm_ms, 3),
         "fp64_solves_per_s": round(1.0 / t64, 2), "fp64_eta_max": max(e for e, _ in e64),
         "ratio_fp32ir_over_fp64": round(t64 / t32, 3),
         "resident_solves_per_s": {"fp32ir": round(1.0 / rt32, 2), "fp64": round(1.0 / rt64, 2)},
@@ -511,29 +530,115 @@ def bench_serve(args):
     _emit(out, args)
 
 
-def cpu_baseline(lo, r):
-    """The FP64 oracle (literal recursive ULV of Sec. 4.3) on the host: one
-    fresh-system solve (factorization and solve) of one instance."""
+def _host_cores():
+    """Host cores available to this process (the machine's CPU share)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def _median_time(fn, reps, warm=1):
+    """Median wall time of fn() over reps runs after warm untimed runs."""
     import numpy as np
+    for _ in range(warm):
+        fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), [round(t, 4) for t in ts]
+
+
+def cpu_baseline(lo, r, reps=3):
+    """The FP64 oracle (literal recursive ULV of Sec. 4.3, unoptimized
+    reference) on the host: the headline step, one fresh-system solve
+    (factorization and solve) of the n=2^18 instance, median of `reps` runs
+    after one warm-up, BLAS threads = the host cores available.  The full
+    table over every workload and at one thread is bench.py --workload cpu."""
+    from threadpoolctl import threadpool_limits
 
     from oracle.hss import HSS
     from oracle.ulv import solve
     from paper_1909_07909_amd import inputs
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    cores = _host_cores()
     g = inputs.synthetic_hss(lo, RANK, seed=2)
     H = HSS.from_packed(g)
     b = inputs.rhs(N, r, 3)
-    t0 = time.perf_counter()
-    solve(H, b)
-    dt = time.perf_counter() - t0
-    return {"value": round(1.0 / dt, 4), "unit": "solves/s", "cores": int(cores),
+    with threadpool_limits(limits=cores):
+        med, ts = _median_time(lambda: solve(H, b), reps)
+    return {"value": round(1.0 / med, 4), "unit": "solves/s", "cores": int(cores),
             "kind": "oracle",
-            "sample": f"1 fresh FP64 solve (literal recursive ULV, factor+solve), n={N}, "
-                      f"k={RANK}, nrhs={r}: {dt:.2f} s"}
+            "sample": f"fresh FP64 solve (literal recursive ULV, factor+solve) of the n={N}, "
+                      f"k={RANK}, nrhs={r} instance, median of {reps} after 1 warm-up "
+                      f"({ts} s); ||A||_2 for eta is not part of it (the oracle's power method, "
+                      f"50 steps, takes about 100 products)"}
+
+
+def bench_cpu(args):
+    """The FP64 oracle timed on the host for every workload, all cores and
+    one core, median of 5 runs after one warm-up: products at 1 and 32 (64)
+    right-hand sides and fresh factor+solve for the small-parity, ragged-rank
+    and headline workloads, and factor+solve of 32 instances of the batching
+    workload.  The oracle is the unoptimized reference implementation (plain
+    NumPy/SciPy recursion), not a tuned CPU library."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+    from cauchy_fixture import cauchy_hss
+    from oracle import tree
+    from oracle.hss import HSS
+    from oracle.matvec import matvec
+    from oracle.ulv import solve
+    from paper_1909_07909_amd import inputs
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    cores = _host_cores()
+    reps = 5
+    cases = []
+    g0 = inputs.synthetic_hss(tree.leaf_offsets(1024, 64), 8, seed=0)
+    cases.append(("c0 n=1024 m=64 k=8", HSS.from_packed(g0), [1, 16], 16))
+    log("[cpu] compressing the ragged-rank workload (n=16384)")
+    g1, _ = cauchy_hss(16384, tree.leaf_offsets(16384, 128), seed=1, tol=1e-10)
+    cases.append(("c1 cauchy n=16384 m=128 ranks<=21", HSS.from_packed(g1), [1, 64], 64))
+    g2 = inputs.synthetic_hss(tree.leaf_offsets(N, LEAF), RANK, seed=2)
+    cases.append((f"c2 n={N} m={LEAF} k={RANK}", HSS.from_packed(g2), [1, 32], 1))
+    kids = np.random.SeedSequence(3).spawn(512)[:32]
+    batch = []
+    for child in kids:
+        rr = np.random.default_rng(child)
+        n = 64 * int(rr.integers(32, 513))
+        k = int(rr.choice([8, 16, 24]))
+        batch.append(HSS.from_packed(inputs.synthetic_hss(tree.leaf_offsets(n, 64), k, seed=child)))
+    rows = []
+    for threads in (cores, 1):
+        with threadpool_limits(limits=threads):
+            for name, H, mm_r, sv_r in cases:
+                for rr in mm_r:
+                    X = inputs.rhs(H.n, rr, 5)
+                    med, ts = _median_time(lambda: matvec(H, X), reps)
+                    rows.append({"workload": name, "op": f"matmul r={rr}", "threads": threads,
+                                 "median_s": round(med, 5), "runs_s": ts})
+                    log(f"[cpu] {threads} thr {name} matmul r={rr}: {med:.4f} s")
+                B = inputs.rhs(H.n, sv_r, 6)
+                med, ts = _median_time(lambda: solve(H, B), reps)
+                rows.append({"workload": name, "op": f"factor+solve r={sv_r}", "threads": threads,
+                             "median_s": round(med, 5), "runs_s": ts})
+                log(f"[cpu] {threads} thr {name} factor+solve r={sv_r}: {med:.4f} s")
+            Bs = [inputs.rhs(H.n, 8, 7 + j) for j, H in enumerate(batch)]
+
+            def run_batch():
+                for H, B in zip(batch, Bs):
+                    solve(H, B)
+            med, ts = _median_time(run_batch, reps)
+            rows.append({"workload": "c3 subset: 32 instances n=64*U{32..512} m=64 k in {8,16,24}",
+                         "op": "factor+solve r=8 (all 32)", "threads": threads,
+                         "median_s": round(med, 5), "runs_s": ts})
+            log(f"[cpu] {threads} thr c3 subset: {med:.4f} s")
+    out = {"metric": "FP64 oracle (unoptimized reference) wall time on the host",
+           "host_cores": cores, "reps": reps, "warmup": 1, "timings": rows}
+    _emit(out, args)
 
 
 if __name__ == "__main__":
