@@ -196,8 +196,14 @@ hss_status ensure_ir(hss_handle* h, int64_t nrhs) {
   return HSS_OK;
 }
 
+// Work sets an instance record carries: the product's (x^, y^, mailboxes)
+// and the solve's (c, z, y, x).  A batched call's device table holds only the
+// set its kernels read, so it does not change when another call grows the
+// other set (a table equal to an earlier one is reused, also under capture).
+constexpr int kUseMM = 1, kUseSV = 2;
+
 template <typename T>
-Inst<T> make_inst(hss_handle* h) {
+Inst<T> make_inst(hss_handle* h, int uses = kUseMM | kUseSV) {
   Inst<T> I{};
   I.nodes = h->d_nodes;
   I.D = gen<T>(h, 0); I.U = gen<T>(h, 1); I.V = gen<T>(h, 2); I.R = gen<T>(h, 3);
@@ -207,9 +213,13 @@ Inst<T> make_inst(hss_handle* h) {
   I.FOP = F.FOP;
   I.rootLU = F.rootLU; I.piv = F.piv;
   Work<T>& w = work<T>(h);
-  I.xh = w.xh; I.yh = w.yh; I.ldm = h->plan.ldm;
-  I.mb = w.mb;
-  I.wc = w.wc; I.wz = w.wz; I.wy = w.wy; I.wx = w.wx; I.lds = h->plan.lds;
+  if (uses & kUseMM) {
+    I.xh = w.xh; I.yh = w.yh; I.ldm = h->plan.ldm;
+    I.mb = w.mb;
+  }
+  if (uses & kUseSV) {
+    I.wc = w.wc; I.wz = w.wz; I.wy = w.wy; I.wx = w.wx; I.lds = h->plan.lds;
+  }
   I.status = h->d_status;
   I.cnt = h->d_cnt;
   I.p = h->plan.p;
@@ -453,14 +463,27 @@ hss_status compute_norm2(hss_handle* h, hipStream_t s) {
 // ===========================================================================
 namespace {
 
-// Device scratch for the task / pointer tables of batched calls, one per
+// Device copies of the task / pointer tables of batched calls, one cache per
 // stream: batched calls on different streams run concurrently, calls on one
-// stream are serialized by the scratch's lock (and by the stream itself).
-struct BatchScratch {
-  void* d = nullptr;
+// stream are serialized by the cache's lock (and by the stream itself).  A
+// table is looked up by its bytes: a call whose tables equal an earlier
+// call's reuses that device copy without an upload, which is what lets a
+// batched call run under HIP graph capture (after an eager call with the same
+// handles and blocks) -- tables used while capturing are kept for good, since
+// a captured graph holds their addresses.  Other tables are replaced least
+// recently used first; the upload that replaces one is ordered on the stream
+// after every earlier launch that read it.
+struct TableEntry {
+  std::vector<char> bytes;
+  void* dev = nullptr;
   size_t cap = 0;
-  void* ir = nullptr;    // refinement descriptors
-  size_t ir_cap = 0;
+  uint64_t last_use = 0;
+  bool pinned = false;
+};
+constexpr size_t kTableCacheEntries = 64;
+struct BatchScratch {
+  std::vector<TableEntry> tables;
+  uint64_t clock = 0;
   std::mutex mu;
 };
 std::mutex g_scratch_mu;
@@ -473,31 +496,63 @@ BatchScratch& scratch_for(hipStream_t s) {
   return *p;
 }
 
-// Grows a scratch buffer.  The buffer it replaces may still be read by work
-// in flight or by captured graphs; it is kept (never freed), and growth is
-// geometric, so what is kept is bounded by the final size.
-hss_status grow(void** d, size_t* cap, size_t need, hipStream_t) {
-  if (*cap >= need) return HSS_OK;
-  *d = nullptr;
-  *cap = 0;
-  const size_t c = std::max<size_t>(need * 2, 1 << 20);
-  if (hipMalloc(d, c) != hipSuccess) {
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
     (void)hipGetLastError();
-    return HSS_ENOMEM;
+    return false;
   }
-  *cap = c;
-  return HSS_OK;
+  return cs == hipStreamCaptureStatusActive;
 }
 
+// Device copy of the table `host` (see BatchScratch).  Under capture a table
+// that no eager call has uploaded is refused (HSS_ESTATE): its upload would
+// be recorded from host memory that is gone when the graph is replayed.
 hss_status scratch_upload(BatchScratch& B, const std::vector<char>& host, hipStream_t s,
                           void** dptr) {
-  hss_status st = grow(&B.d, &B.cap, host.size(), s);
-  if (st) return st;
+  const bool capturing = stream_capturing(s);
+  ++B.clock;
+  for (TableEntry& e : B.tables)
+    if (e.bytes.size() == host.size() &&
+        (host.empty() || std::memcmp(e.bytes.data(), host.data(), host.size()) == 0)) {
+      e.last_use = B.clock;
+      e.pinned = e.pinned || capturing;
+      *dptr = e.dev;
+      return HSS_OK;
+    }
+  if (capturing) return HSS_ESTATE;
+  TableEntry* e = nullptr;
+  if (B.tables.size() < kTableCacheEntries) {
+    B.tables.emplace_back();
+    e = &B.tables.back();
+  } else {
+    for (TableEntry& t : B.tables)
+      if (!t.pinned && (!e || t.last_use < e->last_use)) e = &t;
+    if (!e) {
+      B.tables.emplace_back();
+      e = &B.tables.back();
+    }
+  }
+  if (e->cap < host.size() || !e->dev) {
+    // the buffer being replaced may still be read by launches in flight:
+    // kept (never freed), as are the buffers of pinned tables
+    void* d = nullptr;
+    const size_t c = std::max<size_t>(host.size() * 2, 1 << 16);
+    if (hipMalloc(&d, c) != hipSuccess) {
+      (void)hipGetLastError();
+      return HSS_ENOMEM;
+    }
+    e->dev = d;
+    e->cap = c;
+  }
+  e->bytes = host;
+  e->last_use = B.clock;
+  e->pinned = false;
   // pageable source: the runtime stages it before the call returns
   if (!host.empty() &&
-      hipMemcpyAsync(B.d, host.data(), host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+      hipMemcpyAsync(e->dev, host.data(), host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
     return HSS_EHIP;
-  *dptr = B.d;
+  *dptr = e->dev;
   return HSS_OK;
 }
 
@@ -558,7 +613,7 @@ hss_status batch_matmul_impl(BatchScratch& BS, hss_handle* const* hs, int count,
   for (int j = 0; j < count; ++j) {
     hss_status st = ensure_work_mm<T>(hs[j], std::max<int64_t>(nrhs[j], 1));
     if (st) return st;
-    insts[j] = make_inst<T>(hs[j]);
+    insts[j] = make_inst<T>(hs[j], kUseMM);
     calls[j] = CallMM<T>{(const T*)X[j], (T*)Y[j], ldx[j], ldy[j], (int32_t)nrhs[j], op,
                          gated ? hs[j]->d_status + kStGate : nullptr};
     maxr = std::max(maxr, nrhs[j]);
@@ -661,7 +716,7 @@ hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
   for (int j = 0; j < count; ++j) {
     hss_status st = ensure_factors<T>(hs[j]);
     if (st) return st;
-    insts[j] = make_inst<T>(hs[j]);
+    insts[j] = make_inst<T>(hs[j], 0);
   }
   const int pmax = max_depth(hs, count);
   StepList L;
@@ -726,7 +781,7 @@ hss_status batch_sweep(BatchScratch& BS, hss_handle* const* hs, int count, const
   for (int j = 0; j < count; ++j) {
     hss_status st = ensure_work_sv<T>(hs[j], std::max<int64_t>(nrhs[j], 1));
     if (st) return st;
-    insts[j] = make_inst<T>(hs[j]);
+    insts[j] = make_inst<T>(hs[j], kUseSV);
     calls[j] = CallSV<T>{rhs[j], ld[j], (int32_t)nrhs[j], 0,
                          gated ? hs[j]->d_status + kStGate : nullptr};
     maxr = std::max(maxr, nrhs[j]);
@@ -826,12 +881,12 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
     d64[j] = h->d64;
     res[j] = h->res;
   }
-  // the sweeps below use the table scratch, so the refinement descriptors get their own
-  if ((st = grow(&BS.ir, &BS.ir_cap, sizeof(IRSeg) * count + 256, s))) return st;
-  IRSeg* dsegs = reinterpret_cast<IRSeg*>((char*)BS.ir + 256);
-  if (hipMemcpyAsync(dsegs, segs.data(), sizeof(IRSeg) * count, hipMemcpyHostToDevice, s) !=
-      hipSuccess)
-    return HSS_EHIP;
+  // the refinement descriptors are a table of their own
+  std::vector<char> segbytes(sizeof(IRSeg) * count);
+  std::memcpy(segbytes.data(), segs.data(), segbytes.size());
+  void* dsegp = nullptr;
+  if ((st = scratch_upload(BS, segbytes, s, &dsegp))) return st;
+  IRSeg* dsegs = reinterpret_cast<IRSeg*>(dsegp);
   auto ir = [&](int op, bool gated = false, int step = 0) {
     launch_ir_batch(op, dsegs, count, maxn, gated, step, opt.max_refine, s);
   };

@@ -436,10 +436,11 @@ def batch_matmul(mats, Xs, Ys, op=OP_N, stream=None):
 
 
 def batch_solve(mats, Bs, prec=F64, tol=0.0, max_refine=10, want_eta=False, stream=None,
-                sync=True):
+                sync=True, reports=None):
     """B_i <- A_i^{-1} B_i for every instance (one launch per tree level).
     sync=True: waits and returns one report dict per instance; sync=False
-    returns the SolveReports."""
+    returns the SolveReports.  reports: SolveReports to write (e.g. allocated
+    before a graph capture)."""
     import torch
     if len(mats) != len(Bs):
         raise ValueError("mats and Bs must have the same length")
@@ -451,7 +452,9 @@ def batch_solve(mats, Bs, prec=F64, tol=0.0, max_refine=10, want_eta=False, stre
     hs = _ptr_array([m.h.value for m in mats])
     nr = (C.c_int64 * cnt)(*[b.shape[1] for b in Bs])
     opts = SolveOpts(prec, max_refine, tol, 1 if want_eta else 0, 0)
-    reps = [SolveReport(b.shape[1]) for b in Bs]
+    reps = [SolveReport(b.shape[1]) for b in Bs] if reports is None else list(reports)
+    if len(reps) != cnt or any(r.nrhs < b.shape[1] for r, b in zip(reps, Bs)):
+        raise ValueError("one report per instance, each with room for its columns")
     code = lib().hss_batch_ulv_solve(hs, cnt, nr, _ptr_array(bp), (C.c_int64 * cnt)(*lb),
                                      C.byref(opts), _ptr_array([r.ptr.value for r in reps]),
                                      _stream(stream))
