@@ -669,8 +669,11 @@ __global__ __launch_bounds__(kNT) void k_ulv_fwdop(KArgs<T, CallSV<T>> a) {
       sB21[i + j * kMP] = v[8][u];
     }
     if (tid < 32) staus[tid] = tid < ku ? I.tq[nd.otq + tid] : T(0);
-    // the record starts cleared (its unused rows and columns stay zero)
-    for (int o = tid; o < kRecSize; o += kNT) rec[o] = T(0);
+    // the record starts cleared (its unused rows and columns stay zero),
+    // 16 bytes per store
+    int4* r4 = reinterpret_cast<int4*>(rec);
+    constexpr int n4 = kRecSize * (int)sizeof(T) / 16;
+    for (int o = tid; o < n4; o += kNT) r4[o] = make_int4(0, 0, 0, 0);
   }
   __syncthreads();
   mma4_t<T> acc[2][2];
@@ -685,20 +688,15 @@ __global__ __launch_bounds__(kNT) void k_ulv_fwdop(KArgs<T, CallSV<T>> a) {
     mma_gemm32_acc<T, true, false>(sY1, sY1, acc, g, c);
     mma_store_lds<T>(acc, sG, g, c);
   } else if (w == 1) {
-    if (lane < 32) {
-      // column j = lane of L^-1 by forward substitution (rows i < j stay zero)
-      const int j = lane;
-      T x[32];
-#pragma unroll
-      for (int i = 0; i < 32; ++i) {
-        T s = (i == j) ? T(1) : T(0);
-#pragma unroll
-        for (int k = 0; k < i; ++k) s -= sLt[k + i * kMP] * x[k];
-        const T d = sLt[i + i * kMP];
-        x[i] = (i < e) & (j < e) ? s / d : T(0);
-      }
-#pragma unroll
-      for (int i = 0; i < 32; ++i) sLi[i + j * kMP] = x[i];
+    // W (kw x kv, pitch 65) and Y (with its unit pivots, pitch 65) into the record
+    const T* W = I.W + nd.oW;
+    for (int o = lane; o < kw * kv; o += 64) {
+      const int i = o % kw, j = o / kw;
+      rec[kRecW + i + j * 65] = W[o];
+    }
+    for (int o = lane; o < mp * ku; o += 64) {
+      const int i = o % mp, j = o / mp;
+      rec[kRecY + i + j * 65] = i < 32 ? sY0[i + j * kMP] : sY1[i - 32 + j * kMP];
     }
   } else if (w == 2) {
     // rows 0 .. k1-1, columns kv1 .. of G: U~_c1 B12
@@ -712,32 +710,37 @@ __global__ __launch_bounds__(kNT) void k_ulv_fwdop(KArgs<T, CallSV<T>> a) {
                         c);
   }
   __syncthreads();
+  // T and L^-1, one column per lane; every sum over four partial sums (the
+  // dependence chain of a column is what these steps wait on)
   if (w == 0 && lane < 32) {
     // column j = lane of T, rows from the bottom up
     const int j = lane;
     T t[32];
 #pragma unroll
     for (int i = 31; i >= 0; --i) {
-      T s = (i == j) ? T(1) : T(0);
+      T q[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int m = i + 1; m < 32; ++m) s -= sG[i + m * kMP] * t[m];
+      for (int m = i + 1; m < 32; ++m) q[(m - i - 1) & 3] += sG[i + m * kMP] * t[m];
+      const T s = ((i == j) ? T(1) : T(0)) - ((q[0] + q[1]) + (q[2] + q[3]));
       t[i] = (i < ku) & (j < ku) ? staus[i] * s : T(0);
     }
 #pragma unroll
     for (int i = 0; i < 32; ++i) sT[i + j * kMP] = t[i];
-  } else if (w == 1) {
-    // W (kw x kv) into the record, pitch 65
-    const T* W = I.W + nd.oW;
-    for (int o = lane; o < kw * kv; o += 64) {
-      const int i = o % kw, j = o / kw;
-      rec[kRecW + i + j * 65] = W[o];
+  } else if (w == 1 && lane < 32) {
+    // column j = lane of L^-1 by forward substitution (rows i < j stay zero)
+    const int j = lane;
+    T x[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      T q[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < i; ++k) q[k & 3] += sLt[k + i * kMP] * x[k];
+      const T s = ((i == j) ? T(1) : T(0)) - ((q[0] + q[1]) + (q[2] + q[3]));
+      const T d = sLt[i + i * kMP];
+      x[i] = (i < e) & (j < e) ? s / d : T(0);
     }
-  } else if (w == 2) {
-    // Y (with its unit pivots), pitch 65
-    for (int o = lane; o < mp * ku; o += 64) {
-      const int i = o % mp, j = o / mp;
-      rec[kRecY + i + j * 65] = i < 32 ? sY0[i + j * kMP] : sY1[i - 32 + j * kMP];
-    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) sLi[i + j * kMP] = x[i];
   }
   __syncthreads();
   if (w == 0) {
