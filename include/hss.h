@@ -230,7 +230,16 @@ hss_status hss_plan_node_ranges(const hss_tree_desc *tree, int64_t *start, int64
  * aligned at the leaves for upward passes and at the root for downward
  * passes).  Each result equals the single-handle call on the same stream.
  * hs: host array of count handles; the per-handle arrays are host arrays of
- * count entries; B / X / Y entries are device pointers. */
+ * count entries; B / X / Y entries are device pointers.
+ * Each call uploads small task tables (the handles' records, the per-level
+ * node lists, the right-hand-side pointers) to device memory kept per
+ * stream; a table equal byte for byte to one an earlier call on that stream
+ * uploaded is reused.  Under HIP graph capture no upload can be recorded, so
+ * a batched call is captured only after the same call (same handles, counts,
+ * pointers and options) has run on that stream outside capture; otherwise it
+ * returns HSS_ESTATE, and the capture (which may hold part of the call) is
+ * to be discarded.  Tables used by a captured call are kept for the life of
+ * the process. */
 hss_status hss_batch_matmul(hss_handle *const *hs, int32_t count, int32_t op, int32_t prec,
                             const int64_t *nrhs, const void *const *X, const int64_t *ldx,
                             void *const *Y, const int64_t *ldy, void *stream);
