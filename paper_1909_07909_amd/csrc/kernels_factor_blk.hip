@@ -209,72 +209,17 @@ __device__ __forceinline__ void slab_store_cols(const v4<T> (&X)[8][2], T* A, in
   }
 }
 
-// A panel of 32 vectors spread over the four wavefronts by position:
-// wavefront w holds positions 32 w .. 32 w + 31 of every vector as tiles
-// (rl, ct); lane (g, c), component r holds vector 16 ct + c at position
-// 32 w + 16 rl + 4 g + r.
+// A panel is one wavefront's slab: vector 16 ct + c of the panel is column
+// 16 ct + c of the slab, its position R the slab row.  The position of lane
+// (g, c), tile rt, component r is 16 rt + rho(g, r) = tile_pos(rt, r) +
+// lane_pos(g).
 template <typename T>
-struct Panel {
-  v4<T> t[2][2];
-};
-
-// LDS of the panel steps.
-template <typename T>
-struct PanelLds {
-  T* red;     // partial squared norms: [parity][wavefront] (2 x 4)
-  T* dred;    // partial sums of vector v: [parity][v][wavefront][raw dot, value at pp] (2 x kBW x 8)
-  T* Yt;      // reflectors, vector-major (kBW x kLY)
-  T* bet;
-  T* taus;
-};
-
-// Panel element (vector C, position R) = A[(R - s) + C * ld] for C < cols and
-// R >= s, else 0.
-template <typename T>
-__device__ __forceinline__ void panel_load_cols(Panel<T>& Pn, const T* A, int ld, int cols, int s,
-                                                int w, int g, int c) {
-  constexpr uint32_t sz = sizeof(T);
-  const auto R = buf_rsrc(A, (uint32_t)(ld * cols) * sz);
-  const int base = 32 * w;
-#pragma unroll
-  for (int ct = 0; ct < 2; ++ct) {
-    const int vec = 16 * ct + c;
-    const bool vok = vec < cols;
-#pragma unroll
-    for (int rl = 0; rl < 2; ++rl)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = base + 16 * rl + 4 * g + r - s;
-        const uint32_t o = vok & (row >= 0) ? (uint32_t)(row + vec * ld) * sz : kBufOOB;
-        Pn.t[rl][ct][r] = buf_load<T>(R, o, 0);
-      }
-  }
+__device__ __forceinline__ int lane_pos(int g) {
+  return sizeof(T) == 4 ? 4 * g : g;
 }
-
-// This wavefront's positions of a panel stored vector-major in LDS (pitch kLY).
 template <typename T>
-__device__ __forceinline__ void panel_load_lds(Panel<T>& Pn, const T* Pb, int w, int g, int c) {
-#pragma unroll
-  for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-    for (int rl = 0; rl < 2; ++rl)
-      Pn.t[rl][ct] =
-          *reinterpret_cast<const v4<T>*>(Pb + (16 * ct + c) * kLY + 32 * w + 16 * rl + 4 * g);
-}
-
-// Zero this wavefront's positions of every reflector (and, wavefront 0, the
-// scalars) before a panel.
-template <typename T>
-__device__ __forceinline__ void panel_clear(const PanelLds<T>& L, int w, int lane) {
-  const int q = lane & 7, row0 = lane >> 3;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-    *reinterpret_cast<v4<T>*>(L.Yt + (row0 + 8 * u) * kLY + 32 * w + 4 * q) = v4zero<T>();
-  if (w == 0 && lane < kBW) {
-    L.bet[lane] = T(0);
-    L.taus[lane] = T(0);
-  }
-  wave_lds_sync();
+__device__ __forceinline__ constexpr int tile_pos(int rt, int r) {
+  return 16 * rt + (sizeof(T) == 4 ? r : 4 * r);
 }
 
 __device__ __forceinline__ float lane_fetch(int addr, float v) {
@@ -287,184 +232,216 @@ __device__ __forceinline__ double lane_fetch(int addr, double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One Householder step of a panel (all four wavefronts, one barrier).
-//   QL: vector jv is column jv of U', pivot position pp, support positions
-//       <= pp; the vectors still to update are those before jv.
-//   LQ: vector jv is row i0 + jv of M, pivot position pp = i0 + jv, support
-//       positions >= pp; the vectors still to update are those after jv.
-// With x the pivot vector off the pivot position (zero outside the support)
-// and v = scale x + e_pp the reflector, v . y = scale (x . y) + y(pp) for
-// every vector y, so each wavefront reduces ||x||^2 and, per vector, x . y
-// and y(pp) over its positions before the scale is known: one exchange
-// (double-buffered by step parity) per step.  The reflector goes to row jv
-// of Yt, beta and tau to bet / taus; the pivot vector itself is left as it
-// was (the caller composes its final form).
-// MODE: 0 this wavefront's positions are all outside the support, 1 all
-// inside it, 2 the pivot or an end of the support may lie among them.
-template <typename T, bool QL, int MODE>
-__device__ __forceinline__ void step_sums(const Panel<T>& Pn, const v4<T> (&xp)[2], int pp, int base,
-                                          int g, T (&acc)[5]) {
-#pragma unroll
-  for (int q = 0; q < 5; ++q) acc[q] = T(0);
-  if (MODE == 0) return;
-#pragma unroll
-  for (int rl = 0; rl < 2; ++rl)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      T y = xp[rl][r];
-      if (MODE == 2) {
-        const int th = su(pp - base - 16 * rl - r);   // position - pp = 4 g - th
-        const bool in = QL ? 4 * g < th : 4 * g > th;
-        const bool at = 4 * g == th;
-        y = in ? y : T(0);
-        acc[3] += at ? Pn.t[rl][0][r] : T(0);
-        acc[4] += at ? Pn.t[rl][1][r] : T(0);
-      }
-      acc[0] += y * y;
-      acc[1] += y * Pn.t[rl][0][r];
-      acc[2] += y * Pn.t[rl][1][r];
-    }
-}
+// Per-panel scalars in LDS: the scale of every reflector's off-pivot part,
+// beta and tau, indexed by vector.
+template <typename T>
+struct PanelScal {
+  T* scale;
+  T* bet;
+  T* taus;
+};
 
-template <typename T, bool QL>
-__device__ __forceinline__ void panel_step(Panel<T>& Pn, int jv, int pp, const PanelLds<T>& L,
-                                           int w, int lane, int g, int c) {
-  const int ctj = jv >> 4, cj = jv & 15;
-  const int base = 32 * w;
-  const int par = jv & 1;
-  // the pivot vector at this lane's positions, from lane (g, cj)
+// One Householder step of a panel held by one wavefront (no work-group
+// barrier).
+//   QL: vector jv is column jv of U', pivot position pp, support positions
+//       below pp; the vectors still to update are those before jv.
+//   LQ: vector jv is row i0 + jv of M, pivot position pp = i0 + jv, support
+//       positions above pp; the vectors still to update are those after jv.
+// x, the pivot vector on its support (zero elsewhere), reaches every lane
+// from the lane of the same g that holds vector jv (CT = jv / 16).  With
+// v = scale x + e_pp the reflector, v . y = scale (x . y) + y(pp) for every
+// vector y, so every lane forms x . y and y(pp) for its two vectors at its
+// positions, the four lanes of a column (g = 0..3) add them up, and ||x||^2
+// and alpha = x(pp) are the pivot vector's own sums.  The update is
+// y <- y - tau (v . y) v; the pivot vector keeps x (unscaled) and alpha, and
+// its scale, beta and tau go to the LDS scalars, from which the caller
+// composes the finished vector.  RTB = pp / 16 is the tile of the pivot:
+// tiles wholly outside the support are skipped, those wholly inside need no
+// mask (both known at compile time).
+template <typename T, bool QL, int CT, int RTB>
+__device__ __forceinline__ void wave_step(v4<T> (&X)[8][2], int jv, int pp,
+                                          const PanelScal<T>& S, T* Gs, T (&msc)[2], int g,
+                                          int c, int lane, int* sing) {
+  const int cj = su(jv & 15);
   const int src = (16 * g + cj) * 4;
-  v4<T> xp[2];
-  if (ctj) {
+  const int lp = lane_pos<T>(g);
+  T xm[8][4];
+  T d0[2] = {T(0), T(0)}, d1[2] = {T(0), T(0)};
+  T y0 = T(0), y1 = T(0);
 #pragma unroll
-    for (int rl = 0; rl < 2; ++rl)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) xp[rl][r] = lane_fetch(src, Pn.t[rl][1][r]);
-  } else {
-#pragma unroll
-    for (int rl = 0; rl < 2; ++rl)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) xp[rl][r] = lane_fetch(src, Pn.t[rl][0][r]);
-  }
-  // where this wavefront's positions lie relative to the support
-  const bool inside = QL ? base + 31 < pp : base > pp;
-  const bool outside = QL ? base > pp : base + 31 < pp;
-  T acc[5];
-  if (inside) step_sums<T, QL, 1>(Pn, xp, pp, base, g, acc);
-  else if (outside) step_sums<T, QL, 0>(Pn, xp, pp, base, g, acc);
-  else step_sums<T, QL, 2>(Pn, xp, pp, base, g, acc);
-#pragma unroll
-  for (int q = 0; q < 5; ++q) acc[q] = xsum_rows(acc[q]);
-  T* red = L.red + 4 * par;
-  T* dred = L.dred + 8 * kBW * par;
-  if (lane == 0) red[w] = acc[0];
-  if (g == 0) {
-    dred[8 * c + 2 * w] = acc[1];
-    dred[8 * c + 2 * w + 1] = acc[3];
-    dred[8 * (16 + c) + 2 * w] = acc[2];
-    dred[8 * (16 + c) + 2 * w + 1] = acc[4];
-  }
-  __syncthreads();
-  const v4<T> rd = *reinterpret_cast<const v4<T>*>(red);
-  const T sigma = (rd[0] + rd[1]) + (rd[2] + rd[3]);
-  const T* pj = dred + 8 * jv;
-  const T alpha = (pj[1] + pj[3]) + (pj[5] + pj[7]);
-  T beta, tau, scale;
-  householder_fast(alpha, sigma, beta, tau, scale);
-  const v4<T> e0a = *reinterpret_cast<const v4<T>*>(dred + 8 * c);
-  const v4<T> e0b = *reinterpret_cast<const v4<T>*>(dred + 8 * c + 4);
-  const v4<T> e1a = *reinterpret_cast<const v4<T>*>(dred + 8 * (16 + c));
-  const v4<T> e1b = *reinterpret_cast<const v4<T>*>(dred + 8 * (16 + c) + 4);
-  const T x0 = (e0a[0] + e0a[2]) + (e0b[0] + e0b[2]), y0 = (e0a[1] + e0a[3]) + (e0b[1] + e0b[3]);
-  const T x1 = (e1a[0] + e1a[2]) + (e1b[0] + e1b[2]), y1 = (e1a[1] + e1a[3]) + (e1b[1] + e1b[3]);
-  const int v0 = c, v1 = 16 + c;
-  const T w0 = (QL ? v0 < jv : v0 > jv) ? tau * (scale * x0 + y0) : T(0);
-  const T w1 = (QL ? v1 < jv : v1 > jv) ? tau * (scale * x1 + y1) : T(0);
-  // the reflector at this lane's positions, and the update
-  if (inside) {
-#pragma unroll
-    for (int rl = 0; rl < 2; ++rl)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) xp[rl][r] *= scale;
-  } else if (outside) {
-#pragma unroll
-    for (int rl = 0; rl < 2; ++rl) xp[rl] = v4zero<T>();
-  } else {
-#pragma unroll
-    for (int rl = 0; rl < 2; ++rl)
+  for (int rt = 0; rt < 8; ++rt) {
+    if (QL ? rt < RTB : rt > RTB) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int th = su(pp - base - 16 * rl - r);
-        const bool in = QL ? 4 * g < th : 4 * g > th;
-        const T y = xp[rl][r] * scale;
-        xp[rl][r] = in ? y : (4 * g == th ? T(1) : T(0));
+        const T x = lane_fetch(src, X[rt][CT][r]);
+        xm[rt][r] = x;
+        d0[r & 1] += x * X[rt][0][r];
+        d1[r & 1] += x * X[rt][1][r];
       }
-  }
+    } else if (rt == RTB) {
 #pragma unroll
-  for (int rl = 0; rl < 2; ++rl)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      Pn.t[rl][0][r] -= w0 * xp[rl][r];
-      Pn.t[rl][1][r] -= w1 * xp[rl][r];
+      for (int r = 0; r < 4; ++r) {
+        const int th = su(pp - tile_pos<T>(rt, r));   // position - pp = lp - th
+        const T xr = lane_fetch(src, X[rt][CT][r]);
+        const bool in = QL ? lp < th : lp > th;
+        const bool at = lp == th;
+        const T x = in ? xr : T(0);
+        xm[rt][r] = x;
+        d0[r & 1] += x * X[rt][0][r];
+        d1[r & 1] += x * X[rt][1][r];
+        y0 += at ? X[rt][0][r] : T(0);
+        y1 += at ? X[rt][1][r] : T(0);
+      }
     }
-  if (c == 0) {
-#pragma unroll
-    for (int rl = 0; rl < 2; ++rl)
-      *reinterpret_cast<v4<T>*>(L.Yt + jv * kLY + base + 16 * rl + 4 * g) = xp[rl];
   }
-  if (w == 0 && lane == 0) {
-    L.bet[jv] = beta;
-    L.taus[jv] = tau;
+  const T dot0 = xsum_rows(d0[0] + d0[1]);
+  const T dot1 = xsum_rows(d1[0] + d1[1]);
+  y0 = xsum_rows(y0);
+  y1 = xsum_rows(y1);
+  const T sigma = lane_read(CT ? dot1 : dot0, cj);
+  const T alpha = lane_read(CT ? y1 : y0, cj);
+  T beta, tau, scale;
+  householder_fast(alpha, sigma, beta, tau, scale);
+  // h = v . y for both vectors: the update of the vectors still to come, and
+  // for the finished ones (which keep their unscaled x) the Gram entry
+  // Y_k^T Y_jv = scale_k h_k of the compact-WY factor
+  const T h0 = scale * dot0 + y0, h1 = scale * dot1 + y1;
+  const T w0 = (QL ? c < jv : c > jv) ? tau * h0 : T(0);
+  const T w1 = (QL ? 16 + c < jv : 16 + c > jv) ? tau * h1 : T(0);
+  const T s0 = w0 * scale, s1 = w1 * scale;
+  if (g == 0) {
+    const T gv0 = (QL ? c > jv : c < jv) ? msc[0] * h0 : T(0);
+    const T gv1 = (QL ? 16 + c > jv : 16 + c < jv) ? msc[1] * h1 : T(0);
+    if (QL) {
+      Gs[jv * kLT + c] = gv0;
+      Gs[jv * kLT + 16 + c] = gv1;
+    } else {
+      Gs[c * kLT + jv] = gv0;
+      Gs[(16 + c) * kLT + jv] = gv1;
+    }
+  }
+  if (c == cj) msc[CT] = scale;
+#pragma unroll
+  for (int rt = 0; rt < 8; ++rt) {
+    if (QL ? rt < RTB : rt > RTB) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        X[rt][0][r] -= s0 * xm[rt][r];
+        X[rt][1][r] -= s1 * xm[rt][r];
+      }
+    } else if (rt == RTB) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int th = su(pp - tile_pos<T>(rt, r));
+        const bool at = lp == th;
+        X[rt][0][r] -= at ? w0 : s0 * xm[rt][r];
+        X[rt][1][r] -= at ? w1 : s1 * xm[rt][r];
+      }
+    }
+  }
+  if (lane == 0) {
+    S.scale[jv] = scale;
+    S.bet[jv] = beta;
+    S.taus[jv] = tau;
+    if (!QL && beta == T(0)) *sing = 1;
   }
 }
 
-// T of the panel in Yt / taus into Ts (TRANS: T^T), by the whole work-group.
-// G = Y^T Y (its three upper 16x16 tiles) by the wavefronts other than pw,
-// then the back substitution by wavefront (pw + 1) & 3, lane j < 32 computing
-// column j: T(i, j) = tau_i (delta_ij - sum_{m > i} G(i, m) T(m, j)), i from
-// the bottom up.
-// G and T share Ts (the back substitution reads all of G before it writes).
-template <typename T, int RLO, bool TRANS>
-__device__ __forceinline__ void make_t(const T* Yt, T* Ts, const T* taus, int w, int pw, int lane,
-                                       int g, int c) {
-  __syncthreads();
-  const int gw = (w - pw + 4) & 3;
-  if (gw >= 1) {
-    const int it = gw == 3 ? 1 : 0, jt = gw == 1 ? 0 : 1;
-    v4<T> acc = v4zero<T>();
-#pragma unroll
-    for (int rt = RLO; rt < 8; ++rt) {
-      const v4<T> va = *reinterpret_cast<const v4<T>*>(Yt + (16 * it + c) * kLY + 16 * rt + 4 * g);
-      const v4<T> vb = *reinterpret_cast<const v4<T>*>(Yt + (16 * jt + c) * kLY + 16 * rt + 4 * g);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc = mfma4(va[r], vb[r], acc);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Ts[(16 * it + mma_row<T>(g, r)) * kLT + 16 * jt + c] = acc[r];
+// Zero the scalars and the Gram block before a panel: the compact-WY T reads
+// tau and G of all kBW vectors, and those past the panel's reflectors must be
+// zero.
+template <typename T>
+__device__ __forceinline__ void panel_clear(const PanelScal<T>& S, T* Gs, T (&msc)[2], int lane) {
+  if (lane < kBW) {
+    S.scale[lane] = T(0);
+    S.bet[lane] = T(0);
+    S.taus[lane] = T(0);
   }
-  __syncthreads();
-  if (gw == 1) {
-    // right-looking: once T(m, j) is known its multiples leave every row above
-    // (a dependency chain of kBW steps rather than of kBW^2 / 2 products)
-    const int j = lane & 31;
-    T t[kBW];
+  for (int o = lane; o < kBW * kLT; o += 64) Gs[o] = T(0);
+  msc[0] = msc[1] = T(0);
+  wave_lds_sync();
+}
+
+// The QL panel (columns of U' shifted so that the pivots are the last ku
+// positions, ku <= 32), columns jq = ku - 1 down to 0: the pivot of column jq
+// lies in tile 7 when jq >= ku - 16, else in tile 6.
+template <typename T>
+__device__ __forceinline__ void ql_panel(v4<T> (&X)[8][2], int ku, const PanelScal<T>& S, T* Gs,
+                                         T (&msc)[2], int g, int c, int lane, int* sing) {
+  const int a = max(16, ku - 16), b = max(ku - 16, 0);
+  for (int jq = ku - 1; jq >= a; --jq)
+    wave_step<T, true, 1, 7>(X, jq, kBP - ku + jq, S, Gs, msc, g, c, lane, sing);
+  for (int jq = min(ku, 16) - 1; jq >= b; --jq)
+    wave_step<T, true, 0, 7>(X, jq, kBP - ku + jq, S, Gs, msc, g, c, lane, sing);
+  for (int jq = min(b, 16) - 1; jq >= 0; --jq)
+    wave_step<T, true, 0, 6>(X, jq, kBP - ku + jq, S, Gs, msc, g, c, lane, sing);
+}
+
+// LQ panel P (rows 32 P + j of M, pivot position 32 P + j): the pivot lies in
+// tile 2 P + j / 16.
+template <typename T, int P>
+__device__ __forceinline__ void lq_panel(v4<T> (&X)[8][2], int cnt, const PanelScal<T>& S, T* Gs,
+                                         T (&msc)[2], int g, int c, int lane, int* sing) {
+  const int c0 = min(cnt, 16);
+  for (int j = 0; j < c0; ++j)
+    wave_step<T, false, 0, 2 * P>(X, j, 32 * P + j, S, Gs, msc, g, c, lane, sing);
+  for (int j = 16; j < cnt; ++j)
+    wave_step<T, false, 1, 2 * P + 1>(X, j, 32 * P + j, S, Gs, msc, g, c, lane, sing);
+}
+
+// After the panel: this lane's vector v (tile column ct) with pivot position
+// pp_v (refl: v holds a reflector).  Per element, dpos = position - pp_v.
+// Y (for the compact-WY update): scale x on the support, 1 at the pivot,
+// 0 elsewhere, vector-major in Yt.
+template <typename T, bool QL>
+__device__ __forceinline__ void panel_to_yt(const v4<T> (&X)[8][2], const PanelScal<T>& S, T* Yt,
+                                            int pp0, int nref, int g, int c) {
+  const int lp = lane_pos<T>(g);
 #pragma unroll
-    for (int i = 0; i < kBW; ++i) t[i] = i == j ? T(1) : T(0);
+  for (int ct = 0; ct < 2; ++ct) {
+    const int v = 16 * ct + c;
+    const bool refl = v < nref;
+    const T sc = S.scale[v];
+    const int d0 = lp - (pp0 + v);   // position - pp_v = tile_pos + d0
 #pragma unroll
-    for (int m = kBW - 1; m >= 0; --m) {
-      t[m] *= taus[m];
+    for (int rt = 0; rt < 8; ++rt) {
+      v4<T> y;
 #pragma unroll
-      for (int i = 0; i < m; ++i) t[i] -= Ts[i * kLT + m] * t[m];
-    }
-    if (lane < kBW) {
-#pragma unroll
-      for (int i = 0; i < kBW; ++i) {
-        if (TRANS) Ts[j * kLT + i] = t[i];
-        else Ts[i * kLT + j] = t[i];
+      for (int r = 0; r < 4; ++r) {
+        const int d = d0 + tile_pos<T>(rt, r);
+        const bool in = QL ? d < 0 : d > 0;
+        y[r] = !refl ? T(0) : (in ? X[rt][ct][r] * sc : (d == 0 ? T(1) : T(0)));
       }
+      lds_put_rows4(Yt + v * kLY + 16 * rt, g, y);
     }
   }
-  __syncthreads();
+}
+
+// T of the panel into Ts (TRANS: T^T) from its Gram block Gs (G(i, m) =
+// Y_i^T Y_m for i < m, gathered during the steps) and taus, by one wavefront,
+// lane j < 32 computing column j: T(i, j) = tau_i (delta_ij - sum_{m > i}
+// G(i, m) T(m, j)), i from the bottom up.
+template <typename T, bool TRANS>
+__device__ __forceinline__ void make_t(const T* Gs, T* Ts, const T* taus, int lane) {
+  // right-looking: once T(m, j) is known its multiples leave every row above
+  // (a dependency chain of kBW steps rather than of kBW^2 / 2 products)
+  const int j = lane & 31;
+  T t[kBW];
+#pragma unroll
+  for (int i = 0; i < kBW; ++i) t[i] = i == j ? T(1) : T(0);
+#pragma unroll
+  for (int m = kBW - 1; m >= 0; --m) {
+    t[m] *= taus[m];
+#pragma unroll
+    for (int i = 0; i < m; ++i) t[i] -= Gs[i * kLT + m] * t[m];
+  }
+  if (lane < kBW) {
+#pragma unroll
+    for (int i = 0; i < kBW; ++i) {
+      if (TRANS) Ts[j * kLT + i] = t[i];
+      else Ts[i * kLT + j] = t[i];
+    }
+  }
 }
 
 // X <- X - Y (Tm (Y^T X)) on this wavefront's slab (Y in Yt, Tm in Ts);
@@ -544,65 +521,94 @@ __device__ __forceinline__ void store_rows(const v4<T> (&X)[8][2], T* FD, int mp
   }
 }
 
-// Outputs of LQ panel P from the panel registers (every wavefront its
-// positions): rows i = 32 P + jv, jv < cnt, of FD (L left of the diagonal,
-// beta on it, the reflector to the right) and columns i of FZ (the reflector
-// with its unit and zeros above); when the panel holds rows >= e (the last
-// panel), those rows of FD as they are.
+// U~ and the QL reflectors from the panel wavefront's slab (vector v = column
+// v of U', position = row + s): the reflector above the pivot, beta on it,
+// U~ below, to FU.
 template <typename T>
-__device__ __forceinline__ void store_lq_panel(const Panel<T>& Pn, const PanelLds<T>& L, T* FD,
-                                               T* FZ, int mp, int e, int P, int cnt, bool last,
-                                               int w, int g, int c) {
+__device__ __forceinline__ void ql_panel_out(const v4<T> (&X)[8][2], const PanelScal<T>& S, T* FU,
+                                             int mp, int ku, int s, int g, int c) {
   constexpr uint32_t sz = sizeof(T);
-  const int base = 32 * w;
-  const auto RD = buf_rsrc(FD, (uint32_t)(mp * mp) * sz);
-  const auto RZ = buf_rsrc(FZ, (uint32_t)(mp * e) * sz);
-  const int dgc = 4 * g - c;   // column - row = dgc - th
+  const auto RU = buf_rsrc(FU, (uint32_t)(mp * ku) * sz);
+  const int lp = lane_pos<T>(g);
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
-    const int jv = 16 * ct + c, row = 32 * P + jv;
-    const bool refl = jv < cnt;
-    const bool wr = (row < mp) & (refl | last);
-    const T b = L.bet[jv];
-    const T* y = L.Yt + jv * kLY + base + 4 * g;
-    const uint32_t vd = wr ? (uint32_t)(row + (base + 4 * g) * mp) * sz : kBufOOB;
-    const uint32_t vz = refl ? (uint32_t)(base + 4 * g + row * mp) * sz : kBufOOB;
+    const int v = 16 * ct + c;
+    const bool refl = v < ku;
+    const T sc = S.scale[v], b = S.bet[v];
+    const int d0 = lp - (kBP - ku + v);   // position - pp_v = tile_pos + d0
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t vdr = vd + (uint32_t)(r * mp) * sz;
+    for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
-      for (int rl = 0; rl < 2; ++rl) {
-        const int th = su(32 * P + 16 * ct - base - 16 * rl - r);
-        const T yv = y[16 * rl + r];
-        const T x = Pn.t[rl][ct][r];
-        const T dv = refl ? (dgc < th ? x : (dgc == th ? b : yv)) : x;
-        const T zv = dgc > th ? yv : (dgc == th ? T(1) : T(0));
-        buf_store<T>(dv, RD, vdr, (uint32_t)(16 * rl * mp) * sz);
-        const bool cin = (mp >= kBP) | (4 * g < su(mp - base - 16 * rl - r));
-        buf_store<T>(zv, RZ, cin ? vz + (16 * rl + r) * sz : kBufOOB, 0);
+      for (int r = 0; r < 4; ++r) {
+        const int tp = tile_pos<T>(rt, r);
+        const int d = d0 + tp;
+        const T x = X[rt][ct][r];
+        const T val = d < 0 ? x * sc : (d == 0 ? b : x);
+        const int row = tp + lp - s;
+        const bool in = refl & (row >= 0);
+        buf_store<T>(val, RU, in ? (uint32_t)(row + v * mp) * sz : kBufOOB, 0);
       }
-    }
+  }
+}
+
+// Outputs of LQ panel P from wavefront P's slab (positions = columns of M,
+// vector v = row 32 P + v): rows 32 P + v, v < cnt, of FD (L left of the
+// diagonal, beta on it, the reflector to the right) and columns 32 P + v of
+// FZ (the reflector with its unit and zeros above); when the panel holds rows
+// >= e (the last panel), those rows of FD as they are.
+template <typename T>
+__device__ __forceinline__ void lq_panel_out(const v4<T> (&X)[8][2], const PanelScal<T>& S, T* FD,
+                                             T* FZ, int mp, int e, int P, int cnt, bool last,
+                                             int g, int c) {
+  constexpr uint32_t sz = sizeof(T);
+  const auto RD = buf_rsrc(FD, (uint32_t)(mp * mp) * sz);
+  const auto RZ = buf_rsrc(FZ, (uint32_t)(mp * e) * sz);
+  const int lp = lane_pos<T>(g);
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    const int v = 16 * ct + c, row = 32 * P + v;
+    const bool refl = v < cnt;
+    const bool wr = (row < mp) & (refl | last);
+    const T sc = S.scale[v], b = S.bet[v];
+    const int d0 = lp - row;   // position - pp_v = tile_pos + d0
+    const uint32_t vd = wr ? (uint32_t)(row + lp * mp) * sz : kBufOOB;
+    const uint32_t vz = refl ? (uint32_t)(lp + row * mp) * sz : kBufOOB;
+#pragma unroll
+    for (int rt = 0; rt < 8; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tp = tile_pos<T>(rt, r);
+        const int d = d0 + tp;
+        const T x = X[rt][ct][r];
+        const T dv = refl ? (d < 0 ? x : (d == 0 ? b : x * sc)) : x;
+        const T zv = d > 0 ? x * sc : (d == 0 ? T(1) : T(0));
+        buf_store<T>(dv, RD, vd, (uint32_t)(tp * mp) * sz);
+        const bool pin = lp < mp - tp;
+        buf_store<T>(zv, RZ, pin ? vz : kBufOOB, (uint32_t)tp * sz);
+      }
   }
 }
 
 // FP32: four waves per SIMD (128 registers); FP64: two (its accumulator
-// tiles and panel registers take twice the space).
+// tiles take twice the space).
 template <typename T, bool BATCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_ulv_factor_blk(
     KArgs<T, CallSV<T>> a) {
   __shared__ __attribute__((aligned(16))) T Yt[kBW * kLY];
   __shared__ __attribute__((aligned(16))) T Ts[kBW * kLT];
-  __shared__ __attribute__((aligned(16))) T red[2 * 4];
-  __shared__ __attribute__((aligned(16))) T dred[2 * 8 * kBW];
-  __shared__ T bet[kBW], taus[kBW];
+  __shared__ __attribute__((aligned(16))) T Gs[kBW * kLT];
+  __shared__ T scal[3 * kBW];
   __shared__ int sing;
-  const PanelLds<T> L{red, dred, Yt, bet, taus};
+  const PanelScal<T> S{scal, scal + kBW, scal + 2 * kBW};
   Inst<T> I; CallSV<T> C; int node;
   resolve<BATCH>(a, I, C, node);
   const NodeInfo nd = I.nodes[node];
   const int mp = nd.mp, ku = nd.ku, kv = nd.kv, e = nd.e;
   const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // the roles of the four wavefronts rotate with the work-group, so that the
+  // panel wavefronts of the work-groups sharing a compute unit are spread
+  // over its SIMDs
+  const int w = __builtin_amdgcn_readfirstlane(((tid >> 6) + (int)blockIdx.x) & 3);
   const int g = lane >> 4, c = lane & 15;
   const int s = kBP - mp;
   T* FU = I.FU + nd.oFU;
@@ -612,7 +618,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const T* Dsrc = nd.is_leaf ? I.D + nd.oD : FD;
   const T* Usrc = nd.is_leaf ? I.U + nd.oU : FU;
   const T* Vsrc = nd.is_leaf ? I.V + nd.oV : FV;
-  if (tid == 0) sing = 0;
   if (e == 0) {
     // nothing to eliminate: Q = Z = I, the generators pass through
     if (nd.is_leaf) {
@@ -623,39 +628,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     return;
   }
   v4<T> X[8][2];
-  Panel<T> Pn;
-  // ---- QL of U' (one panel over the four wavefronts) and M = Q^T D'
+  // ---- QL of U' (one panel, wavefront 0) and M = Q^T D'
   if (ku > 0) {
-    panel_load_cols(Pn, Usrc, mp, ku, s, w, g, c);
-    panel_clear(L, w, lane);
-    for (int jq = ku - 1; jq >= 0; --jq) panel_step<T, true>(Pn, jq, kBP - ku + jq, L, w, lane, g, c);
-    __syncthreads();
-    {
-      // finished columns: reflector above the pivot, beta, U~ below
-      constexpr uint32_t sz = sizeof(T);
-      const int base = 32 * w, dgc = 4 * g - c;   // position - pp = dgc - th
-      const auto RU = buf_rsrc(FU, (uint32_t)(mp * ku) * sz);
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        const int jv = 16 * ct + c;
-        const T b = bet[jv];
-        const T* y = Yt + jv * kLY + base + 4 * g;
-#pragma unroll
-        for (int rl = 0; rl < 2; ++rl)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int th = su(kBP - ku + 16 * ct - base - 16 * rl - r);
-            const T yv = y[16 * rl + r];
-            const T v = dgc < th ? yv : (dgc == th ? b : Pn.t[rl][ct][r]);
-            const int row = base + 16 * rl + 4 * g + r - s;
-            const bool in = (jv < ku) & (row >= 0);
-            buf_store<T>(v, RU, in ? (uint32_t)(row + jv * mp) * sz : kBufOOB, 0);
-          }
-      }
-      if (tid < ku) I.tq[nd.otq + tid] = taus[tid];
+    if (w == 0) {
+      slab_load_cols(X, Usrc, mp, mp, ku, s, 0, g, c);
+      T msc[2];
+      panel_clear(S, Gs, msc, lane);
+      ql_panel(X, ku, S, Gs, msc, g, c, lane, &sing);
+      wave_lds_sync();
+      panel_to_yt<T, true>(X, S, Yt, kBP - ku, ku, g, c);
+      ql_panel_out(X, S, FU, mp, ku, s, g, c);
+      if (lane < ku) I.tq[nd.otq + lane] = S.taus[lane];
+      slab_load_cols(X, Dsrc, mp, mp, mp, s, 0, g, c);
+      make_t<T, false>(Gs, Ts, S.taus, lane);
+    } else {
+      slab_load_cols(X, Dsrc, mp, mp, mp, s, 32 * w, g, c);
     }
-    slab_load_cols(X, Dsrc, mp, mp, mp, s, 32 * w, g, c);
-    make_t<T, 0, false>(Yt, Ts, taus, w, 0, lane, g, c);
+    __syncthreads();
     block_update<T, 0>(X, Yt, Ts, g, c);
     // M to FD (column slabs), then back as transposed row slabs
     slab_store_cols(X, FD, mp, mp, mp, s, 32 * w, g, c);
@@ -664,33 +653,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   } else {
     slab_load_rows(X, Dsrc, mp, mp, mp, 32 * w, g, c);
   }
-  // ---- LQ of rows 0 .. e-1 of M, panels of 32 rows: wavefront P's slab is
-  // spread over the four wavefronts by position (through Yt), factored, and
-  // applied to the slabs below it and to V' (wavefront 0 after panel 0).
+  // ---- LQ of rows 0 .. e-1 of M, panels of 32 rows: panel P is wavefront
+  // P's slab, factored by that wavefront and applied to the slabs below it
+  // and to V' (wavefront 0 after panel 0).  Wavefront P + 1 starts its panel
+  // as soon as its own slab has the update with panel P, while the others
+  // are still applying it.
   const int plast = (e - 1) >> 5;
 #define HSS_LQ_PANEL(P)                                                                     \
   if (P <= plast) {                                                                         \
     const int cnt = min(kBW, e - 32 * P);                                                   \
     if (w == P) {                                                                           \
-      _Pragma("unroll") for (int ct = 0; ct < 2; ++ct)                                      \
-        _Pragma("unroll") for (int rt = 0; rt < 8; ++rt)                                    \
-          lds_put_rows4(Yt + (16 * ct + c) * kLY + 16 * rt, g, X[rt][ct]);                 \
+      T msc[2];                                                                             \
+      if (P == 0 && lane == 0) sing = 0;                                                    \
+      panel_clear(S, Gs, msc, lane);                                                        \
+      lq_panel<T, P>(X, cnt, S, Gs, msc, g, c, lane, &sing);                                \
+    }                                                                                       \
+    __syncthreads();   /* the updates with the previous panel have read Yt and Ts */        \
+    if (w == P) {                                                                           \
+      panel_to_yt<T, false>(X, S, Yt, 32 * P, cnt, g, c);                                   \
+      lq_panel_out(X, S, FD, FZ, mp, e, P, cnt, P == plast, g, c);                          \
+      if (lane < cnt) I.tz[nd.otz + 32 * P + lane] = S.taus[lane];                          \
+      if (P == 0 && kv > 0) slab_load_cols(X, Vsrc, mp, mp, kv, 0, 0, g, c);                \
+      make_t<T, true>(Gs, Ts, S.taus, lane);                                                \
     }                                                                                       \
     __syncthreads();                                                                        \
-    panel_load_lds(Pn, Yt, w, g, c);                                                        \
-    panel_clear(L, w, lane);                                                                \
-    for (int j = 0; j < cnt; ++j) panel_step<T, false>(Pn, j, 32 * P + j, L, w, lane, g, c); \
-    __syncthreads();                                                                        \
-    store_lq_panel(Pn, L, FD, FZ, mp, e, P, cnt, P == plast, w, g, c);                      \
-    if (tid < cnt) I.tz[nd.otz + 32 * P + tid] = taus[tid];                                 \
-    if (tid == 0) {                                                                         \
-      for (int j = 0; j < cnt; ++j)                                                         \
-        if (bet[j] == T(0)) sing = 1;                                                       \
-    }                                                                                       \
-    if (P == 0 && w == 0 && kv > 0) slab_load_cols(X, Vsrc, mp, mp, kv, 0, 0, g, c);        \
-    make_t<T, 2 * P, true>(Yt, Ts, taus, w, 0, lane, g, c);                                 \
     if (w > P || (w == 0 && kv > 0)) block_update<T, 2 * P>(X, Yt, Ts, g, c);               \
-    __syncthreads();                                                                        \
   }
   HSS_LQ_PANEL(0)
   HSS_LQ_PANEL(1)
