@@ -5,7 +5,8 @@
 //   H_0 H_1 ... H_{b-1} = I - Y T Y^T,  T upper triangular with
 //   T^{-1} = diag(1 / tau) + strictly-upper(Y^T Y)
 // (the inverse of the usual column recurrence for T; T is obtained from it by
-// back substitution, so a zero tau gives a zero row and column of T).
+// back substitution, so a zero tau gives a zero row and column of T; the
+// entries of Y^T Y come out of the panel steps themselves).
 //   QL of U' (one panel: the ku columns), Q^T = H_0 ... H_{ku-1} applied as
 //   M = Q^T D' = D' - Y (T (Y^T D'));
 //   LQ of the leading e rows of M, panels of 32 rows; the rows below a panel
@@ -25,6 +26,10 @@
 //   (element (column, row - 32 q)), so that panel q is wavefront q's slab and
 //   the rows of a panel's pivots are tiles 2q and 2q + 1; after its panel,
 //   wavefront 0 holds V' (element (row, column)) in the same way.
+// A panel is factored by the one wavefront whose slab it is (U' is loaded as
+// wavefront 0's slab first), with no work-group barrier between its steps;
+// the other wavefronts load their slabs or apply the previous panel
+// meanwhile.
 // The QL-phase slabs reach the LQ layout through the node's FD block (written,
 // one barrier, read back transposed), which the kernel overwrites with the
 // final factor afterwards.
