@@ -557,14 +557,15 @@ __device__ __forceinline__ void ql_panel_out(const v4<T> (&X)[8][2], const Panel
 }
 
 // Outputs of LQ panel P from wavefront P's slab (positions = columns of M,
-// vector v = row 32 P + v): rows 32 P + v, v < cnt, of FD (L left of the
+// vector v = row 32 P + v; scv / bv: scale and beta of this lane's vectors
+// c and 16 + c): rows 32 P + v, v < cnt, of FD (L left of the
 // diagonal, beta on it, the reflector to the right) and columns 32 P + v of
 // FZ (the reflector with its unit and zeros above); when the panel holds rows
 // >= e (the last panel), those rows of FD as they are.
 template <typename T>
-__device__ __forceinline__ void lq_panel_out(const v4<T> (&X)[8][2], const PanelScal<T>& S, T* FD,
-                                             T* FZ, int mp, int e, int P, int cnt, bool last,
-                                             int g, int c) {
+__device__ __forceinline__ void lq_panel_out(const v4<T> (&X)[8][2], const T (&scv)[2],
+                                             const T (&bv)[2], T* FD, T* FZ, int mp, int e, int P,
+                                             int cnt, bool last, int g, int c) {
   constexpr uint32_t sz = sizeof(T);
   const auto RD = buf_rsrc(FD, (uint32_t)(mp * mp) * sz);
   const auto RZ = buf_rsrc(FZ, (uint32_t)(mp * e) * sz);
@@ -574,7 +575,7 @@ __device__ __forceinline__ void lq_panel_out(const v4<T> (&X)[8][2], const Panel
     const int v = 16 * ct + c, row = 32 * P + v;
     const bool refl = v < cnt;
     const bool wr = (row < mp) & (refl | last);
-    const T sc = S.scale[v], b = S.bet[v];
+    const T sc = scv[ct], b = bv[ct];
     const int d0 = lp - row;   // position - pp_v = tile_pos + d0
     const uint32_t vd = wr ? (uint32_t)(row + lp * mp) * sz : kBufOOB;
     const uint32_t vz = refl ? (uint32_t)(lp + row * mp) * sz : kBufOOB;
@@ -674,14 +675,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       lq_panel<T, P>(X, cnt, S, Gs, msc, g, c, lane, &sing);                                \
     }                                                                                       \
     __syncthreads();   /* the updates with the previous panel have read Yt and Ts */        \
+    /* the scalars the outputs need, read before the next panel may reuse them */          \
+    T scv[2], bv[2], tzv = T(0);                                                            \
+    if (w == ((P + 3) & 3)) make_t<T, true>(Gs, Ts, S.taus, lane);                          \
     if (w == P) {                                                                           \
       panel_to_yt<T, false>(X, S, Yt, 32 * P, cnt, g, c);                                   \
-      lq_panel_out(X, S, FD, FZ, mp, e, P, cnt, P == plast, g, c);                          \
-      if (lane < cnt) I.tz[nd.otz + 32 * P + lane] = S.taus[lane];                          \
-      if (P == 0 && kv > 0) slab_load_cols(X, Vsrc, mp, mp, kv, 0, 0, g, c);                \
-      make_t<T, true>(Gs, Ts, S.taus, lane);                                                \
+      scv[0] = S.scale[c];                                                                  \
+      scv[1] = S.scale[16 + c];                                                             \
+      bv[0] = S.bet[c];                                                                     \
+      bv[1] = S.bet[16 + c];                                                                \
+      tzv = S.taus[lane & 31];                                                              \
     }                                                                                       \
     __syncthreads();                                                                        \
+    if (w == P) {   /* outputs while the others apply the panel */                          \
+      lq_panel_out(X, scv, bv, FD, FZ, mp, e, P, cnt, P == plast, g, c);                    \
+      if (lane < cnt) I.tz[nd.otz + 32 * P + lane] = tzv;                                   \
+      if (P == 0 && kv > 0) slab_load_cols(X, Vsrc, mp, mp, kv, 0, 0, g, c);                \
+    }                                                                                       \
     if (w > P || (w == 0 && kv > 0)) block_update<T, 2 * P>(X, Yt, Ts, g, c);               \
   }
   HSS_LQ_PANEL(0)
