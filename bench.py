@@ -32,7 +32,8 @@ FP64_VEC_TFLOPS = 78.6
 # rocprofv3 runs (FETCH_SIZE, then WRITE_SIZE) at the headline size, each
 # scaled by what the counter reads for a plain device copy of known size
 # (x2.0 and x1.0); reported as the roofline line's "traffic".
-MEASURED_TRAFFIC = {"ulv_factor_leaf_f32": 835_566_341, "ulv_factor_leaf_f64": 1_592_086_440}
+# (empty until the counters are taken again for the current leaf factor)
+MEASURED_TRAFFIC = {}
 METRIC = "HSS solves/s & matmul GB/s, n=2^18 k=32; FP32+IR vs FP64 at 1e-10 bkwd err"
 
 
@@ -427,7 +428,7 @@ def bench_batch(args):
             w.copy_(b)
         hss.batch_factor(mats, prec)
         if prec == hss.F32:
-            return hss.batch_solve(mats, work, prec=hss.F32, tol=1e-10, max_refine=10)
+            return hss.batch_solve(mats, work, prec=hss.F32, tol=1e-10, max_refine=args.max_refine)
         return hss.batch_solve(mats, work, prec=hss.F64, want_eta=True)
 
     res = {}

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -578,23 +579,31 @@ struct StepList {
     bool all_op;     // every task's node has a forward operator
   };
   std::vector<Range> ranges;
-  template <typename Pred, typename Stage>
-  void add_step(hss_handle* const* hs, int count, Pred pred, Stage stage) {
+  // One step: for every instance, the nodes of tree levels lev(P) = {lo, hi}
+  // (a contiguous heap range; hi < lo: none), in instance then heap order.
+  template <typename Lev, typename Stage>
+  void add_step(hss_handle* const* hs, int count, Lev lev, Stage stage) {
     Range r{tasks.size(), 0, 0, 0, true};
     for (int j = 0; j < count; ++j) {
       const Plan& P = hs[j]->plan;
-      for (int t = 0; t < P.nnodes; ++t)
-        if (pred(j, P, t)) {
-          tasks.push_back(make_int2(j, t));
-          r.max_mp = std::max(r.max_mp, P.nodes[t].mp);
-          r.stage = std::max<int64_t>(r.stage, stage(P, t));
-          r.all_op = r.all_op && P.nodes[t].oOP >= 0;
-          ++r.cnt;
-        }
+      const std::pair<int, int> lh = lev(P);
+      if (lh.second < lh.first) continue;
+      const int t1 = (2 << lh.second) - 1;
+      for (int t = (1 << lh.first) - 1; t < t1; ++t) {
+        tasks.push_back(make_int2(j, t));
+        r.max_mp = std::max(r.max_mp, P.nodes[t].mp);
+        r.stage = std::max<int64_t>(r.stage, stage(P, t));
+        r.all_op = r.all_op && P.nodes[t].oOP >= 0;
+        ++r.cnt;
+      }
     }
     ranges.push_back(r);
   }
 };
+
+// Level ranges of the batched steps.
+inline std::pair<int, int> lv_one(int l) { return {l, l}; }
+inline std::pair<int, int> lv_none() { return {1, 0}; }
 
 int max_depth(hss_handle* const* hs, int count) {
   int mp = 0;
@@ -602,67 +611,126 @@ int max_depth(hss_handle* const* hs, int count) {
   return mp;
 }
 
+// The instance records and per-level task lists of a batched product (op N)
+// or solve sweep, uploaded once; runs differ only in their calls (right-hand
+// sides, gating), a small table of their own.
+template <typename T>
+struct BatchPlan {
+  StepList L;
+  const Inst<T>* insts = nullptr;   // device
+  const int2* tasks = nullptr;      // device
+  int pmax = 0, mku = 0, mk = 0;
+  int64_t root_bytes = 0, child_bytes = 0;
+};
+
+template <typename C>
+hss_status upload_calls(BatchScratch& BS, const std::vector<C>& calls, hipStream_t s,
+                        const C** out) {
+  std::vector<char> bytes(sizeof(C) * calls.size());
+  if (!calls.empty()) std::memcpy(bytes.data(), calls.data(), bytes.size());
+  void* d = nullptr;
+  hss_status st = scratch_upload(BS, bytes, s, &d);
+  *out = reinterpret_cast<const C*>(d);
+  return st;
+}
+
+template <typename T>
+hss_status plan_upload(BatchScratch& BS, const std::vector<Inst<T>>& insts, BatchPlan<T>& bp,
+                       hipStream_t s) {
+  Packer pk;
+  const size_t oi = pk.add(insts), ot = pk.add(bp.L.tasks);
+  void* d = nullptr;
+  hss_status st = scratch_upload(BS, pk.buf, s, &d);
+  if (st) return st;
+  bp.insts = reinterpret_cast<const Inst<T>*>((char*)d + oi);
+  bp.tasks = reinterpret_cast<const int2*>((char*)d + ot);
+  return HSS_OK;
+}
+
+// op N product: up (subtree roots), down (subtree roots), leaf outputs.
+template <typename T>
+hss_status plan_mm_n(BatchScratch& BS, hss_handle* const* hs, int count, const int64_t* nrhs,
+                     hipStream_t s, BatchPlan<T>& bp) {
+  std::vector<Inst<T>> insts(count);
+  for (int j = 0; j < count; ++j) {
+    hss_status st = ensure_work_mm<T>(hs[j], std::max<int64_t>(nrhs[j], 1));
+    if (st) return st;
+    insts[j] = make_inst<T>(hs[j], kUseMM);
+    bp.mku = std::max(bp.mku, hs[j]->plan.leaf_max_ku);
+    bp.mk = std::max(bp.mk, hs[j]->plan.max_k);
+  }
+  bp.pmax = max_depth(hs, count);
+  auto none = [](const Plan&, int) -> int64_t { return 0; };
+  const int dh = mmf_down_height(), uh = mmf_up_height();
+  bp.L.add_step(hs, count, [&](const Plan& P) {
+    return P.p > 0 ? lv_one(std::max(P.p - uh, 0)) : lv_none(); }, none);   // up: subtree roots
+  bp.L.add_step(hs, count, [&](const Plan& P) {
+    return P.p > 0 ? lv_one(std::max(P.p - dh, 0)) : lv_none(); }, none);   // down: subtree roots
+  bp.L.add_step(hs, count, [&](const Plan& P) { return lv_one(P.p); }, none);  // leaf outputs
+  return plan_upload(BS, insts, bp, s);
+}
+
+template <typename T>
+hss_status run_mm_n(BatchScratch& BS, const BatchPlan<T>& bp, hss_handle* const* hs, int count,
+                    const int64_t* nrhs, const void* const* X, const int64_t* ldx,
+                    void* const* Y, const int64_t* ldy, hipStream_t s, bool gated) {
+  std::vector<CallMM<T>> calls(count);
+  int64_t maxr = 0;
+  for (int j = 0; j < count; ++j) {
+    calls[j] = CallMM<T>{(const T*)X[j], (T*)Y[j], ldx[j], ldy[j], (int32_t)nrhs[j], HSS_OP_N,
+                         gated ? hs[j]->d_status + kStGate : nullptr};
+    maxr = std::max(maxr, nrhs[j]);
+  }
+  if (maxr == 0) return HSS_OK;
+  KArgs<T, CallMM<T>> a{};
+  hss_status st = upload_calls(BS, calls, s, &a.calls);
+  if (st) return st;
+  a.insts = bp.insts;
+  const MMFStep steps[3] = {MMFStep::Up, MMFStep::Down, MMFStep::Leaf};
+  for (int q = 0; q < 3; ++q) {
+    const auto& r = bp.L.ranges[q];
+    a.tasks = bp.tasks + r.off;
+    a.ntasks = r.cnt;
+    launch_mmf<T>(steps[q], a, r.cnt, (int)maxr, bp.mku, bp.mk, s);
+  }
+  return last_launch_status();
+}
+
 template <typename T>
 hss_status batch_matmul_impl(BatchScratch& BS, hss_handle* const* hs, int count, int op,
                              const int64_t* nrhs,
                              const void* const* X, const int64_t* ldx, void* const* Y,
-                             const int64_t* ldy, hipStream_t s, bool gated = false) {
+                             const int64_t* ldy, hipStream_t s) {
   int64_t maxr = 0;
+  for (int j = 0; j < count; ++j) maxr = std::max(maxr, nrhs[j]);
+  if (maxr == 0) return HSS_OK;
+  if (op == HSS_OP_N) {
+    BatchPlan<T> bp;
+    hss_status st = plan_mm_n<T>(BS, hs, count, nrhs, s, bp);
+    if (st) return st;
+    return run_mm_n<T>(BS, bp, hs, count, nrhs, X, ldx, Y, ldy, s, false);
+  }
   std::vector<Inst<T>> insts(count);
   std::vector<CallMM<T>> calls(count);
   for (int j = 0; j < count; ++j) {
     hss_status st = ensure_work_mm<T>(hs[j], std::max<int64_t>(nrhs[j], 1));
     if (st) return st;
     insts[j] = make_inst<T>(hs[j], kUseMM);
-    calls[j] = CallMM<T>{(const T*)X[j], (T*)Y[j], ldx[j], ldy[j], (int32_t)nrhs[j], op,
-                         gated ? hs[j]->d_status + kStGate : nullptr};
-    maxr = std::max(maxr, nrhs[j]);
+    calls[j] = CallMM<T>{(const T*)X[j], (T*)Y[j], ldx[j], ldy[j], (int32_t)nrhs[j], op, nullptr};
   }
-  if (maxr == 0) return HSS_OK;
   const int pmax = max_depth(hs, count);
   StepList L;
   auto none = [](const Plan&, int) -> int64_t { return 0; };
-  auto lvl = [](const Plan& P, int t) { return P.nodes[t].level; };
-  if (op == HSS_OP_N) {
-    const int dh = mmf_down_height(), uh = mmf_up_height();
-    L.add_step(hs, count, [&](int, const Plan& P, int t) {
-      return P.p > 0 && lvl(P, t) == std::max(P.p - uh, 0); }, none);   // up: subtree roots
-    L.add_step(hs, count, [&](int, const Plan& P, int t) {
-      return P.p > 0 && lvl(P, t) == std::max(P.p - dh, 0); }, none);   // down: subtree roots
-    L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.nodes[t].is_leaf != 0; },
-               none);                                                    // leaf outputs
-    Packer pk;
-    const size_t oi = pk.add(insts), oc = pk.add(calls), ot = pk.add(L.tasks);
-    void* d = nullptr;
-    hss_status st = scratch_upload(BS, pk.buf, s, &d);
-    if (st) return st;
-    KArgs<T, CallMM<T>> a{};
-    a.insts = reinterpret_cast<const Inst<T>*>((char*)d + oi);
-    a.calls = reinterpret_cast<const CallMM<T>*>((char*)d + oc);
-    const MMFStep steps[3] = {MMFStep::Up, MMFStep::Down, MMFStep::Leaf};
-    int mku = 0, mk = 0;
-    for (int j = 0; j < count; ++j) {
-      mku = std::max(mku, hs[j]->plan.leaf_max_ku);
-      mk = std::max(mk, hs[j]->plan.max_k);
-    }
-    for (int q = 0; q < 3; ++q) {
-      const auto& r = L.ranges[q];
-      a.tasks = reinterpret_cast<const int2*>((char*)d + ot) + r.off;
-      a.ntasks = r.cnt;
-      launch_mmf<T>(steps[q], a, r.cnt, (int)maxr, mku, mk, s);
-    }
-    return last_launch_status();
-  }
-  L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
+  L.add_step(hs, count, [&](const Plan& P) { return P.p > 0 ? lv_one(P.p) : lv_none(); },
              none);                                                      // 0: leaf up
   for (int st = 1; st <= pmax - 1; ++st)                                 // 1..: up
-    L.add_step(hs, count, [&](int, const Plan& P, int t) {
-      return lvl(P, t) == P.p - st && lvl(P, t) >= 1; }, none);
-  L.add_step(hs, count, [&](int, const Plan& P, int t) { return !P.nodes[t].is_leaf; }, none);
+    L.add_step(hs, count, [&](const Plan& P) {
+      return P.p - st >= 1 ? lv_one(P.p - st) : lv_none(); }, none);
+  L.add_step(hs, count, [&](const Plan& P) { return std::make_pair(0, P.p - 1); }, none);
   for (int st = 1; st <= pmax - 1; ++st)
-    L.add_step(hs, count, [&](int, const Plan& P, int t) {
-      return lvl(P, t) == st && st <= P.p - 1; }, none);
-  L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.nodes[t].is_leaf != 0; }, none);
+    L.add_step(hs, count, [&](const Plan& P) {
+      return st <= P.p - 1 ? lv_one(st) : lv_none(); }, none);
+  L.add_step(hs, count, [&](const Plan& P) { return lv_one(P.p); }, none);
   Packer pk;
   const size_t oi = pk.add(insts), oc = pk.add(calls), ot = pk.add(L.tasks);
   void* d = nullptr;
@@ -696,18 +764,6 @@ hss_status batch_matmul(hss_handle* const* hs, int count, int op, const int64_t*
   return batch_matmul_impl<T>(B, hs, count, op, nrhs, X, ldx, Y, ldy, s);
 }
 
-// FP64 A X for the refinement residuals (the caller holds the scratch lock);
-// gated: instances whose refinement gate is 0 are skipped.
-hss_status batch_matmul_unlocked(BatchScratch& BS, hss_handle* const* hs, int count,
-                                 const int64_t* nrhs, double* const* X, const int64_t* ldx,
-                                 double* const* Y, const int64_t* ldy, hipStream_t s,
-                                 bool gated) {
-  std::vector<const void*> xv(X, X + count);
-  std::vector<void*> yv(Y, Y + count);
-  return batch_matmul_impl<double>(BS, hs, count, HSS_OP_N, nrhs, xv.data(), ldx, yv.data(), ldy,
-                                   s, gated);
-}
-
 template <typename T>
 hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
   BatchScratch& BS = scratch_for(s);
@@ -721,14 +777,13 @@ hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
   const int pmax = max_depth(hs, count);
   StepList L;
   auto none = [](const Plan&, int) -> int64_t { return 0; };
-  auto lvl = [](const Plan& P, int t) { return P.nodes[t].level; };
-  L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
+  L.add_step(hs, count, [&](const Plan& P) { return P.p > 0 ? lv_one(P.p) : lv_none(); },
              none);
   for (int st = 1; st <= pmax - 1; ++st)
-    L.add_step(hs, count, [&](int, const Plan& P, int t) {
-      return lvl(P, t) == P.p - st && lvl(P, t) >= 1; }, none);
-  L.add_step(hs, count, [&](int, const Plan& P, int t) { return t == 0 && P.p > 0; }, none);
-  L.add_step(hs, count, [&](int, const Plan&, int t) { return t == 0; }, none);
+    L.add_step(hs, count, [&](const Plan& P) {
+      return P.p - st >= 1 ? lv_one(P.p - st) : lv_none(); }, none);
+  L.add_step(hs, count, [&](const Plan& P) { return P.p > 0 ? lv_one(0) : lv_none(); }, none);
+  L.add_step(hs, count, [&](const Plan&) { return lv_one(0); }, none);
   Packer pk;
   const size_t oi = pk.add(insts), ot = pk.add(L.tasks);
   void* d = nullptr;
@@ -770,56 +825,62 @@ hss_status batch_factor(hss_handle* const* hs, int count, hipStream_t s) {
   return last_launch_status();
 }
 
-// One batched solve sweep (forward, root, backward) on per-instance
-// right-hand sides rhs[j] (precision T, leading dimension ld[j]).
+// Batched solve sweep (forward, root, backward): plan once, run on
+// per-instance right-hand sides rhs[j] (precision T, leading dimension ld[j]).
 template <typename T>
-hss_status batch_sweep(BatchScratch& BS, hss_handle* const* hs, int count, const int64_t* nrhs,
-                       T* const* rhs, const int64_t* ld, hipStream_t s, bool gated = false) {
+hss_status plan_sweep(BatchScratch& BS, hss_handle* const* hs, int count, const int64_t* nrhs,
+                      hipStream_t s, BatchPlan<T>& bp) {
   std::vector<Inst<T>> insts(count);
-  std::vector<CallSV<T>> calls(count);
-  int64_t maxr = 0;
   for (int j = 0; j < count; ++j) {
     hss_status st = ensure_work_sv<T>(hs[j], std::max<int64_t>(nrhs[j], 1));
     if (st) return st;
     insts[j] = make_inst<T>(hs[j], kUseSV);
+  }
+  const int pmax = bp.pmax = max_depth(hs, count);
+  StepList& L = bp.L;
+  auto fst = [](const Plan& P, int t) { return P.level_fwd_stage[P.nodes[t].level]; };
+  auto bst = [](const Plan& P, int t) { return P.level_bwd_stage[P.nodes[t].level]; };
+  auto none = [](const Plan&, int) -> int64_t { return 0; };
+  L.add_step(hs, count, [&](const Plan& P) { return P.p > 0 ? lv_one(P.p) : lv_none(); },
+             none);
+  for (int st = 1; st <= pmax - 1; ++st)
+    L.add_step(hs, count, [&](const Plan& P) {
+      return P.p - st >= 1 ? lv_one(P.p - st) : lv_none(); }, fst);
+  L.add_step(hs, count, [&](const Plan&) { return lv_one(0); }, fst);
+  for (int st = 1; st <= pmax - 1; ++st)
+    L.add_step(hs, count, [&](const Plan& P) {
+      return st <= P.p - 1 ? lv_one(st) : lv_none(); }, bst);
+  L.add_step(hs, count, [&](const Plan& P) { return P.p > 0 ? lv_one(P.p) : lv_none(); },
+             none);
+  // root staging: FP64 LU + pivots (+ children when everything fits)
+  for (int j = 0; j < count; ++j) {
+    const Plan& P = hs[j]->plan;
+    const int64_t mpr = P.nodes[0].mp;
+    bp.root_bytes = std::max(bp.root_bytes, mpr * mpr * 8 + 4 * ((mpr + 3) & ~int64_t(3)));
+    if (P.p > 0)
+      bp.child_bytes = std::max(bp.child_bytes, P.level_fwd_stage[0] * (int64_t)sizeof(T));
+  }
+  return plan_upload(BS, insts, bp, s);
+}
+
+template <typename T>
+hss_status run_sweep(BatchScratch& BS, const BatchPlan<T>& bp, hss_handle* const* hs, int count,
+                     const int64_t* nrhs, T* const* rhs, const int64_t* ld, hipStream_t s,
+                     bool gated) {
+  std::vector<CallSV<T>> calls(count);
+  int64_t maxr = 0;
+  for (int j = 0; j < count; ++j) {
     calls[j] = CallSV<T>{rhs[j], ld[j], (int32_t)nrhs[j], 0,
                          gated ? hs[j]->d_status + kStGate : nullptr};
     maxr = std::max(maxr, nrhs[j]);
   }
   if (maxr == 0) return HSS_OK;
-  const int pmax = max_depth(hs, count);
-  StepList L;
-  auto lvl = [](const Plan& P, int t) { return P.nodes[t].level; };
-  auto fst = [](const Plan& P, int t) { return P.level_fwd_stage[P.nodes[t].level]; };
-  auto bst = [](const Plan& P, int t) { return P.level_bwd_stage[P.nodes[t].level]; };
-  auto none = [](const Plan&, int) -> int64_t { return 0; };
-  L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
-             none);
-  for (int st = 1; st <= pmax - 1; ++st)
-    L.add_step(hs, count, [&](int, const Plan& P, int t) {
-      return lvl(P, t) == P.p - st && lvl(P, t) >= 1; }, fst);
-  L.add_step(hs, count, [&](int, const Plan&, int t) { return t == 0; }, fst);
-  for (int st = 1; st <= pmax - 1; ++st)
-    L.add_step(hs, count, [&](int, const Plan& P, int t) {
-      return lvl(P, t) == st && st <= P.p - 1; }, bst);
-  L.add_step(hs, count, [&](int, const Plan& P, int t) { return P.p > 0 && lvl(P, t) == P.p; },
-             none);
-  // root staging: FP64 LU + pivots (+ children when everything fits)
-  int64_t root_bytes = 0, child_bytes = 0;
-  for (int j = 0; j < count; ++j) {
-    const Plan& P = hs[j]->plan;
-    const int64_t mpr = P.nodes[0].mp;
-    root_bytes = std::max(root_bytes, mpr * mpr * 8 + 4 * ((mpr + 3) & ~int64_t(3)));
-    if (P.p > 0) child_bytes = std::max(child_bytes, P.level_fwd_stage[0] * (int64_t)sizeof(T));
-  }
-  Packer pk;
-  const size_t oi = pk.add(insts), oc = pk.add(calls), ot = pk.add(L.tasks);
-  void* d = nullptr;
-  hss_status st = scratch_upload(BS, pk.buf, s, &d);
-  if (st) return st;
   KArgs<T, CallSV<T>> a{};
-  a.insts = reinterpret_cast<const Inst<T>*>((char*)d + oi);
-  a.calls = reinterpret_cast<const CallSV<T>*>((char*)d + oc);
+  hss_status st = upload_calls(BS, calls, s, &a.calls);
+  if (st) return st;
+  a.insts = bp.insts;
+  const StepList& L = bp.L;
+  const int pmax = bp.pmax;
   const int nc = (int)maxr;
   size_t k = 0;
   auto staged = [&](int64_t e) -> int64_t {
@@ -827,7 +888,7 @@ hss_status batch_sweep(BatchScratch& BS, hss_handle* const* hs, int count, const
   };
   auto go = [&](UlvStep stp, bool use_stage) {
     const auto& r = L.ranges[k++];
-    a.tasks = reinterpret_cast<const int2*>((char*)d + ot) + r.off;
+    a.tasks = bp.tasks + r.off;
     a.ntasks = r.cnt;
     launch_solve_w<T>(stp, a, r.cnt, nc, use_stage ? staged(r.stage) : 0, s);
   };
@@ -838,12 +899,12 @@ hss_status batch_sweep(BatchScratch& BS, hss_handle* const* hs, int count, const
   }
   {
     const auto& r = L.ranges[k++];
-    a.tasks = reinterpret_cast<const int2*>((char*)d + ot) + r.off;
+    a.tasks = bp.tasks + r.off;
     a.ntasks = r.cnt;
-    int64_t rb = root_bytes;
+    int64_t rb = bp.root_bytes;
     a.flags = 0;
-    if (root_bytes + child_bytes <= 160 * 1024) {
-      rb += child_bytes;
+    if (bp.root_bytes + bp.child_bytes <= 160 * 1024) {
+      rb += bp.child_bytes;
       a.flags = 1;
     }
     launch_solve_w<T>(UlvStep::Root, a, r.cnt, nc, (rb + sizeof(T) - 1) / sizeof(T), s);
@@ -881,7 +942,17 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
     d64[j] = h->d64;
     res[j] = h->res;
   }
-  // the refinement descriptors are a table of their own
+  // every table before any launch: the sweep's and the residual product's
+  // records and task lists (built once, whatever the number of steps), then
+  // the refinement descriptors
+  BatchPlan<double> sv64, mm;
+  BatchPlan<float> sv32;
+  if (is64) {
+    if ((st = plan_sweep<double>(BS, hs, count, nrhs, s, sv64))) return st;
+  } else {
+    if ((st = plan_sweep<float>(BS, hs, count, nrhs, s, sv32))) return st;
+  }
+  if (need_eta && (st = plan_mm_n<double>(BS, hs, count, nrhs, s, mm))) return st;
   std::vector<char> segbytes(sizeof(IRSeg) * count);
   std::memcpy(segbytes.data(), segs.data(), segbytes.size());
   void* dsegp = nullptr;
@@ -896,9 +967,9 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
   auto correction = [&](bool first) -> hss_status {
     hss_status e;
     if (is64) {
-      if (first) return batch_sweep<double>(BS, hs, count, nrhs, Bv.data(), ldb, s);
+      if (first) return run_sweep<double>(BS, sv64, hs, count, nrhs, Bv.data(), ldb, s, false);
       ir(IR_COPY_RES, true);
-      if ((e = batch_sweep<double>(BS, hs, count, nrhs, d64.data(), n_ld.data(), s, true)))
+      if ((e = run_sweep<double>(BS, sv64, hs, count, nrhs, d64.data(), n_ld.data(), s, true)))
         return e;
       ir(IR_AXPY64, true);
       return HSS_OK;
@@ -909,7 +980,7 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
     } else {
       ir(IR_SCALE_RES, true);
     }
-    if ((e = batch_sweep<float>(BS, hs, count, nrhs, r32.data(), n_ld.data(), s, !first)))
+    if ((e = run_sweep<float>(BS, sv32, hs, count, nrhs, r32.data(), n_ld.data(), s, !first)))
       return e;
     ir(first ? IR_CAST_BACK : IR_AXPY_CAST, !first);
     return HSS_OK;
@@ -917,8 +988,10 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
   auto check = [&](int k) -> hss_status {
     const bool gated = k > 0;
     hss_status e;
-    if ((e = batch_matmul_unlocked(BS, hs, count, nrhs, Bv.data(), ldb, res.data(), n_ld.data(),
-                                   s, gated)))
+    std::vector<const void*> xv(Bv.begin(), Bv.end());
+    std::vector<void*> yv(res.begin(), res.end());
+    if ((e = run_mm_n<double>(BS, mm, hs, count, nrhs, xv.data(), ldb, yv.data(), n_ld.data(), s,
+                              gated)))
       return e;
     ir(IR_ZERO, gated);
     ir(IR_RESID, gated);

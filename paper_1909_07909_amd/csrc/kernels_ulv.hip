@@ -901,6 +901,86 @@ __global__ __launch_bounds__(kNT) void k_ulv_root_lu2(KArgs<T, CallSV<T>> a) {
   for (int o = tid; o < mp * mp; o += kNT) I.rootLU[o] = Ls[o % mp + (o / mp) * ld];
 }
 
+// FP64 LU with partial pivoting of a root block of at most 64 rows by one
+// wavefront, the block in registers: lane i holds row i (64 doubles).  Rows
+// are not moved: step j picks the largest |A(i, j)| among the rows not yet
+// chosen (the first lane on ties), every other open row takes its multiplier
+// and subtracts it times the pivot row (read lane by lane from the pivot's
+// registers), and the pivot row is closed.  Row i, closed at step s_i, holds
+// its multipliers left of column s_i and its U row from there on, so writing
+// it to row s_i of the output gives the in-place L U of the permuted block;
+// the sequence of row interchanges (LAPACK's convention, as the solve reads
+// it) is reconstructed at the end from the order in which rows were chosen.
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(64) void k_ulv_root_lu_w(KArgs<T, CallSV<T>> a) {
+  Inst<T> I; CallSV<T> C; int node;
+  resolve<BATCH>(a, I, C, node);
+  const NodeInfo nd = I.nodes[node];
+  const int mp = nd.mp;
+  const int lane = threadIdx.x;
+  const T* src = I.p == 0 ? I.D + nd.oD : I.FD + nd.oFD;
+  const bool row_ok = lane < mp;
+  double A[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    const bool ok = row_ok & (c < mp);
+    A[c] = ok ? (double)src[(ok ? lane : 0) + (int64_t)(ok ? c : 0) * mp] : 0.0;
+  }
+  bool open = row_ok;
+  int rank = lane;   // the step that closes this row (rows >= mp: themselves)
+  int chosen = 0;    // lane j: the row chosen at step j
+  bool sing = false;
+#pragma unroll
+  for (int j = 0; j < 64; ++j) {
+    if (j < mp) {
+    const double v = open ? fabs(A[j]) : -1.0;
+    const double mx = wave_max(v);
+    const uint64_t hit = __ballot(open && v == mx);
+    const uint64_t avail = __ballot(open);
+    int p = (int)__builtin_ctzll(hit ? hit : avail);
+    p = __builtin_amdgcn_readfirstlane(p);
+    if (!(mx > 0.0)) sing = true;
+    const double pv = lane_read(A[j], p);
+    const double dinv = mx > 0.0 ? 1.0 / pv : 0.0;
+    const bool elim = open && lane != p;
+    const double l = elim ? A[j] * dinv : 0.0;
+    if (elim) A[j] = l;
+#pragma unroll
+    for (int c = j + 1; c < 64; ++c) A[c] -= l * lane_read(A[c], p);   // zero past mp
+    if (lane == p) {
+      open = false;
+      rank = j;
+    }
+    if (lane == j) chosen = p;
+    }
+  }
+  // row i of the output is the row closed at step i
+  double* LU = I.rootLU;
+  if (row_ok) {
+#pragma unroll
+    for (int c = 0; c < 64; ++c)
+      if (c < mp) LU[rank + (int64_t)c * mp] = A[c];   // (uniform)
+  }
+  // interchanges: position j takes the row chosen at step j from wherever the
+  // earlier interchanges left it (cur: row at each position, at: position of
+  // each row, one entry per lane)
+  int cur = lane, at = lane;
+  for (int j = 0; j < mp; ++j) {
+    const int r = __builtin_amdgcn_readlane(chosen, j);
+    const int q = __builtin_amdgcn_readlane(at, r);
+    const int rj = __builtin_amdgcn_readlane(cur, j);
+    if (lane == j) I.piv[j] = q;
+    if (lane == j) cur = r;
+    if (lane == q) cur = rj;
+    if (lane == r) at = j;
+    if (lane == rj) at = q;
+  }
+  if (lane == 0 && sing) {
+    atomicOr(I.status, 1 << kCodeSingular);
+    atomicMax(I.status + kStSingularNode, node + 1);
+  }
+}
+
 // ---------------------------------------------------------------------------
 template <typename T>
 void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max_k, int max_mp,
@@ -956,7 +1036,11 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max
       else launch_factor_reg<T>(a, nblocks, max_mp, s);
       break;
     case UlvStep::RootLU:
-      if (max_mp <= 128) { HSS_LAUNCH(k_ulv_root_lu2); }
+      if (max_mp <= 64) {
+        block = dim3(64);
+        sm = 0;
+        HSS_LAUNCH(k_ulv_root_lu_w);
+      } else if (max_mp <= 128) { HSS_LAUNCH(k_ulv_root_lu2); }
       else { HSS_LAUNCH(k_ulv_root_lu); }
       break;
     default: break;
