@@ -151,12 +151,19 @@ hss_status ensure_factors(hss_handle* h) {
 
 // Work buffers grow to the widest call so far.  The buffers they replace are
 // not freed before hss_destroy: a HIP graph captured from an earlier call
-// still holds their addresses.
+// still holds their addresses.  Growth is geometric (at least doubling, in
+// multiples of 8 columns), so the retired buffers never add up to more than
+// the live ones.
+int64_t grown_cap(int64_t old_cap, int64_t nrhs, int64_t min_cap) {
+  const int64_t want = std::max<int64_t>((nrhs + 7) / 8 * 8, min_cap);
+  return old_cap > 0 ? std::max<int64_t>(want, 2 * old_cap) : want;
+}
+
 template <typename T>
 hss_status ensure_work_mm(hss_handle* h, int64_t nrhs) {
   Work<T>& w = work<T>(h);
-  const int64_t cap = std::max<int64_t>(nrhs, kRT);
   if (w.cap_mm >= nrhs && w.xh) return HSS_OK;
+  const int64_t cap = grown_cap(w.xh ? w.cap_mm : 0, nrhs, kRT);
   w.xh = dalloc<T>(h, h->plan.ldm * cap);
   w.yh = dalloc<T>(h, h->plan.ldm * cap);
   w.cap_mm = (w.xh && w.yh) ? cap : 0;
@@ -166,8 +173,8 @@ hss_status ensure_work_mm(hss_handle* h, int64_t nrhs) {
 template <typename T>
 hss_status ensure_work_sv(hss_handle* h, int64_t nrhs) {
   Work<T>& w = work<T>(h);
-  const int64_t cap = std::max<int64_t>(nrhs, kRT);
   if (w.cap_sv >= nrhs && w.wc) return HSS_OK;
+  const int64_t cap = grown_cap(w.wc ? w.cap_sv : 0, nrhs, kRT);
   const int64_t sz = h->plan.lds * cap;
   w.wc = dalloc<T>(h, sz);
   w.wz = dalloc<T>(h, sz);
@@ -178,8 +185,9 @@ hss_status ensure_work_sv(hss_handle* h, int64_t nrhs) {
 }
 
 hss_status ensure_ir(hss_handle* h, int64_t nrhs) {
-  const int64_t cap = std::max<int64_t>(nrhs, 1);
-  if (h->cap_ir < cap || !h->b0) {
+  nrhs = std::max<int64_t>(nrhs, 1);
+  if (h->cap_ir < nrhs || !h->b0) {
+    const int64_t cap = grown_cap(h->b0 ? h->cap_ir : 0, nrhs, 1);
     const int64_t n = h->plan.n;
     h->b0 = dalloc<double>(h, n * cap);
     h->res = dalloc<double>(h, n * cap);
@@ -188,7 +196,8 @@ hss_status ensure_ir(hss_handle* h, int64_t nrhs) {
     h->cap_ir = (h->b0 && h->res && h->d64 && h->r32) ? cap : 0;
     if (!h->cap_ir) return HSS_ENOMEM;
   }
-  if (h->cap_stats < cap || !h->stats) {
+  if (h->cap_stats < nrhs || !h->stats) {
+    const int64_t cap = grown_cap(h->stats ? h->cap_stats : 0, nrhs, 1);
     h->stats = dalloc<double>(h, 8 * cap + 8);
     h->part = dalloc<double>(h, check_partials(cap));
     h->cap_stats = (h->stats && h->part) ? cap : 0;

@@ -310,7 +310,21 @@ class Server:
                     self.phase_s["solve"] += t2 - t1
                     self.phase_s["stage_out"] += t3 - t2
 
+    def reserve_work(self):
+        """Grow every matrix's work buffers to the widest group a round can
+        give it (max_cols_per_group columns, refined FP32 solve) before
+        requests arrive, so that rounds never allocate or retire them."""
+        from . import hss
+        torch = self.torch
+        for m in self.mats:
+            B = hss.empty_colmajor(m.n, self.max_cols, torch.float64)
+            B.fill_(1.0)
+            m.solve(B, prec=hss.F32, tol=1e-10, max_refine=1, check=False)
+            del B
+        torch.cuda.synchronize()
+
     def start(self):
+        self.reserve_work()
         self.threads = [threading.Thread(target=self._worker, daemon=True)
                         for _ in range(self.nworkers)]
         for t in self.threads:
