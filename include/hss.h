@@ -228,7 +228,10 @@ hss_status hss_plan_node_ranges(const hss_tree_desc *tree, int64_t *start, int64
 
 /* Batched calls: one launch per tree level across all handles (levels are
  * aligned at the leaves for upward passes and at the root for downward
- * passes).  Each result equals the single-handle call on the same stream.
+ * passes).  Each result equals the single-handle call on the same stream,
+ * bit for bit, except for products of 2 to 8 columns, which a batch runs on
+ * the per-level kernels and a single call on the mailbox kernels (equal up
+ * to the order of the sums).
  * hs: host array of count handles; the per-handle arrays are host arrays of
  * count entries; B / X / Y entries are device pointers.
  * Each call uploads small task tables (the handles' records, the per-level

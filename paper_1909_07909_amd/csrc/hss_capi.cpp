@@ -250,6 +250,17 @@ bool use_fwd_op(const Plan& P) {
 // ---------------------------------------------------------------------------
 // Single-instance schedules
 // ---------------------------------------------------------------------------
+// Which products run the per-level wide kernels (leaves <= 128, ranks <= 32)
+// rather than the mailbox kernels: a single matrix from kMmwFromCols columns
+// on (below that the mailbox climb is faster: 297 against 349 us at 8
+// columns on the n = 2^18 matrix), a batch from kMmwBatchFromCols (many small
+// trees: the per-level launches are 1.5x faster at 8 columns).
+constexpr int kMmwFromCols = kMbCols + 1;
+constexpr int kMmwBatchFromCols = 2;
+inline bool use_mmw(int p, int64_t nrhs, int leaf_mp, int max_k, int from = kMmwFromCols) {
+  return p > 0 && nrhs >= from && mmw_fits(leaf_mp, max_k);
+}
+
 template <typename T>
 void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T* Y, int64_t ldy,
                 hipStream_t s, const int32_t* gate = nullptr, T* xh = nullptr, T* yh = nullptr) {
@@ -278,10 +289,8 @@ void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T*
       launch_mmf<T>(MMFStep::LeafUY, a, 1 << p, (int)nrhs, mku, mk, s);
       return;
     }
-    if (p > 0 && nrhs > kMbCols && mmw_fits(h->plan.level_max_mp[p], mk)) {
-      // blocks wider than the batched product's (whose sums at up to kMbCols
-      // columns the single-instance call repeats bit for bit): one launch
-      // per level
+    if (use_mmw(p, nrhs, h->plan.level_max_mp[p], mk)) {
+      // wide blocks: one launch per level
       a.node0 = level_first(p);
       launch_mmw<T>(MMWStep::LeafUp, a, 1 << p, (int)nrhs, s);
       for (int l = p - 1; l >= 0; --l) {
@@ -629,6 +638,7 @@ struct BatchPlan {
   const Inst<T>* insts = nullptr;   // device
   const int2* tasks = nullptr;      // device
   int pmax = 0, mku = 0, mk = 0;
+  bool wide = false;   // product: per-level wide kernels
   int64_t root_bytes = 0, child_bytes = 0;
 };
 
@@ -670,6 +680,30 @@ hss_status plan_mm_n(BatchScratch& BS, hss_handle* const* hs, int count, const i
   }
   bp.pmax = max_depth(hs, count);
   auto none = [](const Plan&, int) -> int64_t { return 0; };
+  int64_t maxr = 0;
+  bp.wide = true;
+  for (int j = 0; j < count; ++j) {
+    const Plan& P = hs[j]->plan;
+    maxr = std::max(maxr, nrhs[j]);
+    bp.wide = bp.wide && use_mmw(P.p, kMmwBatchFromCols, P.level_max_mp[P.p], P.max_k,
+                                 kMmwBatchFromCols);
+  }
+  bp.wide = bp.wide && maxr >= kMmwBatchFromCols;
+  if (bp.wide) {
+    // leaf projections; upward levels aligned at the leaves (down to each
+    // root, whose core blocks the up step applies); downward levels aligned
+    // at the roots; leaf outputs
+    const int pmax = bp.pmax;
+    bp.L.add_step(hs, count, [&](const Plan& P) { return lv_one(P.p); }, none);
+    for (int st = 1; st <= pmax; ++st)
+      bp.L.add_step(hs, count, [&](const Plan& P) {
+        return P.p - st >= 0 ? lv_one(P.p - st) : lv_none(); }, none);
+    for (int st = 1; st <= pmax - 1; ++st)
+      bp.L.add_step(hs, count, [&](const Plan& P) {
+        return st <= P.p - 1 ? lv_one(st) : lv_none(); }, none);
+    bp.L.add_step(hs, count, [&](const Plan& P) { return lv_one(P.p); }, none);
+    return plan_upload(BS, insts, bp, s);
+  }
   const int dh = mmf_down_height(), uh = mmf_up_height();
   bp.L.add_step(hs, count, [&](const Plan& P) {
     return P.p > 0 ? lv_one(std::max(P.p - uh, 0)) : lv_none(); }, none);   // up: subtree roots
@@ -695,6 +729,20 @@ hss_status run_mm_n(BatchScratch& BS, const BatchPlan<T>& bp, hss_handle* const*
   hss_status st = upload_calls(BS, calls, s, &a.calls);
   if (st) return st;
   a.insts = bp.insts;
+  if (bp.wide) {
+    size_t k = 0;
+    auto go = [&](MMWStep stp) {
+      const auto& r = bp.L.ranges[k++];
+      a.tasks = bp.tasks + r.off;
+      a.ntasks = r.cnt;
+      launch_mmw<T>(stp, a, r.cnt, (int)maxr, s);
+    };
+    go(MMWStep::LeafUp);
+    for (int q = 1; q <= bp.pmax; ++q) go(MMWStep::Up);
+    for (int q = 1; q <= bp.pmax - 1; ++q) go(MMWStep::Down);
+    go(MMWStep::LeafOut);
+    return last_launch_status();
+  }
   const MMFStep steps[3] = {MMFStep::Up, MMFStep::Down, MMFStep::Leaf};
   for (int q = 0; q < 3; ++q) {
     const auto& r = bp.L.ranges[q];

@@ -29,11 +29,6 @@ constexpr int kWC = 16;    // right-hand-side columns per tile of the level kern
 constexpr int kWL = 32;    // right-hand-side columns per tile of the leaf-out kernel
 
 // Node t of the launch: a level is a contiguous heap range from node0.
-template <typename T>
-__device__ __forceinline__ int wnode(const KArgs<T, CallMM<T>>& a) {
-  return a.node0 + (int)blockIdx.x;
-}
-
 // Stage a rows x cols block (element (i, j) at src[i + j*ld]) into LDS at
 // dst[i*lr + j] (TR) or dst[i + j*lr]: NPT elements per thread, every load
 // issued (from a clamped, valid address) before the first store.
@@ -76,16 +71,16 @@ __device__ __forceinline__ void axpy8(T (&s)[8], T coef, const T* x) {
 // x^_i = V_i^T X_i for leaf i and columns c0 .. c0 + kWC - 1: wavefront w sums
 // rows 32w .. 32w + 31 of V and X; lane (a = lane % 32, half h = lane / 32)
 // keeps x^[a, 8h .. 8h + 7]; the four partial sums meet in LDS.
-template <typename T>
+template <typename T, bool BATCH>
 __global__ __launch_bounds__(kWT) void k_mmw_leaf_up(KArgs<T, CallMM<T>> a) {
   __shared__ T Vs[kMaxBlock * (kWR + 1)];              // Vs[k][a] (row k of V)
   __shared__ __align__(16) T Xs[kMaxBlock * kXR];       // Xs[k][c]
   T* Ps = Vs;   // the four partial sums, once V has been read
   static_assert(4 * kWR * kWC <= kMaxBlock * (kWR + 1), "partial sums fit in Vs");
-  const Inst<T>& I = a.inst;
-  const CallMM<T>& C = a.call;
+  Inst<T> I; CallMM<T> C; int t;
+  resolve<BATCH>(a, I, C, t);
   if (gated_off(C.gate)) return;
-  const int t = wnode(a), c0 = blockIdx.y * kWC;
+  const int c0 = blockIdx.y * kWC;
   const NodeInfo nd = I.nodes[t];
   const int m = nd.m, kv = nd.kv, nc = min(kWC, C.nrhs - c0);
   {
@@ -122,15 +117,15 @@ __global__ __launch_bounds__(kWT) void k_mmw_leaf_up(KArgs<T, CallMM<T>> a) {
 // h) forms one output row for eight columns as a dot product of a
 // coefficient row (column i of W_t, or a row of B12 / B21) with rows of the
 // stacked children's x^.
-template <typename T>
+template <typename T, bool BATCH>
 __global__ __launch_bounds__(kWT) void k_mmw_up(KArgs<T, CallMM<T>> a) {
   __shared__ __align__(16) T Xs[2 * kWR * kXR];      // [x^_c1; x^_c2]
   __shared__ T Ws[2 * kWR * (kWR + 1)];              // Ws[j][b] = W_t(j, b)
   __shared__ T Bs[2 * kWR * (kWR + 1)];              // B12 rows 0..ku1-1, then B21
-  const Inst<T>& I = a.inst;
-  const CallMM<T>& C = a.call;
+  Inst<T> I; CallMM<T> C; int t;
+  resolve<BATCH>(a, I, C, t);
   if (gated_off(C.gate)) return;
-  const int t = wnode(a), c0 = blockIdx.y * kWC;
+  const int c0 = blockIdx.y * kWC;
   const NodeInfo nd = I.nodes[t], n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
   const int kv1 = n1.kv, kv2 = n2.kv, ku1 = n1.ku, ku2 = n2.ku, kw = kv1 + kv2;
   const int kv = t > 0 ? nd.kv : 0;
@@ -180,14 +175,14 @@ __global__ __launch_bounds__(kWT) void k_mmw_up(KArgs<T, CallMM<T>> a) {
 
 // Node t below the root: [y^_c1; y^_c2] += R_t y^_t.  Thread (row i, quarter
 // q) updates row i of four columns.
-template <typename T>
+template <typename T, bool BATCH>
 __global__ __launch_bounds__(kWT) void k_mmw_down(KArgs<T, CallMM<T>> a) {
   __shared__ __align__(16) T Ys[kWR * kXR];          // y^_t
   __shared__ T Rs[2 * kWR * (kWR + 1)];              // Rs[i][j] = R_t(i, j)
-  const Inst<T>& I = a.inst;
-  const CallMM<T>& C = a.call;
+  Inst<T> I; CallMM<T> C; int t;
+  resolve<BATCH>(a, I, C, t);
   if (gated_off(C.gate)) return;
-  const int t = wnode(a), c0 = blockIdx.y * kWC;
+  const int c0 = blockIdx.y * kWC;
   const NodeInfo nd = I.nodes[t], n1 = I.nodes[2 * t + 1], n2 = I.nodes[2 * t + 2];
   const int ku = nd.ku, ku1 = n1.ku, ku2 = n2.ku, kr = ku1 + ku2;
   const int nc = min(kWC, C.nrhs - c0);
@@ -219,15 +214,15 @@ __global__ __launch_bounds__(kWT) void k_mmw_down(KArgs<T, CallMM<T>> a) {
 
 // Y_i = D_i X_i + U_i y^_i for leaf i and columns c0 .. c0 + kWL - 1: thread
 // (r = tid % 128, h = tid / 128) forms row r of columns 16h .. 16h + 15.
-template <typename T>
+template <typename T, bool BATCH>
 __global__ __launch_bounds__(kWT) void k_mmw_leaf_out(KArgs<T, CallMM<T>> a) {
   constexpr int XL = kWL + 2;                // LDS row: 16-byte aligned halves
   __shared__ __align__(16) T Xs[kMaxBlock * XL];
   __shared__ __align__(16) T Ys[kWR * XL];
-  const Inst<T>& I = a.inst;
-  const CallMM<T>& C = a.call;
+  Inst<T> I; CallMM<T> C; int t;
+  resolve<BATCH>(a, I, C, t);
   if (gated_off(C.gate)) return;
-  const int t = wnode(a), c0 = blockIdx.y * kWL;
+  const int c0 = blockIdx.y * kWL;
   const NodeInfo nd = I.nodes[t];
   const int m = nd.m, ku = I.p > 0 ? nd.ku : 0, nc = min(kWL, C.nrhs - c0);
   {
@@ -302,12 +297,17 @@ void launch_mmw(MMWStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
   TimedLaunch tl((sizeof(T) == 8 ? n64 : n32)[(int)step], s);
   const dim3 b(kWT);
   const dim3 g(nblocks, (nrhs + kWC - 1) / kWC), gl(nblocks, (nrhs + kWL - 1) / kWL);
+  const bool batch = a.tasks != nullptr;
+#define HSS_MMW(K, G)                                                  \
+  if (batch) hipLaunchKernelGGL((K<T, true>), G, b, 0, s, a);          \
+  else hipLaunchKernelGGL((K<T, false>), G, b, 0, s, a);
   switch (step) {
-    case MMWStep::LeafUp: hipLaunchKernelGGL((k_mmw_leaf_up<T>), g, b, 0, s, a); break;
-    case MMWStep::Up: hipLaunchKernelGGL((k_mmw_up<T>), g, b, 0, s, a); break;
-    case MMWStep::Down: hipLaunchKernelGGL((k_mmw_down<T>), g, b, 0, s, a); break;
-    case MMWStep::LeafOut: hipLaunchKernelGGL((k_mmw_leaf_out<T>), gl, b, 0, s, a); break;
+    case MMWStep::LeafUp: HSS_MMW(k_mmw_leaf_up, g); break;
+    case MMWStep::Up: HSS_MMW(k_mmw_up, g); break;
+    case MMWStep::Down: HSS_MMW(k_mmw_down, g); break;
+    case MMWStep::LeafOut: HSS_MMW(k_mmw_leaf_out, gl); break;
   }
+#undef HSS_MMW
 }
 
 template void launch_mmw<double>(MMWStep, const KArgs<double, CallMM<double>>&, int, int,
