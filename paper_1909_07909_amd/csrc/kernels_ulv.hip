@@ -901,81 +901,107 @@ __global__ __launch_bounds__(kNT) void k_ulv_root_lu2(KArgs<T, CallSV<T>> a) {
   for (int o = tid; o < mp * mp; o += kNT) I.rootLU[o] = Ls[o % mp + (o / mp) * ld];
 }
 
-// FP64 LU with partial pivoting of a root block of at most 64 rows by one
-// wavefront, the block in registers: lane i holds row i (64 doubles).  Rows
-// are not moved: step j picks the largest |A(i, j)| among the rows not yet
-// chosen (the first lane on ties), every other open row takes its multiplier
-// and subtracts it times the pivot row (read lane by lane from the pivot's
-// registers), and the pivot row is closed.  Row i, closed at step s_i, holds
-// its multipliers left of column s_i and its U row from there on, so writing
-// it to row s_i of the output gives the in-place L U of the permuted block;
-// the sequence of row interchanges (LAPACK's convention, as the solve reads
-// it) is reconstructed at the end from the order in which rows were chosen.
+// FP64 LU with partial pivoting of a root block of at most 64 rows, the block
+// in registers: lane i of every wavefront holds row i, wavefront w columns
+// 16 w .. 16 w + 15.  Rows are not moved: step j picks the largest |A(i, j)|
+// among the rows not yet chosen (the first lane on ties) in the wavefront
+// that holds column j, which publishes the pivot row and the multipliers in
+// LDS (double-buffered by step parity, one barrier per step); every
+// wavefront then subtracts multiplier times pivot row from its columns past
+// j (the pivot row's entries read from the pivot lane's registers).  Row i,
+// closed at step s_i, holds its multipliers left of column s_i and its U row
+// from there on, so writing it to row s_i of the output gives the in-place
+// L U of the permuted block; the sequence of row interchanges (LAPACK's
+// convention, as the solve reads it) is reconstructed at the end from the
+// order in which rows were chosen.
 template <typename T, bool BATCH>
-__global__ __launch_bounds__(64) void k_ulv_root_lu_w(KArgs<T, CallSV<T>> a) {
+__global__ __launch_bounds__(256) void k_ulv_root_lu_w(KArgs<T, CallSV<T>> a) {
+  __shared__ double ls[2][64];
+  __shared__ int sp[2];
+  __shared__ int order[64];
   Inst<T> I; CallSV<T> C; int node;
   resolve<BATCH>(a, I, C, node);
   const NodeInfo nd = I.nodes[node];
   const int mp = nd.mp;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const T* src = I.p == 0 ? I.D + nd.oD : I.FD + nd.oFD;
   const bool row_ok = lane < mp;
-  double A[64];
+  double A[16];
 #pragma unroll
-  for (int c = 0; c < 64; ++c) {
+  for (int cc = 0; cc < 16; ++cc) {
+    const int c = 16 * w + cc;
     const bool ok = row_ok & (c < mp);
-    A[c] = ok ? (double)src[(ok ? lane : 0) + (int64_t)(ok ? c : 0) * mp] : 0.0;
+    A[cc] = ok ? (double)src[(ok ? lane : 0) + (int64_t)(ok ? c : 0) * mp] : 0.0;
   }
   bool open = row_ok;
-  int rank = lane;   // the step that closes this row (rows >= mp: themselves)
-  int chosen = 0;    // lane j: the row chosen at step j
+  int rank = lane;
   bool sing = false;
+  // a rolled loop over the steps (compact code: the kernel runs once per
+  // factorization, so its instructions are fetched cold); column j of the
+  // owner's registers is picked and replaced by selects
+  for (int j = 0; j < mp; ++j) {
+    const int par = j & 1;
+    if (w == (j >> 4)) {
+      const int jc = j & 15;
+      double aj = 0.0;
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
-    if (j < mp) {
-    const double v = open ? fabs(A[j]) : -1.0;
-    const double mx = wave_max(v);
-    const uint64_t hit = __ballot(open && v == mx);
-    const uint64_t avail = __ballot(open);
-    int p = (int)__builtin_ctzll(hit ? hit : avail);
-    p = __builtin_amdgcn_readfirstlane(p);
-    if (!(mx > 0.0)) sing = true;
-    const double pv = lane_read(A[j], p);
-    const double dinv = mx > 0.0 ? 1.0 / pv : 0.0;
-    const bool elim = open && lane != p;
-    const double l = elim ? A[j] * dinv : 0.0;
-    if (elim) A[j] = l;
+      for (int cc = 0; cc < 16; ++cc) aj = cc == jc ? A[cc] : aj;
+      const double v = open ? fabs(aj) : -1.0;
+      const double mx = wave_max(v);
+      const uint64_t hit = __ballot(open && v == mx);
+      const uint64_t avail = __ballot(open);
+      const int p = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(hit ? hit : avail));
+      if (!(mx > 0.0)) sing = true;
+      const double pv = lane_read(aj, p);
+      const double dinv = mx > 0.0 ? 1.0 / pv : 0.0;
+      const bool elim = open && lane != p;
+      const double l = elim ? aj * dinv : 0.0;
 #pragma unroll
-    for (int c = j + 1; c < 64; ++c) A[c] -= l * lane_read(A[c], p);   // zero past mp
+      for (int cc = 0; cc < 16; ++cc) A[cc] = (cc == jc) & elim ? l : A[cc];
+      ls[par][lane] = l;
+      if (lane == 0) {
+        sp[par] = p;
+        order[j] = p;
+      }
+    }
+    __syncthreads();
+    const int p = sp[par];
+    const double l = ls[par][lane];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc)
+      if (16 * w + cc > j) A[cc] -= l * lane_read(A[cc], p);   // (uniform test)
     if (lane == p) {
       open = false;
       rank = j;
     }
-    if (lane == j) chosen = p;
-    }
   }
-  // row i of the output is the row closed at step i
   double* LU = I.rootLU;
   if (row_ok) {
 #pragma unroll
-    for (int c = 0; c < 64; ++c)
-      if (c < mp) LU[rank + (int64_t)c * mp] = A[c];   // (uniform)
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = 16 * w + cc;
+      if (c < mp) LU[rank + (int64_t)c * mp] = A[cc];
+    }
   }
-  // interchanges: position j takes the row chosen at step j from wherever the
-  // earlier interchanges left it (cur: row at each position, at: position of
-  // each row, one entry per lane)
-  int cur = lane, at = lane;
-  for (int j = 0; j < mp; ++j) {
-    const int r = __builtin_amdgcn_readlane(chosen, j);
-    const int q = __builtin_amdgcn_readlane(at, r);
-    const int rj = __builtin_amdgcn_readlane(cur, j);
-    if (lane == j) I.piv[j] = q;
-    if (lane == j) cur = r;
-    if (lane == q) cur = rj;
-    if (lane == r) at = j;
-    if (lane == rj) at = q;
+  if (w == 0) {
+    // interchanges: position j takes the row chosen at step j from wherever
+    // the earlier interchanges left it (cur: row at each position, at:
+    // position of each row, one entry per lane)
+    int cur = lane, at = lane;
+    for (int j = 0; j < mp; ++j) {
+      const int r = order[j];
+      const int q = __builtin_amdgcn_readlane(at, r);
+      const int rj = __builtin_amdgcn_readlane(cur, j);
+      if (lane == j) I.piv[j] = q;
+      if (lane == j) cur = r;
+      if (lane == q) cur = rj;
+      if (lane == r) at = j;
+      if (lane == rj) at = q;
+    }
   }
-  if (lane == 0 && sing) {
+  const uint64_t sg = __ballot(sing);
+  if (threadIdx.x % 64 == 0 && sg && w == 0) {
     atomicOr(I.status, 1 << kCodeSingular);
     atomicMax(I.status + kStSingularNode, node + 1);
   }
@@ -1037,7 +1063,7 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max
       break;
     case UlvStep::RootLU:
       if (max_mp <= 64) {
-        block = dim3(64);
+        block = dim3(256);
         sm = 0;
         HSS_LAUNCH(k_ulv_root_lu_w);
       } else if (max_mp <= 128) { HSS_LAUNCH(k_ulv_root_lu2); }
