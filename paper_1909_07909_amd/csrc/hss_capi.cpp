@@ -143,7 +143,7 @@ hss_status ensure_factors(hss_handle* h) {
   F.FZ = dalloc<T>(h, P.nFZ);
   F.FOP = dalloc<T>(h, sizeof(T) == 4 ? P.nOP : 0);
   F.rootLU = dalloc<double>(h, (int64_t)P.nodes[0].mp * P.nodes[0].mp);
-  F.piv = dalloc<int32_t>(h, P.nodes[0].mp);
+  F.piv = dalloc<int32_t>(h, 2 * (int64_t)P.nodes[0].mp);   // interchanges, then the permutation
   if (!F.FD || !F.FU || !F.FV || !F.tq || !F.tz || !F.FZ || !F.FOP || !F.rootLU || !F.piv)
     return HSS_ENOMEM;
   return HSS_OK;

@@ -83,7 +83,7 @@ struct Inst {
   T *FD, *FU, *FV, *tq, *tz, *FZ;
   T* FOP;           // forward-operator records (internal nodes that have them)
   double* rootLU;
-  int32_t* piv;
+  int32_t* piv;     // root LU: mp interchanges, then the permutation they make (mp)
   T *xh, *yh;       // product work, leading dimension ldm
   int64_t ldm;
   T *wc, *wz, *wy, *wx;   // solve work, leading dimension lds

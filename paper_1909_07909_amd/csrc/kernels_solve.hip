@@ -843,7 +843,8 @@ __global__ __launch_bounds__(kSWS * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) 
   int* piv = reinterpret_cast<int*>(LU + mp * mp);
   T* rest = reinterpret_cast<T*>(piv + ((mp + 3) & ~3));
   stage_block(LU, mp, mp, [&](int i, int j) { return I.rootLU[i + j * mp]; });
-  for (int o = threadIdx.x; o < mp; o += blockDim.x) piv[o] = I.piv[o];   // (mp <= 128 < blockDim)
+  // the row permutation of the root LU (position i holds original row piv[i])
+  for (int o = threadIdx.x; o < mp; o += blockDim.x) piv[o] = I.piv[mp + o];   // (mp <= 128 < blockDim)
   NodeSrc<T> S = (nd.is_leaf || !(a.flags & 1)) ? src_global(I, nd, n1, n2)
                                                  : src_stage_fwd(I, nd, n1, n2, rest);
   __syncthreads();
@@ -866,17 +867,19 @@ __global__ __launch_bounds__(kSWS * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) 
     x0[c] = (double)t0[c];
     x1[c] = (double)t1[c];
   }
-  for (int j = 0; j < mp; ++j) {
-    const int pj = piv[j];
+  {
+    // x <- P x in one gather: row r takes original row piv[r]
+    const int s0 = r0 < mp ? piv[r0] : r0, s1 = r1 < mp ? piv[r1] : r1;
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
-      const double vj = row_of(x0[c], x1[c], j), vp = row_of(x0[c], x1[c], pj);
-      if (r0 == j) x0[c] = vp;
-      if (r1 == j) x1[c] = vp;
-      if (r0 == pj) x0[c] = vj;
-      if (r1 == pj) x1[c] = vj;
+      const double a0 = __shfl(x0[c], s0 & 63, 64), b0 = __shfl(x1[c], s0 & 63, 64);
+      const double a1 = __shfl(x0[c], s1 & 63, 64), b1 = __shfl(x1[c], s1 & 63, 64);
+      x0[c] = s0 < 64 ? a0 : b0;
+      x1[c] = s1 < 64 ? a1 : b1;
     }
   }
+  // (unrolled so that the LDS reads of the next columns are in flight)
+#pragma unroll 8
   for (int i = 0; i < mp; ++i) {
     const double* Li = LU + i * mp;
     const double l0 = r0 > i && r0 < mp ? Li[r0] : 0.0;
@@ -888,6 +891,7 @@ __global__ __launch_bounds__(kSWS * 64) void k_sv_root_w(KArgs<T, CallSV<T>> a) 
       x1[c] -= l1 * xi;
     }
   }
+#pragma unroll 8
   for (int i = mp - 1; i >= 0; --i) {
     const double* Ui = LU + i * mp;
     const double u0 = r0 < i ? Ui[r0] : 0.0, u1 = r1 < i ? Ui[r1] : 0.0;

@@ -770,6 +770,28 @@ __global__ __launch_bounds__(kNT) void k_ulv_fwdop(KArgs<T, CallSV<T>> a) {
 // ---------------------------------------------------------------------------
 // Root: LU with partial pivoting (FP64) of D'_root (or of D when p = 0).
 // ---------------------------------------------------------------------------
+// After the interchanges piv[0 .. mp) of a factored root block: the
+// permutation they make (position i holds original row perm[i]) to
+// piv[mp + i], so that the solve permutes its right-hand side in one gather.
+// Called by the whole work-group; mp <= 256 (the block fits LDS).
+__device__ void store_perm(int32_t* piv, int mp) {
+  __shared__ int ps[256], pv[256];
+  __syncthreads();   // the interchanges written by thread 0 are visible
+  for (int o = threadIdx.x; o < mp; o += blockDim.x) {
+    ps[o] = o;
+    pv[o] = piv[o];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < mp; ++j) {
+      const int q = pv[j], t = ps[j];
+      ps[j] = ps[q];
+      ps[q] = t;
+    }
+  __syncthreads();
+  for (int o = threadIdx.x; o < mp; o += blockDim.x) piv[mp + o] = ps[o];
+}
+
 template <typename T, bool BATCH>
 __global__ __launch_bounds__(kNT) void k_ulv_root_lu(KArgs<T, CallSV<T>> a) {
   HIP_DYNAMIC_SHARED(char, smem_raw)
@@ -827,6 +849,7 @@ __global__ __launch_bounds__(kNT) void k_ulv_root_lu(KArgs<T, CallSV<T>> a) {
     __syncthreads();
   }
   for (int o = tid; o < mp * mp; o += nt) I.rootLU[o] = Ls[o % mp + (o / mp) * ld];
+  store_perm(I.piv, mp);
 }
 
 // The same factorization for mp <= 128, organised for short steps: the pivot
@@ -899,6 +922,7 @@ __global__ __launch_bounds__(kNT) void k_ulv_root_lu2(KArgs<T, CallSV<T>> a) {
     atomicMax(I.status + kStSingularNode, node + 1);
   }
   for (int o = tid; o < mp * mp; o += kNT) I.rootLU[o] = Ls[o % mp + (o / mp) * ld];
+  store_perm(I.piv, mp);
 }
 
 // FP64 LU with partial pivoting of a root block of at most 64 rows, the block
@@ -994,6 +1018,7 @@ __global__ __launch_bounds__(256) void k_ulv_root_lu_w(KArgs<T, CallSV<T>> a) {
       const int q = __builtin_amdgcn_readlane(at, r);
       const int rj = __builtin_amdgcn_readlane(cur, j);
       if (lane == j) I.piv[j] = q;
+      if (lane == j) I.piv[mp + j] = r;   // the permutation: position j holds row r
       if (lane == j) cur = r;
       if (lane == q) cur = rj;
       if (lane == r) at = j;
