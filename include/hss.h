@@ -256,6 +256,31 @@ hss_status hss_batch_ulv_solve(hss_handle *const *hs, int32_t count, const int64
                                double *const *B, const int64_t *ldb, const hss_solve_opts *o,
                                hss_solve_info *const *info, void *stream);
 
+/* Autotuning of launch choices.  The library chooses, per call, between
+ * kernel variants that compute the same result: the product of 2 or more
+ * columns on the mailbox climb or on the per-level wide kernels (Sec. 4.1,
+ * the same four steps), and the number of right-hand-side columns a
+ * wavefront carries through a solve sweep (1 or 4; Sec. 4.3 Steps 2 and 4).
+ * Built-in rules pick them by default; hss_autotune times both variants of
+ * each on h with nrhs columns in precision prec (HSS_F64 / HSS_F32; the
+ * solve part needs that factorization and nrhs >= 4), on the stream, and
+ * records the faster for every later single-matrix call on a matrix of the
+ * same shape class (leaf block size, largest rank, depth, precision, column
+ * bucket 1 | 2-3 | 4-7 | 8-15 | 16-31 | 32+), process-wide.  It allocates and
+ * frees temporary blocks of n x nrhs through h's allocator and synchronizes
+ * the stream.  report (NULL or cap bytes): a JSON object with the shape
+ * class, the measured microseconds and the choices (HSS_ESCRATCH if cap is
+ * too small).  Batched calls keep the built-in rules.
+ * hss_tune_table writes the recorded choices as text, one line per shape
+ * class (leaf_mp max_k depth prec bucket product_wide cpw and the four
+ * times); hss_tune_load reads such text back (-1 on a malformed line, nothing
+ * loaded); hss_tune_reset forgets every choice. */
+hss_status hss_autotune(hss_handle *h, int64_t nrhs, int32_t prec, void *stream, char *report,
+                        int64_t cap);
+hss_status hss_tune_table(char *buf, int64_t cap);
+hss_status hss_tune_load(const char *text);
+hss_status hss_tune_reset(void);
+
 /* Per-kernel timing (profiling aid).  hss_timing_enable(1) makes every
  * kernel launch of the library record a pair of HIP events on its stream;
  * hss_timing_report writes a JSON array [{"kernel", "launches", "total_ms"}]

@@ -6,9 +6,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 #include <string>
 #include <vector>
@@ -250,6 +252,42 @@ bool use_fwd_op(const Plan& P) {
 // ---------------------------------------------------------------------------
 // Single-instance schedules
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Tuned launch choices (hss_autotune): per shape class of a matrix (leaf
+// block size, largest rank, depth), precision and right-hand-side bucket,
+// the product's kernel family and the solve sweeps' columns per wavefront
+// that measured fastest.  Process-wide; calls without an entry use the
+// default rules.  While the tuner times a variant it forces it through the
+// thread-local overrides.
+struct TuneKey {
+  int leaf_mp, max_k, p, prec, bucket;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(leaf_mp, max_k, p, prec, bucket) <
+           std::tie(o.leaf_mp, o.max_k, o.p, o.prec, o.bucket);
+  }
+};
+struct TuneVal {
+  int mm = -1;    // product: 1 per-level wide kernels, 0 mailbox kernels, -1 default
+  int cpw = 0;    // solve sweeps: columns per wavefront (1 or 4), 0 default
+  double t_mm[2] = {0, 0}, t_sv[2] = {0, 0};   // measured us (mailbox, wide; cpw 1, 4)
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+thread_local int g_force_mm = -1;
+thread_local int g_force_cpw = 0;
+
+int rhs_bucket(int64_t n) { return n <= 1 ? 0 : n < 4 ? 1 : n < 8 ? 2 : n < 16 ? 3 : n < 32 ? 4 : 5; }
+TuneKey tune_key(const Plan& P, int prec, int64_t nrhs) {
+  return TuneKey{P.level_max_mp[P.p], P.max_k, P.p, prec, rhs_bucket(nrhs)};
+}
+bool tune_lookup(const Plan& P, int prec, int64_t nrhs, TuneVal* v) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find(tune_key(P, prec, nrhs));
+  if (it == g_tune.end()) return false;
+  *v = it->second;
+  return true;
+}
+
 // Which products run the per-level wide kernels (leaves <= 128, ranks <= 32)
 // rather than the mailbox kernels: a single matrix from kMmwFromCols columns
 // on (below that the mailbox climb is faster: 297 against 349 us at 8
@@ -289,7 +327,14 @@ void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T*
       launch_mmf<T>(MMFStep::LeafUY, a, 1 << p, (int)nrhs, mku, mk, s);
       return;
     }
-    if (use_mmw(p, nrhs, h->plan.level_max_mp[p], mk)) {
+    bool wide = use_mmw(p, nrhs, h->plan.level_max_mp[p], mk);
+    if (p > 0 && nrhs >= 2 && mmw_fits(h->plan.level_max_mp[p], mk)) {
+      TuneVal tv;
+      if (g_force_mm >= 0) wide = g_force_mm == 1;
+      else if (tune_lookup(h->plan, sizeof(T) == 8 ? HSS_F64 : HSS_F32, nrhs, &tv) && tv.mm >= 0)
+        wide = tv.mm == 1;
+    }
+    if (wide) {
       // wide blocks: one launch per level
       a.node0 = level_first(p);
       launch_mmw<T>(MMWStep::LeafUp, a, 1 << p, (int)nrhs, s);
@@ -390,7 +435,14 @@ void run_solve(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, hipStream_t s,
   a.call = CallSV<T>{B, ldb, (int32_t)nrhs, 0, gate};
   const Plan& P = h->plan;
   const int p = P.p;
-  const int nc = (int)nrhs;   // one wavefront per (node, column)
+  const int nc = (int)nrhs;
+  // columns per wavefront: tuned (or forced by the tuner), else the default
+  {
+    TuneVal tv;
+    if (g_force_cpw > 0) a.cpw = g_force_cpw;
+    else if (nrhs >= 4 && tune_lookup(P, sizeof(T) == 8 ? HSS_F64 : HSS_F32, nrhs, &tv))
+      a.cpw = tv.cpw;
+  }
   auto fwd_stage = [&](int l) -> int64_t {
     const int64_t e = P.level_fwd_stage[l];
     return e > 0 && e * (int64_t)sizeof(T) <= kStageBudget ? e : 0;
@@ -1109,6 +1161,98 @@ int64_t noalloc_bytes(const Plan& P, int64_t nrhs, size_t es) {
 }  // namespace
 
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// Autotuning: median of five timed calls (after one untimed) per variant.
+template <typename F>
+double time_calls(hipStream_t s, F fn) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.0;
+  }
+  fn();
+  double t[5];
+  for (int i = 0; i < 5; ++i) {
+    (void)hipEventRecord(e0, s);
+    fn();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    t[i] = 1e3 * ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::sort(t, t + 5);
+  return t[2];
+}
+
+template <typename T>
+hss_status autotune(hss_handle* h, int64_t nrhs, hipStream_t s, TuneVal& tv, bool& did_mm,
+                    bool& did_sv) {
+  const Plan& P = h->plan;
+  const int64_t n = P.n;
+  did_mm = did_sv = false;
+  hss_status st = HSS_OK;
+  if (P.p > 0 && nrhs >= 2 && mmw_fits(P.level_max_mp[P.p], P.max_k)) {
+    T* X = dalloc<T>(h, n * nrhs);
+    T* Y = dalloc<T>(h, n * nrhs);
+    if (!X || !Y) st = HSS_ENOMEM;
+    else if ((st = ensure_work_mm<T>(h, nrhs)) == HSS_OK &&
+             hipMemsetAsync(X, 0, sizeof(T) * n * nrhs, s) == hipSuccess) {
+      for (int v = 0; v < 2; ++v) {
+        g_force_mm = v;
+        tv.t_mm[v] = time_calls(s, [&] { run_matmul<T>(h, HSS_OP_N, nrhs, X, n, Y, n, s); });
+      }
+      g_force_mm = -1;
+      tv.mm = tv.t_mm[1] < tv.t_mm[0] ? 1 : 0;
+      did_mm = true;
+    }
+    (void)hipStreamSynchronize(s);
+    dev_free(h, X);
+    dev_free(h, Y);
+    if (st) return st;
+    if ((st = last_launch_status())) return st;
+  }
+  const bool factored = sizeof(T) == 8 ? h->f64.valid : h->f32.valid;
+  if (factored && nrhs >= 4) {
+    T* B = dalloc<T>(h, n * nrhs);
+    if (!B) return HSS_ENOMEM;
+    if ((st = ensure_work_sv<T>(h, nrhs)) == HSS_OK &&
+        hipMemsetAsync(B, 0, sizeof(T) * n * nrhs, s) == hipSuccess) {
+      const int cand[2] = {1, 4};
+      for (int v = 0; v < 2; ++v) {
+        g_force_cpw = cand[v];
+        tv.t_sv[v] = time_calls(s, [&] { run_solve<T>(h, nrhs, B, n, s); });
+      }
+      g_force_cpw = 0;
+      tv.cpw = tv.t_sv[1] < tv.t_sv[0] ? 4 : 1;
+      did_sv = true;
+    }
+    (void)hipStreamSynchronize(s);
+    dev_free(h, B);
+    if (st) return st;
+    if ((st = last_launch_status())) return st;
+  }
+  return HSS_OK;
+}
+
+std::string tune_line(const TuneKey& k, const TuneVal& v) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %.2f %.2f %.2f %.2f\n", k.leaf_mp, k.max_k,
+                k.p, k.prec, k.bucket, v.mm, v.cpw, v.t_mm[0], v.t_mm[1], v.t_sv[0], v.t_sv[1]);
+  return buf;
+}
+
+hss_status copy_out(const std::string& txt, char* buf, int64_t cap) {
+  if (!buf || cap <= 0) return HSS_OK;
+  const size_t nb = std::min<size_t>(txt.size(), (size_t)cap - 1);
+  std::memcpy(buf, txt.data(), nb);
+  buf[nb] = 0;
+  return txt.size() < (size_t)cap ? HSS_OK : HSS_ESCRATCH;
+}
+
 extern "C" {
 
 const char* hss_status_str(hss_status s) {
@@ -1475,6 +1619,80 @@ hss_status hss_batch_ulv_solve(hss_handle* const* hs, int32_t count, const int64
   }
   if (count == 0) return HSS_OK;
   return batch_solve(hs, count, nrhs, B, ldb, opt, info, (hipStream_t)stream);
+}
+
+hss_status hss_autotune(hss_handle* h, int64_t nrhs, int32_t prec, void* stream, char* report,
+                        int64_t cap) {
+  if (!h) return -1;
+  if (nrhs < 1) return -2;
+  if (prec != HSS_F64 && prec != HSS_F32) return -3;
+  hipStream_t s = (hipStream_t)stream;
+  const TuneKey key = tune_key(h->plan, prec, nrhs);
+  TuneVal tv;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) tv = it->second;
+  }
+  bool did_mm = false, did_sv = false;
+  const hss_status st = prec == HSS_F64 ? autotune<double>(h, nrhs, s, tv, did_mm, did_sv)
+                                        : autotune<float>(h, nrhs, s, tv, did_mm, did_sv);
+  if (st) return st;
+  if (did_mm || did_sv) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = tv;
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof buf,
+                "{\"leaf_mp\": %d, \"max_k\": %d, \"depth\": %d, \"prec\": %d, "
+                "\"rhs_bucket\": %d, \"product_tuned\": %s, \"product_us\": [%.2f, %.2f], "
+                "\"product_wide\": %d, \"solve_tuned\": %s, \"solve_us\": [%.2f, %.2f], "
+                "\"solve_cpw\": %d}",
+                key.leaf_mp, key.max_k, key.p, key.prec, key.bucket, did_mm ? "true" : "false",
+                tv.t_mm[0], tv.t_mm[1], tv.mm, did_sv ? "true" : "false", tv.t_sv[0], tv.t_sv[1],
+                tv.cpw);
+  return copy_out(buf, report, cap);
+}
+
+hss_status hss_tune_table(char* buf, int64_t cap) {
+  std::string txt;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (const auto& kv : g_tune) txt += tune_line(kv.first, kv.second);
+  }
+  if (!buf) return -1;
+  if (cap <= 0) return -2;
+  return copy_out(txt, buf, cap);
+}
+
+hss_status hss_tune_load(const char* text) {
+  if (!text) return -1;
+  std::vector<std::pair<TuneKey, TuneVal>> rows;
+  const char* p = text;
+  while (*p) {
+    TuneKey k{};
+    TuneVal v;
+    int used = 0;
+    const int got = std::sscanf(p, "%d %d %d %d %d %d %d %lf %lf %lf %lf%n", &k.leaf_mp, &k.max_k,
+                                &k.p, &k.prec, &k.bucket, &v.mm, &v.cpw, &v.t_mm[0], &v.t_mm[1],
+                                &v.t_sv[0], &v.t_sv[1], &used);
+    if (got != 11) return -1;
+    if (v.mm < -1 || v.mm > 1 || (v.cpw != 0 && v.cpw != 1 && v.cpw != 4) || k.bucket < 0 ||
+        k.bucket > 5 || (k.prec != HSS_F64 && k.prec != HSS_F32))
+      return -1;
+    rows.emplace_back(k, v);
+    p += used;
+    while (*p == '\n' || *p == ' ' || *p == '\r' || *p == '\t') ++p;
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (const auto& r : rows) g_tune[r.first] = r.second;
+  return HSS_OK;
+}
+
+hss_status hss_tune_reset(void) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune.clear();
+  return HSS_OK;
 }
 
 }  // extern "C"

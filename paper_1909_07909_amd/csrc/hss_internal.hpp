@@ -163,7 +163,7 @@ struct KArgs {
   int32_t node0;
   int32_t ntasks;
   int32_t flags;   // kernel-specific options (root solve: bit 0 = children staged in LDS)
-  int32_t pad;
+  int32_t cpw;     // solve sweeps: right-hand-side columns per wavefront (0: by the count)
 };
 
 }  // namespace hss

@@ -1052,8 +1052,9 @@ void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int 
                      ? 4
                      : (step == UlvStep::Fwd || step == UlvStep::FwdOp ? 0 : 2) + (leafy ? 1 : 0);
   TimedLaunch tl((sizeof(T) == 8 ? nm64 : nm32)[ni], s);
-  // columns per wavefront: 4 when there are enough columns to share the factor reads
-  const int cpw = ncols >= 4 ? 4 : 1;
+  // columns per wavefront: 4 when there are enough columns to share the factor
+  // reads, unless the caller chose (a tuned choice)
+  const int cpw = a.cpw == 1 || a.cpw == 4 ? a.cpw : (ncols >= 4 ? 4 : 1);
   const int cgroups = (ncols + cpw - 1) / cpw;
   dim3 gridw((nitems + kSW - 1) / kSW, cgroups), blockw(kSW * 64);
   // eight wavefronts (one staging round trip) for the root and for the

@@ -28,7 +28,8 @@ EXPORTS = (
     "hss_create", "hss_destroy", "hss_matmul", "hss_ulv_factor", "hss_ulv_solve", "hss_query",
     "hss_plan_depth", "hss_plan_leaf_offsets", "hss_plan_node_ranges", "hss_batch_matmul",
     "hss_batch_ulv_factor", "hss_batch_ulv_solve", "hss_status_str", "hss_timing_enable",
-    "hss_timing_report", "hss_matmul_noalloc", "hss_matmul_noalloc_max_rhs",
+    "hss_timing_report", "hss_matmul_noalloc", "hss_matmul_noalloc_max_rhs", "hss_autotune",
+    "hss_tune_table", "hss_tune_load", "hss_tune_reset",
 )
 
 Q_N, Q_P, Q_RESIDENT_BYTES, Q_NORM2, Q_GEN_ENTRIES, Q_FACTOR_ENTRIES = range(6)
@@ -105,6 +106,10 @@ def lib() -> C.CDLL:
     L.hss_batch_ulv_solve.argtypes = [C.POINTER(vp), i32, C.POINTER(C.c_int64), C.POINTER(vp),
                                       C.POINTER(C.c_int64), C.POINTER(SolveOpts),
                                       C.POINTER(vp), vp]
+    L.hss_autotune.argtypes = [vp, i64, i32, vp, C.c_char_p, i64]
+    L.hss_tune_table.argtypes = [C.c_char_p, i64]
+    L.hss_tune_load.argtypes = [C.c_char_p]
+    L.hss_tune_reset.argtypes = []
     L.hss_timing_enable.argtypes = [i32]
     L.hss_timing_report.argtypes = [C.c_char_p, i64, i32]
     L.hss_status_str.argtypes = [i32]
@@ -157,6 +162,22 @@ def plan_node_ranges(n, p, leaf_off, ku, kv):
                                       size.ctypes.data_as(C.POINTER(C.c_int64))),
            "hss_plan_node_ranges")
     return start, size
+
+
+def tune_table() -> str:
+    """The autotuned launch choices recorded so far (text, one line per shape class)."""
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib().hss_tune_table(buf, len(buf)), "hss_tune_table")
+    return buf.value.decode()
+
+
+def tune_load(text: str):
+    """Load choices written by tune_table()."""
+    _check(lib().hss_tune_load(text.encode()), "hss_tune_load")
+
+
+def tune_reset():
+    _check(lib().hss_tune_reset(), "hss_tune_reset")
 
 
 def timing_enable(on: bool):
@@ -385,6 +406,18 @@ class HSSMatrix:
         opts = SolveOpts(prec, 0, 0.0, 0, 0)
         _check(lib().hss_ulv_solve(self.h, r, bp, ldb, C.byref(opts), None, _stream(stream)),
                "hss_ulv_solve")
+
+    def autotune(self, nrhs: int, prec=F64, stream=None) -> dict:
+        """Time the launch variants for products and solves of nrhs columns
+        on this matrix and record the faster for its shape class (see
+        hss_autotune); returns the report.  Synchronizes the stream."""
+        import json
+        if int(nrhs) < 1:
+            raise ValueError("nrhs must be >= 1")
+        buf = C.create_string_buffer(1024)
+        _check(lib().hss_autotune(self.h, int(nrhs), int(prec), _stream(stream), buf, len(buf)),
+               "hss_autotune")
+        return json.loads(buf.value.decode())
 
     def query(self, key, stream=None):
         if key in (Q_N, Q_RESIDENT_BYTES, Q_GEN_ENTRIES, Q_FACTOR_ENTRIES):

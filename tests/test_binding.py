@@ -80,3 +80,24 @@ def test_colmajor_rejects_mixed_dtypes():
 def test_info_layout():
     # HSS_SOLVE_INFO_BYTES(nrhs) = 32 + 8 nrhs: two doubles, four int32
     assert hss.info_bytes(0) == 32 and hss.info_bytes(5) == 72
+
+
+def test_tune_table_roundtrip():
+    """The tuned-choice table as text (no device work): load, read back,
+    reject malformed lines without loading anything, reset."""
+    hss.tune_reset()
+    assert hss.tune_table() == ""
+    text = ("128 32 11 0 3 1 4 296.90 349.50 410.00 380.25\n"
+            "64 16 5 1 5 0 1 12.00 15.50 8.00 9.25\n")
+    hss.tune_load(text)
+    rows = sorted(hss.tune_table().strip().split("\n"))
+    assert rows == sorted(l.strip() for l in text.strip().split("\n"))
+    for bad in ("128 32 11 0 3 1 4 1.0 2.0\n",          # too few fields
+                "128 32 11 0 3 2 4 1 2 3 4\n",          # product choice out of range
+                "128 32 11 0 3 1 3 1 2 3 4\n",          # columns per wavefront not 0/1/4
+                "128 32 11 7 3 1 4 1 2 3 4\n"):         # unknown precision
+        with pytest.raises(hss.HSSError):
+            hss.tune_load(bad)
+    assert len(hss.tune_table().strip().split("\n")) == 2
+    hss.tune_reset()
+    assert hss.tune_table() == ""
