@@ -93,6 +93,9 @@ def main():
                          "FP64 oracle timed on the host for every workload (no GPU)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-resident", type=float, default=1.0,
+                    help="serving: device budget for resident matrices as a fraction of the "
+                         "whole catalogue (below 1: created and evicted on demand, LRU)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain device copy of this many bytes (a reference "
                          "kernel of known traffic for the HBM byte counters)")
@@ -219,6 +222,13 @@ def main():
                 return A.solve(X, prec=hss.F32, tol=tol, max_refine=mr, sync=False, report=rep)
             return A.solve(X, prec=hss.F64, want_eta=True, sync=False, report=rep)
 
+        # launch choices for 32-column products and sweeps, timed on this
+        # shape (hss_autotune) and used by every later call on it
+        tuned = {"fp32": mats[0].autotune(rw, hss.F32), "fp64": mats[0].autotune(rw, hss.F64)}
+        log("[bench] autotuned r=32: " + ", ".join(
+            f"{k}: product {'wide' if v['product_wide'] else 'mailbox'} "
+            f"({v['product_us'][0]:.0f} / {v['product_us'][1]:.0f} us), sweep cpw {v['solve_cpw']} "
+            f"({v['solve_us'][0]:.0f} / {v['solve_us'][1]:.0f} us)" for k, v in tuned.items()))
         kw = max(K // 2, 3)
         w32, ew32 = timed(step_wide, kw, W, hss.F32, 1e-10, ncols=rw)
         w64, ew64 = timed(step_wide, kw, W, hss.F64, 0.0, ncols=rw)
@@ -228,7 +238,8 @@ def main():
                            "refine_iters_max": max(i for _, i in ew32)},
                 "fp64": {"solves_per_s": round(1.0 / w64, 2), "ms": round(w64 * 1e3, 3),
                          "eta_max": max(e for e, _ in ew64)},
-                "ratio_fp32ir_over_fp64": round(w64 / w32, 3)}
+                "ratio_fp32ir_over_fp64": round(w64 / w32, 3),
+                "autotuned": tuned}
         log(f"[bench] fresh r={rw}: FP32+IR {w32*1e3:.3f} ms (eta_max "
             f"{wide['fp32ir']['eta_max']:.2e}), FP64 {w64*1e3:.3f} ms (eta_max "
             f"{wide['fp64']['eta_max']:.2e})")
@@ -496,13 +507,22 @@ def bench_serve(args):
     gens = serve.build_catalogue(specs, seed=4, workers=16)
     log(f"[bench-serve] catalogue {specs} generated in {time.perf_counter() - t0:.1f} s")
     mats = [hss.HSSMatrix(g) for g in gens]
-    del gens
     t0 = time.perf_counter()
     for m in mats:
         m.factor(hss.F32)
         m.norm2()
     torch.cuda.synchronize()
     log(f"[bench-serve] factored in {time.perf_counter() - t0:.2f} s")
+    cat = None
+    if args.serve_resident < 1.0:
+        # bounded residency: a catalogue with room for that fraction of the
+        # matrices' measured bytes, loading and evicting them on demand
+        total = sum(m.query(hss.Q_RESIDENT_BYTES) for m in mats)
+        for m in mats:
+            m.close()
+        mats = cat = serve.Catalogue(gens, budget_bytes=int(args.serve_resident * total))
+        log(f"[bench-serve] catalogue budget {cat.budget / 2**30:.1f} GiB of {total / 2**30:.1f} GiB")
+    del gens
     pools = serve.rhs_pools(mats, device=True)   # request blocks resident in HBM
     warm = serve.poisson_requests(args.serve_rate, 0.2, len(mats), seed=40)
     serve.run_stream(mats, warm, budget_bytes=24 << 30, workers=2, pools=pools)
@@ -518,14 +538,16 @@ def bench_serve(args):
            "ms_per_step": round(wall / max(len(ok), 1) * 1e3, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64ir", "data": "synthetic",
            "config": {"workload": f"Poisson {args.serve_rate:.0f} req/s for {args.serve_seconds} s, "
-                                  "16 resident matrices n log-uniform [4096, 2^20], k in {16,32,64}, "
+                                  f"16 matrices n log-uniform [4096, 2^20] ({'all resident' if cat is None else f'{args.serve_resident:.0%} resident, LRU'}), k in {{16,32,64}}, "
                                   "leaf 128, tol 1e-6 / 1e-10, 1-16 rhs, request blocks in HBM"},
            "latency": lat, "rhs_columns_per_s": round(cols / wall, 1),
            "all_within_tol": good, "rounds": srv.rounds,
            "mean_requests_per_round": round(float(np.mean(srv.round_sizes)), 2),
            "peak_inflight_bytes": srv.peak_bytes,
            "worker_phase_s": {k: round(v, 3) for k, v in srv.phase_s.items()},
-           "resident_bytes": int(sum(m.query(hss.Q_RESIDENT_BYTES) for m in mats)),
+           "resident_bytes": (cat.resident_bytes() if cat is not None else
+                              int(sum(m.query(hss.Q_RESIDENT_BYTES) for m in mats))),
+           "catalogue": cat.stats() if cat is not None else None,
            "errors": srv.errors[:3], "roofline": None, "cpu_baseline": None}
     _emit(out, args)
 

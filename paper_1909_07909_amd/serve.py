@@ -15,6 +15,11 @@ HIP stream each, repeatedly form a round from the admitted requests:
   class tolerance); requests that arrive meanwhile are admitted as memory frees
   and picked up by the next free worker, so rounds overlap on the device.
 
+A catalogue bounds residency: it holds every matrix's generators on the host
+and keeps at most a device-memory budget of them resident, created and
+FP32-factored when a round first needs them, least recently used idle ones
+evicted to make room (a matrix a round is using is never evicted).
+
 Each completed request records its latency (arrival to result: on the
 host for host requests, in device memory for device-resident requests) and
 the backward error of every column.  The GPU work is all in libhss.so;
@@ -111,7 +116,8 @@ def rhs_pools(mats, width: int = 32, seed: int = 77, device: bool = False):
     of consecutive columns (so that long runs do not draw fresh normals for
     every request).  device=True: the pools are column-major device tensors
     (requests then carry device views, as from a client on the GPU)."""
-    pools = [inputs.rhs(m.n, width, seed + j) for j, m in enumerate(mats)]
+    ns = list(mats.n) if isinstance(mats, Catalogue) else [m.n for m in mats]
+    pools = [inputs.rhs(n, width, seed + j) for j, n in enumerate(ns)]
     if device:
         import torch
         pools = [torch.from_numpy(np.ascontiguousarray(P.T)).cuda().t() for P in pools]
@@ -124,17 +130,123 @@ def rhs_from_pool(req: Request, pools) -> np.ndarray:
     return P[:, s:s + req.nrhs]
 
 
+class Catalogue:
+    """Matrices a server solves with: generators on the host, at most
+    ``budget_bytes`` of them resident on the device.  ``acquire(j)`` returns
+    matrix j created and FP32-factored (and its work buffers sized for
+    ``max_cols`` columns), creating it if it is not resident and first
+    evicting least recently used matrices that no round is using until it
+    fits; ``release(j)`` ends a round's use.  A matrix that alone exceeds the
+    budget is still loaded (the budget is then exceeded by it alone)."""
+
+    def __init__(self, gens, budget_bytes: int, max_cols: int = 64):
+        import torch
+        self.torch = torch
+        self.gens = list(gens)
+        self.n = [g.n for g in self.gens]
+        self.budget = int(budget_bytes)
+        self.max_cols = max_cols
+        self.resident = {}            # j -> HSSMatrix
+        self.bytes = {}               # j -> resident bytes (measured at load)
+        self.last = {}                # j -> use clock
+        self.users = {}               # j -> rounds using it
+        self.seen = {}                # j -> bytes measured at its last load
+        self.clock = 0
+        self.hits = self.misses = self.evictions = 0
+        self.load_s = 0.0
+        self.lock = threading.Lock()
+
+    def __len__(self):
+        return len(self.gens)
+
+    def resident_bytes(self) -> int:
+        with self.lock:
+            return sum(self.bytes.values())
+
+    def is_resident(self, j: int) -> bool:
+        with self.lock:
+            return j in self.resident
+
+    def expected_bytes(self, j: int) -> int:
+        """Device bytes matrix j takes when resident: measured once loaded,
+        else estimated from its generators (FP64 + FP32 copies and an FP32
+        factor set of about their size)."""
+        with self.lock:
+            b = self.bytes.get(j)
+        if b is None:
+            b = self.seen.get(j)
+        return int(b) if b else int(16 * self.gens[j].entries())
+
+    def _evict_for_locked(self, need: int):
+        while self.resident and sum(self.bytes.values()) + need > self.budget:
+            idle = [j for j in self.resident if self.users.get(j, 0) == 0]
+            if not idle:
+                return
+            j = min(idle, key=lambda q: self.last[q])
+            self.resident.pop(j).close()
+            self.bytes.pop(j)
+            self.evictions += 1
+
+    def acquire(self, j: int):
+        with self.lock:
+            self.clock += 1
+            self.last[j] = self.clock
+            self.users[j] = self.users.get(j, 0) + 1
+            if j in self.resident:
+                self.hits += 1
+                return self.resident[j]
+            self.misses += 1
+            # the expected size: a matrix of the same shape loaded before, else
+            # the FP64 + FP32 generators and an FP32 factor set of about their size
+            est = self.seen.get(j) or int(16 * self.gens[j].entries())
+            self._evict_for_locked(est)
+        t0 = time.perf_counter()
+        try:
+            A = hss.HSSMatrix(self.gens[j])
+            A.factor(hss.F32)
+            A.norm2()
+            B = hss.empty_colmajor(A.n, self.max_cols, self.torch.float64)
+            B.fill_(1.0)
+            A.solve(B, prec=hss.F32, tol=1e-10, max_refine=1, check=False)
+            del B
+        except Exception:
+            with self.lock:
+                self.users[j] -= 1
+            raise
+        with self.lock:
+            self.resident[j] = A
+            self.bytes[j] = self.seen[j] = int(A.query(hss.Q_RESIDENT_BYTES))
+            self.load_s += time.perf_counter() - t0
+            self._evict_for_locked(0)
+        return A
+
+    def release(self, j: int):
+        with self.lock:
+            self.users[j] -= 1
+
+    def stats(self) -> dict:
+        with self.lock:
+            return {"hits": self.hits, "misses": self.misses, "evictions": self.evictions,
+                    "resident": len(self.resident), "resident_bytes": sum(self.bytes.values()),
+                    "budget_bytes": self.budget, "load_s": round(self.load_s, 3)}
+
+
 class Server:
     def __init__(self, mats, budget_bytes: int, workers: int = 2, max_mats_per_round: int = 64,
-                 max_cols_per_group: int = 64, max_refine: int = 10):
+                 max_cols_per_group: int = 64, max_refine: int = 10, max_wait_s: float = 0.05):
+        """mats: resident, FP32-factored HSSMatrix objects, or a Catalogue
+        (created and evicted as rounds need them; requests on matrices that
+        are not resident wait up to max_wait_s for others to share a load)."""
         import torch
         self.torch = torch
         self.mats = mats
-        self.n = [m.n for m in mats]
+        self.cat = mats if isinstance(mats, Catalogue) else None
+        self.n = list(mats.n) if self.cat is not None else [m.n for m in mats]
         self.budget = budget_bytes
         self.max_mats = max_mats_per_round
         self.max_cols = max_cols_per_group
         self.max_refine = max_refine
+        self.max_wait_s = max_wait_s
         self.pending = deque()        # arrived, waiting for memory
         self.admitted = deque()       # admitted, waiting for a round
         self.inflight_bytes = 0
@@ -178,6 +290,20 @@ class Server:
         cols = {}
         used = set()
         keep = deque()
+        # with a catalogue, a round's matrices (and those of the rounds
+        # running) must fit its budget together; a round takes at least one
+        room = None
+        if self.cat is not None:
+            room = self.cat.budget - sum(self.cat.expected_bytes(m) for m in self.busy)
+            # requests on resident matrices first, and those that have waited
+            # longer than max_wait_s; the others wait for their matrix's
+            # requests to gather, so that one load serves many of them
+            now = time.perf_counter()
+            first = [r for r in self.admitted
+                     if self.cat.is_resident(r.mat) or now - r.t_arrival > self.max_wait_s]
+            ids = {id(r) for r in first}
+            self.admitted = deque(first + [r for r in self.admitted if id(r) not in ids])
+        round_bytes = 0
         while self.admitted:
             r = self.admitted.popleft()
             key = (r.mat, r.tol)
@@ -188,6 +314,12 @@ class Server:
                 if len(used) >= self.max_mats:
                     keep.append(r)
                     continue
+                if room is not None and r.mat not in used:
+                    b = self.cat.expected_bytes(r.mat)
+                    if used and round_bytes + b > room:
+                        keep.append(r)
+                        continue
+                    round_bytes += b
                 groups[key] = []
                 cols[key] = 0
                 used.add(r.mat)
@@ -250,6 +382,15 @@ class Server:
         by_tol = {}
         for (m, t), reqs in groups.items():
             by_tol.setdefault(t, []).append((m, reqs))
+        acquired = []
+        try:
+            self._run_classes(by_tol, stream, acquired)
+        finally:
+            for m in acquired:
+                self.cat.release(m)
+
+    def _run_classes(self, by_tol, stream, acquired):
+        torch = self.torch
         with torch.cuda.stream(stream):
             for tol, items in by_tol.items():
                 t0 = time.perf_counter()
@@ -271,7 +412,9 @@ class Server:
                             host[c:c + r.nrhs].copy_(torch.from_numpy(np.ascontiguousarray(Bh.T)))
                             c += r.nrhs
                         dev = host.to("cuda", non_blocking=True).t()
-                    mats.append(self.mats[m])
+                    mats.append(self.cat.acquire(m) if self.cat is not None else self.mats[m])
+                    if self.cat is not None:
+                        acquired.append(m)
                     blocks.append(dev)
                     splits.append(reqs)
                 t1 = time.perf_counter()
@@ -311,11 +454,14 @@ class Server:
                     self.phase_s["stage_out"] += t3 - t2
 
     def reserve_work(self):
-        """Grow every matrix's work buffers to the widest group a round can
-        give it (max_cols_per_group columns, refined FP32 solve) before
-        requests arrive, so that rounds never allocate or retire them."""
+        """Grow every resident matrix's work buffers to the widest group a
+        round can give it (max_cols_per_group columns, refined FP32 solve)
+        before requests arrive, so that rounds never allocate or retire them
+        (a catalogue does it when it loads a matrix)."""
         from . import hss
         torch = self.torch
+        if self.cat is not None:
+            return
         for m in self.mats:
             B = hss.empty_colmajor(m.n, self.max_cols, torch.float64)
             B.fill_(1.0)
@@ -338,9 +484,10 @@ class Server:
 def run_stream(mats, requests, budget_bytes: int, workers: int = 2, pools=None):
     """Release ``requests`` at their arrival times (relative to now) into a
     server and wait for all of them.  Returns (server, wall seconds)."""
+    ns = list(mats.n) if isinstance(mats, Catalogue) else [m.n for m in mats]
     for r in requests:
         if r.B is None:
-            r.B = rhs_from_pool(r, pools) if pools is not None else rhs_for(r, mats[r.mat].n)
+            r.B = rhs_from_pool(r, pools) if pools is not None else rhs_for(r, ns[r.mat])
     srv = Server(mats, budget_bytes, workers=workers)
     srv.start()
     start = time.perf_counter()
