@@ -526,6 +526,46 @@ __device__ __forceinline__ void store_rows(const v4<T> (&X)[8][2], T* FD, int mp
   }
 }
 
+// QL-phase slabs to LQ-phase slabs through LDS (blocks of exactly 128 rows):
+// wavefront Q holds columns 32 Q .. 32 Q + 31 of M (rows in position order)
+// and needs rows 32 Q .. 32 Q + 31 (columns in position order).  Four rounds
+// over the 32 x 32 blocks, one barrier pair each: in round r wavefront Q
+// writes its block of rows 32 (Q ^ r) to its own LDS region (pitch 33) and
+// reads back, transposed, the block wavefront Q ^ r wrote for it, into the
+// tiles it has just written out.
+constexpr int kTP = 33, kTBlk = 32 * 33;
+
+template <typename T, int Q, int R>
+__device__ __forceinline__ void tr_round(v4<T> (&X)[8][2], T* buf, int g, int c) {
+  constexpr int S = Q ^ R;
+  T* dst = buf + Q * kTBlk;
+#pragma unroll
+  for (int rl = 0; rl < 2; ++rl)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        dst[(16 * ct + c) * kTP + 16 * rl + mma_row<T>(g, r)] = X[2 * S + rl][ct][r];
+  __syncthreads();
+  const T* src = buf + S * kTBlk;
+#pragma unroll
+  for (int rl = 0; rl < 2; ++rl)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        X[2 * S + rl][ct][r] = src[(16 * rl + mma_row<T>(g, r)) * kTP + 16 * ct + c];
+  __syncthreads();
+}
+
+template <typename T, int Q>
+__device__ __forceinline__ void transpose_slabs(v4<T> (&X)[8][2], T* buf, int g, int c) {
+  tr_round<T, Q, 0>(X, buf, g, c);
+  tr_round<T, Q, 1>(X, buf, g, c);
+  tr_round<T, Q, 2>(X, buf, g, c);
+  tr_round<T, Q, 3>(X, buf, g, c);
+}
+
 // U~ and the QL reflectors from the panel wavefront's slab (vector v = column
 // v of U', position = row + s): the reflector above the pivot, beta on it,
 // U~ below, to FU.
@@ -605,6 +645,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   __shared__ __attribute__((aligned(16))) T Gs[kBW * kLT];
   __shared__ T scal[3 * kBW];
   __shared__ int sing;
+  static_assert(kBW * kLY >= 4 * kTBlk, "the transposition blocks fit in Yt");
   const PanelScal<T> S{scal, scal + kBW, scal + 2 * kBW};
   Inst<T> I; CallSV<T> C; int node;
   resolve<BATCH>(a, I, C, node);
@@ -652,10 +693,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
     __syncthreads();
     block_update<T, 0>(X, Yt, Ts, g, c);
-    // M to FD (column slabs), then back as transposed row slabs
-    slab_store_cols(X, FD, mp, mp, mp, s, 32 * w, g, c);
-    __syncthreads();
-    slab_load_rows(X, FD, mp, mp, mp, 32 * w, g, c);
+    if (sizeof(T) == 4 && s == 0) {
+      // FP32 blocks of 128 rows: M from column slabs to row slabs through
+      // LDS (Yt is free again once every slab's update has read it)
+      __syncthreads();
+      switch (w) {
+        case 0: transpose_slabs<T, 0>(X, Yt, g, c); break;
+        case 1: transpose_slabs<T, 1>(X, Yt, g, c); break;
+        case 2: transpose_slabs<T, 2>(X, Yt, g, c); break;
+        default: transpose_slabs<T, 3>(X, Yt, g, c); break;
+      }
+    } else {
+      // shifted positions: M to FD (column slabs), then back as row slabs
+      slab_store_cols(X, FD, mp, mp, mp, s, 32 * w, g, c);
+      __syncthreads();
+      slab_load_rows(X, FD, mp, mp, mp, 32 * w, g, c);
+    }
   } else {
     slab_load_rows(X, Dsrc, mp, mp, mp, 32 * w, g, c);
   }
