@@ -15,6 +15,9 @@ ulv       A^{-1}B by the four steps of Sec. 4.3 (QL / LQ sparsification,
           Woodbury split A~ = A1 A2, recursion on the merged leaves, apply Z)
 norms     power method on A^T A for ||A||_2 (Sec. 4.5) and the normwise
           backward error used in Sec. 5.1
+hadamard  the Hadamard product of two HSS matrices on one tree (Sec. 4.4):
+          elementwise D, transpose Khatri-Rao bases, Kronecker translation
+          operators and core blocks
 
 Every function is pinned in ``tests/test_oracle_*.py`` against closed forms,
 dense LAPACK, brute force or the worked example of Fig. 1 (see each module's
