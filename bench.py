@@ -351,6 +351,8 @@ def main():
                     "avg_launch_us": round(avg_s * 1e6, 2)}
         break
 
+    had = hadamard_measure(log)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(lo, r)
@@ -377,6 +379,7 @@ def main():
         "resident_solves_per_s": {"fp32ir": round(1.0 / rt32, 2), "fp64": round(1.0 / rt64, 2)},
         "fresh_nrhs32": wide,
         "matmul_fp64": mm,
+        "hadamard": had,
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": kernels[:12],
@@ -386,6 +389,52 @@ def main():
     if args.out:
         with open(args.out, "w") as f:
             f.write(line + "\n")
+
+
+def hadamard_measure(log, reps=5, ka=8, kb=4):
+    """The Hadamard product of two n=2^18, leaf-128 matrices of ranks ka and kb
+    (the result has rank ka*kb = 32, the headline shape): per-kernel times
+    from events around each launch, against the generator bytes each kernel
+    reads and writes, and the whole hss_hadamard call (which also makes the
+    FP32 copy and the ||C||_2 estimate and synchronizes)."""
+    import torch
+
+    from paper_1909_07909_amd import hss, inputs
+    lo = hss.plan_leaf_offsets(N, LEAF)
+    A = hss.HSSMatrix(inputs.synthetic_hss(lo, ka, seed=40))
+    B = hss.HSSMatrix(inputs.synthetic_hss(lo, kb, seed=41))
+    C = A.hadamard(B)   # warm-up
+    sa, sb, sc = A.packed_sizes(), B.packed_sizes(), C.packed_sizes()
+    del C
+    torch.cuda.synchronize()
+    hss.timing_enable(True)
+    hss.timing_report(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        C = A.hadamard(B)
+        del C
+    call_ms = (time.perf_counter() - t0) * 1e3 / reps
+    rep = {d["kernel"]: d for d in hss.timing_report(reset=True)}
+    hss.timing_enable(False)
+    diag_bytes = 8 * (sa["D"] + sb["D"] + sc["D"])
+    rest = ("U", "V", "R", "W", "B12", "B21")
+    gen_bytes = 8 * sum(sa[k] + sb[k] + sc[k] for k in rest)
+    out = {"workload": f"C = A o B, n={N}, leaf={LEAF}, ranks {ka} x {kb} -> {ka * kb}",
+           "call_ms": round(call_ms, 3)}
+    for name, byt in (("hadamard_diag", diag_bytes), ("hadamard_gen", gen_bytes)):
+        d = rep.get(name)
+        if d is None:
+            continue
+        us = d["total_ms"] / d["launches"] * 1e3
+        out[name] = {"us": round(us, 2), "algorithmic_bytes": byt,
+                     "gbps": round(byt / us / 1e3, 1),
+                     "frac_hbm_peak": round(byt / us / 1e3 / HBM_PEAK_GBS, 4)}
+    tot_us = sum(out[k]["us"] for k in ("hadamard_diag", "hadamard_gen") if k in out)
+    out["kernels_us"] = round(tot_us, 2)
+    out["gbps"] = round((diag_bytes + gen_bytes) / tot_us / 1e3, 1)
+    log(f"[bench] hadamard: kernels {tot_us:.1f} us ({out['gbps']} GB/s), "
+        f"whole call {call_ms:.2f} ms")
+    return out
 
 
 def _emit(out, args):

@@ -26,7 +26,8 @@
  * call is enqueued on its stream; the product (op N) forks part of its work
  * to a stream the handle owns and joins it back with events, so it is
  * ordered after earlier work on the caller's stream and before later work
- * there, as if it ran on that stream alone.  Only hss_create and hss_destroy
+ * there, as if it ran on that stream alone.  Only the calls that create a
+ * handle (hss_create, hss_hadamard), hss_get_generators and hss_destroy
  * synchronize; products, factorizations and solves (refined or not) are
  * stream-ordered, and their device-side outcome (backward errors, refinement
  * steps, singular pivots) is written to device-accessible memory that is
@@ -156,6 +157,40 @@ hss_status hss_create(const hss_tree_desc *tree, const hss_gen_host *gen,
 
 /* hss_destroy: free everything the handle owns.  NULL is a no-op. */
 hss_status hss_destroy(hss_handle *h);
+
+/* hss_hadamard: the elementwise product C = A o B of two HSS matrices on the
+ * same cluster tree (Sec. 4.4, eq. "hadamard" and the figure of its
+ * pseudo-codes): D_C = D_A o D_B at the leaves; U_C = U_A .T U_B and
+ * V_C = V_A .T V_B, the transpose Khatri-Rao products (row i is
+ * kron(row i of U_A, row i of U_B), so column a kB + b is
+ * U_A(:, a) o U_B(:, b)); R_C = R_A kron R_B for each child block of the
+ * stacked R (likewise W), B12_C = B12_A kron B12_B, B21_C = B21_A kron B21_B.
+ * Ranks multiply node by node.  The generators are formed on the device from
+ * A's and B's resident FP64 generators (A and B are only read); *out is a new
+ * handle, as from hss_create on those generators: resident FP32 copy,
+ * ||C||_2 estimate, ready for products and factorizations.
+ * Errors: -1/-2 for a NULL A or B, -2 when B's tree (n, leaf offsets)
+ * differs from A's, -3 for incomplete allocator hooks, -5 for a NULL out;
+ * HSS_EUNSUP when a product rank exceeds 64 or a merged block exceeds 128;
+ * HSS_ENOMEM, HSS_EHIP.  Orders after earlier work on the stream, then
+ * synchronizes it. */
+hss_status hss_hadamard(const hss_handle *A, const hss_handle *B,
+                        const hss_alloc *alloc, void *stream, hss_handle **out);
+
+/* Destination of hss_get_generators: host buffers for the canonical packed
+ * arrays (the layout and sizes hss_create reads; a pointer may be NULL only
+ * when its array is empty, e.g. U, V, R, W when p = 0). */
+typedef struct {
+  double *D, *U, *V, *R, *W, *B12, *B21;
+} hss_gen_out;
+
+/* hss_get_generators: copy the handle's FP64 generators, in the canonical
+ * packed layout, to host memory (the read-back of hss_hadamard's result and
+ * of any handle).  Entry counts follow from the tree: leaves m^2, m ku, m kv;
+ * internal non-root nodes (ku_c1 + ku_c2) ku, (kv_c1 + kv_c2) kv; internal
+ * nodes ku_c1 kv_c2 and ku_c2 kv_c1.
+ * Errors: -1 NULL h, -2 a missing buffer, HSS_EHIP.  Synchronizes the stream. */
+hss_status hss_get_generators(const hss_handle *h, const hss_gen_out *g, void *stream);
 
 /* hss_matmul: Y = op(A) X by the four steps of Sec. 4.1 (leaf projections,
  * upward pass with the column translations, core blocks, downward pass with

@@ -1253,6 +1253,78 @@ hss_status copy_out(const std::string& txt, char* buf, int64_t cap) {
   return txt.size() < (size_t)cap ? HSS_OK : HSS_ESCRATCH;
 }
 
+namespace {
+
+// A handle for the plan P with every device array allocated and initialized
+// except the contents of the FP64 generators (g64), which the caller fills
+// on stream s before finish_handle.
+hss_status new_handle(Plan&& P, const hss_alloc* alloc, hipStream_t s, hss_handle** out) {
+  hss_handle* h = new hss_handle();
+  h->plan = std::move(P);
+  const Plan& Q = h->plan;
+  if (alloc) {
+    h->alloc = *alloc;
+    h->custom_alloc = true;
+  }
+  auto fail = [&](hss_status e) {
+    hss_destroy(h);
+    return e;
+  };
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
+    return fail(HSS_EHIP);
+  h->d_nodes = dalloc<NodeInfo>(h, Q.nnodes);
+  h->d_status = dalloc<int32_t>(h, 4);
+  h->d_cnt = dalloc<uint32_t>(h, (int64_t)((Q.nnodes + 2) & ~1) * kMbChunks);
+  h->chk_cnt = dalloc<uint32_t>(h, 2);
+  if (!h->d_nodes || !h->d_status || !h->d_cnt || !h->chk_cnt) return fail(HSS_ENOMEM);
+  if (hipMemcpyAsync(h->d_nodes, Q.nodes.data(), sizeof(NodeInfo) * Q.nnodes,
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(HSS_EHIP);
+  const int64_t sizes[7] = {Q.nD, Q.nU, Q.nV, Q.nR, Q.nW, Q.nB12, Q.nB21};
+  for (int i = 0; i < 7; ++i) {
+    h->g64[i] = dalloc<double>(h, sizes[i]);
+    h->g32[i] = dalloc<float>(h, sizes[i]);
+    if (!h->g64[i] || !h->g32[i]) return fail(HSS_ENOMEM);
+  }
+  launch_fill(reinterpret_cast<double*>(h->d_status), 0.0, 2, s);
+  launch_fill(reinterpret_cast<double*>(h->d_cnt), 0.0, (int64_t)((Q.nnodes + 2) / 2) * kMbChunks, s);
+  launch_fill(reinterpret_cast<double*>(h->chk_cnt), 0.0, 1, s);
+  {
+    // product mailboxes (one set per column chunk), all empty
+    const int64_t nmb = (int64_t)Q.nnodes * kMbSlot * kMbCols * kMbChunks;
+    h->w64.mb = dalloc<double>(h, nmb);
+    h->w32.mb = dalloc<float>(h, nmb + 1);
+    if (!h->w64.mb || !h->w32.mb) return fail(HSS_ENOMEM);
+    const uint64_t e32 = ((uint64_t)kMbEmpty32 << 32) | kMbEmpty32;
+    double v64, v32;
+    std::memcpy(&v64, &kMbEmpty64, sizeof v64);
+    std::memcpy(&v32, &e32, sizeof v32);
+    launch_fill(h->w64.mb, v64, nmb, s);
+    launch_fill(reinterpret_cast<double*>(h->w32.mb), v32, (nmb + 1) / 2, s);
+  }
+  hss_status st = last_launch_status();
+  if (st) return fail(st);
+  *out = h;
+  return HSS_OK;
+}
+
+// The resident FP32 copy of the generators and ||A||_2, then a stream
+// synchronization (the handle is complete when this returns HSS_OK).
+hss_status finish_handle(hss_handle* h, hipStream_t s) {
+  const Plan& P = h->plan;
+  const int64_t sizes[7] = {P.nD, P.nU, P.nV, P.nR, P.nW, P.nB12, P.nB21};
+  for (int i = 0; i < 7; ++i)
+    if (sizes[i] > 0) launch_cast_f64_f32(h->g64[i], h->g32[i], sizes[i], s);
+  hss_status st = last_launch_status();
+  if (st) return st;
+  if ((st = compute_norm2(h, s))) return st;
+  return hipStreamSynchronize(s) == hipSuccess ? HSS_OK : HSS_EHIP;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* hss_status_str(hss_status s) {
@@ -1321,73 +1393,80 @@ hss_status hss_create(const hss_tree_desc* tree, const hss_gen_host* g, const hs
   *out = nullptr;
   if (!g) return -2;
   if (alloc && (!alloc->alloc || !alloc->free)) return -3;
-  hss_handle* h = new hss_handle();
-  hss_status st = build_plan(tree, h->plan, nullptr);
-  if (st) {
-    delete h;
-    return st;
-  }
-  const Plan& P = h->plan;
+  Plan P;
+  hss_status st = build_plan(tree, P, nullptr);
+  if (st) return st;
   const int64_t sizes[7] = {P.nD, P.nU, P.nV, P.nR, P.nW, P.nB12, P.nB21};
   const double* src[7] = {g->D, g->U, g->V, g->R, g->W, g->B12, g->B21};
   for (int i = 0; i < 7; ++i)
-    if (sizes[i] > 0 && !src[i]) {
-      delete h;
-      return -2;
-    }
-  if (alloc) {
-    h->alloc = *alloc;
-    h->custom_alloc = true;
-  }
+    if (sizes[i] > 0 && !src[i]) return -2;
   hipStream_t s = (hipStream_t)stream;
-  auto fail = [&](hss_status e) {
-    hss_destroy(h);
-    return e;
-  };
-  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
-    return fail(HSS_EHIP);
-  h->d_nodes = dalloc<NodeInfo>(h, P.nnodes);
-  h->d_status = dalloc<int32_t>(h, 4);
-  h->d_cnt = dalloc<uint32_t>(h, (int64_t)((P.nnodes + 2) & ~1) * kMbChunks);
-  h->chk_cnt = dalloc<uint32_t>(h, 2);
-  if (!h->d_nodes || !h->d_status || !h->d_cnt || !h->chk_cnt) return fail(HSS_ENOMEM);
-  if (hipMemcpyAsync(h->d_nodes, P.nodes.data(), sizeof(NodeInfo) * P.nnodes,
-                     hipMemcpyHostToDevice, s) != hipSuccess)
-    return fail(HSS_EHIP);
-  for (int i = 0; i < 7; ++i) {
-    h->g64[i] = dalloc<double>(h, sizes[i]);
-    h->g32[i] = dalloc<float>(h, sizes[i]);
-    if (!h->g64[i] || !h->g32[i]) return fail(HSS_ENOMEM);
-    if (sizes[i] > 0) {
-      if (hipMemcpyAsync(h->g64[i], src[i], sizeof(double) * sizes[i], hipMemcpyHostToDevice,
-                         s) != hipSuccess)
-        return fail(HSS_EHIP);
-      launch_cast_f64_f32(h->g64[i], h->g32[i], sizes[i], s);
+  hss_handle* h = nullptr;
+  if ((st = new_handle(std::move(P), alloc, s, &h))) return st;
+  for (int i = 0; i < 7; ++i)
+    if (sizes[i] > 0 && hipMemcpyAsync(h->g64[i], src[i], sizeof(double) * sizes[i],
+                                       hipMemcpyHostToDevice, s) != hipSuccess) {
+      hss_destroy(h);
+      return HSS_EHIP;
     }
+  if ((st = finish_handle(h, s))) {
+    hss_destroy(h);
+    return st;
   }
-  launch_fill(reinterpret_cast<double*>(h->d_status), 0.0, 2, s);
-  launch_fill(reinterpret_cast<double*>(h->d_cnt), 0.0, (int64_t)((P.nnodes + 2) / 2) * kMbChunks, s);
-  launch_fill(reinterpret_cast<double*>(h->chk_cnt), 0.0, 1, s);
-  {
-    // product mailboxes (one set per column chunk), all empty
-    const int64_t nmb = (int64_t)P.nnodes * kMbSlot * kMbCols * kMbChunks;
-    h->w64.mb = dalloc<double>(h, nmb);
-    h->w32.mb = dalloc<float>(h, nmb + 1);
-    if (!h->w64.mb || !h->w32.mb) return fail(HSS_ENOMEM);
-    const uint64_t e32 = ((uint64_t)kMbEmpty32 << 32) | kMbEmpty32;
-    double v64, v32;
-    std::memcpy(&v64, &kMbEmpty64, sizeof v64);
-    std::memcpy(&v32, &e32, sizeof v32);
-    launch_fill(h->w64.mb, v64, nmb, s);
-    launch_fill(reinterpret_cast<double*>(h->w32.mb), v32, (nmb + 1) / 2, s);
-  }
-  if ((st = last_launch_status())) return fail(st);
-  if ((st = compute_norm2(h, s))) return fail(st);
-  if (hipStreamSynchronize(s) != hipSuccess) return fail(HSS_EHIP);
   *out = h;
   return HSS_OK;
+}
+
+hss_status hss_hadamard(const hss_handle* A, const hss_handle* B, const hss_alloc* alloc,
+                        void* stream, hss_handle** out) {
+  if (!out) return -5;
+  *out = nullptr;
+  if (!A) return -1;
+  if (!B) return -2;
+  if (alloc && (!alloc->alloc || !alloc->free)) return -3;
+  const Plan& PA = A->plan;
+  const Plan& PB = B->plan;
+  if (PA.n != PB.n || PA.p != PB.p || PA.leaf_off != PB.leaf_off) return -2;
+  // the tree of A o B: A's partition, ranks multiplied node by node
+  std::vector<int32_t> ku(PA.nnodes), kv(PA.nnodes);
+  for (int32_t t = 0; t < PA.nnodes; ++t) {
+    const int64_t u = (int64_t)PA.nodes[t].ku * PB.nodes[t].ku;
+    const int64_t v = (int64_t)PA.nodes[t].kv * PB.nodes[t].kv;
+    if (u > kMaxRank || v > kMaxRank) return HSS_EUNSUP;
+    ku[t] = (int32_t)u;
+    kv[t] = (int32_t)v;
+  }
+  const hss_tree_desc td{PA.n, PA.p, 0, PA.leaf_off.data(), ku.data(), kv.data()};
+  Plan P;
+  hss_status st = build_plan(&td, P, nullptr);
+  if (st) return st > 0 ? st : HSS_EUNSUP;
+  hipStream_t s = (hipStream_t)stream;
+  hss_handle* h = nullptr;
+  if ((st = new_handle(std::move(P), alloc, s, &h))) return st;
+  launch_hadamard(A->d_nodes, B->d_nodes, h->d_nodes, A->g64, B->g64, h->g64, h->plan.nD,
+                  h->plan.nnodes, h->plan.p, s);
+  if ((st = last_launch_status()) || (st = finish_handle(h, s))) {
+    hss_destroy(h);
+    return st;
+  }
+  *out = h;
+  return HSS_OK;
+}
+
+hss_status hss_get_generators(const hss_handle* h, const hss_gen_out* g, void* stream) {
+  if (!h) return -1;
+  if (!g) return -2;
+  const Plan& P = h->plan;
+  const int64_t sizes[7] = {P.nD, P.nU, P.nV, P.nR, P.nW, P.nB12, P.nB21};
+  double* dst[7] = {g->D, g->U, g->V, g->R, g->W, g->B12, g->B21};
+  for (int i = 0; i < 7; ++i)
+    if (sizes[i] > 0 && !dst[i]) return -2;
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < 7; ++i)
+    if (sizes[i] > 0 && hipMemcpyAsync(dst[i], h->g64[i], sizeof(double) * sizes[i],
+                                       hipMemcpyDeviceToHost, s) != hipSuccess)
+      return HSS_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? HSS_OK : HSS_EHIP;
 }
 
 hss_status hss_destroy(hss_handle* h) {

@@ -63,6 +63,14 @@ template <typename T>
 void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max_k,
                 int max_mp, hipStream_t s);
 
+// Hadamard product C = A o B of two matrices on one tree (kernels_hadamard.hip):
+// the packed D arrays elementwise (nD entries), then one work-group per node
+// for the bases, translation operators and core blocks.  g*[0..6] are the
+// FP64 generator arrays D, U, V, R, W, B12, B21; n* the device node tables.
+void launch_hadamard(const NodeInfo* nA, const NodeInfo* nB, const NodeInfo* nC,
+                     const double* const gA[7], const double* const gB[7], double* const gC[7],
+                     int64_t nD, int32_t nnodes, int32_t p, hipStream_t s);
+
 // Elementwise / reduction helpers (kernels_util.hip).
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 // dst[i + j*ldd] = (float)(src[i + j*lds] * scale[j])   (scale may be null -> 1)

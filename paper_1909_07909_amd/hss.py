@@ -29,7 +29,7 @@ EXPORTS = (
     "hss_plan_depth", "hss_plan_leaf_offsets", "hss_plan_node_ranges", "hss_batch_matmul",
     "hss_batch_ulv_factor", "hss_batch_ulv_solve", "hss_status_str", "hss_timing_enable",
     "hss_timing_report", "hss_matmul_noalloc", "hss_matmul_noalloc_max_rhs", "hss_autotune",
-    "hss_tune_table", "hss_tune_load", "hss_tune_reset",
+    "hss_tune_table", "hss_tune_load", "hss_tune_reset", "hss_hadamard", "hss_get_generators",
 )
 
 Q_N, Q_P, Q_RESIDENT_BYTES, Q_NORM2, Q_GEN_ENTRIES, Q_FACTOR_ENTRIES = range(6)
@@ -42,6 +42,10 @@ class TreeDesc(C.Structure):
 
 
 class GenHost(C.Structure):
+    _fields_ = [(k, C.POINTER(C.c_double)) for k in ("D", "U", "V", "R", "W", "B12", "B21")]
+
+
+class GenOut(C.Structure):
     _fields_ = [(k, C.POINTER(C.c_double)) for k in ("D", "U", "V", "R", "W", "B12", "B21")]
 
 
@@ -89,6 +93,8 @@ def lib() -> C.CDLL:
     L.hss_create.argtypes = [C.POINTER(TreeDesc), C.POINTER(GenHost), C.POINTER(Alloc), vp,
                              C.POINTER(vp)]
     L.hss_destroy.argtypes = [vp]
+    L.hss_hadamard.argtypes = [vp, vp, C.POINTER(Alloc), vp, C.POINTER(vp)]
+    L.hss_get_generators.argtypes = [vp, C.POINTER(GenOut), vp]
     L.hss_matmul.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp]
     L.hss_matmul_noalloc.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp]
     L.hss_matmul_noalloc_max_rhs.argtypes = [vp, i32]
@@ -297,6 +303,10 @@ def _close_all():
             pass
 
 
+class _Gens:
+    """Plain holder of a read-back tree and generator arrays."""
+
+
 class HSSMatrix:
     """Device-resident HSS matrix created from generators in the canonical
     packed layout (attributes n, p, leaf_off, ku, kv, D, U, V, R, W, B12, B21).
@@ -319,10 +329,70 @@ class HSSMatrix:
         code = L.hss_create(C.byref(td), C.byref(gh), C.byref(alloc) if alloc else None,
                             _stream(stream), C.byref(h))
         _check(code, "hss_create")
+        self._adopt(h, g.n, g.p, g.leaf_off, g.ku, g.kv)
+
+    def _adopt(self, h, n, p, leaf_off, ku, kv):
         self.h = h
-        self.n = int(g.n)
-        self.p = int(g.p)
+        self.n = int(n)
+        self.p = int(p)
+        self.leaf_off = np.asarray(leaf_off, dtype=np.int64).copy()
+        self.ku = np.asarray(ku, dtype=np.int32).copy()
+        self.kv = np.asarray(kv, dtype=np.int32).copy()
+        self.ku[0] = self.kv[0] = 0
         _LIVE.add(self)
+
+    def hadamard(self, other, stream=None, alloc="torch"):
+        """The elementwise product self o other (same tree) as a new
+        HSSMatrix, formed on the device by hss_hadamard."""
+        if isinstance(alloc, str):
+            if alloc != "torch":
+                raise ValueError(f"unknown allocator {alloc!r}")
+            alloc = TORCH_ALLOC
+        h = C.c_void_p()
+        code = lib().hss_hadamard(self.h, other.h, C.byref(alloc) if alloc else None,
+                                  _stream(stream), C.byref(h))
+        _check(code, "hss_hadamard")
+        out = HSSMatrix.__new__(HSSMatrix)
+        out._alloc = alloc
+        out._keep = None
+        out._adopt(h, self.n, self.p, self.leaf_off, self.ku.astype(np.int64) * other.ku,
+                   self.kv.astype(np.int64) * other.kv)
+        return out
+
+    def packed_sizes(self):
+        """Entry counts of the canonical packed arrays D, U, V, R, W, B12, B21."""
+        p, ku, kv, lo = self.p, self.ku, self.kv, self.leaf_off
+        sz = dict(D=0, U=0, V=0, R=0, W=0, B12=0, B21=0)
+        for t in range(2 ** (p + 1) - 1):
+            if t >= 2 ** p - 1:
+                m = int(lo[t - (2 ** p - 1) + 1] - lo[t - (2 ** p - 1)])
+                sz["D"] += m * m
+                if p > 0:
+                    sz["U"] += m * int(ku[t])
+                    sz["V"] += m * int(kv[t])
+            else:
+                c1, c2 = 2 * t + 1, 2 * t + 2
+                if t != 0:
+                    sz["R"] += int(ku[c1] + ku[c2]) * int(ku[t])
+                    sz["W"] += int(kv[c1] + kv[c2]) * int(kv[t])
+                sz["B12"] += int(ku[c1]) * int(kv[c2])
+                sz["B21"] += int(ku[c2]) * int(kv[c1])
+        return sz
+
+    def generators(self, stream=None):
+        """The FP64 generators read back (hss_get_generators) as an object
+        with n, p, leaf_off, ku, kv and the packed arrays D .. B21."""
+        sz = self.packed_sizes()
+        arrs = {k: np.zeros(v, dtype=np.float64) for k, v in sz.items()}
+        go = GenOut(*[arrs[k].ctypes.data_as(C.POINTER(C.c_double))
+                      for k in ("D", "U", "V", "R", "W", "B12", "B21")])
+        _check(lib().hss_get_generators(self.h, C.byref(go), _stream(stream)),
+               "hss_get_generators")
+        g = _Gens()
+        g.n, g.p, g.leaf_off, g.ku, g.kv = self.n, self.p, self.leaf_off, self.ku, self.kv
+        for k, v in arrs.items():
+            setattr(g, k, v)
+        return g
 
     def close(self):
         if getattr(self, "h", None):

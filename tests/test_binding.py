@@ -101,3 +101,16 @@ def test_tune_table_roundtrip():
     assert len(hss.tune_table().strip().split("\n")) == 2
     hss.tune_reset()
     assert hss.tune_table() == ""
+
+
+def test_hadamard_and_readback_null_arguments():
+    """hss_hadamard and hss_get_generators reject NULL arguments before any
+    device work."""
+    import ctypes as C
+    L = hss.lib()
+    h = C.c_void_p()
+    assert L.hss_hadamard(None, None, None, None, None) == -5
+    assert L.hss_hadamard(None, None, None, None, C.byref(h)) == -1
+    assert h.value is None
+    assert L.hss_get_generators(None, None, None) == -1
+    assert hss.status_str(-2) == "invalid argument"
