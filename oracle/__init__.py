@@ -18,6 +18,8 @@ norms     power method on A^T A for ||A||_2 (Sec. 4.5) and the normwise
 hadamard  the Hadamard product of two HSS matrices on one tree (Sec. 4.4):
           elementwise D, transpose Khatri-Rao bases, Kronecker translation
           operators and core blocks
+compress  HSS recompression (Sec. 4.5, App. A): proper form by bottom-up
+          QR, then top-down truncated SVDs of the core blocks
 
 Every function is pinned in ``tests/test_oracle_*.py`` against closed forms,
 dense LAPACK, brute force or the worked example of Fig. 1 (see each module's
