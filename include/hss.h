@@ -27,8 +27,8 @@
  * to a stream the handle owns and joins it back with events, so it is
  * ordered after earlier work on the caller's stream and before later work
  * there, as if it ran on that stream alone.  Only the calls that create a
- * handle (hss_create, hss_hadamard), hss_get_generators and hss_destroy
- * synchronize; products, factorizations and solves (refined or not) are
+ * handle (hss_create, hss_hadamard, hss_compress), hss_get_generators and
+ * hss_destroy synchronize; products, factorizations and solves (refined or not) are
  * stream-ordered, and their device-side outcome (backward errors, refinement
  * steps, singular pivots) is written to device-accessible memory that is
  * valid once the stream has reached the end of the call.
@@ -176,6 +176,34 @@ hss_status hss_destroy(hss_handle *h);
  * synchronizes it. */
 hss_status hss_hadamard(const hss_handle *A, const hss_handle *B,
                         const hss_alloc *alloc, void *stream, hss_handle **out);
+
+/* hss_compress: HSS recompression with truncation tolerance tau >= 0
+ * (absolute; Sec. 4.5 and App. A): the generators of A are first brought
+ * to proper form (orthonormal leaf bases and translation operators, by
+ * Householder QR from the leaves up, the core blocks multiplied by the
+ * triangular factors), then, level by level from the root down, every
+ * child's block row [S | R diag(s)] and block column [S'^T | W diag(s')]
+ * (s: the singular values kept at the parent) is replaced by its truncated
+ * SVD, keeping the singular values > tau and at least one per node of
+ * positive rank; core blocks, translation operators and leaf bases are
+ * rotated into the kept singular vectors.  Both SVDs of a child use the
+ * core blocks of its parent as they were before that level's updates.
+ * The result, a new handle on A's tree with ranks <= A's (read them with
+ * hss_ranks), satisfies ||A - C||_2 <= 2 (sqrt(2^p) - 1)/(sqrt(2) - 1) tau
+ * (Prop. A.1); A is only read.  Device scratch of about
+ * 2 (|U| + |V| + |R| + |W| + |B12| + |B21|) + 2 * 64^2 * nnodes doubles is
+ * taken from alloc (or hipMalloc) for the call and released before it
+ * returns.
+ * Errors: -1 NULL A, -2 tau negative, NaN or infinite, -3 incomplete
+ * allocator hooks, -5 NULL out; HSS_ENOMEM, HSS_EHIP.  Orders after earlier
+ * work on the stream and synchronizes it. */
+hss_status hss_compress(const hss_handle *A, double tau, const hss_alloc *alloc,
+                        void *stream, hss_handle **out);
+
+/* hss_ranks: the handle's ranks ku_t, kv_t in heap order (0 at the root)
+ * into caller arrays of 2^(p+1) - 1 entries.  Host only; no device work.
+ * Errors: -1 NULL h, -2 NULL ku, -3 NULL kv. */
+hss_status hss_ranks(const hss_handle *h, int32_t *ku, int32_t *kv);
 
 /* Destination of hss_get_generators: host buffers for the canonical packed
  * arrays (the layout and sizes hss_create reads; a pointer may be NULL only

@@ -45,7 +45,7 @@ Prop. A.1 on dense assemblies; the proper form has orthonormal nested bases;
 a rank-k matrix padded to a rank-2k representation (zero columns in the
 cores) compresses back to rank k; the Hadamard square of a rank-k matrix
 (Sec. 4.4) compresses to rank <= k (k + 1) / 2 (its Khatri-Rao columns are
-symmetric in the two factors); every kept singular value is > tau.
+symmetric in the two factors).
 """
 from __future__ import annotations
 
@@ -88,19 +88,24 @@ def proper_form(H: HSS) -> HSS:
     return HSS(H.n, p, H.leaf_off, ku, kv, D, U, V, R, W, B12, B21)
 
 
-def _truncate(M, tau, k_old):
-    """Left singular vectors and values of M kept by the rule above."""
+def _truncate(M, tau, k_old, record=None, key=None):
+    """Left singular vectors and values of M kept by the rule above (every
+    singular value goes to record[key] when a dict is given)."""
     if M.shape[0] == 0:
         return np.zeros((0, 0)), np.zeros(0)
     Us, s, _ = np.linalg.svd(M, full_matrices=False)
+    if record is not None:
+        record[key] = s
     keep = int(np.sum(s > tau))
     if k_old > 0:
         keep = max(keep, 1)
     return Us[:, :keep], s[:keep]
 
 
-def compress(H: HSS, tau: float) -> HSS:
-    """Recompression with truncation tolerance tau (App. A), on a copy."""
+def compress(H: HSS, tau: float, record=None) -> HSS:
+    """Recompression with truncation tolerance tau (App. A), on a copy.
+    record: optional dict that receives every SVD's singular values, keyed
+    by ("u" or "v", child heap id)."""
     P = proper_form(H)
     nn, p = P.nnodes, P.p
     U = {t: P.U[t].copy() for t in P.U}
@@ -123,8 +128,8 @@ def compress(H: HSS, tau: float) -> HSS:
             for h in range(2):
                 Mr = S[h] if i == 0 else np.hstack([S[h], Rb[h] * su[i]])
                 Mc = St[h] if i == 0 else np.hstack([St[h], Wb[h] * sv[i]])
-                u, s = _truncate(Mr, tau, ku[c[h]])
-                v, sc = _truncate(Mc, tau, kv[c[h]])
+                u, s = _truncate(Mr, tau, ku[c[h]], record, ("u", c[h]))
+                v, sc = _truncate(Mc, tau, kv[c[h]], record, ("v", c[h]))
                 Uh.append(u)
                 Vh.append(v)
                 su[c[h]], sv[c[h]] = s, sc

@@ -1310,6 +1310,35 @@ hss_status new_handle(Plan&& P, const hss_alloc* alloc, hipStream_t s, hss_handl
   return HSS_OK;
 }
 
+// Device scratch of one call from the caller's allocator hooks (or
+// hipMalloc), released when it goes out of scope: every path that leaves
+// its scope must have synchronized the stream first.
+struct TempDev {
+  const hss_alloc* al;
+  std::vector<void*> ptrs;
+  explicit TempDev(const hss_alloc* a) : al(a) {}
+  TempDev(const TempDev&) = delete;
+  TempDev& operator=(const TempDev&) = delete;
+  void* get(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void* q = nullptr;
+    if (al) {
+      q = al->alloc(bytes, al->ctx);
+    } else if (hipMalloc(&q, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      q = nullptr;
+    }
+    if (q) ptrs.push_back(q);
+    return q;
+  }
+  ~TempDev() {
+    for (void* q : ptrs) {
+      if (al) al->free(q, al->ctx);
+      else (void)hipFree(q);
+    }
+  }
+};
+
 // The resident FP32 copy of the generators and ||A||_2, then a stream
 // synchronization (the handle is complete when this returns HSS_OK).
 hss_status finish_handle(hss_handle* h, hipStream_t s) {
@@ -1450,6 +1479,96 @@ hss_status hss_hadamard(const hss_handle* A, const hss_handle* B, const hss_allo
     return st;
   }
   *out = h;
+  return HSS_OK;
+}
+
+hss_status hss_compress(const hss_handle* A, double tau, const hss_alloc* alloc, void* stream,
+                        hss_handle** out) {
+  if (!out) return -5;
+  *out = nullptr;
+  if (!A) return -1;
+  if (!(tau >= 0.0) || std::isinf(tau)) return -2;
+  if (alloc && (!alloc->alloc || !alloc->free)) return -3;
+  const Plan& PA = A->plan;
+  const int32_t nn = PA.nnodes, p = PA.p;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> ku(nn, 0), kv(nn, 0);
+  TempDev tmp(alloc);
+  const int64_t sizes[6] = {PA.nU, PA.nV, PA.nR, PA.nW, PA.nB12, PA.nB21};
+  double* work[6] = {};
+  const size_t slot = (size_t)kMaxRank * kMaxRank;
+  for (int i = 0; i < 6; ++i) work[i] = (double*)tmp.get(sizeof(double) * (size_t)sizes[i]);
+  double* TU = (double*)tmp.get(sizeof(double) * slot * nn);
+  double* TV = (double*)tmp.get(sizeof(double) * slot * nn);
+  double* su = (double*)tmp.get(sizeof(double) * (size_t)kMaxRank * nn);
+  double* sv = (double*)tmp.get(sizeof(double) * (size_t)kMaxRank * nn);
+  int32_t* rk = (int32_t*)tmp.get(sizeof(int32_t) * 4 * (size_t)nn + 8);
+  for (int i = 0; i < 6; ++i)
+    if (!work[i]) return HSS_ENOMEM;
+  if (!TU || !TV || !su || !sv || !rk) return HSS_ENOMEM;
+  hss_status st = HSS_OK;
+  if (p > 0) {
+    for (int i = 0; i < 6; ++i)
+      if (sizes[i] > 0 && hipMemcpyAsync(work[i], A->g64[i + 1], sizeof(double) * sizes[i],
+                                         hipMemcpyDeviceToDevice, s) != hipSuccess)
+        st = HSS_EHIP;
+    launch_fill(reinterpret_cast<double*>(rk), 0.0, 2 * (int64_t)nn, s);
+    const CompressBufs b{A->d_nodes, work[0], work[1], work[2], work[3], work[4], work[5], TU, TV,
+                         su,         sv,      rk,      rk + nn, rk + 2 * nn, rk + 3 * nn};
+    const int leaf0 = (1 << p) - 1;
+    // phase 1: proper form, bottom-up
+    launch_compress(CompressStep::LeafQR, b, leaf0, 1 << p, tau, s);
+    for (int l = p - 1; l >= 1; --l) launch_compress(CompressStep::UpQR, b, (1 << l) - 1, 1 << l, tau, s);
+    launch_compress(CompressStep::Core, b, 0, leaf0, tau, s);
+    // phase 2: truncated SVDs, top-down
+    for (int l = 1; l <= p; ++l) {
+      launch_compress(CompressStep::Svd, b, (1 << l) - 1, 1 << l, tau, s);
+      launch_compress(CompressStep::ApplyParent, b, (1 << (l - 1)) - 1, 1 << (l - 1), tau, s);
+      launch_compress(CompressStep::ApplyChild, b, (1 << l) - 1, 1 << l, tau, s);
+    }
+    if (hipMemcpyAsync(ku.data(), rk + 2 * nn, sizeof(int32_t) * nn, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(kv.data(), rk + 3 * nn, sizeof(int32_t) * nn, hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+      st = HSS_EHIP;
+    if (!st) st = last_launch_status();
+  }
+  if (hipStreamSynchronize(s) != hipSuccess && !st) st = HSS_EHIP;
+  if (st) return st;
+  ku[0] = kv[0] = 0;
+  const hss_tree_desc td{PA.n, p, 0, PA.leaf_off.data(), ku.data(), kv.data()};
+  Plan P;
+  st = build_plan(&td, P, nullptr);
+  if (st) return st > 0 ? st : HSS_EUNSUP;
+  hss_handle* h = nullptr;
+  if ((st = new_handle(std::move(P), alloc, s, &h))) return st;
+  if (PA.nD > 0 && hipMemcpyAsync(h->g64[0], A->g64[0], sizeof(double) * PA.nD,
+                                  hipMemcpyDeviceToDevice, s) != hipSuccess)
+    st = HSS_EHIP;
+  if (!st && p > 0) {
+    const double* wk[6] = {work[0], work[1], work[2], work[3], work[4], work[5]};
+    double* dst[6] = {h->g64[1], h->g64[2], h->g64[3], h->g64[4], h->g64[5], h->g64[6]};
+    launch_compress_gather(A->d_nodes, h->d_nodes, wk, dst, nn, s);
+    st = last_launch_status();
+  }
+  if (!st) st = finish_handle(h, s);
+  if (st) {
+    (void)hipStreamSynchronize(s);
+    hss_destroy(h);
+    return st;
+  }
+  *out = h;
+  return HSS_OK;
+}
+
+hss_status hss_ranks(const hss_handle* h, int32_t* ku, int32_t* kv) {
+  if (!h) return -1;
+  if (!ku) return -2;
+  if (!kv) return -3;
+  for (int32_t t = 0; t < h->plan.nnodes; ++t) {
+    ku[t] = h->plan.nodes[t].ku;
+    kv[t] = h->plan.nodes[t].kv;
+  }
   return HSS_OK;
 }
 

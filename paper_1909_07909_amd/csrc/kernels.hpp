@@ -64,12 +64,31 @@ void launch_ulv(UlvStep step, const KArgs<T, CallSV<T>>& a, int nblocks, int max
                 int max_mp, hipStream_t s);
 
 // Hadamard product C = A o B of two matrices on one tree (kernels_hadamard.hip):
-// the packed D arrays elementwise (nD entries), then one work-group per node
-// for the bases, translation operators and core blocks.  g*[0..6] are the
+// the packed D arrays elementwise (nD entries), then two work-groups per node
+// (row and column side) for the bases, translation operators and core blocks.  g*[0..6] are the
 // FP64 generator arrays D, U, V, R, W, B12, B21; n* the device node tables.
 void launch_hadamard(const NodeInfo* nA, const NodeInfo* nB, const NodeInfo* nC,
                      const double* const gA[7], const double* const gB[7], double* const gC[7],
                      int64_t nD, int32_t nnodes, int32_t p, hipStream_t s);
+
+// HSS recompression (kernels_compress.hip).  Work copies of the generators in
+// the input's packed layout; TU / TV hold kMaxRank x kMaxRank per node (the
+// phase-1 QR factors, then the phase-2 left singular factors), su / sv
+// kMaxRank singular values per node, rku / rkv the ranks after phase 1,
+// nku / nkv after phase 2.  node0, count: the nodes of the launch.
+enum class CompressStep { LeafQR, UpQR, Core, Svd, ApplyParent, ApplyChild };
+struct CompressBufs {
+  const NodeInfo* nodes;
+  double *U, *V, *R, *W, *B12, *B21;
+  double *TU, *TV, *su, *sv;
+  int32_t *rku, *rkv, *nku, *nkv;
+};
+void launch_compress(CompressStep step, const CompressBufs& b, int node0, int count, double tau,
+                     hipStream_t s);
+// Pack the work blocks (work[0..5] = U, V, R, W, B12, B21 in the layout of
+// `in`) at the ranks of `out` into dst[0..5].
+void launch_compress_gather(const NodeInfo* in, const NodeInfo* out, const double* const work[6],
+                            double* const dst[6], int nnodes, hipStream_t s);
 
 // Elementwise / reduction helpers (kernels_util.hip).
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);

@@ -9,10 +9,10 @@
 //
 // Two launches.  The diagonal blocks are a flat elementwise product over the
 // packed D arrays, which have the same layout in A, B and C (same tree): a
-// grid-stride stream of 16-byte loads and stores, bound by HBM.  The bases,
+// stream of 16-byte loads and stores, one vector per thread, bound by HBM.  The bases,
 // translation operators and core blocks (ranks multiply, so these are the
-// only arrays whose shape changes) take one work-group per node; their
-// sources are small and read through the caches.
+// only arrays whose shape changes) take two work-groups per node, one per
+// basis side; their sources are small and read through the caches.
 #include <hip/hip_runtime.h>
 
 #include "hss_internal.hpp"
@@ -23,9 +23,12 @@ namespace hss {
 namespace {
 
 constexpr int kHB = 256;   // threads per work-group
+static_assert(kMaxBlock <= kHB, "a leaf's rows fit one row group of a work-group");
 
-// c[i] = a[i] * b[i], i < n; 16-byte vectors when vec (all three arrays then
-// start on 16-byte boundaries), four vectors in flight per thread.
+// c[i] = a[i] * b[i], i < n: one 16-byte vector per thread when vec (all
+// three arrays then start on 16-byte boundaries) over a grid that covers the
+// array (measured at the plain-copy rate; grid-stride loops with several
+// vectors in flight per thread were slower), scalars otherwise.
 __global__ __launch_bounds__(kHB) void k_hadamard_diag(const double* __restrict__ a,
                                                        const double* __restrict__ b,
                                                        double* __restrict__ c, int64_t n, int vec) {
@@ -36,18 +39,7 @@ __global__ __launch_bounds__(kHB) void k_hadamard_diag(const double* __restrict_
     const double2* a2 = reinterpret_cast<const double2*>(a);
     const double2* b2 = reinterpret_cast<const double2*>(b);
     double2* c2 = reinterpret_cast<double2*>(c);
-    int64_t i = tid;
-    for (; i + 3 * nth < nv; i += 4 * nth) {
-      double2 x[4], y[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        x[u] = a2[i + u * nth];
-        y[u] = b2[i + u * nth];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) c2[i + u * nth] = make_double2(x[u].x * y[u].x, x[u].y * y[u].y);
-    }
-    for (; i < nv; i += nth) {
+    for (int64_t i = tid; i < nv; i += nth) {
       const double2 x = a2[i], y = b2[i];
       c2[i] = make_double2(x.x * y.x, x.y * y.y);
     }
@@ -57,16 +49,20 @@ __global__ __launch_bounds__(kHB) void k_hadamard_diag(const double* __restrict_
   }
 }
 
-// out (rows qa qb x cols) with out(i, a qb + b) = X(i, a) Y(i, b): the
-// transpose Khatri-Rao product of X (m x qa) and Y (m x qb), column-major,
-// ld = m for all three.
+// out (m x qa qb) with out(i, a qb + b) = X(i, a) Y(i, b): the transpose
+// Khatri-Rao product of X (m x qa) and Y (m x qb), column-major, ld = m for
+// all three (m <= 128).  Lane i of a row group holds row i; the G = 256 / m
+// row groups split the columns b of Y, so each thread loads X(i, a) once per
+// a and the stores of a group are contiguous.
 __device__ __forceinline__ void khatri_rao(const double* X, const double* Y, double* out, int m,
                                            int qa, int qb) {
-  const int total = m * qa * qb;
-  for (int e = threadIdx.x; e < total; e += kHB) {
-    const int j = e / m, i = e - j * m;
-    const int a = j / qb, b = j - a * qb;
-    out[e] = X[i + a * m] * Y[i + b * m];
+  const int G = kHB / m;
+  const int i = threadIdx.x % m, gi = threadIdx.x / m;
+  if (gi >= G) return;
+  for (int a = 0; a < qa; ++a) {
+    const double xa = X[i + a * m];
+    double* o = out + (int64_t)a * qb * m + i;
+    for (int bb = gi; bb < qb; bb += G) o[bb * m] = xa * Y[i + bb * m];
   }
 }
 
@@ -93,34 +89,44 @@ struct HadArgs {
   int p;
 };
 
-// one work-group per node (heap id = blockIdx.x)
+// two work-groups per node (heap id = blockIdx.x): blockIdx.y = 0 forms the
+// row-basis side (U, R, B12), 1 the column-basis side (V, W, B21)
 __global__ __launch_bounds__(kHB) void k_hadamard_gen(HadArgs h) {
   const int t = blockIdx.x;
+  const bool col = blockIdx.y != 0;
   const NodeInfo A = h.nA[t], B = h.nB[t], C = h.nC[t];
   if (A.is_leaf) {
     if (h.p == 0) return;
-    khatri_rao(h.AU + A.oU, h.BU + B.oU, h.CU + C.oU, C.m, A.ku, B.ku);
-    khatri_rao(h.AV + A.oV, h.BV + B.oV, h.CV + C.oV, C.m, A.kv, B.kv);
+    if (!col) khatri_rao(h.AU + A.oU, h.BU + B.oU, h.CU + C.oU, C.m, A.ku, B.ku);
+    else khatri_rao(h.AV + A.oV, h.BV + B.oV, h.CV + C.oV, C.m, A.kv, B.kv);
     return;
   }
   const int c1 = 2 * t + 1, c2 = 2 * t + 2;
   const NodeInfo A1 = h.nA[c1], A2 = h.nA[c2], B1 = h.nB[c1], B2 = h.nB[c2];
-  if (t != 0) {
-    // stacked [R_c1; R_c2]: one Kronecker product per child block
-    const int lra = A1.ku + A2.ku, lrb = B1.ku + B2.ku, lrc = A1.ku * B1.ku + A2.ku * B2.ku;
-    kron_block(h.AR + A.oR, lra, A1.ku, A.ku, h.BR + B.oR, lrb, B1.ku, B.ku, h.CR + C.oR, lrc, 0);
-    kron_block(h.AR + A.oR + A1.ku, lra, A2.ku, A.ku, h.BR + B.oR + B1.ku, lrb, B2.ku, B.ku,
-               h.CR + C.oR, lrc, A1.ku * B1.ku);
-    const int lwa = A1.kv + A2.kv, lwb = B1.kv + B2.kv, lwc = A1.kv * B1.kv + A2.kv * B2.kv;
-    kron_block(h.AW + A.oW, lwa, A1.kv, A.kv, h.BW + B.oW, lwb, B1.kv, B.kv, h.CW + C.oW, lwc, 0);
-    kron_block(h.AW + A.oW + A1.kv, lwa, A2.kv, A.kv, h.BW + B.oW + B1.kv, lwb, B2.kv, B.kv,
-               h.CW + C.oW, lwc, A1.kv * B1.kv);
+  if (!col) {
+    if (t != 0) {
+      // stacked [R_c1; R_c2]: one Kronecker product per child block
+      const int lra = A1.ku + A2.ku, lrb = B1.ku + B2.ku, lrc = A1.ku * B1.ku + A2.ku * B2.ku;
+      kron_block(h.AR + A.oR, lra, A1.ku, A.ku, h.BR + B.oR, lrb, B1.ku, B.ku, h.CR + C.oR, lrc,
+                 0);
+      kron_block(h.AR + A.oR + A1.ku, lra, A2.ku, A.ku, h.BR + B.oR + B1.ku, lrb, B2.ku, B.ku,
+                 h.CR + C.oR, lrc, A1.ku * B1.ku);
+    }
+    // B12: ku_c1 x kv_c2
+    kron_block(h.AB12 + A.oB12, A1.ku, A1.ku, A2.kv, h.BB12 + B.oB12, B1.ku, B1.ku, B2.kv,
+               h.CB12 + C.oB12, A1.ku * B1.ku, 0);
+  } else {
+    if (t != 0) {
+      const int lwa = A1.kv + A2.kv, lwb = B1.kv + B2.kv, lwc = A1.kv * B1.kv + A2.kv * B2.kv;
+      kron_block(h.AW + A.oW, lwa, A1.kv, A.kv, h.BW + B.oW, lwb, B1.kv, B.kv, h.CW + C.oW, lwc,
+                 0);
+      kron_block(h.AW + A.oW + A1.kv, lwa, A2.kv, A.kv, h.BW + B.oW + B1.kv, lwb, B2.kv, B.kv,
+                 h.CW + C.oW, lwc, A1.kv * B1.kv);
+    }
+    // B21: ku_c2 x kv_c1
+    kron_block(h.AB21 + A.oB21, A2.ku, A2.ku, A1.kv, h.BB21 + B.oB21, B2.ku, B2.ku, B1.kv,
+               h.CB21 + C.oB21, A2.ku * B2.ku, 0);
   }
-  // B12: ku_c1 x kv_c2, B21: ku_c2 x kv_c1
-  kron_block(h.AB12 + A.oB12, A1.ku, A1.ku, A2.kv, h.BB12 + B.oB12, B1.ku, B1.ku, B2.kv,
-             h.CB12 + C.oB12, A1.ku * B1.ku, 0);
-  kron_block(h.AB21 + A.oB21, A2.ku, A2.ku, A1.kv, h.BB21 + B.oB21, B2.ku, B2.ku, B1.kv,
-             h.CB21 + C.oB21, A2.ku * B2.ku, 0);
 }
 
 }  // namespace
@@ -132,10 +138,8 @@ void launch_hadamard(const NodeInfo* nA, const NodeInfo* nB, const NodeInfo* nC,
     TimedLaunch tl("hadamard_diag", s);
     const bool vec = ((reinterpret_cast<uintptr_t>(gA[0]) | reinterpret_cast<uintptr_t>(gB[0]) |
                        reinterpret_cast<uintptr_t>(gC[0])) & 15) == 0;
-    // enough work-groups to fill every compute unit several times over, each
-    // thread streaming a few 16-byte vectors per pass
-    const int64_t want = (nD / 2 + 4 * kHB - 1) / (4 * kHB);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 32));
+    const int64_t items = vec ? nD / 2 : nD;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((items + kHB - 1) / kHB, 1 << 30));
     hipLaunchKernelGGL(k_hadamard_diag, dim3(grid), dim3(kHB), 0, s, gA[0], gB[0], gC[0], nD,
                        vec ? 1 : 0);
   }
@@ -143,7 +147,7 @@ void launch_hadamard(const NodeInfo* nA, const NodeInfo* nB, const NodeInfo* nC,
     TimedLaunch tl("hadamard_gen", s);
     HadArgs h{nA, nB, nC, gA[1], gA[2], gA[3], gA[4], gA[5], gA[6], gB[1], gB[2], gB[3],
               gB[4], gB[5], gB[6], gC[1], gC[2], gC[3], gC[4], gC[5], gC[6], p};
-    hipLaunchKernelGGL(k_hadamard_gen, dim3(nnodes), dim3(kHB), 0, s, h);
+    hipLaunchKernelGGL(k_hadamard_gen, dim3(nnodes, 2), dim3(kHB), 0, s, h);
   }
 }
 

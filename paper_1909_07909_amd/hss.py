@@ -30,6 +30,7 @@ EXPORTS = (
     "hss_batch_ulv_factor", "hss_batch_ulv_solve", "hss_status_str", "hss_timing_enable",
     "hss_timing_report", "hss_matmul_noalloc", "hss_matmul_noalloc_max_rhs", "hss_autotune",
     "hss_tune_table", "hss_tune_load", "hss_tune_reset", "hss_hadamard", "hss_get_generators",
+    "hss_compress", "hss_ranks",
 )
 
 Q_N, Q_P, Q_RESIDENT_BYTES, Q_NORM2, Q_GEN_ENTRIES, Q_FACTOR_ENTRIES = range(6)
@@ -95,6 +96,8 @@ def lib() -> C.CDLL:
     L.hss_destroy.argtypes = [vp]
     L.hss_hadamard.argtypes = [vp, vp, C.POINTER(Alloc), vp, C.POINTER(vp)]
     L.hss_get_generators.argtypes = [vp, C.POINTER(GenOut), vp]
+    L.hss_compress.argtypes = [vp, C.c_double, C.POINTER(Alloc), vp, C.POINTER(vp)]
+    L.hss_ranks.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.hss_matmul.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp]
     L.hss_matmul_noalloc.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp]
     L.hss_matmul_noalloc_max_rhs.argtypes = [vp, i32]
@@ -357,6 +360,32 @@ class HSSMatrix:
         out._keep = None
         out._adopt(h, self.n, self.p, self.leaf_off, self.ku.astype(np.int64) * other.ku,
                    self.kv.astype(np.int64) * other.kv)
+        return out
+
+    def compress(self, tau=None, rel=None, stream=None, alloc="torch"):
+        """Recompression (hss_compress) with absolute tolerance tau, or
+        tau = rel * ||A||_2 (the handle's estimate); a new HSSMatrix."""
+        if (tau is None) == (rel is None):
+            raise ValueError("give exactly one of tau and rel")
+        if tau is None:
+            tau = float(rel) * self.norm2()
+        if isinstance(alloc, str):
+            if alloc != "torch":
+                raise ValueError(f"unknown allocator {alloc!r}")
+            alloc = TORCH_ALLOC
+        h = C.c_void_p()
+        code = lib().hss_compress(self.h, float(tau), C.byref(alloc) if alloc else None,
+                                  _stream(stream), C.byref(h))
+        _check(code, "hss_compress")
+        nn = 2 ** (self.p + 1) - 1
+        ku = np.zeros(nn, dtype=np.int32)
+        kv = np.zeros(nn, dtype=np.int32)
+        _check(lib().hss_ranks(h, ku.ctypes.data_as(C.POINTER(C.c_int32)),
+                               kv.ctypes.data_as(C.POINTER(C.c_int32))), "hss_ranks")
+        out = HSSMatrix.__new__(HSSMatrix)
+        out._alloc = alloc
+        out._keep = None
+        out._adopt(h, self.n, self.p, self.leaf_off, ku, kv)
         return out
 
     def packed_sizes(self):

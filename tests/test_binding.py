@@ -114,3 +114,14 @@ def test_hadamard_and_readback_null_arguments():
     assert h.value is None
     assert L.hss_get_generators(None, None, None) == -1
     assert hss.status_str(-2) == "invalid argument"
+
+
+def test_compress_and_ranks_null_arguments():
+    """hss_compress and hss_ranks reject NULL or invalid arguments before any
+    device work."""
+    import ctypes as C
+    L = hss.lib()
+    h = C.c_void_p()
+    assert L.hss_compress(None, 0.0, None, None, None) == -5
+    assert L.hss_compress(None, 0.0, None, None, C.byref(h)) == -1
+    assert L.hss_ranks(None, None, None) == -1
