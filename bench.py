@@ -380,6 +380,7 @@ def main():
         "fresh_nrhs32": wide,
         "matmul_fp64": mm,
         "hadamard": had,
+        "compress": had.pop("compress", None),
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": kernels[:12],
@@ -397,6 +398,7 @@ def hadamard_measure(log, reps=5, ka=8, kb=4):
     from events around each launch, against the generator bytes each kernel
     reads and writes, and the whole hss_hadamard call (which also makes the
     FP32 copy and the ||C||_2 estimate and synchronizes)."""
+    import numpy as np
     import torch
 
     from paper_1909_07909_amd import hss, inputs
@@ -434,6 +436,33 @@ def hadamard_measure(log, reps=5, ka=8, kb=4):
     out["gbps"] = round((diag_bytes + gen_bytes) / tot_us / 1e3, 1)
     log(f"[bench] hadamard: kernels {tot_us:.1f} us ({out['gbps']} GB/s), "
         f"whole call {call_ms:.2f} ms")
+
+    # recompression of the product (its ranks are ka*kb, more than the
+    # singular values of its blocks need) at tau = 1e-8 ||C||_2
+    C = A.hadamard(B)
+    tau = 1e-8 * C.norm2()
+    Cc = C.compress(tau=tau)   # warm-up
+    del Cc
+    torch.cuda.synchronize()
+    hss.timing_enable(True)
+    hss.timing_report(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Cc = C.compress(tau=tau)
+    call_c = (time.perf_counter() - t0) * 1e3 / reps
+    repc = hss.timing_report(reset=True)
+    hss.timing_enable(False)
+    k_in = float(np.mean(C.ku[1:]))
+    k_out = float(np.mean(Cc.ku[1:]))
+    comp = {"workload": f"compress C (n={N}, leaf={LEAF}, rank {ka * kb}) at tau = 1e-8 ||C||_2",
+            "call_ms": round(call_c, 3), "mean_rank_in": round(k_in, 2),
+            "mean_rank_out": round(k_out, 2),
+            "max_rank_out": int(max(Cc.ku.max(), Cc.kv.max())),
+            "kernels_ms": {d["kernel"]: round(d["total_ms"] / reps, 3)
+                           for d in repc if d["kernel"].startswith("compress")}}
+    log(f"[bench] compress: {call_c:.2f} ms per call, mean rank {k_in:.1f} -> {k_out:.1f}; "
+        + ", ".join(f"{k} {v:.2f} ms" for k, v in comp["kernels_ms"].items()))
+    out["compress"] = comp
     return out
 
 
