@@ -347,7 +347,7 @@ void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T*
         launch_mmw<T>(MMWStep::Down, a, 1 << l, (int)nrhs, s);
       }
       a.node0 = level_first(p);
-      launch_mmw<T>(MMWStep::LeafOut, a, 1 << p, (int)nrhs, s);
+      launch_mmw<T>(MMWStep::LeafOut, a, 1 << p, (int)nrhs, s, h->plan.level_max_mp[p]);
       return;
     }
     if (p > 0) {
@@ -787,7 +787,7 @@ hss_status run_mm_n(BatchScratch& BS, const BatchPlan<T>& bp, hss_handle* const*
       const auto& r = bp.L.ranges[k++];
       a.tasks = bp.tasks + r.off;
       a.ntasks = r.cnt;
-      launch_mmw<T>(stp, a, r.cnt, (int)maxr, s);
+      launch_mmw<T>(stp, a, r.cnt, (int)maxr, s, r.max_mp);
     };
     go(MMWStep::LeafUp);
     for (int q = 1; q <= bp.pmax; ++q) go(MMWStep::Up);

@@ -284,13 +284,92 @@ __global__ __launch_bounds__(kWT) void k_mmw_leaf_out(KArgs<T, CallMM<T>> a) {
   }
 }
 
+// Y = D X + U y^ for a tile of at most 16 columns: row r of the leaf on lane
+// r of one of G = 256 / RW row groups (RW = 64 for leaves of at most 64 rows,
+// else 128), the inner dimension (columns of D, then of U) split over the
+// groups, the G partial sums reduced through LDS: every entry of D and U is
+// read once, by a coalesced column read.
+template <typename T, bool BATCH, int RW>
+__global__ __launch_bounds__(kWT) void k_mmw_leaf_out_n(KArgs<T, CallMM<T>> a) {
+  constexpr int G = kWT / RW;
+  constexpr int NC = 16;
+  constexpr int PP = NC + 1;   // pitch of the partial sums
+  // the X and y^ tiles, then (after a barrier) the partial sums in the same
+  // space: the smaller footprint keeps more work-groups per compute unit
+  constexpr int kTiles = (kMaxBlock + kWR) * NC, kParts = kWT * PP;
+  __shared__ __align__(16) T lds[kTiles > kParts ? kTiles : kParts];
+  T* Xs = lds;
+  T* Ys = lds + kMaxBlock * NC;
+  T* Ps = lds;
+  Inst<T> I; CallMM<T> C; int t;
+  resolve<BATCH>(a, I, C, t);
+  if (gated_off(C.gate)) return;
+  const int c0 = blockIdx.y * NC;
+  const NodeInfo nd = I.nodes[t];
+  const int m = nd.m, ku = I.p > 0 ? nd.ku : 0, nc = min(NC, C.nrhs - c0);
+  const int tid = threadIdx.x;
+  // X and y^ tiles, columns past nc zero
+  for (int o = tid; o < m * NC; o += kWT) {
+    const int c = o / m, k = o - c * m;
+    Xs[k * NC + c] = c < nc ? C.X[nd.row0 + k + (int64_t)(c0 + c) * C.ldx] : T(0);
+  }
+  for (int o = tid; o < ku * NC; o += kWT) {
+    const int c = o / ku, j = o - c * ku;
+    Ys[j * NC + c] = c < nc ? I.yh[nd.oyh + j + (int64_t)(c0 + c) * I.ldm] : T(0);
+  }
+  __syncthreads();
+  const int r = tid % RW, h = tid / RW;
+  const int rc = min(r, m - 1);
+  T acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = T(0);
+  {
+    const int kb = (m + G - 1) / G, k0 = h * kb, k1 = min(m, k0 + kb);
+    const T* Dr = I.D + nd.oD + rc;
+    constexpr int KB = 8;   // columns of D in flight
+    for (int kk = k0; kk < k1; kk += KB) {
+      T dv[KB];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) dv[u] = Dr[(int64_t)min(kk + u, k1 - 1) * m];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const T d = kk + u < k1 ? dv[u] : T(0);
+        const T* xk = Xs + min(kk + u, m - 1) * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += d * xk[c];
+      }
+    }
+  }
+  if (ku > 0) {
+    const int jb = (ku + G - 1) / G, j0 = h * jb, j1 = min(ku, j0 + jb);
+    const T* Ur = I.U + nd.oU + rc;
+    for (int j = j0; j < j1; ++j) {
+      const T u = Ur[(int64_t)j * m];
+      const T* yk = Ys + j * NC;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] += u * yk[c];
+    }
+  }
+  __syncthreads();   // every read of the tiles done
+#pragma unroll
+  for (int c = 0; c < NC; ++c) Ps[tid * PP + c] = acc[c];
+  __syncthreads();
+  for (int o = tid; o < RW * NC; o += kWT) {
+    const int c = o / RW, rr = o - c * RW;
+    T sum = T(0);
+#pragma unroll
+    for (int g = 0; g < G; ++g) sum += Ps[(g * RW + rr) * PP + c];
+    if (rr < m && c < nc) C.Y[nd.row0 + rr + (int64_t)(c0 + c) * C.ldy] = sum;
+  }
+}
+
 }  // namespace
 
 bool mmw_fits(int max_leaf, int max_k) { return max_leaf <= kMaxBlock && max_k <= kWR; }
 
 template <typename T>
 void launch_mmw(MMWStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrhs,
-                hipStream_t s) {
+                hipStream_t s, int max_m) {
   if (nblocks <= 0 || nrhs <= 0) return;
   static const char* n64[] = {"mmw_leaf_up_f64", "mmw_up_f64", "mmw_down_f64", "mmw_leaf_out_f64"};
   static const char* n32[] = {"mmw_leaf_up_f32", "mmw_up_f32", "mmw_down_f32", "mmw_leaf_out_f32"};
@@ -305,14 +384,28 @@ void launch_mmw(MMWStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
     case MMWStep::LeafUp: HSS_MMW(k_mmw_leaf_up, g); break;
     case MMWStep::Up: HSS_MMW(k_mmw_up, g); break;
     case MMWStep::Down: HSS_MMW(k_mmw_down, g); break;
-    case MMWStep::LeafOut: HSS_MMW(k_mmw_leaf_out, gl); break;
+    case MMWStep::LeafOut:
+      if (nrhs <= 16) {
+        // narrow tiles: every row lane and every read of D and U useful
+        const dim3 gn(nblocks, 1);
+        if (max_m <= 64) {
+          if (batch) hipLaunchKernelGGL((k_mmw_leaf_out_n<T, true, 64>), gn, b, 0, s, a);
+          else hipLaunchKernelGGL((k_mmw_leaf_out_n<T, false, 64>), gn, b, 0, s, a);
+        } else {
+          if (batch) hipLaunchKernelGGL((k_mmw_leaf_out_n<T, true, 128>), gn, b, 0, s, a);
+          else hipLaunchKernelGGL((k_mmw_leaf_out_n<T, false, 128>), gn, b, 0, s, a);
+        }
+      } else {
+        HSS_MMW(k_mmw_leaf_out, gl);
+      }
+      break;
   }
 #undef HSS_MMW
 }
 
 template void launch_mmw<double>(MMWStep, const KArgs<double, CallMM<double>>&, int, int,
-                                 hipStream_t);
+                                 hipStream_t, int);
 template void launch_mmw<float>(MMWStep, const KArgs<float, CallMM<float>>&, int, int,
-                                hipStream_t);
+                                hipStream_t, int);
 
 }  // namespace hss

@@ -1053,8 +1053,11 @@ void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int 
                      : (step == UlvStep::Fwd || step == UlvStep::FwdOp ? 0 : 2) + (leafy ? 1 : 0);
   TimedLaunch tl((sizeof(T) == 8 ? nm64 : nm32)[ni], s);
   // columns per wavefront: 4 when there are enough columns to share the factor
-  // reads, unless the caller chose (a tuned choice)
-  const int cpw = a.cpw == 1 || a.cpw == 4 ? a.cpw : (ncols >= 4 ? 4 : 1);
+  // reads (8 in batched calls of 8 or more columns, where there are nodes
+  // enough to fill the chip with half the wavefronts), unless the caller
+  // chose (a tuned choice)
+  const int cpw = a.cpw == 1 || a.cpw == 4 || a.cpw == 8 ? a.cpw
+                : (ncols >= 8 && batch ? 8 : (ncols >= 4 ? 4 : 1));
   const int cgroups = (ncols + cpw - 1) / cpw;
   dim3 gridw((nitems + kSW - 1) / kSW, cgroups), blockw(kSW * 64);
   // eight wavefronts (one staging round trip) for the root and for the
@@ -1067,14 +1070,17 @@ void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int 
   if (batch) hipLaunchKernelGGL((K<T, true, ST, CP>), G, B, sm, s, b);            \
   else hipLaunchKernelGGL((K<T, false, ST, CP>), G, B, sm, s, b);
 #define HSS_SL2(K, ST, G, B)                 \
-  if (cpw == 4) { HSS_SL(K, ST, 4, G, B) }   \
+  if (cpw == 8) { HSS_SL(K, ST, 8, G, B) }   \
+  else if (cpw == 4) { HSS_SL(K, ST, 4, G, B) }   \
   else { HSS_SL(K, ST, 1, G, B) }
   switch (step) {
     case UlvStep::FwdOp: {
-      const int g4 = (cgroups + kOpW - 1) / kOpW;
+      // at most four columns per wavefront here (eight spill the record products)
+      const int cpo = cpw == 8 ? 4 : cpw;
+      const int g4 = ((ncols + cpo - 1) / cpo + kOpW - 1) / kOpW;
       const dim3 go(nitems, g4), bo(kOpW * 64);
-      const size_t smo = (size_t)fwd_op_lds_elems(cpw) * sizeof(T);
-      if (cpw == 4) {
+      const size_t smo = (size_t)fwd_op_lds_elems(cpo) * sizeof(T);
+      if (cpo == 4) {
         if (batch) hipLaunchKernelGGL((k_sv_fwd_op<T, true, 4>), go, bo, smo, s, b);
         else hipLaunchKernelGGL((k_sv_fwd_op<T, false, 4>), go, bo, smo, s, b);
       } else {
@@ -1092,7 +1098,10 @@ void launch_solve_w(UlvStep step, const KArgs<T, CallSV<T>>& a, int nitems, int 
       else { HSS_SL2(k_sv_bwd_w, false, gridw, blockw) }
       break;
     case UlvStep::Root:
-      if (cpw == 4) {
+      if (cpw == 8) {
+        if (batch) hipLaunchKernelGGL((k_sv_root_w<T, true, 8>), grid1, block1, sm, s, b);
+        else hipLaunchKernelGGL((k_sv_root_w<T, false, 8>), grid1, block1, sm, s, b);
+      } else if (cpw == 4) {
         if (batch) hipLaunchKernelGGL((k_sv_root_w<T, true, 4>), grid1, block1, sm, s, b);
         else hipLaunchKernelGGL((k_sv_root_w<T, false, 4>), grid1, block1, sm, s, b);
       } else {
