@@ -337,7 +337,7 @@ void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T*
     if (wide) {
       // wide blocks: one launch per level
       a.node0 = level_first(p);
-      launch_mmw<T>(MMWStep::LeafUp, a, 1 << p, (int)nrhs, s);
+      launch_mmw<T>(MMWStep::LeafUp, a, 1 << p, (int)nrhs, s, h->plan.level_max_mp[p]);
       for (int l = p - 1; l >= 0; --l) {
         a.node0 = level_first(l);
         launch_mmw<T>(MMWStep::Up, a, 1 << l, (int)nrhs, s);

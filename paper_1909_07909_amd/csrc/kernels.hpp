@@ -36,7 +36,7 @@ enum class MMWStep { LeafUp, Up, Down, LeafOut };
 bool mmw_fits(int max_leaf, int max_k);
 template <typename T>
 void launch_mmw(MMWStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrhs,
-                hipStream_t s, int max_m = kMaxBlock);   // max_m: the largest leaf (LeafOut)
+                hipStream_t s, int max_m = kMaxBlock);   // max_m: the largest leaf (LeafUp, LeafOut)
 enum class UlvStep { Merge, Factor, RootLU, Fwd, Root, Bwd, FwdOp };
 
 // Step 1 (QL / LQ) on one level of blocks, register-resident (kernels_factor.hip).

@@ -69,14 +69,16 @@ __device__ __forceinline__ void axpy8(T (&s)[8], T coef, const T* x) {
 }
 
 // x^_i = V_i^T X_i for leaf i and columns c0 .. c0 + kWC - 1: wavefront w sums
-// rows 32w .. 32w + 31 of V and X; lane (a = lane % 32, half h = lane / 32)
-// keeps x^[a, 8h .. 8h + 7]; the four partial sums meet in LDS.
-template <typename T, bool BATCH>
+// a quarter of the rows of V and X (rows w kb .. w kb + kb - 1, kb = m / 4
+// rounded up); lane (a = lane % 32, half h = lane / 32) keeps
+// x^[a, 8h .. 8h + 7]; the four partial sums meet in LDS.  MR: the largest
+// leaf the launch takes (64 or 128), which sizes the LDS tiles.
+template <typename T, bool BATCH, int MR>
 __global__ __launch_bounds__(kWT) void k_mmw_leaf_up(KArgs<T, CallMM<T>> a) {
-  __shared__ T Vs[kMaxBlock * (kWR + 1)];              // Vs[k][a] (row k of V)
-  __shared__ __align__(16) T Xs[kMaxBlock * kXR];       // Xs[k][c]
+  __shared__ T Vs[MR * (kWR + 1)];              // Vs[k][a] (row k of V)
+  __shared__ __align__(16) T Xs[MR * kXR];       // Xs[k][c]
   T* Ps = Vs;   // the four partial sums, once V has been read
-  static_assert(4 * kWR * kWC <= kMaxBlock * (kWR + 1), "partial sums fit in Vs");
+  static_assert(4 * kWR * kWC <= MR * (kWR + 1), "partial sums fit in Vs");
   Inst<T> I; CallMM<T> C; int t;
   resolve<BATCH>(a, I, C, t);
   if (gated_off(C.gate)) return;
@@ -84,8 +86,8 @@ __global__ __launch_bounds__(kWT) void k_mmw_leaf_up(KArgs<T, CallMM<T>> a) {
   const NodeInfo nd = I.nodes[t];
   const int m = nd.m, kv = nd.kv, nc = min(kWC, C.nrhs - c0);
   {
-    Stage<T, kMaxBlock * kWR / kWT, true> sv;
-    Stage<T, kMaxBlock * kWC / kWT, true> sx;
+    Stage<T, MR * kWR / kWT, true> sv;
+    Stage<T, MR * kWC / kWT, true> sx;
     sv.load(I.V + nd.oV, m, m, kv);
     sx.load(C.X + nd.row0 + (int64_t)c0 * C.ldx, C.ldx, m, nc);
     sv.store(Vs, kWR + 1, m, kv);
@@ -97,8 +99,8 @@ __global__ __launch_bounds__(kWT) void k_mmw_leaf_up(KArgs<T, CallMM<T>> a) {
   T s[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) s[c] = T(0);
-  const int k1 = min(32 * w + 32, m);
-  for (int k = 32 * w; k < k1; ++k) axpy8(s, Vs[k * (kWR + 1) + r], Xs + k * kXR + 8 * h);
+  const int kb = (m + 3) >> 2, k1 = min(kb * w + kb, m);
+  for (int k = kb * w; k < k1; ++k) axpy8(s, Vs[k * (kWR + 1) + r], Xs + k * kXR + 8 * h);
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < 8; ++c) Ps[(w * kWR + r) * kWC + 8 * h + c] = s[c];
@@ -381,7 +383,15 @@ void launch_mmw(MMWStep step, const KArgs<T, CallMM<T>>& a, int nblocks, int nrh
   if (batch) hipLaunchKernelGGL((K<T, true>), G, b, 0, s, a);          \
   else hipLaunchKernelGGL((K<T, false>), G, b, 0, s, a);
   switch (step) {
-    case MMWStep::LeafUp: HSS_MMW(k_mmw_leaf_up, g); break;
+    case MMWStep::LeafUp:
+      if (max_m <= 64) {
+        if (batch) hipLaunchKernelGGL((k_mmw_leaf_up<T, true, 64>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_mmw_leaf_up<T, false, 64>), g, b, 0, s, a);
+      } else {
+        if (batch) hipLaunchKernelGGL((k_mmw_leaf_up<T, true, kMaxBlock>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_mmw_leaf_up<T, false, kMaxBlock>), g, b, 0, s, a);
+      }
+      break;
     case MMWStep::Up: HSS_MMW(k_mmw_up, g); break;
     case MMWStep::Down: HSS_MMW(k_mmw_down, g); break;
     case MMWStep::LeafOut:
