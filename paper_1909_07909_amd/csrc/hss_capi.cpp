@@ -1067,8 +1067,10 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
   void* dsegp = nullptr;
   if ((st = scratch_upload(BS, segbytes, s, &dsegp))) return st;
   IRSeg* dsegs = reinterpret_cast<IRSeg*>(dsegp);
+  int maxc = 0;
+  for (int j = 0; j < count; ++j) maxc = std::max(maxc, (int)nrhs[j]);
   auto ir = [&](int op, bool gated = false, int step = 0) {
-    launch_ir_batch(op, dsegs, count, maxn, gated, step, opt.max_refine, s);
+    launch_ir_batch(op, dsegs, count, maxn, maxc, gated, step, opt.max_refine, s);
   };
   ir(IR_ZERO_ALL);
   if (need_eta) ir(IR_SAVE_B0);

@@ -165,7 +165,9 @@ enum IROp {
 };
 // gated: instances whose gate (st[kStGate]) is 0 are skipped.  step and
 // max_refine: the refinement step a check (IR_ETA) belongs to.
-void launch_ir_batch(int op, const IRSeg* segs, int count, int64_t max_n, bool gated, int step,
-                     int max_refine, hipStream_t s);
+// max_cols: the largest nrhs of the instances (per-column passes take one
+// grid slice per column).
+void launch_ir_batch(int op, const IRSeg* segs, int count, int64_t max_n, int max_cols,
+                     bool gated, int step, int max_refine, hipStream_t s);
 
 }  // namespace hss

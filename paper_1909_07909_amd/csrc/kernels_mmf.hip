@@ -184,6 +184,9 @@ struct NodeStep {
   }
 };
 
+template <typename T>
+__device__ __forceinline__ T tsum8_dpp(T (&v)[8]);
+
 // One work-group per subtree of 2^h leaves (h = min(kUpH, p)), rooted at node
 // g of level p - h.  Each wavefront projects its leaves (x^_i = V_i^T X_i),
 // the subtree's internal nodes are then taken bottom-up inside the
@@ -234,14 +237,19 @@ __global__ __launch_bounds__(kUT) void k_mmf_up(KArgs<T, CallMM<T>> a) {
           va[u] = buf_load<T>(Vr, o0, (uint32_t)(b + u) * cs);   // columns >= kv read zero
           vb[u] = buf_load<T>(Vr, o1, (uint32_t)(b + u) * cs);
         }
+        // eight columns of V per transposed sum: lane j < 8 ends with the
+        // total for column b + 8 hf + j
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          if (b + u < kv) {
+        for (int c = 0; c < MC; ++c) {
+          if (c < nc) {
 #pragma unroll
-            for (int c = 0; c < MC; ++c) {
-              if (c < nc) {
-                const T sv = wave_sum(va[u] * x0[c] + vb[u] * x1[c]);
-                if (lane == 0) out[b + u + c * kMaxRank] = sv;
+            for (int hf = 0; hf < 2; ++hf) {
+              if (b + 8 * hf < kv) {
+                T pv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) pv[u] = va[8 * hf + u] * x0[c] + vb[8 * hf + u] * x1[c];
+                const T sv = tsum8_dpp(pv);
+                if (lane < 8 && b + 8 * hf + lane < kv) out[b + 8 * hf + lane + c * kMaxRank] = sv;
               }
             }
           }

@@ -292,7 +292,7 @@ __global__ void k_ir_batch(int op, const IRSeg* __restrict__ segs, int count, in
   double* outv = eta + nr;
   const int64_t i0 = blockIdx.x * (int64_t)kB + threadIdx.x, st = (int64_t)gridDim.x * kB;
   if (op == IR_ZERO_ALL || op == IR_ZERO) {
-    if (blockIdx.x == 0)
+    if (blockIdx.x == 0 && blockIdx.z == 0)
       for (int j = threadIdx.x; j < 7 * nr; j += kB) {
         const int blk = j / nr;   // 0 rr, 1 xx, 2 bb, 3 rmax, 4 bmax, 5 eta, 6 out
         if (op == IR_ZERO_ALL || blk == 0 || blk == 1 || blk == 3) S.stats[j] = 0.0;
@@ -300,7 +300,7 @@ __global__ void k_ir_batch(int op, const IRSeg* __restrict__ segs, int count, in
     return;
   }
   if (op == IR_ETA) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
       double mx = 0.0;
       for (int j = 0; j < nr; ++j) {
         const double den = S.norm2 * sqrt(xx[j]) + sqrt(bb[j]);
@@ -315,7 +315,7 @@ __global__ void k_ir_batch(int op, const IRSeg* __restrict__ segs, int count, in
     return;
   }
   if (op == IR_INFO) {
-    if (blockIdx.x != 0 || !S.info) return;
+    if (blockIdx.x != 0 || blockIdx.z != 0 || !S.info) return;
     char* info = static_cast<char*>(S.info);
     double* hd = reinterpret_cast<double*>(info);
     int32_t* hi = reinterpret_cast<int32_t*>(info + 16);
@@ -338,7 +338,10 @@ __global__ void k_ir_batch(int op, const IRSeg* __restrict__ segs, int count, in
     }
     return;
   }
-  for (int j = 0; j < nr; ++j) {
+  {
+    // one column per grid slice: blockIdx.z
+    const int j = blockIdx.z;
+    if (j >= nr) return;
     double* Bj = S.B + j * S.ldb;
     double* b0 = S.b0 + j * n;
     double* rs = S.res + j * n;
@@ -386,10 +389,14 @@ __global__ void k_ir_batch(int op, const IRSeg* __restrict__ segs, int count, in
 }
 }  // namespace
 
-void launch_ir_batch(int op, const IRSeg* segs, int count, int64_t max_n, bool gated, int step,
-                     int max_refine, hipStream_t s) {
+void launch_ir_batch(int op, const IRSeg* segs, int count, int64_t max_n, int max_cols,
+                     bool gated, int step, int max_refine, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ir_batch, dim3(grid_for(max_n, 64), count), dim3(kB), 0, s, op, segs,
+  // the per-column passes take one grid slice per column (z); the zeroing,
+  // check and report passes one slice
+  const bool per_col = !(op == IR_ZERO_ALL || op == IR_ZERO || op == IR_ETA || op == IR_INFO);
+  const int gz = per_col ? std::max(max_cols, 1) : 1;
+  hipLaunchKernelGGL(k_ir_batch, dim3(grid_for(max_n, 64), count, gz), dim3(kB), 0, s, op, segs,
                      count, gated ? 1 : 0, step, max_refine);
 }
 
