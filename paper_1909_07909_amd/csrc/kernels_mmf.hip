@@ -988,10 +988,16 @@ struct DownMap {
   }
 };
 
+// KR <= 32: the row of R is prefetched into registers; above that (64 FP64
+// coefficients would take half the register file) it is read from the cache
+// when the slot is applied.
 template <typename T, int KR, int DC>
 struct DownSlot {
+  static constexpr bool kRegR = KR <= 32;
   int d = 0, j = 0, i = 0, ku = 0;   // level (0: none), position, row, rank of the node
-  T r[KR];
+  T r[kRegR ? KR : 1];
+  const T* rp = nullptr;   // the row of R (stride rs, rn coefficients) when not in registers
+  int rs = 0, rn = 0;
   T yc[DC];
 };
 
@@ -1027,24 +1033,35 @@ __device__ __forceinline__ void down_slot_load(const Inst<T>& I, const DownMap& 
   const bool live = have & (i < nn.ku) & (nt.ku > 0);   // rows ku .. KR-1 are written as zero
   const int ic = max(min(i, nn.ku - 1), 0);
   const T* Rr = I.R + nt.oR + ro + ic;
+  if constexpr (!DownSlot<T, KR, DC>::kRegR) {
+    sl.rp = Rr;
+    sl.rs = kk;
+    sl.rn = (live && nn.ku > 0) ? min(nt.ku, KR) : 0;
+  }
   if (nn.ku > 0 && nt.ku > 0) {
+    if constexpr (DownSlot<T, KR, DC>::kRegR) {
 #pragma unroll
-    for (int l = 0; l < KR; ++l) {
-      const T v = Rr[(int64_t)min(l, nt.ku - 1) * kk];
-      sl.r[l] = (l < nt.ku) ? v : T(0);
+      for (int l = 0; l < KR; ++l) {
+        const T v = Rr[(int64_t)min(l, nt.ku - 1) * kk];
+        sl.r[l] = (l < nt.ku) ? v : T(0);
+      }
     }
     const T* yc = I.yh + nn.oyh + ic + (int64_t)c0 * I.ldm;
 #pragma unroll
     for (int c = 0; c < DC; ++c) sl.yc[c] = yc[(int64_t)min(c, nc - 1) * I.ldm];
   } else {
+    if constexpr (DownSlot<T, KR, DC>::kRegR) {
 #pragma unroll
-    for (int l = 0; l < KR; ++l) sl.r[l] = T(0);
+      for (int l = 0; l < KR; ++l) sl.r[l] = T(0);
+    }
 #pragma unroll
     for (int c = 0; c < DC; ++c) sl.yc[c] = T(0);
   }
   if (!live) {
+    if constexpr (DownSlot<T, KR, DC>::kRegR) {
 #pragma unroll
-    for (int l = 0; l < KR; ++l) sl.r[l] = T(0);
+      for (int l = 0; l < KR; ++l) sl.r[l] = T(0);
+    }
 #pragma unroll
     for (int c = 0; c < DC; ++c) sl.yc[c] = T(0);
   }
@@ -1059,13 +1076,27 @@ __device__ __forceinline__ void down_slot_apply(const DownSlot<T, KR, DC>& sl, i
                                                 const T* src, T* dst, int64_t blk) {
   const T* ps = src + (int64_t)(sl.j >> 1) * blk;
   T* o = dst + (int64_t)sl.j * blk + sl.i;
+  if constexpr (DownSlot<T, KR, DC>::kRegR) {
 #pragma unroll
-  for (int c = 0; c < DC; ++c) {
-    if (c >= nc) break;
-    T acc = sl.yc[c];
+    for (int c = 0; c < DC; ++c) {
+      if (c >= nc) break;
+      T acc = sl.yc[c];
 #pragma unroll
-    for (int l = 0; l < KR; ++l) acc += sl.r[l] * ps[l + c * kMaxRank];
-    o[c * kMaxRank] = sl.i < sl.ku ? acc : T(0);
+      for (int l = 0; l < KR; ++l) acc += sl.r[l] * ps[l + c * kMaxRank];
+      o[c * kMaxRank] = sl.i < sl.ku ? acc : T(0);
+    }
+  } else {
+    T acc[DC];
+#pragma unroll
+    for (int c = 0; c < DC; ++c) acc[c] = sl.yc[c];
+    for (int l = 0; l < sl.rn; ++l) {
+      const T rv = sl.rp[(int64_t)l * sl.rs];
+#pragma unroll
+      for (int c = 0; c < DC; ++c) acc[c] += rv * ps[l + c * kMaxRank];
+    }
+#pragma unroll
+    for (int c = 0; c < DC; ++c)
+      if (c < nc) o[c * kMaxRank] = sl.i < sl.ku ? acc[c] : T(0);
   }
 }
 
