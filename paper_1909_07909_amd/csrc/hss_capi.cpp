@@ -805,6 +805,60 @@ hss_status run_mm_n(BatchScratch& BS, const BatchPlan<T>& bp, hss_handle* const*
   return last_launch_status();
 }
 
+// A batched op-N product split by rank class: instances whose ranks are all
+// <= 32 (per-level wide kernels or the one-wavefront climb) and those with a
+// larger rank (the general kernels), one plan per class, run back to back.
+// One instance of rank 64 would otherwise send every instance of the batch
+// down the general kernels.
+template <typename T>
+struct MMSplit {
+  BatchPlan<T> bp[2];
+  std::vector<int> idx[2];
+};
+
+template <typename T>
+hss_status plan_mm_split(BatchScratch& BS, hss_handle* const* hs, int count, const int64_t* nrhs,
+                         hipStream_t s, MMSplit<T>& ms) {
+  for (int j = 0; j < count; ++j) ms.idx[hs[j]->plan.max_k > 32 ? 1 : 0].push_back(j);
+  for (int g = 0; g < 2; ++g) {
+    if (ms.idx[g].empty()) continue;
+    std::vector<hss_handle*> h;
+    std::vector<int64_t> r;
+    for (int j : ms.idx[g]) {
+      h.push_back(hs[j]);
+      r.push_back(nrhs[j]);
+    }
+    const hss_status st = plan_mm_n<T>(BS, h.data(), (int)h.size(), r.data(), s, ms.bp[g]);
+    if (st) return st;
+  }
+  return HSS_OK;
+}
+
+template <typename T>
+hss_status run_mm_split(BatchScratch& BS, const MMSplit<T>& ms, hss_handle* const* hs,
+                        const int64_t* nrhs, const void* const* X, const int64_t* ldx,
+                        void* const* Y, const int64_t* ldy, hipStream_t s, bool gated) {
+  for (int g = 0; g < 2; ++g) {
+    if (ms.idx[g].empty()) continue;
+    std::vector<hss_handle*> h;
+    std::vector<int64_t> r, lx, ly;
+    std::vector<const void*> x;
+    std::vector<void*> y;
+    for (int j : ms.idx[g]) {
+      h.push_back(hs[j]);
+      r.push_back(nrhs[j]);
+      x.push_back(X[j]);
+      lx.push_back(ldx[j]);
+      y.push_back(Y[j]);
+      ly.push_back(ldy[j]);
+    }
+    const hss_status st = run_mm_n<T>(BS, ms.bp[g], h.data(), (int)h.size(), r.data(), x.data(),
+                                      lx.data(), y.data(), ly.data(), s, gated);
+    if (st) return st;
+  }
+  return HSS_OK;
+}
+
 template <typename T>
 hss_status batch_matmul_impl(BatchScratch& BS, hss_handle* const* hs, int count, int op,
                              const int64_t* nrhs,
@@ -814,10 +868,10 @@ hss_status batch_matmul_impl(BatchScratch& BS, hss_handle* const* hs, int count,
   for (int j = 0; j < count; ++j) maxr = std::max(maxr, nrhs[j]);
   if (maxr == 0) return HSS_OK;
   if (op == HSS_OP_N) {
-    BatchPlan<T> bp;
-    hss_status st = plan_mm_n<T>(BS, hs, count, nrhs, s, bp);
+    MMSplit<T> ms;
+    hss_status st = plan_mm_split<T>(BS, hs, count, nrhs, s, ms);
     if (st) return st;
-    return run_mm_n<T>(BS, bp, hs, count, nrhs, X, ldx, Y, ldy, s, false);
+    return run_mm_split<T>(BS, ms, hs, nrhs, X, ldx, Y, ldy, s, false);
   }
   std::vector<Inst<T>> insts(count);
   std::vector<CallMM<T>> calls(count);
@@ -1054,14 +1108,15 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
   // every table before any launch: the sweep's and the residual product's
   // records and task lists (built once, whatever the number of steps), then
   // the refinement descriptors
-  BatchPlan<double> sv64, mm;
+  BatchPlan<double> sv64;
+  MMSplit<double> mm;
   BatchPlan<float> sv32;
   if (is64) {
     if ((st = plan_sweep<double>(BS, hs, count, nrhs, s, sv64))) return st;
   } else {
     if ((st = plan_sweep<float>(BS, hs, count, nrhs, s, sv32))) return st;
   }
-  if (need_eta && (st = plan_mm_n<double>(BS, hs, count, nrhs, s, mm))) return st;
+  if (need_eta && (st = plan_mm_split<double>(BS, hs, count, nrhs, s, mm))) return st;
   std::vector<char> segbytes(sizeof(IRSeg) * count);
   std::memcpy(segbytes.data(), segs.data(), segbytes.size());
   void* dsegp = nullptr;
@@ -1101,8 +1156,8 @@ hss_status batch_solve(hss_handle* const* hs, int count, const int64_t* nrhs, do
     hss_status e;
     std::vector<const void*> xv(Bv.begin(), Bv.end());
     std::vector<void*> yv(res.begin(), res.end());
-    if ((e = run_mm_n<double>(BS, mm, hs, count, nrhs, xv.data(), ldb, yv.data(), n_ld.data(), s,
-                              gated)))
+    if ((e = run_mm_split<double>(BS, mm, hs, nrhs, xv.data(), ldb, yv.data(), n_ld.data(), s,
+                                  gated)))
       return e;
     ir(IR_ZERO, gated);
     ir(IR_RESID, gated);
