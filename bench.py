@@ -196,6 +196,46 @@ def main():
     log(f"[bench] fresh FP32+IR, max_refine 10: {t32_10*1e3:.3f} ms/solve")
     t64, e64 = timed(step_fresh, K, W, hss.F64, 0.0)
     log(f"[bench] fresh FP64   : {t64*1e3:.3f} ms/solve, eta_max {max(e for e, _ in e64):.2e}")
+
+    def graph_rate(prec, tol):
+        """The fresh step (copy of the right-hand side, factorization, solve
+        with its device-gated refinement, device-written report) captured once
+        per instance in a HIP graph and replayed round robin."""
+        reps_g = [hss.SolveReport(r) for _ in mats]
+        fns = [lambda i=i: step_fresh(i, prec, tol, reps_g[i]) for i in range(len(mats))]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for f in fns:
+                f()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graphs = []
+        for f in fns:
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr):
+                f()
+            graphs.append(gr)
+        torch.cuda.synchronize()
+        for i in range(W):
+            graphs[i % len(graphs)].replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(K):
+            graphs[i % len(graphs)].replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / K
+        infos = [rp.result() for rp in reps_g]
+        del graphs
+        for info in infos:
+            if info["status"] != hss.HSS_OK:
+                raise hss.HSSError(info["status"], "bench graph step")
+        return dt, max(info["eta_max"] for info in infos), max(info["iters"] for info in infos)
+
+    g32, ge32, gi32 = graph_rate(hss.F32, 1e-10)
+    g64, ge64, _ = graph_rate(hss.F64, 0.0)
+    log(f"[bench] graph replay: fresh FP32+IR {g32*1e3:.3f} ms/solve (eta_max {ge32:.2e}, "
+        f"iters {gi32}), FP64 {g64*1e3:.3f} ms/solve")
     # resident factors (both precisions factored)
     for A in mats:
         A.factor(hss.F32)
@@ -377,6 +417,10 @@ def main():
         "fp64_solves_per_s": round(1.0 / t64, 2), "fp64_eta_max": max(e for e, _ in e64),
         "ratio_fp32ir_over_fp64": round(t64 / t32, 3),
         "resident_solves_per_s": {"fp32ir": round(1.0 / rt32, 2), "fp64": round(1.0 / rt64, 2)},
+        "graph_replay": {"fp32ir_solves_per_s": round(1.0 / g32, 2), "fp32ir_ms": round(g32 * 1e3, 4),
+                         "fp32ir_eta_max": ge32, "fp32ir_iters": gi32,
+                         "fp64_solves_per_s": round(1.0 / g64, 2), "fp64_ms": round(g64 * 1e3, 4),
+                         "fp64_eta_max": ge64},
         "fresh_nrhs32": wide,
         "matmul_fp64": mm,
         "hadamard": had,
