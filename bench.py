@@ -148,13 +148,25 @@ def main():
     mr = args.max_refine
 
     def step_fresh(i, prec, tol, rep, max_refine=None):
+        """A fresh system: factor and refined solve in one call
+        (hss_ulv_factor_solve; in FP64 the first forward sweep overlapped
+        with the factorization)."""
+        A = mats[i % len(mats)]
+        W = work[i % len(mats)]
+        W.copy_(B0[i % len(mats)])
+        if prec == hss.F32:
+            return A.factor_solve(W, prec=hss.F32, tol=tol, max_refine=mr if max_refine is None
+                                  else max_refine, sync=False, report=rep)
+        return A.factor_solve(W, prec=hss.F64, want_eta=True, sync=False, report=rep)
+
+    def step_fresh_separate(i, prec, tol, rep):
+        """The same as two calls: hss_ulv_factor, then hss_ulv_solve."""
         A = mats[i % len(mats)]
         W = work[i % len(mats)]
         W.copy_(B0[i % len(mats)])
         A.factor(prec)
         if prec == hss.F32:
-            return A.solve(W, prec=hss.F32, tol=tol, max_refine=mr if max_refine is None else
-                           max_refine, sync=False, report=rep)
+            return A.solve(W, prec=hss.F32, tol=tol, max_refine=mr, sync=False, report=rep)
         return A.solve(W, prec=hss.F64, want_eta=True, sync=False, report=rep)
 
     def step_resident(i, prec, tol, rep):
@@ -196,6 +208,10 @@ def main():
     log(f"[bench] fresh FP32+IR, max_refine 10: {t32_10*1e3:.3f} ms/solve")
     t64, e64 = timed(step_fresh, K, W, hss.F64, 0.0)
     log(f"[bench] fresh FP64   : {t64*1e3:.3f} ms/solve, eta_max {max(e for e, _ in e64):.2e}")
+    ts32, _ = timed(step_fresh_separate, K, W, hss.F32, 1e-10)
+    ts64, _ = timed(step_fresh_separate, K, W, hss.F64, 0.0)
+    log(f"[bench] fresh as separate factor + solve calls: FP32+IR {ts32*1e3:.3f} ms, "
+        f"FP64 {ts64*1e3:.3f} ms")
 
     def graph_rate(prec, tol):
         """The fresh step (copy of the right-hand side, factorization, solve
@@ -417,6 +433,8 @@ def main():
         "fp64_solves_per_s": round(1.0 / t64, 2), "fp64_eta_max": max(e for e, _ in e64),
         "ratio_fp32ir_over_fp64": round(t64 / t32, 3),
         "resident_solves_per_s": {"fp32ir": round(1.0 / rt32, 2), "fp64": round(1.0 / rt64, 2)},
+        "separate_calls": {"fp32ir_solves_per_s": round(1.0 / ts32, 2), "fp32ir_ms": round(ts32 * 1e3, 4),
+                           "fp64_solves_per_s": round(1.0 / ts64, 2), "fp64_ms": round(ts64 * 1e3, 4)},
         "graph_replay": {"fp32ir_solves_per_s": round(1.0 / g32, 2), "fp32ir_ms": round(g32 * 1e3, 4),
                          "fp32ir_eta_max": ge32, "fp32ir_iters": gi32,
                          "fp64_solves_per_s": round(1.0 / g64, 2), "fp64_ms": round(g64 * 1e3, 4),

@@ -269,6 +269,21 @@ hss_status hss_ulv_factor(hss_handle *h, int32_t prec, void *stream);
 hss_status hss_ulv_solve(hss_handle *h, int64_t nrhs, double *B, int64_t ldb,
                          const hss_solve_opts *o, hss_solve_info *info, void *stream);
 
+/* hss_ulv_factor_solve: a fresh system in one call, hss_ulv_factor(h, o->prec)
+ * followed by hss_ulv_solve(h, nrhs, B, ldb, o, info) (Sec. 4.3, Steps 1-4),
+ * with the same kernels and the same results bit for bit.  In FP64 the
+ * forward sweep of the first solve (Step 2 for level l) runs on the
+ * handle's second stream as soon as level l is factored, beside the
+ * factorization of the levels above it; in FP32 (shorter sweeps than the
+ * hand-off costs) the sweep of each level runs right after its
+ * factorization on the caller's stream.  The root solve, the backward sweep
+ * and the refinement follow on the caller's stream.  Arguments, errors and report as
+ * hss_ulv_solve (HSS_ESTATE does not arise).  Asynchronous on stream, which
+ * the second stream forks from and joins back with events, so the call is
+ * ordered on stream as if it ran there alone (and can be captured). */
+hss_status hss_ulv_factor_solve(hss_handle *h, int64_t nrhs, double *B, int64_t ldb,
+                                const hss_solve_opts *o, hss_solve_info *info, void *stream);
+
 /* Query keys for hss_query (out is host memory of the stated type). */
 #define HSS_Q_N              0   /* int64_t                                        */
 #define HSS_Q_P              1   /* int32_t                                        */

@@ -400,8 +400,10 @@ void run_matmul(hss_handle* h, int op, int64_t nrhs, const T* X, int64_t ldx, T*
   launch_mm_level<T>(MMStep::LeafOut, a, 1 << p, yt, rows, s);
 }
 
-template <typename T>
-void run_factor(hss_handle* h, hipStream_t s) {
+// on_level(l): called once the factors of level l (leaves: l = p) are
+// enqueued on s, before the next level's launches.
+template <typename T, typename F>
+void run_factor(hss_handle* h, hipStream_t s, F&& on_level) {
   KArgs<T, CallSV<T>> a{};
   a.inst = make_inst<T>(h);
   const Plan& P = h->plan;
@@ -413,75 +415,134 @@ void run_factor(hss_handle* h, hipStream_t s) {
   }
   a.node0 = level_first(p);
   launch_ulv<T>(UlvStep::Factor, a, 1 << p, P.max_k, P.level_max_mp[p], s);
+  on_level(p);
   for (int l = p - 1; l >= 1; --l) {
     a.node0 = level_first(l);
     launch_ulv<T>(UlvStep::Merge, a, 1 << l, P.max_k, P.level_max_mp[l], s);
     launch_ulv<T>(UlvStep::Factor, a, 1 << l, P.max_k, P.level_max_mp[l], s);
     if (use_fwd_op<T>(P)) launch_ulv<T>(UlvStep::FwdOp, a, 1 << l, P.max_k, P.level_max_mp[l], s);
+    on_level(l);
   }
   a.node0 = 0;
   launch_ulv<T>(UlvStep::Merge, a, 1, P.max_k, P.nodes[0].mp, s);
   launch_ulv<T>(UlvStep::RootLU, a, 1, P.max_k, P.nodes[0].mp, s);
 }
 
+template <typename T>
+void run_factor(hss_handle* h, hipStream_t s) {
+  run_factor<T>(h, s, [](int) {});
+}
+
 // LDS bytes a work-group may use for staged copies of one node's factors.
 constexpr int64_t kStageBudget = 120 * 1024;
 
+// One solve's launch schedule: its kernel arguments and LDS budgets.
 template <typename T>
-void run_solve(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, hipStream_t s,
-               const int32_t* gate = nullptr) {
+struct SolveSched {
   KArgs<T, CallSV<T>> a{};
-  a.inst = make_inst<T>(h);
-  a.call = CallSV<T>{B, ldb, (int32_t)nrhs, 0, gate};
+  int nc = 0;
+  int64_t root_elems = 0;
+};
+
+template <typename T>
+SolveSched<T> solve_sched(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, const int32_t* gate) {
+  SolveSched<T> S;
+  S.a.inst = make_inst<T>(h);
+  S.a.call = CallSV<T>{B, ldb, (int32_t)nrhs, 0, gate};
+  S.nc = (int)nrhs;
   const Plan& P = h->plan;
   const int p = P.p;
-  const int nc = (int)nrhs;
   // columns per wavefront: tuned (or forced by the tuner), else the default
   {
     TuneVal tv;
-    if (g_force_cpw > 0) a.cpw = g_force_cpw;
+    if (g_force_cpw > 0) S.a.cpw = g_force_cpw;
     else if (nrhs >= 4 && tune_lookup(P, sizeof(T) == 8 ? HSS_F64 : HSS_F32, nrhs, &tv))
-      a.cpw = tv.cpw;
+      S.a.cpw = tv.cpw;
   }
-  auto fwd_stage = [&](int l) -> int64_t {
-    const int64_t e = P.level_fwd_stage[l];
-    return e > 0 && e * (int64_t)sizeof(T) <= kStageBudget ? e : 0;
-  };
-  auto bwd_stage = [&](int l) -> int64_t {
-    const int64_t e = P.level_bwd_stage[l];
-    return e > 0 && e * (int64_t)sizeof(T) <= kStageBudget ? e : 0;
-  };
   // root: FP64 LU + pivots (+ the children's blocks when everything fits in LDS)
   const int64_t mpr = P.nodes[0].mp;
   int64_t root_bytes = mpr * mpr * 8 + 4 * ((mpr + 3) & ~int64_t(3));
   const int64_t child_bytes = p > 0 ? P.level_fwd_stage[0] * (int64_t)sizeof(T) : 0;
-  a.flags = 0;
+  S.a.flags = 0;
   if (p > 0 && root_bytes + child_bytes <= 160 * 1024) {
     root_bytes += child_bytes;
-    a.flags = 1;
+    S.a.flags = 1;
   }
-  const int64_t root_elems = (root_bytes + sizeof(T) - 1) / sizeof(T);
-  if (p == 0) {
-    a.node0 = 0;
-    launch_solve_w<T>(UlvStep::Root, a, 1, nc, root_elems, s);
+  S.root_elems = (root_bytes + sizeof(T) - 1) / sizeof(T);
+  return S;
+}
+
+// forward sweep of level l (leaves: l = p), p > 0
+template <typename T>
+void solve_fwd_level(hss_handle* h, SolveSched<T>& S, int l, hipStream_t s) {
+  const Plan& P = h->plan;
+  S.a.node0 = level_first(l);
+  if (l == P.p) {
+    launch_solve_w<T>(UlvStep::Fwd, S.a, 1 << l, S.nc, 0, s);
     return;
   }
-  a.node0 = level_first(p);
-  launch_solve_w<T>(UlvStep::Fwd, a, 1 << p, nc, 0, s);
-  for (int l = p - 1; l >= 1; --l) {
-    a.node0 = level_first(l);
-    if (use_fwd_op<T>(P) && P.level_fwd_op[l])
-      launch_solve_w<T>(UlvStep::FwdOp, a, 1 << l, nc, 0, s);
-    else launch_solve_w<T>(UlvStep::Fwd, a, 1 << l, nc, fwd_stage(l), s);
-  }
-  a.node0 = 0;
-  launch_solve_w<T>(UlvStep::Root, a, 1, nc, root_elems, s);
+  const int64_t e = P.level_fwd_stage[l];
+  const int64_t st = e > 0 && e * (int64_t)sizeof(T) <= kStageBudget ? e : 0;
+  if (use_fwd_op<T>(P) && P.level_fwd_op[l]) launch_solve_w<T>(UlvStep::FwdOp, S.a, 1 << l, S.nc, 0, s);
+  else launch_solve_w<T>(UlvStep::Fwd, S.a, 1 << l, S.nc, st, s);
+}
+
+// the root solve and the backward sweep
+template <typename T>
+void solve_root_bwd(hss_handle* h, SolveSched<T>& S, hipStream_t s) {
+  const Plan& P = h->plan;
+  const int p = P.p;
+  S.a.node0 = 0;
+  launch_solve_w<T>(UlvStep::Root, S.a, 1, S.nc, S.root_elems, s);
+  if (p == 0) return;
   for (int l = 1; l <= p - 1; ++l) {
-    a.node0 = level_first(l);
-    launch_solve_w<T>(UlvStep::Bwd, a, 1 << l, nc, bwd_stage(l), s);
+    S.a.node0 = level_first(l);
+    const int64_t e = P.level_bwd_stage[l];
+    const int64_t st = e > 0 && e * (int64_t)sizeof(T) <= kStageBudget ? e : 0;
+    launch_solve_w<T>(UlvStep::Bwd, S.a, 1 << l, S.nc, st, s);
   }
-  a.node0 = level_first(p);
-  launch_solve_w<T>(UlvStep::Bwd, a, 1 << p, nc, 0, s);
+  S.a.node0 = level_first(p);
+  launch_solve_w<T>(UlvStep::Bwd, S.a, 1 << p, S.nc, 0, s);
+}
+
+template <typename T>
+void run_solve(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, hipStream_t s,
+               const int32_t* gate = nullptr) {
+  SolveSched<T> S = solve_sched<T>(h, nrhs, B, ldb, gate);
+  for (int l = h->plan.p; l >= 1; --l) solve_fwd_level<T>(h, S, l, s);
+  solve_root_bwd<T>(h, S, s);
+}
+
+// Factorization, then the forward sweep of a solve, overlapped (FP64): the
+// sweep of level l runs on the handle's second stream as soon as level l is
+// factored, beside the factorization of the levels above (they read and
+// write different nodes); the root solve and the backward sweep follow on s.
+template <typename T>
+void run_factor_solve(hss_handle* h, int64_t nrhs, T* B, int64_t ldb, hipStream_t s) {
+  SolveSched<T> S = solve_sched<T>(h, nrhs, B, ldb, nullptr);
+  if (h->plan.p == 0) {
+    run_factor<T>(h, s);
+    solve_root_bwd<T>(h, S, s);
+    return;
+  }
+  // FP64: every level's sweep on the second stream.  FP32: none (lov = 0),
+  // the sweeps run on s between the factor levels: a level's FP32 sweep
+  // (forward-operator records, ~15 us) is shorter than the event round trip
+  // that hands it to the second stream and back (measured: the overlapped
+  // FP32 step 2.34-2.36 ms against 2.25 ms in order; FP64 2.55 against 2.79)
+  const int lov = sizeof(T) == 8 ? h->plan.p : 0;
+  run_factor<T>(h, s, [&](int l) {
+    if (l > lov) {
+      solve_fwd_level<T>(h, S, l, s);
+      return;
+    }
+    (void)hipEventRecord(h->ev_fork, s);
+    (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+    solve_fwd_level<T>(h, S, l, h->side);
+  });
+  (void)hipEventRecord(h->ev_join, h->side);
+  (void)hipStreamWaitEvent(s, h->ev_join, 0);
+  solve_root_bwd<T>(h, S, s);
 }
 
 hss_status last_launch_status() {
@@ -1742,22 +1803,24 @@ hss_status hss_ulv_factor(hss_handle* h, int32_t prec, void* stream) {
   return last_launch_status();
 }
 
-hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
-                         const hss_solve_opts* o, hss_solve_info* info, void* stream) {
-  if (!h) return -1;
-  if (nrhs < 0) return -2;
-  if (nrhs > 0 && !B) return -3;
-  if (ldb < h->plan.n) return -4;
-  hss_solve_opts opt{HSS_F64, 10, 0.0, 0, 0};
-  if (o) opt = *o;
-  if (opt.prec != HSS_F64 && opt.prec != HSS_F32) return -5;
-  if (opt.max_refine < 0 || !(opt.tol >= 0.0)) return -5;
+}  // extern "C"
+
+namespace {
+
+// The refined solve; fused: the factorization with opt.prec first, its
+// forward sweep overlapped with the factorization (run_factor_solve).
+hss_status ulv_solve_impl(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
+                          const hss_solve_opts& opt, hss_solve_info* info, hipStream_t s,
+                          bool fused) {
   const bool is64 = opt.prec == HSS_F64;
-  if (is64 ? !h->f64.valid : !h->f32.valid) return HSS_ESTATE;
-  hipStream_t s = (hipStream_t)stream;
+  if (!fused && (is64 ? !h->f64.valid : !h->f32.valid)) return HSS_ESTATE;
   const int64_t n = h->plan.n;
   const bool need_eta = nrhs > 0 && (opt.want_eta || opt.tol > 0.0);
   hss_status st;
+  if (fused) {
+    launch_fill(reinterpret_cast<double*>(h->d_status), 0.0, 2, s);
+    if ((st = is64 ? ensure_factors<double>(h) : ensure_factors<float>(h))) return st;
+  }
   if (is64) {
     if ((st = ensure_work_sv<double>(h, nrhs))) return st;
   } else {
@@ -1782,12 +1845,14 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
         double* d = accumulate ? h->d64 : x;
         const int64_t ldd = accumulate ? n : ldx;
         if (rhs != d) launch_copy2d(rhs, ldr, d, ldd, n, nrhs, s, g);
-        run_solve<double>(h, nrhs, d, ldd, s, g);
+        if (fused && !accumulate) run_factor_solve<double>(h, nrhs, d, ldd, s);
+        else run_solve<double>(h, nrhs, d, ldd, s, g);
         if (accumulate) launch_axpy64(d, ldd, x, ldx, n, nrhs, s, g);
       } else {
         if (!scaled) launch_colmax(rhs, ldr, n, nrhs, h->part, h->chk_cnt, bmax, s);
         launch_scale_cast(rhs, ldr, h->r32, n, n, nrhs, bmax, s, g);
-        run_solve<float>(h, nrhs, h->r32, n, s, g);
+        if (fused && !accumulate) run_factor_solve<float>(h, nrhs, h->r32, n, s);
+        else run_solve<float>(h, nrhs, h->r32, n, s, g);
         if (accumulate) launch_axpy_cast(h->r32, n, x, ldx, n, nrhs, bmax, s, g);
         else launch_cast_back(h->r32, n, x, ldx, n, nrhs, bmax, s);
       }
@@ -1808,9 +1873,43 @@ hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
         check(k, gate);
       }
     }
+  } else if (fused) {
+    if (is64) run_factor<double>(h, s);
+    else run_factor<float>(h, s);
   }
+  if (fused) (is64 ? h->f64.valid : h->f32.valid) = true;
   if (info) launch_solve_info(info, nrhs, outv, stb, h->norm2, opt.tol, need_eta, s);
   return last_launch_status();
+}
+
+}  // namespace
+
+extern "C" {
+
+hss_status hss_ulv_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
+                         const hss_solve_opts* o, hss_solve_info* info, void* stream) {
+  if (!h) return -1;
+  if (nrhs < 0) return -2;
+  if (nrhs > 0 && !B) return -3;
+  if (ldb < h->plan.n) return -4;
+  hss_solve_opts opt{HSS_F64, 10, 0.0, 0, 0};
+  if (o) opt = *o;
+  if (opt.prec != HSS_F64 && opt.prec != HSS_F32) return -5;
+  if (opt.max_refine < 0 || !(opt.tol >= 0.0)) return -5;
+  return ulv_solve_impl(h, nrhs, B, ldb, opt, info, (hipStream_t)stream, false);
+}
+
+hss_status hss_ulv_factor_solve(hss_handle* h, int64_t nrhs, double* B, int64_t ldb,
+                                const hss_solve_opts* o, hss_solve_info* info, void* stream) {
+  if (!h) return -1;
+  if (nrhs < 0) return -2;
+  if (nrhs > 0 && !B) return -3;
+  if (ldb < h->plan.n) return -4;
+  hss_solve_opts opt{HSS_F64, 10, 0.0, 0, 0};
+  if (o) opt = *o;
+  if (opt.prec != HSS_F64 && opt.prec != HSS_F32) return -5;
+  if (opt.max_refine < 0 || !(opt.tol >= 0.0)) return -5;
+  return ulv_solve_impl(h, nrhs, B, ldb, opt, info, (hipStream_t)stream, true);
 }
 
 hss_status hss_query(hss_handle* h, int32_t key, void* out, void* stream) {

@@ -30,7 +30,7 @@ EXPORTS = (
     "hss_batch_ulv_factor", "hss_batch_ulv_solve", "hss_status_str", "hss_timing_enable",
     "hss_timing_report", "hss_matmul_noalloc", "hss_matmul_noalloc_max_rhs", "hss_autotune",
     "hss_tune_table", "hss_tune_load", "hss_tune_reset", "hss_hadamard", "hss_get_generators",
-    "hss_compress", "hss_ranks",
+    "hss_compress", "hss_ranks", "hss_ulv_factor_solve",
 )
 
 Q_N, Q_P, Q_RESIDENT_BYTES, Q_NORM2, Q_GEN_ENTRIES, Q_FACTOR_ENTRIES = range(6)
@@ -103,6 +103,7 @@ def lib() -> C.CDLL:
     L.hss_matmul_noalloc_max_rhs.argtypes = [vp, i32]
     L.hss_ulv_factor.argtypes = [vp, i32, vp]
     L.hss_ulv_solve.argtypes = [vp, i64, vp, i64, C.POINTER(SolveOpts), vp, vp]
+    L.hss_ulv_factor_solve.argtypes = [vp, i64, vp, i64, C.POINTER(SolveOpts), vp, vp]
     L.hss_query.argtypes = [vp, i32, vp, vp]
     L.hss_plan_depth.argtypes = [i64, i64]
     L.hss_plan_leaf_offsets.argtypes = [i64, i64, C.POINTER(C.c_int64), i64]
@@ -495,6 +496,36 @@ class HSSMatrix:
         out = rep.result()
         if check and out["status"] != HSS_OK:
             raise HSSError(out["status"], "hss_ulv_solve")
+        return out
+
+    def factor_solve(self, B, prec=F64, tol=0.0, max_refine=10, want_eta=False, stream=None,
+                     check=True, sync=True, report=None):
+        """Factor with prec, then B <- A^{-1} B in place, in one call
+        (hss_ulv_factor_solve; in FP64 the first solve's forward sweep
+        overlapped with the factorization); arguments and result as solve().
+
+        sync=True: waits for the stream and returns a dict with eta (per
+        column), eta_max, iters, status, norm2 and singular_node, raising
+        HSSError for a status other than HSS_OK when check is set.
+        sync=False: returns the SolveReport (read it after the stream has
+        reached the end of the solve); nothing waits.  report: a SolveReport
+        to write (e.g. one allocated before a graph capture)."""
+        import torch
+        bp, ldb = colmajor(B, self.n, (torch.float64,))
+        r = B.shape[1]
+        opts = SolveOpts(prec, max_refine, tol, 1 if want_eta else 0, 0)
+        rep = SolveReport(r) if report is None else report
+        if rep.nrhs < r:
+            raise ValueError(f"report holds {rep.nrhs} columns, the solve has {r}")
+        code = lib().hss_ulv_factor_solve(self.h, r, bp, ldb, C.byref(opts), rep.ptr,
+                                          _stream(stream))
+        _check(code, "hss_ulv_factor_solve")
+        if not sync:
+            return rep
+        _sync(stream)
+        out = rep.result()
+        if check and out["status"] != HSS_OK:
+            raise HSSError(out["status"], "hss_ulv_factor_solve")
         return out
 
     def solve_async(self, B, prec=F64, stream=None):
