@@ -20,6 +20,9 @@ hadamard  the Hadamard product of two HSS matrices on one tree (Sec. 4.4):
           operators and core blocks
 compress  HSS recompression (Sec. 4.5, App. A): proper form by bottom-up
           QR, then top-down truncated SVDs of the core blocks
+construct the dense-to-HSS constructor (Sec. 3.2): truncated SVDs of
+          the block rows and columns from the leaves up, nested through a
+          reduced matrix
 
 Every function is pinned in ``tests/test_oracle_*.py`` against closed forms,
 dense LAPACK, brute force or the worked example of Fig. 1 (see each module's

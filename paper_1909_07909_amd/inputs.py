@@ -341,3 +341,32 @@ def _block_diag_family(leaf_off, k, seed, diag, zero_core):
             pk.add("B21", np.zeros((k, k)))
     a = pk.arrays()
     return Generators(n=n, p=p, leaf_off=leaf_off, ku=ku, kv=kv, **a)
+
+
+# ----------------------------------------------------------------------------
+# Dense inputs of the dense-to-HSS constructor (column-major n x n arrays).
+# ----------------------------------------------------------------------------
+
+def cauchy_kernel_dense(n: int, seed: int = 1, width: float = 0.05,
+                        shift: float = 1e-2) -> np.ndarray:
+    """The Cauchy-like kernel matrix of the ragged-rank workload: points x_i
+    sorted uniform on [0, 1], A_ij = 1 / (1 + ((x_i - x_j) / width)^2) plus
+    shift on the diagonal (symmetric positive definite, numerically low-rank
+    off-diagonal blocks)."""
+    rng = np.random.default_rng(seed)
+    x = np.sort(rng.uniform(0.0, 1.0, n))
+    d = (x[:, None] - x[None, :]) / width
+    A = 1.0 / (1.0 + d * d)
+    A[np.diag_indices_from(A)] += shift
+    return np.asfortranarray(A)
+
+
+def banded_dense(n: int, bl: int, bu: int, seed) -> np.ndarray:
+    """Standard normal entries on the band -bl <= j - i <= bu (diagonal
+    shifted by bl + bu + 2), zeros elsewhere."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    i, j = np.indices((n, n))
+    A[(j - i > bu) | (i - j > bl)] = 0.0
+    A[np.diag_indices_from(A)] += bl + bu + 2.0
+    return np.asfortranarray(A)

@@ -19,19 +19,11 @@ from __future__ import annotations
 
 import numpy as np
 
-from paper_1909_07909_amd.inputs import Generators, _Packer
+from paper_1909_07909_amd.inputs import Generators, _Packer, cauchy_kernel_dense
 
 
-def cauchy_points(n: int, seed: int = 1) -> np.ndarray:
-    rng = np.random.default_rng(seed)
-    return np.sort(rng.uniform(0.0, 1.0, n))
-
-
-def cauchy_matrix(x: np.ndarray, width: float = 0.05, shift: float = 1e-2) -> np.ndarray:
-    d = (x[:, None] - x[None, :]) / width
-    A = 1.0 / (1.0 + d * d)
-    A[np.diag_indices_from(A)] += shift
-    return A
+def cauchy_matrix_for(n: int, seed: int = 1) -> np.ndarray:
+    return np.ascontiguousarray(cauchy_kernel_dense(n, seed))
 
 
 def _trunc_left(M: np.ndarray, tol: float) -> np.ndarray:
@@ -124,6 +116,5 @@ def compress(A: np.ndarray, leaf_off, tol: float = 1e-10) -> Generators:
 
 def cauchy_hss(n: int, leaf_off, seed: int = 1, tol: float = 1e-10):
     """(generators, dense kernel matrix) of the Cauchy-like workload."""
-    x = cauchy_points(n, seed)
-    A = cauchy_matrix(x)
+    A = cauchy_matrix_for(n, seed)
     return compress(A, leaf_off, tol), A
