@@ -200,6 +200,37 @@ hss_status hss_hadamard(const hss_handle *A, const hss_handle *B,
 hss_status hss_compress(const hss_handle *A, double tau, const hss_alloc *alloc,
                         void *stream, hss_handle **out);
 
+/* hss_construct_dense: the HSS approximation of a dense n x n FP64 matrix
+ * (Sec. 3.2, the dense constructor: low-rank truncation of every HSS block
+ * row and column from the leaves to the root, nested, by truncated SVD).
+ * A: DEVICE memory, column-major, leading dimension lda >= n; only read, and
+ * D is copied out of it.  The cluster tree is leaf_off (2^p + 1 entries,
+ * host, as in hss_tree_desc; leaves of at most 128 rows); the ranks are
+ * chosen here.  Level by level from the leaves up, on the matrix M of that
+ * level (A at the leaves, then blkdiag(U^_t)^T A blkdiag(V^_t) over the
+ * nodes t of the level below, the explicit nested bases U^_t, V^_t):
+ *   leaf i:        U_i, V_i = the kept left singular vectors of the block
+ *                  row A(I_i, I \ I_i) and of the block column
+ *                  A(I \ I_i, I_i)^T; D_i = A(I_i, I_i);
+ *   internal t:    R_t, W_t likewise from the block row and block column of
+ *                  M formed by t's two children (both from M as it stands
+ *                  at the start of the level); B12_t, B21_t = the blocks of
+ *                  M coupling the two children.
+ * A singular value is kept when it is > eps * sigma_1 of its block, at least
+ * one per block (an exactly zero block keeps the first unit vector); the
+ * bases come out orthonormal.  *out is a new handle (resident FP32 copy,
+ * ||A||_2 estimate; read the ranks with hss_ranks).  Device scratch of about
+ * n^2 + 2 (rows x ranks) doubles plus 2 * 128^2 doubles per node is taken
+ * from alloc (or hipMalloc) for the call and released before it returns.
+ * Errors: -1 NULL A, -2 lda < n, -3 n < 1, -4 p outside 0..30, -5 leaf
+ * offsets invalid or NULL, -6 eps negative, NaN or infinite, -7 incomplete
+ * allocator hooks, -9 NULL out; HSS_EUNSUP for a leaf above 128 rows or a
+ * kept rank above 64; HSS_ENOMEM, HSS_EHIP.  Orders after earlier work on
+ * the stream; synchronizes it once per level. */
+hss_status hss_construct_dense(const double *A, int64_t lda, int64_t n, int32_t p,
+                               const int64_t *leaf_off, double eps,
+                               const hss_alloc *alloc, void *stream, hss_handle **out);
+
 /* hss_ranks: the handle's ranks ku_t, kv_t in heap order (0 at the root)
  * into caller arrays of 2^(p+1) - 1 entries.  Host only; no device work.
  * Errors: -1 NULL h, -2 NULL ku, -3 NULL kv. */

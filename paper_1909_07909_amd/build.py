@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhss.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["plan.cpp", "timing.cpp", "hss_capi.cpp", "kernels_util.hip", "kernels_mm.hip", "kernels_mmf.hip", "kernels_mmw.hip", "kernels_ulv.hip",
-           "kernels_factor.hip", "kernels_factor_blk.hip", "kernels_solve.hip", "kernels_hadamard.hip", "kernels_compress.hip"]
+           "kernels_factor.hip", "kernels_factor_blk.hip", "kernels_solve.hip", "kernels_hadamard.hip", "kernels_compress.hip",
+           "kernels_construct.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.

@@ -1679,6 +1679,219 @@ hss_status hss_compress(const hss_handle* A, double tau, const hss_alloc* alloc,
   return HSS_OK;
 }
 
+// Dense-to-HSS construction (Sec. 3.2): the levels from the leaves up, each
+// a truncation launch (block rows of X and of X^T), a rank read-back, and
+// the reduced matrix of the next level, M <- blkdiag(R_t)^T M blkdiag(W_t)
+// (at the leaves blkdiag(U_i)^T A blkdiag(V_i)) as Y = X blkdiag(W),
+// M^T = Y^T blkdiag(R), M = (M^T)^T.  Every reduced matrix is kept until the
+// end: the core blocks of the nodes one level up are its blocks.
+}  // extern "C"
+
+namespace {
+
+struct CnLevel {
+  double* M = nullptr;    // Ku x Kv (ld Ku): blkdiag(U^_t)^T A blkdiag(V^_t), t on the level
+  double* Mt = nullptr;   // its transpose
+  int64_t Ku = 0, Kv = 0;
+  std::vector<int64_t> ro, co;   // row / column block offsets of the level's nodes
+};
+
+template <typename V>
+hss_status upload(TempDev& tmp, const std::vector<V>& v, V** d, hipStream_t s) {
+  *d = (V*)tmp.get(sizeof(V) * std::max<size_t>(v.size(), 1));
+  if (!*d) return HSS_ENOMEM;
+  if (!v.empty() &&
+      hipMemcpyAsync(*d, v.data(), sizeof(V) * v.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return HSS_EHIP;
+  return HSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hss_status hss_construct_dense(const double* A, int64_t lda, int64_t n, int32_t p,
+                               const int64_t* leaf_off, double eps, const hss_alloc* alloc,
+                               void* stream, hss_handle** out) {
+  if (!out) return -9;
+  *out = nullptr;
+  if (!A) return -1;
+  if (n < 1) return -3;
+  if (lda < n) return -2;
+  if (p < 0 || p > 30) return -4;
+  if (!leaf_off) return -5;
+  if (!(eps >= 0.0) || std::isinf(eps)) return -6;
+  if (alloc && (!alloc->alloc || !alloc->free)) return -7;
+  const int32_t nn = (int32_t)((2ll << p) - 1), leaf0 = (int32_t)((1ll << p) - 1);
+  // node ranges; the plan below validates the offsets again
+  std::vector<int64_t> st(nn), sz(nn);
+  if (leaf_off[0] != 0 || leaf_off[1ll << p] != n) return -5;
+  for (int32_t i = 0; i < (1 << p); ++i) {
+    if (leaf_off[i + 1] <= leaf_off[i]) return -5;
+    if (leaf_off[i + 1] - leaf_off[i] > kCnMaxRows) return HSS_EUNSUP;
+    st[leaf0 + i] = leaf_off[i];
+    sz[leaf0 + i] = leaf_off[i + 1] - leaf_off[i];
+  }
+  for (int32_t t = leaf0 - 1; t >= 0; --t) {
+    st[t] = st[2 * t + 1];
+    sz[t] = sz[2 * t + 1] + sz[2 * t + 2];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> ku(nn, 0), kv(nn, 0);
+  TempDev tmp(alloc);
+  hss_status stt = HSS_OK;
+  // left singular vectors of every truncation: two slots per node
+  const size_t slot = (size_t)kCnMaxRows * kCnMaxRows;
+  double* Ub = p > 0 ? (double*)tmp.get(sizeof(double) * slot * 2 * nn) : nullptr;
+  double* sg = p > 0 ? (double*)tmp.get(sizeof(double) * kCnMaxRows * 2 * nn) : nullptr;
+  int32_t* rk = p > 0 ? (int32_t*)tmp.get(sizeof(int32_t) * 2 * nn) : nullptr;
+  double* At = p > 0 ? (double*)tmp.get(sizeof(double) * (size_t)n * n) : nullptr;
+  if (p > 0 && (!Ub || !sg || !rk || !At)) return HSS_ENOMEM;
+  auto uslot = [&](int32_t t, int side) { return Ub + slot * (2 * (size_t)t + side); };
+  std::vector<CnLevel> lev(p + 1);   // lev[l]: reduced matrix of level l (l = 1 .. p)
+  std::vector<int32_t> rk_h(2 * nn, 0);
+  // truncations of the nodes of one level: row side on X, column side on Xt
+  auto truncate_level = [&](int l, const double* X, int64_t ldx, int64_t nx, const double* Xt,
+                            int64_t ldxt, int64_t nxt, const std::vector<int64_t>& r0,
+                            const std::vector<int64_t>& rsz, const std::vector<int64_t>& c0,
+                            const std::vector<int64_t>& csz) -> hss_status {
+    const int32_t t0 = (1 << l) - 1, cnt = 1 << l;
+    std::vector<CnTask> tasks(2 * (size_t)cnt);
+    for (int32_t j = 0; j < cnt; ++j) {
+      const int32_t t = t0 + j;
+      if (rsz[j] > kCnMaxRows || csz[j] > kCnMaxRows) return HSS_EUNSUP;
+      tasks[2 * j] = CnTask{X,          ldx,       r0[j],        (int32_t)rsz[j], 0, nx,
+                            c0[j],      c0[j] + csz[j], uslot(t, 0), sg + (size_t)kCnMaxRows * 2 * t,
+                            rk + 2 * t};
+      tasks[2 * j + 1] = CnTask{Xt,     ldxt,      c0[j],        (int32_t)csz[j], 0, nxt,
+                                r0[j],  r0[j] + rsz[j], uslot(t, 1),
+                                sg + (size_t)kCnMaxRows * (2 * t + 1), rk + 2 * t + 1};
+    }
+    CnTask* dt = nullptr;
+    hss_status e = upload(tmp, tasks, &dt, s);
+    if (e) return e;
+    launch_cn_trunc(dt, 2 * cnt, eps, s);
+    if ((e = last_launch_status())) return e;
+    if (hipMemcpyAsync(rk_h.data() + 2 * t0, rk + 2 * t0, sizeof(int32_t) * 2 * cnt,
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return HSS_EHIP;
+    for (int32_t j = 0; j < cnt; ++j) {
+      ku[t0 + j] = rk_h[2 * (t0 + j)];
+      kv[t0 + j] = rk_h[2 * (t0 + j) + 1];
+      if (ku[t0 + j] > kMaxRank || kv[t0 + j] > kMaxRank) return HSS_EUNSUP;
+    }
+    return HSS_OK;
+  };
+  // the reduced matrix of level l from X (rows x cols) and the level's factors
+  auto reduce_level = [&](int l, const double* X, int64_t ldx, int64_t rows,
+                          const std::vector<int64_t>& r0, const std::vector<int64_t>& rsz,
+                          const std::vector<int64_t>& c0,
+                          const std::vector<int64_t>& csz) -> hss_status {
+    const int32_t t0 = (1 << l) - 1, cnt = 1 << l;
+    CnLevel& L = lev[l];
+    L.ro.assign(cnt + 1, 0);
+    L.co.assign(cnt + 1, 0);
+    for (int32_t j = 0; j < cnt; ++j) {
+      L.ro[j + 1] = L.ro[j] + ku[t0 + j];
+      L.co[j + 1] = L.co[j] + kv[t0 + j];
+    }
+    L.Ku = L.ro[cnt];
+    L.Kv = L.co[cnt];
+    double* Y = (double*)tmp.get(sizeof(double) * (size_t)rows * L.Kv);
+    double* Yt = (double*)tmp.get(sizeof(double) * (size_t)rows * L.Kv);
+    L.M = (double*)tmp.get(sizeof(double) * (size_t)L.Ku * L.Kv);
+    L.Mt = (double*)tmp.get(sizeof(double) * (size_t)L.Ku * L.Kv);
+    if (!Y || !Yt || !L.M || !L.Mt) return HSS_ENOMEM;
+    std::vector<CnRmul> a(cnt), b(cnt);
+    for (int32_t j = 0; j < cnt; ++j) {
+      const int32_t t = t0 + j;
+      a[j] = CnRmul{X, ldx, rows, c0[j], (int32_t)csz[j], kv[t], uslot(t, 1), kCnMaxRows,
+                    Y, rows, L.co[j]};
+      b[j] = CnRmul{Yt, L.Kv, L.Kv, r0[j], (int32_t)rsz[j], ku[t], uslot(t, 0), kCnMaxRows,
+                    L.Mt, L.Kv, L.ro[j]};
+    }
+    CnRmul *da = nullptr, *db = nullptr;
+    hss_status e;
+    if ((e = upload(tmp, a, &da, s)) || (e = upload(tmp, b, &db, s))) return e;
+    launch_cn_rmul(da, cnt, rows, s);
+    launch_cn_trans(Y, rows, rows, L.Kv, Yt, L.Kv, s);
+    launch_cn_rmul(db, cnt, L.Kv, s);
+    launch_cn_trans(L.Mt, L.Kv, L.Kv, L.Ku, L.M, L.Ku, s);
+    return last_launch_status();
+  };
+  if (p > 0) {
+    launch_cn_trans(A, lda, n, n, At, n, s);
+    std::vector<int64_t> r0(1 << p), rsz(1 << p);
+    for (int32_t j = 0; j < (1 << p); ++j) {
+      r0[j] = st[leaf0 + j];
+      rsz[j] = sz[leaf0 + j];
+    }
+    if ((stt = truncate_level(p, A, lda, n, At, n, n, r0, rsz, r0, rsz))) return stt;
+    if ((stt = reduce_level(p, A, lda, n, r0, rsz, r0, rsz))) return stt;
+    for (int l = p - 1; l >= 1; --l) {
+      const CnLevel& B = lev[l + 1];
+      const int32_t cnt = 1 << l;
+      std::vector<int64_t> q0(cnt), qs(cnt), w0(cnt), ws(cnt);
+      for (int32_t j = 0; j < cnt; ++j) {
+        q0[j] = B.ro[2 * j];
+        qs[j] = B.ro[2 * j + 2] - B.ro[2 * j];
+        w0[j] = B.co[2 * j];
+        ws[j] = B.co[2 * j + 2] - B.co[2 * j];
+      }
+      if ((stt = truncate_level(l, B.M, B.Ku, B.Kv, B.Mt, B.Kv, B.Ku, q0, qs, w0, ws))) return stt;
+      if ((stt = reduce_level(l, B.M, B.Ku, B.Ku, q0, qs, w0, ws))) return stt;
+    }
+  }
+  ku[0] = kv[0] = 0;
+  const hss_tree_desc td{n, p, 0, leaf_off, ku.data(), kv.data()};
+  Plan P;
+  stt = build_plan(&td, P, nullptr);
+  if (stt) return stt > 0 ? stt : -5;
+  hss_handle* h = nullptr;
+  if ((stt = new_handle(std::move(P), alloc, s, &h))) return stt;
+  const Plan& Q = h->plan;
+  std::vector<CnCopy> cp;
+  cp.reserve(4 * (size_t)nn);
+  for (int32_t t = 0; t < nn; ++t) {
+    const NodeInfo& ni = Q.nodes[t];
+    if (t >= leaf0) {
+      const int32_t m = (int32_t)sz[t];
+      cp.push_back(CnCopy{A + st[t] + st[t] * lda, lda, h->g64[0] + ni.oD, m, m});
+      if (p > 0) {
+        cp.push_back(CnCopy{uslot(t, 0), kCnMaxRows, h->g64[1] + ni.oU, m, ku[t]});
+        cp.push_back(CnCopy{uslot(t, 1), kCnMaxRows, h->g64[2] + ni.oV, m, kv[t]});
+      }
+      continue;
+    }
+    const int32_t c1 = 2 * t + 1, c2 = 2 * t + 2;
+    if (t != 0) {
+      cp.push_back(CnCopy{uslot(t, 0), kCnMaxRows, h->g64[3] + ni.oR, ku[c1] + ku[c2], ku[t]});
+      cp.push_back(CnCopy{uslot(t, 1), kCnMaxRows, h->g64[4] + ni.oW, kv[c1] + kv[c2], kv[t]});
+    }
+    // core blocks: blocks of the reduced matrix of the children's level
+    const int l = Q.nodes[c1].level;
+    const CnLevel& L = lev[l];
+    const int32_t j1 = c1 - ((1 << l) - 1), j2 = j1 + 1;
+    cp.push_back(CnCopy{L.M + L.ro[j1] + L.co[j2] * L.Ku, L.Ku, h->g64[5] + ni.oB12, ku[c1], kv[c2]});
+    cp.push_back(CnCopy{L.M + L.ro[j2] + L.co[j1] * L.Ku, L.Ku, h->g64[6] + ni.oB21, ku[c2], kv[c1]});
+  }
+  CnCopy* dcp = nullptr;
+  if (!(stt = upload(tmp, cp, &dcp, s))) {
+    launch_cn_copy(dcp, (int)cp.size(), s);
+    stt = last_launch_status();
+  }
+  if (!stt) stt = finish_handle(h, s);
+  if (!stt && hipStreamSynchronize(s) != hipSuccess) stt = HSS_EHIP;
+  if (stt) {
+    (void)hipStreamSynchronize(s);
+    hss_destroy(h);
+    return stt;
+  }
+  *out = h;
+  return HSS_OK;
+}
+
 hss_status hss_ranks(const hss_handle* h, int32_t* ku, int32_t* kv) {
   if (!h) return -1;
   if (!ku) return -2;

@@ -90,6 +90,46 @@ void launch_compress(CompressStep step, const CompressBufs& b, int node0, int co
 void launch_compress_gather(const NodeInfo* in, const NodeInfo* out, const double* const work[6],
                             double* const dst[6], int nnodes, hipStream_t s);
 
+// Dense-to-HSS construction (kernels_construct.hip).
+constexpr int kCnMaxRows = 128;   // rows of a block row one truncation takes (slot ld)
+// One block row H: rows row0 .. row0 + r - 1 (r <= kCnMaxRows) of the
+// column-major X (leading dimension ld), every column 0 .. ncols - 1 except
+// ex0 .. ex1 - 1.  Out: U (r x r, ld kCnMaxRows) its left singular vectors by
+// decreasing singular value, sig the singular values, *rank the count kept
+// (sigma > eps * sigma_1, at least one).
+struct CnTask {
+  const double* X;
+  int64_t ld, row0;
+  int32_t r, pad;
+  int64_t ncols, ex0, ex1;
+  double* U;
+  double* sig;
+  int32_t* rank;
+};
+// Y(:, ycol0 .. ycol0 + k - 1) = X(:, xcol0 .. xcol0 + s - 1) B for rows
+// 0 .. rows - 1; B is s x k (ld ldb), s <= 128, k <= 64.
+struct CnRmul {
+  const double* X;
+  int64_t ldx, rows, xcol0;
+  int32_t s, k;
+  const double* B;
+  int64_t ldb;
+  double* Y;
+  int64_t ldy, ycol0;
+};
+// dst (rows x cols, ld rows) = the block of src at leading dimension lds.
+struct CnCopy {
+  const double* src;
+  int64_t lds;
+  double* dst;
+  int32_t rows, cols;
+};
+void launch_cn_trunc(const CnTask* tasks, int count, double eps, hipStream_t s);
+void launch_cn_rmul(const CnRmul* tasks, int count, int64_t rows, hipStream_t s);
+void launch_cn_trans(const double* X, int64_t ldx, int64_t rows, int64_t cols, double* Y,
+                     int64_t ldy, hipStream_t s);
+void launch_cn_copy(const CnCopy* tasks, int count, hipStream_t s);
+
 // Elementwise / reduction helpers (kernels_util.hip).
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 // dst[i + j*ldd] = (float)(src[i + j*lds] * scale[j])   (scale may be null -> 1)

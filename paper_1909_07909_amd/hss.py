@@ -30,7 +30,7 @@ EXPORTS = (
     "hss_batch_ulv_factor", "hss_batch_ulv_solve", "hss_status_str", "hss_timing_enable",
     "hss_timing_report", "hss_matmul_noalloc", "hss_matmul_noalloc_max_rhs", "hss_autotune",
     "hss_tune_table", "hss_tune_load", "hss_tune_reset", "hss_hadamard", "hss_get_generators",
-    "hss_compress", "hss_ranks", "hss_ulv_factor_solve",
+    "hss_compress", "hss_ranks", "hss_ulv_factor_solve", "hss_construct_dense",
 )
 
 Q_N, Q_P, Q_RESIDENT_BYTES, Q_NORM2, Q_GEN_ENTRIES, Q_FACTOR_ENTRIES = range(6)
@@ -98,6 +98,8 @@ def lib() -> C.CDLL:
     L.hss_get_generators.argtypes = [vp, C.POINTER(GenOut), vp]
     L.hss_compress.argtypes = [vp, C.c_double, C.POINTER(Alloc), vp, C.POINTER(vp)]
     L.hss_ranks.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.hss_construct_dense.argtypes = [vp, i64, i64, i32, C.POINTER(C.c_int64), C.c_double,
+                                      C.POINTER(Alloc), vp, C.POINTER(vp)]
     L.hss_matmul.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp]
     L.hss_matmul_noalloc.argtypes = [vp, i32, i32, i64, vp, i64, vp, i64, vp]
     L.hss_matmul_noalloc_max_rhs.argtypes = [vp, i32]
@@ -361,6 +363,45 @@ class HSSMatrix:
         out._keep = None
         out._adopt(h, self.n, self.p, self.leaf_off, self.ku.astype(np.int64) * other.ku,
                    self.kv.astype(np.int64) * other.kv)
+        return out
+
+    @classmethod
+    def from_dense(cls, A, leaf_off=None, nmin=None, eps=1e-12, stream=None, alloc="torch"):
+        """The HSS approximation of a dense n x n float64 CUDA matrix A
+        (column-major view, e.g. M.t() of a contiguous tensor M = A^T) by
+        hss_construct_dense: truncation tolerance eps relative to each
+        block's largest singular value; the tree from leaf_off or from the
+        default split with leaves of at most nmin rows."""
+        import torch
+        n = int(A.shape[0])
+        if A.dim() != 2 or A.shape[1] != n:
+            raise ValueError(f"A must be square, got {tuple(A.shape)}")
+        ap, lda = colmajor(A, n, (torch.float64,))
+        if (leaf_off is None) == (nmin is None):
+            raise ValueError("give exactly one of leaf_off and nmin")
+        lo = plan_leaf_offsets(n, nmin) if leaf_off is None else np.asarray(leaf_off, dtype=np.int64)
+        lo = np.ascontiguousarray(lo, dtype=np.int64)
+        p = int(round(np.log2(lo.size - 1)))
+        if 2 ** p + 1 != lo.size:
+            raise ValueError("leaf_off must have 2^p + 1 entries")
+        if isinstance(alloc, str):
+            if alloc != "torch":
+                raise ValueError(f"unknown allocator {alloc!r}")
+            alloc = TORCH_ALLOC
+        h = C.c_void_p()
+        code = lib().hss_construct_dense(ap, lda, n, p, lo.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         float(eps), C.byref(alloc) if alloc else None,
+                                         _stream(stream), C.byref(h))
+        _check(code, "hss_construct_dense")
+        nn = 2 ** (p + 1) - 1
+        ku = np.zeros(nn, dtype=np.int32)
+        kv = np.zeros(nn, dtype=np.int32)
+        _check(lib().hss_ranks(h, ku.ctypes.data_as(C.POINTER(C.c_int32)),
+                               kv.ctypes.data_as(C.POINTER(C.c_int32))), "hss_ranks")
+        out = cls.__new__(cls)
+        out._alloc = alloc
+        out._keep = None
+        out._adopt(h, n, p, lo, ku, kv)
         return out
 
     def compress(self, tau=None, rel=None, stream=None, alloc="torch"):

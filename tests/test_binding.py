@@ -125,3 +125,31 @@ def test_compress_and_ranks_null_arguments():
     assert L.hss_compress(None, 0.0, None, None, None) == -5
     assert L.hss_compress(None, 0.0, None, None, C.byref(h)) == -1
     assert L.hss_ranks(None, None, None) == -1
+
+
+def test_construct_dense_arguments():
+    """hss_construct_dense rejects invalid arguments before any device work;
+    the binding rejects a host tensor."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    L = hss.lib()
+    h = C.c_void_p()
+    fake = C.c_void_p(256)
+    lo = np.array([0, 100, 200], dtype=np.int64)
+    lp = lo.ctypes.data_as(C.POINTER(C.c_int64))
+    assert L.hss_construct_dense(fake, 200, 200, 1, lp, 1e-10, None, None, None) == -9
+    assert L.hss_construct_dense(None, 200, 200, 1, lp, 1e-10, None, None, C.byref(h)) == -1
+    assert L.hss_construct_dense(fake, 100, 200, 1, lp, 1e-10, None, None, C.byref(h)) == -2
+    assert L.hss_construct_dense(fake, 200, 0, 1, lp, 1e-10, None, None, C.byref(h)) == -3
+    assert L.hss_construct_dense(fake, 200, 200, -1, lp, 1e-10, None, None, C.byref(h)) == -4
+    assert L.hss_construct_dense(fake, 200, 200, 1, None, 1e-10, None, None, C.byref(h)) == -5
+    assert L.hss_construct_dense(fake, 201, 201, 1, lp, 1e-10, None, None, C.byref(h)) == -5
+    assert L.hss_construct_dense(fake, 200, 200, 1, lp, -1.0, None, None, C.byref(h)) == -6
+    assert L.hss_construct_dense(fake, 200, 200, 1, lp, float("nan"), None, None, C.byref(h)) == -6
+    big = np.array([0, 129, 200], dtype=np.int64)
+    assert L.hss_construct_dense(fake, 200, 200, 1, big.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 1e-10, None, None, C.byref(h)) == hss.HSS_EUNSUP
+    assert h.value is None
+    with pytest.raises(TypeError):
+        hss.HSSMatrix.from_dense(torch.zeros(8, 8, dtype=torch.float64), nmin=4)

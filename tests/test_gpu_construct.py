@@ -1,0 +1,143 @@
+"""hss_construct_dense (Sec. 3.2, the dense constructor) against the oracle.
+
+Ranks are integers decided by comparing singular values with eps sigma_1, so
+the tolerance of each case is moved until no singular value ratio of the
+oracle's truncations lies within 1 % of it (the device's ratios differ from
+LAPACK's by rounding, about 1e-16 sigma_1 absolute, i.e. 1e-6 relative at
+eps = 1e-10): both sides then keep the same number in every block, and the
+ranks must agree node by node.  With equal ranks the two HSS matrices agree
+to rounding over the gaps of the kept singular values (the directions near
+eps sigma_1 carry only about eps of the matrix), checked on products at
+1e-10 relative; against A itself the error stays within 4 p eps ||A||_2.
+Bases must be orthonormal to rounding."""
+import numpy as np
+import pytest
+
+from oracle import tree
+from oracle.construct import construct as oconstruct
+from oracle.hss import HSS
+from oracle.matvec import matvec as omatvec
+from paper_1909_07909_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(X):
+    return torch.from_numpy(np.ascontiguousarray(np.asfortranarray(X).T)).cuda().t()
+
+
+def _host(t):
+    return t.t().contiguous().cpu().numpy().T
+
+
+def _separated(A, lo, eps, margin=1e-2):
+    for _ in range(60):
+        rec = {}
+        Co = oconstruct(A, lo, eps, rec)
+        r = np.concatenate([v for v in rec.values() if v.size])
+        if np.all(np.abs(r - eps) > margin * eps):
+            return Co, eps
+        eps *= 1.07
+    raise AssertionError("no separated tolerance found")
+
+
+def _check(A, lo, eps, nrhs=3, seed=0, separate=True):
+    from paper_1909_07909_amd import hss
+    if separate:
+        Co, eps = _separated(A, lo, eps)
+    else:
+        Co = oconstruct(A, lo, eps)
+    n = A.shape[0]
+    print(f"[construct] n={n} leaves={len(lo) - 1} eps={eps:.3e}", flush=True)
+    H = hss.HSSMatrix.from_dense(_dev(A), leaf_off=lo, eps=eps)
+    np.testing.assert_array_equal(H.ku[1:], np.asarray(Co.ku)[1:])
+    np.testing.assert_array_equal(H.kv[1:], np.asarray(Co.kv)[1:])
+    X = inputs.rhs(n, nrhs, seed)
+    Y = _host(H.matmul(_dev(X)))
+    ref = omatvec(Co, X)
+    rel = np.linalg.norm(Y - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert rel.max() <= 1e-10, rel
+    nrm = np.linalg.norm(A, 2) if n <= 4096 else None
+    if nrm is not None:
+        err = np.linalg.norm(Y - A @ X, axis=0) / (nrm * np.linalg.norm(X, axis=0))
+        assert err.max() <= 4 * max(Co.p, 1) * eps, err
+    g = H.generators()
+    Cg = HSS.from_packed(g)
+    np.testing.assert_array_equal(np.concatenate([Cg.D[t].ravel(order="F") for t in sorted(Cg.D)]),
+                                  np.concatenate([Co.D[t].ravel(order="F") for t in sorted(Co.D)]))
+    for t in range(1, Cg.nnodes):
+        for B in ((Cg.U, Cg.V) if Cg.is_leaf(t) else (Cg.R, Cg.W)):
+            np.testing.assert_allclose(B[t].T @ B[t], np.eye(B[t].shape[1]), atol=1e-13)
+    return H, Co
+
+
+def test_cauchy_4096():
+    n = 4096
+    lo = tree.leaf_offsets(n, 128)
+    _check(inputs.cauchy_kernel_dense(n, seed=11), lo, 1e-10)
+
+
+def test_cauchy_ragged_leaves():
+    """Leaves of 93 and 94 rows (n = 3000, n_min = 100)."""
+    n = 3000
+    lo = tree.leaf_offsets(n, 100)
+    _check(inputs.cauchy_kernel_dense(n, seed=12), lo, 1e-8)
+
+
+def test_exact_hss_input():
+    """An exactly rank-7 HSS matrix: ranks 7 everywhere (the 8th singular
+    value of every block is rounding), the matrix back to rounding."""
+    n = 2048
+    lo = tree.leaf_offsets(n, 64)
+    A = HSS.from_packed(inputs.synthetic_hss(lo, 7, seed=13)).dense()
+    H, Co = _check(A, lo, 1e-12, separate=False)
+    assert set(H.ku[1:]) == {7} and set(H.kv[1:]) == {7}
+
+
+@pytest.mark.parametrize("bl,bu", [(2, 3), (0, 4)])
+def test_banded(bl, bu):
+    """Banded: ranks b_l + b_u inside, b_u / b_l at the first and last node
+    of a level (one where nothing couples), exact representation."""
+    n = 1000
+    lo = tree.leaf_offsets(n, 50)
+    A = inputs.banded_dense(n, bl, bu, seed=14)
+    H, Co = _check(A, lo, 1e-12, separate=False)
+    assert int(H.ku[1:].max()) == bl + bu
+
+
+def test_single_leaf_and_block_diagonal():
+    from paper_1909_07909_amd import hss
+    A = inputs.rhs(100, 100, 15)
+    H = hss.HSSMatrix.from_dense(_dev(A), leaf_off=[0, 100], eps=1e-12)
+    g = H.generators()
+    np.testing.assert_array_equal(g.D, np.asfortranarray(A).ravel(order="F"))
+    # zero off-diagonal blocks: every block keeps one (zero-weight) direction
+    n = 512
+    lo = tree.leaf_offsets(n, 64)
+    Bd = np.zeros((n, n))
+    for a, b in zip(lo[:-1], lo[1:]):
+        Bd[a:b, a:b] = inputs.rhs(b - a, b - a, a)
+    H, Co = _check(Bd, lo, 1e-12, separate=False)
+    assert set(H.ku[1:]) == {1} and set(H.kv[1:]) == {1}
+
+
+def test_cauchy_16384_then_solve():
+    """The ragged-rank workload at its full size (n = 16384, leaf 128): ranks
+    node by node against the oracle, sampled products, then the FP64 factor
+    and solve of the constructed matrix to eta <= 1e-12."""
+    from paper_1909_07909_amd import hss
+    n = 16384
+    lo = tree.leaf_offsets(n, 128)
+    A = inputs.cauchy_kernel_dense(n, seed=1)
+    H, Co = _check(A, lo, 1e-10, nrhs=2)
+    B = inputs.rhs(n, 4, 16)
+    Xd = _dev(B)
+    H.factor(hss.F64)
+    info = H.solve(Xd, prec=hss.F64, want_eta=True)
+    assert info["status"] == 0 and info["eta_max"] <= 1e-12
+    # the solution of the constructed matrix against the oracle's products
+    X = _host(Xd)
+    r = B - omatvec(Co, X)
+    assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(B, axis=0)) <= 1e-10
