@@ -87,10 +87,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "batch", "serve", "cpu"],
+                    choices=["headline", "batch", "serve", "construct", "cpu"],
                     help="headline: one n=2^18 system (default); batch: 512 uneven instances "
-                         "in level-batched launches; serve: Poisson request stream; cpu: the "
-                         "FP64 oracle timed on the host for every workload (no GPU)")
+                         "in level-batched launches; serve: Poisson request stream; "
+                         "construct: dense-to-HSS construction of the n=16384 Cauchy-like "
+                         "matrix; cpu: the FP64 oracle timed on the host for every workload "
+                         "(no GPU)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-resident", type=float, default=1.0,
@@ -124,6 +126,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "construct":
+        return bench_construct(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
@@ -408,6 +412,7 @@ def main():
         break
 
     had = hadamard_measure(log)
+    cons = construct_measure(log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -443,12 +448,83 @@ def main():
         "matmul_fp64": mm,
         "hadamard": had,
         "compress": had.pop("compress", None),
+        "construct": cons,
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": kernels[:12],
     }
     line = json.dumps(out)
     print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+def construct_measure(log, reps=3, n=16384, leaf=128, eps=1e-10):
+    """Dense-to-HSS construction (hss_construct_dense) of the Cauchy-like
+    kernel matrix of the ragged-rank workload, n = 16384, leaf 128,
+    eps = 1e-10 (relative to each block's sigma_1), the dense matrix resident
+    in HBM: whole call time, per-kernel times, and the leaf-level truncation
+    (the O(n^2) part) against its Householder-QR flops."""
+    import numpy as np
+    import torch
+
+    from paper_1909_07909_amd import hss
+    rng = np.random.default_rng(1)
+    x = torch.from_numpy(np.sort(rng.uniform(0.0, 1.0, n))).cuda()
+    d = (x[:, None] - x[None, :]) / 0.05
+    A = 1.0 / (1.0 + d * d)
+    A.diagonal().add_(1e-2)
+    Ad = A.t()          # symmetric: the column-major view of the same matrix
+    del d
+    lo = hss.plan_leaf_offsets(n, leaf)
+    H = hss.HSSMatrix.from_dense(Ad, leaf_off=lo, eps=eps)   # warm-up
+    ku = H.ku.copy()
+    del H
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        H = hss.HSSMatrix.from_dense(Ad, leaf_off=lo, eps=eps)
+        del H
+    torch.cuda.synchronize()
+    call_ms = (time.perf_counter() - t0) * 1e3 / reps
+    hss.timing_enable(True)
+    hss.timing_report(reset=True)
+    H = hss.HSSMatrix.from_dense(Ad, leaf_off=lo, eps=eps)
+    torch.cuda.synchronize()
+    rep = hss.timing_report(reset=True)
+    hss.timing_enable(False)
+    del H, A, Ad
+    m = np.diff(lo)
+    # Householder QR of H^T (N x r, N = n - r columns of the block row):
+    # 2 N r^2 - 2 r^3 / 3 flops, a row side and a column side per leaf
+    flops = float(np.sum(2 * (2.0 * (n - m) * m * m - 2.0 * m ** 3 / 3.0)))
+    kt = {d["kernel"]: d for d in rep}
+    leaf_ms = kt["construct_trunc_leaf"]["total_ms"]
+    tf = flops / (leaf_ms * 1e-3) / 1e12
+    out = {"workload": f"Cauchy-like kernel, n={n}, leaf={leaf}, eps={eps:g}",
+           "call_ms": round(call_ms, 3),
+           "mean_rank": round(float(np.mean(ku[1:])), 2), "max_rank": int(ku.max()),
+           "kernels_ms": {d["kernel"]: round(d["total_ms"], 3) for d in rep
+                          if d["kernel"].startswith("construct")},
+           "trunc_leaf": {"ms": round(leaf_ms, 3), "algorithmic_flops": flops,
+                          "tflops": round(tf, 2), "frac_fp64_vector_peak": round(tf / 78.6, 4)}}
+    log(f"[bench] construct n={n}: {call_ms:.2f} ms per call (mean rank "
+        f"{out['mean_rank']}); leaf truncation {leaf_ms:.2f} ms, {tf:.2f} TFLOP/s")
+    return out
+
+
+def bench_construct(args):
+    """The construction workload alone: one JSON line."""
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    c = construct_measure(log, reps=max(args.steps, 1))
+    out = {"metric": "dense-to-HSS constructions/s [construction workload]",
+           "value": round(1e3 / c["call_ms"], 3), "unit": "constructions/s", "n_gpus": 1,
+           "steps": max(args.steps, 1), "warmup": 1, "ms_per_step": c["call_ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": c["workload"]}, "construct": c}
+    line = json.dumps(out)
+    print(line)
     if args.out:
         with open(args.out, "w") as f:
             f.write(line + "\n")

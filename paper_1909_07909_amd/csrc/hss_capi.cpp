@@ -1770,7 +1770,7 @@ hss_status hss_construct_dense(const double* A, int64_t lda, int64_t n, int32_t 
     CnTask* dt = nullptr;
     hss_status e = upload(tmp, tasks, &dt, s);
     if (e) return e;
-    launch_cn_trunc(dt, 2 * cnt, eps, s);
+    launch_cn_trunc(dt, 2 * cnt, eps, l == p, s);
     if ((e = last_launch_status())) return e;
     if (hipMemcpyAsync(rk_h.data() + 2 * t0, rk + 2 * t0, sizeof(int32_t) * 2 * cnt,
                        hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -124,7 +124,8 @@ struct CnCopy {
   double* dst;
   int32_t rows, cols;
 };
-void launch_cn_trunc(const CnTask* tasks, int count, double eps, hipStream_t s);
+// leaves: the launch of the leaf level (named apart in the per-kernel timing)
+void launch_cn_trunc(const CnTask* tasks, int count, double eps, bool leaves, hipStream_t s);
 void launch_cn_rmul(const CnRmul* tasks, int count, int64_t rows, hipStream_t s);
 void launch_cn_trans(const double* X, int64_t ldx, int64_t rows, int64_t cols, double* Y,
                      int64_t ldy, hipStream_t s);

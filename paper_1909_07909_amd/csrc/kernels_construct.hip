@@ -6,7 +6,7 @@
 //                column-major matrix X, every column of X outside one
 //                excluded range): the left singular vectors and values of H.
 //                H^T is reduced to its triangular factor by a streaming
-//                Householder QR (64 columns of H at a time below the
+//                Householder QR (128 columns of H at a time below the
 //                128 x 128 triangle, which stays in LDS), then one-sided
 //                Jacobi (Hestenes) orthogonalizes the rows of that factor:
 //                H = T^T Q^T, so H's left singular pairs are those of T^T,
@@ -30,7 +30,7 @@ namespace {
 constexpr int kQT = 256;           // threads of k_cn_trunc
 constexpr int kQR = kCnMaxRows;    // largest block row (rows)
 constexpr int kRP = kQR + 1;       // LDS row stride of the triangle (bank spread)
-constexpr int kCH = 64;            // columns of H per streaming step
+constexpr int kCH = 128;           // columns of H per streaming step
 constexpr int kHC = kCH / 2;       // of them per thread (two threads per row of H)
 static_assert(kQR == 128 && kQT == 2 * kQR, "two threads per row of the block");
 
@@ -71,9 +71,11 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
     for (int j = 0; j < r; ++j) {
       const int b = j & 1;
       if (c == j) {
-        double ss = 0.0;
+        // four independent partial sums: the chains, not the issue rate, bound a step
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < kHC; ++i) ss += v[i] * v[i];
+        for (int i = 0; i < kHC; ++i) s4[i & 3] += v[i] * v[i];
+        double ss = (s4[0] + s4[1]) + (s4[2] + s4[3]);
         ss += __shfl_xor(ss, 1);
         const double alpha = R[j * kRP + j];
         double tau = 0.0, inv = 0.0;
@@ -91,9 +93,10 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
       __syncthreads();
       const double tau = tb[b];
       if (c > j && c < r && tau != 0.0) {
-        double w = 0.0;
+        double w4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < kHC; ++i) w += vb[b][h * kHC + i] * v[i];
+        for (int i = 0; i < kHC; ++i) w4[i & 3] += vb[b][h * kHC + i] * v[i];
+        double w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
         w += __shfl_xor(w, 1);
         w = tau * (w + R[j * kRP + c]);
         if (h == 0) R[j * kRP + c] -= w;
@@ -250,9 +253,9 @@ __global__ __launch_bounds__(256) void k_cn_copy(const CnCopy* tasks) {
 
 }  // namespace
 
-void launch_cn_trunc(const CnTask* tasks, int count, double eps, hipStream_t s) {
+void launch_cn_trunc(const CnTask* tasks, int count, double eps, bool leaves, hipStream_t s) {
   if (count <= 0) return;
-  TimedLaunch tl("construct_trunc", s);
+  TimedLaunch tl(leaves ? "construct_trunc_leaf" : "construct_trunc", s);
   hipLaunchKernelGGL(k_cn_trunc, dim3(count), dim3(kQT), 0, s, tasks, eps);
 }
 
