@@ -27,12 +27,13 @@
 namespace hss {
 namespace {
 
-constexpr int kQT = 256;           // threads of k_cn_trunc
+constexpr int kQT = 512;           // threads of k_cn_trunc
 constexpr int kQR = kCnMaxRows;    // largest block row (rows)
 constexpr int kRP = kQR + 1;       // LDS row stride of the triangle (bank spread)
 constexpr int kCH = 128;           // columns of H per streaming step
-constexpr int kHC = kCH / 2;       // of them per thread (two threads per row of H)
-static_assert(kQR == 128 && kQT == 2 * kQR, "two threads per row of the block");
+constexpr int kTR = 4;             // threads per row of H
+constexpr int kHC = kCH / kTR;     // columns of H per thread and step
+static_assert(kQR == 128 && kQT == kTR * kQR, "four threads per row of the block");
 
 __device__ __forceinline__ int64_t cn_col(int64_t q, int64_t ex0, int64_t ex1) {
   return q < ex0 ? q : q + (ex1 - ex0);
@@ -48,13 +49,13 @@ __device__ __forceinline__ void rr_pair(int i, int s, int e, int& a, int& b) {
 
 __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double eps) {
   __shared__ double R[kQR * kRP];
-  __shared__ double vb[2][kCH];
+  __shared__ double vb[2][kCH];   // reflector entries, row h * kHC + i of a chunk at i * kTR + h
   __shared__ double tb[2];
   __shared__ double sig[kQR];
   __shared__ int flag;
   const CnTask tk = tasks[blockIdx.x];
   const int tid = threadIdx.x;
-  const int c = tid >> 1, h = tid & 1;   // row c of H (column c of H^T), half h of a chunk
+  const int c = tid >> 2, h = tid & 3;   // row c of H (column c of H^T), quarter h of a chunk
   const int r = tk.r;
   for (int i = tid; i < kQR * kRP; i += kQT) R[i] = 0.0;
   __syncthreads();
@@ -77,6 +78,7 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
         for (int i = 0; i < kHC; ++i) s4[i & 3] += v[i] * v[i];
         double ss = (s4[0] + s4[1]) + (s4[2] + s4[3]);
         ss += __shfl_xor(ss, 1);
+        ss += __shfl_xor(ss, 2);
         const double alpha = R[j * kRP + j];
         double tau = 0.0, inv = 0.0;
         if (ss > 0.0) {
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
           if (h == 0) R[j * kRP + j] = beta;
         }
 #pragma unroll
-        for (int i = 0; i < kHC; ++i) vb[b][h * kHC + i] = v[i] * inv;
+        for (int i = 0; i < kHC; ++i) vb[b][i * kTR + h] = v[i] * inv;
         if (h == 0) tb[b] = tau;
       }
       __syncthreads();
@@ -95,20 +97,21 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
       if (c > j && c < r && tau != 0.0) {
         double w4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < kHC; ++i) w4[i & 3] += vb[b][h * kHC + i] * v[i];
+        for (int i = 0; i < kHC; ++i) w4[i & 3] += vb[b][i * kTR + h] * v[i];
         double w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
         w += __shfl_xor(w, 1);
+        w += __shfl_xor(w, 2);
         w = tau * (w + R[j * kRP + c]);
         if (h == 0) R[j * kRP + c] -= w;
 #pragma unroll
-        for (int i = 0; i < kHC; ++i) v[i] -= w * vb[b][h * kHC + i];
+        for (int i = 0; i < kHC; ++i) v[i] -= w * vb[b][i * kTR + h];
       }
     }
     __syncthreads();
   }
   // ---- one-sided Jacobi on the rows of the triangle (columns of T^T)
   const int e = (r + 1) & ~1;   // an odd count gets a zero row as partner
-  const int pr = tid >> 2, sub = tid & 3;
+  const int pr = tid >> 3, sub = tid & 7;   // 64 pairs x 8 lanes
   const double tol = 2.5e-15;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) flag = 0;
@@ -120,7 +123,7 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
         double* ra = R + a * kRP;
         double* rb = R + b * kRP;
         double aa = 0.0, bb = 0.0, ab = 0.0;
-        for (int x = sub; x < r; x += 4) {
+        for (int x = sub; x < r; x += 8) {
           const double p = ra[x], q = rb[x];
           aa += p * p;
           bb += q * q;
@@ -132,11 +135,14 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
         aa += __shfl_xor(aa, 2);
         bb += __shfl_xor(bb, 2);
         ab += __shfl_xor(ab, 2);
+        aa += __shfl_xor(aa, 4);
+        bb += __shfl_xor(bb, 4);
+        ab += __shfl_xor(ab, 4);
         if (ab != 0.0 && fabs(ab) > tol * sqrt(aa) * sqrt(bb)) {
           const double zeta = (bb - aa) / (2.0 * ab);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int x = sub; x < r; x += 4) {
+          for (int x = sub; x < r; x += 8) {
             const double p = ra[x], q = rb[x];
             ra[x] = cs * p - sn * q;
             rb[x] = sn * p + cs * q;
