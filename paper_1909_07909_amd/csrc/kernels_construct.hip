@@ -20,6 +20,7 @@
 //                generators at the end)
 #include <hip/hip_runtime.h>
 
+#include "device_util.hpp"
 #include "hss_internal.hpp"
 #include "kernels.hpp"
 #include "timing.hpp"
@@ -77,8 +78,8 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
 #pragma unroll
         for (int i = 0; i < kHC; ++i) s4[i & 3] += v[i] * v[i];
         double ss = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-        ss += __shfl_xor(ss, 1);
-        ss += __shfl_xor(ss, 2);
+        ss += dpp<kDppQuadXor1>(ss);
+        ss += dpp<kDppQuadXor2>(ss);
         const double alpha = R[j * kRP + j];
         double tau = 0.0, inv = 0.0;
         if (ss > 0.0) {
@@ -99,8 +100,8 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
 #pragma unroll
         for (int i = 0; i < kHC; ++i) w4[i & 3] += vb[b][i * kTR + h] * v[i];
         double w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
-        w += __shfl_xor(w, 1);
-        w += __shfl_xor(w, 2);
+        w += dpp<kDppQuadXor1>(w);
+        w += dpp<kDppQuadXor2>(w);
         w = tau * (w + R[j * kRP + c]);
         if (h == 0) R[j * kRP + c] -= w;
 #pragma unroll
@@ -129,12 +130,12 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
           bb += q * q;
           ab += p * q;
         }
-        aa += __shfl_xor(aa, 1);
-        bb += __shfl_xor(bb, 1);
-        ab += __shfl_xor(ab, 1);
-        aa += __shfl_xor(aa, 2);
-        bb += __shfl_xor(bb, 2);
-        ab += __shfl_xor(ab, 2);
+        aa += dpp<kDppQuadXor1>(aa);
+        bb += dpp<kDppQuadXor1>(bb);
+        ab += dpp<kDppQuadXor1>(ab);
+        aa += dpp<kDppQuadXor2>(aa);
+        bb += dpp<kDppQuadXor2>(bb);
+        ab += dpp<kDppQuadXor2>(ab);
         aa += __shfl_xor(aa, 4);
         bb += __shfl_xor(bb, 4);
         ab += __shfl_xor(ab, 4);
