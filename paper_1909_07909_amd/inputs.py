@@ -348,15 +348,19 @@ def _block_diag_family(leaf_off, k, seed, diag, zero_core):
 # ----------------------------------------------------------------------------
 
 def cauchy_kernel_dense(n: int, seed: int = 1, width: float = 0.05,
-                        shift: float = 1e-2) -> np.ndarray:
+                        shift: float = 1e-2, skew: float = 0.0) -> np.ndarray:
     """The Cauchy-like kernel matrix of the ragged-rank workload: points x_i
     sorted uniform on [0, 1], A_ij = 1 / (1 + ((x_i - x_j) / width)^2) plus
     shift on the diagonal (symmetric positive definite, numerically low-rank
-    off-diagonal blocks)."""
+    off-diagonal blocks).  skew != 0 multiplies entry (i, j) by
+    1 + skew * tanh((x_i - x_j) / (2 width)): still smooth off the diagonal,
+    no longer symmetric."""
     rng = np.random.default_rng(seed)
     x = np.sort(rng.uniform(0.0, 1.0, n))
     d = (x[:, None] - x[None, :]) / width
     A = 1.0 / (1.0 + d * d)
+    if skew != 0.0:
+        A *= 1.0 + skew * np.tanh(0.5 * d)
     A[np.diag_indices_from(A)] += shift
     return np.asfortranarray(A)
 

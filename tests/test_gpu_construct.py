@@ -86,6 +86,24 @@ def test_cauchy_ragged_leaves():
     _check(inputs.cauchy_kernel_dense(n, seed=12), lo, 1e-8)
 
 
+def test_nonsymmetric_kernel():
+    """A smooth kernel that is not symmetric: block rows and columns get
+    different ranks (ku != kv) on both sides alike."""
+    n = 4096
+    lo = tree.leaf_offsets(n, 128)
+    A = inputs.cauchy_kernel_dense(n, seed=17, skew=0.6)
+    H, Co = _check(A, lo, 1e-9)
+    assert np.any(H.ku[1:] != H.kv[1:])
+
+
+def test_coarse_tolerance():
+    """eps = 0.3: most blocks keep a single direction."""
+    n = 2048
+    lo = tree.leaf_offsets(n, 64)
+    H, Co = _check(inputs.cauchy_kernel_dense(n, seed=18), lo, 0.3)
+    assert np.mean(H.ku[1:] == 1) > 0.5
+
+
 def test_exact_hss_input():
     """An exactly rank-7 HSS matrix: ranks 7 everywhere (the 8th singular
     value of every block is rounding), the matrix back to rounding."""
@@ -141,3 +159,8 @@ def test_cauchy_16384_then_solve():
     X = _host(Xd)
     r = B - omatvec(Co, X)
     assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(B, axis=0)) <= 1e-10
+    # FP32 factors with FP64 refinement on the constructed matrix
+    X32 = _dev(B)
+    H.factor(hss.F32)
+    info = H.solve(X32, prec=hss.F32, tol=1e-10, max_refine=5, want_eta=True)
+    assert info["status"] == 0 and info["eta_max"] <= 1e-10 and info["iters"] <= 3
