@@ -50,7 +50,10 @@ __device__ __forceinline__ void rr_pair(int i, int s, int e, int& a, int& b) {
 
 __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double eps) {
   __shared__ double R[kQR * kRP];
-  __shared__ double vb[2][kCH];   // reflector entries, row h * kHC + i of a chunk at i * kTR + h
+  // reflector entries: chunk row h * kHC + i at (i / 2) * 2 kTR + 2 h + i % 2 (a
+  // thread's pairs adjacent for 16-byte accesses, the four threads of a row
+  // on distinct banks)
+  __shared__ __align__(16) double vb[2][kCH];
   __shared__ double tb[2];
   __shared__ double sig[kQR];
   __shared__ int flag;
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
           if (h == 0) R[j * kRP + j] = beta;
         }
 #pragma unroll
-        for (int i = 0; i < kHC; ++i) vb[b][i * kTR + h] = v[i] * inv;
+        for (int i = 0; i < kHC; ++i) vb[b][(i >> 1) * (2 * kTR) + 2 * h + (i & 1)] = v[i] * inv;
         if (h == 0) tb[b] = tau;
       }
       __syncthreads();
@@ -98,14 +101,14 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
       if (c > j && c < r && tau != 0.0) {
         double w4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < kHC; ++i) w4[i & 3] += vb[b][i * kTR + h] * v[i];
+        for (int i = 0; i < kHC; ++i) w4[i & 3] += vb[b][(i >> 1) * (2 * kTR) + 2 * h + (i & 1)] * v[i];
         double w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
         w += dpp<kDppQuadXor1>(w);
         w += dpp<kDppQuadXor2>(w);
         w = tau * (w + R[j * kRP + c]);
         if (h == 0) R[j * kRP + c] -= w;
 #pragma unroll
-        for (int i = 0; i < kHC; ++i) v[i] -= w * vb[b][i * kTR + h];
+        for (int i = 0; i < kHC; ++i) v[i] -= w * vb[b][(i >> 1) * (2 * kTR) + 2 * h + (i & 1)];
       }
     }
     __syncthreads();
