@@ -28,13 +28,24 @@
 namespace hss {
 namespace {
 
-constexpr int kQT = 512;           // threads of k_cn_trunc
+constexpr int kQT = 1024;          // threads of k_cn_trunc
 constexpr int kQR = kCnMaxRows;    // largest block row (rows)
 constexpr int kRP = kQR + 1;       // LDS row stride of the triangle (bank spread)
 constexpr int kCH = 128;           // columns of H per streaming step
-constexpr int kTR = 4;             // threads per row of H
+constexpr int kTR = 8;             // threads per row of H
 constexpr int kHC = kCH / kTR;     // columns of H per thread and step
-static_assert(kQR == 128 && kQT == kTR * kQR, "four threads per row of the block");
+static_assert(kQR == 128 && kQT == kTR * kQR, "eight threads per row of the block");
+
+// sum over the 8 lanes of an aligned group: quad permutes, then the other
+// quad of the group by a row shift of 4 (left in the low quad, right in the
+// high one)
+__device__ __forceinline__ double oct_sum(double x, int lane) {
+  x += dpp<kDppQuadXor1>(x);
+  x += dpp<kDppQuadXor2>(x);
+  const double lo = dpp<0x104>(x);   // row_shl:4
+  const double hi = dpp<0x114>(x);   // row_shr:4
+  return x + ((lane & 4) ? hi : lo);
+}
 
 __device__ __forceinline__ int64_t cn_col(int64_t q, int64_t ex0, int64_t ex1) {
   return q < ex0 ? q : q + (ex1 - ex0);
@@ -59,7 +70,8 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
   __shared__ int flag;
   const CnTask tk = tasks[blockIdx.x];
   const int tid = threadIdx.x;
-  const int c = tid >> 2, h = tid & 3;   // row c of H (column c of H^T), quarter h of a chunk
+  const int c = tid >> 3, h = tid & 7;   // row c of H (column c of H^T), eighth h of a chunk
+  const int lane = tid & 63;
   const int r = tk.r;
   for (int i = tid; i < kQR * kRP; i += kQT) R[i] = 0.0;
   __syncthreads();
@@ -80,9 +92,7 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
         double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < kHC; ++i) s4[i & 3] += v[i] * v[i];
-        double ss = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-        ss += dpp<kDppQuadXor1>(ss);
-        ss += dpp<kDppQuadXor2>(ss);
+        const double ss = oct_sum((s4[0] + s4[1]) + (s4[2] + s4[3]), lane);
         const double alpha = R[j * kRP + j];
         double tau = 0.0, inv = 0.0;
         if (ss > 0.0) {
@@ -102,9 +112,7 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
         double w4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < kHC; ++i) w4[i & 3] += vb[b][(i >> 1) * (2 * kTR) + 2 * h + (i & 1)] * v[i];
-        double w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
-        w += dpp<kDppQuadXor1>(w);
-        w += dpp<kDppQuadXor2>(w);
+        double w = oct_sum((w4[0] + w4[1]) + (w4[2] + w4[3]), lane);
         w = tau * (w + R[j * kRP + c]);
         if (h == 0) R[j * kRP + c] -= w;
 #pragma unroll
@@ -115,7 +123,7 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
   }
   // ---- one-sided Jacobi on the rows of the triangle (columns of T^T)
   const int e = (r + 1) & ~1;   // an odd count gets a zero row as partner
-  const int pr = tid >> 3, sub = tid & 7;   // 64 pairs x 8 lanes
+  const int pr = tid >> 4, sub = tid & 15;   // 64 pairs x 16 lanes
   const double tol = 2.5e-15;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) flag = 0;
@@ -127,26 +135,23 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
         double* ra = R + a * kRP;
         double* rb = R + b * kRP;
         double aa = 0.0, bb = 0.0, ab = 0.0;
-        for (int x = sub; x < r; x += 8) {
+        for (int x = sub; x < r; x += 16) {
           const double p = ra[x], q = rb[x];
           aa += p * p;
           bb += q * q;
           ab += p * q;
         }
-        aa += dpp<kDppQuadXor1>(aa);
-        bb += dpp<kDppQuadXor1>(bb);
-        ab += dpp<kDppQuadXor1>(ab);
-        aa += dpp<kDppQuadXor2>(aa);
-        bb += dpp<kDppQuadXor2>(bb);
-        ab += dpp<kDppQuadXor2>(ab);
-        aa += __shfl_xor(aa, 4);
-        bb += __shfl_xor(bb, 4);
-        ab += __shfl_xor(ab, 4);
+        aa = oct_sum(aa, lane);
+        bb = oct_sum(bb, lane);
+        ab = oct_sum(ab, lane);
+        aa += dpp<kDppRowRor8>(aa);   // the other half of the row of 16
+        bb += dpp<kDppRowRor8>(bb);
+        ab += dpp<kDppRowRor8>(ab);
         if (ab != 0.0 && fabs(ab) > tol * sqrt(aa) * sqrt(bb)) {
           const double zeta = (bb - aa) / (2.0 * ab);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int x = sub; x < r; x += 8) {
+          for (int x = sub; x < r; x += 16) {
             const double p = ra[x], q = rb[x];
             ra[x] = cs * p - sn * q;
             rb[x] = sn * p + cs * q;
