@@ -104,7 +104,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this "
-              "build (instances shard across GPUs without communication, see DESIGN.md)",
+              "build (independent instances shard across GPUs without communication: run one "
+              "process per GPU)",
               file=sys.stderr)
         sys.exit(2)
 
