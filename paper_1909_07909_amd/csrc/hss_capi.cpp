@@ -1694,6 +1694,9 @@ struct CnLevel {
   double* Mt = nullptr;   // its transpose
   int64_t Ku = 0, Kv = 0;
   std::vector<int64_t> ro, co;   // row / column block offsets of the level's nodes
+  // the product task lists, kept until the call has synchronized (their
+  // uploads are asynchronous)
+  std::vector<CnRmul> ta, tb;
 };
 
 template <typename V>
@@ -1749,6 +1752,11 @@ hss_status hss_construct_dense(const double* A, int64_t lda, int64_t n, int32_t 
   if (p > 0 && (!Ub || !sg || !rk || !At)) return HSS_ENOMEM;
   auto uslot = [&](int32_t t, int side) { return Ub + slot * (2 * (size_t)t + side); };
   std::vector<CnLevel> lev(p + 1);   // lev[l]: reduced matrix of level l (l = 1 .. p)
+  // every exit waits for the stream before the host task lists above go away
+  struct SyncOnExit {
+    hipStream_t s;
+    ~SyncOnExit() { (void)hipStreamSynchronize(s); }
+  } sync_on_exit{s};
   std::vector<int32_t> rk_h(2 * nn, 0);
   // truncations of the nodes of one level: row side on X, column side on Xt
   auto truncate_level = [&](int l, const double* X, int64_t ldx, int64_t nx, const double* Xt,
@@ -1771,7 +1779,10 @@ hss_status hss_construct_dense(const double* A, int64_t lda, int64_t n, int32_t 
     hss_status e = upload(tmp, tasks, &dt, s);
     if (e) return e;
     launch_cn_trunc(dt, 2 * cnt, eps, l == p, s);
-    if ((e = last_launch_status())) return e;
+    if ((e = last_launch_status())) {
+      (void)hipStreamSynchronize(s);
+      return e;
+    }
     if (hipMemcpyAsync(rk_h.data() + 2 * t0, rk + 2 * t0, sizeof(int32_t) * 2 * cnt,
                        hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -1803,7 +1814,10 @@ hss_status hss_construct_dense(const double* A, int64_t lda, int64_t n, int32_t 
     L.M = (double*)tmp.get(sizeof(double) * (size_t)L.Ku * L.Kv);
     L.Mt = (double*)tmp.get(sizeof(double) * (size_t)L.Ku * L.Kv);
     if (!Y || !Yt || !L.M || !L.Mt) return HSS_ENOMEM;
-    std::vector<CnRmul> a(cnt), b(cnt);
+    std::vector<CnRmul>& a = L.ta;
+    std::vector<CnRmul>& b = L.tb;
+    a.resize(cnt);
+    b.resize(cnt);
     for (int32_t j = 0; j < cnt; ++j) {
       const int32_t t = t0 + j;
       a[j] = CnRmul{X, ldx, rows, c0[j], (int32_t)csz[j], kv[t], uslot(t, 1), kCnMaxRows,
