@@ -62,7 +62,7 @@ __device__ __forceinline__ void rr_pair(int i, int s, int e, int& a, int& b) {
 __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double eps) {
   __shared__ double R[kQR * kRP];
   // reflector entries: chunk row h * kHC + i at (i / 2) * 2 kTR + 2 h + i % 2 (a
-  // thread's pairs adjacent for 16-byte accesses, the four threads of a row
+  // thread's pairs adjacent for 16-byte accesses, the eight threads of a row
   // on distinct banks)
   __shared__ __align__(16) double vb[2][kCH];
   __shared__ double tb[2];
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kQT) void k_cn_trunc(const CnTask* tasks, double ep
   const int r = tk.r;
   for (int i = tid; i < kQR * kRP; i += kQT) R[i] = 0.0;
   __syncthreads();
-  // ---- streaming QR of H^T: [T; next 64 columns of H, transposed] = Q T'
+  // ---- streaming QR of H^T: [T; next 128 columns of H, transposed] = Q T'
   const int64_t nc = tk.ncols - (tk.ex1 - tk.ex0);
   const double* xr = tk.X + tk.row0 + c;
   double v[kHC];
