@@ -164,3 +164,22 @@ def test_cauchy_16384_then_solve():
     H.factor(hss.F32)
     info = H.solve(X32, prec=hss.F32, tol=1e-10, max_refine=5, want_eta=True)
     assert info["status"] == 0 and info["eta_max"] <= 1e-10 and info["iters"] <= 3
+
+
+def test_rank_above_64_is_unsupported():
+    """eps = 0 on a random dense matrix keeps every direction: leaf ranks of
+    128 exceed what the kernels take, so the call returns HSS_EUNSUP after
+    the first level and leaves nothing behind (a later call on a smooth
+    matrix gets the oracle's ranks)."""
+    from paper_1909_07909_amd import hss
+    n = 512
+    A = inputs.rhs(n, n, 19)
+    lo = tree.leaf_offsets(n, 128)
+    with pytest.raises(hss.HSSError) as ei:
+        hss.HSSMatrix.from_dense(_dev(A), leaf_off=lo, eps=0.0)
+    assert ei.value.code == hss.HSS_EUNSUP
+    # a smooth matrix on the same tree right after: ranks as the oracle's
+    Bm = inputs.cauchy_kernel_dense(n, seed=20)
+    H = hss.HSSMatrix.from_dense(_dev(Bm), leaf_off=lo, eps=1e-8)
+    Co = oconstruct(Bm, lo, 1e-8)
+    np.testing.assert_array_equal(H.ku[1:], np.asarray(Co.ku)[1:])
